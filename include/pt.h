@@ -1,0 +1,193 @@
+/*
+ * pt.h -- C ABI of the MI355X (gfx950) proxy-sampling BDPT library, libpt.so.
+ *
+ * Method: Su et al., "Proxy Tracing: Unbiased Reciprocal Estimation for Optimized
+ * Sampling in BDPT". Every rendering iteration estimates, for every pixel j, the path
+ * integral I_j = int f_j(x) dmu(x) (Section 3.1, path integral equation) with one sample
+ * per pixel (Section 6.1: one iteration = 1 spp), from a cache of M light sub-paths that
+ * all pixels share (Section 3.2), reciprocal estimates of the densities of incomplete light
+ * sub-paths (Sections 4.2 and 5.2) and proxy retraces at the eye's first diffuse vertex
+ * (Section 5.1).
+ *
+ * Conventions shared by every call:
+ *  - Pointers named *_dev are device pointers (HIP device memory, e.g. torch tensors on
+ *    cuda:0); every other pointer is host memory. The library never frees caller memory.
+ *  - hip_stream is a hipStream_t (may be NULL = the legacy default stream). All device work
+ *    is enqueued on it in order; no call synchronises the host unless it says so.
+ *  - The library owns everything reachable from a pt_scene (geometry, BVH, light cache,
+ *    candidates, statistics, workspaces); pt_scene_release frees it.
+ *  - Return value: PT_OK (0) or a negative pt_status. Invalid arguments return PT_EINVAL
+ *    and change no state. pt_last_error() gives a message for the last failing call on the
+ *    calling thread. No C++ exception crosses this interface.
+ *  - Only gfx950 code objects are built; another device returns PT_EUNSUPPORTED.
+ */
+#ifndef PT_H
+#define PT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t pt_status;
+enum {
+    PT_OK = 0,
+    PT_EINVAL = -1,       /* bad argument; nothing changed */
+    PT_ENOMEM = -2,       /* device allocation failed; the scene stays valid */
+    PT_EDEVICE = -3,      /* a HIP call failed */
+    PT_ESTATE = -4,       /* call out of order (e.g. render before build_subspaces) */
+    PT_EUNSUPPORTED = -5  /* not a gfx950 device */
+};
+
+typedef struct pt_scene pt_scene;
+
+/* Material record: 16 floats per material, host memory.
+ *  [0] type: 0 Lambert, 1 conductor (GGX, alpha = max(roughness^2, 1e-4); roughness exactly 0
+ *      is a perfect mirror), 2 smooth dielectric (outside index 1)
+ *  [1..3] albedo (Lambert) or F0 (conductor, Schlick Fresnel)
+ *  [4] roughness   [5] index of refraction   [6..8] emitted radiance (Lambert only)
+ *  [9] 1: emission is multiplied by the emission texture at the surface (u, v)
+ * A vertex is specular (S) for a conductor or dielectric with roughness < 0.2 (Section 6.1);
+ * every other vertex is diffuse (D). Emitters emit on the front side of their triangles. */
+typedef struct {
+    int32_t n_tri;
+    const float *tri;        /* [n_tri * 9] v0, v1, v2; front = (v1-v0) x (v2-v0) */
+    const int32_t *tri_mat;  /* [n_tri] material index */
+    const float *tri_uv;     /* [n_tri * 6] per-vertex (u, v) */
+    int32_t n_mat;
+    const float *mats;       /* [n_mat * 16] */
+    int32_t tex_w, tex_h;
+    const float *tex;        /* [tex_h * tex_w] emission texture, row-major, nearest lookup */
+    const float *camera;     /* [10] position, target, up, vertical fov (degrees) */
+    int32_t width, height;   /* image size */
+    int32_t bvh_width;       /* 4 (only width 4 is built) */
+    int32_t max_light_paths; /* capacity for M, light sub-paths per iteration */
+} pt_scene_desc;
+
+/* Upload a scene: validates the arrays, builds a binned-SAH BVH on the host, collapses it to
+ * 4-wide 128-byte nodes, copies everything to the current device and allocates per-iteration
+ * workspaces sized for width x height pixels and max_light_paths light sub-paths. Host arrays
+ * may be freed on return. On success *out receives the handle. Synchronises hip_stream. */
+pt_status pt_scene_upload(const pt_scene_desc *desc, void *hip_stream, pt_scene **out);
+
+/* Free everything the scene owns. Synchronises the device first. NULL is a no-op. */
+pt_status pt_scene_release(pt_scene *s);
+
+/* Subspace construction (Section 3.2, SPCBPT's subspaces; Section 5.5's specular and control
+ * subspaces): pre-traces n_pretrace paths and clusters eye first-diffuse vertices and
+ * specular light vertices by (position, normal, incident direction) with k-means. Resets
+ * the selection matrix Gamma (Section 5.6) to uniform and clears all running statistics.
+ * Must be called once before pt_render_iteration. */
+typedef struct {
+    int32_t n_pretrace;      /* pre-traced samples (eye and light paths each) */
+    int32_t n_eye;           /* eye subspaces T (<= 4096) */
+    int32_t n_spec;          /* specular subspaces S (<= 4096) */
+    int32_t kmeans_iters;    /* Lloyd iterations */
+    uint32_t seed;
+} pt_subspace_params;
+pt_status pt_build_subspaces(pt_scene *s, const pt_subspace_params *p, void *hip_stream);
+
+/* flags of pt_iter_params */
+enum {
+    PT_FLAG_NEE = 1u << 0,          /* next-event estimation at non-Dirac eye vertices */
+    PT_FLAG_PROXY = 1u << 1,        /* proxy connections (class A = L S^u, class B = L D S^u) */
+    PT_FLAG_ONLY_PROXY_CLASS = 1u << 2,  /* score only paths the proxy strategy can build */
+    PT_FLAG_ONLY_OTHER = 1u << 3,   /* score only the other paths */
+    PT_FLAG_GAMMA = 1u << 4,        /* select incomplete sub-paths by Gamma[T, S] (else uniformly) */
+    PT_FLAG_TILES = 1u << 5,        /* 10x10-pixel tile gating of proxy attempts (Section 6.1) */
+    PT_FLAG_TIMING = 1u << 6,       /* time the extension kernels with HIP events into the stats */
+    PT_FLAG_COUNT = 1u << 7,        /* count BVH node visits and triangle tests of extension rays */
+    PT_FLAG_MIS = 1u << 8           /* variance-aware MIS for proxy paths (Section 5.4) */
+};
+
+typedef struct {
+    uint32_t iteration;      /* k: keys every random stream of this iteration */
+    uint32_t seed;
+    int32_t max_depth;       /* maximum number of segments of a full path (1 .. 127) */
+    int32_t n_light;         /* M light sub-paths (<= max_light_paths) */
+    int32_t cand_cap;        /* expected number of candidates kept per iteration (400) */
+    int32_t recip_repeats;   /* reciprocal estimates averaged per candidate (5) */
+    int32_t u_max;           /* longest specular run handled by the proxy strategy (<= 4) */
+    int32_t pilot;           /* minimum pilot samples per candidate (B and cost estimate) */
+    float cost_cap;          /* expected chain samples per candidate above which it is roulette-kept */
+    int32_t train_iters;     /* iterations during which Gamma and tile statistics learn (40) */
+    int32_t tile;            /* tile edge in pixels (10) */
+    float tile_threshold;    /* proxy share above which a tile always attempts (0.05) */
+    float tile_low_prob;     /* attempt probability of the other tiles (0.2) */
+    float defensive;         /* uniform fraction mixed into Gamma rows (0.1) */
+    uint32_t flags;
+} pt_iter_params;
+
+/* Host-visible per-iteration statistics (valid once the stream is synchronised when
+ * pt_render_iteration was given a non-NULL pointer; that call synchronises). */
+typedef struct {
+    double rays_extend_eye, rays_extend_light, rays_shadow, rays_proxy, rays_recip;
+    double n_cand, n_kept, n_recip_samples, n_recip_truncated;
+    double n_proxy_attempts, n_proxy_valid, n_nan;
+    double node_visits, tri_tests;   /* eye extension rays, when PT_FLAG_COUNT is set */
+    double ms_extend;                /* summed duration of the extension launches (PT_FLAG_TIMING) */
+    double n_extend_launches;
+} pt_iter_stats;
+
+/* One iteration: 1 sample per pixel of every estimator strategy, added into the CALLER-OWNED
+ * device buffers accum_rgb_dev[H*W*3] (+= the iteration's pixel value) and
+ * accum_sq_dev[H*W*3] (+= its square; may be NULL). Row-major, pixel (x, y) at y*W + x.
+ * stats may be NULL; when given, the call synchronises the stream and fills it. */
+pt_status pt_render_iteration(pt_scene *s, const pt_iter_params *p, float *accum_rgb_dev, float *accum_sq_dev,
+                              pt_iter_stats *stats, void *hip_stream);
+
+/* Reciprocal estimator (Section 4.2, RRS estimator with r = |g|, Appendix A). */
+enum { PT_RECIP_TABLE = 0, PT_RECIP_CANDIDATE = 1 };
+/* One incomplete light sub-path (Section 5.2): the kept specular vertex y_{s-1} and, for
+ * class B, the control vertex y_0 on an emitter. Triangle indices are input indices. */
+typedef struct {
+    int32_t cls;             /* 0: class A (L S^u), 1: class B (L D S^u) */
+    int32_t u;               /* 1 .. 4 */
+    float v[3];              /* y_{s-1} */
+    int32_t v_prim;
+    float hc[3];             /* y_0 (class B) */
+    int32_t hc_prim;         /* -1 for class A */
+    float hc_b1, hc_b2;      /* barycentrics of y_0 on hc_prim (emission texture lookup) */
+} pt_cand_desc;
+enum { PT_EST_ITILDE = 0, PT_EST_SIGN = 1 };
+typedef struct {
+    int32_t mode;            /* PT_RECIP_TABLE */
+    int32_t n;               /* table size */
+    const float *f_dev;      /* [n] target f(x) >= 0 */
+    const float *q_dev;      /* [n] supporting pmf q(x) > 0 where f > 0 (sums to 1) */
+    float B;                 /* the constant B > 0 (B >= max f/q: no splitting) */
+    int32_t n_est;           /* independent estimates of 1 / sum f */
+    int32_t estimator;       /* PT_EST_ITILDE or PT_EST_SIGN */
+    uint32_t seed;
+    uint32_t cap;            /* sample cap per estimate (0: 65536); hitting it marks the count */
+    /* PT_RECIP_CANDIDATE only (s required): the incomplete sub-path, in host memory; per =
+     * samples of f/q averaged into each plain Monte Carlo estimate of P written to out_p_dev[n_est]
+     * (device, may be NULL). f/q follows the supporting distribution of Section 5.3. */
+    const pt_cand_desc *cand;
+    int32_t per;
+    float *out_p_dev;
+} pt_recip_query;
+/* Writes out_est_dev[n_est] (float: estimates of 1 / sum f, or of 1 / P for a candidate) and
+ * out_nsamples_dev[n_est] (samples used; bit 31 set when the cap truncated that estimate).
+ * s may be NULL for PT_RECIP_TABLE. */
+pt_status pt_reciprocal_estimate(pt_scene *s, const pt_recip_query *q, float *out_est_dev,
+                                 uint32_t *out_nsamples_dev, void *hip_stream);
+
+/* Image = accum / n_iter, written to the caller-owned out_rgb_dev[H*W*3]. */
+pt_status pt_resolve_image(pt_scene *s, const float *accum_rgb_dev, uint32_t n_iter, float *out_rgb_dev,
+                           void *hip_stream);
+
+/* Test hook: closest-hit queries against the scene's BVH. rays_dev[n*8] = origin, direction,
+ * tmin, tmax (float); writes t_dev[n] (-1 on a miss) and prim_dev[n] (input triangle index or
+ * -1). Ties in t go to the lower input triangle index. */
+pt_status pt_trace_closest(pt_scene *s, const float *rays_dev, int32_t n, float *t_dev, int32_t *prim_dev,
+                           void *hip_stream);
+
+/* Message for the last non-OK return on this thread ("" if none). */
+const char *pt_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

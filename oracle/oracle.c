@@ -1452,6 +1452,29 @@ int or_render(void *sp, const or_params *p, double *sum, double *sumsq, or_stats
 /* vpos/vn: y_{s-1} and its triangle vprim; hc*: y_0 for class B. Writes n_est values of
  * the averaged f/q (a plain Monte Carlo estimate of P with `per` samples each) into
  * p_est, and n_est reciprocal estimates I~ with constant B into r_est. */
+typedef struct {
+    scene_t *s; cand_t *c; double B; int n_est, per; uint32_t seed;
+    double *p_est, *r_est, *r_ns; int trunc;
+} rc_job;
+static void rc_run(void *ctx, int unused)
+{
+    (void)unused;
+    rc_job *j = (rc_job *)ctx;
+    for (int e = 0; e < j->n_est; ++e) {
+        rng_t r;
+        rng_init(&r, j->seed, ST_TEST, (uint32_t)e, 1, 0);
+        cq_ctx cc = {j->s, j->c, 0};
+        double acc = 0;
+        for (int i = 0; i < j->per; ++i) acc += cand_fq(&cc, &r);
+        j->p_est[e] = acc / j->per;
+        rng_t r2;
+        rng_init(&r2, j->seed, ST_TEST, (uint32_t)e, 2, 0);
+        recip_ctx rc = {cand_fq, &cc, &r2, j->B, 0, 1L << 21, 0};
+        j->r_est[e] = itilde(&rc);
+        j->r_ns[e] = (double)rc.nsamp;
+        j->trunc += rc.truncated;
+    }
+}
 int or_recip_candidate(void *sp, int cls, int u, const double *vpos, int vprim, const double *hcpos, int hcprim,
                        double B, int n_est, int per, uint32_t seed, double *p_est, double *r_est, double *r_ns)
 {
@@ -1462,20 +1485,7 @@ int or_recip_candidate(void *sp, int cls, int u, const double *vpos, int vprim, 
     c.v.p = vmk(vpos[0], vpos[1], vpos[2]); c.v.prim = vprim; c.v.n = s->tri[vprim].n;
     c.v.is_s = 1;
     if (hcprim >= 0) { c.hc.p = vmk(hcpos[0], hcpos[1], hcpos[2]); c.hc.prim = hcprim; c.hc.n = s->tri[hcprim].n; }
-    int trunc = 0;
-    for (int e = 0; e < n_est; ++e) {
-        rng_t r;
-        rng_init(&r, seed, ST_TEST, (uint32_t)e, 1, 0);
-        cq_ctx cc = {s, &c, 0};
-        double acc = 0;
-        for (int i = 0; i < per; ++i) acc += cand_fq(&cc, &r);
-        p_est[e] = acc / per;
-        rng_t r2;
-        rng_init(&r2, seed, ST_TEST, (uint32_t)e, 2, 0);
-        recip_ctx rc = {cand_fq, &cc, &r2, B, 0, 1L << 22, 0};
-        r_est[e] = itilde(&rc);
-        r_ns[e] = (double)rc.nsamp;
-        trunc += rc.truncated;
-    }
-    return trunc;
+    rc_job j = {s, &c, B, n_est, per, seed, p_est, r_est, r_ns, 0};
+    parallel_for(1, 1, rc_run, &j);   /* on a pool thread: its large stack holds the recursion */
+    return j.trunc;
 }

@@ -1,0 +1,400 @@
+// Device-side building blocks of the gfx950 proxy-sampling BDPT path: float3 math, the
+// Philox4x32-10 counter-based generator, the three BSDFs in FP32, emitter sampling, and
+// the 4-wide BVH traversal (closest hit and any hit) with its stack in LDS.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "pt_layout.h"
+
+#define PT_PI 3.14159265358979323846f
+
+// ----------------------------------------------------------------------------- float3
+__device__ __forceinline__ float3 f3(float x, float y, float z) { return make_float3(x, y, z); }
+__device__ __forceinline__ float3 operator+(float3 a, float3 b) { return f3(a.x + b.x, a.y + b.y, a.z + b.z); }
+__device__ __forceinline__ float3 operator-(float3 a, float3 b) { return f3(a.x - b.x, a.y - b.y, a.z - b.z); }
+__device__ __forceinline__ float3 operator-(float3 a) { return f3(-a.x, -a.y, -a.z); }
+__device__ __forceinline__ float3 operator*(float3 a, float s) { return f3(a.x * s, a.y * s, a.z * s); }
+__device__ __forceinline__ float3 operator*(float3 a, float3 b) { return f3(a.x * b.x, a.y * b.y, a.z * b.z); }
+__device__ __forceinline__ float dot3(float3 a, float3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+__device__ __forceinline__ float3 cross3(float3 a, float3 b)
+{
+    return f3(a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x);
+}
+__device__ __forceinline__ float3 normalize3(float3 a) { return a * rsqrtf(dot3(a, a)); }
+__device__ __forceinline__ bool nonzero3(float3 a) { return a.x > 0.f || a.y > 0.f || a.z > 0.f; }
+__device__ __forceinline__ float3 xyz(float4 a) { return f3(a.x, a.y, a.z); }
+__device__ __forceinline__ float lum(float3 a) { return 0.2126f * a.x + 0.7152f * a.y + 0.0722f * a.z; }
+
+// ----------------------------------------------------------------------------- Philox4x32-10
+// Salmon et al. 2011: ten rounds; each round multiplies words 0 and 2 by fixed odd constants
+// (high/low halves of the 64-bit products), mixes with words 1 and 3 and the key, and the key
+// advances by the golden-ratio Weyl constants between rounds.
+struct Rng {
+    uint32_t k0, k1, c0, c1, c2, c3;
+    uint32_t b[4];
+    int pos;
+};
+__device__ __forceinline__ void philox10(uint32_t k0, uint32_t k1, uint32_t c0, uint32_t c1, uint32_t c2,
+                                         uint32_t c3, uint32_t out[4])
+{
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint32_t lo0 = 0xD2511F53u * c0, hi0 = __umulhi(0xD2511F53u, c0);
+        const uint32_t lo1 = 0xCD9E8D57u * c2, hi1 = __umulhi(0xCD9E8D57u, c2);
+        const uint32_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+        c0 = n0; c1 = lo1; c2 = n2; c3 = lo0;
+        k0 += 0x9E3779B9u; k1 += 0xBB67AE85u;
+    }
+    out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+// key = (seed, stream), counter = (a, b, c, block)
+__device__ __forceinline__ Rng rng_make(uint32_t seed, uint32_t stream, uint32_t a, uint32_t b, uint32_t c)
+{
+    Rng r;
+    r.k0 = seed; r.k1 = stream * 0x9E3779B1u + 0x7F4A7C15u;
+    r.c0 = a; r.c1 = b; r.c2 = c; r.c3 = 0;
+    r.pos = 4;
+    return r;
+}
+__device__ __forceinline__ uint32_t rng_u32(Rng &r)
+{
+    if (r.pos == 4) { philox10(r.k0, r.k1, r.c0, r.c1, r.c2, r.c3, r.b); r.c3++; r.pos = 0; }
+    // pos is uniform per thread but dynamic; select without indexing a private array
+    const uint32_t v = r.pos == 0 ? r.b[0] : r.pos == 1 ? r.b[1] : r.pos == 2 ? r.b[2] : r.b[3];
+    r.pos++;
+    return v;
+}
+// uniform float in [0, 1) with 24 random bits
+__device__ __forceinline__ float rng_f(Rng &r) { return (float)(rng_u32(r) >> 8) * (1.0f / 16777216.0f); }
+
+enum { S_LIGHT = 11, S_CAND = 12, S_PILOT = 13, S_RECIP = 14, S_EYE = 15, S_PROXY = 16, S_TABLE = 17,
+       S_ROUL = 18, S_PRE = 19, S_KMEANS = 20, S_TILE = 21 };
+
+// ----------------------------------------------------------------------------- frames
+// branchless orthonormal basis about a unit normal (Duff et al. 2017)
+__device__ __forceinline__ void basis(float3 n, float3 &t, float3 &b)
+{
+    const float s = copysignf(1.0f, n.z);
+    const float a = -1.0f / (s + n.z);
+    const float c = n.x * n.y * a;
+    t = f3(1.0f + s * n.x * n.x * a, s * c, -s * n.x);
+    b = f3(c, s + n.y * n.y * a, -n.y);
+}
+__device__ __forceinline__ float3 cos_hemi(float3 n, float u1, float u2)
+{
+    float3 t, b;
+    basis(n, t, b);
+    const float r = sqrtf(u1);
+    float sp, cp;
+    __sincosf(2.0f * PT_PI * u2, &sp, &cp);
+    const float z = sqrtf(fmaxf(0.0f, 1.0f - u1));
+    return normalize3(t * (r * cp) + b * (r * sp) + n * z);
+}
+
+// ----------------------------------------------------------------------------- materials
+__device__ __forceinline__ float schlick1(float f0, float c)
+{
+    const float m = 1.0f - c, m2 = m * m;
+    return f0 + (1.0f - f0) * m2 * m2 * m;
+}
+// exact dielectric reflectance for light going from index ei (the side of the incident
+// direction, cosine ci) to index et; writes the transmitted cosine
+__device__ __forceinline__ float fresnel_exact(float ci, float ei, float et, float &ct)
+{
+    const float eta = ei / et;
+    const float st2 = eta * eta * fmaxf(0.0f, 1.0f - ci * ci);
+    if (st2 >= 1.0f) { ct = 0.0f; return 1.0f; }
+    ct = sqrtf(1.0f - st2);
+    const float a = ei * ci, b = et * ct, c = et * ci, d = ei * ct;
+    const float rs = (a - b) / (a + b), rp = (c - d) / (c + d);
+    return 0.5f * (rs * rs + rp * rp);
+}
+// GGX normal distribution with the sine computed from the cross product (no 1 - cos^2)
+__device__ __forceinline__ float ggx_d(float alpha, float3 n, float3 h)
+{
+    const float c = dot3(n, h);
+    if (c <= 0.0f) return 0.0f;
+    const float3 x = cross3(n, h);
+    const float a2 = alpha * alpha;
+    const float den = c * c * a2 + dot3(x, x);
+    return a2 / (PT_PI * den * den);
+}
+__device__ __forceinline__ float ggx_g1(float alpha, float3 n, float3 w)
+{
+    const float c = dot3(n, w);
+    if (c <= 0.0f) return 0.0f;
+    const float3 x = cross3(n, w);
+    const float t2 = dot3(x, x) / (c * c);
+    return 2.0f / (1.0f + sqrtf(1.0f + alpha * alpha * t2));
+}
+
+__device__ __forceinline__ float3 bsdf_f(const MatDev &m, float3 n, float3 wo, float3 wi)
+{
+    const float co = dot3(n, wo), ci = dot3(n, wi);
+    if (m.type == MAT_LAMBERT) return co * ci > 0.0f ? m.rgb * (1.0f / PT_PI) : f3(0.f, 0.f, 0.f);
+    if (m.type == MAT_CONDUCTOR && !(m.flags & MF_DELTA)) {
+        if (co <= 0.0f || ci <= 0.0f) return f3(0.f, 0.f, 0.f);
+        const float3 h = normalize3(wo + wi);
+        const float k = ggx_d(m.alpha, n, h) * ggx_g1(m.alpha, n, wo) * ggx_g1(m.alpha, n, wi) / (4.0f * co * ci);
+        const float c = dot3(wi, h);
+        return f3(schlick1(m.rgb.x, c), schlick1(m.rgb.y, c), schlick1(m.rgb.z, c)) * k;
+    }
+    return f3(0.f, 0.f, 0.f);
+}
+__device__ __forceinline__ float bsdf_pdf(const MatDev &m, float3 n, float3 wo, float3 wi)
+{
+    const float co = dot3(n, wo), ci = dot3(n, wi);
+    if (m.type == MAT_LAMBERT) return co * ci > 0.0f ? fabsf(ci) * (1.0f / PT_PI) : 0.0f;
+    if (m.type == MAT_CONDUCTOR && !(m.flags & MF_DELTA)) {
+        if (co <= 0.0f || ci <= 0.0f) return 0.0f;
+        const float3 h = normalize3(wo + wi);
+        const float oh = dot3(wo, h);
+        return oh > 0.0f ? ggx_d(m.alpha, n, h) * dot3(n, h) / (4.0f * oh) : 0.0f;
+    }
+    return 0.0f;
+}
+
+struct BS {
+    float3 wi;
+    float3 w;       // f |cos| / pdf in the requested mode
+    float pdf;      // solid angle (smooth lobes) or lobe probability (Dirac)
+    bool ok, delta;
+};
+// radiance = true: wo faces the camera side and refraction scales by (eta_o / eta_i)^2;
+// false: wo faces the light side and refraction carries weight 1
+__device__ __forceinline__ BS bsdf_sample(const MatDev &m, float3 n, float3 wo, float u1, float u2, float u3,
+                                          bool radiance)
+{
+    BS s;
+    s.ok = false; s.delta = false; s.pdf = 0.0f; s.w = f3(0.f, 0.f, 0.f); s.wi = f3(0.f, 0.f, 1.f);
+    const float co = dot3(n, wo);
+    if (m.type == MAT_LAMBERT) {
+        if (co == 0.0f) return s;
+        const float3 ns = co > 0.0f ? n : -n;
+        s.wi = cos_hemi(ns, u1, u2);
+        const float ci = dot3(ns, s.wi);
+        if (ci <= 0.0f) return s;
+        s.pdf = ci * (1.0f / PT_PI);
+        s.w = m.rgb;
+        s.ok = true;
+        return s;
+    }
+    if (m.type == MAT_CONDUCTOR) {
+        if (co <= 0.0f) return s;
+        if (m.flags & MF_DELTA) {
+            s.wi = n * (2.0f * co) - wo;
+            s.w = f3(schlick1(m.rgb.x, co), schlick1(m.rgb.y, co), schlick1(m.rgb.z, co));
+            s.pdf = 1.0f; s.delta = true; s.ok = true;
+            return s;
+        }
+        const float t2 = m.alpha * m.alpha * u1 / (1.0f - u1);
+        const float ch = rsqrtf(1.0f + t2), sh = sqrtf(t2) * ch;
+        float sp, cp;
+        __sincosf(2.0f * PT_PI * u2, &sp, &cp);
+        float3 t, b;
+        basis(n, t, b);
+        const float3 h = normalize3(t * (sh * cp) + b * (sh * sp) + n * ch);
+        const float oh = dot3(wo, h);
+        if (oh <= 0.0f) return s;
+        s.wi = h * (2.0f * oh) - wo;
+        const float ci = dot3(n, s.wi);
+        if (ci <= 0.0f) return s;
+        s.pdf = bsdf_pdf(m, n, wo, s.wi);
+        if (!(s.pdf > 0.0f)) return s;
+        s.w = bsdf_f(m, n, wo, s.wi) * (ci / s.pdf);
+        s.ok = true;
+        return s;
+    }
+    // smooth dielectric; the geometric normal points outside (index 1)
+    if (co == 0.0f) return s;
+    const bool out = co > 0.0f;
+    const float3 ns = out ? n : -n;
+    const float eo = out ? 1.0f : m.ior, ei = out ? m.ior : 1.0f;
+    const float c = fabsf(co);
+    float ct;
+    const float F = fresnel_exact(c, eo, ei, ct);
+    s.delta = true; s.ok = true;
+    if (u1 < F) {
+        s.wi = ns * (2.0f * c) - wo;
+        s.pdf = F;
+        s.w = f3(1.f, 1.f, 1.f);
+    } else {
+        const float r = eo / ei;
+        s.wi = normalize3(wo * (-r) + ns * (r * c - ct));
+        s.pdf = 1.0f - F;
+        const float k = radiance ? r * r : 1.0f;
+        s.w = f3(k, k, k);
+    }
+    return s;
+}
+// discrete lobe probability of a Dirac vertex mapping wa to wb
+__device__ __forceinline__ float dirac_prob(const MatDev &m, float3 n, float3 wa, float3 wb)
+{
+    const float ca = dot3(n, wa);
+    if (m.type == MAT_CONDUCTOR) return (ca > 0.0f && dot3(n, wb) > 0.0f) ? 1.0f : 0.0f;
+    if (ca == 0.0f) return 0.0f;
+    const bool out = ca > 0.0f;
+    float ct;
+    const float F = fresnel_exact(fabsf(ca), out ? 1.0f : m.ior, out ? m.ior : 1.0f, ct);
+    return ca * dot3(n, wb) > 0.0f ? F : 1.0f - F;
+}
+// refractive index of the medium on the side of w at a surface of material m
+__device__ __forceinline__ float side_eta(const MatDev &m, float3 n, float3 w)
+{
+    return (m.type == MAT_DIELECTRIC && dot3(n, w) < 0.0f) ? m.ior : 1.0f;
+}
+
+// ----------------------------------------------------------------------------- scene access
+struct SceneDev {
+    const BNode *__restrict__ nodes;
+    const TriIsect *__restrict__ tris;     // BVH order
+    const TriShade *__restrict__ shade;    // BVH order
+    const MatDev *__restrict__ mats;
+    const float *__restrict__ tex;
+    int tex_w, tex_h;
+    const int *__restrict__ em_tri;        // emissive triangles (BVH order)
+    const float *__restrict__ em_cdf;      // normalised cumulative areas
+    int n_em;
+    float em_area;
+    float tmin;
+    CamDev cam;
+};
+
+__device__ __forceinline__ float3 emission(const SceneDev &S, int tri, float b1, float b2, float3 w_out)
+{
+    const TriShade &sh = S.shade[tri];
+    const MatDev &m = S.mats[sh.mat];
+    if (!(m.flags & MF_EMIT) || dot3(sh.n, w_out) <= 0.0f) return f3(0.f, 0.f, 0.f);
+    float k = 1.0f;
+    if (m.flags & MF_TEXTURED) {
+        const float b0 = 1.0f - b1 - b2;
+        const float u = b0 * sh.uv[0] + b1 * sh.uv[2] + b2 * sh.uv[4];
+        const float v = b0 * sh.uv[1] + b1 * sh.uv[3] + b2 * sh.uv[5];
+        const int ix = min(max((int)floorf(u * S.tex_w), 0), S.tex_w - 1);
+        const int iy = min(max((int)floorf(v * S.tex_h), 0), S.tex_h - 1);
+        k = S.tex[iy * S.tex_w + ix];
+    }
+    return m.le * k;
+}
+
+struct LPoint { float3 p, n; int tri; float b1, b2; };
+__device__ __forceinline__ LPoint sample_emitter(const SceneDev &S, float u0, float u1, float u2)
+{
+    int lo = 0, hi = S.n_em - 1;
+    while (lo < hi) { const int mid = (lo + hi) >> 1; if (S.em_cdf[mid] > u0) hi = mid; else lo = mid + 1; }
+    LPoint L;
+    L.tri = S.em_tri[lo];
+    const TriIsect &t = S.tris[L.tri];
+    const float su = sqrtf(u1);
+    L.b1 = su * (1.0f - u2); L.b2 = su * u2;
+    L.p = f3(t.v0[0], t.v0[1], t.v0[2]) + f3(t.e1[0], t.e1[1], t.e1[2]) * L.b1 + f3(t.e2[0], t.e2[1], t.e2[2]) * L.b2;
+    L.n = S.shade[L.tri].n;
+    return L;
+}
+__device__ __forceinline__ float3 tri_point(const SceneDev &S, int tri, float b1, float b2)
+{
+    const TriIsect &t = S.tris[tri];
+    return f3(t.v0[0], t.v0[1], t.v0[2]) + f3(t.e1[0], t.e1[1], t.e1[2]) * b1 + f3(t.e2[0], t.e2[1], t.e2[2]) * b2;
+}
+
+// ----------------------------------------------------------------------------- traversal
+struct Hit { float t, b1, b2; int tri; };
+
+// Moller-Trumbore in FP32
+__device__ __forceinline__ bool isect(const TriIsect &T, float3 o, float3 d, float tmin, float tmax, float &t,
+                                      float &b1, float &b2)
+{
+    const float3 e1 = f3(T.e1[0], T.e1[1], T.e1[2]), e2 = f3(T.e2[0], T.e2[1], T.e2[2]);
+    const float3 pv = cross3(d, e2);
+    const float det = dot3(e1, pv);
+    if (det == 0.0f) return false;
+    const float inv = 1.0f / det;
+    const float3 tv = o - f3(T.v0[0], T.v0[1], T.v0[2]);
+    b1 = dot3(tv, pv) * inv;
+    if (b1 < 0.0f || b1 > 1.0f) return false;
+    const float3 qv = cross3(tv, e1);
+    b2 = dot3(d, qv) * inv;
+    if (b2 < 0.0f || b1 + b2 > 1.0f) return false;
+    t = dot3(e2, qv) * inv;
+    return t > tmin && t < tmax;
+}
+
+// The traversal stack lives in LDS, column-major (entry k of thread i at k * nthreads + i) so
+// that a wavefront's pushes and pops hit 64 different banks.
+template <bool ANY, bool COUNT>
+__device__ __forceinline__ bool traverse(const SceneDev &S, float3 o, float3 d, float tmin, float tmax, int ign0,
+                                         int ign1, int *stk, int stride, Hit &h, uint32_t *visits = nullptr,
+                                         uint32_t *tests = nullptr)
+{
+    const float3 inv = f3(1.0f / d.x, 1.0f / d.y, 1.0f / d.z);
+    const float3 oi = o * inv;
+    h.tri = -1; h.t = tmax;
+    int sp = 0;
+    int node = 0;
+    for (;;) {
+        const BNode &N = S.nodes[node];
+        if (COUNT) (*visits)++;
+        // slab tests of the four children
+        const float4 lx = *(const float4 *)N.lo_x, hx = *(const float4 *)N.hi_x;
+        const float4 ly = *(const float4 *)N.lo_y, hy = *(const float4 *)N.hi_y;
+        const float4 lz = *(const float4 *)N.lo_z, hz = *(const float4 *)N.hi_z;
+        const int4 ch = *(const int4 *)N.child;
+        const int4 cn = *(const int4 *)N.count;
+        float tn[4];
+        bool hitc[4];
+        const float lxa[4] = {lx.x, lx.y, lx.z, lx.w}, hxa[4] = {hx.x, hx.y, hx.z, hx.w};
+        const float lya[4] = {ly.x, ly.y, ly.z, ly.w}, hya[4] = {hy.x, hy.y, hy.z, hy.w};
+        const float lza[4] = {lz.x, lz.y, lz.z, lz.w}, hza[4] = {hz.x, hz.y, hz.z, hz.w};
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const float ax = lxa[k] * inv.x - oi.x, bx = hxa[k] * inv.x - oi.x;
+            const float ay = lya[k] * inv.y - oi.y, by = hya[k] * inv.y - oi.y;
+            const float az = lza[k] * inv.z - oi.z, bz = hza[k] * inv.z - oi.z;
+            const float t0 = fmaxf(fmaxf(fminf(ax, bx), fminf(ay, by)), fmaxf(fminf(az, bz), 0.0f));
+            const float t1 = fminf(fminf(fmaxf(ax, bx), fmaxf(ay, by)), fminf(fmaxf(az, bz), h.t));
+            hitc[k] = t0 <= t1 * 1.00000024f;
+            tn[k] = t0;
+        }
+        const int cha[4] = {ch.x, ch.y, ch.z, ch.w}, cna[4] = {cn.x, cn.y, cn.z, cn.w};
+        // leaves: test their triangles now
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            if (hitc[k] && cna[k] > 0) {
+                for (int i = cha[k]; i < cha[k] + cna[k]; ++i) {
+                    const TriIsect &T = S.tris[i];
+                    if (COUNT) (*tests)++;
+                    const int pid = T.prim;
+                    if (i == ign0 || i == ign1) continue;
+                    float t, b1, b2;
+                    if (isect(T, o, d, tmin, tmax, t, b1, b2)) {
+                        if (t < h.t || (t == h.t && h.tri >= 0 && pid < S.tris[h.tri].prim)) {
+                            h.t = t; h.b1 = b1; h.b2 = b2; h.tri = i;
+                            if (ANY) return true;
+                        }
+                    }
+                }
+            }
+        }
+        // inner children: push far-to-near so the nearest is popped first
+        int idx[4];
+        int n = 0;
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            if (hitc[k] && cna[k] == 0 && cha[k] >= 0 && tn[k] <= h.t) idx[n++] = k;
+        // insertion sort by descending entry distance (n <= 4)
+        for (int a = 1; a < n; ++a) {
+            const int v = idx[a];
+            int b = a - 1;
+            while (b >= 0 && tn[idx[b]] < tn[v]) { idx[b + 1] = idx[b]; --b; }
+            idx[b + 1] = v;
+        }
+        // the stack holds PT_STACK entries; a 4-wide tree needs at most 3 per level, so a push
+        // beyond it can only come from a malformed tree and is dropped
+        for (int a = 0; a < n; ++a)
+            if (sp < PT_STACK) stk[(sp++) * stride] = cha[idx[a]];
+        if (sp == 0) break;
+        node = stk[(--sp) * stride];
+    }
+    return h.tri >= 0;
+}

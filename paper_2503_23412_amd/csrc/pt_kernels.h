@@ -1,0 +1,898 @@
+// gfx950 kernels of one proxy-sampling BDPT iteration.
+//
+// Light pass (Section 3.1's tracing pdf chain): k_light_gen -> (k_extend -> k_light_shade) per
+// vertex, wavefront queues compacted with ballot + mbcnt, light vertices stored SoA.
+// Candidates (Sections 5.1 and 6.1): k_candidates -> k_keep.
+// Reciprocal estimates of 1/P (Sections 4.2, 5.2, 5.3): k_pilot -> k_roulette -> k_recip.
+// Eye pass: k_camera -> (k_extend -> k_eye_shade -> k_occluded) per depth, then k_proxy
+// (Section 5.1's retrace) and k_accumulate.
+#pragma once
+#include "pt_device.h"
+
+#define WG 128   // workgroup size of the traversal kernels (LDS stack 128 x 48 x 4 B = 24 KB)
+
+__device__ __forceinline__ int fbits(float f) { return __float_as_int(f); }
+__device__ __forceinline__ float ibits(int i) { return __int_as_float(i); }
+
+// Wave-aggregated queue push: one atomic per wavefront, slots from the ballot prefix (mbcnt).
+// Every lane of the wavefront must call it.
+__device__ __forceinline__ int wave_push(unsigned long long *counter, bool pred)
+{
+    const unsigned long long mask = __ballot(pred);
+    const int lane = __lane_id();
+    const uint32_t below = __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+    int base = 0;
+    if (mask) {
+        const int leader = __ffsll((long long)mask) - 1;
+        if (lane == leader) base = (int)atomicAdd(counter, (unsigned long long)__popcll(mask));
+        base = __shfl(base, leader);
+    }
+    return pred ? base + (int)below : -1;
+}
+__device__ __forceinline__ void wave_count(unsigned long long *counter, uint32_t v)
+{
+    // sum over the wavefront, one atomic
+    uint32_t s = v;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+    if (__lane_id() == 0 && s) atomicAdd(counter, (unsigned long long)s);
+}
+__device__ __forceinline__ void atomic_add3(float *p, float3 v)
+{
+    if (v.x != 0.0f) unsafeAtomicAdd(p + 0, v.x);
+    if (v.y != 0.0f) unsafeAtomicAdd(p + 1, v.y);
+    if (v.z != 0.0f) unsafeAtomicAdd(p + 2, v.z);
+}
+// max of non-negative floats through their integer bit patterns
+__device__ __forceinline__ void atomic_maxf(float *p, float v)
+{
+    if (v > 0.0f) atomicMax((int *)p, __float_as_int(v));
+}
+
+// ---------------------------------------------------------------------------------- queues
+__global__ void k_zero(unsigned long long *cnt, int n)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) cnt[i] = 0ull;
+}
+
+// closest hit for every queued ray; rays live in (ro, rd) by path id, ro.w = ignored triangle,
+// rd.w = tmax; writes hit[pid] = (t, b1, b2, triangle or -1)
+template <bool COUNT>
+__global__ void __launch_bounds__(WG) k_extend(SceneDev S, const uint32_t *__restrict__ q,
+                                               const unsigned long long *__restrict__ cnt, int cidx,
+                                               const float4 *__restrict__ ro, const float4 *__restrict__ rd,
+                                               float4 *__restrict__ hit, unsigned long long *stats, int ray_ctr)
+{
+    __shared__ int stk[PT_STACK * WG];
+    const int i = blockIdx.x * WG + threadIdx.x;
+    const int n = (int)cnt[cidx];
+    uint32_t visits = 0, tests = 0;
+    const bool act = i < n;
+    if (act) {
+        const int pid = q[i];
+        const float4 o = ro[pid], d = rd[pid];
+        Hit h;
+        traverse<false, COUNT>(S, xyz(o), xyz(d), S.tmin, d.w, fbits(o.w), -1, stk + threadIdx.x, WG, h, &visits, &tests);
+        hit[pid] = make_float4(h.t, h.b1, h.b2, ibits(h.tri));
+    }
+    wave_count(stats + ray_ctr, act ? 1u : 0u);
+    if (COUNT) { wave_count(stats + C_VISITS, visits); wave_count(stats + C_TESTS, tests); }
+}
+
+// ---------------------------------------------------------------------------------- light pass
+struct LightBuf {
+    float4 *ro, *rd, *hit;
+    float4 *lv;          // [PT_LMAX * M]: position, w = triangle
+    float2 *lb0;         // [M]: barycentrics of y_0
+    uint32_t *sig;       // [M]: bits 0..5 = vertex i specular, bits 8..11 = vertex count
+    uint32_t *q[2];
+    int M;
+};
+
+__global__ void k_light_gen(SceneDev S, LightBuf L, uint32_t seed, uint32_t iter, unsigned long long *cnt)
+{
+    const int l = blockIdx.x * blockDim.x + threadIdx.x;
+    if (l == 0) cnt[C_LIGHT_Q0] = (unsigned long long)L.M;
+    if (l >= L.M) return;
+    Rng r = rng_make(seed, S_LIGHT, (uint32_t)l, iter, 0u);
+    const float u0 = rng_f(r), u1 = rng_f(r), u2 = rng_f(r);
+    const LPoint y0 = sample_emitter(S, u0, u1, u2);
+    const float3 w = cos_hemi(y0.n, rng_f(r), rng_f(r));
+    L.lv[l] = make_float4(y0.p.x, y0.p.y, y0.p.z, ibits(y0.tri));
+    L.lb0[l] = make_float2(y0.b1, y0.b2);
+    L.sig[l] = 1u << 8;
+    L.ro[l] = make_float4(y0.p.x, y0.p.y, y0.p.z, ibits(y0.tri));
+    L.rd[l] = make_float4(w.x, w.y, w.z, 3.0e38f);
+    L.q[0][l] = (uint32_t)l;
+}
+
+// vertex `vi` of every queued light path: store it and sample the adjoint BSDF for the next
+__global__ void k_light_shade(SceneDev S, LightBuf L, uint32_t seed, uint32_t iter, int vi, int lmax,
+                              unsigned long long *cnt)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int n = (int)cnt[C_LIGHT_Q0 + vi - 1];
+    const uint32_t *qin = L.q[(vi - 1) & 1];
+    uint32_t *qout = L.q[vi & 1];
+    bool cont = false;
+    int pid = 0;
+    if (i < n) {
+        pid = qin[i];
+        const float4 h = L.hit[pid];
+        const int tri = fbits(h.w);
+        if (tri >= 0) {
+            const float4 o = L.ro[pid], d = L.rd[pid];
+            const float3 x = xyz(o) + xyz(d) * h.x;
+            const TriShade &sh = S.shade[tri];
+            const MatDev &m = S.mats[sh.mat];
+            L.lv[vi * L.M + pid] = make_float4(x.x, x.y, x.z, ibits(tri));
+            uint32_t sg = L.sig[pid];
+            if (m.flags & MF_SPEC) sg |= 1u << vi;
+            sg = (sg & 0xFFu) | ((uint32_t)(vi + 1) << 8);
+            L.sig[pid] = sg;
+            if (vi + 1 < lmax) {
+                Rng r = rng_make(seed, S_LIGHT, (uint32_t)pid, iter, (uint32_t)vi);
+                const float a = rng_f(r), b = rng_f(r), c = rng_f(r);
+                const BS bs = bsdf_sample(m, sh.n, -xyz(d), a, b, c, false);
+                if (bs.ok) {
+                    L.ro[pid] = make_float4(x.x, x.y, x.z, ibits(tri));
+                    L.rd[pid] = make_float4(bs.wi.x, bs.wi.y, bs.wi.z, 3.0e38f);
+                    cont = true;
+                }
+            }
+        }
+    }
+    const int slot = wave_push(cnt + C_LIGHT_Q0 + vi, cont);
+    if (cont) qout[slot] = (uint32_t)pid;
+}
+
+// ---------------------------------------------------------------------------------- candidates
+// Every prefix ending at a specular vertex whose trailing specular run (length u <= u_max)
+// starts at y_1 (class A, L S^u) or at y_2 after a diffuse y_1 (class B, L D S^u, control
+// vertex y_0 on the light) is a candidate (Section 5.1; Section 6.1's restrictions).
+__global__ void k_candidates(LightBuf L, int u_max, Cand *cand, unsigned long long *cnt)
+{
+    const int l = blockIdx.x * blockDim.x + threadIdx.x;
+    int nc = 0, cls = 0, first = 0;
+    uint32_t sg = 0;
+    if (l < L.M) {
+        sg = L.sig[l];
+        const int nv = (int)(sg >> 8) & 0xF;
+        if (nv >= 2) {
+            cls = (sg & 2u) ? 0 : 1;
+            first = cls == 0 ? 1 : 2;
+            for (int i = first; i < nv && (sg & (1u << i)) && i - first + 1 <= u_max; ++i) nc++;
+        }
+    }
+    // wavefront exclusive scan of the counts
+    int incl = nc;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const int v = __shfl_up(incl, off);
+        if (__lane_id() >= off) incl += v;
+    }
+    const int total = __shfl(incl, 63);
+    int base = 0;
+    if (__lane_id() == 63 && total) base = (int)atomicAdd(cnt + C_NCAND, (unsigned long long)total);
+    base = __shfl(base, 63);
+    int o = base + incl - nc;
+    for (int k = 0; k < nc; ++k) {
+        const int vi = first + k;
+        Cand c;
+        c.v = L.lv[vi * L.M + l];
+        c.hc = L.lv[l];
+        const float2 b = L.lb0[l];
+        c.hc_b1 = b.x; c.hc_b2 = b.y;
+        c.cls_u = (cls << 8) | (k + 1);
+        c.B = 0.f; c.rho = 1.f; c.recip_sum = 0.f; c.pmax = 0.f; c.psum = 0.f; c.pn = 0.f; c.spec_sub = 0;
+        c.pad[0] = c.pad[1] = 0.f;
+        cand[o + k] = c;
+    }
+}
+
+// keep each candidate with probability pi_inc = min(1, cap / n_cand) (Horvitz-Thompson form of
+// Section 6.1's cap of 400 incomplete sub-paths)
+__global__ void k_keep(int cap, uint32_t seed, uint32_t iter, uint32_t *kept, int max_cand, unsigned long long *cnt)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int n = (int)cnt[C_NCAND];
+    bool keep = false;
+    if (i < n && i < max_cand) {
+        const float pi = fminf(1.0f, (float)cap / (float)n);
+        Rng r = rng_make(seed, S_CAND, (uint32_t)i, iter, 0u);
+        keep = pi >= 1.0f || rng_f(r) < pi;
+    }
+    const int slot = wave_push(cnt + C_NKEPT, keep);
+    if (keep) kept[slot] = (uint32_t)i;
+}
+
+// ---------------------------------------------------------------------------------- f/q samples
+// One sample of f(g)/q(g) for the candidate (Sections 5.2-5.3). f is the light tracer's own
+// density of the dropped vertices g and of y_{s-1} (visibility and the S/D signature
+// included); q is the uniform mixture of the available strategies: light-source sampling
+// (u = 1, class A), tracing from the control vertex (u = 1, class B; cosine lobe at the light
+// vertex), tracing from y_{s-1} (cosine hemisphere, each side with probability 1/2 on a
+// dielectric, then the BSDF at every intermediate vertex).
+struct Ctx {
+    const SceneDev &S;
+    int *stk;        // this thread's column of the workgroup's LDS stack
+    uint32_t rays;
+    int stride;      // threads per workgroup = distance between a thread's stack entries
+};
+
+__device__ __forceinline__ bool occluded(Ctx &C, float3 a, int ta, float3 b, int tb)
+{
+    const float3 d = b - a;
+    const float dist = sqrtf(dot3(d, d));
+    Hit h;
+    C.rays++;
+    return traverse<true, false>(C.S, a, d * (1.0f / dist), C.S.tmin, dist * 0.9999f, ta, tb, C.stk, C.stride, h);
+}
+__device__ __forceinline__ bool closest(Ctx &C, float3 o, float3 d, int ign, Hit &h)
+{
+    C.rays++;
+    return traverse<false, false>(C.S, o, d, C.S.tmin, 3.0e38f, ign, -1, C.stk, C.stride, h);
+}
+// cosine direction at y_{s-1}: on a dielectric each side with probability 1/2, else the front
+__device__ __forceinline__ float3 spec_start(const MatDev &m, float3 n, Rng &r, float &side_p)
+{
+    float3 ns = n;
+    side_p = 1.0f;
+    if (m.type == MAT_DIELECTRIC) { side_p = 0.5f; if (rng_f(r) < 0.5f) ns = -n; }
+    const float a = rng_f(r), b = rng_f(r);
+    return cos_hemi(ns, a, b);
+}
+__device__ __forceinline__ float side_prob(const MatDev &m, float3 n, float3 w)
+{
+    return m.type == MAT_DIELECTRIC ? 0.5f : (dot3(n, w) > 0.0f ? 1.0f : 0.0f);
+}
+
+__device__ float fq_sample(Ctx &C, const Cand &c, Rng &r)
+{
+    const SceneDev &S = C.S;
+    const int cls = c.cls_u >> 8, u = c.cls_u & 0xFF;
+    const float3 v = xyz(c.v);
+    const int vt = fbits(c.v.w);
+    const float3 vn = S.shade[vt].n;
+    const MatDev mv = S.mats[S.shade[vt].mat];
+    const float invA = 1.0f / S.em_area;
+    if (u == 1) {
+        const bool from_spec = rng_f(r) >= 0.5f;
+        if (cls == 0) {
+            float3 y, ny;
+            if (!from_spec) {
+                const float a = rng_f(r), b = rng_f(r), d = rng_f(r);
+                const LPoint L = sample_emitter(S, a, b, d);
+                if (occluded(C, L.p, L.tri, v, vt)) return 0.0f;
+                y = L.p; ny = L.n;
+            } else {
+                float sp;
+                const float3 w = spec_start(mv, vn, r, sp);
+                Hit h;
+                if (!closest(C, v, w, vt, h)) return 0.0f;
+                if (!(S.mats[S.shade[h.tri].mat].flags & MF_EMIT)) return 0.0f;
+                y = tri_point(S, h.tri, h.b1, h.b2); ny = S.shade[h.tri].n;
+            }
+            const float3 dv = v - y;
+            const float d2 = dot3(dv, dv);
+            const float3 w = dv * rsqrtf(d2);
+            const float c0 = dot3(ny, w), cv = fabsf(dot3(vn, w));
+            const float f = c0 > 0.0f ? invA * (c0 / PT_PI) * cv / d2 : 0.0f;
+            const float q3 = side_prob(mv, vn, -w) * (cv / PT_PI) * fabsf(c0) / d2;
+            return f / (0.5f * (invA + q3));
+        }
+        // class B: g = y_1 (diffuse), control vertex y_0 on the light
+        const float3 y0 = xyz(c.hc);
+        const int t0 = fbits(c.hc.w);
+        const float3 n0 = S.shade[t0].n;
+        Hit h;
+        if (!from_spec) {
+            const float a = rng_f(r), b = rng_f(r);
+            if (!closest(C, y0, cos_hemi(n0, a, b), t0, h)) return 0.0f;
+            if (S.mats[S.shade[h.tri].mat].flags & MF_SPEC) return 0.0f;
+            if (occluded(C, tri_point(S, h.tri, h.b1, h.b2), h.tri, v, vt)) return 0.0f;
+        } else {
+            float sp;
+            const float3 w = spec_start(mv, vn, r, sp);
+            if (!closest(C, v, w, vt, h)) return 0.0f;
+            if (S.mats[S.shade[h.tri].mat].flags & MF_SPEC) return 0.0f;
+            if (occluded(C, y0, t0, tri_point(S, h.tri, h.b1, h.b2), h.tri)) return 0.0f;
+        }
+        const float3 y1 = tri_point(S, h.tri, h.b1, h.b2);
+        const float3 n1 = S.shade[h.tri].n;
+        const MatDev m1 = S.mats[S.shade[h.tri].mat];
+        const float3 a = y1 - y0;
+        const float d01 = dot3(a, a);
+        const float3 w01 = a * rsqrtf(d01);
+        const float3 b = v - y1;
+        const float d1v = dot3(b, b);
+        const float3 w1v = b * rsqrtf(d1v);
+        const float c0 = dot3(n0, w01);
+        const float p1 = c0 > 0.0f ? (c0 / PT_PI) * fabsf(dot3(n1, w01)) / d01 : 0.0f;
+        const float cv = fabsf(dot3(vn, w1v));
+        const float f = p1 * bsdf_pdf(m1, n1, -w01, w1v) * cv / d1v;
+        const float q3 = side_prob(mv, vn, -w1v) * (cv / PT_PI) * fabsf(dot3(n1, w1v)) / d1v;
+        return f / (0.5f * (p1 + q3));
+    }
+    // u >= 2: trace from y_{s-1} only. Dirac vertices enter through their lobe probabilities;
+    // the solid angle at each smooth vertex is carried to area at the next smooth vertex, and
+    // only the ratio of the two directions' Jacobians, (eta_b^2 |cos b|) / (eta_a^2 |cos a|),
+    // survives in f/q (etendue is conserved along a Dirac run).
+    float sp;
+    float3 w = spec_start(mv, vn, r, sp);
+    float q = sp * fabsf(dot3(vn, w)) / PT_PI;
+    float f = 1.0f;
+    {
+        const float e = side_eta(mv, vn, w);
+        f *= e * e * fabsf(dot3(vn, w));   // numerator of the run leaving y_{s-1}
+    }
+    float3 x = v;
+    int xt = vt;
+    for (int k = 1; k <= u; ++k) {
+        Hit h;
+        if (!closest(C, x, w, xt, h)) return 0.0f;
+        const float3 y = tri_point(S, h.tri, h.b1, h.b2);
+        const float3 ny = S.shade[h.tri].n;
+        const MatDev m = S.mats[S.shade[h.tri].mat];
+        const float3 w_cam = -w;          // toward y_{s-1}
+        if (k < u) {
+            if (!(m.flags & MF_SPEC)) return 0.0f;
+            const float a = rng_f(r), b = rng_f(r), cc = rng_f(r);
+            const BS bs = bsdf_sample(m, ny, w_cam, a, b, cc, true);
+            if (!bs.ok) return 0.0f;
+            q *= bs.pdf;
+            const float3 w_light = bs.wi;
+            if (m.flags & MF_DELTA) {
+                f *= dirac_prob(m, ny, w_light, w_cam);
+            } else {
+                // close the run arriving here, account the forward density, open the next run
+                const float ea = side_eta(m, ny, w_cam);
+                f /= ea * ea * fabsf(dot3(ny, w_cam));
+                f *= bsdf_pdf(m, ny, w_light, w_cam);
+                const float eb = side_eta(m, ny, w_light);
+                f *= eb * eb * fabsf(dot3(ny, w_light));
+            }
+            if (!(f > 0.0f)) return 0.0f;
+            w = w_light;
+        } else {
+            const float ea = side_eta(m, ny, w_cam);
+            f /= ea * ea * fabsf(dot3(ny, w_cam));
+            if (cls == 0) {
+                if (!(m.flags & MF_EMIT)) return 0.0f;
+                const float c0 = dot3(ny, w_cam);
+                if (c0 <= 0.0f) return 0.0f;
+                f *= (1.0f / S.em_area) * c0 / PT_PI;
+            } else {
+                if (m.flags & MF_SPEC) return 0.0f;
+                const float3 y0 = xyz(c.hc);
+                const int t0 = fbits(c.hc.w);
+                const float3 n0 = S.shade[t0].n;
+                const float3 a = y - y0;
+                const float d2 = dot3(a, a);
+                const float3 w01 = a * rsqrtf(d2);
+                const float c0 = dot3(n0, w01);
+                if (c0 <= 0.0f) return 0.0f;
+                if (occluded(C, y0, t0, y, h.tri)) return 0.0f;
+                f *= (c0 / PT_PI) * fabsf(dot3(ny, w01)) / d2;
+                f *= bsdf_pdf(m, ny, -w01, w_cam);
+            }
+        }
+        x = y; xt = h.tri;
+    }
+    return f > 0.0f ? f / q : 0.0f;
+}
+
+// The pilot and the chains run one wavefront per candidate / chain: each step the 64 lanes
+// draw 64 i.i.d. samples of f/q (sample index = step * 64 + lane, each with its own Philox
+// counter), and the wavefront then consumes them in order with a uniform scalar loop. Samples
+// are i.i.d. whatever the chain's state, so drawing them ahead of need changes nothing but the
+// number of discarded draws (fewer than 64 per chain).
+#define RW 4                       // wavefronts per workgroup
+__device__ __forceinline__ float lane_get(float v, int l) { return __shfl(v, l); }
+
+// pilot: 64-sample steps until at least `pilot` samples with 8 non-zero values, or 256 samples
+__global__ void __launch_bounds__(64 * RW) k_pilot(SceneDev S, Cand *cand, const uint32_t *kept, int pilot,
+                                                   uint32_t seed, uint32_t iter, float *runmax,
+                                                   unsigned long long *cnt)
+{
+    __shared__ int stk[PT_STACK * 64 * RW];
+    const int wave = blockIdx.x * RW + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    const int n = (int)cnt[C_NKEPT];
+    Ctx C{S, stk + threadIdx.x, 0u, (int)blockDim.x};
+    if (wave < n) {   // wave-uniform
+        Cand &c = cand[kept[wave]];
+        float mx = 0.f, sm = 0.f;
+        int nz = 0, k = 0;
+        const int maxn = max(256, pilot);
+        for (int step = 0; k < maxn; ++step) {
+            Rng r = rng_make(seed, S_PILOT, (uint32_t)wave, iter, (uint32_t)(step * 64 + lane));
+            const float v = fq_sample(C, c, r);
+            float wm = v, ws = v;
+            int wz = v > 0.0f ? 1 : 0;
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) {
+                wm = fmaxf(wm, __shfl_xor(wm, off));
+                ws += __shfl_xor(ws, off);
+                wz += __shfl_xor(wz, off);
+            }
+            mx = fmaxf(mx, wm); sm += ws; nz += wz; k += 64;
+            if (k >= pilot && nz >= 8) break;
+        }
+        if (lane == 0) {
+            c.pmax = mx; c.psum = sm; c.pn = (float)k;
+            atomic_maxf(runmax + (c.cls_u >> 8) * 5 + (c.cls_u & 0xFF), mx);
+        }
+    }
+    wave_count(cnt + C_RAYS_RECIP, C.rays);
+}
+
+// B_j = max(pilot max, bucket running max) (Appendix E's B = max f/q, per (class, u) bucket as in
+// Section 5.5's statistics); cost roulette: keep with rho = min(1, cost_cap / (R B / beta))
+__global__ void k_roulette(Cand *cand, const uint32_t *kept, uint32_t *final_, const float *runmax, float em_area,
+                           int repeats, float cost_cap, uint32_t seed, uint32_t iter, unsigned long long *cnt)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int n = (int)cnt[C_NKEPT];
+    bool keep = false;
+    uint32_t ci = 0;
+    if (i < n) {
+        ci = kept[i];
+        Cand &c = cand[ci];
+        const int b = (c.cls_u >> 8) * 5 + (c.cls_u & 0xFF);
+        float gmax = 0.f;
+        for (int k = 0; k < 10; ++k) gmax = fmaxf(gmax, runmax[k]);
+        const float Bb = runmax[b] > 0.f ? runmax[b] : (gmax > 0.f ? gmax : 1.0f / em_area);
+        const float B = fmaxf(c.pmax, Bb);
+        const float beta = c.pmax > 0.f ? c.psum / c.pn : B / (2.0f * fmaxf(c.pn, 1.0f));
+        const float cost = (float)repeats * B / beta;
+        const float rho = (cost_cap > 0.f && cost > cost_cap) ? cost_cap / cost : 1.0f;
+        Rng r = rng_make(seed, S_ROUL, (uint32_t)i, iter, 0u);
+        keep = rho >= 1.0f || rng_f(r) < rho;
+        c.B = B; c.rho = rho; c.recip_sum = 0.0f;
+    }
+    const int slot = wave_push(cnt + C_NFINAL, keep);
+    if (keep) final_[slot] = ci;
+}
+
+// One estimate I~ per wavefront (Section 4.2 with r = |g|). Pending nodes of the splitting tree
+// are kept as two counters by the sign of their prefix product: a node of sign s adds s g / B
+// and spawns floor(|g|) (+1 with probability |g| - floor|g|) children of sign s sgn(g).
+// Chain roulette (reading R12c): when the chain has used n1, 2 n1, 4 n1, ... samples it goes on
+// with probability 1/2 and its estimate is doubled, otherwise its estimate is 0; the flip times
+// depend on the sample count only and the flips are independent, so the expectation is kept and
+// the expected cost stays O(n1 log) however small beta is. `cap` is a hard safety bound.
+__global__ void __launch_bounds__(64 * RW) k_recip(SceneDev S, Cand *cand, const uint32_t *final_, int repeats,
+                                                   uint32_t seed, uint32_t iter, uint32_t n1, uint32_t cap,
+                                                   float *runmax, unsigned long long *cnt)
+{
+    __shared__ int stk[PT_STACK * 64 * RW];
+    const int wave = blockIdx.x * RW + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    const int n = (int)cnt[C_NFINAL] * repeats;
+    Ctx C{S, stk + threadIdx.x, 0u, (int)blockDim.x};
+    uint32_t ns = 0, trunc = 0;
+    if (wave < n) {   // wave-uniform
+        const uint32_t ci = final_[wave / repeats];
+        const uint32_t chain = ci * 8u + (uint32_t)(wave % repeats);
+        Cand &c = cand[ci];
+        const float B = c.B, invB = 1.0f / B;
+        float ans = invB, mx = 0.0f, weight = 1.0f;
+        uint32_t pos = 1, neg = 0, next_flip = n1;
+        Rng rf = rng_make(seed, S_RECIP, chain, iter, 0xFFFFFFFFu);   // roulette coins
+        bool alive = true;
+        for (int step = 0; alive && pos + neg > 0; ++step) {
+            if (ns >= cap) { trunc = 1; break; }
+            Rng r = rng_make(seed, S_RECIP, chain, iter, (uint32_t)(step * 64 + lane));
+            const float fq = fq_sample(C, c, r);
+            const float u = rng_f(r);
+            mx = fmaxf(mx, fq);
+            for (int l = 0; l < 64; ++l) {
+                if (pos + neg == 0) break;
+                if (ns == next_flip) {
+                    if (rng_f(rf) < 0.5f) weight *= 2.0f;
+                    else { alive = false; break; }
+                    next_flip *= 2u;
+                }
+                const float g = 1.0f - lane_get(fq, l) * invB;
+                const float ul = lane_get(u, l);
+                float sgn = 1.0f;
+                if (pos > 0) pos--; else { neg--; sgn = -1.0f; }
+                ns++;
+                ans += sgn * g * invB;
+                const float ag = fabsf(g), fl = floorf(ag);
+                const uint32_t kids = (uint32_t)fminf(fl, 1.0e6f) + (ul < ag - fl ? 1u : 0u);
+                if ((sgn > 0.0f) == (g >= 0.0f)) pos += kids; else neg += kids;
+            }
+        }
+        float wmx = mx;
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) wmx = fmaxf(wmx, __shfl_xor(wmx, off));
+        if (lane == 0) {
+            const float est = (alive && !trunc) ? ans * weight : (trunc ? ans * weight : 0.0f);
+            unsafeAtomicAdd(&c.recip_sum, est);
+            atomic_maxf(runmax + (c.cls_u >> 8) * 5 + (c.cls_u & 0xFF), wmx);
+        }
+    }
+    wave_count(cnt + C_RECIP_SAMPLES, lane == 0 ? ns : 0u);
+    wave_count(cnt + C_RECIP_TRUNC, lane == 0 ? trunc : 0u);
+    wave_count(cnt + C_RAYS_RECIP, C.rays);
+}
+
+// Candidate probe: one wavefront per estimate; `per` samples of f/q averaged into a plain
+// Monte Carlo estimate of P, then one chain of I~ with the given B (no roulette).
+__global__ void __launch_bounds__(64 * RW) k_recip_point(SceneDev S, Cand c, int n_est, int per, uint32_t seed,
+                                                         uint32_t cap, float *est, uint32_t *ns_out, float *p_out)
+{
+    __shared__ int stk[PT_STACK * 64 * RW];
+    const int wave = blockIdx.x * RW + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    Ctx C{S, stk + threadIdx.x, 0u, (int)blockDim.x};
+    if (wave >= n_est) return;   // wave-uniform
+    float acc = 0.0f;
+    for (int base = 0; base < per; base += 64) {
+        Rng r = rng_make(seed, S_TABLE, (uint32_t)wave, 1u, (uint32_t)(base + lane));
+        float v = base + lane < per ? fq_sample(C, c, r) : 0.0f;
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+        acc += v;
+    }
+    const float invB = 1.0f / c.B;
+    float ans = invB;
+    uint32_t pos = 1, neg = 0, ns = 0, trunc = 0;
+    for (int step = 0; pos + neg > 0; ++step) {
+        if (ns >= cap) { trunc = 1; break; }
+        Rng r = rng_make(seed, S_TABLE, (uint32_t)wave, 2u, (uint32_t)(step * 64 + lane));
+        const float fq = fq_sample(C, c, r);
+        const float u = rng_f(r);
+        for (int l = 0; l < 64; ++l) {
+            if (pos + neg == 0) break;
+            const float g = 1.0f - lane_get(fq, l) * invB;
+            const float ul = lane_get(u, l);
+            float sgn = 1.0f;
+            if (pos > 0) pos--; else { neg--; sgn = -1.0f; }
+            ns++;
+            ans += sgn * g * invB;
+            const float ag = fabsf(g), fl = floorf(ag);
+            const uint32_t kids = (uint32_t)fminf(fl, 1.0e6f) + (ul < ag - fl ? 1u : 0u);
+            if ((sgn > 0.0f) == (g >= 0.0f)) pos += kids; else neg += kids;
+        }
+    }
+    if (lane == 0) {
+        est[wave] = ans;
+        ns_out[wave] = ns | (trunc << 31);
+        if (p_out) p_out[wave] = acc / (float)per;
+    }
+}
+
+// ---------------------------------------------------------------------------------- eye pass
+struct EyeBuf {
+    float4 *ro, *rd, *hit, *beta;   // beta.w = solid-angle pdf of the last sampled direction
+    uint32_t *info;                 // bits 0..7 depth, 8 previous vertex Dirac, 9..10 phase, 11..14 u
+    uint32_t *q[2];
+    ShadowRay *shadow;
+    ProxyItem *proxy;
+    float *frame;                   // [npix * 3] this iteration's pixel values
+    int npix;
+};
+
+__global__ void k_camera(SceneDev S, EyeBuf E, uint32_t seed, uint32_t iter, unsigned long long *cnt)
+{
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p == 0) cnt[C_EYE_Q0] = (unsigned long long)E.npix;
+    if (p >= E.npix) return;
+    const int px = p % S.cam.w, py = p / S.cam.w;
+    Rng r = rng_make(seed, S_EYE, (uint32_t)p, iter, 0u);
+    const float jx = rng_f(r), jy = rng_f(r);
+    const float x = (2.0f * (px + jx) / S.cam.w - 1.0f) * S.cam.tan_half * S.cam.aspect;
+    const float y = (1.0f - 2.0f * (py + jy) / S.cam.h) * S.cam.tan_half;
+    const float3 d = normalize3(S.cam.f + S.cam.r * x + S.cam.u * y);
+    E.ro[p] = make_float4(S.cam.p.x, S.cam.p.y, S.cam.p.z, ibits(-1));
+    E.rd[p] = make_float4(d.x, d.y, d.z, 3.0e38f);
+    E.beta[p] = make_float4(1.f, 1.f, 1.f, 0.f);
+    E.info[p] = 1u << 8;   // camera counts as a Dirac predecessor for the first hit
+    E.q[0][p] = (uint32_t)p;
+}
+
+struct EyeParams {
+    uint32_t seed, iter;
+    int K, u_max;
+    int filter;      // 0 all, 1 proxy class only, 2 other only, 3 none (for PT/NEE)
+    int proxy_on;
+    int nee_on;
+};
+
+// proxy-class state machine over eye vertices (emitters count as D): phase 0 before the first
+// diffuse vertex z_d; 1 at/after z_d with only specular vertices since (u of them); 2 after
+// S^u then one diffuse vertex; 3 never a proxy path
+__device__ __forceinline__ void pstate_push(uint32_t &ph, uint32_t &u, bool spec, int umax)
+{
+    if (ph == 0) { if (!spec) { ph = 1; u = 0; } }
+    else if (ph == 1) {
+        if (spec) { if (++u > (uint32_t)umax) ph = 3; }
+        else ph = u >= 1 ? 2 : 3;
+    } else if (ph == 2) ph = 3;
+}
+__device__ __forceinline__ bool class_ok(int filter, bool proxy_class)
+{
+    return filter == 0 || (filter == 1 && proxy_class) || (filter == 2 && !proxy_class);
+}
+
+__global__ void k_eye_shade(SceneDev S, EyeBuf E, EyeParams P, int t, unsigned long long *cnt)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int n = (int)cnt[C_EYE_Q0 + t - 1];
+    const uint32_t *qin = E.q[(t - 1) & 1];
+    uint32_t *qout = E.q[t & 1];
+    bool cont = false, shadow = false, proxy = false;
+    int pid = 0;
+    ShadowRay sr;
+    ProxyItem pi;
+    float4 nro, nrd, nbeta;
+    uint32_t ninfo = 0;
+    if (i < n) {
+        pid = qin[i];
+        const float4 h = E.hit[pid];
+        const int tri = fbits(h.w);
+        if (tri >= 0) {
+            const float4 o = E.ro[pid], d = E.rd[pid];
+            const float3 x = xyz(o) + xyz(d) * h.x;
+            const TriShade &sh = S.shade[tri];
+            const MatDev m = S.mats[sh.mat];
+            const float3 wo = -xyz(d);
+            const float4 bt = E.beta[pid];
+            const float3 beta = xyz(bt);
+            uint32_t info = E.info[pid];
+            uint32_t ph = (info >> 9) & 3u, uu = (info >> 11) & 15u;
+            const bool prev_delta = (info >> 8) & 1u;
+            float3 add = f3(0.f, 0.f, 0.f);
+            if (m.flags & MF_EMIT) {
+                const bool cls = (ph == 1 && uu >= 1) || ph == 2;
+                if (class_ok(P.filter, cls)) {
+                    const float3 le = emission(S, tri, h.y, h.z, wo);
+                    if (nonzero3(le)) {
+                        float w = 1.0f;
+                        if (!(t == 1 || prev_delta)) {
+                            const float pl = h.x * h.x / (fabsf(dot3(sh.n, wo)) * S.em_area);
+                            w = bt.w / (bt.w + pl);
+                        }
+                        add = beta * le * w;
+                    }
+                }
+            }
+            if (nonzero3(add)) atomic_add3(E.frame + 3 * pid, add);
+            if (t < P.K) {
+                const bool spec = (m.flags & MF_SPEC) != 0;
+                pstate_push(ph, uu, spec, P.u_max);
+                Rng r = rng_make(P.seed, S_EYE, (uint32_t)pid, P.iter, (uint32_t)t);
+                if (P.proxy_on && ph == 1 && uu == 0 && !spec) {
+                    proxy = true;
+                    pi.x = make_float4(x.x, x.y, x.z, ibits(tri));
+                    pi.wo = make_float4(wo.x, wo.y, wo.z, ibits(t));
+                    pi.beta = make_float4(beta.x, beta.y, beta.z, ibits(pid));
+                }
+                const float u0 = rng_f(r), u1 = rng_f(r), u2 = rng_f(r);
+                if (P.nee_on && !(m.flags & MF_DELTA) && S.n_em > 0) {
+                    const bool cls = (ph == 1 && uu >= 1) || ph == 2;
+                    if (class_ok(P.filter, cls)) {
+                        const LPoint L = sample_emitter(S, u0, u1, u2);
+                        const float3 dl = L.p - x;
+                        const float dist2 = dot3(dl, dl), dist = sqrtf(dist2);
+                        const float3 wl = dl * (1.0f / dist);
+                        const float cl = -dot3(L.n, wl);
+                        if (cl > 0.0f) {
+                            const float3 fs = bsdf_f(m, sh.n, wo, wl);
+                            if (nonzero3(fs)) {
+                                const float3 le = emission(S, L.tri, L.b1, L.b2, -wl);
+                                const float pl = dist2 / (cl * S.em_area);
+                                const float pb = bsdf_pdf(m, sh.n, wo, wl);
+                                const float3 c = beta * fs * le * (fabsf(dot3(sh.n, wl)) / pl * (pl / (pl + pb)));
+                                if (nonzero3(c)) {
+                                    shadow = true;
+                                    sr.o = make_float4(x.x, x.y, x.z, ibits(tri));
+                                    sr.d = make_float4(wl.x, wl.y, wl.z, dist * 0.9999f);
+                                    sr.c = make_float4(c.x, c.y, c.z, ibits(pid));
+                                    sr.ign1 = L.tri;
+                                }
+                            }
+                        }
+                    }
+                }
+                const float a = rng_f(r), b = rng_f(r), cc = rng_f(r);
+                const BS bs = bsdf_sample(m, sh.n, wo, a, b, cc, true);
+                if (bs.ok) {
+                    const float3 nb = beta * bs.w;
+                    if (nonzero3(nb)) {
+                        cont = true;
+                        nro = make_float4(x.x, x.y, x.z, ibits(tri));
+                        nrd = make_float4(bs.wi.x, bs.wi.y, bs.wi.z, 3.0e38f);
+                        nbeta = make_float4(nb.x, nb.y, nb.z, bs.pdf);
+                        ninfo = (uint32_t)t | (bs.delta ? 1u << 8 : 0u) | (ph << 9) | (uu << 11);
+                    }
+                }
+            }
+        }
+    }
+    const int ss = wave_push(cnt + C_SHD0 + t, shadow);
+    if (shadow) E.shadow[ss] = sr;
+    const int ps = wave_push(cnt + C_PROXYQ, proxy);
+    if (proxy) E.proxy[ps] = pi;
+    const int cs = wave_push(cnt + C_EYE_Q0 + t, cont);
+    if (cont) {
+        qout[cs] = (uint32_t)pid;
+        E.ro[pid] = nro; E.rd[pid] = nrd; E.beta[pid] = nbeta; E.info[pid] = ninfo;
+    }
+}
+
+__global__ void __launch_bounds__(WG) k_occluded(SceneDev S, EyeBuf E, int t, unsigned long long *cnt)
+{
+    __shared__ int stk[PT_STACK * WG];
+    const int i = blockIdx.x * WG + threadIdx.x;
+    const int n = (int)cnt[C_SHD0 + t];
+    const bool act = i < n;
+    if (act) {
+        const ShadowRay sr = E.shadow[i];
+        Hit h;
+        if (!traverse<true, false>(S, xyz(sr.o), xyz(sr.d), S.tmin, sr.d.w, fbits(sr.o.w), sr.ign1, stk + threadIdx.x,
+                                   WG, h))
+            atomic_add3(E.frame + 3 * fbits(sr.c.w), xyz(sr.c));
+    }
+    wave_count(cnt + C_RAYS_SHADOW, act ? 1u : 0u);
+}
+
+struct ProxyParams {
+    uint32_t seed, iter;
+    int K, M, cand_cap, repeats;
+};
+
+// Proxy connection (Section 5.1): pick a kept incomplete sub-path (uniformly), connect z_d to
+// y_{s-1}, retrace the u dropped vertices by sampling the BSDF at y_{s-1} given the direction to
+// z_d and then at each new vertex, abort on an S/D mismatch, weight with 1/P's estimate and
+// normalise by M pi_inc rho pi_j; p(h*) = 1 (class A) or 1/A (class B).
+__global__ void __launch_bounds__(WG) k_proxy(SceneDev S, EyeBuf E, const Cand *__restrict__ cand,
+                                              const uint32_t *__restrict__ final_, ProxyParams P,
+                                              unsigned long long *cnt)
+{
+    __shared__ int stk[PT_STACK * WG];
+    const int i = blockIdx.x * WG + threadIdx.x;
+    const int n = (int)cnt[C_PROXYQ];
+    const int nk = (int)cnt[C_NFINAL];
+    Ctx C{S, stk + threadIdx.x, 0u, (int)blockDim.x};
+    uint32_t valid = 0;
+    if (i < n && nk > 0) {
+        const ProxyItem it = E.proxy[i];
+        const int pix = fbits(it.beta.w);
+        Rng r = rng_make(P.seed, S_PROXY, (uint32_t)pix, P.iter, 0u);
+        const int j = min((int)(rng_f(r) * (float)nk), nk - 1);
+        const Cand c = cand[final_[j]];
+        const float pi_j = 1.0f / (float)nk;
+        const int cls = c.cls_u >> 8, u = c.cls_u & 0xFF;
+        const int d = fbits(it.wo.w);
+        float3 add = f3(0.f, 0.f, 0.f);
+        if (d + 1 + u + cls <= P.K) {
+            const float3 xd = xyz(it.x);
+            const int td = fbits(it.x.w);
+            const TriShade &shd = S.shade[td];
+            const MatDev md = S.mats[shd.mat];
+            const float3 v = xyz(c.v);
+            const int vt = fbits(c.v.w);
+            const float3 vn = S.shade[vt].n;
+            const float3 dv = v - xd;
+            const float d2 = dot3(dv, dv);
+            const float3 wzv = dv * rsqrtf(d2);
+            const float3 fz = bsdf_f(md, shd.n, xyz(it.wo), wzv);
+            if (nonzero3(fz) && !occluded(C, xd, td, v, vt)) {
+                const float G = fabsf(dot3(shd.n, wzv)) * fabsf(dot3(vn, wzv)) / d2;
+                float3 thr = f3(1.f, 1.f, 1.f), term = f3(0.f, 0.f, 0.f);
+                float3 cur = v, wo = -wzv, curn = vn;
+                int curt = vt;
+                bool ok = true;
+                for (int k = 1; k <= u && ok; ++k) {
+                    const MatDev m = S.mats[S.shade[curt].mat];
+                    const float a = rng_f(r), b = rng_f(r), cc = rng_f(r);
+                    const BS bs = bsdf_sample(m, curn, wo, a, b, cc, true);
+                    Hit h;
+                    if (!bs.ok || !closest(C, cur, bs.wi, curt, h)) { ok = false; break; }
+                    thr = thr * bs.w;
+                    const MatDev mh = S.mats[S.shade[h.tri].mat];
+                    const float3 y = tri_point(S, h.tri, h.b1, h.b2);
+                    const float3 ny = S.shade[h.tri].n;
+                    if (k < u) {
+                        if (!(mh.flags & MF_SPEC)) { ok = false; break; }
+                    } else if (cls == 0) {
+                        if (!(mh.flags & MF_EMIT)) { ok = false; break; }
+                        term = emission(S, h.tri, h.b1, h.b2, -bs.wi);
+                    } else {
+                        if (mh.flags & MF_SPEC) { ok = false; break; }
+                        const float3 y0 = xyz(c.hc);
+                        const int t0 = fbits(c.hc.w);
+                        const float3 a0 = y0 - y;
+                        const float e2 = dot3(a0, a0);
+                        const float3 wl = a0 * rsqrtf(e2);
+                        const float c0 = -dot3(S.shade[t0].n, wl);
+                        const float3 f1 = bsdf_f(mh, ny, -bs.wi, wl);
+                        if (c0 <= 0.0f || !nonzero3(f1) || occluded(C, y, h.tri, y0, t0)) { ok = false; break; }
+                        const float3 le = emission(S, t0, c.hc_b1, c.hc_b2, -wl);
+                        term = f1 * le * (c0 * fabsf(dot3(ny, wl)) / e2 * S.em_area);
+                    }
+                    cur = y; curt = h.tri; curn = ny; wo = -bs.wi;
+                }
+                if (ok) {
+                    const float pi_inc = fminf(1.0f, (float)P.cand_cap / (float)cnt[C_NCAND]);
+                    const float scale = (c.recip_sum / (float)P.repeats) / ((float)P.M * pi_inc * c.rho * pi_j);
+                    add = xyz(it.beta) * fz * thr * term * (G * scale);
+                }
+            }
+        }
+        if (nonzero3(add)) { atomic_add3(E.frame + 3 * pix, add); valid = 1; }
+    }
+    wave_count(cnt + C_PROXY_ATT, (i < n && nk > 0) ? 1u : 0u);
+    wave_count(cnt + C_PROXY_VALID, valid);
+    wave_count(cnt + C_RAYS_PROXY, C.rays);
+}
+
+// frame -> caller accumulators; non-finite values are counted and dropped; frame cleared
+__global__ void k_accumulate(float *frame, float *acc, float *acc2, int n, unsigned long long *cnt)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    uint32_t bad = 0;
+    if (i < n) {
+        float v = frame[i];
+        if (!isfinite(v)) { v = 0.0f; bad = 1; }
+        acc[i] += v;
+        if (acc2) acc2[i] += v * v;
+        frame[i] = 0.0f;
+    }
+    wave_count(cnt + C_NAN, bad);
+}
+
+__global__ void k_resolve(const float *acc, float *out, int n, float inv)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = acc[i] * inv;
+}
+
+// ---------------------------------------------------------------------------------- test hooks
+__global__ void __launch_bounds__(WG) k_trace_closest(SceneDev S, const float *rays, int n, float *t_out, int *prim_out)
+{
+    __shared__ int stk[PT_STACK * WG];
+    const int i = blockIdx.x * WG + threadIdx.x;
+    if (i >= n) return;
+    const float *r = rays + 8 * (size_t)i;
+    Hit h;
+    const bool ok = traverse<false, false>(S, f3(r[0], r[1], r[2]), f3(r[3], r[4], r[5]), r[6], r[7], -1, -1,
+                                           stk + threadIdx.x, WG, h);
+    t_out[i] = ok ? h.t : -1.0f;
+    prim_out[i] = ok ? S.tris[h.tri].prim : -1;
+}
+
+// Table mode of the reciprocal estimator: target 1 / sum f, supporting pmf q (inverse-CDF by a
+// linear scan), estimator I~ (sign_est = 0) or the sign estimator I (sign_est = 1).
+__global__ void k_recip_table(const float *f, const float *q, int n, float B, int n_est, int sign_est, uint32_t seed,
+                              uint32_t cap, float *out, uint32_t *ns_out)
+{
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n_est) return;
+    Rng r = rng_make(seed, S_TABLE, (uint32_t)e, 0u, 0u);
+    const float invB = 1.0f / B;
+    float ans = invB;
+    uint32_t pos = 1, neg = 0, ns = 0, trunc = 0;
+    while (pos + neg > 0) {
+        if (ns >= cap) { trunc = 1; break; }
+        float s = 1.0f;
+        if (pos > 0) pos--; else { neg--; s = -1.0f; }
+        const float x = rng_f(r);
+        float acc = 0.0f;
+        int k = 0;
+        for (; k < n - 1; ++k) { acc += q[k]; if (x < acc) break; }
+        const float g = 1.0f - f[k] / (q[k] * B);
+        ns++;
+        ans += sign_est ? (ns > 1 ? s * invB : 0.0f) : s * g * invB;
+        const float ag = fabsf(g), fl = floorf(ag);
+        const uint32_t kids = (uint32_t)fl + (rng_f(r) < ag - fl ? 1u : 0u);
+        if ((s > 0.0f) == (g >= 0.0f)) pos += kids; else neg += kids;
+    }
+    out[e] = ans;
+    ns_out[e] = ns | (trunc << 31);
+}

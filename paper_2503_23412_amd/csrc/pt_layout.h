@@ -1,0 +1,92 @@
+// Memory layouts shared by the host code and the gfx950 kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+// 4-wide BVH node: one 128-byte line. Child k is empty when count[k] < 0, a leaf of
+// count[k] > 0 consecutive triangles starting at child[k], or an inner node (count[k] == 0).
+struct alignas(128) BNode {
+    float lo_x[4], hi_x[4], lo_y[4], hi_y[4], lo_z[4], hi_z[4];
+    int32_t child[4];
+    int32_t count[4];
+};
+static_assert(sizeof(BNode) == 128, "BNode must be one 128-byte line");
+
+// Triangle for intersection (BVH order): 48 bytes.
+struct alignas(16) TriIsect {
+    float v0[3];
+    float e1[3];
+    float e2[3];
+    int32_t prim;   // input triangle index
+    int32_t pad[2];
+};
+static_assert(sizeof(TriIsect) == 48, "TriIsect must be 48 bytes");
+
+// Shading data (BVH order): normal, material, per-vertex (u, v).
+struct TriShade {
+    float3 n;
+    int32_t mat;
+    float uv[6];
+};
+
+enum { MAT_LAMBERT = 0, MAT_CONDUCTOR = 1, MAT_DIELECTRIC = 2 };
+enum { MF_EMIT = 1, MF_TEXTURED = 2, MF_SPEC = 4, MF_DELTA = 8 };
+
+struct MatDev {
+    int32_t type;
+    uint32_t flags;
+    float alpha, ior;
+    float3 rgb;
+    float3 le;
+};
+
+struct CamDev {
+    float3 p, f, r, u;
+    float tan_half, aspect;
+    int32_t w, h;
+};
+
+// at most this many light vertices are kept per light sub-path: y_0 .. y_5, enough for a
+// class B candidate with a specular run of 4
+#define PT_LMAX 6
+#define PT_STACK 48
+
+// Incomplete light sub-path candidate (y_{s-1} plus the control vertex), 80 bytes.
+struct Cand {
+    float4 v;        // y_{s-1} position, w = triangle (bits)
+    float4 hc;       // class B: y_0 position, w = triangle (bits)
+    float hc_b1, hc_b2;
+    int32_t cls_u;   // class << 8 | u
+    float B;
+    float rho;       // probability it survived the cost roulette
+    float recip_sum; // sum of the reciprocal estimates of this iteration
+    float pmax, psum, pn;
+    int32_t spec_sub;// specular subspace S
+    float pad[2];
+};
+static_assert(sizeof(Cand) == 80, "Cand layout");
+
+// Device counters of one iteration (64-bit so that large runs do not wrap).
+enum {
+    C_LIGHT_Q0 = 0,          // light queue counts per vertex index: 0 .. PT_LMAX
+    C_EYE_Q0 = 8,            // eye queue counts per depth: 8 .. 135
+    C_SHD0 = 136,            // shadow-ray queue counts per depth: 136 .. 263
+    C_PROXYQ = 264, C_NCAND, C_NKEPT, C_NFINAL,
+    C_RAYS_EYE, C_RAYS_LIGHT, C_RAYS_SHADOW, C_RAYS_PROXY, C_RAYS_RECIP,
+    C_RECIP_SAMPLES, C_RECIP_TRUNC, C_PROXY_ATT, C_PROXY_VALID, C_NAN, C_VISITS, C_TESTS, C_STACK_OVF,
+    C_COUNT
+};
+#define PT_MAX_DEPTH 127
+
+// queued shadow ray: origin + first ignored triangle, direction + tmax, contribution + pixel,
+// second ignored triangle
+struct ShadowRay {
+    float4 o, d, c;
+    int32_t ign1, pad[3];
+};
+// proxy work item at an eye path's first diffuse vertex
+struct ProxyItem {
+    float4 x;        // position, w = triangle (bits)
+    float4 wo;       // direction toward the previous eye vertex, w = segments so far (bits)
+    float4 beta;     // eye throughput, w = pixel (bits)
+};

@@ -1,0 +1,194 @@
+"""ctypes binding of libpt.so (include/pt.h). Argument marshalling only: every step of the
+rendering path runs in the library's HIP kernels. Device buffers are torch tensors on the
+current HIP device; the stream is torch's current stream unless one is given.
+
+The binding raises if libpt.so is missing or fails to load; there is no fallback path.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpt.so")
+
+PT_FLAG_NEE = 1 << 0
+PT_FLAG_PROXY = 1 << 1
+PT_FLAG_ONLY_PROXY_CLASS = 1 << 2
+PT_FLAG_ONLY_OTHER = 1 << 3
+PT_FLAG_GAMMA = 1 << 4
+PT_FLAG_TILES = 1 << 5
+PT_FLAG_TIMING = 1 << 6
+PT_FLAG_COUNT = 1 << 7
+PT_FLAG_MIS = 1 << 8
+
+PT_EST_ITILDE = 0
+PT_EST_SIGN = 1
+
+EXPORTED = ["pt_scene_upload", "pt_scene_release", "pt_build_subspaces", "pt_render_iteration",
+            "pt_reciprocal_estimate", "pt_resolve_image", "pt_trace_closest", "pt_last_error"]
+
+
+class SceneDesc(ctypes.Structure):
+    _fields_ = [
+        ("n_tri", ctypes.c_int32), ("tri", ctypes.c_void_p), ("tri_mat", ctypes.c_void_p),
+        ("tri_uv", ctypes.c_void_p), ("n_mat", ctypes.c_int32), ("mats", ctypes.c_void_p),
+        ("tex_w", ctypes.c_int32), ("tex_h", ctypes.c_int32), ("tex", ctypes.c_void_p),
+        ("camera", ctypes.c_void_p), ("width", ctypes.c_int32), ("height", ctypes.c_int32),
+        ("bvh_width", ctypes.c_int32), ("max_light_paths", ctypes.c_int32),
+    ]
+
+
+class SubspaceParams(ctypes.Structure):
+    _fields_ = [("n_pretrace", ctypes.c_int32), ("n_eye", ctypes.c_int32), ("n_spec", ctypes.c_int32),
+                ("kmeans_iters", ctypes.c_int32), ("seed", ctypes.c_uint32)]
+
+
+class IterParams(ctypes.Structure):
+    _fields_ = [
+        ("iteration", ctypes.c_uint32), ("seed", ctypes.c_uint32), ("max_depth", ctypes.c_int32),
+        ("n_light", ctypes.c_int32), ("cand_cap", ctypes.c_int32), ("recip_repeats", ctypes.c_int32),
+        ("u_max", ctypes.c_int32), ("pilot", ctypes.c_int32), ("cost_cap", ctypes.c_float),
+        ("train_iters", ctypes.c_int32), ("tile", ctypes.c_int32), ("tile_threshold", ctypes.c_float),
+        ("tile_low_prob", ctypes.c_float), ("defensive", ctypes.c_float), ("flags", ctypes.c_uint32),
+    ]
+
+
+class IterStats(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_double) for n in (
+        "rays_extend_eye", "rays_extend_light", "rays_shadow", "rays_proxy", "rays_recip",
+        "n_cand", "n_kept", "n_recip_samples", "n_recip_truncated",
+        "n_proxy_attempts", "n_proxy_valid", "n_nan", "node_visits", "tri_tests",
+        "ms_extend", "n_extend_launches")]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class CandDesc(ctypes.Structure):
+    _fields_ = [("cls", ctypes.c_int32), ("u", ctypes.c_int32), ("v", ctypes.c_float * 3), ("v_prim", ctypes.c_int32),
+                ("hc", ctypes.c_float * 3), ("hc_prim", ctypes.c_int32), ("hc_b1", ctypes.c_float),
+                ("hc_b2", ctypes.c_float)]
+
+
+class RecipQuery(ctypes.Structure):
+    _fields_ = [("mode", ctypes.c_int32), ("n", ctypes.c_int32), ("f_dev", ctypes.c_void_p),
+                ("q_dev", ctypes.c_void_p), ("B", ctypes.c_float), ("n_est", ctypes.c_int32),
+                ("estimator", ctypes.c_int32), ("seed", ctypes.c_uint32), ("cap", ctypes.c_uint32),
+                ("cand", ctypes.POINTER(CandDesc)), ("per", ctypes.c_int32), ("out_p_dev", ctypes.c_void_p)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libpt.so (raises OSError when it is missing or does not load)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise OSError(f"{LIB_PATH} is not built; run __graft_entry__.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        P, I = ctypes.c_void_p, ctypes.c_int32
+        L.pt_scene_upload.argtypes = [ctypes.POINTER(SceneDesc), P, ctypes.POINTER(P)]
+        L.pt_scene_release.argtypes = [P]
+        L.pt_build_subspaces.argtypes = [P, ctypes.POINTER(SubspaceParams), P]
+        L.pt_render_iteration.argtypes = [P, ctypes.POINTER(IterParams), P, P, ctypes.POINTER(IterStats), P]
+        L.pt_reciprocal_estimate.argtypes = [P, ctypes.POINTER(RecipQuery), P, P, P]
+        L.pt_resolve_image.argtypes = [P, P, ctypes.c_uint32, P, P]
+        L.pt_trace_closest.argtypes = [P, P, I, P, P, P]
+        L.pt_last_error.restype = ctypes.c_char_p
+        for name in ("pt_scene_upload", "pt_scene_release", "pt_build_subspaces", "pt_render_iteration",
+                     "pt_reciprocal_estimate", "pt_resolve_image", "pt_trace_closest"):
+            getattr(L, name).restype = ctypes.c_int32
+        _lib = L
+    return _lib
+
+
+class PTError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"libpt error {code}: {msg}")
+        self.code = code
+
+
+def _check(code):
+    if code != 0:
+        raise PTError(code, lib().pt_last_error().decode())
+
+
+def _stream(stream):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def default_params(**kw):
+    p = dict(iteration=0, seed=0, max_depth=8, n_light=4096, cand_cap=400, recip_repeats=5, u_max=4, pilot=16,
+             cost_cap=4096.0, train_iters=40, tile=10, tile_threshold=0.05, tile_low_prob=0.2, defensive=0.1,
+             flags=PT_FLAG_NEE | PT_FLAG_PROXY)
+    p.update(kw)
+    return p
+
+
+class Scene:
+    """A scene uploaded to the current HIP device."""
+
+    def __init__(self, sc, max_light_paths=4096, stream=None):
+        self._host = [np.ascontiguousarray(sc[k]) for k in ("tri", "tri_mat", "tri_uv", "mats", "tex", "cam")]
+        tri, tri_mat, tri_uv, mats, tex, cam = self._host
+        self.width, self.height = int(sc["width"]), int(sc["height"])
+        d = SceneDesc(tri.shape[0], tri.ctypes.data, tri_mat.ctypes.data, tri_uv.ctypes.data, mats.shape[0],
+                      mats.ctypes.data, tex.shape[1], tex.shape[0], tex.ctypes.data, cam.ctypes.data,
+                      self.width, self.height, 4, int(max_light_paths))
+        h = ctypes.c_void_p()
+        _check(lib().pt_scene_upload(ctypes.byref(d), _stream(stream), ctypes.byref(h)))
+        self.h = h
+        self.max_light_paths = int(max_light_paths)
+
+    def release(self):
+        if getattr(self, "h", None):
+            lib().pt_scene_release(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.release()
+        except Exception:
+            pass
+
+    def build_subspaces(self, n_pretrace=0, n_eye=64, n_spec=64, kmeans_iters=8, seed=0, stream=None):
+        p = SubspaceParams(n_pretrace, n_eye, n_spec, kmeans_iters, seed)
+        _check(lib().pt_build_subspaces(self.h, ctypes.byref(p), _stream(stream)))
+
+    def render_iteration(self, accum, accum_sq=None, stats=False, stream=None, **params):
+        p = IterParams(**default_params(**params))
+        st = IterStats() if stats else None
+        _check(lib().pt_render_iteration(self.h, ctypes.byref(p), _ptr(accum), _ptr(accum_sq),
+                                         ctypes.byref(st) if st is not None else None, _stream(stream)))
+        return st.as_dict() if st is not None else None
+
+    def resolve(self, accum, n_iter, out, stream=None):
+        _check(lib().pt_resolve_image(self.h, _ptr(accum), int(n_iter), _ptr(out), _stream(stream)))
+
+    def recip_candidate(self, cls, u, v, v_prim, B, n_est, out, nsamples, p_out=None, hc=(0.0, 0.0, 0.0), hc_prim=-1,
+                        hc_b=(0.0, 0.0), per=1, seed=3, cap=0, stream=None):
+        """Estimates of 1/P (out) and of P (p_out, `per` samples each) for one incomplete sub-path."""
+        d = CandDesc(int(cls), int(u), (ctypes.c_float * 3)(*v), int(v_prim), (ctypes.c_float * 3)(*hc), int(hc_prim),
+                     float(hc_b[0]), float(hc_b[1]))
+        q = RecipQuery(1, 0, None, None, float(B), int(n_est), 0, int(seed), int(cap), ctypes.pointer(d), int(per),
+                       p_out.data_ptr() if p_out is not None else None)
+        _check(lib().pt_reciprocal_estimate(self.h, ctypes.byref(q), _ptr(out), _ptr(nsamples), _stream(stream)))
+
+    def trace_closest(self, rays, t_out, prim_out, stream=None):
+        _check(lib().pt_trace_closest(self.h, _ptr(rays), int(rays.shape[0]), _ptr(t_out), _ptr(prim_out),
+                                      _stream(stream)))
+
+
+def reciprocal_table(f, q, B, n_est, out, nsamples, estimator=PT_EST_ITILDE, seed=1, cap=0, stream=None):
+    """f, q: float32 device tensors; out float32 [n_est], nsamples int32 [n_est] (device)."""
+    qq = RecipQuery(0, int(f.shape[0]), f.data_ptr(), q.data_ptr(), float(B), int(n_est), int(estimator), int(seed),
+                    int(cap), None, 0, None)
+    _check(lib().pt_reciprocal_estimate(None, ctypes.byref(qq), _ptr(out), _ptr(nsamples), _stream(stream)))

@@ -1,0 +1,55 @@
+"""Writes the oracle reference images used by the GPU parity tests.
+
+Only the FP64 oracle (oracle/) is called: O1 (path tracing with next-event estimation, the
+plain definition of the path integral). Output per scene: per-pixel mean of the per-iteration
+pixel values, the variance of that mean, and the number of iterations, as a compressed .npz.
+
+usage: python tests/golden/make_references.py [cfg0|cfg1_128|all] [spp]
+"""
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+sys.path.insert(0, ROOT)
+
+from oracle import oracle as O  # noqa: E402
+from synth import scenes  # noqa: E402
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+REFS = {
+    # name: (scene builder, max depth, default spp)
+    "cfg0": (lambda: scenes.cornell_glass(64, 64), 8, 65536),
+    "cfg1_128": (lambda: scenes.projector(128, 128), 12, 16384),
+}
+
+
+def make(name, spp=None, batch=1024):
+    build, depth, default = REFS[name]
+    spp = spp or default
+    S = O.Scene(build())
+    s = np.zeros((S.H, S.W, 3))
+    s2 = np.zeros((S.H, S.W, 3))
+    t0 = time.time()
+    for first in range(0, spp, batch):
+        n = min(batch, spp - first)
+        a, b, _ = S.render(method=0, n_iter=n, first_iter=first, max_depth=depth, seed=12345)
+        s += a
+        s2 += b
+        print(f"{name}: {first + n}/{spp} spp, {time.time() - t0:.0f} s", flush=True)
+    mean = s / spp
+    var_mean = np.maximum(s2 / spp - mean * mean, 0.0) / spp
+    out = os.path.join(HERE, f"{name}_o1_ref.npz")
+    np.savez_compressed(out, mean=mean.astype(np.float64), var_mean=var_mean.astype(np.float64), spp=spp,
+                        max_depth=depth, seed=12345)
+    print("wrote", out, flush=True)
+
+
+if __name__ == "__main__":
+    which = sys.argv[1] if len(sys.argv) > 1 else "all"
+    spp = int(sys.argv[2]) if len(sys.argv) > 2 else None
+    for name in (REFS if which == "all" else [which]):
+        make(name, spp)

@@ -1,0 +1,65 @@
+"""CPU checks of the C ABI: the library loads, exports every symbol include/pt.h declares, and
+rejects invalid arguments before touching a device."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def ptlib():
+    from paper_2503_23412_amd import build, pt
+    if not os.path.exists(pt.LIB_PATH):
+        build.build()
+    return pt
+
+
+def test_header_symbols_exported(ptlib):
+    hdr = open(os.path.join(ROOT, "include", "pt.h")).read()
+    decl = set(re.findall(r"^(?:pt_status|const char \*)\s*(pt_\w+)\s*\(", hdr, re.M))
+    assert {"pt_scene_upload", "pt_scene_release", "pt_build_subspaces", "pt_render_iteration",
+            "pt_reciprocal_estimate", "pt_resolve_image", "pt_last_error"} <= decl
+    L = ptlib.lib()
+    for name in decl:
+        assert hasattr(L, name), name
+    assert set(ptlib.EXPORTED) == decl
+
+
+def test_struct_sizes_match_header(ptlib):
+    # the ctypes mirrors must have the C layouts (checked against hand-computed sizes)
+    assert ctypes.sizeof(ptlib.SceneDesc) == 4 + 4 + 8 * 3 + 4 + 4 + 8 + 4 + 4 + 8 + 8 + 4 * 4
+    assert ctypes.sizeof(ptlib.IterParams) == 15 * 4
+    assert ctypes.sizeof(ptlib.IterStats) == 16 * 8
+    assert ctypes.sizeof(ptlib.SubspaceParams) == 5 * 4
+
+
+def test_invalid_arguments_rejected_without_device(ptlib):
+    L = ptlib.lib()
+    h = ctypes.c_void_p()
+    assert L.pt_scene_upload(None, None, ctypes.byref(h)) == -1
+    d = ptlib.SceneDesc()
+    d.n_tri = 0
+    assert L.pt_scene_upload(ctypes.byref(d), None, ctypes.byref(h)) == -1
+    assert b"missing" in L.pt_last_error()
+    # bad material index
+    tri = np.zeros((1, 9), np.float32)
+    tri[0, 3], tri[0, 7] = 1, 1
+    mat = np.array([5], np.int32)
+    uv = np.zeros((1, 6), np.float32)
+    mats = np.zeros((1, 16), np.float32)
+    tex = np.ones((1, 1), np.float32)
+    cam = np.zeros(10, np.float32)
+    d = ptlib.SceneDesc(1, tri.ctypes.data, mat.ctypes.data, uv.ctypes.data, 1, mats.ctypes.data, 1, 1,
+                        tex.ctypes.data, cam.ctypes.data, 8, 8, 4, 16)
+    assert L.pt_scene_upload(ctypes.byref(d), None, ctypes.byref(h)) == -1
+    assert b"material" in L.pt_last_error()
+    d.bvh_width = 8
+    assert L.pt_scene_upload(ctypes.byref(d), None, ctypes.byref(h)) == -1
+    assert L.pt_render_iteration(None, None, None, None, None, None) == -1
+    assert L.pt_reciprocal_estimate(None, None, None, None, None) == -1
+    assert L.pt_resolve_image(None, None, 1, None, None) == -1
+    assert L.pt_scene_release(None) == 0
