@@ -98,7 +98,11 @@ enum {
     PT_FLAG_TILES = 1u << 5,        /* 10x10-pixel tile gating of proxy attempts (Section 6.1) */
     PT_FLAG_TIMING = 1u << 6,       /* time the extension kernels with HIP events into the stats */
     PT_FLAG_COUNT = 1u << 7,        /* count BVH node visits and triangle tests of extension rays */
-    PT_FLAG_MIS = 1u << 8           /* variance-aware MIS for proxy paths (Section 5.4) */
+    PT_FLAG_MIS = 1u << 8,          /* variance-aware MIS for proxy paths (Section 5.4) */
+    PT_FLAG_MLP = 1u << 9           /* learned subspace selection: mlp_mix x network softmax +
+                                       (1 - mlp_mix) x the plain row (Gamma row with PT_FLAG_GAMMA,
+                                       else uniform over the non-empty subspaces); trained online
+                                       while iteration < train_iters */
 };
 
 typedef struct {
@@ -117,6 +121,8 @@ typedef struct {
     float tile_low_prob;     /* attempt probability of the other tiles (0.2) */
     float defensive;         /* uniform fraction mixed into Gamma rows (0.1) */
     uint32_t flags;
+    float mlp_lr;            /* Adam step size of the learned selection (1e-3) */
+    float mlp_mix;           /* weight of the network in the selection mixture, in [0, 1) (0.9) */
 } pt_iter_params;
 
 /* Host-visible per-iteration statistics (valid once the stream is synchronised when
@@ -136,6 +142,39 @@ typedef struct {
  * stats may be NULL; when given, the call synchronises the stream and fills it. */
 pt_status pt_render_iteration(pt_scene *s, const pt_iter_params *p, float *accum_rgb_dev, float *accum_sq_dev,
                               pt_iter_stats *stats, void *hip_stream);
+
+/* n_iter consecutive iterations (p->iteration, p->iteration + 1, ...) by replaying one captured
+ * HIP graph of an iteration; the same results as n_iter pt_render_iteration calls with the same
+ * parameters. The graph is captured on first use and re-captured when the parameters (other
+ * than the iteration index) or the buffers change. No statistics; PT_FLAG_TIMING is rejected. */
+pt_status pt_render_batch(pt_scene *s, const pt_iter_params *p, uint32_t n_iter, float *accum_rgb_dev,
+                          float *accum_sq_dev, void *hip_stream);
+
+/* Learned selection of the specular subspace (PT_FLAG_MLP). Not part of the paper's method: it
+ * replaces the Gamma row of Section 5.6 by a network's softmax mixed with that row, and keeps
+ * the selection probability exact, so the proxy estimator stays unbiased.
+ *
+ * Network: input = 9 features of the first diffuse eye vertex (position scaled to the scene's
+ * bounding box in [0, 1], shading normal, unit direction toward the previous eye vertex), each
+ * encoded as [raw, sin(2^b pi f), cos(2^b pi f) for b = 0..11] (225 values) and zero-padded to
+ * 256; three hidden layers of 64 ReLU units; n_spec output logits (one per specular subspace).
+ * BF16 operands with FP32 accumulation. Parameter vector (FP32, this order, row-major with the
+ * input index first): W1[256][64], b1[64], W2[64][64], b2[64], W3[64][64], b3[64],
+ * W4[64][n_spec], b4[n_spec]; logits = h3 W4 + b4. The network is re-initialised by
+ * pt_build_subspaces (and on first use); the parameters live with the scene. */
+pt_status pt_mlp_param_count(const pt_scene *s, int32_t *count);   /* after pt_build_subspaces */
+/* host_params[count] -> the scene's network; clears the Adam moments and step count. Synchronous. */
+pt_status pt_mlp_set_params(pt_scene *s, const float *host_params, int32_t count, void *hip_stream);
+/* the scene's network -> host_params[count]. Synchronous. */
+pt_status pt_mlp_get_params(pt_scene *s, float *host_params, int32_t count, void *hip_stream);
+/* logits_dev[n][n_spec] (bias included) of feat_dev[n][9] (device, FP32). 1 <= n <= max(H*W, 65536). */
+pt_status pt_mlp_forward(pt_scene *s, const float *feat_dev, int32_t n, float *logits_dev, void *hip_stream);
+/* One training step on n weighted samples (device arrays feat[n][9], label[n] in [0, n_spec),
+ * weight[n] >= 0): loss = sum_i w_i CE(softmax(logits_i), label_i) / sum_i w_i; the gradient is
+ * copied to grad_host[count] when it is not NULL, then one Adam step (b1 0.9, b2 0.999, eps 1e-8,
+ * step size lr) is applied. Synchronous. 1 <= n <= 65536. */
+pt_status pt_mlp_train_step(pt_scene *s, const float *feat_dev, const int32_t *label_dev, const float *weight_dev,
+                            int32_t n, float lr, float *grad_host, void *hip_stream);
 
 /* Reciprocal estimator (Section 4.2, RRS estimator with r = |g|, Appendix A). */
 enum { PT_RECIP_TABLE = 0, PT_RECIP_CANDIDATE = 1 };

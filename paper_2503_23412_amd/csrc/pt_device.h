@@ -69,7 +69,7 @@ __device__ __forceinline__ uint32_t rng_u32(Rng &r)
 __device__ __forceinline__ float rng_f(Rng &r) { return (float)(rng_u32(r) >> 8) * (1.0f / 16777216.0f); }
 
 enum { S_LIGHT = 11, S_CAND = 12, S_PILOT = 13, S_RECIP = 14, S_EYE = 15, S_PROXY = 16, S_TABLE = 17,
-       S_ROUL = 18, S_PRE = 19, S_KMEANS = 20, S_TILE = 21 };
+       S_ROUL = 18, S_PRE = 19, S_KMEANS = 20, S_TILE = 21, S_MLP = 22 };
 
 // ----------------------------------------------------------------------------- frames
 // branchless orthonormal basis about a unit normal (Duff et al. 2017)
@@ -259,6 +259,7 @@ struct SceneDev {
     float em_area;
     float tmin;
     CamDev cam;
+    float3 lo, inv_ext;   // scene box, for subspace features
 };
 
 __device__ __forceinline__ float3 emission(const SceneDev &S, int tri, float b1, float b2, float3 w_out)

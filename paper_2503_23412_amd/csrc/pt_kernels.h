@@ -8,6 +8,7 @@
 // (Section 5.1's retrace) and k_accumulate.
 #pragma once
 #include "pt_device.h"
+#include "pt_subspace.h"
 
 #define WG 128   // workgroup size of the traversal kernels (LDS stack 128 x 48 x 4 B = 24 KB)
 
@@ -53,8 +54,18 @@ __device__ __forceinline__ void atomic_maxf(float *p, float v)
 __global__ void k_zero(unsigned long long *cnt, int n)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) cnt[i] = 0ull;
+    if (i < n && i != C_ITER && i != C_LEARN && i != C_MLP_T) cnt[i] = 0ull;
 }
+// iteration index in device memory: set (direct calls) or advanced by one (graph replays)
+__global__ void k_iter(unsigned long long *cnt, uint32_t value, int advance, int train_iters)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        const uint32_t it = advance ? (uint32_t)cnt[C_ITER] + 1u : value;
+        cnt[C_ITER] = it;
+        cnt[C_LEARN] = (int)it < train_iters ? 1ull : 0ull;
+    }
+}
+__device__ __forceinline__ uint32_t iter_of(const unsigned long long *cnt) { return (uint32_t)cnt[C_ITER]; }
 
 // closest hit for every queued ray; rays live in (ro, rd) by path id, ro.w = ignored triangle,
 // rd.w = tmax; writes hit[pid] = (t, b1, b2, triangle or -1)
@@ -90,8 +101,9 @@ struct LightBuf {
     int M;
 };
 
-__global__ void k_light_gen(SceneDev S, LightBuf L, uint32_t seed, uint32_t iter, unsigned long long *cnt)
+__global__ void k_light_gen(SceneDev S, LightBuf L, uint32_t seed, unsigned long long *cnt)
 {
+    const uint32_t iter = iter_of(cnt);
     const int l = blockIdx.x * blockDim.x + threadIdx.x;
     if (l == 0) cnt[C_LIGHT_Q0] = (unsigned long long)L.M;
     if (l >= L.M) return;
@@ -108,9 +120,9 @@ __global__ void k_light_gen(SceneDev S, LightBuf L, uint32_t seed, uint32_t iter
 }
 
 // vertex `vi` of every queued light path: store it and sample the adjoint BSDF for the next
-__global__ void k_light_shade(SceneDev S, LightBuf L, uint32_t seed, uint32_t iter, int vi, int lmax,
-                              unsigned long long *cnt)
+__global__ void k_light_shade(SceneDev S, LightBuf L, uint32_t seed, int vi, int lmax, unsigned long long *cnt)
 {
+    const uint32_t iter = iter_of(cnt);
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const int n = (int)cnt[C_LIGHT_Q0 + vi - 1];
     const uint32_t *qin = L.q[(vi - 1) & 1];
@@ -186,15 +198,17 @@ __global__ void k_candidates(LightBuf L, int u_max, Cand *cand, unsigned long lo
         c.hc_b1 = b.x; c.hc_b2 = b.y;
         c.cls_u = (cls << 8) | (k + 1);
         c.B = 0.f; c.rho = 1.f; c.recip_sum = 0.f; c.pmax = 0.f; c.psum = 0.f; c.pn = 0.f; c.spec_sub = 0;
-        c.pad[0] = c.pad[1] = 0.f;
+        const float2 wi = oct_enc(normalize3(xyz(L.lv[(vi - 1) * L.M + l]) - xyz(c.v)));
+        c.pad[0] = wi.x; c.pad[1] = wi.y;
         cand[o + k] = c;
     }
 }
 
 // keep each candidate with probability pi_inc = min(1, cap / n_cand) (Horvitz-Thompson form of
 // Section 6.1's cap of 400 incomplete sub-paths)
-__global__ void k_keep(int cap, uint32_t seed, uint32_t iter, uint32_t *kept, int max_cand, unsigned long long *cnt)
+__global__ void k_keep(int cap, uint32_t seed, uint32_t *kept, int max_cand, unsigned long long *cnt)
 {
+    const uint32_t iter = iter_of(cnt);
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const int n = (int)cnt[C_NCAND];
     bool keep = false;
@@ -393,9 +407,9 @@ __device__ __forceinline__ float lane_get(float v, int l) { return __shfl(v, l);
 
 // pilot: 64-sample steps until at least `pilot` samples with 8 non-zero values, or 256 samples
 __global__ void __launch_bounds__(64 * RW) k_pilot(SceneDev S, Cand *cand, const uint32_t *kept, int pilot,
-                                                   uint32_t seed, uint32_t iter, float *runmax,
-                                                   unsigned long long *cnt)
+                                                   uint32_t seed, float *runmax, unsigned long long *cnt)
 {
+    const uint32_t iter = iter_of(cnt);
     __shared__ int stk[PT_STACK * 64 * RW];
     const int wave = blockIdx.x * RW + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
@@ -431,8 +445,9 @@ __global__ void __launch_bounds__(64 * RW) k_pilot(SceneDev S, Cand *cand, const
 // B_j = max(pilot max, bucket running max) (Appendix E's B = max f/q, per (class, u) bucket as in
 // Section 5.5's statistics); cost roulette: keep with rho = min(1, cost_cap / (R B / beta))
 __global__ void k_roulette(Cand *cand, const uint32_t *kept, uint32_t *final_, const float *runmax, float em_area,
-                           int repeats, float cost_cap, uint32_t seed, uint32_t iter, unsigned long long *cnt)
+                           int repeats, float cost_cap, uint32_t seed, unsigned long long *cnt)
 {
+    const uint32_t iter = iter_of(cnt);
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const int n = (int)cnt[C_NKEPT];
     bool keep = false;
@@ -464,9 +479,10 @@ __global__ void k_roulette(Cand *cand, const uint32_t *kept, uint32_t *final_, c
 // depend on the sample count only and the flips are independent, so the expectation is kept and
 // the expected cost stays O(n1 log) however small beta is. `cap` is a hard safety bound.
 __global__ void __launch_bounds__(64 * RW) k_recip(SceneDev S, Cand *cand, const uint32_t *final_, int repeats,
-                                                   uint32_t seed, uint32_t iter, uint32_t n1, uint32_t cap,
-                                                   float *runmax, unsigned long long *cnt)
+                                                   uint32_t seed, uint32_t n1, uint32_t cap, float *runmax,
+                                                   unsigned long long *cnt)
 {
+    const uint32_t iter = iter_of(cnt);
     __shared__ int stk[PT_STACK * 64 * RW];
     const int wave = blockIdx.x * RW + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
@@ -570,6 +586,7 @@ __global__ void __launch_bounds__(64 * RW) k_recip_point(SceneDev S, Cand c, int
 struct EyeBuf {
     float4 *ro, *rd, *hit, *beta;   // beta.w = solid-angle pdf of the last sampled direction
     uint32_t *info;                 // bits 0..7 depth, 8 previous vertex Dirac, 9..10 phase, 11..14 u
+    float4 *mis;                    // x = p(z_d -> y_{s-1}) in area measure, y = T, z = S (bits)
     uint32_t *q[2];
     ShadowRay *shadow;
     ProxyItem *proxy;
@@ -577,8 +594,9 @@ struct EyeBuf {
     int npix;
 };
 
-__global__ void k_camera(SceneDev S, EyeBuf E, uint32_t seed, uint32_t iter, unsigned long long *cnt)
+__global__ void k_camera(SceneDev S, EyeBuf E, uint32_t seed, unsigned long long *cnt)
 {
+    const uint32_t iter = iter_of(cnt);
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p == 0) cnt[C_EYE_Q0] = (unsigned long long)E.npix;
     if (p >= E.npix) return;
@@ -592,16 +610,40 @@ __global__ void k_camera(SceneDev S, EyeBuf E, uint32_t seed, uint32_t iter, uns
     E.rd[p] = make_float4(d.x, d.y, d.z, 3.0e38f);
     E.beta[p] = make_float4(1.f, 1.f, 1.f, 0.f);
     E.info[p] = 1u << 8;   // camera counts as a Dirac predecessor for the first hit
+    E.mis[p] = make_float4(0.f, 0.f, 0.f, 0.f);
     E.q[0][p] = (uint32_t)p;
 }
 
 struct EyeParams {
-    uint32_t seed, iter;
+    uint32_t seed;
     int K, u_max;
     int filter;      // 0 all, 1 proxy class only, 2 other only, 3 none (for PT/NEE)
     int proxy_on;
     int nee_on;
+    int mis_on;      // variance-aware MIS between the proxy strategy and PT/NEE (else a partition)
+    int labels_on;   // compute eye subspaces T (Gamma selection or MIS)
+    int gamma_on;
+    int mlp_on;      // subspace S chosen by k_mlp_select (learned mixture) before k_proxy
+    int tiles_on;
+    int M, cand_cap;
 };
+// k_sel = M pi_inc c pi_sel: the proxy strategy's selection factor for a path whose first
+// diffuse eye vertex lies in T and whose y_{s-1} lies in S (surrogate used by both strategies)
+__device__ __forceinline__ float proxy_ksel(const SubDev &D, const EyeParams &P, const unsigned long long *cnt, int T,
+                                            int S, float c)
+{
+    const float ncand = (float)cnt[C_NCAND], nk = (float)cnt[C_NFINAL];
+    if (!(nk > 0.0f)) return 0.0f;
+    const float pi_inc = fminf(1.0f, (float)P.cand_cap / ncand);
+    float ps;
+    if (P.gamma_on) {
+        const int cs = D.s_count[S];
+        ps = cs > 0 ? sel_prob(D, T, S) / (float)cs : 0.0f;
+    } else {
+        ps = 1.0f / nk;
+    }
+    return (float)P.M * pi_inc * c * ps;
+}
 
 // proxy-class state machine over eye vertices (emitters count as D): phase 0 before the first
 // diffuse vertex z_d; 1 at/after z_d with only specular vertices since (u of them); 2 after
@@ -619,7 +661,7 @@ __device__ __forceinline__ bool class_ok(int filter, bool proxy_class)
     return filter == 0 || (filter == 1 && proxy_class) || (filter == 2 && !proxy_class);
 }
 
-__global__ void k_eye_shade(SceneDev S, EyeBuf E, EyeParams P, int t, unsigned long long *cnt)
+__global__ void k_eye_shade(SceneDev S, EyeBuf E, EyeParams P, SubDev D, int t, unsigned long long *cnt)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const int n = (int)cnt[C_EYE_Q0 + t - 1];
@@ -629,7 +671,7 @@ __global__ void k_eye_shade(SceneDev S, EyeBuf E, EyeParams P, int t, unsigned l
     int pid = 0;
     ShadowRay sr;
     ProxyItem pi;
-    float4 nro, nrd, nbeta;
+    float4 nro, nrd, nbeta, nmis;
     uint32_t ninfo = 0;
     if (i < n) {
         pid = qin[i];
@@ -646,6 +688,9 @@ __global__ void k_eye_shade(SceneDev S, EyeBuf E, EyeParams P, int t, unsigned l
             uint32_t info = E.info[pid];
             uint32_t ph = (info >> 9) & 3u, uu = (info >> 11) & 15u;
             const bool prev_delta = (info >> 8) & 1u;
+            float4 mis = P.labels_on ? E.mis[pid] : make_float4(0.f, 0.f, 0.f, 0.f);
+            const int Tl = fbits(mis.y), Sl = fbits(mis.z);
+            const float c_pix = P.tiles_on ? tile_prob(D, pid, S.cam.w) : 1.0f;
             float3 add = f3(0.f, 0.f, 0.f);
             if (m.flags & MF_EMIT) {
                 const bool cls = (ph == 1 && uu >= 1) || ph == 2;
@@ -653,8 +698,19 @@ __global__ void k_eye_shade(SceneDev S, EyeBuf E, EyeParams P, int t, unsigned l
                     const float3 le = emission(S, tri, h.y, h.z, wo);
                     if (nonzero3(le)) {
                         float w = 1.0f;
-                        if (!(t == 1 || prev_delta)) {
-                            const float pl = h.x * h.x / (fabsf(dot3(sh.n, wo)) * S.em_area);
+                        const float cl = fabsf(dot3(sh.n, wo));
+                        const float pl = h.x * h.x / (cl * S.em_area);   // light sampling, solid angle
+                        if (cls && P.mis_on && P.proxy_on) {
+                            // three strategies build this proxy-class path (area measure at y_0,
+                            // common factors dropped): BSDF hit, NEE at the previous vertex, proxy
+                            const float J0 = cl / (h.x * h.x);
+                            const float Ap = proxy_mis_factor(D, ph == 2 ? 1 : 0, (int)uu, Sl,
+                                                              proxy_ksel(D, P, cnt, Tl, Sl, c_pix));
+                            const float hit = mis.x * bt.w * J0;
+                            const float nee = prev_delta ? 0.0f : mis.x / S.em_area;
+                            const float prx = ph == 2 ? Ap / S.em_area : Ap * bt.w * J0;
+                            w = hit / (hit + nee + prx);
+                        } else if (!(t == 1 || prev_delta)) {
                             w = bt.w / (bt.w + pl);
                         }
                         add = beta * le * w;
@@ -664,17 +720,28 @@ __global__ void k_eye_shade(SceneDev S, EyeBuf E, EyeParams P, int t, unsigned l
             if (nonzero3(add)) atomic_add3(E.frame + 3 * pid, add);
             if (t < P.K) {
                 const bool spec = (m.flags & MF_SPEC) != 0;
+                const uint32_t ph0 = ph, uu0 = uu;
                 pstate_push(ph, uu, spec, P.u_max);
-                Rng r = rng_make(P.seed, S_EYE, (uint32_t)pid, P.iter, (uint32_t)t);
-                if (P.proxy_on && ph == 1 && uu == 0 && !spec) {
+                Rng r = rng_make(P.seed, S_EYE, (uint32_t)pid, iter_of(cnt), (uint32_t)t);
+                const bool at_zd = ph == 1 && uu == 0 && !spec;
+                int Tnew = Tl;
+                if (at_zd && P.labels_on) {
+                    float f[9];
+                    feat9(S, x, sh.n, wo, f);
+                    Tnew = nearest(D.eye_c, D.n_eye, f);
+                }
+                const float u0 = rng_f(r), u1 = rng_f(r), u2 = rng_f(r);
+                const float ut = rng_f(r);
+                if (P.proxy_on && at_zd && ut < c_pix) {
                     proxy = true;
                     pi.x = make_float4(x.x, x.y, x.z, ibits(tri));
                     pi.wo = make_float4(wo.x, wo.y, wo.z, ibits(t));
                     pi.beta = make_float4(beta.x, beta.y, beta.z, ibits(pid));
+                    pi.aux = make_float4(ibits(Tnew), c_pix, 0.f, 0.f);
                 }
-                const float u0 = rng_f(r), u1 = rng_f(r), u2 = rng_f(r);
                 if (P.nee_on && !(m.flags & MF_DELTA) && S.n_em > 0) {
                     const bool cls = (ph == 1 && uu >= 1) || ph == 2;
+                    const bool mis3 = cls && P.mis_on && P.proxy_on;
                     if (class_ok(P.filter, cls)) {
                         const LPoint L = sample_emitter(S, u0, u1, u2);
                         const float3 dl = L.p - x;
@@ -687,7 +754,28 @@ __global__ void k_eye_shade(SceneDev S, EyeBuf E, EyeParams P, int t, unsigned l
                                 const float3 le = emission(S, L.tri, L.b1, L.b2, -wl);
                                 const float pl = dist2 / (cl * S.em_area);
                                 const float pb = bsdf_pdf(m, sh.n, wo, wl);
-                                const float3 c = beta * fs * le * (fabsf(dot3(sh.n, wl)) / pl * (pl / (pl + pb)));
+                                float w = pl / (pl + pb);
+                                if (mis3) {
+                                    // this vertex is y_1. If it is y_{s-1} itself (class A, u = 1), its
+                                    // density from z_d and its subspace (with the direction toward this
+                                    // path's light-side neighbour, here the light sample) are taken now
+                                    const bool at_v = ph == 1 && uu == 1;
+                                    float pz = mis.x;
+                                    int Sv = Sl;
+                                    if (at_v) {
+                                        pz = bt.w * fabsf(dot3(sh.n, wo)) / (h.x * h.x);
+                                        float f[9];
+                                        feat9(S, x, sh.n, wl, f);
+                                        Sv = nearest(D.spec_c, D.n_spec, f);
+                                    }
+                                    const float J0 = cl / dist2;
+                                    const float Ap = proxy_mis_factor(D, ph == 2 ? 1 : 0, (int)uu, Sv,
+                                                                      proxy_ksel(D, P, cnt, Tl, Sv, c_pix));
+                                    const float hitp = pz * pb * J0, nee = pz / S.em_area;
+                                    const float prx = ph == 2 ? Ap / S.em_area : Ap * pb * J0;
+                                    w = nee / (hitp + nee + prx);
+                                }
+                                const float3 c = beta * fs * le * (fabsf(dot3(sh.n, wl)) / pl * w);
                                 if (nonzero3(c)) {
                                     shadow = true;
                                     sr.o = make_float4(x.x, x.y, x.z, ibits(tri));
@@ -709,6 +797,15 @@ __global__ void k_eye_shade(SceneDev S, EyeBuf E, EyeParams P, int t, unsigned l
                         nrd = make_float4(bs.wi.x, bs.wi.y, bs.wi.z, 3.0e38f);
                         nbeta = make_float4(nb.x, nb.y, nb.z, bs.pdf);
                         ninfo = (uint32_t)t | (bs.delta ? 1u << 8 : 0u) | (ph << 9) | (uu << 11);
+                        nmis = make_float4(mis.x, ibits(Tnew), mis.z, 0.f);
+                        if (P.labels_on && ph0 == 1 && uu0 == 0 && ph == 1 && uu == 1) {
+                            // this vertex is y_{s-1}: record p(z_d -> y_{s-1}) (area) and its specular
+                            // subspace from (position, normal, direction toward the light side)
+                            float f[9];
+                            feat9(S, x, sh.n, bs.wi, f);
+                            nmis.x = bt.w * fabsf(dot3(sh.n, wo)) / (h.x * h.x);
+                            nmis.z = ibits(nearest(D.spec_c, D.n_spec, f));
+                        }
                     }
                 }
             }
@@ -722,6 +819,7 @@ __global__ void k_eye_shade(SceneDev S, EyeBuf E, EyeParams P, int t, unsigned l
     if (cont) {
         qout[cs] = (uint32_t)pid;
         E.ro[pid] = nro; E.rd[pid] = nrd; E.beta[pid] = nbeta; E.info[pid] = ninfo;
+        if (P.labels_on) E.mis[pid] = nmis;
     }
 }
 
@@ -741,18 +839,23 @@ __global__ void __launch_bounds__(WG) k_occluded(SceneDev S, EyeBuf E, int t, un
     wave_count(cnt + C_RAYS_SHADOW, act ? 1u : 0u);
 }
 
-struct ProxyParams {
-    uint32_t seed, iter;
-    int K, M, cand_cap, repeats;
+struct StatBuf {
+    float *gamma_acc;      // [n_eye * n_spec] accumulated proxy luminance per (T, S)
+    float *tile_proxy, *tile_total;
 };
 
-// Proxy connection (Section 5.1): pick a kept incomplete sub-path (uniformly), connect z_d to
-// y_{s-1}, retrace the u dropped vertices by sampling the BSDF at y_{s-1} given the direction to
-// z_d and then at each new vertex, abort on an S/D mismatch, weight with 1/P's estimate and
-// normalise by M pi_inc rho pi_j; p(h*) = 1 (class A) or 1/A (class B).
+// the learned selection's kernels (they read the proxy queue filled above)
+#include "pt_mlp.h"
+
+// Proxy connection (Section 5.1): pick a kept incomplete sub-path (Gamma[T, S] row by its alias
+// table, then uniformly within S, Section 5.6; or uniformly among all), connect z_d to y_{s-1},
+// retrace the u dropped vertices by sampling the BSDF at y_{s-1} given the direction to z_d and
+// then at each new vertex, abort on an S/D mismatch, weight with 1/P's estimate and normalise by
+// M pi_inc rho pi_j c; p(h*) = 1 (class A) or 1/A (class B). With MIS the contribution is
+// weighted against PT and NEE (Section 5.4) with the same surrogate densities the eye pass uses.
 __global__ void __launch_bounds__(WG) k_proxy(SceneDev S, EyeBuf E, const Cand *__restrict__ cand,
-                                              const uint32_t *__restrict__ final_, ProxyParams P,
-                                              unsigned long long *cnt)
+                                              const uint32_t *__restrict__ final_, EyeParams P, SubDev D,
+                                              StatBuf SB, MlpTrain MT, int repeats, unsigned long long *cnt)
 {
     __shared__ int stk[PT_STACK * WG];
     const int i = blockIdx.x * WG + threadIdx.x;
@@ -763,18 +866,49 @@ __global__ void __launch_bounds__(WG) k_proxy(SceneDev S, EyeBuf E, const Cand *
     if (i < n && nk > 0) {
         const ProxyItem it = E.proxy[i];
         const int pix = fbits(it.beta.w);
-        Rng r = rng_make(P.seed, S_PROXY, (uint32_t)pix, P.iter, 0u);
-        const int j = min((int)(rng_f(r) * (float)nk), nk - 1);
-        const Cand c = cand[final_[j]];
-        const float pi_j = 1.0f / (float)nk;
+        const int T = fbits(it.aux.x);
+        const float c_pix = it.aux.y;
+        Rng r = rng_make(P.seed, S_PROXY, (uint32_t)pix, iter_of(cnt), 0u);
+        int ci;
+        float pi_j;
+        int Ssel = 0;
+        const float u0 = rng_f(r), u1 = rng_f(r), u2 = rng_f(r);
+        if (P.mlp_on) {
+            // S and its mixture probability from k_mlp_select, then uniformly within S
+            Ssel = fbits(it.aux.z);
+            const int cs = Ssel >= 0 ? D.s_count[Ssel] : 0;
+            if (cs > 0) {
+                ci = D.s_list[D.s_off[Ssel] + min((int)(u2 * (float)cs), cs - 1)];
+                pi_j = it.aux.w / (float)cs;
+            } else {
+                ci = 0;
+                pi_j = 0.0f;
+            }
+        } else if (P.gamma_on) {
+            const int ne = *D.n_nonempty;
+            const int j = min((int)(u0 * (float)ne), ne - 1);
+            const size_t row = (size_t)T * D.n_spec;
+            const int jj = u1 < D.al_prob[row + j] ? j : D.al_idx[row + j];
+            Ssel = D.nonempty[jj];
+            const int cs = D.s_count[Ssel];
+            const int k = min((int)(u2 * (float)cs), cs - 1);
+            ci = D.s_list[D.s_off[Ssel] + k];
+            pi_j = sel_prob(D, T, Ssel) / (float)cs;
+        } else {
+            ci = (int)final_[min((int)(u0 * (float)nk), nk - 1)];
+            pi_j = 1.0f / (float)nk;
+        }
+        const Cand c = cand[ci];
         const int cls = c.cls_u >> 8, u = c.cls_u & 0xFF;
         const int d = fbits(it.wo.w);
+        float3 zn = f3(0.f, 0.f, 1.f);
         float3 add = f3(0.f, 0.f, 0.f);
-        if (d + 1 + u + cls <= P.K) {
+        if (d + 1 + u + cls <= P.K && pi_j > 0.0f) {
             const float3 xd = xyz(it.x);
             const int td = fbits(it.x.w);
             const TriShade &shd = S.shade[td];
             const MatDev md = S.mats[shd.mat];
+            zn = shd.n;
             const float3 v = xyz(c.v);
             const int vt = fbits(c.v.w);
             const float3 vn = S.shade[vt].n;
@@ -785,16 +919,19 @@ __global__ void __launch_bounds__(WG) k_proxy(SceneDev S, EyeBuf E, const Cand *
             if (nonzero3(fz) && !occluded(C, xd, td, v, vt)) {
                 const float G = fabsf(dot3(shd.n, wzv)) * fabsf(dot3(vn, wzv)) / d2;
                 float3 thr = f3(1.f, 1.f, 1.f), term = f3(0.f, 0.f, 0.f);
-                float3 cur = v, wo = -wzv, curn = vn;
+                float3 cur = v, wo = -wzv, curn = vn, first_dir = f3(0.f, 0.f, 1.f);
                 int curt = vt;
-                bool ok = true;
+                bool ok = true, last_delta = false;
+                float last_pdf = 0.0f, J0 = 0.0f, pb_y1 = 0.0f;
                 for (int k = 1; k <= u && ok; ++k) {
                     const MatDev m = S.mats[S.shade[curt].mat];
                     const float a = rng_f(r), b = rng_f(r), cc = rng_f(r);
                     const BS bs = bsdf_sample(m, curn, wo, a, b, cc, true);
                     Hit h;
                     if (!bs.ok || !closest(C, cur, bs.wi, curt, h)) { ok = false; break; }
+                    if (k == 1) first_dir = bs.wi;
                     thr = thr * bs.w;
+                    last_pdf = bs.pdf; last_delta = bs.delta;
                     const MatDev mh = S.mats[S.shade[h.tri].mat];
                     const float3 y = tri_point(S, h.tri, h.b1, h.b2);
                     const float3 ny = S.shade[h.tri].n;
@@ -803,6 +940,7 @@ __global__ void __launch_bounds__(WG) k_proxy(SceneDev S, EyeBuf E, const Cand *
                     } else if (cls == 0) {
                         if (!(mh.flags & MF_EMIT)) { ok = false; break; }
                         term = emission(S, h.tri, h.b1, h.b2, -bs.wi);
+                        J0 = fabsf(dot3(ny, bs.wi)) / (h.t * h.t);
                     } else {
                         if (mh.flags & MF_SPEC) { ok = false; break; }
                         const float3 y0 = xyz(c.hc);
@@ -815,36 +953,97 @@ __global__ void __launch_bounds__(WG) k_proxy(SceneDev S, EyeBuf E, const Cand *
                         if (c0 <= 0.0f || !nonzero3(f1) || occluded(C, y, h.tri, y0, t0)) { ok = false; break; }
                         const float3 le = emission(S, t0, c.hc_b1, c.hc_b2, -wl);
                         term = f1 * le * (c0 * fabsf(dot3(ny, wl)) / e2 * S.em_area);
+                        J0 = c0 / e2;
+                        pb_y1 = bsdf_pdf(mh, ny, -bs.wi, wl);
                     }
                     cur = y; curt = h.tri; curn = ny; wo = -bs.wi;
                 }
                 if (ok) {
                     const float pi_inc = fminf(1.0f, (float)P.cand_cap / (float)cnt[C_NCAND]);
-                    const float scale = (c.recip_sum / (float)P.repeats) / ((float)P.M * pi_inc * c.rho * pi_j);
-                    add = xyz(it.beta) * fz * thr * term * (G * scale);
+                    const float scale = (c.recip_sum / (float)repeats) /
+                                        ((float)P.M * pi_inc * c.rho * pi_j * c_pix);
+                    float w = 1.0f;
+                    if (P.mis_on) {
+                        // the same three densities the eye pass weighs with (area measure at y_0,
+                        // common factors dropped): BSDF hit from y_1, NEE at y_1, proxy
+                        float f[9];
+                        feat9(S, v, vn, first_dir, f);
+                        const int Sm = nearest(D.spec_c, D.n_spec, f);
+                        const float pz = bsdf_pdf(md, shd.n, xyz(it.wo), wzv) * fabsf(dot3(vn, wzv)) / d2;
+                        const float Ap = proxy_mis_factor(D, cls, u, Sm, proxy_ksel(D, P, cnt, T, Sm, c_pix));
+                        float hit, nee, prx;
+                        if (cls == 0) {
+                            hit = pz * last_pdf * J0;
+                            nee = last_delta ? 0.0f : pz / S.em_area;
+                            prx = Ap * last_pdf * J0;
+                        } else {
+                            hit = pz * pb_y1 * J0;
+                            nee = pz / S.em_area;
+                            prx = Ap / S.em_area;
+                        }
+                        w = prx > 0.0f ? prx / (hit + nee + prx) : 0.0f;
+                    }
+                    add = xyz(it.beta) * fz * thr * term * (G * scale * w);
                 }
             }
         }
-        if (nonzero3(add)) { atomic_add3(E.frame + 3 * pix, add); valid = 1; }
+        if (nonzero3(add)) {
+            atomic_add3(E.frame + 3 * pix, add);
+            valid = 1;
+            if (cnt[C_LEARN]) {
+                const float l = lum(add);
+                if (P.gamma_on) unsafeAtomicAdd(SB.gamma_acc + (size_t)T * D.n_spec + Ssel, l);
+                if (P.mlp_on && l > 0.0f) mlp_record(S, MT, cnt, xyz(it.x), zn, xyz(it.wo), Ssel, l);
+                if (P.tiles_on) {
+                    const int tl = (pix / S.cam.w) / D.tile * D.tiles_x + (pix % S.cam.w) / D.tile;
+                    unsafeAtomicAdd(SB.tile_proxy + tl, l);
+                }
+            }
+        }
     }
     wave_count(cnt + C_PROXY_ATT, (i < n && nk > 0) ? 1u : 0u);
     wave_count(cnt + C_PROXY_VALID, valid);
     wave_count(cnt + C_RAYS_PROXY, C.rays);
 }
 
-// frame -> caller accumulators; non-finite values are counted and dropped; frame cleared
-__global__ void k_accumulate(float *frame, float *acc, float *acc2, int n, unsigned long long *cnt)
+// frame -> caller accumulators; non-finite values are counted and dropped; frame cleared;
+// while learning, each tile's total luminance is accumulated for the tile rule
+__global__ void k_accumulate(float *frame, float *acc, float *acc2, int npix, int W, int tile, int tiles_x,
+                             float *tile_total, unsigned long long *cnt)
 {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
     uint32_t bad = 0;
-    if (i < n) {
-        float v = frame[i];
-        if (!isfinite(v)) { v = 0.0f; bad = 1; }
-        acc[i] += v;
-        if (acc2) acc2[i] += v * v;
-        frame[i] = 0.0f;
+    if (p < npix) {
+        float v[3];
+        for (int k = 0; k < 3; ++k) {
+            v[k] = frame[3 * p + k];
+            if (!isfinite(v[k])) { v[k] = 0.0f; bad = 1; }
+            acc[3 * p + k] += v[k];
+            if (acc2) acc2[3 * p + k] += v[k] * v[k];
+            frame[3 * p + k] = 0.0f;
+        }
+        if (tile_total && cnt[C_LEARN]) {
+            const float l = lum(f3(v[0], v[1], v[2]));
+            if (l > 0.0f) unsafeAtomicAdd(tile_total + (p / W) / tile * tiles_x + (p % W) / tile, l);
+        }
     }
     wave_count(cnt + C_NAN, bad);
+}
+
+__global__ void k_copy(const float *src, float *dst, size_t n)
+{
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) dst[i] = src[i];
+}
+__global__ void k_fill(float *p, float v, size_t n)
+{
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+__global__ void k_fill_i(int *p, int v, size_t n)
+{
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
 }
 
 __global__ void k_resolve(const float *acc, float *out, int n, float inv)

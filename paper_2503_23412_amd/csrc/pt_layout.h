@@ -62,7 +62,7 @@ struct Cand {
     float recip_sum; // sum of the reciprocal estimates of this iteration
     float pmax, psum, pn;
     int32_t spec_sub;// specular subspace S
-    float pad[2];
+    float pad[2];    // octahedral encoding of y_{s-1}'s incident direction (toward y_{s-2})
 };
 static_assert(sizeof(Cand) == 80, "Cand layout");
 
@@ -74,6 +74,9 @@ enum {
     C_PROXYQ = 264, C_NCAND, C_NKEPT, C_NFINAL,
     C_RAYS_EYE, C_RAYS_LIGHT, C_RAYS_SHADOW, C_RAYS_PROXY, C_RAYS_RECIP,
     C_RECIP_SAMPLES, C_RECIP_TRUNC, C_PROXY_ATT, C_PROXY_VALID, C_NAN, C_VISITS, C_TESTS, C_STACK_OVF,
+    C_MLP_N,                 // training samples recorded this iteration
+    C_ITER, C_LEARN,         // iteration index and "still learning" flag (kept across k_zero)
+    C_MLP_T,                 // Adam steps taken (kept across k_zero)
     C_COUNT
 };
 #define PT_MAX_DEPTH 127
@@ -89,4 +92,5 @@ struct ProxyItem {
     float4 x;        // position, w = triangle (bits)
     float4 wo;       // direction toward the previous eye vertex, w = segments so far (bits)
     float4 beta;     // eye throughput, w = pixel (bits)
+    float4 aux;      // x = eye subspace T (bits), y = tile attempt probability c
 };

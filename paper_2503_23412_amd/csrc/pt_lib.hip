@@ -71,9 +71,29 @@ struct pt_scene {
     unsigned long long *cnt = nullptr;
     float *runmax = nullptr;   // [2 * 5] running maxima of f/q per (class, u)
     bool subspaces_ready = false;
+    // subspaces, selection and statistics (allocated by pt_build_subspaces)
+    int n_eye = 0, n_spec = 0, tile = 10, tiles_x = 0, n_tiles = 0;
+    float *eye_c = nullptr, *spec_c = nullptr, *km_sum = nullptr, *km_cnt = nullptr, *feat = nullptr;
+    int *s_count = nullptr, *s_off = nullptr, *s_fill = nullptr, *s_list = nullptr, *nonempty = nullptr, *n_ne = nullptr;
+    float *al_prob = nullptr, *row_sum = nullptr, *gamma_acc = nullptr, *gamma_frz = nullptr;
+    int *al_idx = nullptr, *al_scratch = nullptr;
+    float *rstat_acc = nullptr, *rstat_frz = nullptr, *tile_proxy = nullptr, *tile_total = nullptr;
+    // learned selection: parameters (FP32 master, BF16 copy, gradient, Adam moments) and
+    // activations for max(npix, MLP_CAP) rows
+    int mlp_nout = 0, mlp_rows = 0, mlp_np = 0;
+    bool mlp_ready = false;
+    float *mw = nullptr, *mg = nullptr, *mm = nullptr, *mv = nullptr;
+    uint16_t *mwb = nullptr, *mx = nullptr, *mh[3] = {nullptr, nullptr, nullptr}, *mdz[2] = {nullptr, nullptr},
+             *mg4 = nullptr;
+    float *mz = nullptr, *ml = nullptr, *mdh = nullptr;
+    MlpTrain MT{};
     std::vector<int> inv_order;  // input triangle index -> BVH order
     std::vector<hipEvent_t> ev;
     std::vector<void *> allocs;
+    // captured iteration graph (pt_render_batch) and the key it was captured for
+    hipStream_t cap_stream = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    std::vector<char> gkey;
 
     template <class T> pt_status alloc(T *&p, size_t n)
     {
@@ -88,6 +108,8 @@ struct pt_scene {
     }
     ~pt_scene()
     {
+        if (gexec) (void)hipGraphExecDestroy(gexec);
+        if (cap_stream) (void)hipStreamDestroy(cap_stream);
         for (void *p : allocs) (void)hipFree(p);
         for (hipEvent_t e : ev) (void)hipEventDestroy(e);
     }
@@ -197,7 +219,7 @@ extern "C" pt_status pt_scene_upload(const pt_scene_desc *d, void *stream_, pt_s
         AL(s->L.q[0], M); AL(s->L.q[1], M);
         AL(s->cand, (size_t)4 * M);
         AL(s->kept, (size_t)4 * M); AL(s->final_, (size_t)4 * M);
-        AL(s->E.ro, np); AL(s->E.rd, np); AL(s->E.hit, np); AL(s->E.beta, np); AL(s->E.info, np);
+        AL(s->E.ro, np); AL(s->E.rd, np); AL(s->E.hit, np); AL(s->E.beta, np); AL(s->E.info, np); AL(s->E.mis, np);
         AL(s->E.q[0], np); AL(s->E.q[1], np);
         AL(s->E.shadow, np); AL(s->E.proxy, np);
         AL(s->E.frame, (size_t)3 * np);
@@ -221,6 +243,9 @@ extern "C" pt_status pt_scene_upload(const pt_scene_desc *d, void *stream_, pt_s
         S.tex_w = d->tex_w; S.tex_h = d->tex_h; S.em_tri = s->em_tri; S.em_cdf = s->em_cdf; S.n_em = (int)em.size();
         S.em_area = (float)area_acc;
         S.tmin = 2e-6f * s->scene_diag;
+        S.lo = make_float3(lo[0], lo[1], lo[2]);
+        S.inv_ext = make_float3(1.0f / std::max(hi[0] - lo[0], 1e-6f), 1.0f / std::max(hi[1] - lo[1], 1e-6f),
+                                1.0f / std::max(hi[2] - lo[2], 1e-6f));
         const float *c = d->camera;
         float3 p = make_float3(c[0], c[1], c[2]), tg = make_float3(c[3], c[4], c[5]), up = make_float3(c[6], c[7], c[8]);
         auto nrm = [](float3 a) { float l = std::sqrt(a.x * a.x + a.y * a.y + a.z * a.z); return make_float3(a.x / l, a.y / l, a.z / l); };
@@ -248,20 +273,252 @@ extern "C" pt_status pt_scene_release(pt_scene *s)
     return PT_OK;
 }
 
+namespace {
+pt_status run_kmeans(pt_scene *s, const float *feat, int n, float *cent, int K, int iters, hipStream_t st)
+{
+    k_km_init<<<blocks(K, 256), 256, 0, st>>>(feat, n, cent, K);
+    for (int it = 0; it < iters && n > 0; ++it) {
+        k_fill<<<blocks((long)K * FEAT, 256), 256, 0, st>>>(s->km_sum, 0.0f, (size_t)K * FEAT);
+        k_fill<<<blocks(K, 256), 256, 0, st>>>(s->km_cnt, 0.0f, (size_t)K);
+        k_km_assign<<<blocks(n, 256), 256, 0, st>>>(feat, n, cent, K, s->km_sum, s->km_cnt);
+        k_km_update<<<blocks(K, 256), 256, 0, st>>>(cent, s->km_sum, s->km_cnt, K);
+    }
+    HIPCHK(hipGetLastError());
+    return PT_OK;
+}
+__global__ void k_feat_cands(SceneDev S, const Cand *cand, const unsigned long long *cnt, float *feat)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (int)cnt[C_NCAND]) return;
+    const Cand &c = cand[i];
+    float f[9];
+    feat9(S, xyz(c.v), S.shade[__float_as_int(c.v.w)].n, oct_dec(make_float2(c.pad[0], c.pad[1])), f);
+    for (int j = 0; j < 9; ++j) feat[FEAT * (size_t)i + j] = f[j];
+}
+__global__ void k_feat_proxy(SceneDev S, const ProxyItem *items, const unsigned long long *cnt, float *feat)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (int)cnt[C_PROXYQ]) return;
+    const ProxyItem &p = items[i];
+    float f[9];
+    feat9(S, xyz(p.x), S.shade[__float_as_int(p.x.w)].n, xyz(p.wo), f);
+    for (int j = 0; j < 9; ++j) feat[FEAT * (size_t)i + j] = f[j];
+}
+}  // namespace
+
 extern "C" pt_status pt_build_subspaces(pt_scene *s, const pt_subspace_params *p, void *stream_)
 {
     if (!s || !p) return set_err(PT_EINVAL, "null argument");
     if (p->n_eye <= 0 || p->n_eye > 4096 || p->n_spec <= 0 || p->n_spec > 4096 || p->n_pretrace < 0 ||
-        p->kmeans_iters < 0)
+        p->kmeans_iters < 0 || p->kmeans_iters > 64)
         return set_err(PT_EINVAL, "subspace parameters out of range");
-    hipStream_t stream = (hipStream_t)stream_;
-    HIPCHK(hipMemsetAsync(s->runmax, 0, sizeof(float) * 16, stream));
+    hipStream_t st = (hipStream_t)stream_;
+    const int M = s->max_light, np = s->npix;
+    const int ne = p->n_eye, ns = p->n_spec;
+    if (ne != s->n_eye || ns != s->n_spec || !s->eye_c) {
+        pt_status e;
+#define AL(ptr, n) if ((e = s->alloc(ptr, n)) != PT_OK) return e;
+        AL(s->eye_c, (size_t)ne * FEAT); AL(s->spec_c, (size_t)ns * FEAT);
+        AL(s->km_sum, (size_t)std::max(ne, ns) * FEAT); AL(s->km_cnt, (size_t)std::max(ne, ns));
+        if (!s->feat) AL(s->feat, (size_t)std::max(np, 4 * M) * FEAT);
+        AL(s->s_count, ns); AL(s->s_off, ns); AL(s->s_fill, ns); AL(s->nonempty, ns); AL(s->n_ne, 1);
+        if (!s->s_list) AL(s->s_list, (size_t)4 * M);
+        AL(s->al_prob, (size_t)ne * ns); AL(s->al_idx, (size_t)ne * ns); AL(s->al_scratch, (size_t)2 * ne * ns);
+        AL(s->row_sum, ne); AL(s->gamma_acc, (size_t)ne * ns); AL(s->gamma_frz, (size_t)ne * ns);
+        AL(s->rstat_acc, (size_t)30 * ns); AL(s->rstat_frz, (size_t)30 * ns);
+        s->tiles_x = (s->W + s->tile - 1) / s->tile;
+        s->n_tiles = s->tiles_x * ((s->H + s->tile - 1) / s->tile);
+        if (!s->tile_proxy) { AL(s->tile_proxy, s->n_tiles); AL(s->tile_total, s->n_tiles); }
+#undef AL
+        s->n_eye = ne; s->n_spec = ns;
+    }
+    // pre-trace: light sub-paths -> candidate specular vertices; eye paths -> first diffuse vertices
+    SceneDev S = s->S;
+    LightBuf L = s->L;
+    L.M = std::max(1, std::min(M, p->n_pretrace > 0 ? p->n_pretrace : M));
+    const uint32_t key = 0xFFFFFF00u;
+    k_zero<<<blocks(C_COUNT, 256), 256, 0, st>>>(s->cnt, C_COUNT);
+    k_iter<<<1, 1, 0, st>>>(s->cnt, key, 0, 0);
+    k_light_gen<<<blocks(L.M, 256), 256, 0, st>>>(S, L, p->seed, s->cnt);
+    for (int vi = 1; vi < PT_LMAX; ++vi) {
+        k_extend<false><<<blocks(L.M, WG), WG, 0, st>>>(S, L.q[(vi - 1) & 1], s->cnt, C_LIGHT_Q0 + vi - 1, L.ro, L.rd,
+                                                        L.hit, s->cnt, C_RAYS_LIGHT);
+        k_light_shade<<<blocks(L.M, 256), 256, 0, st>>>(S, L, p->seed, vi, PT_LMAX, s->cnt);
+    }
+    k_candidates<<<blocks(L.M, 256), 256, 0, st>>>(L, 4, s->cand, s->cnt);
+    k_feat_cands<<<blocks(4L * L.M, 256), 256, 0, st>>>(S, s->cand, s->cnt, s->feat);
+    unsigned long long c[C_COUNT];
+    HIPCHK(hipMemcpyAsync(c, s->cnt, sizeof(c), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    TRY(run_kmeans(s, s->feat, (int)c[C_NCAND], s->spec_c, ns, p->kmeans_iters, st));
+    // eye: first diffuse vertices of one pass (the proxy queue collects them)
+    EyeBuf E = s->E;
+    EyeParams EP{};
+    EP.seed = p->seed; EP.K = 8; EP.u_max = 4; EP.filter = 3; EP.proxy_on = 1; EP.nee_on = 0;
+    SubDev D{};
+    k_zero<<<blocks(C_COUNT, 256), 256, 0, st>>>(s->cnt, C_COUNT);
+    k_camera<<<blocks(np, 256), 256, 0, st>>>(S, E, p->seed, s->cnt);
+    for (int t = 1; t <= EP.K; ++t) {
+        k_extend<false><<<blocks(np, WG), WG, 0, st>>>(S, E.q[(t - 1) & 1], s->cnt, C_EYE_Q0 + t - 1, E.ro, E.rd, E.hit,
+                                                       s->cnt, C_RAYS_EYE);
+        k_eye_shade<<<blocks(np, 256), 256, 0, st>>>(S, E, EP, D, t, s->cnt);
+    }
+    k_fill<<<blocks(3L * np, 256), 256, 0, st>>>(E.frame, 0.0f, (size_t)3 * np);
+    k_feat_proxy<<<blocks(np, 256), 256, 0, st>>>(S, E.proxy, s->cnt, s->feat);
+    HIPCHK(hipMemcpyAsync(c, s->cnt, sizeof(c), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    TRY(run_kmeans(s, s->feat, (int)c[C_PROXYQ], s->eye_c, ne, p->kmeans_iters, st));
+    // statistics start from nothing
+    k_fill<<<blocks((long)ne * ns, 256), 256, 0, st>>>(s->gamma_acc, 0.0f, (size_t)ne * ns);
+    k_fill<<<blocks(30L * ns, 256), 256, 0, st>>>(s->rstat_acc, 0.0f, (size_t)30 * ns);
+    k_fill<<<blocks(s->n_tiles, 256), 256, 0, st>>>(s->tile_proxy, 0.0f, (size_t)s->n_tiles);
+    k_fill<<<blocks(s->n_tiles, 256), 256, 0, st>>>(s->tile_total, 0.0f, (size_t)s->n_tiles);
+    k_fill<<<1, 16, 0, st>>>(s->runmax, 0.0f, 16);
+    k_fill_i<<<blocks(ns, 256), 256, 0, st>>>(s->s_count, 0, (size_t)ns);
+    k_fill_i<<<1, 64, 0, st>>>(s->n_ne, 0, 1);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(st));
     s->subspaces_ready = true;
+    s->mlp_ready = false;   // the network starts again with the new subspaces
     return PT_OK;
 }
 
-extern "C" pt_status pt_render_iteration(pt_scene *s, const pt_iter_params *p, float *acc, float *acc2,
-                                         pt_iter_stats *stats, void *stream_)
+namespace {
+#define MLP_CAP 65536   // training samples per iteration
+#define MLP_KSPLIT 32   // K splits of the weight-gradient products (K = samples)
+
+struct MlpOff {
+    size_t W1, b1, W2, b2, W3, b3, W4, b4, n;
+};
+MlpOff mlp_off(int nout)
+{
+    MlpOff o;
+    o.W1 = 0; o.b1 = o.W1 + MLP_IN * MLP_H;
+    o.W2 = o.b1 + MLP_H; o.b2 = o.W2 + MLP_H * MLP_H;
+    o.W3 = o.b2 + MLP_H; o.b3 = o.W3 + MLP_H * MLP_H;
+    o.W4 = o.b3 + MLP_H; o.b4 = o.W4 + (size_t)MLP_H * nout;
+    o.n = o.b4 + nout;
+    return o;
+}
+
+__global__ void k_set_counter(unsigned long long *cnt, int idx, unsigned long long v)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) cnt[idx] = v;
+}
+__global__ void k_to_bf16(const float *w, uint16_t *wb, size_t n)
+{
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) wb[i] = f2bf(w[i]);
+}
+__global__ void k_sum1(const float *x, int n, float *out)
+{
+    __shared__ float red[256];
+    float a = 0.0f;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) a += x[i];
+    red[threadIdx.x] = a;
+    __syncthreads();
+    for (int k = blockDim.x / 2; k > 0; k >>= 1) {
+        if ((int)threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = red[0];
+}
+
+// C = A B on MFMA (see k_gemm); ksplit > 1 adds into C with atomics
+void gemm(hipStream_t st, int M, int N, int K, const uint16_t *A, int sam, int sak, const uint16_t *B, int sbk, int sbn,
+          float *C, int scm, const unsigned long long *cnt, int m_cidx, int k_cidx, int ksplit)
+{
+    const long waves = (long)((M + 15) / 16) * ((N + 15) / 16);
+    dim3 grid(blocks(waves, 4), 1, ksplit);
+    k_gemm<<<grid, 256, 0, st>>>(M, N, K, A, sam, sak, B, sbk, sbn, C, scm, 0, cnt, m_cidx, k_cidx);
+}
+
+// allocation (once per output width) and, unless ready, initialisation of the network
+pt_status ensure_mlp(pt_scene *s, hipStream_t st)
+{
+    if (!s->subspaces_ready) return set_err(PT_ESTATE, "pt_build_subspaces must run first");
+    const int nout = s->n_spec;
+    if (s->mlp_nout != nout) {
+        const MlpOff o = mlp_off(nout);
+        const int R = std::max(s->npix, MLP_CAP);
+        pt_status e;
+#define AL(ptr, n) if ((e = s->alloc(ptr, n)) != PT_OK) return e;
+        AL(s->mw, o.n); AL(s->mg, o.n); AL(s->mm, o.n); AL(s->mv, o.n); AL(s->mwb, o.n);
+        AL(s->mx, (size_t)R * MLP_IN);
+        for (int k = 0; k < 3; ++k) AL(s->mh[k], (size_t)R * MLP_H);
+        for (int k = 0; k < 2; ++k) AL(s->mdz[k], (size_t)R * MLP_H);
+        AL(s->mg4, (size_t)MLP_CAP * nout);
+        AL(s->mz, (size_t)R * MLP_H); AL(s->mdh, (size_t)R * MLP_H);
+        AL(s->ml, (size_t)R * nout);
+        if (!s->MT.feat) {
+            AL(s->MT.feat, (size_t)MLP_CAP * 9); AL(s->MT.label, MLP_CAP); AL(s->MT.weight, MLP_CAP);
+            AL(s->MT.wsum, 1);
+            s->MT.cap = MLP_CAP;
+        }
+#undef AL
+        s->mlp_nout = nout; s->mlp_rows = R; s->mlp_np = (int)o.n;
+        s->mlp_ready = false;
+    }
+    if (!s->mlp_ready) {
+        k_mlp_init<<<blocks(s->mlp_np, 256), 256, 0, st>>>(s->mw, s->mwb, s->mg, s->mm, s->mv, nout, 0x6d6c7001u);
+        k_set_counter<<<1, 1, 0, st>>>(s->cnt, C_MLP_T, 0ull);
+        HIPCHK(hipGetLastError());
+        s->mlp_ready = true;
+    }
+    return PT_OK;
+}
+
+// logits (no bias) of the first rows of s->mx: rows = min(M, cnt[m_cidx]) (or M); hidden
+// activations kept in mh[0..2] for the backward pass
+void mlp_forward(pt_scene *s, int M, const unsigned long long *cnt, int m_cidx, float *logits, hipStream_t st)
+{
+    const MlpOff o = mlp_off(s->mlp_nout);
+    const uint16_t *in = s->mx;
+    const size_t Wo[3] = {o.W1, o.W2, o.W3}, bo[3] = {o.b1, o.b2, o.b3};
+    for (int l = 0; l < 3; ++l) {
+        const int K = l == 0 ? MLP_IN : MLP_H;
+        gemm(st, M, MLP_H, K, in, K, 1, s->mwb + Wo[l], MLP_H, 1, s->mz, MLP_H, cnt, m_cidx, -1, 1);
+        k_bias_relu<<<blocks((long)M * MLP_H, 256), 256, 0, st>>>(s->mz, s->mw + bo[l], s->mh[l], M, MLP_H, cnt, m_cidx);
+        in = s->mh[l];
+    }
+    gemm(st, M, s->mlp_nout, MLP_H, in, MLP_H, 1, s->mwb + o.W4, s->mlp_nout, 1, logits, s->mlp_nout, cnt, m_cidx, -1, 1);
+}
+
+// gradient of the weighted cross entropy over the R = min(MLP_CAP, cnt[C_MLP_N]) samples whose
+// features are encoded in s->mx, labels/weights in s->MT (sum of weights in MT.wsum), added into
+// s->mg (which is zero before)
+void mlp_backward(pt_scene *s, const int *label, const float *weight, hipStream_t st)
+{
+    const int R = MLP_CAP, N = s->mlp_nout;
+    const MlpOff o = mlp_off(N);
+    unsigned long long *cnt = s->cnt;
+    mlp_forward(s, R, cnt, C_MLP_N, s->ml, st);
+    k_ce_grad<<<R, 256, 0, st>>>(s->ml, s->mw + o.b4, label, weight, s->MT.wsum, R, N, s->mg4, cnt, C_MLP_N);
+    k_colsum<<<dim3(blocks(N, 64), R / MLP_STRIP), 64, 0, st>>>(s->mg4, R, N, s->mg + o.b4, cnt, C_MLP_N);
+    // layer 4: dW4 = H3^T G4, dH3 = G4 W4^T
+    gemm(st, MLP_H, N, R, s->mh[2], 1, MLP_H, s->mg4, N, 1, s->mg + o.W4, N, cnt, -1, C_MLP_N, MLP_KSPLIT);
+    gemm(st, R, MLP_H, N, s->mg4, N, 1, s->mwb + o.W4, 1, N, s->mdh, MLP_H, cnt, C_MLP_N, -1, 1);
+    const size_t Wo[3] = {o.W1, o.W2, o.W3}, bo[3] = {o.b1, o.b2, o.b3};
+    for (int l = 2; l >= 0; --l) {
+        uint16_t *dz = s->mdz[l & 1];
+        k_relu_back<<<blocks((long)R * MLP_H, 256), 256, 0, st>>>(s->mdh, s->mh[l], dz, R, MLP_H, cnt, C_MLP_N);
+        k_colsum<<<dim3(1, R / MLP_STRIP), 64, 0, st>>>(dz, R, MLP_H, s->mg + bo[l], cnt, C_MLP_N);
+        const uint16_t *in = l == 0 ? s->mx : s->mh[l - 1];
+        const int K = l == 0 ? MLP_IN : MLP_H;
+        gemm(st, K, MLP_H, R, in, 1, K, dz, MLP_H, 1, s->mg + Wo[l], MLP_H, cnt, -1, C_MLP_N, MLP_KSPLIT);
+        if (l > 0)
+            gemm(st, R, MLP_H, MLP_H, dz, MLP_H, 1, s->mwb + Wo[l], 1, MLP_H, s->mdh, MLP_H, cnt, C_MLP_N, -1, 1);
+    }
+}
+
+void mlp_adam(pt_scene *s, float lr, hipStream_t st)
+{
+    k_adam<<<blocks(s->mlp_np, 256), 256, 0, st>>>(s->mw, s->mwb, s->mg, s->mm, s->mv, s->mlp_np, lr, 0.9f, 0.999f,
+                                                   1e-8f, s->cnt);
+    k_mlp_tick<<<1, 1, 0, st>>>(s->cnt);
+}
+
+pt_status check_params(pt_scene *s, const pt_iter_params *p, float *acc)
 {
     if (!s || !p || !acc) return set_err(PT_EINVAL, "null argument");
     if (!s->subspaces_ready) return set_err(PT_ESTATE, "pt_build_subspaces must run before pt_render_iteration");
@@ -272,7 +529,17 @@ extern "C" pt_status pt_render_iteration(pt_scene *s, const pt_iter_params *p, f
     if (p->cand_cap < 1 || p->pilot < 1) return set_err(PT_EINVAL, "cand_cap and pilot must be positive");
     if ((p->flags & PT_FLAG_ONLY_PROXY_CLASS) && (p->flags & PT_FLAG_ONLY_OTHER))
         return set_err(PT_EINVAL, "class filters are exclusive");
-    hipStream_t stream = (hipStream_t)stream_;
+    if ((p->flags & PT_FLAG_MLP) && !(p->mlp_mix >= 0.0f && p->mlp_mix < 1.0f && p->mlp_lr > 0.0f))
+        return set_err(PT_EINVAL, "PT_FLAG_MLP needs 0 <= mlp_mix < 1 and mlp_lr > 0");
+    return PT_OK;
+}
+
+// Enqueues one iteration on `stream`: kernel launches only (no host synchronisation, no
+// memset), so the sequence can be captured into a HIP graph. graph = true: the iteration index
+// in device memory is advanced by one instead of being set from p->iteration.
+pt_status enqueue_iteration(pt_scene *s, const pt_iter_params *p, float *acc, float *acc2, hipStream_t stream,
+                            bool graph)
+{
     SceneDev S = s->S;
     LightBuf L = s->L;
     L.M = p->n_light;
@@ -288,38 +555,81 @@ extern "C" pt_status pt_render_iteration(pt_scene *s, const pt_iter_params *p, f
             s->ev.push_back(e);
         }
     }
+    const bool gamma = proxy && (p->flags & PT_FLAG_GAMMA);
+    const bool mis = proxy && (p->flags & PT_FLAG_MIS);
+    const bool tiles = proxy && (p->flags & PT_FLAG_TILES) && p->tile == s->tile;
+    const bool mlp = proxy && (p->flags & PT_FLAG_MLP) && s->mlp_ready && s->mlp_nout == s->n_spec;
+    const bool labels = gamma || mis || mlp;
+    const int ne = s->n_eye, ns = s->n_spec;
     k_zero<<<blocks(C_COUNT, 256), 256, 0, stream>>>(s->cnt, C_COUNT);
+    k_iter<<<1, 1, 0, stream>>>(s->cnt, p->iteration, graph ? 1 : 0, p->train_iters);
+    if (labels) {
+        // statistics of earlier iterations only: frozen copies for this iteration
+        k_copy<<<blocks((long)ne * ns, 256), 256, 0, stream>>>(s->gamma_acc, s->gamma_frz, (size_t)ne * ns);
+        k_copy<<<blocks(30L * ns, 256), 256, 0, stream>>>(s->rstat_acc, s->rstat_frz, (size_t)30 * ns);
+    }
     if (proxy) {
         // light pass: y_0 .. y_{lmax-1}
         const int lmax = std::min(p->max_depth - 1, PT_LMAX);
-        k_light_gen<<<blocks(M, 256), 256, 0, stream>>>(S, L, p->seed, p->iteration, s->cnt);
+        k_light_gen<<<blocks(M, 256), 256, 0, stream>>>(S, L, p->seed, s->cnt);
         for (int vi = 1; vi < lmax; ++vi) {
             k_extend<false><<<blocks(M, WG), WG, 0, stream>>>(S, L.q[(vi - 1) & 1], s->cnt, C_LIGHT_Q0 + vi - 1, L.ro,
                                                               L.rd, L.hit, s->cnt, C_RAYS_LIGHT);
-            k_light_shade<<<blocks(M, 256), 256, 0, stream>>>(S, L, p->seed, p->iteration, vi, lmax, s->cnt);
+            k_light_shade<<<blocks(M, 256), 256, 0, stream>>>(S, L, p->seed, vi, lmax, s->cnt);
         }
         if (lmax >= 2) {
             k_candidates<<<blocks(M, 256), 256, 0, stream>>>(L, p->u_max, s->cand, s->cnt);
             const int maxc = 4 * M;
-            k_keep<<<blocks(maxc, 256), 256, 0, stream>>>(p->cand_cap, p->seed, p->iteration, s->kept, maxc, s->cnt);
-            k_pilot<<<blocks(maxc, RW), 64 * RW, 0, stream>>>(S, s->cand, s->kept, p->pilot, p->seed, p->iteration,
-                                                             s->runmax, s->cnt);
+            k_keep<<<blocks(maxc, 256), 256, 0, stream>>>(p->cand_cap, p->seed, s->kept, maxc, s->cnt);
+            k_pilot<<<blocks(maxc, RW), 64 * RW, 0, stream>>>(S, s->cand, s->kept, p->pilot, p->seed, s->runmax,
+                                                             s->cnt);
             k_roulette<<<blocks(maxc, 256), 256, 0, stream>>>(s->cand, s->kept, s->final_, s->runmax, S.em_area,
-                                                              p->recip_repeats, p->cost_cap, p->seed, p->iteration,
-                                                              s->cnt);
+                                                              p->recip_repeats, p->cost_cap, p->seed, s->cnt);
             const uint32_t n1 = (uint32_t)std::max(64.0f, p->cost_cap / (float)p->recip_repeats);
             k_recip<<<blocks((long)maxc * p->recip_repeats, RW), 64 * RW, 0, stream>>>(
-                S, s->cand, s->final_, p->recip_repeats, p->seed, p->iteration, n1, 1u << 20, s->runmax, s->cnt);
+                S, s->cand, s->final_, p->recip_repeats, p->seed, n1, 1u << 20, s->runmax, s->cnt);
+            if (labels) {
+                SubDev D0{};
+                D0.spec_c = s->spec_c; D0.n_spec = ns;
+                k_fill_i<<<blocks(ns, 256), 256, 0, stream>>>(s->s_count, 0, (size_t)ns);
+                k_label_cands<<<blocks(maxc, 256), 256, 0, stream>>>(S, D0, s->cand, s->final_, s->cnt, s->s_count);
+                k_scan_sub<<<1, 1024, 0, stream>>>(s->s_count, s->s_off, s->s_fill, s->nonempty, s->n_ne, ns);
+                k_scatter_sub<<<blocks(maxc, 256), 256, 0, stream>>>(s->cand, s->final_, s->cnt, s->s_fill, s->s_list);
+                if (gamma)
+                    k_alias_rows<<<blocks(ne, 64), 64, 0, stream>>>(s->gamma_frz, ne, ns, s->nonempty, s->n_ne,
+                                                                   p->defensive, s->al_prob, s->al_idx, s->row_sum,
+                                                                   s->al_scratch);
+                k_rstat<<<blocks(maxc, 256), 256, 0, stream>>>(s->cand, s->final_, s->cnt, p->recip_repeats, ns,
+                                                                  s->rstat_acc);
+            }
         }
     }
-    // eye pass
-    EyeParams EP;
-    EP.seed = p->seed; EP.iter = p->iteration; EP.K = p->max_depth; EP.u_max = p->u_max;
-    EP.filter = (p->flags & PT_FLAG_ONLY_PROXY_CLASS) ? (proxy ? 3 : 1) : (proxy ? 2 : ((p->flags & PT_FLAG_ONLY_OTHER) ? 2 : 0));
+    // eye pass. Without MIS the proxy strategy alone scores the proxy-class paths (a partition);
+    // with MIS, PT/NEE keep them with the weights of Section 5.4.
+    EyeParams EP{};
+    EP.seed = p->seed; EP.K = p->max_depth; EP.u_max = p->u_max;
     EP.proxy_on = proxy && !(p->flags & PT_FLAG_ONLY_OTHER);
+    const bool only_cls = (p->flags & PT_FLAG_ONLY_PROXY_CLASS) != 0, only_oth = (p->flags & PT_FLAG_ONLY_OTHER) != 0;
+    if (EP.proxy_on && !mis) EP.filter = only_cls ? 3 : 2;
+    else EP.filter = only_cls ? 1 : (only_oth ? 2 : 0);
     EP.nee_on = (p->flags & PT_FLAG_NEE) != 0;
+    EP.mis_on = mis && EP.proxy_on;
+    EP.labels_on = labels && EP.proxy_on;
+    EP.gamma_on = gamma;
+    EP.mlp_on = mlp && EP.proxy_on;
+    EP.tiles_on = tiles;
+    EP.M = M; EP.cand_cap = p->cand_cap;
+    SubDev D{};
+    if (s->n_eye > 0) {
+        D.eye_c = s->eye_c; D.spec_c = s->spec_c; D.n_eye = ne; D.n_spec = ns;
+        D.s_count = s->s_count; D.s_off = s->s_off; D.s_list = s->s_list; D.nonempty = s->nonempty; D.n_nonempty = s->n_ne;
+        D.al_prob = s->al_prob; D.al_idx = s->al_idx; D.row_sum = s->row_sum; D.gamma = s->gamma_frz;
+        D.defensive = p->defensive; D.rstat = s->rstat_frz;
+        D.tile_proxy = s->tile_proxy; D.tile_total = s->tile_total; D.tile = s->tile; D.tiles_x = s->tiles_x;
+        D.tile_thr = p->tile_threshold; D.tile_low = p->tile_low_prob;
+    }
     const int np = s->npix;
-    k_camera<<<blocks(np, 256), 256, 0, stream>>>(S, E, p->seed, p->iteration, s->cnt);
+    k_camera<<<blocks(np, 256), 256, 0, stream>>>(S, E, p->seed, s->cnt);
     for (int t = 1; t <= p->max_depth; ++t) {
         if (timing) HIPCHK(hipEventRecord(s->ev[2 * (t - 1)], stream));
         if (count)
@@ -329,17 +639,43 @@ extern "C" pt_status pt_render_iteration(pt_scene *s, const pt_iter_params *p, f
             k_extend<false><<<blocks(np, WG), WG, 0, stream>>>(S, E.q[(t - 1) & 1], s->cnt, C_EYE_Q0 + t - 1, E.ro, E.rd,
                                                                E.hit, s->cnt, C_RAYS_EYE);
         if (timing) HIPCHK(hipEventRecord(s->ev[2 * (t - 1) + 1], stream));
-        k_eye_shade<<<blocks(np, 256), 256, 0, stream>>>(S, E, EP, t, s->cnt);
+        k_eye_shade<<<blocks(np, 256), 256, 0, stream>>>(S, E, EP, D, t, s->cnt);
         k_occluded<<<blocks(np, WG), WG, 0, stream>>>(S, E, t, s->cnt);
     }
-    if (EP.proxy_on) {
-        ProxyParams PP;
-        PP.seed = p->seed; PP.iter = p->iteration; PP.K = p->max_depth; PP.M = M; PP.cand_cap = p->cand_cap;
-        PP.repeats = p->recip_repeats;
-        k_proxy<<<blocks(np, WG), WG, 0, stream>>>(S, E, s->cand, s->final_, PP, s->cnt);
+    StatBuf SB{s->gamma_acc, s->tile_proxy, s->tile_total};
+    if (EP.mlp_on) {
+        // the network's logits for every queued first diffuse vertex, then S per item
+        const MlpOff o = mlp_off(s->mlp_nout);
+        k_fill<<<1, 64, 0, stream>>>(s->MT.wsum, 0.0f, 1);
+        k_mlp_enc_items<<<blocks(np, 256), 256, 0, stream>>>(S, E.proxy, s->cnt, s->mx);
+        mlp_forward(s, np, s->cnt, C_PROXYQ, s->ml, stream);
+        k_mlp_select<<<blocks(np, 256), 256, 0, stream>>>(E, D, s->ml, s->mw + o.b4, s->mlp_nout, p->mlp_mix,
+                                                          gamma ? 1 : 0, p->seed, s->cnt);
     }
-    k_accumulate<<<blocks(3L * np, 256), 256, 0, stream>>>(E.frame, acc, acc2, 3 * np, s->cnt);
+    if (EP.proxy_on)
+        k_proxy<<<blocks(np, WG), WG, 0, stream>>>(S, E, s->cand, s->final_, EP, D, SB, s->MT, p->recip_repeats,
+                                                   s->cnt);
+    if (EP.mlp_on) {
+        // online training on this iteration's samples (no work unless the iteration recorded some)
+        k_mlp_enc_feat<<<blocks(MLP_CAP, 256), 256, 0, stream>>>(s->MT.feat, MLP_CAP, s->cnt, C_MLP_N, s->mx);
+        mlp_backward(s, s->MT.label, s->MT.weight, stream);
+        mlp_adam(s, p->mlp_lr, stream);
+    }
+    k_accumulate<<<blocks(np, 256), 256, 0, stream>>>(E.frame, acc, acc2, np, s->W, s->tile, s->tiles_x,
+                                                      tiles ? s->tile_total : nullptr, s->cnt);
     HIPCHK(hipGetLastError());
+    return PT_OK;
+}
+}  // namespace
+
+extern "C" pt_status pt_render_iteration(pt_scene *s, const pt_iter_params *p, float *acc, float *acc2,
+                                         pt_iter_stats *stats, void *stream_)
+{
+    TRY(check_params(s, p, acc));
+    hipStream_t stream = (hipStream_t)stream_;
+    const bool timing = (p->flags & PT_FLAG_TIMING) != 0;
+    if (p->flags & PT_FLAG_MLP) TRY(ensure_mlp(s, stream));
+    TRY(enqueue_iteration(s, p, acc, acc2, stream, false));
     if (stats) {
         unsigned long long c[C_COUNT];
         HIPCHK(hipMemcpyAsync(c, s->cnt, sizeof(c), hipMemcpyDeviceToHost, stream));
@@ -370,6 +706,45 @@ extern "C" pt_status pt_render_iteration(pt_scene *s, const pt_iter_params *p, f
             stats->n_extend_launches = p->max_depth;
         }
     }
+    return PT_OK;
+}
+
+extern "C" pt_status pt_render_batch(pt_scene *s, const pt_iter_params *p, uint32_t n_iter, float *acc, float *acc2,
+                                     void *stream_)
+{
+    TRY(check_params(s, p, acc));
+    if (n_iter == 0) return set_err(PT_EINVAL, "n_iter must be positive");
+    if (p->flags & PT_FLAG_TIMING) return set_err(PT_EINVAL, "PT_FLAG_TIMING cannot be captured");
+    hipStream_t stream = (hipStream_t)stream_;
+    if (p->flags & PT_FLAG_MLP) {
+        TRY(ensure_mlp(s, stream));
+        // the capture stream does not wait on `stream`: finish the initialisation first
+        HIPCHK(hipStreamSynchronize(stream));
+    }
+    // the graph depends on everything but the iteration index
+    pt_iter_params key = *p;
+    key.iteration = 0;
+    std::vector<char> k((const char *)&key, (const char *)&key + sizeof(key));
+    k.insert(k.end(), (const char *)&acc, (const char *)&acc + sizeof(acc));
+    k.insert(k.end(), (const char *)&acc2, (const char *)&acc2 + sizeof(acc2));
+    if (!s->gexec || k != s->gkey) {
+        if (s->gexec) { HIPCHK(hipGraphExecDestroy(s->gexec)); s->gexec = nullptr; }
+        if (!s->cap_stream) HIPCHK(hipStreamCreateWithFlags(&s->cap_stream, hipStreamNonBlocking));
+        hipGraph_t g = nullptr;
+        HIPCHK(hipStreamBeginCapture(s->cap_stream, hipStreamCaptureModeThreadLocal));
+        pt_status st = enqueue_iteration(s, p, acc, acc2, s->cap_stream, true);
+        hipError_t e = hipStreamEndCapture(s->cap_stream, &g);
+        if (st != PT_OK) { if (g) (void)hipGraphDestroy(g); return st; }
+        if (e != hipSuccess) return set_err(PT_EDEVICE, "graph capture failed: %s", hipGetErrorString(e));
+        e = hipGraphInstantiate(&s->gexec, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (e != hipSuccess) { s->gexec = nullptr; return set_err(PT_EDEVICE, "graph instantiation failed: %s", hipGetErrorString(e)); }
+        s->gkey = k;
+    }
+    // the captured iteration advances the device-side index first: start one below
+    k_iter<<<1, 1, 0, stream>>>(s->cnt, p->iteration - 1u, 0, p->train_iters);
+    for (uint32_t i = 0; i < n_iter; ++i) HIPCHK(hipGraphLaunch(s->gexec, stream));
+    HIPCHK(hipGetLastError());
     return PT_OK;
 }
 
@@ -426,5 +801,78 @@ extern "C" pt_status pt_trace_closest(pt_scene *s, const float *rays, int32_t n,
     hipStream_t stream = (hipStream_t)stream_;
     k_trace_closest<<<blocks(n, WG), WG, 0, stream>>>(s->S, rays, n, t, prim);
     HIPCHK(hipGetLastError());
+    return PT_OK;
+}
+
+extern "C" pt_status pt_mlp_param_count(const pt_scene *s, int32_t *count)
+{
+    if (!s || !count) return set_err(PT_EINVAL, "null argument");
+    if (!s->subspaces_ready) return set_err(PT_ESTATE, "pt_build_subspaces must run first");
+    *count = (int32_t)mlp_off(s->n_spec).n;
+    return PT_OK;
+}
+
+extern "C" pt_status pt_mlp_set_params(pt_scene *s, const float *host, int32_t count, void *stream_)
+{
+    if (!s || !host) return set_err(PT_EINVAL, "null argument");
+    hipStream_t st = (hipStream_t)stream_;
+    TRY(ensure_mlp(s, st));
+    if (count != s->mlp_np) return set_err(PT_EINVAL, "parameter count %d, expected %d", count, s->mlp_np);
+    const size_t n = (size_t)count;
+    HIPCHK(hipMemcpyAsync(s->mw, host, n * sizeof(float), hipMemcpyHostToDevice, st));
+    k_to_bf16<<<blocks((long)n, 256), 256, 0, st>>>(s->mw, s->mwb, n);
+    k_fill<<<blocks((long)n, 256), 256, 0, st>>>(s->mg, 0.0f, n);
+    k_fill<<<blocks((long)n, 256), 256, 0, st>>>(s->mm, 0.0f, n);
+    k_fill<<<blocks((long)n, 256), 256, 0, st>>>(s->mv, 0.0f, n);
+    k_set_counter<<<1, 1, 0, st>>>(s->cnt, C_MLP_T, 0ull);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(st));
+    return PT_OK;
+}
+
+extern "C" pt_status pt_mlp_get_params(pt_scene *s, float *host, int32_t count, void *stream_)
+{
+    if (!s || !host) return set_err(PT_EINVAL, "null argument");
+    hipStream_t st = (hipStream_t)stream_;
+    TRY(ensure_mlp(s, st));
+    if (count != s->mlp_np) return set_err(PT_EINVAL, "parameter count %d, expected %d", count, s->mlp_np);
+    HIPCHK(hipMemcpyAsync(host, s->mw, (size_t)count * sizeof(float), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    return PT_OK;
+}
+
+extern "C" pt_status pt_mlp_forward(pt_scene *s, const float *feat, int32_t n, float *logits, void *stream_)
+{
+    if (!s || !feat || !logits) return set_err(PT_EINVAL, "null argument");
+    hipStream_t st = (hipStream_t)stream_;
+    TRY(ensure_mlp(s, st));
+    if (n < 1 || n > s->mlp_rows) return set_err(PT_EINVAL, "n out of range [1, %d]", s->mlp_rows);
+    const MlpOff o = mlp_off(s->mlp_nout);
+    k_mlp_enc_feat<<<blocks(n, 256), 256, 0, st>>>(feat, n, s->cnt, -1, s->mx);
+    mlp_forward(s, n, s->cnt, -1, logits, st);
+    k_add_bias<<<blocks((long)n * s->mlp_nout, 256), 256, 0, st>>>(logits, s->mw + o.b4, n, s->mlp_nout);
+    HIPCHK(hipGetLastError());
+    return PT_OK;
+}
+
+extern "C" pt_status pt_mlp_train_step(pt_scene *s, const float *feat, const int32_t *label, const float *weight,
+                                       int32_t n, float lr, float *grad_host, void *stream_)
+{
+    if (!s || !feat || !label || !weight) return set_err(PT_EINVAL, "null argument");
+    if (n < 1 || n > MLP_CAP) return set_err(PT_EINVAL, "n out of range [1, %d]", MLP_CAP);
+    if (!(lr > 0.0f)) return set_err(PT_EINVAL, "lr must be positive");
+    hipStream_t st = (hipStream_t)stream_;
+    TRY(ensure_mlp(s, st));
+    k_set_counter<<<1, 1, 0, st>>>(s->cnt, C_MLP_N, (unsigned long long)n);
+    k_sum1<<<1, 256, 0, st>>>(weight, n, s->MT.wsum);
+    k_mlp_enc_feat<<<blocks(n, 256), 256, 0, st>>>(feat, n, s->cnt, -1, s->mx);
+    mlp_backward(s, label, weight, st);
+    if (grad_host) {
+        HIPCHK(hipMemcpyAsync(grad_host, s->mg, (size_t)s->mlp_np * sizeof(float), hipMemcpyDeviceToHost, st));
+    }
+    mlp_adam(s, lr, st);
+    k_set_counter<<<1, 1, 0, st>>>(s->cnt, C_MLP_N, 0ull);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(st));
     return PT_OK;
 }

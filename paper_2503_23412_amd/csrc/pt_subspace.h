@@ -1,0 +1,218 @@
+// Subspaces and probabilistic selection (Section 3.2's subspaces, Sections 5.5 and 5.6):
+// k-means over 9-D features (position normalised to the scene box, normal, incident
+// direction), per-iteration bucketing of kept incomplete sub-paths by specular subspace S,
+// Walker/Vose alias rows of the selection matrix Gamma[T, S], and the frozen statistics the
+// MIS weights of Section 5.4 use.
+#pragma once
+#include "pt_device.h"
+
+#define FEAT 12   // 9 features padded to 12 floats (three float4 loads)
+
+struct SubDev {
+    const float *eye_c;      // [n_eye * FEAT] centroids of eye first-diffuse vertices (T)
+    const float *spec_c;     // [n_spec * FEAT] centroids of specular vertices y_{s-1} (S)
+    int n_eye, n_spec;
+    // this iteration's bucketing of the final candidates
+    const int *s_count, *s_off, *s_list, *nonempty;
+    const int *n_nonempty;
+    // alias rows over the non-empty subspaces, and the row normalisers
+    const float *al_prob;    // [n_eye * n_spec]
+    const int *al_idx;       // [n_eye * n_spec]
+    const float *row_sum;    // [n_eye] sum of Gamma over non-empty S (0 = uniform row)
+    const float *gamma;      // [n_eye * n_spec] frozen Gamma of this iteration
+    float defensive;
+    // frozen reciprocal statistics per (class, u, S): sum R, sum R^2, count
+    const float *rstat;      // [10 * n_spec * 3]
+    // tiles
+    const float *tile_proxy, *tile_total;
+    int tile, tiles_x;
+    float tile_thr, tile_low;
+};
+
+__device__ __forceinline__ void feat9(const SceneDev &S, float3 p, float3 n, float3 w, float f[9])
+{
+    f[0] = (p.x - S.lo.x) * S.inv_ext.x; f[1] = (p.y - S.lo.y) * S.inv_ext.y; f[2] = (p.z - S.lo.z) * S.inv_ext.z;
+    f[3] = n.x; f[4] = n.y; f[5] = n.z;
+    f[6] = w.x; f[7] = w.y; f[8] = w.z;
+}
+__device__ __forceinline__ int nearest(const float *__restrict__ cent, int K, const float f[9])
+{
+    int best = 0;
+    float bd = 3.0e38f;
+    for (int k = 0; k < K; ++k) {
+        const float4 a = *(const float4 *)(cent + FEAT * k), b = *(const float4 *)(cent + FEAT * k + 4),
+                     c = *(const float4 *)(cent + FEAT * k + 8);
+        const float d0 = a.x - f[0], d1 = a.y - f[1], d2 = a.z - f[2], d3 = a.w - f[3], d4 = b.x - f[4],
+                    d5 = b.y - f[5], d6 = b.z - f[6], d7 = b.w - f[7], d8 = c.x - f[8];
+        const float d = d0 * d0 + d1 * d1 + d2 * d2 + d3 * d3 + d4 * d4 + d5 * d5 + d6 * d6 + d7 * d7 + d8 * d8;
+        if (d < bd) { bd = d; best = k; }
+    }
+    return best;
+}
+
+// octahedral encoding of a unit vector into two floats
+__device__ __forceinline__ float2 oct_enc(float3 v)
+{
+    const float s = fabsf(v.x) + fabsf(v.y) + fabsf(v.z);
+    float x = v.x / s, y = v.y / s;
+    if (v.z < 0.0f) {
+        const float ox = (1.0f - fabsf(y)) * copysignf(1.0f, x), oy = (1.0f - fabsf(x)) * copysignf(1.0f, y);
+        x = ox; y = oy;
+    }
+    return make_float2(x, y);
+}
+__device__ __forceinline__ float3 oct_dec(float2 e)
+{
+    float3 v = f3(e.x, e.y, 1.0f - fabsf(e.x) - fabsf(e.y));
+    if (v.z < 0.0f) {
+        const float ox = (1.0f - fabsf(v.y)) * copysignf(1.0f, v.x), oy = (1.0f - fabsf(v.x)) * copysignf(1.0f, v.y);
+        v.x = ox; v.y = oy;
+    }
+    return normalize3(v);
+}
+
+// ------------------------------------------------------------------------------ k-means
+__global__ void k_km_init(const float *feat, int n, float *cent, int K)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= K) return;
+    const int src = n > 0 ? (int)(((long)k * n) / K) : -1;
+    for (int j = 0; j < FEAT; ++j) cent[FEAT * k + j] = src >= 0 ? feat[FEAT * (size_t)src + j] : 0.0f;
+}
+__global__ void k_km_assign(const float *feat, int n, const float *cent, int K, float *sums, float *counts)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    float f[9];
+    for (int j = 0; j < 9; ++j) f[j] = feat[FEAT * (size_t)i + j];
+    const int k = nearest(cent, K, f);
+    for (int j = 0; j < 9; ++j) unsafeAtomicAdd(sums + FEAT * k + j, f[j]);
+    unsafeAtomicAdd(counts + k, 1.0f);
+}
+__global__ void k_km_update(float *cent, const float *sums, const float *counts, int K)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= K || counts[k] <= 0.0f) return;
+    for (int j = 0; j < 9; ++j) cent[FEAT * k + j] = sums[FEAT * k + j] / counts[k];
+}
+
+// ------------------------------------------------------------------------------ bucketing
+__global__ void k_label_cands(SceneDev S, SubDev D, Cand *cand, const uint32_t *final_, const unsigned long long *cnt,
+                              int *s_count)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (int)cnt[C_NFINAL]) return;
+    Cand &c = cand[final_[i]];
+    float f[9];
+    feat9(S, xyz(c.v), S.shade[__float_as_int(c.v.w)].n, oct_dec(make_float2(c.pad[0], c.pad[1])), f);
+    const int s = nearest(D.spec_c, D.n_spec, f);
+    c.spec_sub = s;
+    atomicAdd(s_count + s, 1);
+}
+// one workgroup: exclusive scan of the counts and the list of non-empty subspaces
+__global__ void k_scan_sub(const int *s_count, int *s_off, int *s_fill, int *nonempty, int *n_nonempty, int K)
+{
+    __shared__ int part[1024];
+    const int t = threadIdx.x;
+    const int per = (K + blockDim.x - 1) / blockDim.x;
+    int acc = 0;
+    for (int j = t * per; j < min(K, (t + 1) * per); ++j) acc += s_count[j];
+    part[t] = acc;
+    __syncthreads();
+    if (t == 0) {
+        int run = 0, ne = 0;
+        for (int b = 0; b < (int)blockDim.x; ++b) { const int v = part[b]; part[b] = run; run += v; }
+        for (int j = 0; j < K; ++j) if (s_count[j] > 0) nonempty[ne++] = j;
+        *n_nonempty = ne;
+    }
+    __syncthreads();
+    int run = part[t];
+    for (int j = t * per; j < min(K, (t + 1) * per); ++j) { s_off[j] = run; s_fill[j] = run; run += s_count[j]; }
+}
+__global__ void k_scatter_sub(const Cand *cand, const uint32_t *final_, const unsigned long long *cnt, int *s_fill,
+                              int *s_list)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (int)cnt[C_NFINAL]) return;
+    const int s = cand[final_[i]].spec_sub;
+    s_list[atomicAdd(s_fill + s, 1)] = (int)final_[i];
+}
+
+// Gamma row T -> alias table over the non-empty subspaces (Vose's construction, one thread per
+// row, worklists in global scratch). Row probabilities: (1 - defensive) Gamma[T, S] / sum over
+// non-empty S + defensive / n_nonempty, or uniform when the row has no data.
+__global__ void k_alias_rows(const float *gamma, int n_eye, int n_spec, const int *nonempty, const int *n_nonempty,
+                             float defensive, float *al_prob, int *al_idx, float *row_sum, int *scratch)
+{
+    const int T = blockIdx.x * blockDim.x + threadIdx.x;
+    if (T >= n_eye) return;
+    const int ne = *n_nonempty;
+    const float *g = gamma + (size_t)T * n_spec;
+    float rs = 0.0f;
+    for (int j = 0; j < ne; ++j) rs += g[nonempty[j]];
+    row_sum[T] = rs;
+    if (ne == 0) return;
+    float *pr = al_prob + (size_t)T * n_spec;
+    int *ai = al_idx + (size_t)T * n_spec;
+    int *small = scratch + (size_t)T * 2 * n_spec, *large = small + n_spec;
+    int ns = 0, nl = 0;
+    for (int j = 0; j < ne; ++j) {
+        const float p = rs > 0.0f ? (1.0f - defensive) * g[nonempty[j]] / rs + defensive / ne : 1.0f / ne;
+        pr[j] = p * ne;
+        if (pr[j] < 1.0f) small[ns++] = j; else large[nl++] = j;
+    }
+    while (ns > 0 && nl > 0) {
+        const int l = small[--ns], gg = large[--nl];
+        ai[l] = gg;
+        pr[gg] = (pr[gg] + pr[l]) - 1.0f;
+        if (pr[gg] < 1.0f) small[ns++] = gg; else large[nl++] = gg;
+    }
+    while (nl > 0) { const int gg = large[--nl]; pr[gg] = 1.0f; ai[gg] = gg; }
+    while (ns > 0) { const int l = small[--ns]; pr[l] = 1.0f; ai[l] = l; }
+}
+// selection probability of subspace S from eye subspace T (the density the alias row samples)
+__device__ __forceinline__ float sel_prob(const SubDev &D, int T, int S)
+{
+    const int ne = *D.n_nonempty;
+    if (ne == 0 || D.s_count[S] == 0) return 0.0f;
+    const float rs = D.row_sum[T];
+    return rs > 0.0f ? (1.0f - D.defensive) * D.gamma[(size_t)T * D.n_spec + S] / rs + D.defensive / ne : 1.0f / ne;
+}
+
+// reciprocal statistics of the final candidates (accumulated for later iterations)
+__global__ void k_rstat(const Cand *cand, const uint32_t *final_, const unsigned long long *cnt, int repeats, int n_spec,
+                        float *rstat_acc)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (int)cnt[C_NFINAL] || !cnt[C_LEARN]) return;
+    const Cand &c = cand[final_[i]];
+    const float R = c.recip_sum / (float)repeats;
+    const int b = ((c.cls_u >> 8) * 5 + (c.cls_u & 0xFF)) * n_spec + c.spec_sub;
+    unsafeAtomicAdd(rstat_acc + 3 * b + 0, R);
+    unsafeAtomicAdd(rstat_acc + 3 * b + 1, R * R);
+    unsafeAtomicAdd(rstat_acc + 3 * b + 2, 1.0f);
+}
+
+// Surrogate of the proxy strategy's density factor for MIS (Section 5.4, equ:MIS_1 with
+// E[1/p~^2] p = (1 + V_rel) / p): K' P^ / (1 + V_rel), with P^ = 1 / mean R and V_rel =
+// Var R / mean^2 of the (class, u, S) bucket from earlier iterations, K' = M pi_inc c pi_sel.
+__device__ __forceinline__ float proxy_mis_factor(const SubDev &D, int cls, int u, int S, float k_sel)
+{
+    const int b = (cls * 5 + u) * D.n_spec + S;
+    const float n = D.rstat[3 * b + 2];
+    if (!(n > 0.0f) || !(k_sel > 0.0f)) return 0.0f;
+    const float m = D.rstat[3 * b + 0] / n, m2 = D.rstat[3 * b + 1] / n;
+    if (!(m > 0.0f)) return 0.0f;
+    const float vrel = fmaxf(0.0f, m2 / (m * m) - 1.0f);
+    return k_sel / (m * (1.0f + vrel));
+}
+// tile attempt probability c (Section 6.1): 1 when the proxy's share of the tile's contribution
+// (previous iterations) exceeds the threshold or nothing is known yet, else the low probability
+__device__ __forceinline__ float tile_prob(const SubDev &D, int pix, int W)
+{
+    if (D.tile <= 0) return 1.0f;
+    const int t = (pix / W) / D.tile * D.tiles_x + (pix % W) / D.tile;
+    const float tot = D.tile_total[t];
+    if (!(tot > 0.0f)) return 1.0f;
+    return D.tile_proxy[t] > D.tile_thr * tot ? 1.0f : D.tile_low;
+}

@@ -21,11 +21,13 @@ PT_FLAG_TILES = 1 << 5
 PT_FLAG_TIMING = 1 << 6
 PT_FLAG_COUNT = 1 << 7
 PT_FLAG_MIS = 1 << 8
+PT_FLAG_MLP = 1 << 9
 
 PT_EST_ITILDE = 0
 PT_EST_SIGN = 1
 
-EXPORTED = ["pt_scene_upload", "pt_scene_release", "pt_build_subspaces", "pt_render_iteration",
+EXPORTED = ["pt_scene_upload", "pt_scene_release", "pt_build_subspaces", "pt_render_iteration", "pt_render_batch",
+            "pt_mlp_param_count", "pt_mlp_set_params", "pt_mlp_get_params", "pt_mlp_forward", "pt_mlp_train_step",
             "pt_reciprocal_estimate", "pt_resolve_image", "pt_trace_closest", "pt_last_error"]
 
 
@@ -51,6 +53,7 @@ class IterParams(ctypes.Structure):
         ("u_max", ctypes.c_int32), ("pilot", ctypes.c_int32), ("cost_cap", ctypes.c_float),
         ("train_iters", ctypes.c_int32), ("tile", ctypes.c_int32), ("tile_threshold", ctypes.c_float),
         ("tile_low_prob", ctypes.c_float), ("defensive", ctypes.c_float), ("flags", ctypes.c_uint32),
+        ("mlp_lr", ctypes.c_float), ("mlp_mix", ctypes.c_float),
     ]
 
 
@@ -93,12 +96,19 @@ def lib():
         L.pt_scene_release.argtypes = [P]
         L.pt_build_subspaces.argtypes = [P, ctypes.POINTER(SubspaceParams), P]
         L.pt_render_iteration.argtypes = [P, ctypes.POINTER(IterParams), P, P, ctypes.POINTER(IterStats), P]
+        L.pt_render_batch.argtypes = [P, ctypes.POINTER(IterParams), ctypes.c_uint32, P, P, P]
         L.pt_reciprocal_estimate.argtypes = [P, ctypes.POINTER(RecipQuery), P, P, P]
         L.pt_resolve_image.argtypes = [P, P, ctypes.c_uint32, P, P]
         L.pt_trace_closest.argtypes = [P, P, I, P, P, P]
+        L.pt_mlp_param_count.argtypes = [P, ctypes.POINTER(I)]
+        L.pt_mlp_set_params.argtypes = [P, P, I, P]
+        L.pt_mlp_get_params.argtypes = [P, P, I, P]
+        L.pt_mlp_forward.argtypes = [P, P, I, P, P]
+        L.pt_mlp_train_step.argtypes = [P, P, P, P, I, ctypes.c_float, P, P]
         L.pt_last_error.restype = ctypes.c_char_p
-        for name in ("pt_scene_upload", "pt_scene_release", "pt_build_subspaces", "pt_render_iteration",
-                     "pt_reciprocal_estimate", "pt_resolve_image", "pt_trace_closest"):
+        for name in EXPORTED:
+            if name == "pt_last_error":
+                continue
             getattr(L, name).restype = ctypes.c_int32
         _lib = L
     return _lib
@@ -128,7 +138,7 @@ def _ptr(t):
 def default_params(**kw):
     p = dict(iteration=0, seed=0, max_depth=8, n_light=4096, cand_cap=400, recip_repeats=5, u_max=4, pilot=16,
              cost_cap=4096.0, train_iters=40, tile=10, tile_threshold=0.05, tile_low_prob=0.2, defensive=0.1,
-             flags=PT_FLAG_NEE | PT_FLAG_PROXY)
+             flags=PT_FLAG_NEE | PT_FLAG_PROXY, mlp_lr=1e-3, mlp_mix=0.9)
     p.update(kw)
     return p
 
@@ -170,6 +180,12 @@ class Scene:
                                          ctypes.byref(st) if st is not None else None, _stream(stream)))
         return st.as_dict() if st is not None else None
 
+    def render_batch(self, accum, accum_sq, n_iter, stream=None, **params):
+        """n_iter iterations from params['iteration'] on, replaying one captured HIP graph."""
+        p = IterParams(**default_params(**params))
+        _check(lib().pt_render_batch(self.h, ctypes.byref(p), int(n_iter), _ptr(accum), _ptr(accum_sq),
+                                     _stream(stream)))
+
     def resolve(self, accum, n_iter, out, stream=None):
         _check(lib().pt_resolve_image(self.h, _ptr(accum), int(n_iter), _ptr(out), _stream(stream)))
 
@@ -181,6 +197,32 @@ class Scene:
         q = RecipQuery(1, 0, None, None, float(B), int(n_est), 0, int(seed), int(cap), ctypes.pointer(d), int(per),
                        p_out.data_ptr() if p_out is not None else None)
         _check(lib().pt_reciprocal_estimate(self.h, ctypes.byref(q), _ptr(out), _ptr(nsamples), _stream(stream)))
+
+    # learned subspace selection (PT_FLAG_MLP): parameters and the network's two passes
+    def mlp_param_count(self):
+        n = ctypes.c_int32()
+        _check(lib().pt_mlp_param_count(self.h, ctypes.byref(n)))
+        return n.value
+
+    def mlp_set_params(self, params, stream=None):
+        a = np.ascontiguousarray(params, dtype=np.float32)
+        _check(lib().pt_mlp_set_params(self.h, a.ctypes.data, int(a.size), _stream(stream)))
+
+    def mlp_get_params(self, stream=None):
+        a = np.empty(self.mlp_param_count(), dtype=np.float32)
+        _check(lib().pt_mlp_get_params(self.h, a.ctypes.data, int(a.size), _stream(stream)))
+        return a
+
+    def mlp_forward(self, feat, logits, stream=None):
+        """feat: float32 device [n, 9]; logits: float32 device [n, n_spec]."""
+        _check(lib().pt_mlp_forward(self.h, _ptr(feat), int(feat.shape[0]), _ptr(logits), _stream(stream)))
+
+    def mlp_train_step(self, feat, label, weight, lr, want_grad=False, stream=None):
+        """One Adam step on weighted samples (device tensors); returns the gradient when asked."""
+        g = np.empty(self.mlp_param_count(), dtype=np.float32) if want_grad else None
+        _check(lib().pt_mlp_train_step(self.h, _ptr(feat), _ptr(label), _ptr(weight), int(feat.shape[0]), float(lr),
+                                       g.ctypes.data if g is not None else None, _stream(stream)))
+        return g
 
     def trace_closest(self, rays, t_out, prim_out, stream=None):
         _check(lib().pt_trace_closest(self.h, _ptr(rays), int(rays.shape[0]), _ptr(t_out), _ptr(prim_out),

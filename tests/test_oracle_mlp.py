@@ -1,0 +1,151 @@
+"""Pins of the FP64 network oracle (oracle/mlp.py) against facts that do not come from it:
+closed forms of the encoding, the loss and Adam, central finite differences and an independent
+reverse-mode differentiation (torch.autograd in float64 on the CPU)."""
+import numpy as np
+import pytest
+
+from oracle import mlp
+
+N_OUT = 24
+
+
+def _params(rng, n_out=N_OUT, scale=1.0):
+    blocks = {}
+    for name, shape in mlp.layout(n_out):
+        fan = shape[0] if len(shape) == 2 else 1
+        blocks[name] = rng.normal(0.0, scale / np.sqrt(fan), size=shape) if len(shape) == 2 else \
+            rng.normal(0.0, 0.1, size=shape)
+    return mlp.pack(blocks, n_out)
+
+
+def _data(rng, n, n_out=N_OUT):
+    feat = rng.uniform(-1.0, 1.0, size=(n, 9))
+    label = rng.integers(0, n_out, size=n)
+    weight = rng.exponential(1.0, size=n)
+    return feat, label, weight
+
+
+def test_encoding_closed_form():
+    f = np.zeros((3, 9))
+    f[1, :] = 0.5
+    f[2, 4] = 0.25
+    X = mlp.encode(f)
+    assert X.shape == (3, 256)
+    assert np.all(X[:, 225:] == 0.0)
+    # f = 0: raw 0, sin 0, cos 1 in every band
+    row = X[0, :25]
+    assert row[0] == 0.0 and np.all(row[1::2] == 0.0) and np.all(row[2::2] == 1.0)
+    # f = 1/2: band 0 -> (1, 0), band 1 -> (0, -1), bands >= 2 -> (0, 1)
+    row = X[1, 25:50]
+    assert row[0] == 0.5
+    np.testing.assert_allclose(row[1:3], [1.0, 0.0], atol=1e-12)
+    np.testing.assert_allclose(row[3:5], [0.0, -1.0], atol=1e-12)
+    np.testing.assert_allclose(row[5::2], 0.0, atol=1e-9)
+    np.testing.assert_allclose(row[6::2], 1.0, atol=1e-12)
+    # feature 4 at 1/4 occupies columns 100..124: band 0 -> (sqrt(1/2), sqrt(1/2)), band 1 -> (1, 0)
+    row = X[2, 100:125]
+    assert row[0] == 0.25
+    np.testing.assert_allclose(row[1:3], [np.sqrt(0.5), np.sqrt(0.5)], atol=1e-12)
+    np.testing.assert_allclose(row[3:5], [1.0, 0.0], atol=1e-12)
+
+
+def test_parameter_count():
+    assert mlp.count(N_OUT) == 256 * 64 + 64 + 2 * (64 * 64 + 64) + 64 * N_OUT + N_OUT
+
+
+def test_loss_uniform_logits_is_log_n():
+    rng = np.random.default_rng(1)
+    p = mlp.unpack(_params(rng), N_OUT)
+    p = {k: v.copy() for k, v in p.items()}
+    p["W4"][:] = 0.0
+    p["b4"][:] = 0.0
+    feat, label, weight = _data(rng, 17)
+    assert mlp.loss(mlp.pack(p, N_OUT), N_OUT, feat, label, weight) == pytest.approx(np.log(N_OUT), rel=1e-14)
+    # with uniform logits the bias gradient is sum_i w_i (1/N - onehot) / W
+    g = mlp.unpack(mlp.grad(mlp.pack(p, N_OUT), N_OUT, feat, label, weight), N_OUT)
+    expect = np.full(N_OUT, 1.0 / N_OUT)
+    for i in range(17):
+        expect[label[i]] -= weight[i] / weight.sum()
+    np.testing.assert_allclose(g["b4"], expect, atol=1e-14)
+
+
+def test_known_linear_network():
+    """A network that passes one input straight through: logits depend on f_0 as written."""
+    blocks = {name: np.zeros(shape) for name, shape in mlp.layout(3)}
+    blocks["W1"][0, 0] = 1.0        # h1_0 = relu(f_0)
+    blocks["W2"][0, 0] = 2.0        # h2_0 = 2 relu(f_0)
+    blocks["W3"][0, 0] = 1.0
+    blocks["W4"][0, :] = [1.0, -1.0, 0.0]
+    blocks["b4"][:] = [0.0, 0.0, 0.5]
+    f = np.zeros((2, 9))
+    f[0, 0] = 0.75
+    f[1, 0] = -0.75
+    L, _ = mlp.forward(mlp.pack(blocks, 3), 3, f)
+    np.testing.assert_allclose(L, [[1.5, -1.5, 0.5], [0.0, 0.0, 0.5]], atol=1e-15)
+
+
+def test_gradient_by_finite_differences():
+    rng = np.random.default_rng(2)
+    params = _params(rng)
+    feat, label, weight = _data(rng, 9)
+    g = mlp.grad(params, N_OUT, feat, label, weight)
+    eps = 1e-6
+    for _ in range(6):
+        d = rng.normal(size=params.size)
+        d /= np.linalg.norm(d)
+        fd = (mlp.loss(params + eps * d, N_OUT, feat, label, weight) -
+              mlp.loss(params - eps * d, N_OUT, feat, label, weight)) / (2 * eps)
+        assert fd == pytest.approx(float(g @ d), rel=1e-6, abs=1e-12)
+    # single coordinates of every block
+    off = 0
+    for name, shape in mlp.layout(N_OUT):
+        k = int(np.prod(shape))
+        idx = off + int(rng.integers(0, k if name != "W1" else 225 * 64))
+        e = np.zeros(params.size)
+        e[idx] = 1.0
+        fd = (mlp.loss(params + eps * e, N_OUT, feat, label, weight) -
+              mlp.loss(params - eps * e, N_OUT, feat, label, weight)) / (2 * eps)
+        assert fd == pytest.approx(float(g[idx]), rel=1e-5, abs=1e-10), name
+        off += k
+
+
+def test_gradient_against_autograd():
+    torch = pytest.importorskip("torch")
+    rng = np.random.default_rng(3)
+    params = _params(rng)
+    feat, label, weight = _data(rng, 31)
+    g = mlp.grad(params, N_OUT, feat, label, weight)
+    blocks = {k: torch.tensor(v, dtype=torch.float64, requires_grad=True) for k, v in mlp.unpack(params, N_OUT).items()}
+    # the encoding written independently with torch ops
+    f = torch.tensor(feat, dtype=torch.float64)
+    cols = []
+    for j in range(9):
+        cols.append(f[:, j:j + 1])
+        for b in range(12):
+            a = f[:, j:j + 1] * (np.pi * 2.0 ** b)
+            cols += [torch.sin(a), torch.cos(a)]
+    X = torch.cat(cols + [torch.zeros(f.shape[0], 31, dtype=torch.float64)], dim=1)
+    h = X
+    for l in (1, 2, 3):
+        h = torch.relu(h @ blocks[f"W{l}"] + blocks[f"b{l}"])
+    logits = h @ blocks["W4"] + blocks["b4"]
+    w = torch.tensor(weight, dtype=torch.float64)
+    ce = torch.nn.functional.cross_entropy(logits, torch.tensor(label), reduction="none")
+    ((w * ce).sum() / w.sum()).backward()
+    ref = np.concatenate([blocks[name].grad.numpy().ravel() for name, _ in mlp.layout(N_OUT)])
+    np.testing.assert_allclose(g, ref, rtol=1e-10, atol=1e-14)
+
+
+def test_adam_closed_form():
+    # with a constant gradient g the bias-corrected moments are g and g^2 at every step, so each
+    # step moves w by -lr g / (|g| + eps)
+    rng = np.random.default_rng(4)
+    w0 = rng.normal(size=50)
+    g = rng.normal(size=50)
+    w, m, v = w0.copy(), np.zeros(50), np.zeros(50)
+    for t in range(1, 6):
+        w, m, v = mlp.adam_step(w, g, m, v, t, lr=1e-3)
+        np.testing.assert_allclose(w, w0 - t * 1e-3 * g / (np.abs(g) + 1e-8), rtol=0, atol=1e-12)
+    # first step with zero gradient leaves w unchanged
+    w1, _, _ = mlp.adam_step(w0, np.zeros(50), np.zeros(50), np.zeros(50), 1, lr=1e-3)
+    np.testing.assert_array_equal(w1, w0)
