@@ -99,6 +99,9 @@ enum {
     PT_FLAG_TIMING = 1u << 6,       /* time the extension kernels with HIP events into the stats */
     PT_FLAG_COUNT = 1u << 7,        /* count BVH node visits and triangle tests of extension rays */
     PT_FLAG_MIS = 1u << 8,          /* variance-aware MIS for proxy paths (Section 5.4) */
+    PT_FLAG_SPC = 1u << 10,         /* probabilistic connections: each eye vertex to one light vertex
+                                       drawn from the pool of all light sub-path vertices (max_depth <= 16) */
+    PT_FLAG_LT = 1u << 11,          /* light tracing: every pool vertex splats onto the image (max_depth <= 16) */
     PT_FLAG_MLP = 1u << 9           /* learned subspace selection: mlp_mix x network softmax +
                                        (1 - mlp_mix) x the plain row (Gamma row with PT_FLAG_GAMMA,
                                        else uniform over the non-empty subspaces); trained online
@@ -134,6 +137,9 @@ typedef struct {
     double node_visits, tri_tests;   /* eye extension rays, when PT_FLAG_COUNT is set */
     double ms_extend;                /* summed duration of the extension launches (PT_FLAG_TIMING) */
     double n_extend_launches;
+    double n_pool, n_connections, n_lt_splats;   /* light vertices in the pool; connections and splats made */
+    double chain_len_hist[24];       /* reciprocal chains by samples used: bin b counts [2^b, 2^(b+1)) */
+    double chain_len_max;            /* longest chain of the iteration (samples) */
 } pt_iter_stats;
 
 /* One iteration: 1 sample per pixel of every estimator strategy, added into the CALLER-OWNED

@@ -94,12 +94,19 @@ __global__ void __launch_bounds__(WG) k_extend(SceneDev S, const uint32_t *__res
 // ---------------------------------------------------------------------------------- light pass
 struct LightBuf {
     float4 *ro, *rd, *hit;
-    float4 *lv;          // [PT_LMAX * M]: position, w = triangle
+    float4 *lv;          // [PT_LSTORE * M]: position, w = triangle
+    float4 *lt;          // [PT_LSTORE * M]: throughput arriving at the vertex (rgb), w = its forward
+                         // area density (the light tracer's density of this vertex given the previous)
+    float *lphi;         // [PT_LSTORE * M]: MIS partial sum of the strategies with fewer light vertices
+    uint8_t *lfl;        // [PT_LSTORE * M]: LV_S, LV_DIRAC
+    float4 *lbeta;       // [M]: throughput and solid-angle pdf of the ray in flight
     float2 *lb0;         // [M]: barycentrics of y_0
-    uint32_t *sig;       // [M]: bits 0..5 = vertex i specular, bits 8..11 = vertex count
+    uint32_t *sig;       // [M]: bits 0..15 = vertex i specular, bits 24..28 = vertex count
     uint32_t *q[2];
+    uint32_t *pool;      // [PT_LSTORE * M]: vertices eye vertices may connect to (index i * M + path)
     int M;
 };
+__device__ __forceinline__ int sig_count(uint32_t sg) { return (int)((sg >> 24) & 0x1Fu); }
 
 __global__ void k_light_gen(SceneDev S, LightBuf L, uint32_t seed, unsigned long long *cnt)
 {
@@ -112,14 +119,20 @@ __global__ void k_light_gen(SceneDev S, LightBuf L, uint32_t seed, unsigned long
     const LPoint y0 = sample_emitter(S, u0, u1, u2);
     const float3 w = cos_hemi(y0.n, rng_f(r), rng_f(r));
     L.lv[l] = make_float4(y0.p.x, y0.p.y, y0.p.z, ibits(y0.tri));
+    L.lt[l] = make_float4(0.f, 0.f, 0.f, 1.0f / S.em_area);
+    L.lfl[l] = 0;
     L.lb0[l] = make_float2(y0.b1, y0.b2);
-    L.sig[l] = 1u << 8;
+    L.sig[l] = 1u << 24;
+    // cosine emission: L_e cos / (p_A p_w) = L_e A pi
+    const float3 le = emission(S, y0.tri, y0.b1, y0.b2, w) * (S.em_area * PT_PI);
+    L.lbeta[l] = make_float4(le.x, le.y, le.z, fmaxf(dot3(y0.n, w), 0.0f) / PT_PI);
     L.ro[l] = make_float4(y0.p.x, y0.p.y, y0.p.z, ibits(y0.tri));
     L.rd[l] = make_float4(w.x, w.y, w.z, 3.0e38f);
     L.q[0][l] = (uint32_t)l;
 }
 
-// vertex `vi` of every queued light path: store it and sample the adjoint BSDF for the next
+// vertex `vi` of every queued light path: store it (position, arriving throughput, forward
+// area density, flags) and sample the adjoint BSDF for the next
 __global__ void k_light_shade(SceneDev S, LightBuf L, uint32_t seed, int vi, int lmax, unsigned long long *cnt)
 {
     const uint32_t iter = iter_of(cnt);
@@ -138,16 +151,22 @@ __global__ void k_light_shade(SceneDev S, LightBuf L, uint32_t seed, int vi, int
             const float3 x = xyz(o) + xyz(d) * h.x;
             const TriShade &sh = S.shade[tri];
             const MatDev &m = S.mats[sh.mat];
-            L.lv[vi * L.M + pid] = make_float4(x.x, x.y, x.z, ibits(tri));
+            const float4 bt = L.lbeta[pid];
+            const size_t v = (size_t)vi * L.M + pid;
+            L.lv[v] = make_float4(x.x, x.y, x.z, ibits(tri));
+            L.lt[v] = make_float4(bt.x, bt.y, bt.z, bt.w * fabsf(dot3(sh.n, xyz(d))) / (h.x * h.x));
+            L.lfl[v] = (uint8_t)(((m.flags & MF_SPEC) ? LV_S : 0) | ((m.flags & MF_DELTA) ? LV_DIRAC : 0));
             uint32_t sg = L.sig[pid];
             if (m.flags & MF_SPEC) sg |= 1u << vi;
-            sg = (sg & 0xFFu) | ((uint32_t)(vi + 1) << 8);
+            sg = (sg & 0xFFFFu) | ((uint32_t)(vi + 1) << 24);
             L.sig[pid] = sg;
             if (vi + 1 < lmax) {
                 Rng r = rng_make(seed, S_LIGHT, (uint32_t)pid, iter, (uint32_t)vi);
                 const float a = rng_f(r), b = rng_f(r), c = rng_f(r);
                 const BS bs = bsdf_sample(m, sh.n, -xyz(d), a, b, c, false);
                 if (bs.ok) {
+                    const float3 nb = xyz(bt) * bs.w;
+                    L.lbeta[pid] = make_float4(nb.x, nb.y, nb.z, bs.pdf);
                     L.ro[pid] = make_float4(x.x, x.y, x.z, ibits(tri));
                     L.rd[pid] = make_float4(bs.wi.x, bs.wi.y, bs.wi.z, 3.0e38f);
                     cont = true;
@@ -157,6 +176,117 @@ __global__ void k_light_shade(SceneDev S, LightBuf L, uint32_t seed, int vi, int
     }
     const int slot = wave_push(cnt + C_LIGHT_Q0 + vi, cont);
     if (cont) qout[slot] = (uint32_t)pid;
+}
+
+// proxy-class state machine over eye vertices (emitters count as D): phase 0 before the first
+// diffuse vertex z_d; 1 at/after z_d with only specular vertices since (u of them); 2 after
+// S^u then one diffuse vertex; 3 never a proxy path
+__device__ __forceinline__ void pstate_push(uint32_t &ph, uint32_t &u, bool spec, int umax)
+{
+    if (ph == 0) { if (!spec) { ph = 1; u = 0; } }
+    else if (ph == 1) {
+        if (spec) { if (++u > (uint32_t)umax) ph = 3; }
+        else ph = u >= 1 ? 2 : 3;
+    } else if (ph == 2) ph = 3;
+}
+__device__ __forceinline__ bool class_ok(int filter, bool proxy_class)
+{
+    return filter == 0 || (filter == 1 && proxy_class) || (filter == 2 && !proxy_class);
+}
+
+// ---------------------------------------------------------------------------------- connections
+// Light-vertex connections (Section 3.2's probabilistic connections): every non-Dirac light
+// vertex y_i, i >= 1, of this iteration's M light sub-paths enters one pool; an eye vertex picks
+// one of them uniformly (probability 1/N) and the contribution is divided by M / N. Light
+// tracing splats every pool vertex onto the image.
+//
+// MIS: balance heuristic over every strategy that builds the path. With light vertices
+// x_0..x_{s-1} and eye vertices x_s..x_k (x_k the camera), strategy s has density
+//   P_s = prod_{i<s} fwd_i * prod_{i>=s} rev_i * K_s,
+// fwd_i / rev_i the area densities of x_i from the light / eye side, and K_0 = 1 (emission hit),
+// K_1 = 1 (next-event estimation), K_s = kappa for a connection (2 <= s <= k-1; kappa = M
+// sigma, sigma the selection probability), K_k = M (light tracing); K_s = 0 when x_{s-1} or x_s
+// is Dirac or the strategy is off. Then w_s = K_s / (K_s + A_s + C_s) with
+//   A_s = sum_{s'<s} K_s' prod_{i=s'}^{s-1} rev_i / fwd_i   (recursion A_{s+1} = (A_s + K_s) rev_s / fwd_s)
+//   C_s = sum_{s'>s} K_s' prod_{i=s}^{s'-1} fwd_i / rev_i   (recursion C_s = fwd_s / rev_s (K_{s+1} + C_{s+1})).
+// Every factor that does not depend on the other sub-path is accumulated while tracing: the
+// light side stores phi_j = (A_{j-1} + K_{j-1}) |cos_{j-1}| / (d_{j-1,j}^2 fwd_{j-1}), so that
+// A_j = phi_j rev-pdf(y_j) once the direction leaving y_j is known; the eye side carries the
+// analogous quantity along the path. The weights use kappa from the previous iteration's pool
+// size (any value the strategies share keeps the weights summing to one; one that does not
+// depend on this iteration's light paths keeps them independent of the sample they weigh).
+// Paths of the proxy class get their weights from the proxy combination and none from these
+// connections when the proxy strategy is on.
+
+__global__ void k_pool(LightBuf L, int lmax, unsigned long long *cnt)
+{
+    const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = 1 + (int)(idx / L.M), pid = (int)(idx % L.M);
+    bool in = false;
+    if (j < lmax) {
+        const uint32_t v = (uint32_t)j * (uint32_t)L.M + (uint32_t)pid;
+        in = j < sig_count(L.sig[pid]) && !(L.lfl[v] & LV_DIRAC);
+    }
+    const int slot = wave_push(cnt + C_POOL, in);
+    if (in) L.pool[slot] = (uint32_t)j * (uint32_t)L.M + (uint32_t)pid;
+}
+
+// reverse density (solid angle) at a vertex of direction `wi` given the direction `wo` toward
+// the other neighbour; a Dirac vertex gives its lobe probability
+__device__ __forceinline__ float rev_pdf(const MatDev &m, float3 n, float3 wo, float3 wi)
+{
+    return (m.flags & MF_DELTA) ? dirac_prob(m, n, wo, wi) : bsdf_pdf(m, n, wo, wi);
+}
+
+struct MisK {
+    float kN, kS, kL;   // next-event estimation, connection (kappa), light tracing (M)
+};
+
+// one thread per light path: phi_j for j = 1 .. count - 1
+__global__ void k_light_phi(SceneDev S, LightBuf L, MisK K, const float *kappa, unsigned long long *cnt)
+{
+    const int pid = blockIdx.x * blockDim.x + threadIdx.x;
+    if (pid >= L.M) return;
+    const int nv = sig_count(L.sig[pid]);
+    if (nv < 2) return;
+    const float kS = K.kS * *kappa;
+    float3 yp = xyz(L.lv[pid]);
+    float3 y = xyz(L.lv[(size_t)L.M + pid]);
+    {
+        const float3 d = y - yp;
+        const float d2 = dot3(d, d);
+        const float c0 = fabsf(dot3(S.shade[fbits(L.lv[pid].w)].n, d)) * rsqrtf(d2);
+        L.lphi[(size_t)L.M + pid] = c0 / d2 * S.em_area;   // (A_0 + K_0) g_0 / fwd_0, fwd_0 = 1 / A
+    }
+    float phi = L.lphi[(size_t)L.M + pid];
+    for (int j = 2; j < nv; ++j) {
+        const size_t v1 = (size_t)(j - 1) * L.M + pid;
+        const float4 a = L.lv[v1], b = L.lv[(size_t)j * L.M + pid];
+        const int t1 = fbits(a.w);
+        const float3 n1 = S.shade[t1].n;
+        const MatDev m1 = S.mats[S.shade[t1].mat];
+        const float3 toj = xyz(b) - y;
+        const float d2 = dot3(toj, toj);
+        const float3 wj = toj * rsqrtf(d2);
+        const float3 wp = normalize3(yp - y);
+        const float rho = rev_pdf(m1, n1, wj, wp);
+        const bool dirac1 = (L.lfl[v1] & LV_DIRAC) != 0;
+        const bool dirac0 = j - 2 >= 1 ? (L.lfl[(size_t)(j - 2) * L.M + pid] & LV_DIRAC) != 0 : false;
+        const float Kp = dirac1 ? 0.0f : (j - 1 == 1 ? K.kN : (dirac0 ? 0.0f : kS));
+        const float fwd = L.lt[v1].w;
+        phi = fwd > 0.0f ? (phi * rho + Kp) * fabsf(dot3(n1, wj)) / (d2 * fwd) : 0.0f;
+        L.lphi[(size_t)j * L.M + pid] = phi;
+        yp = y;
+        y = xyz(b);
+    }
+}
+
+// eye-side state machine over a connected light sub-path y_j .. y_1 (then the emitter, a D
+// vertex): is the full path in the proxy class?
+__device__ __forceinline__ bool light_tail_class(uint32_t ph, uint32_t uu, uint32_t sg, int j, int umax)
+{
+    for (int i = j; i >= 1; --i) pstate_push(ph, uu, (sg >> i) & 1u, umax);
+    return (ph == 1 && uu >= 1) || ph == 2;
 }
 
 // ---------------------------------------------------------------------------------- candidates
@@ -170,7 +300,7 @@ __global__ void k_candidates(LightBuf L, int u_max, Cand *cand, unsigned long lo
     uint32_t sg = 0;
     if (l < L.M) {
         sg = L.sig[l];
-        const int nv = (int)(sg >> 8) & 0xF;
+        const int nv = min(sig_count(sg), PT_LMAX);
         if (nv >= 2) {
             cls = (sg & 2u) ? 0 : 1;
             first = cls == 0 ? 1 : 2;
@@ -471,16 +601,101 @@ __global__ void k_roulette(Cand *cand, const uint32_t *kept, uint32_t *final_, c
     if (keep) final_[slot] = ci;
 }
 
-// One estimate I~ per wavefront (Section 4.2 with r = |g|). Pending nodes of the splitting tree
+// One estimate I~ per chain (Section 4.2 with r = |g|). Pending nodes of the splitting tree
 // are kept as two counters by the sign of their prefix product: a node of sign s adds s g / B
 // and spawns floor(|g|) (+1 with probability |g| - floor|g|) children of sign s sgn(g).
 // Chain roulette (reading R12c): when the chain has used n1, 2 n1, 4 n1, ... samples it goes on
 // with probability 1/2 and its estimate is doubled, otherwise its estimate is 0; the flip times
 // depend on the sample count only and the flips are independent, so the expectation is kept and
-// the expected cost stays O(n1 log) however small beta is. `cap` is a hard safety bound.
+// the expected cost stays O(n1 log) however small beta is.
+//
+// Samples are i.i.d. (sample k of a chain is Philox counter k of its stream), so they can be
+// drawn ahead of need and by any lanes: stage A runs one wavefront per chain, 64 samples per
+// step, up to a budget; the chains still running then continue in rounds in which the whole
+// GPU draws a block of samples for every remaining chain (k_chain_gen) and one wavefront per
+// chain consumes its block in order (k_chain_consume). While a chain holds exactly one positive
+// pending node and g is in [0, 1] (f/q <= B, the usual case) each sample either continues the
+// chain or ends it, so a ballot finds the next event among 64 samples at once.
+struct ChainState {
+    uint32_t ci, chain;        // candidate index; chain id = ci * 8 + repeat
+    double ans;                // 1 + sum of s g so far (the estimate is ans weight / B)
+    float weight, mx;          // roulette weight; largest f/q drawn (bucket statistics)
+    uint32_t pos, neg, ns, next_flip, coin, pad;
+};
+struct ChainRun {
+    double ans;
+    float weight;
+    uint32_t pos, neg, ns, next_flip, coin;
+    bool alive;
+};
+#define CHAIN_COIN 0x80000000u   // Philox counters of the roulette coins
+#define CHAIN_LONG 0x00100000u   // Philox counters of the samples drawn in rounds
+#define CHAIN_ROUNDS 10
+#define CHAIN_BUF (1u << 24)     // samples per round over all chains
+#define CHAIN_LIST_CAP (CHAIN_BUF / 64)   // running chains carried between rounds
+
+__device__ __forceinline__ float chain_coin(uint32_t seed, uint32_t chain, uint32_t iter, uint32_t k)
+{
+    Rng r = rng_make(seed, S_RECIP, chain, iter, CHAIN_COIN + k);
+    return rng_f(r);
+}
+
+// consume lanes 0 .. nv-1 of (fq, u) in lane order; wave-uniform state
+__device__ __forceinline__ void chain_consume(float fq, float u, int nv, float invB, ChainRun &st, uint32_t seed,
+                                              uint32_t chain, uint32_t iter)
+{
+    const int lane = __lane_id();
+    const float g = 1.0f - fq * invB;
+    const float ag = fabsf(g), fl = floorf(ag);
+    const uint32_t kids = (uint32_t)fminf(fl, 1.0e6f) + (u < ag - fl ? 1u : 0u);
+    int l = 0;
+    while (l < nv && st.alive && st.pos + st.neg > 0) {
+        if (st.pos == 1 && st.neg == 0) {
+            // lanes before the first event continue the chain by one positive node each
+            const bool ev = lane >= l && lane < nv &&
+                            (kids == 0u || g < 0.0f || st.ns + (uint32_t)(lane - l) == st.next_flip);
+            const unsigned long long m = __ballot(ev);
+            const int e = m ? (__ffsll((long long)m) - 1) : nv;
+            float sum = (lane >= l && lane < e) ? g : 0.0f;
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) sum += __shfl_xor(sum, off);
+            st.ans += (double)sum;
+            st.ns += (uint32_t)(e - l);
+            l = e;
+            if (l >= nv) break;
+        }
+        // one sample through the general rule
+        if (st.ns == st.next_flip) {
+            if (chain_coin(seed, chain, iter, st.coin++) < 0.5f) st.weight *= 2.0f;
+            else { st.alive = false; break; }
+            st.next_flip *= 2u;
+        }
+        const float gl = __shfl(g, l);
+        const uint32_t kl = (uint32_t)__shfl((int)kids, l);
+        bool positive = st.pos > 0;
+        if (positive) st.pos--; else st.neg--;
+        st.ns++;
+        st.ans += positive ? (double)gl : -(double)gl;
+        if (positive == (gl >= 0.0f)) st.pos += kl; else st.neg += kl;
+        ++l;
+    }
+}
+
+__device__ __forceinline__ void chain_finish(Cand &c, const ChainRun &st, bool trunc, float mx, float *runmax,
+                                             unsigned long long *cnt)
+{
+    // lane 0 of the chain's wavefront
+    atomicAdd(cnt + C_CHAIN_HIST + min(23, 31 - __clz((int)max(st.ns, 1u))), 1ull);
+    atomicMax(cnt + C_CHAIN_MAX, (unsigned long long)st.ns);
+    const float est = (st.alive || trunc) ? (float)(st.ans * (double)st.weight / (double)c.B) : 0.0f;
+    unsafeAtomicAdd(&c.recip_sum, est);
+    atomic_maxf(runmax + (c.cls_u >> 8) * 5 + (c.cls_u & 0xFF), mx);
+}
+
+// stage A: one wavefront per chain, at most `budget` samples, then hand over to the rounds
 __global__ void __launch_bounds__(64 * RW) k_recip(SceneDev S, Cand *cand, const uint32_t *final_, int repeats,
-                                                   uint32_t seed, uint32_t n1, uint32_t cap, float *runmax,
-                                                   unsigned long long *cnt)
+                                                   uint32_t seed, uint32_t n1, uint32_t budget, float *runmax,
+                                                   ChainState *longq, unsigned long long *cnt)
 {
     const uint32_t iter = iter_of(cnt);
     __shared__ int stk[PT_STACK * 64 * RW];
@@ -488,52 +703,119 @@ __global__ void __launch_bounds__(64 * RW) k_recip(SceneDev S, Cand *cand, const
     const int lane = threadIdx.x & 63;
     const int n = (int)cnt[C_NFINAL] * repeats;
     Ctx C{S, stk + threadIdx.x, 0u, (int)blockDim.x};
-    uint32_t ns = 0, trunc = 0;
+    uint32_t ns = 0;
     if (wave < n) {   // wave-uniform
         const uint32_t ci = final_[wave / repeats];
         const uint32_t chain = ci * 8u + (uint32_t)(wave % repeats);
         Cand &c = cand[ci];
-        const float B = c.B, invB = 1.0f / B;
-        float ans = invB, mx = 0.0f, weight = 1.0f;
-        uint32_t pos = 1, neg = 0, next_flip = n1;
-        Rng rf = rng_make(seed, S_RECIP, chain, iter, 0xFFFFFFFFu);   // roulette coins
-        bool alive = true;
-        for (int step = 0; alive && pos + neg > 0; ++step) {
-            if (ns >= cap) { trunc = 1; break; }
+        const float invB = 1.0f / c.B;
+        ChainRun st{1.0, 1.0f, 1u, 0u, 0u, n1, 0u, true};
+        float mx = 0.0f;
+        for (int step = 0; st.alive && st.pos + st.neg > 0 && st.ns < budget; ++step) {
             Rng r = rng_make(seed, S_RECIP, chain, iter, (uint32_t)(step * 64 + lane));
             const float fq = fq_sample(C, c, r);
             const float u = rng_f(r);
             mx = fmaxf(mx, fq);
-            for (int l = 0; l < 64; ++l) {
-                if (pos + neg == 0) break;
-                if (ns == next_flip) {
-                    if (rng_f(rf) < 0.5f) weight *= 2.0f;
-                    else { alive = false; break; }
-                    next_flip *= 2u;
-                }
-                const float g = 1.0f - lane_get(fq, l) * invB;
-                const float ul = lane_get(u, l);
-                float sgn = 1.0f;
-                if (pos > 0) pos--; else { neg--; sgn = -1.0f; }
-                ns++;
-                ans += sgn * g * invB;
-                const float ag = fabsf(g), fl = floorf(ag);
-                const uint32_t kids = (uint32_t)fminf(fl, 1.0e6f) + (ul < ag - fl ? 1u : 0u);
-                if ((sgn > 0.0f) == (g >= 0.0f)) pos += kids; else neg += kids;
-            }
+            chain_consume(fq, u, 64, invB, st, seed, chain, iter);
         }
-        float wmx = mx;
 #pragma unroll
-        for (int off = 32; off > 0; off >>= 1) wmx = fmaxf(wmx, __shfl_xor(wmx, off));
+        for (int off = 32; off > 0; off >>= 1) mx = fmaxf(mx, __shfl_xor(mx, off));
+        ns = st.ns;
         if (lane == 0) {
-            const float est = (alive && !trunc) ? ans * weight : (trunc ? ans * weight : 0.0f);
-            unsafeAtomicAdd(&c.recip_sum, est);
-            atomic_maxf(runmax + (c.cls_u >> 8) * 5 + (c.cls_u & 0xFF), wmx);
+            const bool running = st.alive && st.pos + st.neg > 0;
+            int slot = -1;
+            if (running) {
+                slot = (int)atomicAdd(cnt + C_LONGQ0, 1ull);
+                if (slot >= CHAIN_LIST_CAP) slot = -1;
+            }
+            if (slot >= 0) {
+                ChainState q{ci, chain, st.ans, st.weight, mx, st.pos, st.neg, st.ns, st.next_flip, st.coin, 0u};
+                longq[slot] = q;
+            } else {
+                if (running) atomicAdd(cnt + C_RECIP_TRUNC, 1ull);
+                chain_finish(c, st, running, mx, runmax, cnt);
+            }
         }
     }
     wave_count(cnt + C_RECIP_SAMPLES, lane == 0 ? ns : 0u);
-    wave_count(cnt + C_RECIP_TRUNC, lane == 0 ? trunc : 0u);
     wave_count(cnt + C_RAYS_RECIP, C.rays);
+}
+
+// samples per chain in round r for n running chains: doubling from 4096, within the buffer
+__device__ __forceinline__ uint32_t chain_round_size(uint32_t n, int round)
+{
+    const uint32_t gmax = 4096u << round;
+    const uint32_t fit = (CHAIN_BUF / max(n, 1u)) & ~63u;
+    return max(64u, min(gmax, fit));
+}
+
+// round r, part 1: every lane of the grid draws samples for the running chains
+__global__ void __launch_bounds__(WG) k_chain_gen(SceneDev S, const Cand *__restrict__ cand,
+                                                  const ChainState *__restrict__ list, int cidx, int round,
+                                                  uint32_t seed, float2 *buf, unsigned long long *cnt)
+{
+    __shared__ int stk[PT_STACK * WG];
+    const uint32_t iter = iter_of(cnt);
+    const uint32_t n = (uint32_t)min(cnt[cidx], (unsigned long long)CHAIN_LIST_CAP);
+    Ctx C{S, stk + threadIdx.x, 0u, WG};
+    if (n > 0) {
+        const uint32_t G = chain_round_size(n, round);
+        const uint64_t total = (uint64_t)n * G;
+        for (uint64_t idx = (uint64_t)blockIdx.x * WG + threadIdx.x; idx < total; idx += (uint64_t)gridDim.x * WG) {
+            const uint32_t slot = (uint32_t)(idx / G), j = (uint32_t)(idx % G);
+            const ChainState &q = list[slot];
+            Rng r = rng_make(seed, S_RECIP, q.chain, iter, CHAIN_LONG + ((uint32_t)round << 21) + j);
+            const float fq = fq_sample(C, cand[q.ci], r);
+            buf[idx] = make_float2(fq, rng_f(r));
+        }
+    }
+    wave_count(cnt + C_RAYS_RECIP, C.rays);
+}
+
+// round r, part 2: one wavefront per running chain consumes its block in order; chains that
+// still run move to the other list (or, after the last round, end as truncated)
+__global__ void __launch_bounds__(64 * RW) k_chain_consume(Cand *cand, const ChainState *__restrict__ list, int cidx,
+                                                           ChainState *next, int cidx_next, int round, int last,
+                                                           uint32_t seed, const float2 *__restrict__ buf,
+                                                           float *runmax, unsigned long long *cnt)
+{
+    const uint32_t iter = iter_of(cnt);
+    const int lane = threadIdx.x & 63;
+    const uint32_t n = (uint32_t)min(cnt[cidx], (unsigned long long)CHAIN_LIST_CAP);
+    uint32_t used = 0;
+    for (uint32_t wave = blockIdx.x * RW + (threadIdx.x >> 6); wave < n; wave += gridDim.x * RW) {   // wave-uniform
+        const ChainState q = list[wave];
+        Cand &c = cand[q.ci];
+        const float invB = 1.0f / c.B;
+        ChainRun st{q.ans, q.weight, q.pos, q.neg, q.ns, q.next_flip, q.coin, true};
+        const uint32_t G = chain_round_size(n, round);
+        const float2 *b = buf + (size_t)wave * G;
+        float mx = q.mx;
+        for (uint32_t base = 0; base < G && st.alive && st.pos + st.neg > 0; base += 64) {
+            const float2 v = b[base + lane];
+            mx = fmaxf(mx, v.x);
+            chain_consume(v.x, v.y, 64, invB, st, seed, q.chain, iter);
+        }
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) mx = fmaxf(mx, __shfl_xor(mx, off));
+        used += st.ns - q.ns;
+        if (lane == 0) {
+            const bool running = st.alive && st.pos + st.neg > 0;
+            int slot = -1;
+            if (running && !last) {
+                slot = (int)atomicAdd(cnt + cidx_next, 1ull);
+                if (slot >= CHAIN_LIST_CAP) slot = -1;
+            }
+            if (slot >= 0) {
+                ChainState o{q.ci, q.chain, st.ans, st.weight, mx, st.pos, st.neg, st.ns, st.next_flip, st.coin, 0u};
+                next[slot] = o;
+            } else {
+                if (running) atomicAdd(cnt + C_RECIP_TRUNC, 1ull);
+                chain_finish(c, st, running, mx, runmax, cnt);
+            }
+        }
+    }
+    wave_count(cnt + C_RECIP_SAMPLES, lane == 0 ? used : 0u);
 }
 
 // Candidate probe: one wavefront per estimate; `per` samples of f/q averaged into a plain
@@ -587,12 +869,23 @@ struct EyeBuf {
     float4 *ro, *rd, *hit, *beta;   // beta.w = solid-angle pdf of the last sampled direction
     uint32_t *info;                 // bits 0..7 depth, 8 previous vertex Dirac, 9..10 phase, 11..14 u
     float4 *mis;                    // x = p(z_d -> y_{s-1}) in area measure, y = T, z = S (bits)
+    float *mis2;                    // eye-side MIS partial of the ray in flight (times its d^2)
     uint32_t *q[2];
     ShadowRay *shadow;
     ProxyItem *proxy;
     float *frame;                   // [npix * 3] this iteration's pixel values
     int npix;
 };
+
+// solid-angle density of the camera direction d for a uniform point on its pixel (image plane at
+// distance 1): 1 / (pixel area cos^3)
+__device__ __forceinline__ float camera_pdf(const CamDev &c, float3 d)
+{
+    const float ct = dot3(d, c.f);
+    if (!(ct > 0.0f)) return 0.0f;
+    const float a_pix = 4.0f * c.tan_half * c.tan_half * c.aspect / ((float)c.w * (float)c.h);
+    return 1.0f / (a_pix * ct * ct * ct);
+}
 
 __global__ void k_camera(SceneDev S, EyeBuf E, uint32_t seed, unsigned long long *cnt)
 {
@@ -608,7 +901,8 @@ __global__ void k_camera(SceneDev S, EyeBuf E, uint32_t seed, unsigned long long
     const float3 d = normalize3(S.cam.f + S.cam.r * x + S.cam.u * y);
     E.ro[p] = make_float4(S.cam.p.x, S.cam.p.y, S.cam.p.z, ibits(-1));
     E.rd[p] = make_float4(d.x, d.y, d.z, 3.0e38f);
-    E.beta[p] = make_float4(1.f, 1.f, 1.f, 0.f);
+    E.beta[p] = make_float4(1.f, 1.f, 1.f, camera_pdf(S.cam, d));
+    E.mis2[p] = 0.0f;
     E.info[p] = 1u << 8;   // camera counts as a Dirac predecessor for the first hit
     E.mis[p] = make_float4(0.f, 0.f, 0.f, 0.f);
     E.q[0][p] = (uint32_t)p;
@@ -626,6 +920,9 @@ struct EyeParams {
     int mlp_on;      // subspace S chosen by k_mlp_select (learned mixture) before k_proxy
     int tiles_on;
     int M, cand_cap;
+    MisK mk;             // strategy factors of the connection MIS (kS times *kappa)
+    const float *kappa;  // connection selection factor from the previous iteration's pool
+    int conn_on;         // light-vertex connections
 };
 // k_sel = M pi_inc c pi_sel: the proxy strategy's selection factor for a path whose first
 // diffuse eye vertex lies in T and whose y_{s-1} lies in S (surrogate used by both strategies)
@@ -645,34 +942,33 @@ __device__ __forceinline__ float proxy_ksel(const SubDev &D, const EyeParams &P,
     return (float)P.M * pi_inc * c * ps;
 }
 
-// proxy-class state machine over eye vertices (emitters count as D): phase 0 before the first
-// diffuse vertex z_d; 1 at/after z_d with only specular vertices since (u of them); 2 after
-// S^u then one diffuse vertex; 3 never a proxy path
-__device__ __forceinline__ void pstate_push(uint32_t &ph, uint32_t &u, bool spec, int umax)
+// eye-side factor K of the split whose light end is z_t and whose eye end is z_{t-1} (z_t not
+// the emitter x_0): light tracing when z_{t-1} is the camera, else a connection
+__device__ __forceinline__ float eye_split_k(const EyeParams &P, float kS, int t, bool z_dirac, bool prev_dirac)
 {
-    if (ph == 0) { if (!spec) { ph = 1; u = 0; } }
-    else if (ph == 1) {
-        if (spec) { if (++u > (uint32_t)umax) ph = 3; }
-        else ph = u >= 1 ? 2 : 3;
-    } else if (ph == 2) ph = 3;
+    if (z_dirac) return 0.0f;
+    return t == 1 ? P.mk.kL : (prev_dirac ? 0.0f : kS);
 }
-__device__ __forceinline__ bool class_ok(int filter, bool proxy_class)
+// may a light-vertex connection or splat score a path of this class?
+__device__ __forceinline__ bool conn_ok(const EyeParams &P, bool cls)
 {
-    return filter == 0 || (filter == 1 && proxy_class) || (filter == 2 && !proxy_class);
+    return P.proxy_on ? (!cls && (P.filter == 0 || P.filter == 2)) : class_ok(P.filter, cls);
 }
 
-__global__ void k_eye_shade(SceneDev S, EyeBuf E, EyeParams P, SubDev D, int t, unsigned long long *cnt)
+__global__ void k_eye_shade(SceneDev S, EyeBuf E, EyeParams P, SubDev D, LightBuf L, int t, unsigned long long *cnt)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const int n = (int)cnt[C_EYE_Q0 + t - 1];
     const uint32_t *qin = E.q[(t - 1) & 1];
     uint32_t *qout = E.q[t & 1];
-    bool cont = false, shadow = false, proxy = false;
+    bool cont = false, shadow = false, shadow2 = false, proxy = false;
     int pid = 0;
-    ShadowRay sr;
+    ShadowRay sr, sr2;
     ProxyItem pi;
     float4 nro, nrd, nbeta, nmis;
+    float nmis2 = 0.0f;
     uint32_t ninfo = 0;
+    const float kS = P.mk.kS * *P.kappa;
     if (i < n) {
         pid = qin[i];
         const float4 h = E.hit[pid];
@@ -691,6 +987,12 @@ __global__ void k_eye_shade(SceneDev S, EyeBuf E, EyeParams P, SubDev D, int t, 
             float4 mis = P.labels_on ? E.mis[pid] : make_float4(0.f, 0.f, 0.f, 0.f);
             const int Tl = fbits(mis.y), Sl = fbits(mis.z);
             const float c_pix = P.tiles_on ? tile_prob(D, pid, S.cam.w) : 1.0f;
+            // eye-side MIS state at z_t: its density from the eye side, and e_t with
+            // C(z_{t-1}) = e_t * (density at z_t of the direction toward z_{t-1})
+            const float d2 = h.x * h.x;
+            const float cos_o = fabsf(dot3(sh.n, wo));
+            const float rev_z = bt.w * cos_o / d2;
+            const float e_t = t >= 2 ? E.mis2[pid] / d2 : 0.0f;
             float3 add = f3(0.f, 0.f, 0.f);
             if (m.flags & MF_EMIT) {
                 const bool cls = (ph == 1 && uu >= 1) || ph == 2;
@@ -699,19 +1001,22 @@ __global__ void k_eye_shade(SceneDev S, EyeBuf E, EyeParams P, SubDev D, int t, 
                     if (nonzero3(le)) {
                         float w = 1.0f;
                         const float cl = fabsf(dot3(sh.n, wo));
-                        const float pl = h.x * h.x / (cl * S.em_area);   // light sampling, solid angle
                         if (cls && P.mis_on && P.proxy_on) {
                             // three strategies build this proxy-class path (area measure at y_0,
                             // common factors dropped): BSDF hit, NEE at the previous vertex, proxy
-                            const float J0 = cl / (h.x * h.x);
+                            const float J0 = cl / d2;
                             const float Ap = proxy_mis_factor(D, ph == 2 ? 1 : 0, (int)uu, Sl,
                                                               proxy_ksel(D, P, cnt, Tl, Sl, c_pix));
                             const float hit = mis.x * bt.w * J0;
                             const float nee = prev_delta ? 0.0f : mis.x / S.em_area;
                             const float prx = ph == 2 ? Ap / S.em_area : Ap * bt.w * J0;
                             w = hit / (hit + nee + prx);
-                        } else if (!(t == 1 || prev_delta)) {
-                            w = bt.w / (bt.w + pl);
+                        } else if (t >= 2) {
+                            // emission hit (s = 0): w = 1 / (1 + C_0), C_0 = fwd(x_0) / rev(x_0) (K_1 + C_1)
+                            const float K1 = prev_delta ? 0.0f : P.mk.kN;
+                            const float c1 = e_t * (cl / PT_PI);
+                            const float C0 = (1.0f / S.em_area) / rev_z * (K1 + c1);
+                            w = 1.0f / (1.0f + C0);
                         }
                         add = beta * le * w;
                     }
@@ -720,6 +1025,7 @@ __global__ void k_eye_shade(SceneDev S, EyeBuf E, EyeParams P, SubDev D, int t, 
             if (nonzero3(add)) atomic_add3(E.frame + 3 * pid, add);
             if (t < P.K) {
                 const bool spec = (m.flags & MF_SPEC) != 0;
+                const bool z_dirac = (m.flags & MF_DELTA) != 0;
                 const uint32_t ph0 = ph, uu0 = uu;
                 pstate_push(ph, uu, spec, P.u_max);
                 Rng r = rng_make(P.seed, S_EYE, (uint32_t)pid, iter_of(cnt), (uint32_t)t);
@@ -739,22 +1045,22 @@ __global__ void k_eye_shade(SceneDev S, EyeBuf E, EyeParams P, SubDev D, int t, 
                     pi.beta = make_float4(beta.x, beta.y, beta.z, ibits(pid));
                     pi.aux = make_float4(ibits(Tnew), c_pix, 0.f, 0.f);
                 }
-                if (P.nee_on && !(m.flags & MF_DELTA) && S.n_em > 0) {
+                if (P.nee_on && !z_dirac && S.n_em > 0) {
                     const bool cls = (ph == 1 && uu >= 1) || ph == 2;
                     const bool mis3 = cls && P.mis_on && P.proxy_on;
                     if (class_ok(P.filter, cls)) {
-                        const LPoint L = sample_emitter(S, u0, u1, u2);
-                        const float3 dl = L.p - x;
+                        const LPoint Lp = sample_emitter(S, u0, u1, u2);
+                        const float3 dl = Lp.p - x;
                         const float dist2 = dot3(dl, dl), dist = sqrtf(dist2);
                         const float3 wl = dl * (1.0f / dist);
-                        const float cl = -dot3(L.n, wl);
+                        const float cl = -dot3(Lp.n, wl);
                         if (cl > 0.0f) {
                             const float3 fs = bsdf_f(m, sh.n, wo, wl);
                             if (nonzero3(fs)) {
-                                const float3 le = emission(S, L.tri, L.b1, L.b2, -wl);
+                                const float3 le = emission(S, Lp.tri, Lp.b1, Lp.b2, -wl);
                                 const float pl = dist2 / (cl * S.em_area);
                                 const float pb = bsdf_pdf(m, sh.n, wo, wl);
-                                float w = pl / (pl + pb);
+                                float w;
                                 if (mis3) {
                                     // this vertex is y_1. If it is y_{s-1} itself (class A, u = 1), its
                                     // density from z_d and its subspace (with the direction toward this
@@ -763,7 +1069,7 @@ __global__ void k_eye_shade(SceneDev S, EyeBuf E, EyeParams P, SubDev D, int t, 
                                     float pz = mis.x;
                                     int Sv = Sl;
                                     if (at_v) {
-                                        pz = bt.w * fabsf(dot3(sh.n, wo)) / (h.x * h.x);
+                                        pz = bt.w * cos_o / d2;
                                         float f[9];
                                         feat9(S, x, sh.n, wl, f);
                                         Sv = nearest(D.spec_c, D.n_spec, f);
@@ -774,6 +1080,13 @@ __global__ void k_eye_shade(SceneDev S, EyeBuf E, EyeParams P, SubDev D, int t, 
                                     const float hitp = pz * pb * J0, nee = pz / S.em_area;
                                     const float prx = ph == 2 ? Ap / S.em_area : Ap * pb * J0;
                                     w = nee / (hitp + nee + prx);
+                                } else {
+                                    // s = 1: A_1 = rev(x_0) / fwd(x_0); C_1 = fwd(z) / rev(z) (K + e_t rev-pdf)
+                                    const float A1 = pb / pl;
+                                    const float fwd_z = (cl / PT_PI) * fabsf(dot3(sh.n, wl)) / dist2;
+                                    const float c = e_t * bsdf_pdf(m, sh.n, wl, wo);
+                                    const float C1 = fwd_z / rev_z * (eye_split_k(P, kS, t, false, prev_delta) + c);
+                                    w = P.mk.kN / (P.mk.kN + A1 + C1);
                                 }
                                 const float3 c = beta * fs * le * (fabsf(dot3(sh.n, wl)) / pl * w);
                                 if (nonzero3(c)) {
@@ -781,8 +1094,51 @@ __global__ void k_eye_shade(SceneDev S, EyeBuf E, EyeParams P, SubDev D, int t, 
                                     sr.o = make_float4(x.x, x.y, x.z, ibits(tri));
                                     sr.d = make_float4(wl.x, wl.y, wl.z, dist * 0.9999f);
                                     sr.c = make_float4(c.x, c.y, c.z, ibits(pid));
-                                    sr.ign1 = L.tri;
+                                    sr.ign1 = Lp.tri;
                                 }
+                            }
+                        }
+                    }
+                }
+                // connection to one light vertex drawn uniformly from the pool
+                const float uc = rng_f(r);
+                const uint32_t npool = (uint32_t)cnt[C_POOL];
+                if (P.conn_on && !z_dirac && npool > 0 && kS > 0.0f) {
+                    const uint32_t v = L.pool[min((uint32_t)(uc * (float)npool), npool - 1u)];
+                    const int j = (int)(v / (uint32_t)L.M), lp = (int)(v % (uint32_t)L.M);
+                    const uint32_t sg = L.sig[lp];
+                    if (t + j + 1 <= P.K && conn_ok(P, light_tail_class(ph, uu, sg, j, P.u_max))) {
+                        const float4 yv = L.lv[v];
+                        const int ty = fbits(yv.w);
+                        const float3 y = xyz(yv), ny = S.shade[ty].n;
+                        const MatDev my = S.mats[S.shade[ty].mat];
+                        const float3 wyp = normalize3(xyz(L.lv[v - (uint32_t)L.M]) - y);
+                        const float3 dv = y - x;
+                        const float dd2 = dot3(dv, dv), dist = sqrtf(dd2);
+                        const float3 wzy = dv * (1.0f / dist), wyz = -wzy;
+                        const float3 fz = bsdf_f(m, sh.n, wo, wzy);
+                        const float3 fy = bsdf_f(my, ny, wyz, wyp);
+                        if (nonzero3(fz) && nonzero3(fy)) {
+                            const float cy = fabsf(dot3(ny, wyz)), cz = fabsf(dot3(sh.n, wzy));
+                            const float4 lt = L.lt[v];
+                            // light side: A_s = (phi_j rev-pdf(y_j) + K_j) rev(y_j) / fwd(y_j)
+                            const bool prev_y_dirac = j >= 2 && (L.lfl[v - (uint32_t)L.M] & LV_DIRAC);
+                            const float Kj = j == 1 ? P.mk.kN : (prev_y_dirac ? 0.0f : kS);
+                            const float rev_y = bsdf_pdf(m, sh.n, wo, wzy) * cy / dd2;
+                            const float As = (L.lphi[v] * bsdf_pdf(my, ny, wyz, wyp) + Kj) * rev_y / lt.w;
+                            // eye side: C_s = fwd(z) / rev(z) (K + e_t rev-pdf(z))
+                            const float fwd_z = bsdf_pdf(my, ny, wyp, wyz) * cz / dd2;
+                            const float c = e_t * bsdf_pdf(m, sh.n, wzy, wo);
+                            const float Cs = fwd_z / rev_z * (eye_split_k(P, kS, t, false, prev_delta) + c);
+                            const float w = kS / (kS + As + Cs);
+                            const float3 cc = beta * fz * fy * xyz(lt) *
+                                              (cy * cz / dd2 * ((float)npool / (float)P.M) * w);
+                            if (nonzero3(cc) && lt.w > 0.0f) {
+                                shadow2 = true;
+                                sr2.o = make_float4(x.x, x.y, x.z, ibits(tri));
+                                sr2.d = make_float4(wzy.x, wzy.y, wzy.z, dist * 0.9999f);
+                                sr2.c = make_float4(cc.x, cc.y, cc.z, ibits(pid));
+                                sr2.ign1 = ty;
                             }
                         }
                     }
@@ -798,12 +1154,15 @@ __global__ void k_eye_shade(SceneDev S, EyeBuf E, EyeParams P, SubDev D, int t, 
                         nbeta = make_float4(nb.x, nb.y, nb.z, bs.pdf);
                         ninfo = (uint32_t)t | (bs.delta ? 1u << 8 : 0u) | (ph << 9) | (uu << 11);
                         nmis = make_float4(mis.x, ibits(Tnew), mis.z, 0.f);
+                        // e_{t+1} d^2 = (K + e_t rev-pdf(z)) |cos| / rev(z), the light side being z_{t+1}
+                        const float c = e_t * rev_pdf(m, sh.n, bs.wi, wo);
+                        nmis2 = (eye_split_k(P, kS, t, z_dirac, prev_delta) + c) * fabsf(dot3(sh.n, bs.wi)) / rev_z;
                         if (P.labels_on && ph0 == 1 && uu0 == 0 && ph == 1 && uu == 1) {
                             // this vertex is y_{s-1}: record p(z_d -> y_{s-1}) (area) and its specular
                             // subspace from (position, normal, direction toward the light side)
                             float f[9];
                             feat9(S, x, sh.n, bs.wi, f);
-                            nmis.x = bt.w * fabsf(dot3(sh.n, wo)) / (h.x * h.x);
+                            nmis.x = bt.w * cos_o / d2;
                             nmis.z = ibits(nearest(D.spec_c, D.n_spec, f));
                         }
                     }
@@ -813,14 +1172,73 @@ __global__ void k_eye_shade(SceneDev S, EyeBuf E, EyeParams P, SubDev D, int t, 
     }
     const int ss = wave_push(cnt + C_SHD0 + t, shadow);
     if (shadow) E.shadow[ss] = sr;
+    const int ss2 = wave_push(cnt + C_SHD0 + t, shadow2);
+    if (shadow2) E.shadow[ss2] = sr2;
+    wave_count(cnt + C_SPC, shadow2 ? 1u : 0u);
     const int ps = wave_push(cnt + C_PROXYQ, proxy);
     if (proxy) E.proxy[ps] = pi;
     const int cs = wave_push(cnt + C_EYE_Q0 + t, cont);
     if (cont) {
         qout[cs] = (uint32_t)pid;
         E.ro[pid] = nro; E.rd[pid] = nrd; E.beta[pid] = nbeta; E.info[pid] = ninfo;
+        E.mis2[pid] = nmis2;
         if (P.labels_on) E.mis[pid] = nmis;
     }
+}
+
+// Light tracing: every pool vertex y_j connects to the camera and splats onto its pixel,
+// weighted against the other strategies (w = M / (M + A_k)).
+__global__ void __launch_bounds__(WG) k_lt(SceneDev S, LightBuf L, EyeParams P, float *frame, unsigned long long *cnt)
+{
+    __shared__ int stk[PT_STACK * WG];
+    const int i = blockIdx.x * WG + threadIdx.x;
+    const uint32_t npool = (uint32_t)cnt[C_POOL];
+    uint32_t done = 0, rays = 0;
+    if ((uint32_t)i < npool) {
+        const uint32_t v = L.pool[i];
+        const int j = (int)(v / (uint32_t)L.M), lp = (int)(v % (uint32_t)L.M);
+        const CamDev &cam = S.cam;
+        const float4 yv = L.lv[v];
+        const int ty = fbits(yv.w);
+        const float3 y = xyz(yv), ny = S.shade[ty].n;
+        const float3 dc = cam.p - y;
+        const float dd2 = dot3(dc, dc), dist = sqrtf(dd2);
+        const float3 wyc = dc * (1.0f / dist), dir = -wyc;
+        const float ct = dot3(dir, cam.f);
+        if (ct > 0.0f && conn_ok(P, light_tail_class(0u, 0u, L.sig[lp], j, P.u_max))) {
+            const float sx = dot3(dir, cam.r) / ct / (cam.tan_half * cam.aspect);
+            const float sy = dot3(dir, cam.u) / ct / cam.tan_half;
+            const float fx = (sx + 1.0f) * 0.5f * (float)cam.w, fy = (1.0f - sy) * 0.5f * (float)cam.h;
+            if (fx >= 0.0f && fy >= 0.0f && fx < (float)cam.w && fy < (float)cam.h) {
+                const int px = min((int)fx, cam.w - 1), py = min((int)fy, cam.h - 1);
+                const MatDev my = S.mats[S.shade[ty].mat];
+                const float3 wyp = normalize3(xyz(L.lv[v - (uint32_t)L.M]) - y);
+                const float3 fy3 = bsdf_f(my, ny, wyc, wyp);
+                const float4 lt = L.lt[v];
+                if (nonzero3(fy3) && lt.w > 0.0f) {
+                    const float kS = P.mk.kS * *P.kappa;
+                    const float cy = fabsf(dot3(ny, wyc));
+                    const float pw = camera_pdf(cam, dir);
+                    const float rev_y = pw * cy / dd2;
+                    const bool prev_y_dirac = j >= 2 && (L.lfl[v - (uint32_t)L.M] & LV_DIRAC);
+                    const float Kj = j == 1 ? P.mk.kN : (prev_y_dirac ? 0.0f : kS);
+                    const float Ak = (L.lphi[v] * bsdf_pdf(my, ny, wyc, wyp) + Kj) * rev_y / lt.w;
+                    const float w = P.mk.kL / (P.mk.kL + Ak);
+                    const float3 c = xyz(lt) * fy3 * (pw * cy / dd2 / (float)P.M * w);
+                    if (nonzero3(c)) {
+                        Hit hh;
+                        rays = 1;
+                        if (!traverse<true, false>(S, y, wyc, S.tmin, dist * 0.9999f, ty, -1, stk + threadIdx.x, WG, hh)) {
+                            atomic_add3(frame + 3 * (py * cam.w + px), c);
+                            done = 1;
+                        }
+                    }
+                }
+            }
+        }
+    }
+    wave_count(cnt + C_LT, done);
+    wave_count(cnt + C_RAYS_SHADOW, rays);
 }
 
 __global__ void __launch_bounds__(WG) k_occluded(SceneDev S, EyeBuf E, int t, unsigned long long *cnt)

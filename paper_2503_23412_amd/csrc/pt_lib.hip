@@ -70,6 +70,9 @@ struct pt_scene {
     uint32_t *kept = nullptr, *final_ = nullptr;
     unsigned long long *cnt = nullptr;
     float *runmax = nullptr;   // [2 * 5] running maxima of f/q per (class, u)
+    float *kappa = nullptr;   // [2]: connection factor of this iteration, previous pool size
+    ChainState *chq[2] = {nullptr, nullptr};   // running reciprocal chains between rounds
+    float2 *chbuf = nullptr;                   // (f/q, u) samples of one round
     bool subspaces_ready = false;
     // subspaces, selection and statistics (allocated by pt_build_subspaces)
     int n_eye = 0, n_spec = 0, tile = 10, tiles_x = 0, n_tiles = 0;
@@ -215,16 +218,21 @@ extern "C" pt_status pt_scene_upload(const pt_scene_desc *d, void *stream_, pt_s
         AL(s->em_cdf, emc.size());
         const int M = s->max_light, np = s->npix;
         AL(s->L.ro, M); AL(s->L.rd, M); AL(s->L.hit, M);
-        AL(s->L.lv, (size_t)PT_LMAX * M); AL(s->L.lb0, M); AL(s->L.sig, M);
+        AL(s->L.lv, (size_t)PT_LSTORE * M); AL(s->L.lt, (size_t)PT_LSTORE * M); AL(s->L.lphi, (size_t)PT_LSTORE * M);
+        AL(s->L.lfl, (size_t)PT_LSTORE * M); AL(s->L.pool, (size_t)PT_LSTORE * M); AL(s->L.lbeta, M);
+        AL(s->L.lb0, M); AL(s->L.sig, M);
         AL(s->L.q[0], M); AL(s->L.q[1], M);
         AL(s->cand, (size_t)4 * M);
         AL(s->kept, (size_t)4 * M); AL(s->final_, (size_t)4 * M);
         AL(s->E.ro, np); AL(s->E.rd, np); AL(s->E.hit, np); AL(s->E.beta, np); AL(s->E.info, np); AL(s->E.mis, np);
         AL(s->E.q[0], np); AL(s->E.q[1], np);
-        AL(s->E.shadow, np); AL(s->E.proxy, np);
+        AL(s->E.shadow, 2 * (size_t)np); AL(s->E.proxy, np); AL(s->E.mis2, np);
+        AL(s->kappa, 2);
         AL(s->E.frame, (size_t)3 * np);
         AL(s->cnt, C_COUNT);
         AL(s->runmax, 16);
+        AL(s->chq[0], CHAIN_LIST_CAP); AL(s->chq[1], CHAIN_LIST_CAP);
+        AL(s->chbuf, CHAIN_BUF);
 #undef AL
         s->L.M = M;
         s->E.npix = np;
@@ -237,6 +245,7 @@ extern "C" pt_status pt_scene_upload(const pt_scene_desc *d, void *stream_, pt_s
         HIPCHK(hipMemcpyAsync(s->em_cdf, emc.data(), emc.size() * sizeof(float), hipMemcpyHostToDevice, stream));
         HIPCHK(hipMemsetAsync(s->E.frame, 0, sizeof(float) * 3 * np, stream));
         HIPCHK(hipMemsetAsync(s->runmax, 0, sizeof(float) * 16, stream));
+        HIPCHK(hipMemsetAsync(s->kappa, 0, sizeof(float) * 2, stream));
         HIPCHK(hipStreamSynchronize(stream));
         SceneDev &S = s->S;
         S.nodes = s->nodes; S.tris = s->tris; S.shade = s->shade; S.mats = s->mats; S.tex = s->tex;
@@ -355,13 +364,14 @@ extern "C" pt_status pt_build_subspaces(pt_scene *s, const pt_subspace_params *p
     EyeBuf E = s->E;
     EyeParams EP{};
     EP.seed = p->seed; EP.K = 8; EP.u_max = 4; EP.filter = 3; EP.proxy_on = 1; EP.nee_on = 0;
+    EP.kappa = s->kappa;
     SubDev D{};
     k_zero<<<blocks(C_COUNT, 256), 256, 0, st>>>(s->cnt, C_COUNT);
     k_camera<<<blocks(np, 256), 256, 0, st>>>(S, E, p->seed, s->cnt);
     for (int t = 1; t <= EP.K; ++t) {
         k_extend<false><<<blocks(np, WG), WG, 0, st>>>(S, E.q[(t - 1) & 1], s->cnt, C_EYE_Q0 + t - 1, E.ro, E.rd, E.hit,
                                                        s->cnt, C_RAYS_EYE);
-        k_eye_shade<<<blocks(np, 256), 256, 0, st>>>(S, E, EP, D, t, s->cnt);
+        k_eye_shade<<<blocks(np, 256), 256, 0, st>>>(S, E, EP, D, L, t, s->cnt);
     }
     k_fill<<<blocks(3L * np, 256), 256, 0, st>>>(E.frame, 0.0f, (size_t)3 * np);
     k_feat_proxy<<<blocks(np, 256), 256, 0, st>>>(S, E.proxy, s->cnt, s->feat);
@@ -422,6 +432,16 @@ __global__ void k_sum1(const float *x, int n, float *out)
         __syncthreads();
     }
     if (threadIdx.x == 0) *out = red[0];
+}
+
+// connection factor kappa = M / N from the previous iteration's pool size N (1 before any)
+__global__ void k_kappa(float *kappa, int M)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) kappa[0] = kappa[1] > 0.0f ? (float)M / kappa[1] : 1.0f;
+}
+__global__ void k_kappa_store(float *kappa, const unsigned long long *cnt)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) kappa[1] = (float)cnt[C_POOL];
 }
 
 // C = A B on MFMA (see k_gemm); ksplit > 1 adds into C with atomics
@@ -529,6 +549,8 @@ pt_status check_params(pt_scene *s, const pt_iter_params *p, float *acc)
     if (p->cand_cap < 1 || p->pilot < 1) return set_err(PT_EINVAL, "cand_cap and pilot must be positive");
     if ((p->flags & PT_FLAG_ONLY_PROXY_CLASS) && (p->flags & PT_FLAG_ONLY_OTHER))
         return set_err(PT_EINVAL, "class filters are exclusive");
+    if ((p->flags & (PT_FLAG_SPC | PT_FLAG_LT)) && p->max_depth > PT_LSTORE)
+        return set_err(PT_EINVAL, "light-vertex connections and light tracing support max_depth <= %d", PT_LSTORE);
     if ((p->flags & PT_FLAG_MLP) && !(p->mlp_mix >= 0.0f && p->mlp_mix < 1.0f && p->mlp_lr > 0.0f))
         return set_err(PT_EINVAL, "PT_FLAG_MLP needs 0 <= mlp_mix < 1 and mlp_lr > 0");
     return PT_OK;
@@ -568,15 +590,25 @@ pt_status enqueue_iteration(pt_scene *s, const pt_iter_params *p, float *acc, fl
         k_copy<<<blocks((long)ne * ns, 256), 256, 0, stream>>>(s->gamma_acc, s->gamma_frz, (size_t)ne * ns);
         k_copy<<<blocks(30L * ns, 256), 256, 0, stream>>>(s->rstat_acc, s->rstat_frz, (size_t)30 * ns);
     }
-    if (proxy) {
-        // light pass: y_0 .. y_{lmax-1}
-        const int lmax = std::min(p->max_depth - 1, PT_LMAX);
+    const bool conn = (p->flags & PT_FLAG_SPC) != 0, ltr = (p->flags & PT_FLAG_LT) != 0;
+    // light sub-paths: y_0 .. y_{lmax-1}; connections and light tracing use every vertex a path
+    // within max_depth segments can have, the proxy candidates the first PT_LMAX
+    const int lmax = (conn || ltr) ? p->max_depth : std::min(p->max_depth - 1, PT_LMAX);
+    if (proxy || conn || ltr) {
         k_light_gen<<<blocks(M, 256), 256, 0, stream>>>(S, L, p->seed, s->cnt);
         for (int vi = 1; vi < lmax; ++vi) {
             k_extend<false><<<blocks(M, WG), WG, 0, stream>>>(S, L.q[(vi - 1) & 1], s->cnt, C_LIGHT_Q0 + vi - 1, L.ro,
                                                               L.rd, L.hit, s->cnt, C_RAYS_LIGHT);
             k_light_shade<<<blocks(M, 256), 256, 0, stream>>>(S, L, p->seed, vi, lmax, s->cnt);
         }
+    }
+    const MisK mk{(p->flags & PT_FLAG_NEE) ? 1.0f : 0.0f, conn ? 1.0f : 0.0f, ltr ? (float)M : 0.0f};
+    if ((conn || ltr) && lmax >= 2) {
+        k_kappa<<<1, 1, 0, stream>>>(s->kappa, M);
+        k_pool<<<blocks((long)(lmax - 1) * M, 256), 256, 0, stream>>>(L, lmax, s->cnt);
+        k_light_phi<<<blocks(M, 256), 256, 0, stream>>>(S, L, mk, s->kappa, s->cnt);
+    }
+    if (proxy) {
         if (lmax >= 2) {
             k_candidates<<<blocks(M, 256), 256, 0, stream>>>(L, p->u_max, s->cand, s->cnt);
             const int maxc = 4 * M;
@@ -587,7 +619,16 @@ pt_status enqueue_iteration(pt_scene *s, const pt_iter_params *p, float *acc, fl
                                                               p->recip_repeats, p->cost_cap, p->seed, s->cnt);
             const uint32_t n1 = (uint32_t)std::max(64.0f, p->cost_cap / (float)p->recip_repeats);
             k_recip<<<blocks((long)maxc * p->recip_repeats, RW), 64 * RW, 0, stream>>>(
-                S, s->cand, s->final_, p->recip_repeats, p->seed, n1, 1u << 20, s->runmax, s->cnt);
+                S, s->cand, s->final_, p->recip_repeats, p->seed, n1, 1024u, s->runmax, s->chq[0], s->cnt);
+            for (int r = 0; r < CHAIN_ROUNDS; ++r) {
+                const int in = r & 1, out = in ^ 1;
+                k_set_counter<<<1, 1, 0, stream>>>(s->cnt, C_LONGQ0 + out, 0ull);
+                k_chain_gen<<<8192, WG, 0, stream>>>(S, s->cand, s->chq[in], C_LONGQ0 + in, r, p->seed, s->chbuf,
+                                                     s->cnt);
+                k_chain_consume<<<2048, 64 * RW, 0, stream>>>(s->cand, s->chq[in], C_LONGQ0 + in, s->chq[out],
+                                                              C_LONGQ0 + out, r, r == CHAIN_ROUNDS - 1 ? 1 : 0,
+                                                              p->seed, s->chbuf, s->runmax, s->cnt);
+            }
             if (labels) {
                 SubDev D0{};
                 D0.spec_c = s->spec_c; D0.n_spec = ns;
@@ -619,6 +660,7 @@ pt_status enqueue_iteration(pt_scene *s, const pt_iter_params *p, float *acc, fl
     EP.mlp_on = mlp && EP.proxy_on;
     EP.tiles_on = tiles;
     EP.M = M; EP.cand_cap = p->cand_cap;
+    EP.mk = mk; EP.kappa = s->kappa; EP.conn_on = conn && lmax >= 2;
     SubDev D{};
     if (s->n_eye > 0) {
         D.eye_c = s->eye_c; D.spec_c = s->spec_c; D.n_eye = ne; D.n_spec = ns;
@@ -639,9 +681,12 @@ pt_status enqueue_iteration(pt_scene *s, const pt_iter_params *p, float *acc, fl
             k_extend<false><<<blocks(np, WG), WG, 0, stream>>>(S, E.q[(t - 1) & 1], s->cnt, C_EYE_Q0 + t - 1, E.ro, E.rd,
                                                                E.hit, s->cnt, C_RAYS_EYE);
         if (timing) HIPCHK(hipEventRecord(s->ev[2 * (t - 1) + 1], stream));
-        k_eye_shade<<<blocks(np, 256), 256, 0, stream>>>(S, E, EP, D, t, s->cnt);
-        k_occluded<<<blocks(np, WG), WG, 0, stream>>>(S, E, t, s->cnt);
+        k_eye_shade<<<blocks(np, 256), 256, 0, stream>>>(S, E, EP, D, L, t, s->cnt);
+        k_occluded<<<blocks(2L * np, WG), WG, 0, stream>>>(S, E, t, s->cnt);
     }
+    if (ltr && lmax >= 2)
+        k_lt<<<blocks((long)(lmax - 1) * M, WG), WG, 0, stream>>>(S, L, EP, E.frame, s->cnt);
+    if (conn || ltr) k_kappa_store<<<1, 1, 0, stream>>>(s->kappa, s->cnt);
     StatBuf SB{s->gamma_acc, s->tile_proxy, s->tile_total};
     if (EP.mlp_on) {
         // the network's logits for every queued first diffuse vertex, then S per item
@@ -705,6 +750,11 @@ extern "C" pt_status pt_render_iteration(pt_scene *s, const pt_iter_params *p, f
             stats->ms_extend = ms;
             stats->n_extend_launches = p->max_depth;
         }
+        stats->n_pool = (double)c[C_POOL];
+        stats->n_connections = (double)c[C_SPC];
+        stats->n_lt_splats = (double)c[C_LT];
+        for (int b = 0; b < 24; ++b) stats->chain_len_hist[b] = (double)c[C_CHAIN_HIST + b];
+        stats->chain_len_max = (double)c[C_CHAIN_MAX];
     }
     return PT_OK;
 }

@@ -22,6 +22,8 @@ PT_FLAG_TIMING = 1 << 6
 PT_FLAG_COUNT = 1 << 7
 PT_FLAG_MIS = 1 << 8
 PT_FLAG_MLP = 1 << 9
+PT_FLAG_SPC = 1 << 10
+PT_FLAG_LT = 1 << 11
 
 PT_EST_ITILDE = 0
 PT_EST_SIGN = 1
@@ -62,10 +64,13 @@ class IterStats(ctypes.Structure):
         "rays_extend_eye", "rays_extend_light", "rays_shadow", "rays_proxy", "rays_recip",
         "n_cand", "n_kept", "n_recip_samples", "n_recip_truncated",
         "n_proxy_attempts", "n_proxy_valid", "n_nan", "node_visits", "tri_tests",
-        "ms_extend", "n_extend_launches")]
+        "ms_extend", "n_extend_launches", "n_pool", "n_connections", "n_lt_splats")] + [
+        ("chain_len_hist", ctypes.c_double * 24), ("chain_len_max", ctypes.c_double)]
 
     def as_dict(self):
-        return {k: getattr(self, k) for k, _ in self._fields_}
+        d = {k: getattr(self, k) for k, _ in self._fields_}
+        d["chain_len_hist"] = list(self.chain_len_hist)
+        return d
 
 
 class CandDesc(ctypes.Structure):

@@ -44,7 +44,12 @@ def _render(gpu, sc, N, max_light=1024, subspaces=(8, 8), **params):
             say(f"  {k + 1}/{N} iterations")
         if st:
             for key, v in st.items():
-                tot[key] = tot.get(key, 0) + v
+                if key == "chain_len_hist":
+                    tot[key] = [a + b for a, b in zip(tot.get(key, [0] * len(v)), v)]
+                elif key == "chain_len_max":
+                    tot[key] = max(tot.get(key, 0), v)
+                else:
+                    tot[key] = tot.get(key, 0) + v
     torch.cuda.synchronize()
     m = (acc / N).double().cpu().numpy().reshape(H, W, 3)
     v = np.maximum((acc2 / N).double().cpu().numpy().reshape(H, W, 3) - m * m, 0) / N
@@ -139,14 +144,18 @@ def test_bvh_closest_hit_matches_brute_force(gpu, oracle, which):
 
 
 # ------------------------------------------------------------------------------ furnaces
-@pytest.mark.parametrize("proxy", [False, True])
+@pytest.mark.parametrize("proxy", ["pt_nee", "proxy", "connections", "light_tracing", "full"])
 def test_diffuse_furnace(gpu, proxy):
     from synth import scenes
     torch, pt = gpu
     a, K = 0.5, 6
     sc = scenes.furnace(albedo=a, le=1.0, width=16, height=16)
-    say(f"diffuse furnace proxy={proxy}")
-    flags = pt.PT_FLAG_NEE | (pt.PT_FLAG_PROXY if proxy else 0)
+    say(f"diffuse furnace {proxy}")
+    flags = {"pt_nee": pt.PT_FLAG_NEE, "proxy": pt.PT_FLAG_NEE | pt.PT_FLAG_PROXY,
+             "connections": pt.PT_FLAG_NEE | pt.PT_FLAG_SPC | pt.PT_FLAG_LT,
+             "light_tracing": pt.PT_FLAG_NEE | pt.PT_FLAG_LT,
+             "full": pt.PT_FLAG_NEE | pt.PT_FLAG_PROXY | pt.PT_FLAG_MIS | pt.PT_FLAG_GAMMA | pt.PT_FLAG_SPC |
+             pt.PT_FLAG_LT}[proxy]
     m, v, st = _render(gpu, sc, 512, max_depth=K, n_light=1024, cand_cap=128, flags=flags)
     expect = (1 - a ** K) / (1 - a)
     z = (m - expect) / np.sqrt(v + 1e-30)

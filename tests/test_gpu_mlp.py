@@ -1,11 +1,18 @@
 """GPU tests of the learned subspace selection's network (BF16 MFMA, FP32 accumulation) against
 the FP64 oracle of oracle/mlp.py, through the C ABI.
 
-Tolerances: operands are rounded to BF16 (unit roundoff 2^-8) at every layer's input and
-weights, so each layer's products carry a relative error of about 2^-8 / sqrt(2) per factor
-pair, accumulating to a few 1e-3 over four layers on random data; the tests allow 2e-2 (rel-L2)
-with cosine similarity above 0.999, which a transposed operand or a wrong MFMA lane layout
-(errors of order 1) cannot meet."""
+Tolerances: operands are rounded to BF16 (unit roundoff u = 2^-8) at every layer's input and
+weights, so each layer's products carry a relative error of about u / sqrt(2) per factor pair,
+accumulating to a few 1e-3 over four layers on random data; the forward test allows 2e-2
+(rel-L2) with cosine similarity above 0.999.
+
+Gradients: a gradient block is a sum over samples whose terms cancel, and BF16 storage of the
+weights, inputs and activations moves it by several per cent of sqrt(sum_i ||term_i||^2) (the
+oracle's grad_scale) on random networks. The oracle's bf16 mode rounds at the same storage
+points, so the GPU gradient is compared with it at 1 % of that scale (what remains is FP32
+accumulation order and the rare ReLU whose sign the order flips), and with the FP64 gradient
+within 1.5 times the bf16 model's own distance from it plus 1 % of the scale. A transposed
+operand, a wrong MFMA lane layout or a lost split-K chunk gives errors of order 10-100 %."""
 import numpy as np
 import pytest
 
@@ -84,16 +91,23 @@ def test_gradient_and_adam_match_oracle(scene, n):
                              want_grad=True)
     ref = mlp.grad(p.astype(np.float64), N_SPEC, feat.astype(np.float32).astype(np.float64), label,
                    weight.astype(np.float32).astype(np.float64))
-    off = 0
+    f64, w64 = feat.astype(np.float32).astype(np.float64), weight.astype(np.float32).astype(np.float64)
+    scale = mlp.grad_scale(p.astype(np.float64), N_SPEC, f64, label, w64)
+    ref16 = mlp.grad(p.astype(np.float64), N_SPEC, f64, label, w64, bf16=True)
+    off, bad = 0, []
     for name, shape in mlp.layout(N_SPEC):
         k = int(np.prod(shape))
-        a, b = g[off:off + k].astype(np.float64), ref[off:off + k]
-        print(f"grad {name}: rel-L2 {_rel(a, b):.2e} cos {_cos(a, b):.6f}", flush=True)
-        assert np.all(np.isfinite(a)), name
-        assert _rel(a, b) < 5e-2 and _cos(a, b) > 0.999, name
+        a, b, b16 = g[off:off + k].astype(np.float64), ref[off:off + k], ref16[off:off + k]
+        e64, e16, model = (float(np.linalg.norm(a - b)), float(np.linalg.norm(a - b16)),
+                           float(np.linalg.norm(b16 - b)))
+        print(f"grad {name}: vs fp64 {e64 / scale[name]:.2e}, vs bf16 model {e16 / scale[name]:.2e}, "
+              f"model vs fp64 {model / scale[name]:.2e} (of scale); cos vs fp64 {_cos(a, b):.5f}", flush=True)
+        if not (np.all(np.isfinite(a)) and e16 <= 1e-2 * scale[name] and e64 <= 1.5 * model + 1e-2 * scale[name]):
+            bad.append(name)
         if name == "W1":
             assert np.all(a.reshape(shape)[225:] == 0.0)
         off += k
+    assert not bad, bad
     # one Adam step from zero moments: w - lr g / (|g| + eps), with the GPU's own gradient
     p1 = scene.mlp_get_params()
     g32 = g.astype(np.float32)

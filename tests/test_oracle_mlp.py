@@ -149,3 +149,81 @@ def test_adam_closed_form():
     # first step with zero gradient leaves w unchanged
     w1, _, _ = mlp.adam_step(w0, np.zeros(50), np.zeros(50), np.zeros(50), 1, lr=1e-3)
     np.testing.assert_array_equal(w1, w0)
+
+
+def test_grad_scale_single_sample_is_the_gradient_norm():
+    # with one sample there is no cancellation: the scale equals each block's gradient norm
+    rng = np.random.default_rng(5)
+    params = _params(rng)
+    feat, label, weight = _data(rng, 1)
+    g = mlp.unpack(mlp.grad(params, N_OUT, feat, label, weight), N_OUT)
+    sc = mlp.grad_scale(params, N_OUT, feat, label, weight)
+    for name, _ in mlp.layout(N_OUT):
+        assert sc[name] == pytest.approx(np.linalg.norm(g[name]), rel=1e-12), name
+    # and with many samples it bounds the norm of the sum (triangle inequality with Cauchy-Schwarz)
+    feat, label, weight = _data(rng, 40)
+    g = mlp.unpack(mlp.grad(params, N_OUT, feat, label, weight), N_OUT)
+    sc = mlp.grad_scale(params, N_OUT, feat, label, weight)
+    for name, _ in mlp.layout(N_OUT):
+        assert np.linalg.norm(g[name]) <= sc[name] * np.sqrt(40) * (1 + 1e-12), name
+
+
+def test_bf16_rounding():
+    # BF16 keeps 8 significant bits: spacing 2^-7 in [1, 2); halfway cases go to the even neighbour
+    x = np.array([1.0, 1.0 + 2.0 ** -8, 1.0 + 3 * 2.0 ** -8, 1.0 + 2.0 ** -7 + 2.0 ** -9, -2.5, 3.0e-3, 65504.0])
+    r = mlp.round_bf16(x)
+    np.testing.assert_array_equal(r[:4], [1.0, 1.0, 1.0 + 2.0 ** -6, 1.0 + 2.0 ** -7])
+    assert r[4] == -2.5
+    # relative error at most 2^-8 for normal numbers
+    assert np.all(np.abs(r[5:] - x[5:]) <= 2.0 ** -8 * np.abs(x[5:]))
+    rng = np.random.default_rng(6)
+    y = rng.normal(size=10000) * 10.0 ** rng.uniform(-3, 3, size=10000)
+    ry = mlp.round_bf16(y)
+    assert np.all(np.abs(ry - y) <= 2.0 ** -8 * np.abs(y) * (1 + 1e-6))
+    # idempotent, and values with 8 significant bits are kept exactly
+    np.testing.assert_array_equal(mlp.round_bf16(ry), ry)
+
+
+def test_bf16_mode_on_a_known_network():
+    """The pass-through network of test_known_linear_network: every value is a BF16 value, so the
+    bf16 mode gives the exact logits; a weight of 1 + 2^-9 (below the halfway point to the next
+    BF16 value) is stored as 1 and the logits follow."""
+    blocks = {name: np.zeros(shape) for name, shape in mlp.layout(3)}
+    blocks["W1"][0, 0] = 1.0
+    blocks["W2"][0, 0] = 2.0
+    blocks["W3"][0, 0] = 1.0
+    blocks["W4"][0, :] = [1.0, -1.0, 0.0]
+    blocks["b4"][:] = [0.0, 0.0, 0.5]
+    f = np.zeros((2, 9))
+    f[0, 0] = 0.75
+    f[1, 0] = -0.75
+    L16, _ = mlp.forward(mlp.pack(blocks, 3), 3, f, bf16=True)
+    np.testing.assert_array_equal(L16, [[1.5, -1.5, 0.5], [0.0, 0.0, 0.5]])
+    blocks["W1"][0, 0] = 1.0 + 2.0 ** -9
+    L64, _ = mlp.forward(mlp.pack(blocks, 3), 3, f)
+    L16, _ = mlp.forward(mlp.pack(blocks, 3), 3, f, bf16=True)
+    np.testing.assert_allclose(L64[0, :2], [1.5 * (1 + 2.0 ** -9), -1.5 * (1 + 2.0 ** -9)], rtol=1e-15)
+    np.testing.assert_array_equal(L16[0], [1.5, -1.5, 0.5])
+    # the gradient in bf16 mode: with uniform weights and these exact values the logit gradient
+    # (softmax - onehot) / n is rounded once; W4's gradient is h3^T G4 with h3 = (1.5, 0, ...)
+    label = np.array([2, 2])
+    g16 = mlp.unpack(mlp.grad(mlp.pack(blocks, 3), 3, f, label, np.ones(2), bf16=True), 3)
+    Lr = np.array([1.5, -1.5, 0.5])
+    sm = np.exp(Lr - Lr.max()) / np.exp(Lr - Lr.max()).sum()
+    G0 = mlp.round_bf16((sm - np.array([0, 0, 1.0])) / 2)
+    np.testing.assert_allclose(g16["W4"][0], 1.5 * G0, rtol=1e-15)
+
+
+def test_fp32_argument_encoding():
+    # fp32 arguments: exact for features whose products with pi round the same way (f = 0),
+    # and within the FP32 rounding of f pi (2^-24 relative), times 2^b, of the exact argument
+    f = np.zeros((1, 9))
+    np.testing.assert_array_equal(mlp.encode(f, fp32_args=True), mlp.encode(f))
+    rng = np.random.default_rng(8)
+    f = rng.uniform(0, 1, size=(200, 9)).astype(np.float32).astype(np.float64)
+    X, X32 = mlp.encode(f), mlp.encode(f, fp32_args=True)
+    for b in range(12):
+        cols = [1 + 25 * j + 2 * b for j in range(9)]
+        # fp32(pi) and the product each round by at most half an ulp (2^-24 relative)
+        bound = 2.0 ** b * np.pi * 2 * 2.0 ** -24 * 1.01 + 1e-15
+        assert np.all(np.abs(X32[:, cols] - X[:, cols]) <= bound)
