@@ -1,9 +1,10 @@
 """Benchmark of the proxy-sampling BDPT hot path on one MI355X.
 
 A step is one rendering iteration (1 sample per pixel through every strategy: light pass,
-candidates, reciprocal estimates, eye pass with next-event estimation and proxy connections,
-accumulation) of the projector caustic workload (512 x 512, depth 12, 500,000 light
-sub-paths per iteration, 20,000 expected candidates). Prints one JSON line.
+connection pool, candidates, reciprocal estimates, eye pass with emission hits, next-event
+estimation and probabilistic connections, light tracing, proxy connections, accumulation) of
+the projector caustic workload (512 x 512, depth 12, 500,000 light sub-paths per iteration,
+20,000 expected candidates). Prints one JSON line.
 
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
 """
@@ -68,6 +69,9 @@ def main():
     cfg = scenes.config(args.config)
     sc = cfg["scene"]
     W, H = sc["width"], sc["height"]
+    # the plain method: every strategy of the iteration, no learned selection
+    flags = (pt.PT_FLAG_NEE | pt.PT_FLAG_PROXY | pt.PT_FLAG_MIS | pt.PT_FLAG_GAMMA | pt.PT_FLAG_TILES |
+             pt.PT_FLAG_SPC | pt.PT_FLAG_LT)
     params = dict(max_depth=cfg["max_depth"], n_light=cfg["n_light"], cand_cap=cfg["cand_cap"], seed=cfg["seed"])
     torch.cuda.set_device(0)
     log(f"upload: {sc['tri'].shape[0]} tris, {W}x{H}")
@@ -75,35 +79,42 @@ def main():
     S.build_subspaces(n_eye=cfg["n_subspaces"], n_spec=cfg["n_spec"])
     acc = torch.zeros(W * H * 3, device="cuda")
     acc2 = torch.zeros_like(acc)
-    stream = torch.cuda.current_stream()
     for k in range(args.warmup):
-        S.render_iteration(acc, acc2, iteration=k, **params)
+        S.render_iteration(acc, acc2, iteration=k, flags=flags, **params)
     torch.cuda.synchronize()
     log("warmup done")
     t0 = time.perf_counter()
     for k in range(args.steps):
-        S.render_iteration(acc, acc2, iteration=args.warmup + k, **params)
+        S.render_iteration(acc, acc2, iteration=args.warmup + k, flags=flags, **params)
+        if k % 16 == 15:
+            log(f"step {k + 1}/{args.steps}")
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     log(f"timed {args.steps} steps in {dt:.3f} s")
-    # one iteration with counters for ray totals and traversal work, one with extension timing
+    # one iteration with traversal counters, then timed ones (HIP events recorded on the stream the
+    # kernels are launched on, inside the library)
     it = args.warmup + args.steps
-    st = S.render_iteration(acc, acc2, stats=True, iteration=it, **params)
-    stc = S.render_iteration(acc, acc2, stats=True, iteration=it + 1,
-                             flags=pt.PT_FLAG_NEE | pt.PT_FLAG_PROXY | pt.PT_FLAG_COUNT, **params)
-    times = []
-    for j in range(4):
-        stt = S.render_iteration(acc, acc2, stats=True, iteration=it + 2 + j,
-                                 flags=pt.PT_FLAG_NEE | pt.PT_FLAG_PROXY | pt.PT_FLAG_TIMING, **params)
-        times.append(stt["ms_extend"])
-    ms_ext = float(np.mean(times))
+    stc = S.render_iteration(acc, acc2, stats=True, iteration=it, flags=flags | pt.PT_FLAG_COUNT, **params)
+    tim = [S.render_iteration(acc, acc2, stats=True, iteration=it + 1 + j, flags=flags | pt.PT_FLAG_TIMING, **params)
+           for j in range(4)]
+    ms_ext = float(np.mean([t["ms_extend"] for t in tim]))
+    ms_a = float(np.mean([t["ms_recip_stage_a"] for t in tim]))
+    ms_rec = float(np.mean([t["ms_recip"] for t in tim]))
+    st = tim[-1]
     rays = st["rays_extend_eye"] + st["rays_extend_light"] + st["rays_shadow"] + st["rays_proxy"] + st["rays_recip"]
-    # algorithmic bytes of the eye extension launches: every visited 128-byte node, every tested
-    # 48-byte triangle, the ray (32 B) and queue index (4 B) read, the hit (16 B) written
-    eye_rays = stc["rays_extend_eye"]
-    traffic_alg = stc["node_visits"] * 128 + stc["tri_tests"] * 48 + eye_rays * (32 + 4 + 16)
     n_launch = params["max_depth"]
-    achieved = (traffic_alg / n_launch) / (ms_ext / n_launch * 1e-3) / 1e9
+    # algorithmic bytes: every visited 128-byte node, every tested 48-byte triangle record; eye
+    # extension also reads the ray (32 B) and queue index (4 B) and writes the hit (16 B); a chain
+    # sample reads its 80-byte candidate record once per wavefront step (1/64 per sample)
+    ext_bytes = stc["node_visits"] * 128 + stc["tri_tests"] * 48 + stc["rays_extend_eye"] * (32 + 4 + 16)
+    a_bytes = stc["node_visits_stage_a"] * 128 + stc["tri_tests_stage_a"] * 48 + stc["n_samples_stage_a"] * 80 / 64
+    cands = [
+        {"kernel": "k_extend (eye closest hit)", "ms_per_step": ms_ext, "launches": n_launch, "bytes": ext_bytes},
+        {"kernel": "k_recip (reciprocal chains, stage A)", "ms_per_step": ms_a, "launches": 1, "bytes": a_bytes},
+    ]
+    dom = max(cands, key=lambda c: c["ms_per_step"])
+    per_launch_s = dom["ms_per_step"] / dom["launches"] * 1e-3
+    achieved = dom["bytes"] / dom["launches"] / per_launch_s / 1e9 if per_launch_s > 0 else 0.0
     value = W * H * args.steps / dt
     out = {
         "metric": "full-path samples/s",
@@ -118,20 +129,23 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "projector caustic (config 1): 512x512, 8,206 tris, depth 12, "
-                               "M=500,000 light sub-paths, 20,000 expected candidates, plain method",
+        "config": {"workload": f"projector caustic (config 1): {W}x{H}, {sc['tri'].shape[0]:,} tris, depth "
+                               f"{params['max_depth']}, M={params['n_light']:,} light sub-paths, "
+                               f"{params['cand_cap']:,} expected candidates; plain method (PT, NEE, probabilistic "
+                               f"connections, light tracing, proxy connections with variance-aware MIS, Gamma, tiles)",
                    "spp_per_step": 1, "max_depth": params["max_depth"], "n_light": params["n_light"]},
         "mrays_per_s": rays * args.steps / dt / 1e6,
         "rays_per_step": rays,
         "ray_breakdown": {k: st[k] for k in ("rays_extend_eye", "rays_extend_light", "rays_shadow", "rays_proxy",
                                              "rays_recip")},
         "proxy": {k: st[k] for k in ("n_cand", "n_kept", "n_recip_samples", "n_recip_truncated",
-                                     "n_proxy_attempts", "n_proxy_valid", "n_nan")},
-        "roofline": {"kernel": "k_extend (eye closest hit)", "bound": "hbm", "achieved": achieved,
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "bytes_per_step": traffic_alg, "ms_per_step": ms_ext,
-                     "nodes_per_ray": stc["node_visits"] / max(eye_rays, 1),
-                     "tris_per_ray": stc["tri_tests"] / max(eye_rays, 1)},
+                                     "n_proxy_attempts", "n_proxy_valid", "n_pool", "n_connections", "n_lt_splats",
+                                     "n_nan", "chain_len_max")},
+        "ms_breakdown": {"eye_extension": ms_ext, "reciprocal_block": ms_rec, "reciprocal_stage_a": ms_a},
+        "roofline": {"kernel": dom["kernel"], "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "bytes_per_launch": dom["bytes"] / dom["launches"],
+                     "ms_per_launch": dom["ms_per_step"] / dom["launches"]},
     }
     if not args.no_cpu:
         log("cpu baseline (oracle)")

@@ -138,6 +138,10 @@ typedef struct {
     double ms_extend;                /* summed duration of the extension launches (PT_FLAG_TIMING) */
     double n_extend_launches;
     double n_pool, n_connections, n_lt_splats;   /* light vertices in the pool; connections and splats made */
+    double ms_recip, ms_recip_stage_a;  /* reciprocal block (pilot to last round) and its first chain
+                                           kernel, HIP events on the stream (PT_FLAG_TIMING) */
+    double node_visits_recip, tri_tests_recip;   /* traversal work of the pilot and the chain rounds */
+    double node_visits_stage_a, tri_tests_stage_a, n_samples_stage_a;   /* the first chain kernel's */
     double chain_len_hist[24];       /* reciprocal chains by samples used: bin b counts [2^b, 2^(b+1)) */
     double chain_len_max;            /* longest chain of the iteration (samples) */
 } pt_iter_stats;

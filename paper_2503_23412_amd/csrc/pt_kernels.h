@@ -363,6 +363,7 @@ struct Ctx {
     int *stk;        // this thread's column of the workgroup's LDS stack
     uint32_t rays;
     int stride;      // threads per workgroup = distance between a thread's stack entries
+    uint32_t visits = 0, tests = 0;   // BVH nodes visited and triangles tested (traffic accounting)
 };
 
 __device__ __forceinline__ bool occluded(Ctx &C, float3 a, int ta, float3 b, int tb)
@@ -371,12 +372,20 @@ __device__ __forceinline__ bool occluded(Ctx &C, float3 a, int ta, float3 b, int
     const float dist = sqrtf(dot3(d, d));
     Hit h;
     C.rays++;
-    return traverse<true, false>(C.S, a, d * (1.0f / dist), C.S.tmin, dist * 0.9999f, ta, tb, C.stk, C.stride, h);
+    return traverse<true, true>(C.S, a, d * (1.0f / dist), C.S.tmin, dist * 0.9999f, ta, tb, C.stk, C.stride, h,
+                                &C.visits, &C.tests);
 }
 __device__ __forceinline__ bool closest(Ctx &C, float3 o, float3 d, int ign, Hit &h)
 {
     C.rays++;
-    return traverse<false, false>(C.S, o, d, C.S.tmin, 3.0e38f, ign, -1, C.stk, C.stride, h);
+    return traverse<false, true>(C.S, o, d, C.S.tmin, 3.0e38f, ign, -1, C.stk, C.stride, h, &C.visits, &C.tests);
+}
+// a kernel's traversal work, one atomic per wavefront
+__device__ __forceinline__ void count_traversal(const Ctx &C, unsigned long long *cnt, int cv = C_VISITS_R,
+                                                int ct = C_TESTS_R)
+{
+    wave_count(cnt + cv, C.visits);
+    wave_count(cnt + ct, C.tests);
 }
 // cosine direction at y_{s-1}: on a dielectric each side with probability 1/2, else the front
 __device__ __forceinline__ float3 spec_start(const MatDev &m, float3 n, Rng &r, float &side_p)
@@ -570,6 +579,7 @@ __global__ void __launch_bounds__(64 * RW) k_pilot(SceneDev S, Cand *cand, const
         }
     }
     wave_count(cnt + C_RAYS_RECIP, C.rays);
+    count_traversal(C, cnt);
 }
 
 // B_j = max(pilot max, bucket running max) (Appendix E's B = max f/q, per (class, u) bucket as in
@@ -738,7 +748,9 @@ __global__ void __launch_bounds__(64 * RW) k_recip(SceneDev S, Cand *cand, const
         }
     }
     wave_count(cnt + C_RECIP_SAMPLES, lane == 0 ? ns : 0u);
+    wave_count(cnt + C_SAMPLES_A, lane == 0 ? ns : 0u);
     wave_count(cnt + C_RAYS_RECIP, C.rays);
+    count_traversal(C, cnt, C_VISITS_A, C_TESTS_A);
 }
 
 // samples per chain in round r for n running chains: doubling from 4096, within the buffer
@@ -770,6 +782,7 @@ __global__ void __launch_bounds__(WG) k_chain_gen(SceneDev S, const Cand *__rest
         }
     }
     wave_count(cnt + C_RAYS_RECIP, C.rays);
+    count_traversal(C, cnt);
 }
 
 // round r, part 2: one wavefront per running chain consumes its block in order; chains that
@@ -929,13 +942,15 @@ struct EyeParams {
 __device__ __forceinline__ float proxy_ksel(const SubDev &D, const EyeParams &P, const unsigned long long *cnt, int T,
                                             int S, float c)
 {
-    const float ncand = (float)cnt[C_NCAND], nk = (float)cnt[C_NFINAL];
-    if (!(nk > 0.0f)) return 0.0f;
+    // frozen inputs only (the previous iteration's counts), so that the weight of a proxy
+    // sample does not depend on the light paths that produced it
+    const float ncand = D.prev[0], nk = D.prev[1];
+    if (!(nk > 0.0f) || !(ncand > 0.0f)) return 0.0f;
     const float pi_inc = fminf(1.0f, (float)P.cand_cap / ncand);
     float ps;
     if (P.gamma_on) {
-        const int cs = D.s_count[S];
-        ps = cs > 0 ? sel_prob(D, T, S) / (float)cs : 0.0f;
+        const int cs = D.s_count_prev[S];
+        ps = cs > 0 ? sel_prob_frozen(D, T, S) / (float)cs : 0.0f;
     } else {
         ps = 1.0f / nk;
     }

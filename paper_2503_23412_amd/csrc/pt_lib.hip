@@ -81,6 +81,8 @@ struct pt_scene {
     float *al_prob = nullptr, *row_sum = nullptr, *gamma_acc = nullptr, *gamma_frz = nullptr;
     int *al_idx = nullptr, *al_scratch = nullptr;
     float *rstat_acc = nullptr, *rstat_frz = nullptr, *tile_proxy = nullptr, *tile_total = nullptr;
+    float *prev = nullptr, *row_tot = nullptr;
+    int *s_count_prev = nullptr;
     // learned selection: parameters (FP32 master, BF16 copy, gradient, Adam moments) and
     // activations for max(npix, MLP_CAP) rows
     int mlp_nout = 0, mlp_rows = 0, mlp_np = 0;
@@ -335,6 +337,8 @@ extern "C" pt_status pt_build_subspaces(pt_scene *s, const pt_subspace_params *p
         AL(s->al_prob, (size_t)ne * ns); AL(s->al_idx, (size_t)ne * ns); AL(s->al_scratch, (size_t)2 * ne * ns);
         AL(s->row_sum, ne); AL(s->gamma_acc, (size_t)ne * ns); AL(s->gamma_frz, (size_t)ne * ns);
         AL(s->rstat_acc, (size_t)30 * ns); AL(s->rstat_frz, (size_t)30 * ns);
+        AL(s->s_count_prev, ns); AL(s->row_tot, ne);
+        if (!s->prev) AL(s->prev, 4);
         s->tiles_x = (s->W + s->tile - 1) / s->tile;
         s->n_tiles = s->tiles_x * ((s->H + s->tile - 1) / s->tile);
         if (!s->tile_proxy) { AL(s->tile_proxy, s->n_tiles); AL(s->tile_total, s->n_tiles); }
@@ -386,6 +390,8 @@ extern "C" pt_status pt_build_subspaces(pt_scene *s, const pt_subspace_params *p
     k_fill<<<1, 16, 0, st>>>(s->runmax, 0.0f, 16);
     k_fill_i<<<blocks(ns, 256), 256, 0, st>>>(s->s_count, 0, (size_t)ns);
     k_fill_i<<<1, 64, 0, st>>>(s->n_ne, 0, 1);
+    k_fill_i<<<blocks(ns, 256), 256, 0, st>>>(s->s_count_prev, 0, (size_t)ns);
+    k_fill<<<1, 64, 0, st>>>(s->prev, 0.0f, 4);
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(st));
     s->subspaces_ready = true;
@@ -570,8 +576,10 @@ pt_status enqueue_iteration(pt_scene *s, const pt_iter_params *p, float *acc, fl
     const bool proxy = (p->flags & PT_FLAG_PROXY) != 0;
     const bool count = (p->flags & PT_FLAG_COUNT) != 0;
     const bool timing = (p->flags & PT_FLAG_TIMING) != 0;
-    if (timing && s->ev.size() < 2 * (size_t)p->max_depth) {
-        while (s->ev.size() < 2 * (size_t)p->max_depth) {
+    // events: two per eye extension launch, then four around the reciprocal block
+    const size_t n_ev = 2 * (size_t)p->max_depth + 4;
+    if (timing && s->ev.size() < n_ev) {
+        while (s->ev.size() < n_ev) {
             hipEvent_t e;
             HIPCHK(hipEventCreate(&e));
             s->ev.push_back(e);
@@ -589,6 +597,7 @@ pt_status enqueue_iteration(pt_scene *s, const pt_iter_params *p, float *acc, fl
         // statistics of earlier iterations only: frozen copies for this iteration
         k_copy<<<blocks((long)ne * ns, 256), 256, 0, stream>>>(s->gamma_acc, s->gamma_frz, (size_t)ne * ns);
         k_copy<<<blocks(30L * ns, 256), 256, 0, stream>>>(s->rstat_acc, s->rstat_frz, (size_t)30 * ns);
+        k_row_tot<<<blocks(ne, 256), 256, 0, stream>>>(s->gamma_frz, ne, ns, s->row_tot);
     }
     const bool conn = (p->flags & PT_FLAG_SPC) != 0, ltr = (p->flags & PT_FLAG_LT) != 0;
     // light sub-paths: y_0 .. y_{lmax-1}; connections and light tracing use every vertex a path
@@ -613,13 +622,17 @@ pt_status enqueue_iteration(pt_scene *s, const pt_iter_params *p, float *acc, fl
             k_candidates<<<blocks(M, 256), 256, 0, stream>>>(L, p->u_max, s->cand, s->cnt);
             const int maxc = 4 * M;
             k_keep<<<blocks(maxc, 256), 256, 0, stream>>>(p->cand_cap, p->seed, s->kept, maxc, s->cnt);
+            const size_t e0 = 2 * (size_t)p->max_depth;
+            if (timing) HIPCHK(hipEventRecord(s->ev[e0], stream));
             k_pilot<<<blocks(maxc, RW), 64 * RW, 0, stream>>>(S, s->cand, s->kept, p->pilot, p->seed, s->runmax,
                                                              s->cnt);
             k_roulette<<<blocks(maxc, 256), 256, 0, stream>>>(s->cand, s->kept, s->final_, s->runmax, S.em_area,
                                                               p->recip_repeats, p->cost_cap, p->seed, s->cnt);
             const uint32_t n1 = (uint32_t)std::max(64.0f, p->cost_cap / (float)p->recip_repeats);
+            if (timing) HIPCHK(hipEventRecord(s->ev[e0 + 1], stream));
             k_recip<<<blocks((long)maxc * p->recip_repeats, RW), 64 * RW, 0, stream>>>(
                 S, s->cand, s->final_, p->recip_repeats, p->seed, n1, 1024u, s->runmax, s->chq[0], s->cnt);
+            if (timing) HIPCHK(hipEventRecord(s->ev[e0 + 2], stream));
             for (int r = 0; r < CHAIN_ROUNDS; ++r) {
                 const int in = r & 1, out = in ^ 1;
                 k_set_counter<<<1, 1, 0, stream>>>(s->cnt, C_LONGQ0 + out, 0ull);
@@ -629,6 +642,7 @@ pt_status enqueue_iteration(pt_scene *s, const pt_iter_params *p, float *acc, fl
                                                               C_LONGQ0 + out, r, r == CHAIN_ROUNDS - 1 ? 1 : 0,
                                                               p->seed, s->chbuf, s->runmax, s->cnt);
             }
+            if (timing) HIPCHK(hipEventRecord(s->ev[e0 + 3], stream));
             if (labels) {
                 SubDev D0{};
                 D0.spec_c = s->spec_c; D0.n_spec = ns;
@@ -667,6 +681,7 @@ pt_status enqueue_iteration(pt_scene *s, const pt_iter_params *p, float *acc, fl
         D.s_count = s->s_count; D.s_off = s->s_off; D.s_list = s->s_list; D.nonempty = s->nonempty; D.n_nonempty = s->n_ne;
         D.al_prob = s->al_prob; D.al_idx = s->al_idx; D.row_sum = s->row_sum; D.gamma = s->gamma_frz;
         D.defensive = p->defensive; D.rstat = s->rstat_frz;
+        D.prev = s->prev; D.s_count_prev = s->s_count_prev; D.row_tot = s->row_tot;
         D.tile_proxy = s->tile_proxy; D.tile_total = s->tile_total; D.tile = s->tile; D.tiles_x = s->tiles_x;
         D.tile_thr = p->tile_threshold; D.tile_low = p->tile_low_prob;
     }
@@ -706,6 +721,8 @@ pt_status enqueue_iteration(pt_scene *s, const pt_iter_params *p, float *acc, fl
         mlp_backward(s, s->MT.label, s->MT.weight, stream);
         mlp_adam(s, p->mlp_lr, stream);
     }
+    if (labels && s->prev)
+        k_prev_store<<<blocks(ns, 256), 256, 0, stream>>>(s->cnt, s->s_count, s->n_ne, ns, s->prev, s->s_count_prev);
     k_accumulate<<<blocks(np, 256), 256, 0, stream>>>(E.frame, acc, acc2, np, s->W, s->tile, s->tiles_x,
                                                       tiles ? s->tile_total : nullptr, s->cnt);
     HIPCHK(hipGetLastError());
@@ -749,7 +766,20 @@ extern "C" pt_status pt_render_iteration(pt_scene *s, const pt_iter_params *p, f
             }
             stats->ms_extend = ms;
             stats->n_extend_launches = p->max_depth;
+            if ((p->flags & PT_FLAG_PROXY) && std::min(p->max_depth - 1, PT_LMAX) >= 2) {
+                const size_t e0 = 2 * (size_t)p->max_depth;
+                float a = 0.0f, b = 0.0f;
+                HIPCHK(hipEventElapsedTime(&a, s->ev[e0], s->ev[e0 + 3]));
+                HIPCHK(hipEventElapsedTime(&b, s->ev[e0 + 1], s->ev[e0 + 2]));
+                stats->ms_recip = a;
+                stats->ms_recip_stage_a = b;
+            }
         }
+        stats->node_visits_recip = (double)c[C_VISITS_R];
+        stats->tri_tests_recip = (double)c[C_TESTS_R];
+        stats->node_visits_stage_a = (double)c[C_VISITS_A];
+        stats->tri_tests_stage_a = (double)c[C_TESTS_A];
+        stats->n_samples_stage_a = (double)c[C_SAMPLES_A];
         stats->n_pool = (double)c[C_POOL];
         stats->n_connections = (double)c[C_SPC];
         stats->n_lt_splats = (double)c[C_LT];

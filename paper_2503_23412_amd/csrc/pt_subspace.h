@@ -23,6 +23,12 @@ struct SubDev {
     float defensive;
     // frozen reciprocal statistics per (class, u, S): sum R, sum R^2, count
     const float *rstat;      // [10 * n_spec * 3]
+    // the previous iteration's candidate counts (n_cand, n_final, non-empty subspaces), its
+    // per-subspace counts and the frozen Gamma row totals: the MIS surrogate's inputs, none of
+    // which depends on this iteration's light paths
+    const float *prev;       // [3]
+    const int *s_count_prev; // [n_spec]
+    const float *row_tot;    // [n_eye]
     // tiles
     const float *tile_proxy, *tile_total;
     int tile, tiles_x;
@@ -179,6 +185,35 @@ __device__ __forceinline__ float sel_prob(const SubDev &D, int T, int S)
     return rs > 0.0f ? (1.0f - D.defensive) * D.gamma[(size_t)T * D.n_spec + S] / rs + D.defensive / ne : 1.0f / ne;
 }
 
+// selection probability of S from T under the frozen Gamma row (defensive mixture over the
+// previous iteration's non-empty subspaces): the surrogate the MIS weights use
+__device__ __forceinline__ float sel_prob_frozen(const SubDev &D, int T, int S)
+{
+    const float ne = fmaxf(D.prev[2], 1.0f);
+    const float rt = D.row_tot[T];
+    return rt > 0.0f ? (1.0f - D.defensive) * D.gamma[(size_t)T * D.n_spec + S] / rt + D.defensive / ne : 1.0f / ne;
+}
+__global__ void k_row_tot(const float *gamma, int n_eye, int n_spec, float *row_tot)
+{
+    const int T = blockIdx.x * blockDim.x + threadIdx.x;
+    if (T >= n_eye) return;
+    float a = 0.0f;
+    for (int j = 0; j < n_spec; ++j) a += gamma[(size_t)T * n_spec + j];
+    row_tot[T] = a;
+}
+// end of an iteration: its counts become the next iteration's frozen inputs
+__global__ void k_prev_store(const unsigned long long *cnt, const int *s_count, const int *n_ne, int n_spec,
+                             float *prev, int *s_count_prev)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n_spec) s_count_prev[i] = s_count[i];
+    if (i == 0) {
+        prev[0] = (float)cnt[C_NCAND];
+        prev[1] = (float)cnt[C_NFINAL];
+        prev[2] = cnt[C_NFINAL] > 0 ? (float)*n_ne : 0.0f;
+    }
+}
+
 // reciprocal statistics of the final candidates (accumulated for later iterations)
 __global__ void k_rstat(const Cand *cand, const uint32_t *final_, const unsigned long long *cnt, int repeats, int n_spec,
                         float *rstat_acc)
@@ -188,14 +223,16 @@ __global__ void k_rstat(const Cand *cand, const uint32_t *final_, const unsigned
     const Cand &c = cand[final_[i]];
     const float R = c.recip_sum / (float)repeats;
     const int b = ((c.cls_u >> 8) * 5 + (c.cls_u & 0xFF)) * n_spec + c.spec_sub;
+    // the second moment of the unbiased factor R 1{kept} / rho is E[R^2] / rho
     unsafeAtomicAdd(rstat_acc + 3 * b + 0, R);
-    unsafeAtomicAdd(rstat_acc + 3 * b + 1, R * R);
+    unsafeAtomicAdd(rstat_acc + 3 * b + 1, R * R / fmaxf(c.rho, 1e-6f));
     unsafeAtomicAdd(rstat_acc + 3 * b + 2, 1.0f);
 }
 
 // Surrogate of the proxy strategy's density factor for MIS (Section 5.4, equ:MIS_1 with
-// E[1/p~^2] p = (1 + V_rel) / p): K' P^ / (1 + V_rel), with P^ = 1 / mean R and V_rel =
-// Var R / mean^2 of the (class, u, S) bucket from earlier iterations, K' = M pi_inc c pi_sel.
+// E[1/p~^2] p = (1 + V_rel) / p): K' P^ / (1 + V_rel), with P^ = 1 / mean R and V_rel the
+// relative variance of R 1{kept} / rho (second moment E[R^2 / rho]) in the (class, u, S) bucket
+// from earlier iterations, K' = M pi_inc c pi_sel.
 __device__ __forceinline__ float proxy_mis_factor(const SubDev &D, int cls, int u, int S, float k_sel)
 {
     const int b = (cls * 5 + u) * D.n_spec + S;
