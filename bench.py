@@ -56,6 +56,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=4)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--config", type=int, default=1)
+    ap.add_argument("--copy-mib", type=int, default=0,
+                    help="after the run, one device-to-device copy of this many MiB: the reference kernel of "
+                         "known size for scaling hardware byte counters")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (this build has no multi-GPU path)",
@@ -151,6 +154,13 @@ def main():
         log("cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(sc, params)
     S.release()
+    if args.copy_mib > 0:
+        a = torch.empty(args.copy_mib << 18, dtype=torch.float32, device="cuda").fill_(1.0)
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        log(f"reference copy: {args.copy_mib} MiB read, {args.copy_mib} MiB written")
     print(json.dumps(out), flush=True)
 
 

@@ -97,7 +97,8 @@ struct LightBuf {
     float4 *lv;          // [PT_LSTORE * M]: position, w = triangle
     float4 *lt;          // [PT_LSTORE * M]: throughput arriving at the vertex (rgb), w = its forward
                          // area density (the light tracer's density of this vertex given the previous)
-    float *lphi;         // [PT_LSTORE * M]: MIS partial sum of the strategies with fewer light vertices
+    float4 *lphi;        // [PT_LSTORE * M]: MIS partial sums of the strategies with fewer light vertices:
+                         // x with connections, y without (proxy-class paths), z the emission-hit term alone
     uint8_t *lfl;        // [PT_LSTORE * M]: LV_S, LV_DIRAC
     float4 *lbeta;       // [M]: throughput and solid-angle pdf of the ray in flight
     float2 *lb0;         // [M]: barycentrics of y_0
@@ -242,7 +243,8 @@ struct MisK {
     float kN, kS, kL;   // next-event estimation, connection (kappa), light tracing (M)
 };
 
-// one thread per light path: phi_j for j = 1 .. count - 1
+// one thread per light path: phi_j for j = 1 .. count - 1 (x: every strategy; y: without the
+// connections, the combination of proxy-class paths; z: the emission-hit strategy alone)
 __global__ void k_light_phi(SceneDev S, LightBuf L, MisK K, const float *kappa, unsigned long long *cnt)
 {
     const int pid = blockIdx.x * blockDim.x + threadIdx.x;
@@ -252,13 +254,14 @@ __global__ void k_light_phi(SceneDev S, LightBuf L, MisK K, const float *kappa, 
     const float kS = K.kS * *kappa;
     float3 yp = xyz(L.lv[pid]);
     float3 y = xyz(L.lv[(size_t)L.M + pid]);
+    float phi, phi0, pt;
     {
         const float3 d = y - yp;
         const float d2 = dot3(d, d);
         const float c0 = fabsf(dot3(S.shade[fbits(L.lv[pid].w)].n, d)) * rsqrtf(d2);
-        L.lphi[(size_t)L.M + pid] = c0 / d2 * S.em_area;   // (A_0 + K_0) g_0 / fwd_0, fwd_0 = 1 / A
+        phi = phi0 = pt = c0 / d2 * S.em_area;   // (A_0 + K_0) g_0 / fwd_0, fwd_0 = 1 / A
+        L.lphi[(size_t)L.M + pid] = make_float4(phi, phi0, pt, 0.0f);
     }
-    float phi = L.lphi[(size_t)L.M + pid];
     for (int j = 2; j < nv; ++j) {
         const size_t v1 = (size_t)(j - 1) * L.M + pid;
         const float4 a = L.lv[v1], b = L.lv[(size_t)j * L.M + pid];
@@ -273,9 +276,13 @@ __global__ void k_light_phi(SceneDev S, LightBuf L, MisK K, const float *kappa, 
         const bool dirac1 = (L.lfl[v1] & LV_DIRAC) != 0;
         const bool dirac0 = j - 2 >= 1 ? (L.lfl[(size_t)(j - 2) * L.M + pid] & LV_DIRAC) != 0 : false;
         const float Kp = dirac1 ? 0.0f : (j - 1 == 1 ? K.kN : (dirac0 ? 0.0f : kS));
+        const float Kp0 = (dirac1 || j - 1 != 1) ? 0.0f : K.kN;
         const float fwd = L.lt[v1].w;
-        phi = fwd > 0.0f ? (phi * rho + Kp) * fabsf(dot3(n1, wj)) / (d2 * fwd) : 0.0f;
-        L.lphi[(size_t)j * L.M + pid] = phi;
+        const float gf = fwd > 0.0f ? fabsf(dot3(n1, wj)) / (d2 * fwd) : 0.0f;
+        phi = (phi * rho + Kp) * gf;
+        phi0 = (phi0 * rho + Kp0) * gf;
+        pt = pt * rho * gf;
+        L.lphi[(size_t)j * L.M + pid] = make_float4(phi, phi0, pt, 0.0f);
         yp = y;
         y = xyz(b);
     }
@@ -882,7 +889,8 @@ struct EyeBuf {
     float4 *ro, *rd, *hit, *beta;   // beta.w = solid-angle pdf of the last sampled direction
     uint32_t *info;                 // bits 0..7 depth, 8 previous vertex Dirac, 9..10 phase, 11..14 u
     float4 *mis;                    // x = p(z_d -> y_{s-1}) in area measure, y = T, z = S (bits)
-    float *mis2;                    // eye-side MIS partial of the ray in flight (times its d^2)
+    float2 *mis2;                   // eye-side MIS partials of the ray in flight (times its d^2):
+                                    // x with connections, y without (proxy-class paths)
     uint32_t *q[2];
     ShadowRay *shadow;
     ProxyItem *proxy;
@@ -915,7 +923,7 @@ __global__ void k_camera(SceneDev S, EyeBuf E, uint32_t seed, unsigned long long
     E.ro[p] = make_float4(S.cam.p.x, S.cam.p.y, S.cam.p.z, ibits(-1));
     E.rd[p] = make_float4(d.x, d.y, d.z, 3.0e38f);
     E.beta[p] = make_float4(1.f, 1.f, 1.f, camera_pdf(S.cam, d));
-    E.mis2[p] = 0.0f;
+    E.mis2[p] = make_float2(0.0f, 0.0f);
     E.info[p] = 1u << 8;   // camera counts as a Dirac predecessor for the first hit
     E.mis[p] = make_float4(0.f, 0.f, 0.f, 0.f);
     E.q[0][p] = (uint32_t)p;
@@ -981,7 +989,7 @@ __global__ void k_eye_shade(SceneDev S, EyeBuf E, EyeParams P, SubDev D, LightBu
     ShadowRay sr, sr2;
     ProxyItem pi;
     float4 nro, nrd, nbeta, nmis;
-    float nmis2 = 0.0f;
+    float2 nmis2 = make_float2(0.0f, 0.0f);
     uint32_t ninfo = 0;
     const float kS = P.mk.kS * *P.kappa;
     if (i < n) {
@@ -1007,7 +1015,8 @@ __global__ void k_eye_shade(SceneDev S, EyeBuf E, EyeParams P, SubDev D, LightBu
             const float d2 = h.x * h.x;
             const float cos_o = fabsf(dot3(sh.n, wo));
             const float rev_z = bt.w * cos_o / d2;
-            const float e_t = t >= 2 ? E.mis2[pid] / d2 : 0.0f;
+            const float2 m2 = t >= 2 ? E.mis2[pid] : make_float2(0.0f, 0.0f);
+            const float e_t = m2.x / d2, e0_t = m2.y / d2;
             float3 add = f3(0.f, 0.f, 0.f);
             if (m.flags & MF_EMIT) {
                 const bool cls = (ph == 1 && uu >= 1) || ph == 2;
@@ -1022,10 +1031,12 @@ __global__ void k_eye_shade(SceneDev S, EyeBuf E, EyeParams P, SubDev D, LightBu
                             const float J0 = cl / d2;
                             const float Ap = proxy_mis_factor(D, ph == 2 ? 1 : 0, (int)uu, Sl,
                                                               proxy_ksel(D, P, cnt, Tl, Sl, c_pix));
+                            // w = 1 / (1 + C_0 + P_proxy / P_0), C_0 without the connections
                             const float hit = mis.x * bt.w * J0;
-                            const float nee = prev_delta ? 0.0f : mis.x / S.em_area;
                             const float prx = ph == 2 ? Ap / S.em_area : Ap * bt.w * J0;
-                            w = hit / (hit + nee + prx);
+                            const float K1 = prev_delta ? 0.0f : P.mk.kN;
+                            const float C0 = (1.0f / S.em_area) / rev_z * (K1 + e0_t * (cl / PT_PI));
+                            w = hit > 0.0f ? hit / (hit * (1.0f + C0) + prx) : 0.0f;
                         } else if (t >= 2) {
                             // emission hit (s = 0): w = 1 / (1 + C_0), C_0 = fwd(x_0) / rev(x_0) (K_1 + C_1)
                             const float K1 = prev_delta ? 0.0f : P.mk.kN;
@@ -1059,6 +1070,7 @@ __global__ void k_eye_shade(SceneDev S, EyeBuf E, EyeParams P, SubDev D, LightBu
                     pi.wo = make_float4(wo.x, wo.y, wo.z, ibits(t));
                     pi.beta = make_float4(beta.x, beta.y, beta.z, ibits(pid));
                     pi.aux = make_float4(ibits(Tnew), c_pix, 0.f, 0.f);
+                    pi.mis = make_float4(rev_z, e0_t, 0.f, 0.f);
                 }
                 if (P.nee_on && !z_dirac && S.n_em > 0) {
                     const bool cls = (ph == 1 && uu >= 1) || ph == 2;
@@ -1094,7 +1106,11 @@ __global__ void k_eye_shade(SceneDev S, EyeBuf E, EyeParams P, SubDev D, LightBu
                                                                       proxy_ksel(D, P, cnt, Tl, Sv, c_pix));
                                     const float hitp = pz * pb * J0, nee = pz / S.em_area;
                                     const float prx = ph == 2 ? Ap / S.em_area : Ap * pb * J0;
-                                    w = nee / (hitp + nee + prx);
+                                    // w = K_1 / (K_1 + A_1 + C_1 + A_1 P_proxy / P_0), without connections
+                                    const float fwd_z = (cl / PT_PI) * fabsf(dot3(sh.n, wl)) / dist2;
+                                    const float C1 = fwd_z / rev_z *
+                                                     (eye_split_k(P, 0.0f, t, false, prev_delta) + e0_t * bsdf_pdf(m, sh.n, wl, wo));
+                                    w = nee > 0.0f ? P.mk.kN / (P.mk.kN + (hitp + prx) / nee + C1) : 0.0f;
                                 } else {
                                     // s = 1: A_1 = rev(x_0) / fwd(x_0); C_1 = fwd(z) / rev(z) (K + e_t rev-pdf)
                                     const float A1 = pb / pl;
@@ -1140,7 +1156,7 @@ __global__ void k_eye_shade(SceneDev S, EyeBuf E, EyeParams P, SubDev D, LightBu
                             const bool prev_y_dirac = j >= 2 && (L.lfl[v - (uint32_t)L.M] & LV_DIRAC);
                             const float Kj = j == 1 ? P.mk.kN : (prev_y_dirac ? 0.0f : kS);
                             const float rev_y = bsdf_pdf(m, sh.n, wo, wzy) * cy / dd2;
-                            const float As = (L.lphi[v] * bsdf_pdf(my, ny, wyz, wyp) + Kj) * rev_y / lt.w;
+                            const float As = (L.lphi[v].x * bsdf_pdf(my, ny, wyz, wyp) + Kj) * rev_y / lt.w;
                             // eye side: C_s = fwd(z) / rev(z) (K + e_t rev-pdf(z))
                             const float fwd_z = bsdf_pdf(my, ny, wyp, wyz) * cz / dd2;
                             const float c = e_t * bsdf_pdf(m, sh.n, wzy, wo);
@@ -1170,8 +1186,9 @@ __global__ void k_eye_shade(SceneDev S, EyeBuf E, EyeParams P, SubDev D, LightBu
                         ninfo = (uint32_t)t | (bs.delta ? 1u << 8 : 0u) | (ph << 9) | (uu << 11);
                         nmis = make_float4(mis.x, ibits(Tnew), mis.z, 0.f);
                         // e_{t+1} d^2 = (K + e_t rev-pdf(z)) |cos| / rev(z), the light side being z_{t+1}
-                        const float c = e_t * rev_pdf(m, sh.n, bs.wi, wo);
-                        nmis2 = (eye_split_k(P, kS, t, z_dirac, prev_delta) + c) * fabsf(dot3(sh.n, bs.wi)) / rev_z;
+                        const float rp = rev_pdf(m, sh.n, bs.wi, wo), cw = fabsf(dot3(sh.n, bs.wi)) / rev_z;
+                        nmis2.x = (eye_split_k(P, kS, t, z_dirac, prev_delta) + e_t * rp) * cw;
+                        nmis2.y = (eye_split_k(P, 0.0f, t, z_dirac, prev_delta) + e0_t * rp) * cw;
                         if (P.labels_on && ph0 == 1 && uu0 == 0 && ph == 1 && uu == 1) {
                             // this vertex is y_{s-1}: record p(z_d -> y_{s-1}) (area) and its specular
                             // subspace from (position, normal, direction toward the light side)
@@ -1202,8 +1219,11 @@ __global__ void k_eye_shade(SceneDev S, EyeBuf E, EyeParams P, SubDev D, LightBu
 }
 
 // Light tracing: every pool vertex y_j connects to the camera and splats onto its pixel,
-// weighted against the other strategies (w = M / (M + A_k)).
-__global__ void __launch_bounds__(WG) k_lt(SceneDev S, LightBuf L, EyeParams P, float *frame, unsigned long long *cnt)
+// weighted against the other strategies (w = M / (M + A_k)); with the proxy strategy and its MIS,
+// proxy-class paths are weighed against emission hits, NEE and the proxy (w = M / (M + A'_k +
+// B_k P_proxy / P_0), A' without connections, B_k the emission-hit term of A_k).
+__global__ void __launch_bounds__(WG) k_lt(SceneDev S, LightBuf L, EyeParams P, SubDev D, float *frame,
+                                           unsigned long long *cnt)
 {
     __shared__ int stk[PT_STACK * WG];
     const int i = blockIdx.x * WG + threadIdx.x;
@@ -1220,14 +1240,20 @@ __global__ void __launch_bounds__(WG) k_lt(SceneDev S, LightBuf L, EyeParams P, 
         const float dd2 = dot3(dc, dc), dist = sqrtf(dd2);
         const float3 wyc = dc * (1.0f / dist), dir = -wyc;
         const float ct = dot3(dir, cam.f);
-        if (ct > 0.0f && conn_ok(P, light_tail_class(0u, 0u, L.sig[lp], j, P.u_max))) {
+        const uint32_t sg = L.sig[lp];
+        const bool cls = light_tail_class(0u, 0u, sg, j, P.u_max);
+        const bool with_proxy = P.proxy_on && P.mis_on;
+        const bool ok = P.proxy_on ? (with_proxy ? class_ok(P.filter, cls) : (!cls && (P.filter == 0 || P.filter == 2)))
+                                   : class_ok(P.filter, cls);
+        if (ct > 0.0f && ok) {
             const float sx = dot3(dir, cam.r) / ct / (cam.tan_half * cam.aspect);
             const float sy = dot3(dir, cam.u) / ct / cam.tan_half;
             const float fx = (sx + 1.0f) * 0.5f * (float)cam.w, fy = (1.0f - sy) * 0.5f * (float)cam.h;
             if (fx >= 0.0f && fy >= 0.0f && fx < (float)cam.w && fy < (float)cam.h) {
                 const int px = min((int)fx, cam.w - 1), py = min((int)fy, cam.h - 1);
                 const MatDev my = S.mats[S.shade[ty].mat];
-                const float3 wyp = normalize3(xyz(L.lv[v - (uint32_t)L.M]) - y);
+                const float3 yprev = xyz(L.lv[v - (uint32_t)L.M]);
+                const float3 wyp = normalize3(yprev - y);
                 const float3 fy3 = bsdf_f(my, ny, wyc, wyp);
                 const float4 lt = L.lt[v];
                 if (nonzero3(fy3) && lt.w > 0.0f) {
@@ -1235,10 +1261,63 @@ __global__ void __launch_bounds__(WG) k_lt(SceneDev S, LightBuf L, EyeParams P, 
                     const float cy = fabsf(dot3(ny, wyc));
                     const float pw = camera_pdf(cam, dir);
                     const float rev_y = pw * cy / dd2;
+                    const float rho = bsdf_pdf(my, ny, wyc, wyp);
+                    const float4 ph4 = L.lphi[v];
                     const bool prev_y_dirac = j >= 2 && (L.lfl[v - (uint32_t)L.M] & LV_DIRAC);
-                    const float Kj = j == 1 ? P.mk.kN : (prev_y_dirac ? 0.0f : kS);
-                    const float Ak = (L.lphi[v] * bsdf_pdf(my, ny, wyc, wyp) + Kj) * rev_y / lt.w;
-                    const float w = P.mk.kL / (P.mk.kL + Ak);
+                    float w;
+                    if (cls && with_proxy) {
+                        // A'_k and B_k; P_proxy / P_0 from the proxy's surrogate at this path's z_d
+                        const float K0j = j == 1 ? P.mk.kN : 0.0f;
+                        const float Ak = (ph4.y * rho + K0j) * rev_y / lt.w;
+                        const float Bk = ph4.z * rho * rev_y / lt.w;
+                        int m = j;
+                        while (m >= 1 && ((sg >> m) & 1u)) --m;   // z_d: first non-specular vertex from the camera
+                        float BX = 0.0f;
+                        if (m >= 2) {
+                            const bool clsB = !((sg >> 1) & 1u);
+                            const int u = clsB ? m - 2 : m - 1;
+                            const size_t vm = (size_t)m * L.M + lp, vs = (size_t)(m - 1) * L.M + lp;
+                            const float4 zd4 = L.lv[vm], ys4 = L.lv[vs];
+                            const float3 zd = xyz(zd4), ys = xyz(ys4), ys2 = xyz(L.lv[vs - L.M]);
+                            const int tz = fbits(zd4.w), ts = fbits(ys4.w);
+                            const float3 nz = S.shade[tz].n, ns = S.shade[ts].n;
+                            const MatDev mz = S.mats[S.shade[tz].mat];
+                            const float3 eprev = m == j ? cam.p : xyz(L.lv[vm + L.M]);
+                            const float3 wze = normalize3(eprev - zd);
+                            const float3 dzs = ys - zd;
+                            const float dzs2 = dot3(dzs, dzs);
+                            const float3 wzs = dzs * rsqrtf(dzs2);
+                            const float pz = bsdf_pdf(mz, nz, wze, wzs) * fabsf(dot3(ns, wzs)) / dzs2;
+                            if (pz > 0.0f && P.labels_on) {
+                                float f[9];
+                                feat9(S, zd, nz, wze, f);
+                                const int Tl = nearest(D.eye_c, D.n_eye, f);
+                                feat9(S, ys, ns, normalize3(ys2 - ys), f);
+                                const int Sl = nearest(D.spec_c, D.n_spec, f);
+                                const float c_pix = P.tiles_on ? tile_prob(D, py * cam.w + px, cam.w) : 1.0f;
+                                const float Ap = proxy_mis_factor(D, clsB ? 1 : 0, u, Sl, proxy_ksel(D, P, cnt, Tl, Sl, c_pix));
+                                float X;
+                                if (clsB) {
+                                    const float3 y0 = xyz(L.lv[lp]), y1 = xyz(L.lv[(size_t)L.M + lp]), y2 = xyz(L.lv[2 * (size_t)L.M + lp]);
+                                    const int t1 = fbits(L.lv[(size_t)L.M + lp].w), t0 = fbits(L.lv[lp].w);
+                                    const float3 d10 = y0 - y1;
+                                    const float d102 = dot3(d10, d10);
+                                    const float3 w10 = d10 * rsqrtf(d102);
+                                    const float pb = bsdf_pdf(S.mats[S.shade[t1].mat], S.shade[t1].n, normalize3(y2 - y1), w10);
+                                    const float J0 = fabsf(dot3(S.shade[t0].n, w10)) / d102;
+                                    X = pb * J0 > 0.0f ? (Ap / S.em_area) / (pz * pb * J0) : 0.0f;
+                                } else {
+                                    X = Ap / pz;
+                                }
+                                BX = Bk * X;
+                            }
+                        }
+                        w = P.mk.kL / (P.mk.kL + Ak + BX);
+                    } else {
+                        const float Kj = j == 1 ? P.mk.kN : (prev_y_dirac ? 0.0f : kS);
+                        const float Ak = (ph4.x * rho + Kj) * rev_y / lt.w;
+                        w = P.mk.kL / (P.mk.kL + Ak);
+                    }
                     const float3 c = xyz(lt) * fy3 * (pw * cy / dd2 / (float)P.M * w);
                     if (nonzero3(c)) {
                         Hit hh;
@@ -1354,6 +1433,11 @@ __global__ void __launch_bounds__(WG) k_proxy(SceneDev S, EyeBuf E, const Cand *
                 float3 thr = f3(1.f, 1.f, 1.f), term = f3(0.f, 0.f, 0.f);
                 float3 cur = v, wo = -wzv, curn = vn, first_dir = f3(0.f, 0.f, 1.f);
                 int curt = vt;
+                // the path from z_d toward the light, for the light-tracing term of the weight
+                float3 qp[PT_LMAX + 2];
+                int qt[PT_LMAX + 2];
+                int nq = 2;
+                qp[0] = xd; qt[0] = td; qp[1] = v; qt[1] = vt;
                 bool ok = true, last_delta = false;
                 float last_pdf = 0.0f, J0 = 0.0f, pb_y1 = 0.0f;
                 for (int k = 1; k <= u && ok; ++k) {
@@ -1390,7 +1474,9 @@ __global__ void __launch_bounds__(WG) k_proxy(SceneDev S, EyeBuf E, const Cand *
                         pb_y1 = bsdf_pdf(mh, ny, -bs.wi, wl);
                     }
                     cur = y; curt = h.tri; curn = ny; wo = -bs.wi;
+                    qp[nq] = y; qt[nq] = h.tri; ++nq;
                 }
+                if (ok && cls == 1) { qp[nq] = xyz(c.hc); qt[nq] = fbits(c.hc.w); ++nq; }
                 if (ok) {
                     const float pi_inc = fminf(1.0f, (float)P.cand_cap / (float)cnt[C_NCAND]);
                     const float scale = (c.recip_sum / (float)repeats) /
@@ -1414,7 +1500,50 @@ __global__ void __launch_bounds__(WG) k_proxy(SceneDev S, EyeBuf E, const Cand *
                             nee = pz / S.em_area;
                             prx = Ap / S.em_area;
                         }
-                        w = prx > 0.0f ? prx / (hit + nee + prx) : 0.0f;
+                        // light tracing and the eye-side strategies beyond z_d, relative to the
+                        // emission hit: prod over q_0 = z_d .. q_n = y_0 of fwd / rev, times the
+                        // eye-side factor at z_d (light tracing if z_d is the first vertex)
+                        float lt = 0.0f;
+                        const float e0 = it.mis.y;
+                        const float kz = (d == 1 ? P.mk.kL : 0.0f) +
+                                         e0 * rev_pdf(md, shd.n, wzv, xyz(it.wo));
+                        if (kz > 0.0f && it.mis.x > 0.0f) {
+                            float R = 1.0f;
+                            for (int q = 0; q < nq; ++q) {
+                                const float3 yq = qp[q];
+                                // eye-side density of q_q
+                                float rev;
+                                if (q == 0) {
+                                    rev = it.mis.x;
+                                } else {
+                                    const float3 a = qp[q - 1];
+                                    const TriShade &sa = S.shade[qt[q - 1]];
+                                    const float3 wi = normalize3(yq - a);
+                                    const float3 wo2 = q == 1 ? xyz(it.wo) : normalize3(qp[q - 2] - a);
+                                    const float3 dd = yq - a;
+                                    rev = rev_pdf(S.mats[sa.mat], sa.n, wo2, wi) * fabsf(dot3(S.shade[qt[q]].n, wi)) /
+                                          dot3(dd, dd);
+                                }
+                                // light-side density of q_q
+                                float fwd;
+                                if (q == nq - 1) {
+                                    fwd = 1.0f / S.em_area;
+                                } else {
+                                    const float3 b = qp[q + 1];
+                                    const TriShade &sb = S.shade[qt[q + 1]];
+                                    const float3 dd = yq - b;
+                                    const float dd2 = dot3(dd, dd);
+                                    const float3 wq = dd * rsqrtf(dd2);
+                                    float pdir;
+                                    if (q + 1 == nq - 1) pdir = fmaxf(dot3(sb.n, wq), 0.0f) / PT_PI;   // cosine emission
+                                    else pdir = rev_pdf(S.mats[sb.mat], sb.n, normalize3(qp[q + 2] - b), wq);
+                                    fwd = pdir * fabsf(dot3(S.shade[qt[q]].n, wq)) / dd2;
+                                }
+                                R = rev > 0.0f ? R * fwd / rev : 0.0f;
+                            }
+                            lt = hit * R * kz;
+                        }
+                        w = prx > 0.0f ? prx / (hit + lt + nee + prx) : 0.0f;
                     }
                     add = xyz(it.beta) * fz * thr * term * (G * scale * w);
                 }

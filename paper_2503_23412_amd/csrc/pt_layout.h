@@ -94,5 +94,6 @@ struct ProxyItem {
     float4 x;        // position, w = triangle (bits)
     float4 wo;       // direction toward the previous eye vertex, w = segments so far (bits)
     float4 beta;     // eye throughput, w = pixel (bits)
-    float4 aux;      // x = eye subspace T (bits), y = tile attempt probability c
+    float4 aux;      // x = eye subspace T (bits), y = tile attempt probability c, z/w = learned selection
+    float4 mis;      // x = eye-side area density of z_d, y = eye-side MIS partial at z_d (no connections)
 };

@@ -700,7 +700,7 @@ pt_status enqueue_iteration(pt_scene *s, const pt_iter_params *p, float *acc, fl
         k_occluded<<<blocks(2L * np, WG), WG, 0, stream>>>(S, E, t, s->cnt);
     }
     if (ltr && lmax >= 2)
-        k_lt<<<blocks((long)(lmax - 1) * M, WG), WG, 0, stream>>>(S, L, EP, E.frame, s->cnt);
+        k_lt<<<blocks((long)(lmax - 1) * M, WG), WG, 0, stream>>>(S, L, EP, D, E.frame, s->cnt);
     if (conn || ltr) k_kappa_store<<<1, 1, 0, stream>>>(s->kappa, s->cnt);
     StatBuf SB{s->gamma_acc, s->tile_proxy, s->tile_total};
     if (EP.mlp_on) {

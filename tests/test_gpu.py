@@ -261,14 +261,17 @@ def test_candidate_probe_closed_forms(gpu, oracle):
 # ------------------------------------------------------------------------------ config 0 parity
 @pytest.mark.timeout(900)
 def test_zz_config0_parity_with_oracle_reference(gpu):
-    """Config 0 (64 x 64 glass Cornell box, depth 8) vs the stored O1 reference image."""
+    """Config 0 (64 x 64 glass Cornell box, depth 8), every strategy of the method, vs the stored O1
+    reference image."""
     from synth import scenes
     torch, pt = gpu
     ref = np.load(os.path.join(GOLD, "cfg0_o1_ref.npz"))
     N = 4096
     say(f"config 0 parity, {N} spp")
-    m, v, st = _render(gpu, scenes.cornell_glass(64, 64), N, max_light=4096, max_depth=8, n_light=4096,
-                       cand_cap=400)
+    flags = (pt.PT_FLAG_NEE | pt.PT_FLAG_PROXY | pt.PT_FLAG_MIS | pt.PT_FLAG_GAMMA | pt.PT_FLAG_TILES |
+             pt.PT_FLAG_SPC | pt.PT_FLAG_LT)
+    m, v, st = _render(gpu, scenes.cornell_glass(64, 64), N, max_light=4096, subspaces=(64, 64), max_depth=8,
+                       n_light=4096, cand_cap=400, flags=flags)
     mo, vo = ref["mean"], ref["var_mean"]
     z = (m - mo) / np.sqrt(v + vo + 1e-30)
     frac = (np.abs(z) < 4).mean()
