@@ -50,6 +50,7 @@ struct CamDev {
 // class B candidate with a specular run of 4
 #define PT_LMAX 6
 #define PT_LSTORE 16   // light vertices stored per path when light vertices are connected (SPC, LT)
+#define PT_MAX_DEPTH 127   // longest path, in segments
 enum { LV_S = 1, LV_DIRAC = 2 };   // per light vertex flags
 #define PT_STACK 48
 
@@ -70,10 +71,10 @@ static_assert(sizeof(Cand) == 80, "Cand layout");
 
 // Device counters of one iteration (64-bit so that large runs do not wrap).
 enum {
-    C_LIGHT_Q0 = 0,          // light queue counts per vertex index: 0 .. PT_LMAX
-    C_EYE_Q0 = 8,            // eye queue counts per depth: 8 .. 135
-    C_SHD0 = 136,            // shadow-ray queue counts per depth: 136 .. 263
-    C_PROXYQ = 264, C_NCAND, C_NKEPT, C_NFINAL,
+    C_LIGHT_Q0 = 0,          // light queue counts per vertex index: 0 .. PT_LSTORE - 1
+    C_EYE_Q0 = C_LIGHT_Q0 + PT_LSTORE,   // eye queue counts per depth 0 .. PT_MAX_DEPTH
+    C_SHD0 = C_EYE_Q0 + PT_MAX_DEPTH + 1,   // shadow-ray queue counts per depth 0 .. PT_MAX_DEPTH
+    C_PROXYQ = C_SHD0 + PT_MAX_DEPTH + 1, C_NCAND, C_NKEPT, C_NFINAL,
     C_RAYS_EYE, C_RAYS_LIGHT, C_RAYS_SHADOW, C_RAYS_PROXY, C_RAYS_RECIP,
     C_RECIP_SAMPLES, C_RECIP_TRUNC, C_LONGQ0, C_LONGQ1, C_CHAIN_HIST, C_CHAIN_MAX = C_CHAIN_HIST + 24, C_POOL, C_SPC, C_LT, C_PROXY_ATT, C_PROXY_VALID, C_NAN, C_VISITS, C_TESTS, C_VISITS_R, C_TESTS_R, C_VISITS_A, C_TESTS_A, C_SAMPLES_A, C_STACK_OVF,
     C_MLP_N,                 // training samples recorded this iteration
@@ -81,7 +82,10 @@ enum {
     C_MLP_T,                 // Adam steps taken (kept across k_zero)
     C_COUNT
 };
-#define PT_MAX_DEPTH 127
+// a light sub-path has at most PT_LSTORE vertices and an eye path at most PT_MAX_DEPTH segments:
+// every queue count has its own slot
+static_assert(C_EYE_Q0 - C_LIGHT_Q0 >= PT_LSTORE, "light queue counters overlap");
+static_assert(C_SHD0 - C_EYE_Q0 >= PT_MAX_DEPTH + 1 && C_PROXYQ - C_SHD0 >= PT_MAX_DEPTH + 1, "queue counters overlap");
 
 // queued shadow ray: origin + first ignored triangle, direction + tmax, contribution + pixel,
 // second ignored triangle

@@ -144,18 +144,20 @@ def test_bvh_closest_hit_matches_brute_force(gpu, oracle, which):
 
 
 # ------------------------------------------------------------------------------ furnaces
-@pytest.mark.parametrize("proxy", ["pt_nee", "proxy", "connections", "light_tracing", "full"])
+@pytest.mark.parametrize("proxy", ["pt_nee", "proxy", "connections", "light_tracing", "full", "full_depth16"])
 def test_diffuse_furnace(gpu, proxy):
+    """Closed form of the furnace; full_depth16 keeps light sub-paths of 16 vertices, every slot of
+    the light-queue counters (a regression test: those counters once ran into the eye queue's)."""
     from synth import scenes
     torch, pt = gpu
-    a, K = 0.5, 6
+    a, K = 0.5, (16 if proxy == "full_depth16" else 6)
     sc = scenes.furnace(albedo=a, le=1.0, width=16, height=16)
     say(f"diffuse furnace {proxy}")
     flags = {"pt_nee": pt.PT_FLAG_NEE, "proxy": pt.PT_FLAG_NEE | pt.PT_FLAG_PROXY,
              "connections": pt.PT_FLAG_NEE | pt.PT_FLAG_SPC | pt.PT_FLAG_LT,
              "light_tracing": pt.PT_FLAG_NEE | pt.PT_FLAG_LT,
              "full": pt.PT_FLAG_NEE | pt.PT_FLAG_PROXY | pt.PT_FLAG_MIS | pt.PT_FLAG_GAMMA | pt.PT_FLAG_SPC |
-             pt.PT_FLAG_LT}[proxy]
+             pt.PT_FLAG_LT}[proxy.replace("_depth16", "")]
     m, v, st = _render(gpu, sc, 512, max_depth=K, n_light=1024, cand_cap=128, flags=flags)
     expect = (1 - a ** K) / (1 - a)
     z = (m - expect) / np.sqrt(v + 1e-30)
