@@ -75,9 +75,10 @@ pt_status pt_scene_upload(const pt_scene_desc *desc, void *hip_stream, pt_scene 
 pt_status pt_scene_release(pt_scene *s);
 
 /* Subspace construction (Section 3.2, SPCBPT's subspaces; Section 5.5's specular and control
- * subspaces): pre-traces n_pretrace paths and clusters eye first-diffuse vertices and
- * specular light vertices by (position, normal, incident direction) with k-means. Resets
- * the selection matrix Gamma (Section 5.6) to uniform and clears all running statistics.
+ * subspaces): pre-traces n_pretrace paths and clusters eye first-diffuse vertices (T), specular
+ * light vertices (S) and connectable light vertices (S_L) by (position, normal, incident
+ * direction) with k-means. Resets the selection matrices Gamma (Section 5.6) and Q (light-vertex
+ * connections) to uniform and clears all running statistics.
  * Must be called once before pt_render_iteration. */
 typedef struct {
     int32_t n_pretrace;      /* pre-traced samples (eye and light paths each) */
@@ -85,6 +86,7 @@ typedef struct {
     int32_t n_spec;          /* specular subspaces S (<= 4096) */
     int32_t kmeans_iters;    /* Lloyd iterations */
     uint32_t seed;
+    int32_t n_light;         /* light subspaces S_L of the probabilistic connections (<= 4096; 0: n_eye) */
 } pt_subspace_params;
 pt_status pt_build_subspaces(pt_scene *s, const pt_subspace_params *p, void *hip_stream);
 

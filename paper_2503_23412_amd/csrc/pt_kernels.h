@@ -196,28 +196,32 @@ __device__ __forceinline__ bool class_ok(int filter, bool proxy_class)
 }
 
 // ---------------------------------------------------------------------------------- connections
-// Light-vertex connections (Section 3.2's probabilistic connections): every non-Dirac light
-// vertex y_i, i >= 1, of this iteration's M light sub-paths enters one pool; an eye vertex picks
-// one of them uniformly (probability 1/N) and the contribution is divided by M / N. Light
-// tracing splats every pool vertex onto the image.
+// Light-vertex connections (Section 3.2's subspace-based probabilistic connections): every
+// non-Dirac light vertex y_i, i >= 1, of this iteration's M light sub-paths enters one pool,
+// bucketed by its light subspace S_L (nearest centroid of position, normal, direction toward
+// y_{i-1}). An eye vertex z in eye subspace T picks S_L from row T of the selection matrix Q
+// (alias table over the non-empty subspaces, a defensive fraction uniform), then one vertex of
+// that bucket uniformly: sigma = pi(S_L | T) / |S_L|, and the contribution is divided by
+// M sigma. Q is learned like Gamma, from the connections' contributions of earlier iterations.
+// Light tracing splats every pool vertex onto the image.
 //
 // MIS: balance heuristic over every strategy that builds the path. With light vertices
 // x_0..x_{s-1} and eye vertices x_s..x_k (x_k the camera), strategy s has density
 //   P_s = prod_{i<s} fwd_i * prod_{i>=s} rev_i * K_s,
 // fwd_i / rev_i the area densities of x_i from the light / eye side, and K_0 = 1 (emission hit),
-// K_1 = 1 (next-event estimation), K_s = kappa for a connection (2 <= s <= k-1; kappa = M
-// sigma, sigma the selection probability), K_k = M (light tracing); K_s = 0 when x_{s-1} or x_s
-// is Dirac or the strategy is off. Then w_s = K_s / (K_s + A_s + C_s) with
+// K_1 = 1 (next-event estimation), K_s = M sigma(x_{s-1} | x_s) for a connection
+// (2 <= s <= k-1), K_k = M (light tracing); K_s = 0 when x_{s-1} or x_s is Dirac or the strategy
+// is off. Then w_s = K_s / (K_s + A_s + C_s) with
 //   A_s = sum_{s'<s} K_s' prod_{i=s'}^{s-1} rev_i / fwd_i   (recursion A_{s+1} = (A_s + K_s) rev_s / fwd_s)
 //   C_s = sum_{s'>s} K_s' prod_{i=s}^{s'-1} fwd_i / rev_i   (recursion C_s = fwd_s / rev_s (K_{s+1} + C_{s+1})).
 // Every factor that does not depend on the other sub-path is accumulated while tracing: the
 // light side stores phi_j = (A_{j-1} + K_{j-1}) |cos_{j-1}| / (d_{j-1,j}^2 fwd_{j-1}), so that
 // A_j = phi_j rev-pdf(y_j) once the direction leaving y_j is known; the eye side carries the
-// analogous quantity along the path. The weights use kappa from the previous iteration's pool
-// size (any value the strategies share keeps the weights summing to one; one that does not
-// depend on this iteration's light paths keeps them independent of the sample they weigh).
-// Paths of the proxy class get their weights from the proxy combination and none from these
-// connections when the proxy strategy is on.
+// analogous quantity along the path. sigma in the weights comes from the frozen Q and the
+// previous iteration's bucket sizes (any function the strategies share keeps the weights
+// summing to one; one that does not depend on this iteration's light paths keeps them
+// independent of the sample they weigh). Paths of the proxy class are weighed by the proxy
+// combination (emission hit, NEE, light tracing, proxy) and never by a connection.
 
 __global__ void k_pool(LightBuf L, int lmax, unsigned long long *cnt)
 {
@@ -240,18 +244,97 @@ __device__ __forceinline__ float rev_pdf(const MatDev &m, float3 n, float3 wo, f
 }
 
 struct MisK {
-    float kN, kS, kL;   // next-event estimation, connection (kappa), light tracing (M)
+    float kN, kS, kL;   // next-event estimation, connections (on/off), light tracing (M)
 };
+
+// subspace-based selection of the light vertex a connection joins
+struct ConnDev {
+    const float *light_c;      // [n_lsub * FEAT] light subspace centroids
+    const float *eye_c;        // [n_eye * FEAT] eye subspace centroids
+    int n_lsub, n_eye, M;
+    // this iteration: label of every pool vertex (index i * M + path), buckets, alias rows
+    int *lab;
+    int *count, *off, *fill, *list, *nonempty, *n_nonempty;
+    const float *al_prob, *row_sum;
+    const int *al_idx;
+    const float *q;            // [n_eye * n_lsub] Q frozen for this iteration
+    // MIS inputs from earlier iterations only
+    const float *row_tot;      // [n_eye] row totals of the frozen Q
+    const int *count_prev;     // [n_lsub] bucket sizes of the previous iteration
+    const float *ne_prev;      // [1] non-empty light subspaces of the previous iteration
+    float defensive;
+    float *qacc;               // [n_eye * n_lsub] learning accumulator
+};
+__device__ __forceinline__ int conn_label_light(const SceneDev &S, const ConnDev &C, float3 p, float3 n, float3 w)
+{
+    float f[9];
+    feat9(S, p, n, w, f);
+    return nearest(C.light_c, C.n_lsub, f);
+}
+__device__ __forceinline__ int conn_label_eye(const SceneDev &S, const ConnDev &C, float3 p, float3 n, float3 w)
+{
+    float f[9];
+    feat9(S, p, n, w, f);
+    return nearest(C.eye_c, C.n_eye, f);
+}
+// the weights' factor M sigma of a connection joining light vertex label Sl to eye label T,
+// from frozen inputs (the selection probability the previous iteration's buckets would give)
+__device__ __forceinline__ float conn_k(const ConnDev &C, float on, int T, int Sl)
+{
+    if (!(on > 0.0f) || Sl < 0) return 0.0f;
+    const float ne = *C.ne_prev;
+    if (!(ne > 0.0f)) return 0.0f;
+    const int cp = C.count_prev[Sl];
+    if (cp <= 0) return 0.0f;
+    const float rt = C.row_tot[T];
+    const float pi = rt > 0.0f ? (1.0f - C.defensive) * C.q[(size_t)T * C.n_lsub + Sl] / rt + C.defensive / ne : 1.0f / ne;
+    return (float)C.M * pi / (float)cp;
+}
+// this iteration's selection probability of bucket Sl from row T (what the alias row samples)
+__device__ __forceinline__ float conn_sel(const ConnDev &C, int T, int Sl)
+{
+    const int ne = *C.n_nonempty;
+    if (ne <= 0 || C.count[Sl] <= 0) return 0.0f;
+    const float rs = C.row_sum[T];
+    return rs > 0.0f ? (1.0f - C.defensive) * C.q[(size_t)T * C.n_lsub + Sl] / rs + C.defensive / (float)ne
+                     : 1.0f / (float)ne;
+}
+
+// label every pool vertex and count the buckets
+__global__ void k_pool_label(SceneDev S, LightBuf L, ConnDev C, unsigned long long *cnt)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (int)cnt[C_POOL]) return;
+    const uint32_t v = L.pool[i];
+    const float4 y = L.lv[v];
+    const float3 w = normalize3(xyz(L.lv[v - (uint32_t)L.M]) - xyz(y));
+    const int lab = conn_label_light(S, C, xyz(y), S.shade[fbits(y.w)].n, w);
+    C.lab[v] = lab;
+    atomicAdd(C.count + lab, 1);
+}
+__global__ void k_scatter_pool(LightBuf L, ConnDev C, const unsigned long long *cnt)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (int)cnt[C_POOL]) return;
+    const uint32_t v = L.pool[i];
+    C.list[atomicAdd(C.fill + C.lab[v], 1)] = (int)v;
+}
+// end of an iteration: its bucket sizes become the next iteration's frozen inputs
+__global__ void k_conn_prev(ConnDev C, int *count_prev, float *ne_prev)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < C.n_lsub) count_prev[i] = C.count[i];
+    if (i == 0) *ne_prev = (float)*C.n_nonempty;
+}
 
 // one thread per light path: phi_j for j = 1 .. count - 1 (x: every strategy; y: without the
 // connections, the combination of proxy-class paths; z: the emission-hit strategy alone)
-__global__ void k_light_phi(SceneDev S, LightBuf L, MisK K, const float *kappa, unsigned long long *cnt)
+__global__ void k_light_phi(SceneDev S, LightBuf L, MisK K, ConnDev C, unsigned long long *cnt)
 {
     const int pid = blockIdx.x * blockDim.x + threadIdx.x;
     if (pid >= L.M) return;
     const int nv = sig_count(L.sig[pid]);
     if (nv < 2) return;
-    const float kS = K.kS * *kappa;
     float3 yp = xyz(L.lv[pid]);
     float3 y = xyz(L.lv[(size_t)L.M + pid]);
     float phi, phi0, pt;
@@ -275,7 +358,14 @@ __global__ void k_light_phi(SceneDev S, LightBuf L, MisK K, const float *kappa, 
         const float rho = rev_pdf(m1, n1, wj, wp);
         const bool dirac1 = (L.lfl[v1] & LV_DIRAC) != 0;
         const bool dirac0 = j - 2 >= 1 ? (L.lfl[(size_t)(j - 2) * L.M + pid] & LV_DIRAC) != 0 : false;
-        const float Kp = dirac1 ? 0.0f : (j - 1 == 1 ? K.kN : (dirac0 ? 0.0f : kS));
+        // split between x_{j-2} (light end) and x_{j-1} (eye end, its eye subspace taken with the
+        // direction toward x_j)
+        float Kp = 0.0f;
+        if (!dirac1) {
+            if (j - 1 == 1) Kp = K.kN;
+            else if (!dirac0 && K.kS > 0.0f)
+                Kp = conn_k(C, K.kS, conn_label_eye(S, C, y, n1, wj), C.lab[(size_t)(j - 2) * L.M + pid]);
+        }
         const float Kp0 = (dirac1 || j - 1 != 1) ? 0.0f : K.kN;
         const float fwd = L.lt[v1].w;
         const float gf = fwd > 0.0f ? fabsf(dot3(n1, wj)) / (d2 * fwd) : 0.0f;
@@ -285,6 +375,28 @@ __global__ void k_light_phi(SceneDev S, LightBuf L, MisK K, const float *kappa, 
         L.lphi[(size_t)j * L.M + pid] = make_float4(phi, phi0, pt, 0.0f);
         yp = y;
         y = xyz(b);
+    }
+}
+
+// features of pre-traced light vertices y_i, i >= 1, non-Dirac (direction toward y_{i-1}), for
+// the light subspaces; at most `cap` rows
+__global__ void k_feat_light(SceneDev S, LightBuf L, int lmax, float *feat, int cap, unsigned long long *cnt,
+                             int cidx)
+{
+    const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = 1 + (int)(idx / L.M), pid = (int)(idx % L.M);
+    bool in = false;
+    if (j < lmax) {
+        const size_t v = (size_t)j * L.M + pid;
+        in = j < sig_count(L.sig[pid]) && !(L.lfl[v] & LV_DIRAC);
+    }
+    const int slot = wave_push(cnt + cidx, in);
+    if (in && slot < cap) {
+        const size_t v = (size_t)j * L.M + pid;
+        const float4 y = L.lv[v];
+        float f[9];
+        feat9(S, xyz(y), S.shade[fbits(y.w)].n, normalize3(xyz(L.lv[v - L.M]) - xyz(y)), f);
+        for (int k = 0; k < 9; ++k) feat[FEAT * (size_t)slot + k] = f[k];
     }
 }
 
@@ -889,8 +1001,9 @@ struct EyeBuf {
     float4 *ro, *rd, *hit, *beta;   // beta.w = solid-angle pdf of the last sampled direction
     uint32_t *info;                 // bits 0..7 depth, 8 previous vertex Dirac, 9..10 phase, 11..14 u
     float4 *mis;                    // x = p(z_d -> y_{s-1}) in area measure, y = T, z = S (bits)
-    float2 *mis2;                   // eye-side MIS partials of the ray in flight (times its d^2):
-                                    // x with connections, y without (proxy-class paths)
+    float4 *mis2;                   // eye-side MIS partials of the ray in flight (times its d^2):
+                                    // x with connections, y without (proxy-class paths); z = eye
+                                    // subspace of the vertex the ray left (bits)
     uint32_t *q[2];
     ShadowRay *shadow;
     ProxyItem *proxy;
@@ -923,7 +1036,7 @@ __global__ void k_camera(SceneDev S, EyeBuf E, uint32_t seed, unsigned long long
     E.ro[p] = make_float4(S.cam.p.x, S.cam.p.y, S.cam.p.z, ibits(-1));
     E.rd[p] = make_float4(d.x, d.y, d.z, 3.0e38f);
     E.beta[p] = make_float4(1.f, 1.f, 1.f, camera_pdf(S.cam, d));
-    E.mis2[p] = make_float2(0.0f, 0.0f);
+    E.mis2[p] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
     E.info[p] = 1u << 8;   // camera counts as a Dirac predecessor for the first hit
     E.mis[p] = make_float4(0.f, 0.f, 0.f, 0.f);
     E.q[0][p] = (uint32_t)p;
@@ -941,8 +1054,7 @@ struct EyeParams {
     int mlp_on;      // subspace S chosen by k_mlp_select (learned mixture) before k_proxy
     int tiles_on;
     int M, cand_cap;
-    MisK mk;             // strategy factors of the connection MIS (kS times *kappa)
-    const float *kappa;  // connection selection factor from the previous iteration's pool
+    MisK mk;             // strategy factors of the connection MIS
     int conn_on;         // light-vertex connections
 };
 // k_sel = M pi_inc c pi_sel: the proxy strategy's selection factor for a path whose first
@@ -966,11 +1078,17 @@ __device__ __forceinline__ float proxy_ksel(const SubDev &D, const EyeParams &P,
 }
 
 // eye-side factor K of the split whose light end is z_t and whose eye end is z_{t-1} (z_t not
-// the emitter x_0): light tracing when z_{t-1} is the camera, else a connection
-__device__ __forceinline__ float eye_split_k(const EyeParams &P, float kS, int t, bool z_dirac, bool prev_dirac)
+// the emitter x_0): light tracing when z_{t-1} is the camera, else a connection (z_t labelled as
+// a light vertex with the direction toward its light-side neighbour w_light, z_{t-1} by T_prev);
+// conn = false leaves the connections out (proxy-class paths)
+__device__ __forceinline__ float eye_split(const EyeParams &P, const ConnDev &C, const SceneDev &S, bool conn, int t,
+                                           bool z_dirac, bool prev_dirac, int T_prev, float3 x, float3 n,
+                                           float3 w_light)
 {
     if (z_dirac) return 0.0f;
-    return t == 1 ? P.mk.kL : (prev_dirac ? 0.0f : kS);
+    if (t == 1) return P.mk.kL;
+    if (!conn || prev_dirac || !(P.mk.kS > 0.0f)) return 0.0f;
+    return conn_k(C, P.mk.kS, T_prev, conn_label_light(S, C, x, n, w_light));
 }
 // may a light-vertex connection or splat score a path of this class?
 __device__ __forceinline__ bool conn_ok(const EyeParams &P, bool cls)
@@ -978,7 +1096,8 @@ __device__ __forceinline__ bool conn_ok(const EyeParams &P, bool cls)
     return P.proxy_on ? (!cls && (P.filter == 0 || P.filter == 2)) : class_ok(P.filter, cls);
 }
 
-__global__ void k_eye_shade(SceneDev S, EyeBuf E, EyeParams P, SubDev D, LightBuf L, int t, unsigned long long *cnt)
+__global__ void k_eye_shade(SceneDev S, EyeBuf E, EyeParams P, SubDev D, LightBuf L, ConnDev C, int t,
+                            unsigned long long *cnt)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const int n = (int)cnt[C_EYE_Q0 + t - 1];
@@ -989,9 +1108,8 @@ __global__ void k_eye_shade(SceneDev S, EyeBuf E, EyeParams P, SubDev D, LightBu
     ShadowRay sr, sr2;
     ProxyItem pi;
     float4 nro, nrd, nbeta, nmis;
-    float2 nmis2 = make_float2(0.0f, 0.0f);
+    float4 nmis2 = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
     uint32_t ninfo = 0;
-    const float kS = P.mk.kS * *P.kappa;
     if (i < n) {
         pid = qin[i];
         const float4 h = E.hit[pid];
@@ -1015,8 +1133,9 @@ __global__ void k_eye_shade(SceneDev S, EyeBuf E, EyeParams P, SubDev D, LightBu
             const float d2 = h.x * h.x;
             const float cos_o = fabsf(dot3(sh.n, wo));
             const float rev_z = bt.w * cos_o / d2;
-            const float2 m2 = t >= 2 ? E.mis2[pid] : make_float2(0.0f, 0.0f);
+            const float4 m2 = t >= 2 ? E.mis2[pid] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
             const float e_t = m2.x / d2, e0_t = m2.y / d2;
+            const int T_prev = fbits(m2.z);
             float3 add = f3(0.f, 0.f, 0.f);
             if (m.flags & MF_EMIT) {
                 const bool cls = (ph == 1 && uu >= 1) || ph == 2;
@@ -1109,14 +1228,16 @@ __global__ void k_eye_shade(SceneDev S, EyeBuf E, EyeParams P, SubDev D, LightBu
                                     // w = K_1 / (K_1 + A_1 + C_1 + A_1 P_proxy / P_0), without connections
                                     const float fwd_z = (cl / PT_PI) * fabsf(dot3(sh.n, wl)) / dist2;
                                     const float C1 = fwd_z / rev_z *
-                                                     (eye_split_k(P, 0.0f, t, false, prev_delta) + e0_t * bsdf_pdf(m, sh.n, wl, wo));
+                                                     (eye_split(P, C, S, false, t, false, prev_delta, T_prev, x, sh.n, wl) +
+                                                      e0_t * bsdf_pdf(m, sh.n, wl, wo));
                                     w = nee > 0.0f ? P.mk.kN / (P.mk.kN + (hitp + prx) / nee + C1) : 0.0f;
                                 } else {
                                     // s = 1: A_1 = rev(x_0) / fwd(x_0); C_1 = fwd(z) / rev(z) (K + e_t rev-pdf)
                                     const float A1 = pb / pl;
                                     const float fwd_z = (cl / PT_PI) * fabsf(dot3(sh.n, wl)) / dist2;
                                     const float c = e_t * bsdf_pdf(m, sh.n, wl, wo);
-                                    const float C1 = fwd_z / rev_z * (eye_split_k(P, kS, t, false, prev_delta) + c);
+                                    const float C1 = fwd_z / rev_z *
+                                                     (eye_split(P, C, S, true, t, false, prev_delta, T_prev, x, sh.n, wl) + c);
                                     w = P.mk.kN / (P.mk.kN + A1 + C1);
                                 }
                                 const float3 c = beta * fs * le * (fabsf(dot3(sh.n, wl)) / pl * w);
@@ -1126,19 +1247,26 @@ __global__ void k_eye_shade(SceneDev S, EyeBuf E, EyeParams P, SubDev D, LightBu
                                     sr.d = make_float4(wl.x, wl.y, wl.z, dist * 0.9999f);
                                     sr.c = make_float4(c.x, c.y, c.z, ibits(pid));
                                     sr.ign1 = Lp.tri;
+                                    sr.tag = -1;
                                 }
                             }
                         }
                     }
                 }
-                // connection to one light vertex drawn uniformly from the pool
-                const float uc = rng_f(r);
-                const uint32_t npool = (uint32_t)cnt[C_POOL];
-                if (P.conn_on && !z_dirac && npool > 0 && kS > 0.0f) {
-                    const uint32_t v = L.pool[min((uint32_t)(uc * (float)npool), npool - 1u)];
+                // connection: light subspace from row T of Q, then one vertex of that bucket
+                const float uc = rng_f(r), uc1 = rng_f(r), uc2 = rng_f(r);
+                const int T_z = (P.conn_on && !z_dirac) ? conn_label_eye(S, C, x, sh.n, wo) : 0;
+                const int ne_l = P.conn_on ? *C.n_nonempty : 0;
+                if (P.conn_on && !z_dirac && ne_l > 0 && P.mk.kS > 0.0f) {
+                    const int jl = min((int)(uc * (float)ne_l), ne_l - 1);
+                    const size_t row = (size_t)T_z * C.n_lsub;
+                    const int Sl = C.nonempty[uc1 < C.al_prob[row + jl] ? jl : C.al_idx[row + jl]];
+                    const int cs = C.count[Sl];
+                    const float sel = cs > 0 ? conn_sel(C, T_z, Sl) : 0.0f;
+                    const uint32_t v = (uint32_t)C.list[C.off[Sl] + min((int)(uc2 * (float)cs), max(cs - 1, 0))];
                     const int j = (int)(v / (uint32_t)L.M), lp = (int)(v % (uint32_t)L.M);
                     const uint32_t sg = L.sig[lp];
-                    if (t + j + 1 <= P.K && conn_ok(P, light_tail_class(ph, uu, sg, j, P.u_max))) {
+                    if (sel > 0.0f && t + j + 1 <= P.K && conn_ok(P, light_tail_class(ph, uu, sg, j, P.u_max))) {
                         const float4 yv = L.lv[v];
                         const int ty = fbits(yv.w);
                         const float3 y = xyz(yv), ny = S.shade[ty].n;
@@ -1152,24 +1280,31 @@ __global__ void k_eye_shade(SceneDev S, EyeBuf E, EyeParams P, SubDev D, LightBu
                         if (nonzero3(fz) && nonzero3(fy)) {
                             const float cy = fabsf(dot3(ny, wyz)), cz = fabsf(dot3(sh.n, wzy));
                             const float4 lt = L.lt[v];
-                            // light side: A_s = (phi_j rev-pdf(y_j) + K_j) rev(y_j) / fwd(y_j)
+                            const float Kown = conn_k(C, P.mk.kS, T_z, Sl);
+                            // light side: A_s = (phi_j rev-pdf(y_j) + K_j) rev(y_j) / fwd(y_j); K_j is the
+                            // split before y_j, with y_j's eye subspace taken toward z
                             const bool prev_y_dirac = j >= 2 && (L.lfl[v - (uint32_t)L.M] & LV_DIRAC);
-                            const float Kj = j == 1 ? P.mk.kN : (prev_y_dirac ? 0.0f : kS);
+                            const float Kj = j == 1 ? P.mk.kN
+                                                    : (prev_y_dirac ? 0.0f
+                                                                    : conn_k(C, P.mk.kS, conn_label_eye(S, C, y, ny, wyz),
+                                                                             C.lab[v - (uint32_t)L.M]));
                             const float rev_y = bsdf_pdf(m, sh.n, wo, wzy) * cy / dd2;
                             const float As = (L.lphi[v].x * bsdf_pdf(my, ny, wyz, wyp) + Kj) * rev_y / lt.w;
                             // eye side: C_s = fwd(z) / rev(z) (K + e_t rev-pdf(z))
                             const float fwd_z = bsdf_pdf(my, ny, wyp, wyz) * cz / dd2;
                             const float c = e_t * bsdf_pdf(m, sh.n, wzy, wo);
-                            const float Cs = fwd_z / rev_z * (eye_split_k(P, kS, t, false, prev_delta) + c);
-                            const float w = kS / (kS + As + Cs);
+                            const float Cs = fwd_z / rev_z *
+                                             (eye_split(P, C, S, true, t, false, prev_delta, T_prev, x, sh.n, wzy) + c);
+                            const float w = Kown > 0.0f ? Kown / (Kown + As + Cs) : 0.0f;
                             const float3 cc = beta * fz * fy * xyz(lt) *
-                                              (cy * cz / dd2 * ((float)npool / (float)P.M) * w);
+                                              (cy * cz / dd2 * ((float)cs / ((float)P.M * sel)) * w);
                             if (nonzero3(cc) && lt.w > 0.0f) {
                                 shadow2 = true;
                                 sr2.o = make_float4(x.x, x.y, x.z, ibits(tri));
                                 sr2.d = make_float4(wzy.x, wzy.y, wzy.z, dist * 0.9999f);
                                 sr2.c = make_float4(cc.x, cc.y, cc.z, ibits(pid));
                                 sr2.ign1 = ty;
+                                sr2.tag = (T_z << 12) | Sl;
                             }
                         }
                     }
@@ -1187,8 +1322,9 @@ __global__ void k_eye_shade(SceneDev S, EyeBuf E, EyeParams P, SubDev D, LightBu
                         nmis = make_float4(mis.x, ibits(Tnew), mis.z, 0.f);
                         // e_{t+1} d^2 = (K + e_t rev-pdf(z)) |cos| / rev(z), the light side being z_{t+1}
                         const float rp = rev_pdf(m, sh.n, bs.wi, wo), cw = fabsf(dot3(sh.n, bs.wi)) / rev_z;
-                        nmis2.x = (eye_split_k(P, kS, t, z_dirac, prev_delta) + e_t * rp) * cw;
-                        nmis2.y = (eye_split_k(P, 0.0f, t, z_dirac, prev_delta) + e0_t * rp) * cw;
+                        nmis2.x = (eye_split(P, C, S, true, t, z_dirac, prev_delta, T_prev, x, sh.n, bs.wi) + e_t * rp) * cw;
+                        nmis2.y = (eye_split(P, C, S, false, t, z_dirac, prev_delta, T_prev, x, sh.n, bs.wi) + e0_t * rp) * cw;
+                        nmis2.z = ibits(T_z);
                         if (P.labels_on && ph0 == 1 && uu0 == 0 && ph == 1 && uu == 1) {
                             // this vertex is y_{s-1}: record p(z_d -> y_{s-1}) (area) and its specular
                             // subspace from (position, normal, direction toward the light side)
@@ -1222,7 +1358,7 @@ __global__ void k_eye_shade(SceneDev S, EyeBuf E, EyeParams P, SubDev D, LightBu
 // weighted against the other strategies (w = M / (M + A_k)); with the proxy strategy and its MIS,
 // proxy-class paths are weighed against emission hits, NEE and the proxy (w = M / (M + A'_k +
 // B_k P_proxy / P_0), A' without connections, B_k the emission-hit term of A_k).
-__global__ void __launch_bounds__(WG) k_lt(SceneDev S, LightBuf L, EyeParams P, SubDev D, float *frame,
+__global__ void __launch_bounds__(WG) k_lt(SceneDev S, LightBuf L, EyeParams P, SubDev D, ConnDev C, float *frame,
                                            unsigned long long *cnt)
 {
     __shared__ int stk[PT_STACK * WG];
@@ -1257,7 +1393,6 @@ __global__ void __launch_bounds__(WG) k_lt(SceneDev S, LightBuf L, EyeParams P, 
                 const float3 fy3 = bsdf_f(my, ny, wyc, wyp);
                 const float4 lt = L.lt[v];
                 if (nonzero3(fy3) && lt.w > 0.0f) {
-                    const float kS = P.mk.kS * *P.kappa;
                     const float cy = fabsf(dot3(ny, wyc));
                     const float pw = camera_pdf(cam, dir);
                     const float rev_y = pw * cy / dd2;
@@ -1314,7 +1449,9 @@ __global__ void __launch_bounds__(WG) k_lt(SceneDev S, LightBuf L, EyeParams P, 
                         }
                         w = P.mk.kL / (P.mk.kL + Ak + BX);
                     } else {
-                        const float Kj = j == 1 ? P.mk.kN : (prev_y_dirac ? 0.0f : kS);
+                        float Kj = j == 1 ? P.mk.kN : 0.0f;
+                        if (j >= 2 && !prev_y_dirac && P.mk.kS > 0.0f)
+                            Kj = conn_k(C, P.mk.kS, conn_label_eye(S, C, y, ny, wyc), C.lab[v - (uint32_t)L.M]);
                         const float Ak = (ph4.x * rho + Kj) * rev_y / lt.w;
                         w = P.mk.kL / (P.mk.kL + Ak);
                     }
@@ -1335,7 +1472,8 @@ __global__ void __launch_bounds__(WG) k_lt(SceneDev S, LightBuf L, EyeParams P, 
     wave_count(cnt + C_RAYS_SHADOW, rays);
 }
 
-__global__ void __launch_bounds__(WG) k_occluded(SceneDev S, EyeBuf E, int t, unsigned long long *cnt)
+// shadow rays of NEE and connections; a visible connection's luminance trains Q while learning
+__global__ void __launch_bounds__(WG) k_occluded(SceneDev S, EyeBuf E, ConnDev C, int t, unsigned long long *cnt)
 {
     __shared__ int stk[PT_STACK * WG];
     const int i = blockIdx.x * WG + threadIdx.x;
@@ -1345,8 +1483,11 @@ __global__ void __launch_bounds__(WG) k_occluded(SceneDev S, EyeBuf E, int t, un
         const ShadowRay sr = E.shadow[i];
         Hit h;
         if (!traverse<true, false>(S, xyz(sr.o), xyz(sr.d), S.tmin, sr.d.w, fbits(sr.o.w), sr.ign1, stk + threadIdx.x,
-                                   WG, h))
+                                   WG, h)) {
             atomic_add3(E.frame + 3 * fbits(sr.c.w), xyz(sr.c));
+            if (sr.tag >= 0 && C.qacc && cnt[C_LEARN])
+                unsafeAtomicAdd(C.qacc + (size_t)(sr.tag >> 12) * C.n_lsub + (sr.tag & 0xFFF), lum(xyz(sr.c)));
+        }
     }
     wave_count(cnt + C_RAYS_SHADOW, act ? 1u : 0u);
 }

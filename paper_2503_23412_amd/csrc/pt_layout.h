@@ -91,7 +91,9 @@ static_assert(C_SHD0 - C_EYE_Q0 >= PT_MAX_DEPTH + 1 && C_PROXYQ - C_SHD0 >= PT_M
 // second ignored triangle
 struct ShadowRay {
     float4 o, d, c;
-    int32_t ign1, pad[3];
+    int32_t ign1;
+    int32_t tag;     // connection rays: eye subspace T << 12 | light subspace S_L (learning); else -1
+    int32_t pad[2];
 };
 // proxy work item at an eye path's first diffuse vertex
 struct ProxyItem {

@@ -70,12 +70,17 @@ struct pt_scene {
     uint32_t *kept = nullptr, *final_ = nullptr;
     unsigned long long *cnt = nullptr;
     float *runmax = nullptr;   // [2 * 5] running maxima of f/q per (class, u)
-    float *kappa = nullptr;   // [2]: connection factor of this iteration, previous pool size
+    // subspace-based connections: light subspaces, buckets of the pool, Q (learned, frozen), alias rows
+    int n_lsub = 0;
+    float *light_c = nullptr, *qacc = nullptr, *qfrz = nullptr, *q_alprob = nullptr, *q_rowsum = nullptr,
+          *q_rowtot = nullptr, *lne_prev = nullptr;
+    int *lcount = nullptr, *loff = nullptr, *lfill = nullptr, *lnonempty = nullptr, *ln_ne = nullptr, *llist = nullptr,
+        *plab = nullptr, *q_alidx = nullptr, *q_scratch = nullptr, *lcount_prev = nullptr;
     ChainState *chq[2] = {nullptr, nullptr};   // running reciprocal chains between rounds
     float2 *chbuf = nullptr;                   // (f/q, u) samples of one round
     bool subspaces_ready = false;
     // subspaces, selection and statistics (allocated by pt_build_subspaces)
-    int n_eye = 0, n_spec = 0, tile = 10, tiles_x = 0, n_tiles = 0;
+    int n_eye = 0, n_spec = 0, tile = 10, tiles_x = 0, n_tiles = 0, km_cap = 0;
     float *eye_c = nullptr, *spec_c = nullptr, *km_sum = nullptr, *km_cnt = nullptr, *feat = nullptr;
     int *s_count = nullptr, *s_off = nullptr, *s_fill = nullptr, *s_list = nullptr, *nonempty = nullptr, *n_ne = nullptr;
     float *al_prob = nullptr, *row_sum = nullptr, *gamma_acc = nullptr, *gamma_frz = nullptr;
@@ -229,7 +234,7 @@ extern "C" pt_status pt_scene_upload(const pt_scene_desc *d, void *stream_, pt_s
         AL(s->E.ro, np); AL(s->E.rd, np); AL(s->E.hit, np); AL(s->E.beta, np); AL(s->E.info, np); AL(s->E.mis, np);
         AL(s->E.q[0], np); AL(s->E.q[1], np);
         AL(s->E.shadow, 2 * (size_t)np); AL(s->E.proxy, np); AL(s->E.mis2, np);
-        AL(s->kappa, 2);
+        AL(s->llist, (size_t)PT_LSTORE * M); AL(s->plab, (size_t)PT_LSTORE * M);
         AL(s->E.frame, (size_t)3 * np);
         AL(s->cnt, C_COUNT);
         AL(s->runmax, 16);
@@ -247,7 +252,6 @@ extern "C" pt_status pt_scene_upload(const pt_scene_desc *d, void *stream_, pt_s
         HIPCHK(hipMemcpyAsync(s->em_cdf, emc.data(), emc.size() * sizeof(float), hipMemcpyHostToDevice, stream));
         HIPCHK(hipMemsetAsync(s->E.frame, 0, sizeof(float) * 3 * np, stream));
         HIPCHK(hipMemsetAsync(s->runmax, 0, sizeof(float) * 16, stream));
-        HIPCHK(hipMemsetAsync(s->kappa, 0, sizeof(float) * 2, stream));
         HIPCHK(hipStreamSynchronize(stream));
         SceneDev &S = s->S;
         S.nodes = s->nodes; S.tris = s->tris; S.shade = s->shade; S.mats = s->mats; S.tex = s->tex;
@@ -321,16 +325,36 @@ extern "C" pt_status pt_build_subspaces(pt_scene *s, const pt_subspace_params *p
 {
     if (!s || !p) return set_err(PT_EINVAL, "null argument");
     if (p->n_eye <= 0 || p->n_eye > 4096 || p->n_spec <= 0 || p->n_spec > 4096 || p->n_pretrace < 0 ||
-        p->kmeans_iters < 0 || p->kmeans_iters > 64)
+        p->kmeans_iters < 0 || p->kmeans_iters > 64 || p->n_light < 0 || p->n_light > 4096)
         return set_err(PT_EINVAL, "subspace parameters out of range");
+    const int nl = p->n_light > 0 ? p->n_light : p->n_eye;
     hipStream_t st = (hipStream_t)stream_;
     const int M = s->max_light, np = s->npix;
     const int ne = p->n_eye, ns = p->n_spec;
+    // k-means scratch for the largest clustering
+    const int kmax = std::max(std::max(ne, ns), nl);
+    if (kmax > s->km_cap) {
+        pt_status e;
+        if ((e = s->alloc(s->km_sum, (size_t)kmax * FEAT)) != PT_OK) return e;
+        if ((e = s->alloc(s->km_cnt, (size_t)kmax)) != PT_OK) return e;
+        s->km_cap = kmax;
+    }
+    if (nl != s->n_lsub || ne != s->n_eye || !s->light_c) {
+        pt_status e;
+#define AL(ptr, n) if ((e = s->alloc(ptr, n)) != PT_OK) return e;
+        AL(s->light_c, (size_t)nl * FEAT); AL(s->lcount, nl); AL(s->loff, nl); AL(s->lfill, nl); AL(s->lnonempty, nl);
+        if (!s->ln_ne) { AL(s->ln_ne, 1); AL(s->lne_prev, 1); }
+        AL(s->lcount_prev, nl);
+        AL(s->qacc, (size_t)ne * nl); AL(s->qfrz, (size_t)ne * nl); AL(s->q_alprob, (size_t)ne * nl);
+        AL(s->q_alidx, (size_t)ne * nl); AL(s->q_scratch, (size_t)2 * ne * nl); AL(s->q_rowsum, ne); AL(s->q_rowtot, ne);
+#undef AL
+        s->n_lsub = nl;
+    }
     if (ne != s->n_eye || ns != s->n_spec || !s->eye_c) {
         pt_status e;
 #define AL(ptr, n) if ((e = s->alloc(ptr, n)) != PT_OK) return e;
         AL(s->eye_c, (size_t)ne * FEAT); AL(s->spec_c, (size_t)ns * FEAT);
-        AL(s->km_sum, (size_t)std::max(ne, ns) * FEAT); AL(s->km_cnt, (size_t)std::max(ne, ns));
+
         if (!s->feat) AL(s->feat, (size_t)std::max(np, 4 * M) * FEAT);
         AL(s->s_count, ns); AL(s->s_off, ns); AL(s->s_fill, ns); AL(s->nonempty, ns); AL(s->n_ne, 1);
         if (!s->s_list) AL(s->s_list, (size_t)4 * M);
@@ -358,9 +382,18 @@ extern "C" pt_status pt_build_subspaces(pt_scene *s, const pt_subspace_params *p
                                                         L.hit, s->cnt, C_RAYS_LIGHT);
         k_light_shade<<<blocks(L.M, 256), 256, 0, st>>>(S, L, p->seed, vi, PT_LMAX, s->cnt);
     }
+    unsigned long long c[C_COUNT];
+    // light subspaces: non-Dirac light vertices y_i, i >= 1 (the connection pool's vertices)
+    {
+        const int cap = std::max(np, 4 * M);
+        k_feat_light<<<blocks((long)(PT_LMAX - 1) * L.M, 256), 256, 0, st>>>(S, L, PT_LMAX, s->feat, cap, s->cnt, C_POOL);
+        HIPCHK(hipMemcpyAsync(c, s->cnt, sizeof(c), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        TRY(run_kmeans(s, s->feat, (int)std::min<unsigned long long>(c[C_POOL], (unsigned long long)cap), s->light_c,
+                       nl, p->kmeans_iters, st));
+    }
     k_candidates<<<blocks(L.M, 256), 256, 0, st>>>(L, 4, s->cand, s->cnt);
     k_feat_cands<<<blocks(4L * L.M, 256), 256, 0, st>>>(S, s->cand, s->cnt, s->feat);
-    unsigned long long c[C_COUNT];
     HIPCHK(hipMemcpyAsync(c, s->cnt, sizeof(c), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
     TRY(run_kmeans(s, s->feat, (int)c[C_NCAND], s->spec_c, ns, p->kmeans_iters, st));
@@ -368,14 +401,13 @@ extern "C" pt_status pt_build_subspaces(pt_scene *s, const pt_subspace_params *p
     EyeBuf E = s->E;
     EyeParams EP{};
     EP.seed = p->seed; EP.K = 8; EP.u_max = 4; EP.filter = 3; EP.proxy_on = 1; EP.nee_on = 0;
-    EP.kappa = s->kappa;
     SubDev D{};
     k_zero<<<blocks(C_COUNT, 256), 256, 0, st>>>(s->cnt, C_COUNT);
     k_camera<<<blocks(np, 256), 256, 0, st>>>(S, E, p->seed, s->cnt);
     for (int t = 1; t <= EP.K; ++t) {
         k_extend<false><<<blocks(np, WG), WG, 0, st>>>(S, E.q[(t - 1) & 1], s->cnt, C_EYE_Q0 + t - 1, E.ro, E.rd, E.hit,
                                                        s->cnt, C_RAYS_EYE);
-        k_eye_shade<<<blocks(np, 256), 256, 0, st>>>(S, E, EP, D, L, t, s->cnt);
+        k_eye_shade<<<blocks(np, 256), 256, 0, st>>>(S, E, EP, D, L, ConnDev{}, t, s->cnt);
     }
     k_fill<<<blocks(3L * np, 256), 256, 0, st>>>(E.frame, 0.0f, (size_t)3 * np);
     k_feat_proxy<<<blocks(np, 256), 256, 0, st>>>(S, E.proxy, s->cnt, s->feat);
@@ -392,6 +424,11 @@ extern "C" pt_status pt_build_subspaces(pt_scene *s, const pt_subspace_params *p
     k_fill_i<<<1, 64, 0, st>>>(s->n_ne, 0, 1);
     k_fill_i<<<blocks(ns, 256), 256, 0, st>>>(s->s_count_prev, 0, (size_t)ns);
     k_fill<<<1, 64, 0, st>>>(s->prev, 0.0f, 4);
+    k_fill<<<blocks((long)ne * nl, 256), 256, 0, st>>>(s->qacc, 0.0f, (size_t)ne * nl);
+    k_fill_i<<<blocks(nl, 256), 256, 0, st>>>(s->lcount_prev, 0, (size_t)nl);
+    k_fill_i<<<blocks(nl, 256), 256, 0, st>>>(s->lcount, 0, (size_t)nl);
+    k_fill_i<<<1, 64, 0, st>>>(s->ln_ne, 0, 1);
+    k_fill<<<1, 64, 0, st>>>(s->lne_prev, 0.0f, 1);
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(st));
     s->subspaces_ready = true;
@@ -438,16 +475,6 @@ __global__ void k_sum1(const float *x, int n, float *out)
         __syncthreads();
     }
     if (threadIdx.x == 0) *out = red[0];
-}
-
-// connection factor kappa = M / N from the previous iteration's pool size N (1 before any)
-__global__ void k_kappa(float *kappa, int M)
-{
-    if (threadIdx.x == 0 && blockIdx.x == 0) kappa[0] = kappa[1] > 0.0f ? (float)M / kappa[1] : 1.0f;
-}
-__global__ void k_kappa_store(float *kappa, const unsigned long long *cnt)
-{
-    if (threadIdx.x == 0 && blockIdx.x == 0) kappa[1] = (float)cnt[C_POOL];
 }
 
 // C = A B on MFMA (see k_gemm); ksplit > 1 adds into C with atomics
@@ -612,10 +639,32 @@ pt_status enqueue_iteration(pt_scene *s, const pt_iter_params *p, float *acc, fl
         }
     }
     const MisK mk{(p->flags & PT_FLAG_NEE) ? 1.0f : 0.0f, conn ? 1.0f : 0.0f, ltr ? (float)M : 0.0f};
+    const int nl = s->n_lsub;
+    ConnDev CD{};
+    if (conn) {
+        CD.light_c = s->light_c; CD.eye_c = s->eye_c; CD.n_lsub = nl; CD.n_eye = ne; CD.M = M;
+        CD.lab = s->plab; CD.count = s->lcount; CD.off = s->loff; CD.fill = s->lfill; CD.list = s->llist;
+        CD.nonempty = s->lnonempty; CD.n_nonempty = s->ln_ne;
+        CD.al_prob = s->q_alprob; CD.al_idx = s->q_alidx; CD.row_sum = s->q_rowsum; CD.q = s->qfrz;
+        CD.row_tot = s->q_rowtot; CD.count_prev = s->lcount_prev; CD.ne_prev = s->lne_prev;
+        CD.defensive = p->defensive; CD.qacc = s->qacc;
+        // Q of earlier iterations only
+        k_copy<<<blocks((long)ne * nl, 256), 256, 0, stream>>>(s->qacc, s->qfrz, (size_t)ne * nl);
+        k_row_tot<<<blocks(ne, 256), 256, 0, stream>>>(s->qfrz, ne, nl, s->q_rowtot);
+    }
     if ((conn || ltr) && lmax >= 2) {
-        k_kappa<<<1, 1, 0, stream>>>(s->kappa, M);
         k_pool<<<blocks((long)(lmax - 1) * M, 256), 256, 0, stream>>>(L, lmax, s->cnt);
-        k_light_phi<<<blocks(M, 256), 256, 0, stream>>>(S, L, mk, s->kappa, s->cnt);
+        if (conn) {
+            // bucket the pool by light subspace; alias rows of Q over the non-empty buckets
+            const long maxp = (long)(lmax - 1) * M;
+            k_fill_i<<<blocks(nl, 256), 256, 0, stream>>>(s->lcount, 0, (size_t)nl);
+            k_pool_label<<<blocks(maxp, 256), 256, 0, stream>>>(S, L, CD, s->cnt);
+            k_scan_sub<<<1, 1024, 0, stream>>>(s->lcount, s->loff, s->lfill, s->lnonempty, s->ln_ne, nl);
+            k_scatter_pool<<<blocks(maxp, 256), 256, 0, stream>>>(L, CD, s->cnt);
+            k_alias_rows<<<blocks(ne, 64), 64, 0, stream>>>(s->qfrz, ne, nl, s->lnonempty, s->ln_ne, p->defensive,
+                                                           s->q_alprob, s->q_alidx, s->q_rowsum, s->q_scratch);
+        }
+        k_light_phi<<<blocks(M, 256), 256, 0, stream>>>(S, L, mk, CD, s->cnt);
     }
     if (proxy) {
         if (lmax >= 2) {
@@ -674,7 +723,7 @@ pt_status enqueue_iteration(pt_scene *s, const pt_iter_params *p, float *acc, fl
     EP.mlp_on = mlp && EP.proxy_on;
     EP.tiles_on = tiles;
     EP.M = M; EP.cand_cap = p->cand_cap;
-    EP.mk = mk; EP.kappa = s->kappa; EP.conn_on = conn && lmax >= 2;
+    EP.mk = mk; EP.conn_on = conn && lmax >= 2;
     SubDev D{};
     if (s->n_eye > 0) {
         D.eye_c = s->eye_c; D.spec_c = s->spec_c; D.n_eye = ne; D.n_spec = ns;
@@ -696,12 +745,12 @@ pt_status enqueue_iteration(pt_scene *s, const pt_iter_params *p, float *acc, fl
             k_extend<false><<<blocks(np, WG), WG, 0, stream>>>(S, E.q[(t - 1) & 1], s->cnt, C_EYE_Q0 + t - 1, E.ro, E.rd,
                                                                E.hit, s->cnt, C_RAYS_EYE);
         if (timing) HIPCHK(hipEventRecord(s->ev[2 * (t - 1) + 1], stream));
-        k_eye_shade<<<blocks(np, 256), 256, 0, stream>>>(S, E, EP, D, L, t, s->cnt);
-        k_occluded<<<blocks(2L * np, WG), WG, 0, stream>>>(S, E, t, s->cnt);
+        k_eye_shade<<<blocks(np, 256), 256, 0, stream>>>(S, E, EP, D, L, CD, t, s->cnt);
+        k_occluded<<<blocks(2L * np, WG), WG, 0, stream>>>(S, E, CD, t, s->cnt);
     }
     if (ltr && lmax >= 2)
-        k_lt<<<blocks((long)(lmax - 1) * M, WG), WG, 0, stream>>>(S, L, EP, D, E.frame, s->cnt);
-    if (conn || ltr) k_kappa_store<<<1, 1, 0, stream>>>(s->kappa, s->cnt);
+        k_lt<<<blocks((long)(lmax - 1) * M, WG), WG, 0, stream>>>(S, L, EP, D, CD, E.frame, s->cnt);
+    if (conn && lmax >= 2) k_conn_prev<<<blocks(nl, 256), 256, 0, stream>>>(CD, s->lcount_prev, s->lne_prev);
     StatBuf SB{s->gamma_acc, s->tile_proxy, s->tile_total};
     if (EP.mlp_on) {
         // the network's logits for every queued first diffuse vertex, then S per item

@@ -45,7 +45,7 @@ class SceneDesc(ctypes.Structure):
 
 class SubspaceParams(ctypes.Structure):
     _fields_ = [("n_pretrace", ctypes.c_int32), ("n_eye", ctypes.c_int32), ("n_spec", ctypes.c_int32),
-                ("kmeans_iters", ctypes.c_int32), ("seed", ctypes.c_uint32)]
+                ("kmeans_iters", ctypes.c_int32), ("seed", ctypes.c_uint32), ("n_light", ctypes.c_int32)]
 
 
 class IterParams(ctypes.Structure):
@@ -175,8 +175,8 @@ class Scene:
         except Exception:
             pass
 
-    def build_subspaces(self, n_pretrace=0, n_eye=64, n_spec=64, kmeans_iters=8, seed=0, stream=None):
-        p = SubspaceParams(n_pretrace, n_eye, n_spec, kmeans_iters, seed)
+    def build_subspaces(self, n_pretrace=0, n_eye=64, n_spec=64, kmeans_iters=8, seed=0, n_light=0, stream=None):
+        p = SubspaceParams(n_pretrace, n_eye, n_spec, kmeans_iters, seed, n_light)
         _check(lib().pt_build_subspaces(self.h, ctypes.byref(p), _stream(stream)))
 
     def render_iteration(self, accum, accum_sq=None, stats=False, stream=None, **params):
