@@ -390,12 +390,17 @@ __device__ __forceinline__ bool traverse(const SceneDev &S, float3 o, float3 d, 
             while (b >= 0 && tn[idx[b]] < tn[v]) { idx[b + 1] = idx[b]; --b; }
             idx[b + 1] = v;
         }
-        // the stack holds PT_STACK entries; a 4-wide tree needs at most 3 per level, so a push
-        // beyond it can only come from a malformed tree and is dropped
-        for (int a = 0; a < n; ++a)
-            if (sp < PT_STACK) stk[(sp++) * stride] = cha[idx[a]];
-        if (sp == 0) break;
-        node = stk[(--sp) * stride];
+        // the nearest child continues in a register; the stack holds PT_STACK entries and a 4-wide
+        // tree needs at most 3 per level, so a push beyond it can only come from a malformed tree
+        // and is dropped
+        if (n > 0) {
+            for (int a = 0; a < n - 1; ++a)
+                if (sp < PT_STACK) stk[(sp++) * stride] = cha[idx[a]];
+            node = cha[idx[n - 1]];
+        } else {
+            if (sp == 0) break;
+            node = stk[(--sp) * stride];
+        }
     }
     return h.tri >= 0;
 }

@@ -759,7 +759,7 @@ struct ChainRun {
 };
 #define CHAIN_COIN 0x80000000u   // Philox counters of the roulette coins
 #define CHAIN_LONG 0x00100000u   // Philox counters of the samples drawn in rounds
-#define CHAIN_ROUNDS 10
+#define CHAIN_ROUNDS 11
 #define CHAIN_BUF (1u << 24)     // samples per round over all chains
 #define CHAIN_LIST_CAP (CHAIN_BUF / 64)   // running chains carried between rounds
 
@@ -872,10 +872,11 @@ __global__ void __launch_bounds__(64 * RW) k_recip(SceneDev S, Cand *cand, const
     count_traversal(C, cnt, C_VISITS_A, C_TESTS_A);
 }
 
-// samples per chain in round r for n running chains: doubling from 4096, within the buffer
+// samples per chain in round r for n running chains: doubling from stage A's budget (1024), so
+// that a chain draws at most about twice the samples it uses, within the buffer
 __device__ __forceinline__ uint32_t chain_round_size(uint32_t n, int round)
 {
-    const uint32_t gmax = 4096u << round;
+    const uint32_t gmax = 1024u << round;
     const uint32_t fit = (CHAIN_BUF / max(n, 1u)) & ~63u;
     return max(64u, min(gmax, fit));
 }
