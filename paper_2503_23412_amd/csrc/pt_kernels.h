@@ -249,8 +249,7 @@ struct MisK {
 
 // subspace-based selection of the light vertex a connection joins
 struct ConnDev {
-    const float *light_c;      // [n_lsub * FEAT] light subspace centroids
-    const float *eye_c;        // [n_eye * FEAT] eye subspace centroids
+    CentSet light, eye;        // light subspace (S_L) and eye subspace (T) centroids
     int n_lsub, n_eye, M;
     // this iteration: label of every pool vertex (index i * M + path), buckets, alias rows
     int *lab;
@@ -269,13 +268,13 @@ __device__ __forceinline__ int conn_label_light(const SceneDev &S, const ConnDev
 {
     float f[9];
     feat9(S, p, n, w, f);
-    return nearest(C.light_c, C.n_lsub, f);
+    return nearest_set(C.light, f);
 }
 __device__ __forceinline__ int conn_label_eye(const SceneDev &S, const ConnDev &C, float3 p, float3 n, float3 w)
 {
     float f[9];
     feat9(S, p, n, w, f);
-    return nearest(C.eye_c, C.n_eye, f);
+    return nearest_set(C.eye, f);
 }
 // the weights' factor M sigma of a connection joining light vertex label Sl to eye label T,
 // from frozen inputs (the selection probability the previous iteration's buckets would give)
@@ -1180,7 +1179,7 @@ __global__ void k_eye_shade(SceneDev S, EyeBuf E, EyeParams P, SubDev D, LightBu
                 if (at_zd && P.labels_on) {
                     float f[9];
                     feat9(S, x, sh.n, wo, f);
-                    Tnew = nearest(D.eye_c, D.n_eye, f);
+                    Tnew = nearest_set(D.eye, f);
                 }
                 const float u0 = rng_f(r), u1 = rng_f(r), u2 = rng_f(r);
                 const float ut = rng_f(r);
@@ -1219,7 +1218,7 @@ __global__ void k_eye_shade(SceneDev S, EyeBuf E, EyeParams P, SubDev D, LightBu
                                         pz = bt.w * cos_o / d2;
                                         float f[9];
                                         feat9(S, x, sh.n, wl, f);
-                                        Sv = nearest(D.spec_c, D.n_spec, f);
+                                        Sv = nearest_set(D.spec, f);
                                     }
                                     const float J0 = cl / dist2;
                                     const float Ap = proxy_mis_factor(D, ph == 2 ? 1 : 0, (int)uu, Sv,
@@ -1332,7 +1331,7 @@ __global__ void k_eye_shade(SceneDev S, EyeBuf E, EyeParams P, SubDev D, LightBu
                             float f[9];
                             feat9(S, x, sh.n, bs.wi, f);
                             nmis.x = bt.w * cos_o / d2;
-                            nmis.z = ibits(nearest(D.spec_c, D.n_spec, f));
+                            nmis.z = ibits(nearest_set(D.spec, f));
                         }
                     }
                 }
@@ -1427,9 +1426,9 @@ __global__ void __launch_bounds__(WG) k_lt(SceneDev S, LightBuf L, EyeParams P, 
                             if (pz > 0.0f && P.labels_on) {
                                 float f[9];
                                 feat9(S, zd, nz, wze, f);
-                                const int Tl = nearest(D.eye_c, D.n_eye, f);
+                                const int Tl = nearest_set(D.eye, f);
                                 feat9(S, ys, ns, normalize3(ys2 - ys), f);
-                                const int Sl = nearest(D.spec_c, D.n_spec, f);
+                                const int Sl = nearest_set(D.spec, f);
                                 const float c_pix = P.tiles_on ? tile_prob(D, py * cam.w + px, cam.w) : 1.0f;
                                 const float Ap = proxy_mis_factor(D, clsB ? 1 : 0, u, Sl, proxy_ksel(D, P, cnt, Tl, Sl, c_pix));
                                 float X;
@@ -1629,7 +1628,7 @@ __global__ void __launch_bounds__(WG) k_proxy(SceneDev S, EyeBuf E, const Cand *
                         // common factors dropped): BSDF hit from y_1, NEE at y_1, proxy
                         float f[9];
                         feat9(S, v, vn, first_dir, f);
-                        const int Sm = nearest(D.spec_c, D.n_spec, f);
+                        const int Sm = nearest_set(D.spec, f);
                         const float pz = bsdf_pdf(md, shd.n, xyz(it.wo), wzv) * fabsf(dot3(vn, wzv)) / d2;
                         const float Ap = proxy_mis_factor(D, cls, u, Sm, proxy_ksel(D, P, cnt, T, Sm, c_pix));
                         float hit, nee, prx;

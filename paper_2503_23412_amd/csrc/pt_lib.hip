@@ -97,6 +97,12 @@ struct pt_scene {
              *mg4 = nullptr;
     float *mz = nullptr, *ml = nullptr, *mdh = nullptr;
     MlpTrain MT{};
+    // group searches of the centroid sets (eye T, specular S, light S_L)
+    struct GroupSet {
+        float *g = nullptr;
+        int *start = nullptr, *mem = nullptr;
+        int G = 0, K = 0, cap_G = 0, cap_K = 0;
+    } gs_eye, gs_spec, gs_light;
     std::vector<int> inv_order;  // input triangle index -> BVH order
     std::vector<hipEvent_t> ev;
     std::vector<void *> allocs;
@@ -301,6 +307,53 @@ pt_status run_kmeans(pt_scene *s, const float *feat, int n, float *cent, int K, 
     HIPCHK(hipGetLastError());
     return PT_OK;
 }
+// groups for the two-level centroid search: k-means of the K centroids into ceil(sqrt K) groups,
+// each centroid a member of its nearest group (flat search for K <= 64)
+pt_status build_groups(pt_scene *s, const float *cent, int K, pt_scene::GroupSet &gs, int iters, hipStream_t st)
+{
+    gs.K = K;
+    gs.G = 0;
+    if (K <= 64) return PT_OK;
+    const int G = (int)std::ceil(std::sqrt((double)K));
+    if (gs.cap_G < G || gs.cap_K < K) {
+        pt_status e;
+        if ((e = s->alloc(gs.g, (size_t)G * FEAT)) != PT_OK) return e;
+        if ((e = s->alloc(gs.start, (size_t)G + 1)) != PT_OK) return e;
+        if ((e = s->alloc(gs.mem, (size_t)K)) != PT_OK) return e;
+        gs.cap_G = G; gs.cap_K = K;
+    }
+    TRY(run_kmeans(s, cent, K, gs.g, G, std::max(iters, 4), st));
+    std::vector<float> hc((size_t)K * FEAT), hg((size_t)G * FEAT);
+    HIPCHK(hipMemcpyAsync(hc.data(), cent, hc.size() * sizeof(float), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(hg.data(), gs.g, hg.size() * sizeof(float), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    std::vector<int> grp(K), start(G + 1, 0), mem(K);
+    for (int k = 0; k < K; ++k) {
+        float bd = 3.0e38f;
+        for (int g = 0; g < G; ++g) {
+            float d = 0.0f;
+            for (int j = 0; j < 9; ++j) {
+                const float t = hc[(size_t)FEAT * k + j] - hg[(size_t)FEAT * g + j];
+                d += t * t;
+            }
+            if (d < bd) { bd = d; grp[k] = g; }
+        }
+        start[grp[k] + 1]++;
+    }
+    for (int g = 0; g < G; ++g) start[g + 1] += start[g];
+    std::vector<int> fill(start.begin(), start.end() - 1);
+    for (int k = 0; k < K; ++k) mem[fill[grp[k]]++] = k;
+    HIPCHK(hipMemcpyAsync(gs.start, start.data(), start.size() * sizeof(int), hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(gs.mem, mem.data(), mem.size() * sizeof(int), hipMemcpyHostToDevice, st));
+    HIPCHK(hipStreamSynchronize(st));
+    gs.G = G;
+    return PT_OK;
+}
+CentSet cent_set(const float *c, const pt_scene::GroupSet &gs)
+{
+    return CentSet{c, gs.g, gs.start, gs.mem, gs.K, gs.G};
+}
+
 __global__ void k_feat_cands(SceneDev S, const Cand *cand, const unsigned long long *cnt, float *feat)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -391,12 +444,14 @@ extern "C" pt_status pt_build_subspaces(pt_scene *s, const pt_subspace_params *p
         HIPCHK(hipStreamSynchronize(st));
         TRY(run_kmeans(s, s->feat, (int)std::min<unsigned long long>(c[C_POOL], (unsigned long long)cap), s->light_c,
                        nl, p->kmeans_iters, st));
+        TRY(build_groups(s, s->light_c, nl, s->gs_light, p->kmeans_iters, st));
     }
     k_candidates<<<blocks(L.M, 256), 256, 0, st>>>(L, 4, s->cand, s->cnt);
     k_feat_cands<<<blocks(4L * L.M, 256), 256, 0, st>>>(S, s->cand, s->cnt, s->feat);
     HIPCHK(hipMemcpyAsync(c, s->cnt, sizeof(c), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
     TRY(run_kmeans(s, s->feat, (int)c[C_NCAND], s->spec_c, ns, p->kmeans_iters, st));
+    TRY(build_groups(s, s->spec_c, ns, s->gs_spec, p->kmeans_iters, st));
     // eye: first diffuse vertices of one pass (the proxy queue collects them)
     EyeBuf E = s->E;
     EyeParams EP{};
@@ -414,6 +469,7 @@ extern "C" pt_status pt_build_subspaces(pt_scene *s, const pt_subspace_params *p
     HIPCHK(hipMemcpyAsync(c, s->cnt, sizeof(c), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
     TRY(run_kmeans(s, s->feat, (int)c[C_PROXYQ], s->eye_c, ne, p->kmeans_iters, st));
+    TRY(build_groups(s, s->eye_c, ne, s->gs_eye, p->kmeans_iters, st));
     // statistics start from nothing
     k_fill<<<blocks((long)ne * ns, 256), 256, 0, st>>>(s->gamma_acc, 0.0f, (size_t)ne * ns);
     k_fill<<<blocks(30L * ns, 256), 256, 0, st>>>(s->rstat_acc, 0.0f, (size_t)30 * ns);
@@ -642,7 +698,8 @@ pt_status enqueue_iteration(pt_scene *s, const pt_iter_params *p, float *acc, fl
     const int nl = s->n_lsub;
     ConnDev CD{};
     if (conn) {
-        CD.light_c = s->light_c; CD.eye_c = s->eye_c; CD.n_lsub = nl; CD.n_eye = ne; CD.M = M;
+        CD.light = cent_set(s->light_c, s->gs_light); CD.eye = cent_set(s->eye_c, s->gs_eye);
+        CD.n_lsub = nl; CD.n_eye = ne; CD.M = M;
         CD.lab = s->plab; CD.count = s->lcount; CD.off = s->loff; CD.fill = s->lfill; CD.list = s->llist;
         CD.nonempty = s->lnonempty; CD.n_nonempty = s->ln_ne;
         CD.al_prob = s->q_alprob; CD.al_idx = s->q_alidx; CD.row_sum = s->q_rowsum; CD.q = s->qfrz;
@@ -694,7 +751,7 @@ pt_status enqueue_iteration(pt_scene *s, const pt_iter_params *p, float *acc, fl
             if (timing) HIPCHK(hipEventRecord(s->ev[e0 + 3], stream));
             if (labels) {
                 SubDev D0{};
-                D0.spec_c = s->spec_c; D0.n_spec = ns;
+                D0.spec_c = s->spec_c; D0.n_spec = ns; D0.spec = cent_set(s->spec_c, s->gs_spec);
                 k_fill_i<<<blocks(ns, 256), 256, 0, stream>>>(s->s_count, 0, (size_t)ns);
                 k_label_cands<<<blocks(maxc, 256), 256, 0, stream>>>(S, D0, s->cand, s->final_, s->cnt, s->s_count);
                 k_scan_sub<<<1, 1024, 0, stream>>>(s->s_count, s->s_off, s->s_fill, s->nonempty, s->n_ne, ns);
@@ -727,6 +784,7 @@ pt_status enqueue_iteration(pt_scene *s, const pt_iter_params *p, float *acc, fl
     SubDev D{};
     if (s->n_eye > 0) {
         D.eye_c = s->eye_c; D.spec_c = s->spec_c; D.n_eye = ne; D.n_spec = ns;
+        D.eye = cent_set(s->eye_c, s->gs_eye); D.spec = cent_set(s->spec_c, s->gs_spec);
         D.s_count = s->s_count; D.s_off = s->s_off; D.s_list = s->s_list; D.nonempty = s->nonempty; D.n_nonempty = s->n_ne;
         D.al_prob = s->al_prob; D.al_idx = s->al_idx; D.row_sum = s->row_sum; D.gamma = s->gamma_frz;
         D.defensive = p->defensive; D.rstat = s->rstat_frz;

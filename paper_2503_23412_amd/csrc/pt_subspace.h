@@ -8,9 +8,29 @@
 
 #define FEAT 12   // 9 features padded to 12 floats (three float4 loads)
 
+// A set of K centroids with a two-level search: the nearest of G group centroids, then the
+// nearest member of that group (the groups cluster the centroids themselves). The label is a
+// deterministic function of the features, which is all the estimators and weights need; an
+// empty nearest group falls back to the full search. G = 0: flat search.
+struct CentSet {
+    const float *c;          // [K * FEAT]
+    const float *g;          // [G * FEAT]
+    const int *start;        // [G + 1] member ranges
+    const int *mem;          // [K] centroid ids by group
+    int K, G;
+};
+__device__ __forceinline__ float feat_d2(const float *__restrict__ c, const float f[9])
+{
+    const float4 a = *(const float4 *)c, b = *(const float4 *)(c + 4), e = *(const float4 *)(c + 8);
+    const float d0 = a.x - f[0], d1 = a.y - f[1], d2 = a.z - f[2], d3 = a.w - f[3], d4 = b.x - f[4],
+                d5 = b.y - f[5], d6 = b.z - f[6], d7 = b.w - f[7], d8 = e.x - f[8];
+    return d0 * d0 + d1 * d1 + d2 * d2 + d3 * d3 + d4 * d4 + d5 * d5 + d6 * d6 + d7 * d7 + d8 * d8;
+}
+
 struct SubDev {
     const float *eye_c;      // [n_eye * FEAT] centroids of eye first-diffuse vertices (T)
     const float *spec_c;     // [n_spec * FEAT] centroids of specular vertices y_{s-1} (S)
+    CentSet eye, spec;       // the same centroids with their group search
     int n_eye, n_spec;
     // this iteration's bucketing of the final candidates
     const int *s_count, *s_off, *s_list, *nonempty;
@@ -51,6 +71,22 @@ __device__ __forceinline__ int nearest(const float *__restrict__ cent, int K, co
         const float d0 = a.x - f[0], d1 = a.y - f[1], d2 = a.z - f[2], d3 = a.w - f[3], d4 = b.x - f[4],
                     d5 = b.y - f[5], d6 = b.z - f[6], d7 = b.w - f[7], d8 = c.x - f[8];
         const float d = d0 * d0 + d1 * d1 + d2 * d2 + d3 * d3 + d4 * d4 + d5 * d5 + d6 * d6 + d7 * d7 + d8 * d8;
+        if (d < bd) { bd = d; best = k; }
+    }
+    return best;
+}
+
+__device__ __forceinline__ int nearest_set(const CentSet &C, const float f[9])
+{
+    if (C.G <= 0) return nearest(C.c, C.K, f);
+    const int g = nearest(C.g, C.G, f);
+    const int a = C.start[g], b = C.start[g + 1];
+    if (a >= b) return nearest(C.c, C.K, f);
+    int best = C.mem[a];
+    float bd = 3.0e38f;
+    for (int i = a; i < b; ++i) {
+        const int k = C.mem[i];
+        const float d = feat_d2(C.c + FEAT * k, f);
         if (d < bd) { bd = d; best = k; }
     }
     return best;
@@ -111,7 +147,7 @@ __global__ void k_label_cands(SceneDev S, SubDev D, Cand *cand, const uint32_t *
     Cand &c = cand[final_[i]];
     float f[9];
     feat9(S, xyz(c.v), S.shade[__float_as_int(c.v.w)].n, oct_dec(make_float2(c.pad[0], c.pad[1])), f);
-    const int s = nearest(D.spec_c, D.n_spec, f);
+    const int s = nearest_set(D.spec, f);
     c.spec_sub = s;
     atomicAdd(s_count + s, 1);
 }

@@ -286,3 +286,28 @@ def test_zz_config0_parity_with_oracle_reference(gpu):
     assert st["n_nan"] == 0 and st["n_recip_truncated"] == 0
 
 
+
+
+def test_zz_config1_128_parity_with_oracle_reference(gpu):
+    """The projector scene of config 1 at 128 x 128 (depth 12), every strategy, 256 eye and light
+    subspaces and 100 specular subspaces (the grouped centroid search), vs the stored O1
+    reference image."""
+    from synth import scenes
+    torch, pt = gpu
+    ref = np.load(os.path.join(GOLD, "cfg1_128_o1_ref.npz"))
+    N = 2048
+    say(f"config 1 at 128x128 parity, {N} spp")
+    flags = (pt.PT_FLAG_NEE | pt.PT_FLAG_PROXY | pt.PT_FLAG_MIS | pt.PT_FLAG_GAMMA | pt.PT_FLAG_TILES |
+             pt.PT_FLAG_SPC | pt.PT_FLAG_LT)
+    m, v, st = _render(gpu, scenes.projector(128, 128), N, max_light=65536, subspaces=(256, 100), max_depth=12,
+                       n_light=65536, cand_cap=2600, flags=flags)
+    mo, vo = ref["mean"], ref["var_mean"]
+    z = (m - mo) / np.sqrt(v + vo + 1e-30)
+    frac = (np.abs(z) < 4).mean()
+    rel_l1 = np.abs(m - mo).sum() / mo.sum()
+    floor = (np.sqrt(2 / np.pi) * np.sqrt(v + vo)).sum() / mo.sum()
+    say(f"config 1 (128): frac |z|<4 {frac:.5f} max|z| {np.abs(z).max():.2f} relL1 {rel_l1:.5f} noise floor {floor:.5f} "
+        f"connections {st['n_connections']:.0f} proxy valid {st['n_proxy_valid']:.0f}")
+    assert frac >= 0.999
+    assert rel_l1 < 1.1 * floor + 0.005
+    assert st["n_nan"] == 0 and st["n_recip_truncated"] == 0
