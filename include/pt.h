@@ -162,6 +162,33 @@ pt_status pt_render_iteration(pt_scene *s, const pt_iter_params *p, float *accum
 pt_status pt_render_batch(pt_scene *s, const pt_iter_params *p, uint32_t n_iter, float *accum_rgb_dev,
                           float *accum_sq_dev, void *hip_stream);
 
+/* Several scenes (1 .. 64, each appearing once) per launch: one HIP graph holds one iteration of
+ * every scene, each on its own branch so that the device runs small scenes side by side, and is
+ * replayed n_iter times on hip_stream (iterations params[i].iteration, +1, ...). Scene i
+ * accumulates into accum_rgb[i] / accum_sq[i] (accum_sq may be NULL) as pt_render_iteration
+ * does. The graph belongs to scenes[0] and is rebuilt when a scene, a parameter other than the
+ * iteration index, a buffer or a scene's tuned schedule changes; release the scenes of a batch
+ * together. PT_FLAG_TIMING is rejected. */
+pt_status pt_render_scenes(pt_scene *const *scenes, const pt_iter_params *params, int32_t n_scenes, uint32_t n_iter,
+                           float *const *accum_rgb, float *const *accum_sq, void *hip_stream);
+
+/* Schedule autotuning of the reciprocal chains on this scene and parameters: the sample budget
+ * of the one-wavefront stage (256 .. 2048) and the grid of the round kernels (2,048 .. 32,768
+ * blocks) are each timed over two iterations (after one to settle) and the fastest pair is kept
+ * by the scene for later iterations. Every pair gives the same estimator (the chains consume
+ * i.i.d. samples whoever draws them), so the choice changes speed only. The timed iterations
+ * render into accum_rgb / accum_sq (iterations p->iteration, +1, ...); their number is returned
+ * in iterations_rendered. Synchronises hip_stream. */
+typedef struct {
+    uint32_t stage_a_budget;     /* chosen sample budget of the one-wavefront stage */
+    int32_t round_grid;          /* chosen blocks of the round kernels */
+    float ms_best;               /* iteration time with the chosen pair */
+    float ms_previous;           /* iteration time with the pair the scene had before */
+    uint32_t iterations_rendered;
+} pt_tune_result;
+pt_status pt_autotune(pt_scene *s, const pt_iter_params *p, float *accum_rgb_dev, float *accum_sq_dev,
+                      pt_tune_result *out, void *hip_stream);
+
 /* Learned selection of the specular subspace (PT_FLAG_MLP). Not part of the paper's method: it
  * replaces the Gamma row of Section 5.6 by a network's softmax mixed with that row, and keeps
  * the selection probability exact, so the proxy estimator stays unbiased.

@@ -108,6 +108,14 @@ struct pt_scene {
     std::vector<void *> allocs;
     // captured iteration graph (pt_render_batch) and the key it was captured for
     hipStream_t cap_stream = nullptr;
+    // reciprocal-chain schedule (pt_autotune): stage-A sample budget, blocks of the round kernels
+    uint32_t tune_budget = 1024;
+    int tune_gen_grid = 8192;
+    // multi-scene graph (pt_render_scenes) owned by the first scene of a batch
+    hipGraphExec_t mgexec = nullptr;
+    std::vector<char> mgkey;
+    std::vector<hipStream_t> mstreams;
+    std::vector<hipEvent_t> mevents;
     hipGraphExec_t gexec = nullptr;
     std::vector<char> gkey;
 
@@ -125,6 +133,9 @@ struct pt_scene {
     ~pt_scene()
     {
         if (gexec) (void)hipGraphExecDestroy(gexec);
+        if (mgexec) (void)hipGraphExecDestroy(mgexec);
+        for (hipStream_t q : mstreams) (void)hipStreamDestroy(q);
+        for (hipEvent_t e : mevents) (void)hipEventDestroy(e);
         if (cap_stream) (void)hipStreamDestroy(cap_stream);
         for (void *p : allocs) (void)hipFree(p);
         for (hipEvent_t e : ev) (void)hipEventDestroy(e);
@@ -737,12 +748,12 @@ pt_status enqueue_iteration(pt_scene *s, const pt_iter_params *p, float *acc, fl
             const uint32_t n1 = (uint32_t)std::max(64.0f, p->cost_cap / (float)p->recip_repeats);
             if (timing) HIPCHK(hipEventRecord(s->ev[e0 + 1], stream));
             k_recip<<<blocks((long)maxc * p->recip_repeats, RW), 64 * RW, 0, stream>>>(
-                S, s->cand, s->final_, p->recip_repeats, p->seed, n1, 1024u, s->runmax, s->chq[0], s->cnt);
+                S, s->cand, s->final_, p->recip_repeats, p->seed, n1, s->tune_budget, s->runmax, s->chq[0], s->cnt);
             if (timing) HIPCHK(hipEventRecord(s->ev[e0 + 2], stream));
             for (int r = 0; r < CHAIN_ROUNDS; ++r) {
                 const int in = r & 1, out = in ^ 1;
                 k_set_counter<<<1, 1, 0, stream>>>(s->cnt, C_LONGQ0 + out, 0ull);
-                k_chain_gen<<<8192, WG, 0, stream>>>(S, s->cand, s->chq[in], C_LONGQ0 + in, r, p->seed, s->chbuf,
+                k_chain_gen<<<s->tune_gen_grid, WG, 0, stream>>>(S, s->cand, s->chq[in], C_LONGQ0 + in, r, p->seed, s->chbuf,
                                                      s->cnt);
                 k_chain_consume<<<2048, 64 * RW, 0, stream>>>(s->cand, s->chq[in], C_LONGQ0 + in, s->chq[out],
                                                               C_LONGQ0 + out, r, r == CHAIN_ROUNDS - 1 ? 1 : 0,
@@ -1061,5 +1072,138 @@ extern "C" pt_status pt_mlp_train_step(pt_scene *s, const float *feat, const int
     k_set_counter<<<1, 1, 0, st>>>(s->cnt, C_MLP_N, 0ull);
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(st));
+    return PT_OK;
+}
+
+extern "C" pt_status pt_render_scenes(pt_scene *const *scenes, const pt_iter_params *params, int32_t n, uint32_t n_iter,
+                                      float *const *acc, float *const *acc2, void *stream_)
+{
+    if (!scenes || !params || !acc || n <= 0 || n > 64) return set_err(PT_EINVAL, "bad scene batch (1 .. 64 scenes)");
+    if (n_iter == 0) return set_err(PT_EINVAL, "n_iter must be positive");
+    for (int i = 0; i < n; ++i) {
+        TRY(check_params(scenes[i], &params[i], acc[i]));
+        if (params[i].flags & PT_FLAG_TIMING) return set_err(PT_EINVAL, "PT_FLAG_TIMING cannot be captured");
+        for (int j = 0; j < i; ++j)
+            if (scenes[j] == scenes[i]) return set_err(PT_EINVAL, "a scene appears twice in the batch");
+    }
+    hipStream_t stream = (hipStream_t)stream_;
+    pt_scene *own = scenes[0];
+    for (int i = 0; i < n; ++i)
+        if (params[i].flags & PT_FLAG_MLP) {
+            TRY(ensure_mlp(scenes[i], stream));
+            HIPCHK(hipStreamSynchronize(stream));
+        }
+    // the graph depends on every scene, its parameters but the iteration index, and the buffers
+    std::vector<char> k;
+    for (int i = 0; i < n; ++i) {
+        pt_iter_params key = params[i];
+        key.iteration = 0;
+        const pt_scene *sp = scenes[i];
+        float *a = acc[i], *b = acc2 ? acc2[i] : nullptr;
+        k.insert(k.end(), (const char *)&sp, (const char *)&sp + sizeof(sp));
+        k.insert(k.end(), (const char *)&key, (const char *)&key + sizeof(key));
+        k.insert(k.end(), (const char *)&a, (const char *)&a + sizeof(a));
+        k.insert(k.end(), (const char *)&b, (const char *)&b + sizeof(b));
+        k.insert(k.end(), (const char *)&sp->tune_budget, (const char *)&sp->tune_budget + sizeof(uint32_t));
+        k.insert(k.end(), (const char *)&sp->tune_gen_grid, (const char *)&sp->tune_gen_grid + sizeof(int));
+    }
+    if (!own->mgexec || k != own->mgkey) {
+        if (own->mgexec) { HIPCHK(hipGraphExecDestroy(own->mgexec)); own->mgexec = nullptr; }
+        if (!own->cap_stream) HIPCHK(hipStreamCreateWithFlags(&own->cap_stream, hipStreamNonBlocking));
+        while ((int)own->mstreams.size() < n) {
+            hipStream_t q;
+            HIPCHK(hipStreamCreateWithFlags(&q, hipStreamNonBlocking));
+            own->mstreams.push_back(q);
+        }
+        while ((int)own->mevents.size() < n + 1) {
+            hipEvent_t e;
+            HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+            own->mevents.push_back(e);
+        }
+        // fork: every scene's iteration on its own stream, joined back into the capture stream
+        hipGraph_t g = nullptr;
+        HIPCHK(hipStreamBeginCapture(own->cap_stream, hipStreamCaptureModeThreadLocal));
+        pt_status st = PT_OK;
+        hipError_t e = hipEventRecord(own->mevents[0], own->cap_stream);
+        for (int i = 0; i < n && st == PT_OK && e == hipSuccess; ++i) {
+            e = hipStreamWaitEvent(own->mstreams[i], own->mevents[0], 0);
+            if (e != hipSuccess) break;
+            st = enqueue_iteration(scenes[i], &params[i], acc[i], acc2 ? acc2[i] : nullptr, own->mstreams[i], true);
+            if (st != PT_OK) break;
+            e = hipEventRecord(own->mevents[i + 1], own->mstreams[i]);
+            if (e == hipSuccess) e = hipStreamWaitEvent(own->cap_stream, own->mevents[i + 1], 0);
+        }
+        const hipError_t e2 = hipStreamEndCapture(own->cap_stream, &g);
+        if (st != PT_OK) { if (g) (void)hipGraphDestroy(g); return st; }
+        if (e != hipSuccess || e2 != hipSuccess) {
+            if (g) (void)hipGraphDestroy(g);
+            return set_err(PT_EDEVICE, "multi-scene capture failed: %s", hipGetErrorString(e != hipSuccess ? e : e2));
+        }
+        e = hipGraphInstantiate(&own->mgexec, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (e != hipSuccess) { own->mgexec = nullptr; return set_err(PT_EDEVICE, "graph instantiation failed: %s", hipGetErrorString(e)); }
+        own->mgkey = k;
+    }
+    for (int i = 0; i < n; ++i)
+        k_iter<<<1, 1, 0, stream>>>(scenes[i]->cnt, params[i].iteration - 1u, 0, params[i].train_iters);
+    for (uint32_t it = 0; it < n_iter; ++it) HIPCHK(hipGraphLaunch(own->mgexec, stream));
+    HIPCHK(hipGetLastError());
+    return PT_OK;
+}
+
+extern "C" pt_status pt_autotune(pt_scene *s, const pt_iter_params *p, float *acc, float *acc2, pt_tune_result *out,
+                                 void *stream_)
+{
+    TRY(check_params(s, p, acc));
+    if (!out) return set_err(PT_EINVAL, "null result");
+    hipStream_t stream = (hipStream_t)stream_;
+    if (p->flags & PT_FLAG_MLP) TRY(ensure_mlp(s, stream));
+    static const uint32_t budgets[4] = {256u, 512u, 1024u, 2048u};
+    static const int grids[3] = {2048, 8192, 32768};
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    pt_iter_params q = *p;
+    q.flags &= ~(uint32_t)(PT_FLAG_TIMING | PT_FLAG_COUNT);
+    float best = 3.0e38f, dflt = 0.0f;
+    uint32_t bb = s->tune_budget;
+    int bg = s->tune_gen_grid;
+    const uint32_t b0 = s->tune_budget;
+    const int g0 = s->tune_gen_grid;
+    int used = 0;
+    pt_status st = PT_OK;
+    for (int bi = 0; bi < 4 && st == PT_OK; ++bi)
+        for (int gi = 0; gi < 3 && st == PT_OK; ++gi) {
+            s->tune_budget = budgets[bi];
+            s->tune_gen_grid = grids[gi];
+            // one iteration to settle, two timed
+            q.iteration = p->iteration + (uint32_t)used++;
+            if ((st = enqueue_iteration(s, &q, acc, acc2, stream, false)) != PT_OK) break;
+            if (hipEventRecord(e0, stream) != hipSuccess) { st = set_err(PT_EDEVICE, "event record failed"); break; }
+            for (int r = 0; r < 2 && st == PT_OK; ++r) {
+                q.iteration = p->iteration + (uint32_t)used++;
+                st = enqueue_iteration(s, &q, acc, acc2, stream, false);
+            }
+            if (st != PT_OK) break;
+            float ms = 0.0f;
+            if (hipEventRecord(e1, stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+                st = set_err(PT_EDEVICE, "event timing failed");
+                break;
+            }
+            ms *= 0.5f;
+            if (budgets[bi] == b0 && grids[gi] == g0) dflt = ms;
+            if (ms < best) { best = ms; bb = budgets[bi]; bg = grids[gi]; }
+        }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (st != PT_OK) { s->tune_budget = b0; s->tune_gen_grid = g0; return st; }
+    s->tune_budget = bb;
+    s->tune_gen_grid = bg;
+    out->stage_a_budget = bb;
+    out->round_grid = bg;
+    out->ms_best = best;
+    out->ms_previous = dflt;
+    out->iterations_rendered = (uint32_t)used;
     return PT_OK;
 }

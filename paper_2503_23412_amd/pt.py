@@ -29,6 +29,7 @@ PT_EST_ITILDE = 0
 PT_EST_SIGN = 1
 
 EXPORTED = ["pt_scene_upload", "pt_scene_release", "pt_build_subspaces", "pt_render_iteration", "pt_render_batch",
+            "pt_render_scenes", "pt_autotune",
             "pt_mlp_param_count", "pt_mlp_set_params", "pt_mlp_get_params", "pt_mlp_forward", "pt_mlp_train_step",
             "pt_reciprocal_estimate", "pt_resolve_image", "pt_trace_closest", "pt_last_error"]
 
@@ -74,6 +75,11 @@ class IterStats(ctypes.Structure):
         return d
 
 
+class TuneResult(ctypes.Structure):
+    _fields_ = [("stage_a_budget", ctypes.c_uint32), ("round_grid", ctypes.c_int32), ("ms_best", ctypes.c_float),
+                ("ms_previous", ctypes.c_float), ("iterations_rendered", ctypes.c_uint32)]
+
+
 class CandDesc(ctypes.Structure):
     _fields_ = [("cls", ctypes.c_int32), ("u", ctypes.c_int32), ("v", ctypes.c_float * 3), ("v_prim", ctypes.c_int32),
                 ("hc", ctypes.c_float * 3), ("hc_prim", ctypes.c_int32), ("hc_b1", ctypes.c_float),
@@ -106,6 +112,8 @@ def lib():
         L.pt_reciprocal_estimate.argtypes = [P, ctypes.POINTER(RecipQuery), P, P, P]
         L.pt_resolve_image.argtypes = [P, P, ctypes.c_uint32, P, P]
         L.pt_trace_closest.argtypes = [P, P, I, P, P, P]
+        L.pt_render_scenes.argtypes = [P, P, I, ctypes.c_uint32, P, P, P]
+        L.pt_autotune.argtypes = [P, ctypes.POINTER(IterParams), P, P, ctypes.POINTER(TuneResult), P]
         L.pt_mlp_param_count.argtypes = [P, ctypes.POINTER(I)]
         L.pt_mlp_set_params.argtypes = [P, P, I, P]
         L.pt_mlp_get_params.argtypes = [P, P, I, P]
@@ -204,6 +212,14 @@ class Scene:
                        p_out.data_ptr() if p_out is not None else None)
         _check(lib().pt_reciprocal_estimate(self.h, ctypes.byref(q), _ptr(out), _ptr(nsamples), _stream(stream)))
 
+    def autotune(self, accum, accum_sq=None, stream=None, **params):
+        """Time the reciprocal-chain schedule choices and keep the fastest (renders into accum)."""
+        p = IterParams(**default_params(**params))
+        r = TuneResult()
+        _check(lib().pt_autotune(self.h, ctypes.byref(p), _ptr(accum), _ptr(accum_sq), ctypes.byref(r),
+                                 _stream(stream)))
+        return {k: getattr(r, k) for k, _ in r._fields_}
+
     # learned subspace selection (PT_FLAG_MLP): parameters and the network's two passes
     def mlp_param_count(self):
         n = ctypes.c_int32()
@@ -240,3 +256,13 @@ def reciprocal_table(f, q, B, n_est, out, nsamples, estimator=PT_EST_ITILDE, see
     qq = RecipQuery(0, int(f.shape[0]), f.data_ptr(), q.data_ptr(), float(B), int(n_est), int(estimator), int(seed),
                     int(cap), None, 0, None)
     _check(lib().pt_reciprocal_estimate(None, ctypes.byref(qq), _ptr(out), _ptr(nsamples), _stream(stream)))
+
+
+def render_scenes(scenes, accums, accums_sq, n_iter, params, stream=None):
+    """n_iter iterations of every scene from one captured multi-scene graph; params: one dict each."""
+    n = len(scenes)
+    hs = (ctypes.c_void_p * n)(*[sc.h.value for sc in scenes])
+    ps = (IterParams * n)(*[IterParams(**default_params(**q)) for q in params])
+    a = (ctypes.c_void_p * n)(*[t.data_ptr() for t in accums])
+    b = (ctypes.c_void_p * n)(*[t.data_ptr() for t in accums_sq]) if accums_sq is not None else None
+    _check(lib().pt_render_scenes(hs, ps, n, int(n_iter), a, b, _stream(stream)))

@@ -166,6 +166,55 @@ def test_diffuse_furnace(gpu, proxy):
     assert st["n_nan"] == 0
 
 
+def test_multi_scene_graph_and_autotune(gpu):
+    """Two furnaces of different size and albedo rendered by one multi-scene graph, and a third
+    after schedule autotuning, each against its closed form."""
+    from synth import scenes
+    torch, pt = gpu
+    K = 6
+    flags = pt.PT_FLAG_NEE | pt.PT_FLAG_PROXY | pt.PT_FLAG_MIS | pt.PT_FLAG_GAMMA | pt.PT_FLAG_SPC | pt.PT_FLAG_LT
+    specs = [(0.5, 16, 16), (0.3, 24, 8)]
+    S, A, A2 = [], [], []
+    for a, w, h in specs:
+        sc = pt.Scene(scenes.furnace(albedo=a, le=1.0, width=w, height=h), max_light_paths=1024)
+        sc.build_subspaces(n_eye=8, n_spec=8)
+        S.append(sc)
+        A.append(torch.zeros(w * h * 3, device="cuda"))
+        A2.append(torch.zeros(w * h * 3, device="cuda"))
+    N = 512
+    prm = [dict(iteration=0, max_depth=K, n_light=1024, cand_cap=128, flags=flags)] * 2
+    pt.render_scenes(S, A, A2, N // 2, prm)
+    prm2 = [dict(q, iteration=N // 2) for q in prm]
+    pt.render_scenes(S, A, A2, N // 2, prm2)   # the cached graph, continued
+    torch.cuda.synchronize()
+    for (a, w, h), acc, acc2 in zip(specs, A, A2):
+        m = (acc / N).double().cpu().numpy()
+        v = np.maximum((acc2 / N).double().cpu().numpy() - m * m, 0) / N
+        expect = (1 - a ** K) / (1 - a)
+        z = (m - expect) / np.sqrt(v + 1e-30)
+        say(f"multi-scene furnace a={a}: mean {m.mean():.5f} expect {expect:.5f} max|z| {np.abs(z).max():.2f}")
+        assert (np.abs(z) < 4).mean() >= 0.999
+    for sc in S:
+        sc.release()
+    # autotuning renders its timed iterations into the accumulators like any other
+    sc = pt.Scene(scenes.furnace(albedo=0.5, le=1.0, width=16, height=16), max_light_paths=1024)
+    sc.build_subspaces(n_eye=8, n_spec=8)
+    acc = torch.zeros(16 * 16 * 3, device="cuda")
+    acc2 = torch.zeros_like(acc)
+    r = sc.autotune(acc, acc2, iteration=0, max_depth=K, n_light=1024, cand_cap=128, flags=flags)
+    say("autotune", r)
+    assert r["stage_a_budget"] in (256, 512, 1024, 2048) and r["round_grid"] in (2048, 8192, 32768)
+    n = r["iterations_rendered"]
+    for k in range(n, 512):
+        sc.render_iteration(acc, acc2, iteration=k, max_depth=K, n_light=1024, cand_cap=128, flags=flags)
+    torch.cuda.synchronize()
+    m = (acc / 512).double().cpu().numpy()
+    v = np.maximum((acc2 / 512).double().cpu().numpy() - m * m, 0) / 512
+    z = (m - (1 - 0.5 ** K) / 0.5) / np.sqrt(v + 1e-30)
+    assert (np.abs(z) < 4).mean() >= 0.999
+    sc.release()
+
+
 def test_glass_furnace_through_proxy(gpu):
     from synth import scenes
     a, K = 0.5, 120
