@@ -16,6 +16,9 @@
  *     equation), estimated two ways:
  *       O1  unidirectional path tracing with next-event estimation, balance
  *           heuristic between the two (the plain definition);
+ *       O3  plain bidirectional path tracing: one light and one eye sub-path
+ *           per pixel sample, every (s, t) strategy, balance-heuristic weights
+ *           from explicit products of vertex densities (Section 3.1);
  *       O2  proxy-sampling BDPT: light sub-path cache, incomplete sub-path
  *           candidates, reciprocal estimates of 1/P (Section 5), proxy
  *           connections at the eye's first diffuse vertex; every path that the
@@ -73,7 +76,7 @@ void or_philox4x32_10(const uint32_t ctr_in[4], const uint32_t key_in[2], uint32
 
 /* A stream: key = (seed, purpose), counter = (a, b, c, running block). */
 typedef struct { uint32_t key[2]; uint32_t ctr[4]; uint32_t buf[4]; int pos; } rng_t;
-enum { ST_PT = 1, ST_LIGHT = 2, ST_CAND = 3, ST_RECIP = 4, ST_EYE = 5, ST_PILOT = 6, ST_TABLE = 7, ST_TEST = 8 };
+enum { ST_PT = 1, ST_LIGHT = 2, ST_CAND = 3, ST_RECIP = 4, ST_EYE = 5, ST_PILOT = 6, ST_TABLE = 7, ST_TEST = 8, ST_BDPT = 9 };
 
 static void rng_init(rng_t *r, uint32_t seed, uint32_t purpose, uint32_t a, uint32_t b, uint32_t c)
 {
@@ -769,7 +772,7 @@ static void parallel_for(int n, int threads, work_fn fn, void *ctx)
 /* render parameters and statistics                                           */
 /* ------------------------------------------------------------------------- */
 typedef struct {
-    int method;        /* 0 = O1 (PT + NEE), 1 = O2 (proxy-sampling BDPT) */
+    int method;        /* 0 = O1 (PT + NEE), 1 = O2 (proxy-sampling BDPT), 2 = O3 (plain BDPT) */
     int n_iter;        /* iterations = samples per pixel (1 spp each, Section 6.1) */
     int first_iter;    /* index of the first iteration (streams are keyed by it) */
     int max_depth;     /* maximum number of path segments */
@@ -783,6 +786,8 @@ typedef struct {
     int pilot;         /* minimum pilot samples per candidate (B and cost estimate) */
     long chain_cap;    /* sample cap per reciprocal estimate */
     double cost_cap;   /* expected chain samples per candidate above which it is roulette-kept */
+    int o3_weights;    /* O3 only: 0 balance heuristic, 1 uniform over the strategies that can
+                        * build the path, 2 light tracing alone (pins of the strategies) */
 } or_params;
 
 typedef struct {
@@ -1338,12 +1343,306 @@ static double proxy_connect(const scene_t *s, const or_params *p, struct o2_iter
 /* ------------------------------------------------------------------------- */
 /* render entry point                                                         */
 /* ------------------------------------------------------------------------- */
+/* ------------------------------------------------------------------------- */
+/* O3: plain bidirectional path tracing (Section 3.1)                         */
+/* ------------------------------------------------------------------------- */
+/* Every pixel sample traces one eye sub-path z_0 (the pinhole) z_1 .. z_D and one light
+ * sub-path y_0 .. y_{D-1} (D = max_depth) and forms every full path x = y_0..y_{s-1}
+ * z_{t-1}..z_0 of at most D segments (n = s + t - 1): s = 0 is an eye sub-path that hits an
+ * emitter, s = 1 joins z_{t-1} to y_0, s >= 2 joins z_{t-1} to y_{s-1}, and t = 1 joins
+ * y_{s-1} to the pinhole and adds the result to the pixel that the join passes through (light
+ * tracing; the W * H light sub-paths of an iteration all do this, so each splat is divided by
+ * W * H). The contribution of a strategy is f(x) / p_s(x) with f = L_e T W_e (path integral
+ * equation, Section 3.1) and p_s = p(y) p(z), the product of the tracing densities of its
+ * vertices in area measure (tracing pdf equation).
+ *
+ * Weights: the balance heuristic over the strategies s' = 0 .. n that can build x, each
+ * density q_s' written out as the product over the path's vertices of the density with which
+ * the light side (vertices below s') or the eye side (the others) generates them; light
+ * tracing counts W * H samples per pixel, every other strategy one. A Dirac vertex has no
+ * area density: the factor for the vertex generated across it is taken as 1 from both sides,
+ * and a strategy whose joining segment ends at a Dirac vertex cannot build x (weight 0).
+ * Any weights that sum to one over the strategies able to build x keep the sum unbiased
+ * (the weights only need to be a partition of unity), so the uniform and the light-tracing-
+ * only variants (o3_weights 1, 2) estimate the same image and pin each strategy's raw
+ * contribution. */
+#define O3_MAXD 128
+typedef struct {
+    v3 p, n;
+    int prim;
+    double b1, b2;
+    const mat_t *m;
+    double beta[3];   /* eye: W_e / p product up to here; light: L_e / p up to here (no BSDF at this vertex) */
+} o3_vert;
+
+typedef struct {
+    const scene_t *s; const or_params *p;
+    int iter;
+    double *frame;          /* per-iteration pixel values (H * W * 3) */
+    int *spl_pix;           /* per-row splat lists: row py holds at most W * D entries */
+    double *spl_val;
+    int *spl_n;
+} o3_ctx;
+
+/* image-plane position of direction d from the pinhole; 0 if it misses the image */
+static int o3_project(const scene_t *s, v3 d, int *pix, double *cos_cam)
+{
+    double cf = vdot(d, s->cam_f);
+    if (cf <= 0) return 0;
+    double aspect = (double)s->W / s->H;
+    double X = vdot(d, s->cam_r) / cf, Y = vdot(d, s->cam_u) / cf;
+    double fx = (X / (s->tan_half * aspect) + 1.0) * 0.5 * s->W;
+    double fy = (1.0 - Y / s->tan_half) * 0.5 * s->H;
+    if (!(fx >= 0 && fx < s->W && fy >= 0 && fy < s->H)) return 0;
+    *pix = (int)floor(fy) * s->W + (int)floor(fx);
+    *cos_cam = cf;
+    return 1;
+}
+
+/* pixel sensitivity per solid angle, W_e = 1 / (a_pix cos^3): uniform over the pixel's area on
+ * the image plane at unit distance, which is also the eye sub-path's density of its first direction */
+static double o3_we(const scene_t *s, double cos_cam)
+{
+    double aspect = (double)s->W / s->H;
+    double a_pix = (2.0 * s->tan_half * aspect / s->W) * (2.0 * s->tan_half / s->H);
+    return 1.0 / (a_pix * cos_cam * cos_cam * cos_cam);
+}
+
+/* vertex i of the full path for strategy s: x_0..x_{s-1} = y, x_s..x_{n-1} = z_{n-s}..z_1 */
+static const o3_vert *o3_x(const o3_vert *Y, const o3_vert *Z, int s, int n, int i)
+{
+    return i < s ? &Y[i] : &Z[n - i];
+}
+
+static double o3_geo(v3 a, v3 na, v3 b, v3 nb, double *ca, double *cb)
+{
+    v3 d = vsub(b, a);
+    double r2 = vdot(d, d);
+    v3 w = vscl(d, 1.0 / sqrt(r2));
+    *ca = vdot(na, w); *cb = -vdot(nb, w);
+    return r2;
+}
+
+/* the weight of strategy s for the path it built (n segments) */
+static double o3_weight(const scene_t *s, const or_params *p, const o3_vert *Y, const o3_vert *Z, int st, int n)
+{
+    if (p->o3_weights == 2) return st == n ? 1.0 : 0.0;
+    double pl[O3_MAXD + 1], pe[O3_MAXD + 1];
+    int dirac[O3_MAXD + 1];
+    const double NL = (double)s->W * s->H;
+    for (int i = 0; i < n; ++i) {
+        const o3_vert *v = o3_x(Y, Z, st, n, i);
+        dirac[i] = i > 0 && v->m->delta;
+    }
+    /* light-side densities: y_0 by area, y_1 by cosine emission, then BSDF sampling */
+    for (int i = 0; i < n; ++i) {
+        const o3_vert *v = o3_x(Y, Z, st, n, i);
+        if (i == 0) { pl[0] = 1.0 / s->em_area; continue; }
+        const o3_vert *a = o3_x(Y, Z, st, n, i - 1);
+        double ca, cb, r2 = o3_geo(a->p, a->n, v->p, v->n, &ca, &cb);
+        if (i == 1) { pl[1] = fmax(ca, 0.0) / PI * fabs(cb) / r2; continue; }
+        if (dirac[i - 1]) { pl[i] = 1.0; continue; }
+        const o3_vert *b = o3_x(Y, Z, st, n, i - 2);
+        v3 wo = vnorm(vsub(b->p, a->p)), wi = vnorm(vsub(v->p, a->p));
+        pl[i] = bsdf_pdf(a->m, a->n, wo, wi) * fabs(cb) / r2;
+    }
+    /* eye-side densities: x_{n-1} through the pixel, then BSDF sampling toward the light */
+    for (int i = n - 1; i >= 0; --i) {
+        const o3_vert *v = o3_x(Y, Z, st, n, i);
+        if (i == n - 1) {
+            v3 d = vsub(v->p, s->cam_p);
+            double r2 = vdot(d, d);
+            v3 w = vscl(d, 1.0 / sqrt(r2));
+            double cf = vdot(w, s->cam_f);
+            pe[i] = cf > 0 ? o3_we(s, cf) * fabs(vdot(v->n, w)) / r2 : 0.0;
+            continue;
+        }
+        const o3_vert *a = o3_x(Y, Z, st, n, i + 1);
+        if (dirac[i + 1]) { pe[i] = 1.0; continue; }
+        v3 bp = i + 2 == n ? s->cam_p : o3_x(Y, Z, st, n, i + 2)->p;
+        double ca, cb, r2 = o3_geo(a->p, a->n, v->p, v->n, &ca, &cb);
+        v3 wo = vnorm(vsub(bp, a->p)), wi = vnorm(vsub(v->p, a->p));
+        pe[i] = bsdf_pdf(a->m, a->n, wo, wi) * fabs(cb) / r2;
+    }
+    double qs = 0.0, sum = 0.0;
+    int nvalid = 0;
+    for (int sp = 0; sp <= n; ++sp) {
+        /* the joining segment x_{sp-1} x_sp may not end at a Dirac vertex */
+        if (sp >= 1 && sp <= n - 1 && (dirac[sp - 1] || dirac[sp])) continue;
+        if (sp == n && dirac[n - 1]) continue;
+        double q = sp == n ? NL : 1.0;
+        for (int i = 0; i < sp; ++i) q *= pl[i];
+        for (int i = sp; i < n; ++i) q *= pe[i];
+        if (!(q > 0)) continue;
+        nvalid++;
+        sum += q;
+        if (sp == st) qs = q;
+    }
+    if (p->o3_weights == 1) return qs > 0 ? 1.0 / nvalid : 0.0;
+    return sum > 0 ? qs / sum : 0.0;
+}
+
+static void o3_pixel(const o3_ctx *c, int px, int py)
+{
+    const scene_t *s = c->s;
+    const or_params *p = c->p;
+    const int D = p->max_depth, pix = py * s->W + px;
+    o3_vert Z[O3_MAXD + 2], Y[O3_MAXD + 1];
+    int nz = 0, ny = 0;   /* eye vertices z_1..z_nz, light vertices y_0..y_{ny-1} */
+    rng_t r;
+    /* eye sub-path */
+    rng_init(&r, p->seed, ST_BDPT, (uint32_t)pix, (uint32_t)c->iter, 0);
+    v3 o, d;
+    camera_ray(s, px, py, rng_u01(&r), rng_u01(&r), &o, &d);
+    Z[0].p = s->cam_p; Z[0].n = s->cam_f; Z[0].prim = -1; Z[0].m = NULL;
+    double beta[3] = {1, 1, 1};
+    int ign = -1;
+    while (nz < D) {
+        hit_t h;
+        if (!trace_closest(s, o, d, s->tmin, 1e300, ign, -1, &h)) break;
+        o3_vert *v = &Z[++nz];
+        v->p = hit_point(s, &h); v->n = s->tri[h.prim].n; v->prim = h.prim; v->b1 = h.b1; v->b2 = h.b2;
+        v->m = &s->mat[s->tri[h.prim].mat];
+        for (int k = 0; k < 3; ++k) v->beta[k] = beta[k];
+        if (nz == D) break;
+        bsample_t bs = bsdf_sample(v->m, v->n, vscl(d, -1.0), rng_u01(&r), rng_u01(&r), rng_u01(&r), MODE_CAMERA);
+        if (!bs.ok) break;
+        for (int k = 0; k < 3; ++k) beta[k] *= bs.w[k];
+        if (beta[0] == 0 && beta[1] == 0 && beta[2] == 0) break;
+        o = v->p; d = bs.wi; ign = h.prim;
+    }
+    /* light sub-path: y_0 uniform by area, cosine emission, BSDF sampling (adjoint) */
+    rng_init(&r, p->seed, ST_BDPT, (uint32_t)pix, (uint32_t)c->iter, 1);
+    lpoint_t lp;
+    if (D >= 1 && sample_light(s, &r, &lp)) {
+        o3_vert *y0 = &Y[ny++];
+        y0->p = lp.p; y0->n = lp.n; y0->prim = lp.prim; y0->b1 = lp.b1; y0->b2 = lp.b2;
+        y0->m = &s->mat[s->tri[lp.prim].mat];
+        y0->beta[0] = y0->beta[1] = y0->beta[2] = s->em_area;
+        d = cosine_dir(lp.n, rng_u01(&r), rng_u01(&r));
+        double le[3];
+        emitted(s, lp.prim, lp.b1, lp.b2, d, le);
+        for (int k = 0; k < 3; ++k) beta[k] = s->em_area * le[k] * PI;
+        o = lp.p; ign = lp.prim;
+        while (ny < D && (beta[0] > 0 || beta[1] > 0 || beta[2] > 0)) {
+            hit_t h;
+            if (!trace_closest(s, o, d, s->tmin, 1e300, ign, -1, &h)) break;
+            o3_vert *v = &Y[ny++];
+            v->p = hit_point(s, &h); v->n = s->tri[h.prim].n; v->prim = h.prim; v->b1 = h.b1; v->b2 = h.b2;
+            v->m = &s->mat[s->tri[h.prim].mat];
+            for (int k = 0; k < 3; ++k) v->beta[k] = beta[k];
+            bsample_t bs = bsdf_sample(v->m, v->n, vscl(d, -1.0), rng_u01(&r), rng_u01(&r), rng_u01(&r), MODE_LIGHT);
+            if (!bs.ok) break;
+            for (int k = 0; k < 3; ++k) beta[k] *= bs.w[k];
+            o = v->p; d = bs.wi; ign = h.prim;
+        }
+    }
+    double L[3] = {0, 0, 0};
+    /* t >= 2: strategies that end at the eye vertex z_{t-1} */
+    for (int t = 2; t <= nz + 1; ++t) {
+        const o3_vert *z = &Z[t - 1];
+        v3 zprev = Z[t - 2].p;
+        v3 wo = vnorm(vsub(zprev, z->p));
+        if (z->m->emissive && t - 1 <= D) {   /* s = 0: the eye sub-path reached an emitter */
+            double le[3];
+            emitted(s, z->prim, z->b1, z->b2, wo, le);
+            if (le[0] > 0 || le[1] > 0 || le[2] > 0) {
+                double w = o3_weight(s, p, Y, Z, 0, t - 1);
+                for (int k = 0; k < 3; ++k) L[k] += w * z->beta[k] * le[k];
+            }
+        }
+        if (z->m->delta) continue;
+        for (int sn = 1; sn <= ny && sn + t - 1 <= D; ++sn) {
+            const o3_vert *y = &Y[sn - 1];
+            if (sn >= 2 && y->m->delta) continue;
+            double cy, cz, r2 = o3_geo(y->p, y->n, z->p, z->n, &cy, &cz);
+            v3 wyz = vscl(vsub(z->p, y->p), 1.0 / sqrt(r2));
+            double fy[3], fz[3];
+            if (sn == 1) emitted(s, y->prim, y->b1, y->b2, wyz, fy);
+            else bsdf_eval(y->m, y->n, vnorm(vsub(Y[sn - 2].p, y->p)), wyz, fy);
+            bsdf_eval(z->m, z->n, wo, vscl(wyz, -1.0), fz);
+            double g = (sn == 1 ? fmax(cy, 0.0) : fabs(cy)) * fabs(cz) / r2;
+            double c[3];
+            int any = 0;
+            for (int k = 0; k < 3; ++k) { c[k] = y->beta[k] * fy[k] * g * fz[k] * z->beta[k]; any |= c[k] > 0; }
+            if (!any || !visible(s, y->p, y->prim, z->p, z->prim)) continue;
+            double w = o3_weight(s, p, Y, Z, sn, sn + t - 1);
+            for (int k = 0; k < 3; ++k) L[k] += w * c[k];
+        }
+    }
+    for (int k = 0; k < 3; ++k) c->frame[3 * pix + k] += L[k];
+    /* t = 1: light tracing, the light vertex y_{s-1} joined to the pinhole */
+    const double NL = (double)s->W * s->H;
+    for (int sn = 1; sn <= ny && sn <= D; ++sn) {
+        const o3_vert *y = &Y[sn - 1];
+        if (sn >= 2 && y->m->delta) continue;
+        v3 dc = vsub(y->p, s->cam_p);
+        double r2 = vdot(dc, dc);
+        v3 w = vscl(dc, 1.0 / sqrt(r2));
+        int tp;
+        double cf;
+        if (!o3_project(s, w, &tp, &cf)) continue;
+        double fy[3];
+        v3 to_cam = vscl(w, -1.0);
+        if (sn == 1) emitted(s, y->prim, y->b1, y->b2, to_cam, fy);
+        else bsdf_eval(y->m, y->n, vnorm(vsub(Y[sn - 2].p, y->p)), to_cam, fy);
+        double cy = vdot(y->n, to_cam);
+        double g = (sn == 1 ? fmax(cy, 0.0) : fabs(cy)) / r2 * o3_we(s, cf) / NL;
+        double cc[3];
+        int any = 0;
+        for (int k = 0; k < 3; ++k) { cc[k] = y->beta[k] * fy[k] * g; any |= cc[k] > 0; }
+        if (!any || !visible(s, y->p, y->prim, s->cam_p, -1)) continue;
+        /* the eye side of this path is the pinhole alone */
+        double wgt = o3_weight(s, p, Y, Z, sn, sn);
+        int *cnt = &c->spl_n[py];
+        size_t at = (size_t)py * s->W * D + (size_t)*cnt;
+        c->spl_pix[at] = tp;
+        for (int k = 0; k < 3; ++k) c->spl_val[3 * at + k] = wgt * cc[k];
+        (*cnt)++;
+    }
+}
+
+static void o3_row(void *ctx, int py)
+{
+    const o3_ctx *c = (const o3_ctx *)ctx;
+    c->spl_n[py] = 0;
+    for (int px = 0; px < c->s->W; ++px) o3_pixel(c, px, py);
+}
+
+static int o3_render(const scene_t *s, const or_params *p, double *sum, double *sumsq)
+{
+    if (p->max_depth < 1 || p->max_depth > O3_MAXD) return -1;
+    int threads = p->threads > 0 ? p->threads : 1;
+    size_t npix = (size_t)s->W * s->H;
+    o3_ctx c;
+    c.s = s; c.p = p;
+    c.frame = (double *)calloc(npix * 3, sizeof(double));
+    c.spl_pix = (int *)malloc(sizeof(int) * npix * (size_t)p->max_depth);
+    c.spl_val = (double *)malloc(sizeof(double) * 3 * npix * (size_t)p->max_depth);
+    c.spl_n = (int *)calloc((size_t)s->H, sizeof(int));
+    for (int it = 0; it < p->n_iter; ++it) {
+        c.iter = p->first_iter + it;
+        memset(c.frame, 0, sizeof(double) * npix * 3);
+        parallel_for(s->H, threads, o3_row, &c);
+        /* splats in row order, so the sums do not depend on the thread count */
+        for (int py = 0; py < s->H; ++py)
+            for (int e = 0; e < c.spl_n[py]; ++e) {
+                size_t at = (size_t)py * s->W * p->max_depth + (size_t)e;
+                for (int k = 0; k < 3; ++k) c.frame[3 * c.spl_pix[at] + k] += c.spl_val[3 * at + k];
+            }
+        for (size_t i = 0; i < npix * 3; ++i) { sum[i] += c.frame[i]; sumsq[i] += c.frame[i] * c.frame[i]; }
+    }
+    free(c.frame); free(c.spl_pix); free(c.spl_val); free(c.spl_n);
+    return 0;
+}
+
 int or_render(void *sp, const or_params *p, double *sum, double *sumsq, or_stats *stats)
 {
     scene_t *s = (scene_t *)sp;
     int npix = s->W * s->H;
     int threads = p->threads > 0 ? p->threads : 1;
     if (stats) memset(stats, 0, sizeof(*stats));
+    if (p->method == 2) return o3_render(s, p, sum, sumsq);
     if (p->method == 0) {
         for (int it = 0; it < p->n_iter; ++it) {
             eye_ctx c = {s, p, sum, sumsq, p->first_iter + it, NULL};

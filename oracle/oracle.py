@@ -31,7 +31,7 @@ class Params(ctypes.Structure):
         ("max_depth", ctypes.c_int), ("n_light", ctypes.c_int), ("cand_cap", ctypes.c_int),
         ("repeats", ctypes.c_int), ("u_max", ctypes.c_int), ("class_filter", ctypes.c_int),
         ("threads", ctypes.c_int), ("seed", ctypes.c_uint32), ("pilot", ctypes.c_int),
-        ("chain_cap", ctypes.c_long), ("cost_cap", ctypes.c_double),
+        ("chain_cap", ctypes.c_long), ("cost_cap", ctypes.c_double), ("o3_weights", ctypes.c_int),
     ]
 
 
@@ -140,11 +140,15 @@ class Scene:
         return t, prim
 
     def render(self, method=0, n_iter=1, first_iter=0, max_depth=8, n_light=4096, cand_cap=400, repeats=5,
-               u_max=4, class_filter=0, threads=None, seed=0, pilot=16, chain_cap=1 << 21, cost_cap=4096.0):
-        """Returns (sum, sumsq, stats): per-pixel sums of per-iteration values, shape (H, W, 3)."""
+               u_max=4, class_filter=0, threads=None, seed=0, pilot=16, chain_cap=1 << 21, cost_cap=4096.0,
+               o3_weights=0):
+        """Returns (sum, sumsq, stats): per-pixel sums of per-iteration values, shape (H, W, 3).
+
+        method 0: O1 (PT + NEE), 1: O2 (proxy-sampling BDPT), 2: O3 (plain BDPT; o3_weights 0 balance
+        heuristic, 1 uniform weights, 2 light tracing alone)."""
         threads = threads or os.cpu_count() or 1
         p = Params(method, n_iter, first_iter, max_depth, n_light, cand_cap, repeats, u_max, class_filter,
-                   threads, seed, pilot, chain_cap, cost_cap)
+                   threads, seed, pilot, chain_cap, cost_cap, o3_weights)
         s = np.zeros((self.H, self.W, 3))
         s2 = np.zeros((self.H, self.W, 3))
         st = Stats()
