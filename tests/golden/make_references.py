@@ -1,7 +1,13 @@
 """Writes the oracle reference images used by the GPU parity tests.
 
-Only the FP64 oracle (oracle/) is called: O1 (path tracing with next-event estimation, the
-plain definition of the path integral). Output per scene: per-pixel mean of the per-iteration
+Only the FP64 oracle (oracle/) is called. The small Cornell box uses O1 (path tracing with
+next-event estimation, the plain definition of the path integral). The projector scene uses O3
+(plain bidirectional path tracing with every (s, t) strategy): its dim walls are lit through
+the lens, and the light paths that reach them there are found by path tracing only when a BSDF
+sample happens to hit the small emitter through the lens. The per-pixel sample mean of such an
+estimator is skewed, and its variance estimate comes out low exactly where the mean is low,
+so O1 at any affordable sample count misreports its own error there. O3 reaches the same paths
+by light tracing and vertex connections. Output per scene: per-pixel mean of the per-iteration
 pixel values, the variance of that mean, and the number of iterations, as a compressed .npz.
 
 usage: python tests/golden/make_references.py [cfg0|cfg1_128|all] [spp]
@@ -21,14 +27,14 @@ from synth import scenes  # noqa: E402
 HERE = os.path.dirname(os.path.abspath(__file__))
 
 REFS = {
-    # name: (scene builder, max depth, default spp)
-    "cfg0": (lambda: scenes.cornell_glass(64, 64), 8, 65536),
-    "cfg1_128": (lambda: scenes.projector(128, 128), 12, 16384),
+    # name: (scene builder, max depth, default spp, oracle method, file tag)
+    "cfg0": (lambda: scenes.cornell_glass(64, 64), 8, 65536, 0, "o1"),
+    "cfg1_128": (lambda: scenes.projector(128, 128), 12, 8192, 2, "o3"),
 }
 
 
-def make(name, spp=None, batch=1024):
-    build, depth, default = REFS[name]
+def make(name, spp=None, batch=256):
+    build, depth, default, method, tag = REFS[name]
     spp = spp or default
     S = O.Scene(build())
     s = np.zeros((S.H, S.W, 3))
@@ -36,15 +42,15 @@ def make(name, spp=None, batch=1024):
     t0 = time.time()
     for first in range(0, spp, batch):
         n = min(batch, spp - first)
-        a, b, _ = S.render(method=0, n_iter=n, first_iter=first, max_depth=depth, seed=12345)
+        a, b, _ = S.render(method=method, n_iter=n, first_iter=first, max_depth=depth, seed=12345)
         s += a
         s2 += b
         print(f"{name}: {first + n}/{spp} spp, {time.time() - t0:.0f} s", flush=True)
     mean = s / spp
     var_mean = np.maximum(s2 / spp - mean * mean, 0.0) / spp
-    out = os.path.join(HERE, f"{name}_o1_ref.npz")
+    out = os.path.join(HERE, f"{name}_{tag}_ref.npz")
     np.savez_compressed(out, mean=mean.astype(np.float64), var_mean=var_mean.astype(np.float64), spp=spp,
-                        max_depth=depth, seed=12345)
+                        max_depth=depth, seed=12345, method=method)
     print("wrote", out, flush=True)
 
 

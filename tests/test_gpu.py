@@ -339,11 +339,13 @@ def test_zz_config0_parity_with_oracle_reference(gpu):
 
 def test_zz_config1_128_parity_with_oracle_reference(gpu):
     """The projector scene of config 1 at 128 x 128 (depth 12), every strategy, 256 eye and light
-    subspaces and 100 specular subspaces (the grouped centroid search), vs the stored O1
-    reference image."""
+    subspaces and 100 specular subspaces (the grouped centroid search), vs the stored O3
+    reference image (plain bidirectional path tracing: path tracing with next-event estimation
+    reaches the lens-lit dim walls only through rare emitter hits, and its per-pixel variance
+    estimate there is too low where its mean is low)."""
     from synth import scenes
     torch, pt = gpu
-    ref = np.load(os.path.join(GOLD, "cfg1_128_o1_ref.npz"))
+    ref = np.load(os.path.join(GOLD, "cfg1_128_o3_ref.npz"))
     N = 2048
     say(f"config 1 at 128x128 parity, {N} spp")
     flags = (pt.PT_FLAG_NEE | pt.PT_FLAG_PROXY | pt.PT_FLAG_MIS | pt.PT_FLAG_GAMMA | pt.PT_FLAG_TILES |
