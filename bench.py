@@ -18,10 +18,51 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+FP32_PEAK_TFLOPS = 157.3   # MI355X vector FP32 (256 CUs, 2.4 GHz, packed FMA)
+# algorithmic FP32 operations per unit of traversal work (an FMA counts two):
+# a 4-wide node visit is four slab tests, each 6 FMAs for the six plane distances, 6 min/max
+# for the entry distance, 6 for the exit distance and 1 compare (25 per child);
+# a triangle test is Moller-Trumbore: two cross products (18), four dot products (20), one
+# reciprocal, the translation (3), three scalings by the reciprocal (3), 7 for the determinant,
+# barycentric and distance bounds (52)
+FLOP_NODE = 100
+FLOP_TRI = 52
+PMC_FILE = os.path.join(ROOT, "profiles", "pmc_k_recip_projector_512.txt")
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash():
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2503_23412_amd", "csrc")
+    for f in sorted(glob.glob(os.path.join(csrc, "*.h")) + glob.glob(os.path.join(csrc, "*.hip")),
+                    key=os.path.basename):
+        h.update(os.path.basename(f).encode())
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def recorded_traffic():
+    """HBM bytes per k_recip launch from the committed hardware-counter summary, or None when
+    the kernel sources no longer hash to the value the counters were taken with."""
+    try:
+        txt = open(PMC_FILE).read()
+    except OSError:
+        return None
+    vals = {}
+    for line in txt.splitlines():
+        line = line.strip()
+        for key in ("traffic_bytes_per_launch:", "source_sha256:"):
+            if line.startswith(key):
+                vals[key] = line[len(key):].strip()
+    if vals.get("source_sha256:") != kernel_source_hash() or "traffic_bytes_per_launch:" not in vals:
+        return None
+    return float(vals["traffic_bytes_per_launch:"])
 
 
 def cpu_baseline(sc, params, budget_s=20.0):
@@ -106,18 +147,23 @@ def main():
     st = tim[-1]
     rays = st["rays_extend_eye"] + st["rays_extend_light"] + st["rays_shadow"] + st["rays_proxy"] + st["rays_recip"]
     n_launch = params["max_depth"]
-    # algorithmic bytes: every visited 128-byte node, every tested 48-byte triangle record; eye
-    # extension also reads the ray (32 B) and queue index (4 B) and writes the hit (16 B); a chain
-    # sample reads its 80-byte candidate record once per wavefront step (1/64 per sample)
-    ext_bytes = stc["node_visits"] * 128 + stc["tri_tests"] * 48 + stc["rays_extend_eye"] * (32 + 4 + 16)
-    a_bytes = stc["node_visits_stage_a"] * 128 + stc["tri_tests_stage_a"] * 48 + stc["n_samples_stage_a"] * 80 / 64
+    # algorithmic work of the two traversal kernels: FP32 operations of every node visit and
+    # triangle test (FLOP_NODE, FLOP_TRI); the bytes of every visited 128-byte node and tested
+    # 48-byte triangle record are reported beside them (those reads are served from the caches:
+    # the measured HBM traffic is the `traffic` field)
+    ext_flops = stc["node_visits"] * FLOP_NODE + stc["tri_tests"] * FLOP_TRI
+    a_flops = stc["node_visits_stage_a"] * FLOP_NODE + stc["tri_tests_stage_a"] * FLOP_TRI
+    ext_bytes = stc["node_visits"] * 128 + stc["tri_tests"] * 48
+    a_bytes = stc["node_visits_stage_a"] * 128 + stc["tri_tests_stage_a"] * 48
     cands = [
-        {"kernel": "k_extend (eye closest hit)", "ms_per_step": ms_ext, "launches": n_launch, "bytes": ext_bytes},
-        {"kernel": "k_recip (reciprocal chains, stage A)", "ms_per_step": ms_a, "launches": 1, "bytes": a_bytes},
+        {"kernel": "k_extend (eye closest hit)", "ms_per_step": ms_ext, "launches": n_launch, "flops": ext_flops,
+         "bytes": ext_bytes, "traffic": None},
+        {"kernel": "k_recip (reciprocal chains, stage A)", "ms_per_step": ms_a, "launches": 1, "flops": a_flops,
+         "bytes": a_bytes, "traffic": recorded_traffic() if args.config == 1 else None},
     ]
     dom = max(cands, key=lambda c: c["ms_per_step"])
     per_launch_s = dom["ms_per_step"] / dom["launches"] * 1e-3
-    achieved = dom["bytes"] / dom["launches"] / per_launch_s / 1e9 if per_launch_s > 0 else 0.0
+    achieved = dom["flops"] / dom["launches"] / per_launch_s / 1e12 if per_launch_s > 0 else 0.0
     value = W * H * args.steps / dt
     out = {
         "metric": "full-path samples/s",
@@ -145,10 +191,14 @@ def main():
                                      "n_proxy_attempts", "n_proxy_valid", "n_pool", "n_connections", "n_lt_splats",
                                      "n_nan", "chain_len_max")},
         "ms_breakdown": {"eye_extension": ms_ext, "reciprocal_block": ms_rec, "reciprocal_stage_a": ms_a},
-        "roofline": {"kernel": dom["kernel"], "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "bytes_per_launch": dom["bytes"] / dom["launches"],
-                     "ms_per_launch": dom["ms_per_step"] / dom["launches"]},
+        "roofline": {"kernel": dom["kernel"], "bound": "alu", "achieved": achieved, "peak": FP32_PEAK_TFLOPS,
+                     "unit": "TFLOP/s", "frac": achieved / FP32_PEAK_TFLOPS, "traffic": dom["traffic"],
+                     "flops_per_launch": dom["flops"] / dom["launches"],
+                     "ms_per_launch": dom["ms_per_step"] / dom["launches"],
+                     "node_tri_bytes_per_launch": dom["bytes"] / dom["launches"],
+                     "node_tri_GBs": dom["bytes"] / dom["launches"] / per_launch_s / 1e9 if per_launch_s > 0 else 0.0,
+                     "hbm_frac_of_traffic": (dom["traffic"] / per_launch_s / 1e9 / HBM_PEAK_GBS
+                                             if dom["traffic"] and per_launch_s > 0 else None)},
     }
     if not args.no_cpu:
         log("cpu baseline (oracle)")

@@ -57,6 +57,17 @@ def _render(gpu, sc, N, max_light=1024, subspaces=(8, 8), **params):
     return m, v, tot
 
 
+def _furnace_ok(m, v, expect, tag):
+    """Per-pixel bar of the grey furnaces: at least 99.9 % of pixels within 4 standard errors of
+    the closed form. The three channels of a grey furnace carry the same value, so pixels (not
+    channels) are counted; furnace images are 48 x 48, so the bar allows two of 2,304 pixels
+    beyond 4 (at 16 x 16 it would allow none and fail by chance in a few percent of runs)."""
+    z = (m[..., 0] - expect) / np.sqrt(v[..., 0] + 1e-30)
+    frac = (np.abs(z) < 4).mean()
+    say(f"{tag}: mean {m.mean():.5f} expect {expect:.5f} frac |z|<4 {frac:.5f} max|z| {np.abs(z).max():.2f}")
+    return frac >= 0.999
+
+
 # ------------------------------------------------------------------------------ reciprocal
 def _closed(f, q, B):
     g = 1.0 - f / (q * B)
@@ -151,7 +162,7 @@ def test_diffuse_furnace(gpu, proxy):
     from synth import scenes
     torch, pt = gpu
     a, K = 0.5, (16 if proxy == "full_depth16" else 6)
-    sc = scenes.furnace(albedo=a, le=1.0, width=16, height=16)
+    sc = scenes.furnace(albedo=a, le=1.0, width=48, height=48)
     say(f"diffuse furnace {proxy}")
     flags = {"pt_nee": pt.PT_FLAG_NEE, "proxy": pt.PT_FLAG_NEE | pt.PT_FLAG_PROXY,
              "connections": pt.PT_FLAG_NEE | pt.PT_FLAG_SPC | pt.PT_FLAG_LT,
@@ -160,8 +171,7 @@ def test_diffuse_furnace(gpu, proxy):
              pt.PT_FLAG_LT}[proxy.replace("_depth16", "")]
     m, v, st = _render(gpu, sc, 512, max_depth=K, n_light=1024, cand_cap=128, flags=flags)
     expect = (1 - a ** K) / (1 - a)
-    z = (m - expect) / np.sqrt(v + 1e-30)
-    assert (np.abs(z) < 4).mean() >= 0.999, np.abs(z).max()
+    assert _furnace_ok(m, v, expect, f"diffuse furnace {proxy}")
     assert abs(m.mean() - expect) < 4 * math.sqrt(v.mean() / m.size)
     assert st["n_nan"] == 0
 
@@ -173,7 +183,7 @@ def test_multi_scene_graph_and_autotune(gpu):
     torch, pt = gpu
     K = 6
     flags = pt.PT_FLAG_NEE | pt.PT_FLAG_PROXY | pt.PT_FLAG_MIS | pt.PT_FLAG_GAMMA | pt.PT_FLAG_SPC | pt.PT_FLAG_LT
-    specs = [(0.5, 16, 16), (0.3, 24, 8)]
+    specs = [(0.5, 48, 48), (0.3, 64, 36)]
     S, A, A2 = [], [], []
     for a, w, h in specs:
         sc = pt.Scene(scenes.furnace(albedo=a, le=1.0, width=w, height=h), max_light_paths=1024)
@@ -188,18 +198,16 @@ def test_multi_scene_graph_and_autotune(gpu):
     pt.render_scenes(S, A, A2, N // 2, prm2)   # the cached graph, continued
     torch.cuda.synchronize()
     for (a, w, h), acc, acc2 in zip(specs, A, A2):
-        m = (acc / N).double().cpu().numpy()
-        v = np.maximum((acc2 / N).double().cpu().numpy() - m * m, 0) / N
+        m = (acc / N).double().cpu().numpy().reshape(h, w, 3)
+        v = np.maximum((acc2 / N).double().cpu().numpy().reshape(h, w, 3) - m * m, 0) / N
         expect = (1 - a ** K) / (1 - a)
-        z = (m - expect) / np.sqrt(v + 1e-30)
-        say(f"multi-scene furnace a={a}: mean {m.mean():.5f} expect {expect:.5f} max|z| {np.abs(z).max():.2f}")
-        assert (np.abs(z) < 4).mean() >= 0.999
+        assert _furnace_ok(m, v, expect, f"multi-scene furnace a={a}")
     for sc in S:
         sc.release()
     # autotuning renders its timed iterations into the accumulators like any other
-    sc = pt.Scene(scenes.furnace(albedo=0.5, le=1.0, width=16, height=16), max_light_paths=1024)
+    sc = pt.Scene(scenes.furnace(albedo=0.5, le=1.0, width=48, height=48), max_light_paths=1024)
     sc.build_subspaces(n_eye=8, n_spec=8)
-    acc = torch.zeros(16 * 16 * 3, device="cuda")
+    acc = torch.zeros(48 * 48 * 3, device="cuda")
     acc2 = torch.zeros_like(acc)
     r = sc.autotune(acc, acc2, iteration=0, max_depth=K, n_light=1024, cand_cap=128, flags=flags)
     say("autotune", r)
@@ -208,23 +216,21 @@ def test_multi_scene_graph_and_autotune(gpu):
     for k in range(n, 512):
         sc.render_iteration(acc, acc2, iteration=k, max_depth=K, n_light=1024, cand_cap=128, flags=flags)
     torch.cuda.synchronize()
-    m = (acc / 512).double().cpu().numpy()
-    v = np.maximum((acc2 / 512).double().cpu().numpy() - m * m, 0) / 512
-    z = (m - (1 - 0.5 ** K) / 0.5) / np.sqrt(v + 1e-30)
-    assert (np.abs(z) < 4).mean() >= 0.999
+    m = (acc / 512).double().cpu().numpy().reshape(48, 48, 3)
+    v = np.maximum((acc2 / 512).double().cpu().numpy().reshape(48, 48, 3) - m * m, 0) / 512
+    assert _furnace_ok(m, v, (1 - 0.5 ** K) / 0.5, "autotuned furnace")
     sc.release()
 
 
 def test_glass_furnace_through_proxy(gpu):
     from synth import scenes
     a, K = 0.5, 120
-    sc = scenes.furnace(albedo=a, le=1.0, glass_sphere=True, width=16, height=16, sphere_subdiv=2,
+    sc = scenes.furnace(albedo=a, le=1.0, glass_sphere=True, width=48, height=48, sphere_subdiv=2,
                         enclosure="sphere")
     say("glass furnace")
     m, v, st = _render(gpu, sc, 384, max_depth=K, n_light=1024, cand_cap=128)
     expect = (1 - a ** K) / (1 - a)
-    z = (m - expect) / np.sqrt(v + 1e-30)
-    assert (np.abs(z) < 4).mean() >= 0.999, np.abs(z).max()
+    assert _furnace_ok(m, v, expect, "glass furnace")
     assert st["n_proxy_valid"] > 0 and st["n_recip_truncated"] == 0 and st["n_nan"] == 0
 
 
