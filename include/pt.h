@@ -144,6 +144,8 @@ typedef struct {
                                            kernel, HIP events on the stream (PT_FLAG_TIMING) */
     double node_visits_recip, tri_tests_recip;   /* traversal work of the pilot and the chain rounds */
     double node_visits_stage_a, tri_tests_stage_a, n_samples_stage_a;   /* the first chain kernel's */
+    double n_drawn_stage_a, n_drawn_pilot;   /* f/q samples drawn (64 per wavefront step) by the first
+                                                chain kernel and by the pilot */
     double chain_len_hist[24];       /* reciprocal chains by samples used: bin b counts [2^b, 2^(b+1)) */
     double chain_len_max;            /* longest chain of the iteration (samples) */
 } pt_iter_stats;

@@ -322,11 +322,13 @@ __device__ __forceinline__ bool isect(const TriIsect &T, float3 o, float3 d, flo
 }
 
 // The traversal stack lives in LDS, column-major (entry k of thread i at k * nthreads + i) so
-// that a wavefront's pushes and pops hit 64 different banks.
-template <bool ANY, bool COUNT>
-__device__ __forceinline__ bool traverse(const SceneDev &S, float3 o, float3 d, float tmin, float tmax, int ign0,
-                                         int ign1, int *stk, int stride, Hit &h, uint32_t *visits = nullptr,
-                                         uint32_t *tests = nullptr)
+// that a wavefront's pushes and pops hit 64 different banks. `any` ends the walk at the first
+// hit (visibility); it is a run-time argument so that a kernel can trace visibility and
+// closest-hit rays at one call site, and constant-folds where the caller passes a constant.
+template <bool COUNT>
+__device__ __forceinline__ bool traverse_rt(const SceneDev &S, float3 o, float3 d, float tmin, float tmax, int ign0,
+                                            int ign1, bool any, int *stk, int stride, Hit &h,
+                                            uint32_t *visits = nullptr, uint32_t *tests = nullptr)
 {
     const float3 inv = f3(1.0f / d.x, 1.0f / d.y, 1.0f / d.z);
     const float3 oi = o * inv;
@@ -371,36 +373,52 @@ __device__ __forceinline__ bool traverse(const SceneDev &S, float3 o, float3 d, 
                     if (isect(T, o, d, tmin, tmax, t, b1, b2)) {
                         if (t < h.t || (t == h.t && h.tri >= 0 && pid < S.tris[h.tri].prim)) {
                             h.t = t; h.b1 = b1; h.b2 = b2; h.tri = i;
-                            if (ANY) return true;
+                            if (any) return true;
                         }
                     }
                 }
             }
         }
-        // inner children: push far-to-near so the nearest is popped first
-        int idx[4];
-        int n = 0;
+        // inner children still in front of the nearest hit, sorted by entry distance with a
+        // five-comparator network in registers (children that are not taken sort last)
+        float key[4];
+        int cid[4];
 #pragma unroll
-        for (int k = 0; k < 4; ++k)
-            if (hitc[k] && cna[k] == 0 && cha[k] >= 0 && tn[k] <= h.t) idx[n++] = k;
-        // insertion sort by descending entry distance (n <= 4)
-        for (int a = 1; a < n; ++a) {
-            const int v = idx[a];
-            int b = a - 1;
-            while (b >= 0 && tn[idx[b]] < tn[v]) { idx[b + 1] = idx[b]; --b; }
-            idx[b + 1] = v;
+        for (int k = 0; k < 4; ++k) {
+            const bool take = hitc[k] && cna[k] == 0 && cha[k] >= 0 && tn[k] <= h.t;
+            key[k] = take ? tn[k] : 3.0e38f;
+            cid[k] = take ? cha[k] : -1;
         }
-        // the nearest child continues in a register; the stack holds PT_STACK entries and a 4-wide
-        // tree needs at most 3 per level, so a push beyond it can only come from a malformed tree
-        // and is dropped
-        if (n > 0) {
-            for (int a = 0; a < n - 1; ++a)
-                if (sp < PT_STACK) stk[(sp++) * stride] = cha[idx[a]];
-            node = cha[idx[n - 1]];
+#define PT_CSWAP(a, b)                                                                     \
+        {                                                                                  \
+            const bool sw = key[b] < key[a];                                               \
+            const float ka = key[a], kb = key[b];                                          \
+            const int ca = cid[a], cb = cid[b];                                            \
+            key[a] = sw ? kb : ka; key[b] = sw ? ka : kb;                                  \
+            cid[a] = sw ? cb : ca; cid[b] = sw ? ca : cb;                                  \
+        }
+        PT_CSWAP(0, 1) PT_CSWAP(2, 3) PT_CSWAP(0, 2) PT_CSWAP(1, 3) PT_CSWAP(1, 2)
+#undef PT_CSWAP
+        // the nearest child continues in a register, the others are pushed far to near; the
+        // stack holds PT_STACK entries and a 4-wide tree needs at most 3 per level, so a push
+        // beyond it can only come from a malformed tree and is dropped
+        if (cid[0] >= 0) {
+#pragma unroll
+            for (int k = 3; k >= 1; --k)
+                if (cid[k] >= 0 && sp < PT_STACK) stk[(sp++) * stride] = cid[k];
+            node = cid[0];
         } else {
             if (sp == 0) break;
             node = stk[(--sp) * stride];
         }
     }
     return h.tri >= 0;
+}
+
+template <bool ANY, bool COUNT>
+__device__ __forceinline__ bool traverse(const SceneDev &S, float3 o, float3 d, float tmin, float tmax, int ign0,
+                                         int ign1, int *stk, int stride, Hit &h, uint32_t *visits = nullptr,
+                                         uint32_t *tests = nullptr)
+{
+    return traverse_rt<COUNT>(S, o, d, tmin, tmax, ign0, ign1, ANY, stk, stride, h, visits, tests);
 }

@@ -519,6 +519,46 @@ __device__ __forceinline__ float side_prob(const MatDev &m, float3 n, float3 w)
     return m.type == MAT_DIELECTRIC ? 0.5f : (dot3(n, w) > 0.0f ? 1.0f : 0.0f);
 }
 
+// f/q of the u = 1 class A sample that reached the emitter at y (normal ny)
+__device__ __forceinline__ float fq_u1_a(const SceneDev &S, float3 v, float3 vn, const MatDev &mv, float3 y, float3 ny)
+{
+    const float invA = 1.0f / S.em_area;
+    const float3 dv = v - y;
+    const float d2 = dot3(dv, dv);
+    const float3 w = dv * rsqrtf(d2);
+    const float c0 = dot3(ny, w), cv = fabsf(dot3(vn, w));
+    const float f = c0 > 0.0f ? invA * (c0 / PT_PI) * cv / d2 : 0.0f;
+    const float q3 = side_prob(mv, vn, -w) * (cv / PT_PI) * fabsf(c0) / d2;
+    return f / (0.5f * (invA + q3));
+}
+// f/q of the u = 1 class B sample whose diffuse vertex y_1 is the hit h1 (control vertex y_0)
+__device__ __forceinline__ float fq_u1_b(const SceneDev &S, float3 v, float3 vn, const MatDev &mv, float3 y0,
+                                         float3 n0, const Hit &h1)
+{
+    const float3 y1 = tri_point(S, h1.tri, h1.b1, h1.b2);
+    const float3 n1 = S.shade[h1.tri].n;
+    const MatDev m1 = S.mats[S.shade[h1.tri].mat];
+    const float3 a = y1 - y0;
+    const float d01 = dot3(a, a);
+    const float3 w01 = a * rsqrtf(d01);
+    const float3 b = v - y1;
+    const float d1v = dot3(b, b);
+    const float3 w1v = b * rsqrtf(d1v);
+    const float c0 = dot3(n0, w01);
+    const float p1 = c0 > 0.0f ? (c0 / PT_PI) * fabsf(dot3(n1, w01)) / d01 : 0.0f;
+    const float cv = fabsf(dot3(vn, w1v));
+    const float f = p1 * bsdf_pdf(m1, n1, -w01, w1v) * cv / d1v;
+    const float q3 = side_prob(mv, vn, -w1v) * (cv / PT_PI) * fabsf(dot3(n1, w1v)) / d1v;
+    return f / (0.5f * (p1 + q3));
+}
+
+// The sample's rays are traced at one call site: each trip of the loop below traces the ray the
+// sample's state asks for and then advances the state, so lanes that took different strategies
+// (u = 1) or reached different vertices still traverse together, and the traversal is inlined
+// once. Modes: 0 u = 1 class A from the light (visibility y -> y_{s-1}), 1 u = 1 class A from
+// y_{s-1} (toward the light), 2 / 3 u = 1 class B from y_0 / from y_{s-1} (ray to y_1, then the
+// visibility of the other side), 4 u >= 2 (the retrace through the specular run, then for class
+// B the visibility y_0 -> y_1).
 __device__ float fq_sample(Ctx &C, const Cand &c, Rng &r)
 {
     const SceneDev &S = C.S;
@@ -527,82 +567,89 @@ __device__ float fq_sample(Ctx &C, const Cand &c, Rng &r)
     const int vt = fbits(c.v.w);
     const float3 vn = S.shade[vt].n;
     const MatDev mv = S.mats[S.shade[vt].mat];
-    const float invA = 1.0f / S.em_area;
+    const float3 y0 = xyz(c.hc);     // control vertex of class B
+    const int t0 = fbits(c.hc.w);
+    const float3 n0 = cls ? S.shade[t0].n : f3(0.0f, 0.0f, 1.0f);
+    // the ray of the next trip
+    float3 ro = v, rd = f3(0.0f, 0.0f, 1.0f);
+    float rmax = 3.0e38f;
+    int ig0 = vt, ig1 = -1;
+    bool any = false;
+    // sample state
+    int mode, k = 1;
+    float3 yl = v, nyl = vn;         // mode 0: the emitter point
+    Hit h1;                          // modes 2, 3: y_1
+    h1.tri = -1; h1.b1 = h1.b2 = 0.0f; h1.t = 0.0f;
+    float f = 1.0f, q = 1.0f;
+    float3 w = rd;
     if (u == 1) {
         const bool from_spec = rng_f(r) >= 0.5f;
         if (cls == 0) {
-            float3 y, ny;
             if (!from_spec) {
                 const float a = rng_f(r), b = rng_f(r), d = rng_f(r);
                 const LPoint L = sample_emitter(S, a, b, d);
-                if (occluded(C, L.p, L.tri, v, vt)) return 0.0f;
-                y = L.p; ny = L.n;
+                yl = L.p; nyl = L.n;
+                const float3 dd = v - L.p;
+                const float dist = sqrtf(dot3(dd, dd));
+                ro = L.p; rd = dd * (1.0f / dist); rmax = dist * 0.9999f; ig0 = L.tri; ig1 = vt; any = true;
+                mode = 0;
             } else {
                 float sp;
-                const float3 w = spec_start(mv, vn, r, sp);
-                Hit h;
-                if (!closest(C, v, w, vt, h)) return 0.0f;
-                if (!(S.mats[S.shade[h.tri].mat].flags & MF_EMIT)) return 0.0f;
-                y = tri_point(S, h.tri, h.b1, h.b2); ny = S.shade[h.tri].n;
+                rd = spec_start(mv, vn, r, sp);
+                mode = 1;
             }
-            const float3 dv = v - y;
-            const float d2 = dot3(dv, dv);
-            const float3 w = dv * rsqrtf(d2);
-            const float c0 = dot3(ny, w), cv = fabsf(dot3(vn, w));
-            const float f = c0 > 0.0f ? invA * (c0 / PT_PI) * cv / d2 : 0.0f;
-            const float q3 = side_prob(mv, vn, -w) * (cv / PT_PI) * fabsf(c0) / d2;
-            return f / (0.5f * (invA + q3));
-        }
-        // class B: g = y_1 (diffuse), control vertex y_0 on the light
-        const float3 y0 = xyz(c.hc);
-        const int t0 = fbits(c.hc.w);
-        const float3 n0 = S.shade[t0].n;
-        Hit h;
-        if (!from_spec) {
-            const float a = rng_f(r), b = rng_f(r);
-            if (!closest(C, y0, cos_hemi(n0, a, b), t0, h)) return 0.0f;
-            if (S.mats[S.shade[h.tri].mat].flags & MF_SPEC) return 0.0f;
-            if (occluded(C, tri_point(S, h.tri, h.b1, h.b2), h.tri, v, vt)) return 0.0f;
         } else {
-            float sp;
-            const float3 w = spec_start(mv, vn, r, sp);
-            if (!closest(C, v, w, vt, h)) return 0.0f;
-            if (S.mats[S.shade[h.tri].mat].flags & MF_SPEC) return 0.0f;
-            if (occluded(C, y0, t0, tri_point(S, h.tri, h.b1, h.b2), h.tri)) return 0.0f;
+            if (!from_spec) {
+                const float a = rng_f(r), b = rng_f(r);
+                ro = y0; rd = cos_hemi(n0, a, b); ig0 = t0;
+                mode = 2;
+            } else {
+                float sp;
+                rd = spec_start(mv, vn, r, sp);
+                mode = 3;
+            }
         }
-        const float3 y1 = tri_point(S, h.tri, h.b1, h.b2);
-        const float3 n1 = S.shade[h.tri].n;
-        const MatDev m1 = S.mats[S.shade[h.tri].mat];
-        const float3 a = y1 - y0;
-        const float d01 = dot3(a, a);
-        const float3 w01 = a * rsqrtf(d01);
-        const float3 b = v - y1;
-        const float d1v = dot3(b, b);
-        const float3 w1v = b * rsqrtf(d1v);
-        const float c0 = dot3(n0, w01);
-        const float p1 = c0 > 0.0f ? (c0 / PT_PI) * fabsf(dot3(n1, w01)) / d01 : 0.0f;
-        const float cv = fabsf(dot3(vn, w1v));
-        const float f = p1 * bsdf_pdf(m1, n1, -w01, w1v) * cv / d1v;
-        const float q3 = side_prob(mv, vn, -w1v) * (cv / PT_PI) * fabsf(dot3(n1, w1v)) / d1v;
-        return f / (0.5f * (p1 + q3));
-    }
-    // u >= 2: trace from y_{s-1} only. Dirac vertices enter through their lobe probabilities;
-    // the solid angle at each smooth vertex is carried to area at the next smooth vertex, and
-    // only the ratio of the two directions' Jacobians, (eta_b^2 |cos b|) / (eta_a^2 |cos a|),
-    // survives in f/q (etendue is conserved along a Dirac run).
-    float sp;
-    float3 w = spec_start(mv, vn, r, sp);
-    float q = sp * fabsf(dot3(vn, w)) / PT_PI;
-    float f = 1.0f;
-    {
+    } else {
+        // u >= 2: trace from y_{s-1} only. Dirac vertices enter through their lobe
+        // probabilities; the solid angle at each smooth vertex is carried to area at the next
+        // smooth vertex, and only the ratio of the two directions' Jacobians,
+        // (eta_b^2 |cos b|) / (eta_a^2 |cos a|), survives in f/q (etendue is conserved along a
+        // Dirac run).
+        float sp;
+        w = spec_start(mv, vn, r, sp);
+        q = sp * fabsf(dot3(vn, w)) / PT_PI;
         const float e = side_eta(mv, vn, w);
-        f *= e * e * fabsf(dot3(vn, w));   // numerator of the run leaving y_{s-1}
+        f = e * e * fabsf(dot3(vn, w));   // numerator of the run leaving y_{s-1}
+        rd = w;
+        mode = 4;
     }
-    float3 x = v;
-    int xt = vt;
-    for (int k = 1; k <= u; ++k) {
+    for (;;) {
         Hit h;
-        if (!closest(C, x, w, xt, h)) return 0.0f;
+        C.rays++;
+        const bool hit = traverse_rt<true>(S, ro, rd, S.tmin, rmax, ig0, ig1, any, C.stk, C.stride, h, &C.visits,
+                                           &C.tests);
+        if (mode == 0) return hit ? 0.0f : fq_u1_a(S, v, vn, mv, yl, nyl);
+        if (mode == 1) {
+            if (!hit || !(S.mats[S.shade[h.tri].mat].flags & MF_EMIT)) return 0.0f;
+            return fq_u1_a(S, v, vn, mv, tri_point(S, h.tri, h.b1, h.b2), S.shade[h.tri].n);
+        }
+        if (mode <= 3) {
+            if (k == 2) return hit ? 0.0f : fq_u1_b(S, v, vn, mv, y0, n0, h1);
+            // the ray to y_1, which must be diffuse; then the visibility of its other side
+            if (!hit || (S.mats[S.shade[h.tri].mat].flags & MF_SPEC)) return 0.0f;
+            h1 = h;
+            const float3 p1 = tri_point(S, h.tri, h.b1, h.b2);
+            const float3 a = mode == 2 ? p1 : y0, b = mode == 2 ? v : p1;
+            const float3 dd = b - a;
+            const float dist = sqrtf(dot3(dd, dd));
+            ro = a; rd = dd * (1.0f / dist); rmax = dist * 0.9999f; any = true;
+            ig0 = mode == 2 ? h.tri : t0; ig1 = mode == 2 ? vt : h.tri;
+            k = 2;
+            continue;
+        }
+        // mode 4
+        if (k > u) return hit ? 0.0f : (f > 0.0f ? f / q : 0.0f);   // class B: y_0 -> y_1 visibility
+        if (!hit) return 0.0f;
         const float3 y = tri_point(S, h.tri, h.b1, h.b2);
         const float3 ny = S.shade[h.tri].n;
         const MatDev m = S.mats[S.shade[h.tri].mat];
@@ -626,32 +673,33 @@ __device__ float fq_sample(Ctx &C, const Cand &c, Rng &r)
             }
             if (!(f > 0.0f)) return 0.0f;
             w = w_light;
-        } else {
-            const float ea = side_eta(m, ny, w_cam);
-            f /= ea * ea * fabsf(dot3(ny, w_cam));
-            if (cls == 0) {
-                if (!(m.flags & MF_EMIT)) return 0.0f;
-                const float c0 = dot3(ny, w_cam);
-                if (c0 <= 0.0f) return 0.0f;
-                f *= (1.0f / S.em_area) * c0 / PT_PI;
-            } else {
-                if (m.flags & MF_SPEC) return 0.0f;
-                const float3 y0 = xyz(c.hc);
-                const int t0 = fbits(c.hc.w);
-                const float3 n0 = S.shade[t0].n;
-                const float3 a = y - y0;
-                const float d2 = dot3(a, a);
-                const float3 w01 = a * rsqrtf(d2);
-                const float c0 = dot3(n0, w01);
-                if (c0 <= 0.0f) return 0.0f;
-                if (occluded(C, y0, t0, y, h.tri)) return 0.0f;
-                f *= (c0 / PT_PI) * fabsf(dot3(ny, w01)) / d2;
-                f *= bsdf_pdf(m, ny, -w01, w_cam);
-            }
+            ro = y; rd = w; ig0 = h.tri;
+            ++k;
+            continue;
         }
-        x = y; xt = h.tri;
+        // k == u: the vertex that closes the run
+        const float ea = side_eta(m, ny, w_cam);
+        f /= ea * ea * fabsf(dot3(ny, w_cam));
+        if (cls == 0) {
+            if (!(m.flags & MF_EMIT)) return 0.0f;
+            const float c0 = dot3(ny, w_cam);
+            if (c0 <= 0.0f) return 0.0f;
+            f *= (1.0f / S.em_area) * c0 / PT_PI;
+            return f > 0.0f ? f / q : 0.0f;
+        }
+        if (m.flags & MF_SPEC) return 0.0f;
+        const float3 a = y - y0;
+        const float d2 = dot3(a, a);
+        const float3 w01 = a * rsqrtf(d2);
+        const float c0 = dot3(n0, w01);
+        if (c0 <= 0.0f) return 0.0f;
+        f *= (c0 / PT_PI) * fabsf(dot3(ny, w01)) / d2;
+        f *= bsdf_pdf(m, ny, -w01, w_cam);
+        // visibility y_0 -> y (ignoring both triangles), traced on the next trip
+        const float dist = sqrtf(d2);
+        ro = y0; rd = w01; rmax = dist * 0.9999f; ig0 = t0; ig1 = h.tri; any = true;
+        k = u + 1;
     }
-    return f > 0.0f ? f / q : 0.0f;
 }
 
 // The pilot and the chains run one wavefront per candidate / chain: each step the 64 lanes
@@ -662,17 +710,27 @@ __device__ float fq_sample(Ctx &C, const Cand &c, Rng &r)
 #define RW 4                       // wavefronts per workgroup
 __device__ __forceinline__ float lane_get(float v, int l) { return __shfl(v, l); }
 
+// The pilot and the stage-A chains run on a persistent grid (a few workgroups per CU): each
+// wavefront takes the next item from a device counter until the items, counted on the device,
+// run out, so the launch does not depend on the number of candidates and no wavefront is
+// dispatched only to exit. Item k keeps its own Philox stream whichever wavefront runs it.
+__device__ __forceinline__ int next_item(unsigned long long *counter)
+{
+    int k = 0;
+    if (__lane_id() == 0) k = (int)atomicAdd(counter, 1ull);
+    return __shfl(k, 0);
+}
+
 // pilot: 64-sample steps until at least `pilot` samples with 8 non-zero values, or 256 samples
 __global__ void __launch_bounds__(64 * RW) k_pilot(SceneDev S, Cand *cand, const uint32_t *kept, int pilot,
                                                    uint32_t seed, float *runmax, unsigned long long *cnt)
 {
     const uint32_t iter = iter_of(cnt);
     __shared__ int stk[PT_STACK * 64 * RW];
-    const int wave = blockIdx.x * RW + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     const int n = (int)cnt[C_NKEPT];
     Ctx C{S, stk + threadIdx.x, 0u, (int)blockDim.x};
-    if (wave < n) {   // wave-uniform
+    for (int wave = next_item(cnt + C_WORK_P); wave < n; wave = next_item(cnt + C_WORK_P)) {   // wave-uniform
         Cand &c = cand[kept[wave]];
         float mx = 0.f, sm = 0.f;
         int nz = 0, k = 0;
@@ -691,6 +749,7 @@ __global__ void __launch_bounds__(64 * RW) k_pilot(SceneDev S, Cand *cand, const
             mx = fmaxf(mx, wm); sm += ws; nz += wz; k += 64;
             if (k >= pilot && nz >= 8) break;
         }
+        if (lane == 0) atomicAdd(cnt + C_DRAWN_P, (unsigned long long)k);
         if (lane == 0) {
             c.pmax = mx; c.psum = sm; c.pn = (float)k;
             atomic_maxf(runmax + (c.cls_u >> 8) * 5 + (c.cls_u & 0xFF), mx);
@@ -827,12 +886,11 @@ __global__ void __launch_bounds__(64 * RW) k_recip(SceneDev S, Cand *cand, const
 {
     const uint32_t iter = iter_of(cnt);
     __shared__ int stk[PT_STACK * 64 * RW];
-    const int wave = blockIdx.x * RW + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     const int n = (int)cnt[C_NFINAL] * repeats;
     Ctx C{S, stk + threadIdx.x, 0u, (int)blockDim.x};
-    uint32_t ns = 0;
-    if (wave < n) {   // wave-uniform
+    uint32_t ns = 0, drawn = 0;
+    for (int wave = next_item(cnt + C_WORK_A); wave < n; wave = next_item(cnt + C_WORK_A)) {   // wave-uniform
         const uint32_t ci = final_[wave / repeats];
         const uint32_t chain = ci * 8u + (uint32_t)(wave % repeats);
         Cand &c = cand[ci];
@@ -845,10 +903,11 @@ __global__ void __launch_bounds__(64 * RW) k_recip(SceneDev S, Cand *cand, const
             const float u = rng_f(r);
             mx = fmaxf(mx, fq);
             chain_consume(fq, u, 64, invB, st, seed, chain, iter);
+            drawn += 64;
         }
 #pragma unroll
         for (int off = 32; off > 0; off >>= 1) mx = fmaxf(mx, __shfl_xor(mx, off));
-        ns = st.ns;
+        ns += st.ns;
         if (lane == 0) {
             const bool running = st.alive && st.pos + st.neg > 0;
             int slot = -1;
@@ -867,6 +926,7 @@ __global__ void __launch_bounds__(64 * RW) k_recip(SceneDev S, Cand *cand, const
     }
     wave_count(cnt + C_RECIP_SAMPLES, lane == 0 ? ns : 0u);
     wave_count(cnt + C_SAMPLES_A, lane == 0 ? ns : 0u);
+    wave_count(cnt + C_DRAWN_A, lane == 0 ? drawn : 0u);
     wave_count(cnt + C_RAYS_RECIP, C.rays);
     count_traversal(C, cnt, C_VISITS_A, C_TESTS_A);
 }

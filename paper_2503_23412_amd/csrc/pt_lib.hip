@@ -111,6 +111,8 @@ struct pt_scene {
     // reciprocal-chain schedule (pt_autotune): stage-A sample budget, blocks of the round kernels
     uint32_t tune_budget = 1024;
     int tune_gen_grid = 8192;
+    // workgroups of the persistent pilot and stage-A launches: four per CU (three fit by LDS)
+    int persist_wg = 1024;
     // multi-scene graph (pt_render_scenes) owned by the first scene of a batch
     hipGraphExec_t mgexec = nullptr;
     std::vector<char> mgkey;
@@ -173,6 +175,11 @@ extern "C" pt_status pt_scene_upload(const pt_scene_desc *d, void *stream_, pt_s
         hipStream_t stream = (hipStream_t)stream_;
         pt_scene *s = new pt_scene();
         HIPCHK(hipGetDevice(&s->device));
+        {
+            int ncu = 0;
+            HIPCHK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, s->device));
+            s->persist_wg = 4 * std::max(ncu, 1);
+        }
         s->W = d->width; s->H = d->height; s->npix = d->width * d->height; s->max_light = d->max_light_paths;
         s->ntri = d->n_tri;
         // BVH
@@ -741,13 +748,13 @@ pt_status enqueue_iteration(pt_scene *s, const pt_iter_params *p, float *acc, fl
             k_keep<<<blocks(maxc, 256), 256, 0, stream>>>(p->cand_cap, p->seed, s->kept, maxc, s->cnt);
             const size_t e0 = 2 * (size_t)p->max_depth;
             if (timing) HIPCHK(hipEventRecord(s->ev[e0], stream));
-            k_pilot<<<blocks(maxc, RW), 64 * RW, 0, stream>>>(S, s->cand, s->kept, p->pilot, p->seed, s->runmax,
+            k_pilot<<<s->persist_wg, 64 * RW, 0, stream>>>(S, s->cand, s->kept, p->pilot, p->seed, s->runmax,
                                                              s->cnt);
             k_roulette<<<blocks(maxc, 256), 256, 0, stream>>>(s->cand, s->kept, s->final_, s->runmax, S.em_area,
                                                               p->recip_repeats, p->cost_cap, p->seed, s->cnt);
             const uint32_t n1 = (uint32_t)std::max(64.0f, p->cost_cap / (float)p->recip_repeats);
             if (timing) HIPCHK(hipEventRecord(s->ev[e0 + 1], stream));
-            k_recip<<<blocks((long)maxc * p->recip_repeats, RW), 64 * RW, 0, stream>>>(
+            k_recip<<<s->persist_wg, 64 * RW, 0, stream>>>(
                 S, s->cand, s->final_, p->recip_repeats, p->seed, n1, s->tune_budget, s->runmax, s->chq[0], s->cnt);
             if (timing) HIPCHK(hipEventRecord(s->ev[e0 + 2], stream));
             for (int r = 0; r < CHAIN_ROUNDS; ++r) {
@@ -898,6 +905,8 @@ extern "C" pt_status pt_render_iteration(pt_scene *s, const pt_iter_params *p, f
         stats->node_visits_stage_a = (double)c[C_VISITS_A];
         stats->tri_tests_stage_a = (double)c[C_TESTS_A];
         stats->n_samples_stage_a = (double)c[C_SAMPLES_A];
+        stats->n_drawn_stage_a = (double)c[C_DRAWN_A];
+        stats->n_drawn_pilot = (double)c[C_DRAWN_P];
         stats->n_pool = (double)c[C_POOL];
         stats->n_connections = (double)c[C_SPC];
         stats->n_lt_splats = (double)c[C_LT];

@@ -60,8 +60,8 @@ def _render(gpu, sc, N, max_light=1024, subspaces=(8, 8), **params):
 def _furnace_ok(m, v, expect, tag):
     """Per-pixel bar of the grey furnaces: at least 99.9 % of pixels within 4 standard errors of
     the closed form. The three channels of a grey furnace carry the same value, so pixels (not
-    channels) are counted; furnace images are 48 x 48, so the bar allows two of 2,304 pixels
-    beyond 4 (at 16 x 16 it would allow none and fail by chance in a few percent of runs)."""
+    channels) are counted; furnace images have at least 2,304 pixels, so the bar allows two or
+    more beyond 4 (at 16 x 16 it would allow none and fail by chance in a few percent of runs)."""
     z = (m[..., 0] - expect) / np.sqrt(v[..., 0] + 1e-30)
     frac = (np.abs(z) < 4).mean()
     say(f"{tag}: mean {m.mean():.5f} expect {expect:.5f} frac |z|<4 {frac:.5f} max|z| {np.abs(z).max():.2f}")
@@ -225,10 +225,15 @@ def test_multi_scene_graph_and_autotune(gpu):
 def test_glass_furnace_through_proxy(gpu):
     from synth import scenes
     a, K = 0.5, 120
-    sc = scenes.furnace(albedo=a, le=1.0, glass_sphere=True, width=48, height=48, sphere_subdiv=2,
+    sc = scenes.furnace(albedo=a, le=1.0, glass_sphere=True, width=96, height=96, sphere_subdiv=2,
                         enclosure="sphere")
     say("glass furnace")
-    m, v, st = _render(gpu, sc, 384, max_depth=K, n_light=1024, cand_cap=128)
+    # Without MIS the proxy alone scores its class here, and its reciprocal estimates make the
+    # per-pixel means skewed (z skewness about -0.4 at 1,024 iterations, 1-2 pixels in 2,304 below
+    # -4, none above). 96 x 96 pixels let the 99.9 % bar count them (9 of 9,216) instead of
+    # hinging on one pixel. At depth 120 the paths cut by the depth limit (glancing reflections
+    # inside the sphere) take 0.0003 +- 0.0003 from the closed form (oracle O1).
+    m, v, st = _render(gpu, sc, 1024, max_depth=K, n_light=1024, cand_cap=128)
     expect = (1 - a ** K) / (1 - a)
     assert _furnace_ok(m, v, expect, "glass furnace")
     assert st["n_proxy_valid"] > 0 and st["n_recip_truncated"] == 0 and st["n_nan"] == 0
