@@ -15,6 +15,9 @@ FLAGS = [
     # keep the compiler from forming packed FP32 instructions
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wno-unused-result",
+    # the 32-bit-stack instances of the chain kernels are held to three waves by LDS, below the
+    # register budget they are compiled for
+    "-Wno-pass-failed",
 ]
 
 

@@ -321,13 +321,25 @@ __device__ __forceinline__ bool isect(const TriIsect &T, float3 o, float3 d, flo
     return t > tmin && t < tmax;
 }
 
-// The traversal stack lives in LDS, column-major (entry k of thread i at k * nthreads + i) so
-// that a wavefront's pushes and pops hit 64 different banks. `any` ends the walk at the first
-// hit (visibility); it is a run-time argument so that a kernel can trace visibility and
-// closest-hit rays at one call site, and constant-folds where the caller passes a constant.
-template <bool COUNT>
+// The traversal stack lives in LDS, column-major so that a wavefront's pushes and pops hit
+// different banks: 32-bit entries put entry k of thread i at k * nthreads + i; 16-bit entries
+// (trees of fewer than 65,536 nodes, half the LDS) pack entries 2j and 2j + 1 of thread i into
+// the two halves of dword j * nthreads + i. A thread's pointer is its column's first element
+// (stk_col).
+__device__ __forceinline__ int &stk_at(int *stk, int k, int stride) { return stk[k * stride]; }
+__device__ __forceinline__ uint16_t &stk_at(uint16_t *stk, int k, int stride)
+{
+    return stk[(k >> 1) * 2 * stride + (k & 1)];
+}
+template <typename SE>
+__device__ __forceinline__ SE *stk_col(SE *base, int thread) { return base + (sizeof(SE) == 2 ? 2 : 1) * thread; }
+
+// `any` ends the walk at the first hit (visibility); it is a run-time argument so that a kernel
+// can trace visibility and closest-hit rays at one call site, and constant-folds where the
+// caller passes a constant.
+template <bool COUNT, typename SE>
 __device__ __forceinline__ bool traverse_rt(const SceneDev &S, float3 o, float3 d, float tmin, float tmax, int ign0,
-                                            int ign1, bool any, int *stk, int stride, Hit &h,
+                                            int ign1, bool any, SE *stk, int stride, Hit &h,
                                             uint32_t *visits = nullptr, uint32_t *tests = nullptr)
 {
     const float3 inv = f3(1.0f / d.x, 1.0f / d.y, 1.0f / d.z);
@@ -405,19 +417,19 @@ __device__ __forceinline__ bool traverse_rt(const SceneDev &S, float3 o, float3 
         if (cid[0] >= 0) {
 #pragma unroll
             for (int k = 3; k >= 1; --k)
-                if (cid[k] >= 0 && sp < PT_STACK) stk[(sp++) * stride] = cid[k];
+                if (cid[k] >= 0 && sp < PT_STACK) stk_at(stk, sp++, stride) = (SE)cid[k];
             node = cid[0];
         } else {
             if (sp == 0) break;
-            node = stk[(--sp) * stride];
+            node = (int)stk_at(stk, --sp, stride);
         }
     }
     return h.tri >= 0;
 }
 
-template <bool ANY, bool COUNT>
+template <bool ANY, bool COUNT, typename SE>
 __device__ __forceinline__ bool traverse(const SceneDev &S, float3 o, float3 d, float tmin, float tmax, int ign0,
-                                         int ign1, int *stk, int stride, Hit &h, uint32_t *visits = nullptr,
+                                         int ign1, SE *stk, int stride, Hit &h, uint32_t *visits = nullptr,
                                          uint32_t *tests = nullptr)
 {
     return traverse_rt<COUNT>(S, o, d, tmin, tmax, ign0, ign1, ANY, stk, stride, h, visits, tests);

@@ -476,15 +476,18 @@ __global__ void k_keep(int cap, uint32_t seed, uint32_t *kept, int max_cand, uns
 // (u = 1, class A), tracing from the control vertex (u = 1, class B; cosine lobe at the light
 // vertex), tracing from y_{s-1} (cosine hemisphere, each side with probability 1/2 on a
 // dielectric, then the BSDF at every intermediate vertex).
-struct Ctx {
+template <typename SE>
+struct CtxT {
     const SceneDev &S;
-    int *stk;        // this thread's column of the workgroup's LDS stack
+    SE *stk;         // this thread's column of the workgroup's LDS stack (stk_col)
     uint32_t rays;
-    int stride;      // threads per workgroup = distance between a thread's stack entries
+    int stride;      // threads per workgroup
     uint32_t visits = 0, tests = 0;   // BVH nodes visited and triangles tested (traffic accounting)
 };
+using Ctx = CtxT<int>;
 
-__device__ __forceinline__ bool occluded(Ctx &C, float3 a, int ta, float3 b, int tb)
+template <typename SE>
+__device__ __forceinline__ bool occluded(CtxT<SE> &C, float3 a, int ta, float3 b, int tb)
 {
     const float3 d = b - a;
     const float dist = sqrtf(dot3(d, d));
@@ -493,13 +496,15 @@ __device__ __forceinline__ bool occluded(Ctx &C, float3 a, int ta, float3 b, int
     return traverse<true, true>(C.S, a, d * (1.0f / dist), C.S.tmin, dist * 0.9999f, ta, tb, C.stk, C.stride, h,
                                 &C.visits, &C.tests);
 }
-__device__ __forceinline__ bool closest(Ctx &C, float3 o, float3 d, int ign, Hit &h)
+template <typename SE>
+__device__ __forceinline__ bool closest(CtxT<SE> &C, float3 o, float3 d, int ign, Hit &h)
 {
     C.rays++;
     return traverse<false, true>(C.S, o, d, C.S.tmin, 3.0e38f, ign, -1, C.stk, C.stride, h, &C.visits, &C.tests);
 }
 // a kernel's traversal work, one atomic per wavefront
-__device__ __forceinline__ void count_traversal(const Ctx &C, unsigned long long *cnt, int cv = C_VISITS_R,
+template <typename SE>
+__device__ __forceinline__ void count_traversal(const CtxT<SE> &C, unsigned long long *cnt, int cv = C_VISITS_R,
                                                 int ct = C_TESTS_R)
 {
     wave_count(cnt + cv, C.visits);
@@ -559,7 +564,8 @@ __device__ __forceinline__ float fq_u1_b(const SceneDev &S, float3 v, float3 vn,
 // y_{s-1} (toward the light), 2 / 3 u = 1 class B from y_0 / from y_{s-1} (ray to y_1, then the
 // visibility of the other side), 4 u >= 2 (the retrace through the specular run, then for class
 // B the visibility y_0 -> y_1).
-__device__ float fq_sample(Ctx &C, const Cand &c, Rng &r)
+template <typename SE>
+__device__ float fq_sample(CtxT<SE> &C, const Cand &c, Rng &r)
 {
     const SceneDev &S = C.S;
     const int cls = c.cls_u >> 8, u = c.cls_u & 0xFF;
@@ -708,6 +714,17 @@ __device__ float fq_sample(Ctx &C, const Cand &c, Rng &r)
 // are i.i.d. whatever the chain's state, so drawing them ahead of need changes nothing but the
 // number of discarded draws (fewer than 64 per chain).
 #define RW 4                       // wavefronts per workgroup
+// minimum waves per SIMD the chain kernels are compiled for (register budget 512 / waves);
+// with 16-bit stack entries LDS allows more than three
+#ifndef PT_RECIP_WAVES
+#define PT_RECIP_WAVES 4
+#endif
+#ifndef PT_PILOT_WAVES
+#define PT_PILOT_WAVES 4
+#endif
+#ifndef PT_GEN_WAVES
+#define PT_GEN_WAVES 1
+#endif
 __device__ __forceinline__ float lane_get(float v, int l) { return __shfl(v, l); }
 
 // The pilot and the stage-A chains run on a persistent grid (a few workgroups per CU): each
@@ -722,14 +739,15 @@ __device__ __forceinline__ int next_item(unsigned long long *counter)
 }
 
 // pilot: 64-sample steps until at least `pilot` samples with 8 non-zero values, or 256 samples
-__global__ void __launch_bounds__(64 * RW) k_pilot(SceneDev S, Cand *cand, const uint32_t *kept, int pilot,
+template <typename SE>
+__global__ void __launch_bounds__(64 * RW, PT_PILOT_WAVES) k_pilot(SceneDev S, Cand *cand, const uint32_t *kept, int pilot,
                                                    uint32_t seed, float *runmax, unsigned long long *cnt)
 {
     const uint32_t iter = iter_of(cnt);
-    __shared__ int stk[PT_STACK * 64 * RW];
+    __shared__ SE stk[PT_STACK * 64 * RW];
     const int lane = threadIdx.x & 63;
     const int n = (int)cnt[C_NKEPT];
-    Ctx C{S, stk + threadIdx.x, 0u, (int)blockDim.x};
+    CtxT<SE> C{S, stk_col(stk, (int)threadIdx.x), 0u, (int)blockDim.x};
     for (int wave = next_item(cnt + C_WORK_P); wave < n; wave = next_item(cnt + C_WORK_P)) {   // wave-uniform
         Cand &c = cand[kept[wave]];
         float mx = 0.f, sm = 0.f;
@@ -880,15 +898,16 @@ __device__ __forceinline__ void chain_finish(Cand &c, const ChainRun &st, bool t
 }
 
 // stage A: one wavefront per chain, at most `budget` samples, then hand over to the rounds
-__global__ void __launch_bounds__(64 * RW) k_recip(SceneDev S, Cand *cand, const uint32_t *final_, int repeats,
+template <typename SE>
+__global__ void __launch_bounds__(64 * RW, PT_RECIP_WAVES) k_recip(SceneDev S, Cand *cand, const uint32_t *final_, int repeats,
                                                    uint32_t seed, uint32_t n1, uint32_t budget, float *runmax,
                                                    ChainState *longq, unsigned long long *cnt)
 {
     const uint32_t iter = iter_of(cnt);
-    __shared__ int stk[PT_STACK * 64 * RW];
+    __shared__ SE stk[PT_STACK * 64 * RW];
     const int lane = threadIdx.x & 63;
     const int n = (int)cnt[C_NFINAL] * repeats;
-    Ctx C{S, stk + threadIdx.x, 0u, (int)blockDim.x};
+    CtxT<SE> C{S, stk_col(stk, (int)threadIdx.x), 0u, (int)blockDim.x};
     uint32_t ns = 0, drawn = 0;
     for (int wave = next_item(cnt + C_WORK_A); wave < n; wave = next_item(cnt + C_WORK_A)) {   // wave-uniform
         const uint32_t ci = final_[wave / repeats];
@@ -941,14 +960,15 @@ __device__ __forceinline__ uint32_t chain_round_size(uint32_t n, int round)
 }
 
 // round r, part 1: every lane of the grid draws samples for the running chains
-__global__ void __launch_bounds__(WG) k_chain_gen(SceneDev S, const Cand *__restrict__ cand,
+template <typename SE>
+__global__ void __launch_bounds__(WG, PT_GEN_WAVES) k_chain_gen(SceneDev S, const Cand *__restrict__ cand,
                                                   const ChainState *__restrict__ list, int cidx, int round,
                                                   uint32_t seed, float2 *buf, unsigned long long *cnt)
 {
-    __shared__ int stk[PT_STACK * WG];
+    __shared__ SE stk[PT_STACK * WG];
     const uint32_t iter = iter_of(cnt);
     const uint32_t n = (uint32_t)min(cnt[cidx], (unsigned long long)CHAIN_LIST_CAP);
-    Ctx C{S, stk + threadIdx.x, 0u, WG};
+    CtxT<SE> C{S, stk_col(stk, (int)threadIdx.x), 0u, WG};
     if (n > 0) {
         const uint32_t G = chain_round_size(n, round);
         const uint64_t total = (uint64_t)n * G;

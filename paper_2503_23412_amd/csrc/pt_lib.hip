@@ -111,8 +111,10 @@ struct pt_scene {
     // reciprocal-chain schedule (pt_autotune): stage-A sample budget, blocks of the round kernels
     uint32_t tune_budget = 1024;
     int tune_gen_grid = 8192;
-    // workgroups of the persistent pilot and stage-A launches: four per CU (three fit by LDS)
+    // workgroups of the persistent pilot and stage-A launches: four per CU
     int persist_wg = 1024;
+    // the chain kernels keep 16-bit traversal stack entries when the tree has fewer than 65,536 nodes
+    bool stk16 = false;
     // multi-scene graph (pt_render_scenes) owned by the first scene of a batch
     hipGraphExec_t mgexec = nullptr;
     std::vector<char> mgkey;
@@ -186,6 +188,7 @@ extern "C" pt_status pt_scene_upload(const pt_scene_desc *d, void *stream_, pt_s
         std::vector<BNode> nodes;
         std::vector<int> order;
         pt_build_bvh4(d->tri, d->n_tri, nodes, order);
+        s->stk16 = nodes.size() < 65536;
         s->inv_order.assign(d->n_tri, 0);
         for (int i = 0; i < d->n_tri; ++i) s->inv_order[order[i]] = i;
         std::vector<TriIsect> ti(d->n_tri);
@@ -663,6 +666,14 @@ pt_status check_params(pt_scene *s, const pt_iter_params *p, float *acc)
     return PT_OK;
 }
 
+// launch a chain kernel with the scene's traversal-stack entry type
+#define PT_STK_LAUNCH(kern, grid, block, ...)                                                   \
+    do {                                                                                        \
+        if (s->stk16) kern<uint16_t><<<(grid), (block), 0, stream>>>(__VA_ARGS__);             \
+        else kern<int><<<(grid), (block), 0, stream>>>(__VA_ARGS__);                            \
+    } while (0)
+
+
 // Enqueues one iteration on `stream`: kernel launches only (no host synchronisation, no
 // memset), so the sequence can be captured into a HIP graph. graph = true: the iteration index
 // in device memory is advanced by one instead of being set from p->iteration.
@@ -748,20 +759,19 @@ pt_status enqueue_iteration(pt_scene *s, const pt_iter_params *p, float *acc, fl
             k_keep<<<blocks(maxc, 256), 256, 0, stream>>>(p->cand_cap, p->seed, s->kept, maxc, s->cnt);
             const size_t e0 = 2 * (size_t)p->max_depth;
             if (timing) HIPCHK(hipEventRecord(s->ev[e0], stream));
-            k_pilot<<<s->persist_wg, 64 * RW, 0, stream>>>(S, s->cand, s->kept, p->pilot, p->seed, s->runmax,
-                                                             s->cnt);
+            PT_STK_LAUNCH(k_pilot, s->persist_wg, 64 * RW, S, s->cand, s->kept, p->pilot, p->seed, s->runmax, s->cnt);
             k_roulette<<<blocks(maxc, 256), 256, 0, stream>>>(s->cand, s->kept, s->final_, s->runmax, S.em_area,
                                                               p->recip_repeats, p->cost_cap, p->seed, s->cnt);
             const uint32_t n1 = (uint32_t)std::max(64.0f, p->cost_cap / (float)p->recip_repeats);
             if (timing) HIPCHK(hipEventRecord(s->ev[e0 + 1], stream));
-            k_recip<<<s->persist_wg, 64 * RW, 0, stream>>>(
-                S, s->cand, s->final_, p->recip_repeats, p->seed, n1, s->tune_budget, s->runmax, s->chq[0], s->cnt);
+            PT_STK_LAUNCH(k_recip, s->persist_wg, 64 * RW, S, s->cand, s->final_, p->recip_repeats, p->seed, n1,
+                          s->tune_budget, s->runmax, s->chq[0], s->cnt);
             if (timing) HIPCHK(hipEventRecord(s->ev[e0 + 2], stream));
             for (int r = 0; r < CHAIN_ROUNDS; ++r) {
                 const int in = r & 1, out = in ^ 1;
                 k_set_counter<<<1, 1, 0, stream>>>(s->cnt, C_LONGQ0 + out, 0ull);
-                k_chain_gen<<<s->tune_gen_grid, WG, 0, stream>>>(S, s->cand, s->chq[in], C_LONGQ0 + in, r, p->seed, s->chbuf,
-                                                     s->cnt);
+                PT_STK_LAUNCH(k_chain_gen, s->tune_gen_grid, WG, S, s->cand, s->chq[in], C_LONGQ0 + in, r, p->seed,
+                              s->chbuf, s->cnt);
                 k_chain_consume<<<2048, 64 * RW, 0, stream>>>(s->cand, s->chq[in], C_LONGQ0 + in, s->chq[out],
                                                               C_LONGQ0 + out, r, r == CHAIN_ROUNDS - 1 ? 1 : 0,
                                                               p->seed, s->chbuf, s->runmax, s->cnt);
