@@ -123,13 +123,19 @@ def main():
     S.build_subspaces(n_eye=cfg["n_subspaces"], n_spec=cfg["n_spec"])
     acc = torch.zeros(W * H * 3, device="cuda")
     acc2 = torch.zeros_like(acc)
+    # warmup: the reciprocal-chain schedule autotuner (its timed iterations render like any other),
+    # then plain iterations
+    tune = S.autotune(acc, acc2, iteration=0, flags=flags, **params)
+    log(f"autotune: {tune}")
+    k0 = tune["iterations_rendered"]
     for k in range(args.warmup):
-        S.render_iteration(acc, acc2, iteration=k, flags=flags, **params)
+        S.render_iteration(acc, acc2, iteration=k0 + k, flags=flags, **params)
     torch.cuda.synchronize()
     log("warmup done")
+    first = k0 + args.warmup
     t0 = time.perf_counter()
     for k in range(args.steps):
-        S.render_iteration(acc, acc2, iteration=args.warmup + k, flags=flags, **params)
+        S.render_iteration(acc, acc2, iteration=first + k, flags=flags, **params)
         if k % 16 == 15:
             log(f"step {k + 1}/{args.steps}")
     torch.cuda.synchronize()
@@ -137,7 +143,7 @@ def main():
     log(f"timed {args.steps} steps in {dt:.3f} s")
     # one iteration with traversal counters, then timed ones (HIP events recorded on the stream the
     # kernels are launched on, inside the library)
-    it = args.warmup + args.steps
+    it = first + args.steps
     stc = S.render_iteration(acc, acc2, stats=True, iteration=it, flags=flags | pt.PT_FLAG_COUNT, **params)
     tim = [S.render_iteration(acc, acc2, stats=True, iteration=it + 1 + j, flags=flags | pt.PT_FLAG_TIMING, **params)
            for j in range(4)]
@@ -191,6 +197,8 @@ def main():
                                      "n_proxy_attempts", "n_proxy_valid", "n_pool", "n_connections", "n_lt_splats",
                                      "n_nan", "chain_len_max")},
         "ms_breakdown": {"eye_extension": ms_ext, "reciprocal_block": ms_rec, "reciprocal_stage_a": ms_a},
+        "schedule": {"stage_a_budget": tune["stage_a_budget"], "round_grid": tune["round_grid"],
+                     "autotune_iterations": k0, "ms_tuned": tune["ms_best"], "ms_default": tune["ms_previous"]},
         "roofline": {"kernel": dom["kernel"], "bound": "alu", "achieved": achieved, "peak": FP32_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / FP32_PEAK_TFLOPS, "traffic": dom["traffic"],
                      "flops_per_launch": dom["flops"] / dom["launches"],

@@ -175,8 +175,8 @@ pt_status pt_render_scenes(pt_scene *const *scenes, const pt_iter_params *params
                            float *const *accum_rgb, float *const *accum_sq, void *hip_stream);
 
 /* Schedule autotuning of the reciprocal chains on this scene and parameters: the sample budget
- * of the one-wavefront stage (256 .. 2048) and the grid of the round kernels (2,048 .. 32,768
- * blocks) are each timed over two iterations (after one to settle) and the fastest pair is kept
+ * of the one-wavefront stage (512 .. 8192) and the grid of the round kernels (1,024 .. 8,192
+ * blocks) are each timed over three iterations (after one to settle) and the fastest pair is kept
  * by the scene for later iterations. Every pair gives the same estimator (the chains consume
  * i.i.d. samples whoever draws them), so the choice changes speed only. The timed iterations
  * render into accum_rgb / accum_sq (iterations p->iteration, +1, ...); their number is returned

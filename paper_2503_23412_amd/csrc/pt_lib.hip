@@ -1177,8 +1177,8 @@ extern "C" pt_status pt_autotune(pt_scene *s, const pt_iter_params *p, float *ac
     if (!out) return set_err(PT_EINVAL, "null result");
     hipStream_t stream = (hipStream_t)stream_;
     if (p->flags & PT_FLAG_MLP) TRY(ensure_mlp(s, stream));
-    static const uint32_t budgets[4] = {256u, 512u, 1024u, 2048u};
-    static const int grids[3] = {2048, 8192, 32768};
+    static const uint32_t budgets[5] = {512u, 1024u, 2048u, 4096u, 8192u};
+    static const int grids[3] = {1024, 2048, 8192};
     hipEvent_t e0, e1;
     HIPCHK(hipEventCreate(&e0));
     HIPCHK(hipEventCreate(&e1));
@@ -1191,15 +1191,15 @@ extern "C" pt_status pt_autotune(pt_scene *s, const pt_iter_params *p, float *ac
     const int g0 = s->tune_gen_grid;
     int used = 0;
     pt_status st = PT_OK;
-    for (int bi = 0; bi < 4 && st == PT_OK; ++bi)
+    for (int bi = 0; bi < 5 && st == PT_OK; ++bi)
         for (int gi = 0; gi < 3 && st == PT_OK; ++gi) {
             s->tune_budget = budgets[bi];
             s->tune_gen_grid = grids[gi];
-            // one iteration to settle, two timed
+            // one iteration to settle, three timed
             q.iteration = p->iteration + (uint32_t)used++;
             if ((st = enqueue_iteration(s, &q, acc, acc2, stream, false)) != PT_OK) break;
             if (hipEventRecord(e0, stream) != hipSuccess) { st = set_err(PT_EDEVICE, "event record failed"); break; }
-            for (int r = 0; r < 2 && st == PT_OK; ++r) {
+            for (int r = 0; r < 3 && st == PT_OK; ++r) {
                 q.iteration = p->iteration + (uint32_t)used++;
                 st = enqueue_iteration(s, &q, acc, acc2, stream, false);
             }
@@ -1210,7 +1210,7 @@ extern "C" pt_status pt_autotune(pt_scene *s, const pt_iter_params *p, float *ac
                 st = set_err(PT_EDEVICE, "event timing failed");
                 break;
             }
-            ms *= 0.5f;
+            ms *= 1.0f / 3.0f;
             if (budgets[bi] == b0 && grids[gi] == g0) dflt = ms;
             if (ms < best) { best = ms; bb = budgets[bi]; bg = grids[gi]; }
         }
