@@ -779,14 +779,15 @@ __global__ void __launch_bounds__(64 * RW, PT_PILOT_WAVES) k_pilot(SceneDev S, C
 
 // B_j = max(pilot max, bucket running max) (Appendix E's B = max f/q, per (class, u) bucket as in
 // Section 5.5's statistics); cost roulette: keep with rho = min(1, cost_cap / (R B / beta))
-__global__ void k_roulette(Cand *cand, const uint32_t *kept, uint32_t *final_, const float *runmax, float em_area,
-                           int repeats, float cost_cap, uint32_t seed, unsigned long long *cnt)
+__global__ void k_roulette(Cand *cand, const uint32_t *kept, uint32_t *final_, uint32_t *cost_bin,
+                           const float *runmax, float em_area, int repeats, float cost_cap, uint32_t seed,
+                           unsigned long long *cnt)
 {
     const uint32_t iter = iter_of(cnt);
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const int n = (int)cnt[C_NKEPT];
     bool keep = false;
-    uint32_t ci = 0;
+    uint32_t ci = 0, bin = 0;
     if (i < n) {
         ci = kept[i];
         Cand &c = cand[ci];
@@ -801,9 +802,29 @@ __global__ void k_roulette(Cand *cand, const uint32_t *kept, uint32_t *final_, c
         Rng r = rng_make(seed, S_ROUL, (uint32_t)i, iter, 0u);
         keep = rho >= 1.0f || rng_f(r) < rho;
         c.B = B; c.rho = rho; c.recip_sum = 0.0f;
+        // class of the expected samples per chain, B / beta: log2, 0 .. 15
+        bin = (uint32_t)min(15, max(0, (int)log2f(fmaxf(B / beta, 1.0f))));
     }
     const int slot = wave_push(cnt + C_NFINAL, keep);
-    if (keep) final_[slot] = ci;
+    if (keep) {
+        final_[slot] = ci;
+        cost_bin[slot] = bin;
+        atomicAdd(cnt + C_COSTH0 + bin, 1ull);
+    }
+}
+
+// order of the final candidates for the chains: the classes of expected chain length from the
+// longest down, so that the persistent stage-A grid starts the long chains first and does not end
+// on one (longest-first scheduling); within a class in any order
+__global__ void k_order(const uint32_t *cost_bin, uint32_t *order, unsigned long long *cnt)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int n = (int)cnt[C_NFINAL];
+    if (i >= n) return;
+    const uint32_t b = cost_bin[i];
+    unsigned long long base = 0;
+    for (int k = 15; k > (int)b; --k) base += cnt[C_COSTH0 + k];
+    order[base + atomicAdd(cnt + C_COSTF0 + b, 1ull)] = (uint32_t)i;
 }
 
 // One estimate I~ per chain (Section 4.2 with r = |g|). Pending nodes of the splitting tree
@@ -899,7 +920,8 @@ __device__ __forceinline__ void chain_finish(Cand &c, const ChainRun &st, bool t
 
 // stage A: one wavefront per chain, at most `budget` samples, then hand over to the rounds
 template <typename SE>
-__global__ void __launch_bounds__(64 * RW, PT_RECIP_WAVES) k_recip(SceneDev S, Cand *cand, const uint32_t *final_, int repeats,
+__global__ void __launch_bounds__(64 * RW, PT_RECIP_WAVES) k_recip(SceneDev S, Cand *cand, const uint32_t *final_,
+                                                   const uint32_t *order, int repeats,
                                                    uint32_t seed, uint32_t n1, uint32_t budget, float *runmax,
                                                    ChainState *longq, unsigned long long *cnt)
 {
@@ -910,7 +932,7 @@ __global__ void __launch_bounds__(64 * RW, PT_RECIP_WAVES) k_recip(SceneDev S, C
     CtxT<SE> C{S, stk_col(stk, (int)threadIdx.x), 0u, (int)blockDim.x};
     uint32_t ns = 0, drawn = 0;
     for (int wave = next_item(cnt + C_WORK_A); wave < n; wave = next_item(cnt + C_WORK_A)) {   // wave-uniform
-        const uint32_t ci = final_[wave / repeats];
+        const uint32_t ci = final_[order[wave / repeats]];
         const uint32_t chain = ci * 8u + (uint32_t)(wave % repeats);
         Cand &c = cand[ci];
         const float invB = 1.0f / c.B;

@@ -68,6 +68,7 @@ struct pt_scene {
     EyeBuf E{};
     Cand *cand = nullptr;
     uint32_t *kept = nullptr, *final_ = nullptr;
+    uint32_t *cost_bin = nullptr, *order = nullptr;   // chain scheduling (longest expected first)
     unsigned long long *cnt = nullptr;
     float *runmax = nullptr;   // [2 * 5] running maxima of f/q per (class, u)
     // subspace-based connections: light subspaces, buckets of the pool, Q (learned, frozen), alias rows
@@ -258,6 +259,7 @@ extern "C" pt_status pt_scene_upload(const pt_scene_desc *d, void *stream_, pt_s
         AL(s->L.q[0], M); AL(s->L.q[1], M);
         AL(s->cand, (size_t)4 * M);
         AL(s->kept, (size_t)4 * M); AL(s->final_, (size_t)4 * M);
+        AL(s->cost_bin, (size_t)4 * M); AL(s->order, (size_t)4 * M);
         AL(s->E.ro, np); AL(s->E.rd, np); AL(s->E.hit, np); AL(s->E.beta, np); AL(s->E.info, np); AL(s->E.mis, np);
         AL(s->E.q[0], np); AL(s->E.q[1], np);
         AL(s->E.shadow, 2 * (size_t)np); AL(s->E.proxy, np); AL(s->E.mis2, np);
@@ -760,11 +762,12 @@ pt_status enqueue_iteration(pt_scene *s, const pt_iter_params *p, float *acc, fl
             const size_t e0 = 2 * (size_t)p->max_depth;
             if (timing) HIPCHK(hipEventRecord(s->ev[e0], stream));
             PT_STK_LAUNCH(k_pilot, s->persist_wg, 64 * RW, S, s->cand, s->kept, p->pilot, p->seed, s->runmax, s->cnt);
-            k_roulette<<<blocks(maxc, 256), 256, 0, stream>>>(s->cand, s->kept, s->final_, s->runmax, S.em_area,
-                                                              p->recip_repeats, p->cost_cap, p->seed, s->cnt);
+            k_roulette<<<blocks(maxc, 256), 256, 0, stream>>>(s->cand, s->kept, s->final_, s->cost_bin, s->runmax,
+                                                              S.em_area, p->recip_repeats, p->cost_cap, p->seed, s->cnt);
+            k_order<<<blocks(maxc, 256), 256, 0, stream>>>(s->cost_bin, s->order, s->cnt);
             const uint32_t n1 = (uint32_t)std::max(64.0f, p->cost_cap / (float)p->recip_repeats);
             if (timing) HIPCHK(hipEventRecord(s->ev[e0 + 1], stream));
-            PT_STK_LAUNCH(k_recip, s->persist_wg, 64 * RW, S, s->cand, s->final_, p->recip_repeats, p->seed, n1,
+            PT_STK_LAUNCH(k_recip, s->persist_wg, 64 * RW, S, s->cand, s->final_, s->order, p->recip_repeats, p->seed, n1,
                           s->tune_budget, s->runmax, s->chq[0], s->cnt);
             if (timing) HIPCHK(hipEventRecord(s->ev[e0 + 2], stream));
             for (int r = 0; r < CHAIN_ROUNDS; ++r) {
