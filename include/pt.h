@@ -146,6 +146,9 @@ typedef struct {
     double node_visits_stage_a, tri_tests_stage_a, n_samples_stage_a;   /* the first chain kernel's */
     double n_drawn_stage_a, n_drawn_pilot;   /* f/q samples drawn (64 per wavefront step) by the first
                                                 chain kernel and by the pilot */
+    double wave_trips_stage_a;               /* traversal loop trips of the first chain kernel's
+                                                wavefronts: node visits / (64 trips) is its SIMD
+                                                efficiency (PT_FLAG_COUNT) */
     double chain_len_hist[24];       /* reciprocal chains by samples used: bin b counts [2^b, 2^(b+1)) */
     double chain_len_max;            /* longest chain of the iteration (samples) */
 } pt_iter_stats;

@@ -340,7 +340,8 @@ __device__ __forceinline__ SE *stk_col(SE *base, int thread) { return base + (si
 template <bool COUNT, typename SE>
 __device__ __forceinline__ bool traverse_rt(const SceneDev &S, float3 o, float3 d, float tmin, float tmax, int ign0,
                                             int ign1, bool any, SE *stk, int stride, Hit &h,
-                                            uint32_t *visits = nullptr, uint32_t *tests = nullptr)
+                                            uint32_t *visits = nullptr, uint32_t *tests = nullptr,
+                                            uint32_t *wave_trips = nullptr)
 {
     const float3 inv = f3(1.0f / d.x, 1.0f / d.y, 1.0f / d.z);
     const float3 oi = o * inv;
@@ -349,7 +350,12 @@ __device__ __forceinline__ bool traverse_rt(const SceneDev &S, float3 o, float3 
     int node = 0;
     for (;;) {
         const BNode &N = S.nodes[node];
-        if (COUNT) (*visits)++;
+        if (COUNT) {
+            (*visits)++;
+            // loop trips of the wavefront (counted by its first active lane): node visits over
+            // 64 x trips is the SIMD efficiency of the traversal
+            if (wave_trips && __lane_id() == __ffsll((long long)__ballot(1)) - 1) (*wave_trips)++;
+        }
         // slab tests of the four children
         const float4 lx = *(const float4 *)N.lo_x, hx = *(const float4 *)N.hi_x;
         const float4 ly = *(const float4 *)N.lo_y, hy = *(const float4 *)N.hi_y;
@@ -372,22 +378,29 @@ __device__ __forceinline__ bool traverse_rt(const SceneDev &S, float3 o, float3 
             tn[k] = t0;
         }
         const int cha[4] = {ch.x, ch.y, ch.z, ch.w}, cna[4] = {cn.x, cn.y, cn.z, cn.w};
-        // leaves: test their triangles now
+        // leaves: test their triangles now, as one run over the hit leaves' triangles, so that a
+        // wavefront's lanes step through their leaves together whichever children they are
+        int e[4];
+        int ntot = 0;
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
-            if (hitc[k] && cna[k] > 0) {
-                for (int i = cha[k]; i < cha[k] + cna[k]; ++i) {
-                    const TriIsect &T = S.tris[i];
-                    if (COUNT) (*tests)++;
-                    const int pid = T.prim;
-                    if (i == ign0 || i == ign1) continue;
-                    float t, b1, b2;
-                    if (isect(T, o, d, tmin, tmax, t, b1, b2)) {
-                        if (t < h.t || (t == h.t && h.tri >= 0 && pid < S.tris[h.tri].prim)) {
-                            h.t = t; h.b1 = b1; h.b2 = b2; h.tri = i;
-                            if (any) return true;
-                        }
-                    }
+            ntot += (hitc[k] && cna[k] > 0) ? cna[k] : 0;
+            e[k] = ntot;   // end of child k's triangles in the run
+        }
+        for (int j = 0; j < ntot; ++j) {
+            const int i = j < e[0] ? cha[0] + j
+                        : j < e[1] ? cha[1] + (j - e[0])
+                        : j < e[2] ? cha[2] + (j - e[1])
+                                   : cha[3] + (j - e[2]);
+            const TriIsect &T = S.tris[i];
+            if (COUNT) (*tests)++;
+            const int pid = T.prim;
+            if (i == ign0 || i == ign1) continue;
+            float t, b1, b2;
+            if (isect(T, o, d, tmin, tmax, t, b1, b2)) {
+                if (t < h.t || (t == h.t && h.tri >= 0 && pid < S.tris[h.tri].prim)) {
+                    h.t = t; h.b1 = b1; h.b2 = b2; h.tri = i;
+                    if (any) return true;
                 }
             }
         }

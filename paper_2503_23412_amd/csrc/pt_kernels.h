@@ -483,6 +483,7 @@ struct CtxT {
     uint32_t rays;
     int stride;      // threads per workgroup
     uint32_t visits = 0, tests = 0;   // BVH nodes visited and triangles tested (traffic accounting)
+    uint32_t trips = 0;               // traversal loop trips of the wavefront (first active lane)
 };
 using Ctx = CtxT<int>;
 
@@ -505,10 +506,11 @@ __device__ __forceinline__ bool closest(CtxT<SE> &C, float3 o, float3 d, int ign
 // a kernel's traversal work, one atomic per wavefront
 template <typename SE>
 __device__ __forceinline__ void count_traversal(const CtxT<SE> &C, unsigned long long *cnt, int cv = C_VISITS_R,
-                                                int ct = C_TESTS_R)
+                                                int ct = C_TESTS_R, int cw = -1)
 {
     wave_count(cnt + cv, C.visits);
     wave_count(cnt + ct, C.tests);
+    if (cw >= 0) wave_count(cnt + cw, C.trips);
 }
 // cosine direction at y_{s-1}: on a dielectric each side with probability 1/2, else the front
 __device__ __forceinline__ float3 spec_start(const MatDev &m, float3 n, Rng &r, float &side_p)
@@ -633,7 +635,7 @@ __device__ float fq_sample(CtxT<SE> &C, const Cand &c, Rng &r)
         Hit h;
         C.rays++;
         const bool hit = traverse_rt<true>(S, ro, rd, S.tmin, rmax, ig0, ig1, any, C.stk, C.stride, h, &C.visits,
-                                           &C.tests);
+                                           &C.tests, &C.trips);
         if (mode == 0) return hit ? 0.0f : fq_u1_a(S, v, vn, mv, yl, nyl);
         if (mode == 1) {
             if (!hit || !(S.mats[S.shade[h.tri].mat].flags & MF_EMIT)) return 0.0f;
@@ -969,7 +971,7 @@ __global__ void __launch_bounds__(64 * RW, PT_RECIP_WAVES) k_recip(SceneDev S, C
     wave_count(cnt + C_SAMPLES_A, lane == 0 ? ns : 0u);
     wave_count(cnt + C_DRAWN_A, lane == 0 ? drawn : 0u);
     wave_count(cnt + C_RAYS_RECIP, C.rays);
-    count_traversal(C, cnt, C_VISITS_A, C_TESTS_A);
+    count_traversal(C, cnt, C_VISITS_A, C_TESTS_A, C_TRIPS_A);
 }
 
 // samples per chain in round r for n running chains: doubling from stage A's budget (1024), so

@@ -920,6 +920,7 @@ extern "C" pt_status pt_render_iteration(pt_scene *s, const pt_iter_params *p, f
         stats->n_samples_stage_a = (double)c[C_SAMPLES_A];
         stats->n_drawn_stage_a = (double)c[C_DRAWN_A];
         stats->n_drawn_pilot = (double)c[C_DRAWN_P];
+        stats->wave_trips_stage_a = (double)c[C_TRIPS_A];
         stats->n_pool = (double)c[C_POOL];
         stats->n_connections = (double)c[C_SPC];
         stats->n_lt_splats = (double)c[C_LT];

@@ -67,7 +67,7 @@ class IterStats(ctypes.Structure):
         "n_proxy_attempts", "n_proxy_valid", "n_nan", "node_visits", "tri_tests",
         "ms_extend", "n_extend_launches", "n_pool", "n_connections", "n_lt_splats", "ms_recip", "ms_recip_stage_a",
         "node_visits_recip", "tri_tests_recip", "node_visits_stage_a", "tri_tests_stage_a", "n_samples_stage_a",
-        "n_drawn_stage_a", "n_drawn_pilot")] + [
+        "n_drawn_stage_a", "n_drawn_pilot", "wave_trips_stage_a")] + [
         ("chain_len_hist", ctypes.c_double * 24), ("chain_len_max", ctypes.c_double)]
 
     def as_dict(self):
