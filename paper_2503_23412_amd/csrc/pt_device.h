@@ -302,7 +302,9 @@ __device__ __forceinline__ float3 tri_point(const SceneDev &S, int tri, float b1
 // ----------------------------------------------------------------------------- traversal
 struct Hit { float t, b1, b2; int tri; };
 
-// Moller-Trumbore in FP32
+// Moller-Trumbore in FP32. The barycentric and distance bounds are tested on the numerators,
+// scaled by the sign of the determinant against |det| (the same inequalities times |det| > 0), so
+// a rejected triangle costs no division; an accepted one takes one hardware reciprocal.
 __device__ __forceinline__ bool isect(const TriIsect &T, float3 o, float3 d, float tmin, float tmax, float &t,
                                       float &b1, float &b2)
 {
@@ -310,14 +312,17 @@ __device__ __forceinline__ bool isect(const TriIsect &T, float3 o, float3 d, flo
     const float3 pv = cross3(d, e2);
     const float det = dot3(e1, pv);
     if (det == 0.0f) return false;
-    const float inv = 1.0f / det;
+    const float sg = det > 0.0f ? 1.0f : -1.0f, adet = fabsf(det);
     const float3 tv = o - f3(T.v0[0], T.v0[1], T.v0[2]);
-    b1 = dot3(tv, pv) * inv;
-    if (b1 < 0.0f || b1 > 1.0f) return false;
+    const float u = dot3(tv, pv) * sg;
+    if (u < 0.0f || u > adet) return false;
     const float3 qv = cross3(tv, e1);
-    b2 = dot3(d, qv) * inv;
-    if (b2 < 0.0f || b1 + b2 > 1.0f) return false;
-    t = dot3(e2, qv) * inv;
+    const float v = dot3(d, qv) * sg;
+    if (v < 0.0f || u + v > adet) return false;
+    const float tt = dot3(e2, qv) * sg;
+    if (!(tt > tmin * adet && tt < tmax * adet)) return false;
+    const float inv = __builtin_amdgcn_rcpf(adet);
+    t = tt * inv; b1 = u * inv; b2 = v * inv;
     return t > tmin && t < tmax;
 }
 

@@ -116,6 +116,10 @@ struct pt_scene {
     int persist_wg = 1024;
     // the chain kernels keep 16-bit traversal stack entries when the tree has fewer than 65,536 nodes
     bool stk16 = false;
+    // second stream of an iteration: the eye pass and light tracing run on it beside the
+    // reciprocal estimates (default priority), forked and joined with these events
+    hipStream_t side = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     // multi-scene graph (pt_render_scenes) owned by the first scene of a batch
     hipGraphExec_t mgexec = nullptr;
     std::vector<char> mgkey;
@@ -142,6 +146,9 @@ struct pt_scene {
         for (hipStream_t q : mstreams) (void)hipStreamDestroy(q);
         for (hipEvent_t e : mevents) (void)hipEventDestroy(e);
         if (cap_stream) (void)hipStreamDestroy(cap_stream);
+        if (side) { (void)hipStreamSynchronize(side); (void)hipStreamDestroy(side); }
+        if (ev_fork) (void)hipEventDestroy(ev_fork);
+        if (ev_join) (void)hipEventDestroy(ev_join);
         for (void *p : allocs) (void)hipFree(p);
         for (hipEvent_t e : ev) (void)hipEventDestroy(e);
     }
@@ -182,6 +189,10 @@ extern "C" pt_status pt_scene_upload(const pt_scene_desc *d, void *stream_, pt_s
             int ncu = 0;
             HIPCHK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, s->device));
             s->persist_wg = 4 * std::max(ncu, 1);
+            // the second stream of an iteration (default priority) and its fork / join events
+            HIPCHK(hipStreamCreateWithFlags(&s->side, hipStreamNonBlocking));
+            HIPCHK(hipEventCreateWithFlags(&s->ev_fork, hipEventDisableTiming));
+            HIPCHK(hipEventCreateWithFlags(&s->ev_join, hipEventDisableTiming));
         }
         s->W = d->width; s->H = d->height; s->npix = d->width * d->height; s->max_light = d->max_light_paths;
         s->ntri = d->n_tri;
@@ -754,6 +765,64 @@ pt_status enqueue_iteration(pt_scene *s, const pt_iter_params *p, float *acc, fl
         }
         k_light_phi<<<blocks(M, 256), 256, 0, stream>>>(S, L, mk, CD, s->cnt);
     }
+    // The eye pass, light tracing and the bucket sizes kept for the next iteration read the light
+    // store, the connection pool and frozen statistics only, none of the reciprocal estimates, so
+    // they run on a second stream beside the reciprocal block and join before the proxy
+    // connections. Iterations with PT_FLAG_TIMING stay on one stream so that each timed kernel has
+    // the device to itself, and so do captured iterations (pt_render_batch, pt_render_scenes: a
+    // fork inside the multi-scene capture ended the process; their scenes already run side by
+    // side as the graph's branches).
+    const bool overlap = !timing && !graph && proxy && s->side;
+    hipStream_t es = stream;
+    if (overlap) {
+        HIPCHK(hipEventRecord(s->ev_fork, stream));
+        HIPCHK(hipStreamWaitEvent(s->side, s->ev_fork, 0));
+        es = s->side;
+    }
+    // eye pass. Without MIS the proxy strategy alone scores the proxy-class paths (a partition);
+    // with MIS, PT/NEE keep them with the weights of Section 5.4.
+    EyeParams EP{};
+    EP.seed = p->seed; EP.K = p->max_depth; EP.u_max = p->u_max;
+    EP.proxy_on = proxy && !(p->flags & PT_FLAG_ONLY_OTHER);
+    const bool only_cls = (p->flags & PT_FLAG_ONLY_PROXY_CLASS) != 0, only_oth = (p->flags & PT_FLAG_ONLY_OTHER) != 0;
+    if (EP.proxy_on && !mis) EP.filter = only_cls ? 3 : 2;
+    else EP.filter = only_cls ? 1 : (only_oth ? 2 : 0);
+    EP.nee_on = (p->flags & PT_FLAG_NEE) != 0;
+    EP.mis_on = mis && EP.proxy_on;
+    EP.labels_on = labels && EP.proxy_on;
+    EP.gamma_on = gamma;
+    EP.mlp_on = mlp && EP.proxy_on;
+    EP.tiles_on = tiles;
+    EP.M = M; EP.cand_cap = p->cand_cap;
+    EP.mk = mk; EP.conn_on = conn && lmax >= 2;
+    SubDev D{};
+    if (s->n_eye > 0) {
+        D.eye_c = s->eye_c; D.spec_c = s->spec_c; D.n_eye = ne; D.n_spec = ns;
+        D.eye = cent_set(s->eye_c, s->gs_eye); D.spec = cent_set(s->spec_c, s->gs_spec);
+        D.s_count = s->s_count; D.s_off = s->s_off; D.s_list = s->s_list; D.nonempty = s->nonempty; D.n_nonempty = s->n_ne;
+        D.al_prob = s->al_prob; D.al_idx = s->al_idx; D.row_sum = s->row_sum; D.gamma = s->gamma_frz;
+        D.defensive = p->defensive; D.rstat = s->rstat_frz;
+        D.prev = s->prev; D.s_count_prev = s->s_count_prev; D.row_tot = s->row_tot;
+        D.tile_proxy = s->tile_proxy; D.tile_total = s->tile_total; D.tile = s->tile; D.tiles_x = s->tiles_x;
+        D.tile_thr = p->tile_threshold; D.tile_low = p->tile_low_prob;
+    }
+    const int np = s->npix;
+    k_camera<<<blocks(np, 256), 256, 0, es>>>(S, E, p->seed, s->cnt);
+    for (int t = 1; t <= p->max_depth; ++t) {
+        if (timing) HIPCHK(hipEventRecord(s->ev[2 * (t - 1)], es));
+        if (count)
+            k_extend<true><<<blocks(np, WG), WG, 0, es>>>(S, E.q[(t - 1) & 1], s->cnt, C_EYE_Q0 + t - 1, E.ro, E.rd,
+                                                              E.hit, s->cnt, C_RAYS_EYE);
+        else
+            k_extend<false><<<blocks(np, WG), WG, 0, es>>>(S, E.q[(t - 1) & 1], s->cnt, C_EYE_Q0 + t - 1, E.ro, E.rd,
+                                                               E.hit, s->cnt, C_RAYS_EYE);
+        if (timing) HIPCHK(hipEventRecord(s->ev[2 * (t - 1) + 1], es));
+        k_eye_shade<<<blocks(np, 256), 256, 0, es>>>(S, E, EP, D, L, CD, t, s->cnt);
+        k_occluded<<<blocks(2L * np, WG), WG, 0, es>>>(S, E, CD, t, s->cnt);
+    }
+    if (ltr && lmax >= 2)
+        k_lt<<<blocks((long)(lmax - 1) * M, WG), WG, 0, es>>>(S, L, EP, D, CD, E.frame, s->cnt);
+    if (conn && lmax >= 2) k_conn_prev<<<blocks(nl, 256), 256, 0, es>>>(CD, s->lcount_prev, s->lne_prev);
     if (proxy) {
         if (lmax >= 2) {
             k_candidates<<<blocks(M, 256), 256, 0, stream>>>(L, p->u_max, s->cand, s->cnt);
@@ -796,50 +865,10 @@ pt_status enqueue_iteration(pt_scene *s, const pt_iter_params *p, float *acc, fl
             }
         }
     }
-    // eye pass. Without MIS the proxy strategy alone scores the proxy-class paths (a partition);
-    // with MIS, PT/NEE keep them with the weights of Section 5.4.
-    EyeParams EP{};
-    EP.seed = p->seed; EP.K = p->max_depth; EP.u_max = p->u_max;
-    EP.proxy_on = proxy && !(p->flags & PT_FLAG_ONLY_OTHER);
-    const bool only_cls = (p->flags & PT_FLAG_ONLY_PROXY_CLASS) != 0, only_oth = (p->flags & PT_FLAG_ONLY_OTHER) != 0;
-    if (EP.proxy_on && !mis) EP.filter = only_cls ? 3 : 2;
-    else EP.filter = only_cls ? 1 : (only_oth ? 2 : 0);
-    EP.nee_on = (p->flags & PT_FLAG_NEE) != 0;
-    EP.mis_on = mis && EP.proxy_on;
-    EP.labels_on = labels && EP.proxy_on;
-    EP.gamma_on = gamma;
-    EP.mlp_on = mlp && EP.proxy_on;
-    EP.tiles_on = tiles;
-    EP.M = M; EP.cand_cap = p->cand_cap;
-    EP.mk = mk; EP.conn_on = conn && lmax >= 2;
-    SubDev D{};
-    if (s->n_eye > 0) {
-        D.eye_c = s->eye_c; D.spec_c = s->spec_c; D.n_eye = ne; D.n_spec = ns;
-        D.eye = cent_set(s->eye_c, s->gs_eye); D.spec = cent_set(s->spec_c, s->gs_spec);
-        D.s_count = s->s_count; D.s_off = s->s_off; D.s_list = s->s_list; D.nonempty = s->nonempty; D.n_nonempty = s->n_ne;
-        D.al_prob = s->al_prob; D.al_idx = s->al_idx; D.row_sum = s->row_sum; D.gamma = s->gamma_frz;
-        D.defensive = p->defensive; D.rstat = s->rstat_frz;
-        D.prev = s->prev; D.s_count_prev = s->s_count_prev; D.row_tot = s->row_tot;
-        D.tile_proxy = s->tile_proxy; D.tile_total = s->tile_total; D.tile = s->tile; D.tiles_x = s->tiles_x;
-        D.tile_thr = p->tile_threshold; D.tile_low = p->tile_low_prob;
+    if (overlap) {
+        HIPCHK(hipEventRecord(s->ev_join, es));
+        HIPCHK(hipStreamWaitEvent(stream, s->ev_join, 0));
     }
-    const int np = s->npix;
-    k_camera<<<blocks(np, 256), 256, 0, stream>>>(S, E, p->seed, s->cnt);
-    for (int t = 1; t <= p->max_depth; ++t) {
-        if (timing) HIPCHK(hipEventRecord(s->ev[2 * (t - 1)], stream));
-        if (count)
-            k_extend<true><<<blocks(np, WG), WG, 0, stream>>>(S, E.q[(t - 1) & 1], s->cnt, C_EYE_Q0 + t - 1, E.ro, E.rd,
-                                                              E.hit, s->cnt, C_RAYS_EYE);
-        else
-            k_extend<false><<<blocks(np, WG), WG, 0, stream>>>(S, E.q[(t - 1) & 1], s->cnt, C_EYE_Q0 + t - 1, E.ro, E.rd,
-                                                               E.hit, s->cnt, C_RAYS_EYE);
-        if (timing) HIPCHK(hipEventRecord(s->ev[2 * (t - 1) + 1], stream));
-        k_eye_shade<<<blocks(np, 256), 256, 0, stream>>>(S, E, EP, D, L, CD, t, s->cnt);
-        k_occluded<<<blocks(2L * np, WG), WG, 0, stream>>>(S, E, CD, t, s->cnt);
-    }
-    if (ltr && lmax >= 2)
-        k_lt<<<blocks((long)(lmax - 1) * M, WG), WG, 0, stream>>>(S, L, EP, D, CD, E.frame, s->cnt);
-    if (conn && lmax >= 2) k_conn_prev<<<blocks(nl, 256), 256, 0, stream>>>(CD, s->lcount_prev, s->lne_prev);
     StatBuf SB{s->gamma_acc, s->tile_proxy, s->tile_total};
     if (EP.mlp_on) {
         // the network's logits for every queued first diffuse vertex, then S per item
