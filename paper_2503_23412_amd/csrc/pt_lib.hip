@@ -736,6 +736,21 @@ pt_status enqueue_iteration(pt_scene *s, const pt_iter_params *p, float *acc, fl
             k_light_shade<<<blocks(M, 256), 256, 0, stream>>>(S, L, p->seed, vi, lmax, s->cnt);
         }
     }
+    // The connection pool, the eye pass, light tracing and the bucket sizes kept for the next
+    // iteration read the light store and frozen statistics only, none of the reciprocal
+    // estimates, and the reciprocal block reads none of theirs, so they run on a second stream
+    // beside the reciprocal block, forked after the light pass and joined before the proxy
+    // connections. Iterations with PT_FLAG_TIMING stay on one stream so that each timed kernel has
+    // the device to itself, and so do captured iterations (pt_render_batch, pt_render_scenes: a
+    // fork inside the multi-scene capture ended the process; their scenes already run side by
+    // side as the graph's branches).
+    const bool overlap = !timing && !graph && proxy && s->side;
+    hipStream_t es = stream;
+    if (overlap) {
+        HIPCHK(hipEventRecord(s->ev_fork, stream));
+        HIPCHK(hipStreamWaitEvent(s->side, s->ev_fork, 0));
+        es = s->side;
+    }
     const MisK mk{(p->flags & PT_FLAG_NEE) ? 1.0f : 0.0f, conn ? 1.0f : 0.0f, ltr ? (float)M : 0.0f};
     const int nl = s->n_lsub;
     ConnDev CD{};
@@ -748,36 +763,22 @@ pt_status enqueue_iteration(pt_scene *s, const pt_iter_params *p, float *acc, fl
         CD.row_tot = s->q_rowtot; CD.count_prev = s->lcount_prev; CD.ne_prev = s->lne_prev;
         CD.defensive = p->defensive; CD.qacc = s->qacc;
         // Q of earlier iterations only
-        k_copy<<<blocks((long)ne * nl, 256), 256, 0, stream>>>(s->qacc, s->qfrz, (size_t)ne * nl);
-        k_row_tot<<<blocks(ne, 256), 256, 0, stream>>>(s->qfrz, ne, nl, s->q_rowtot);
+        k_copy<<<blocks((long)ne * nl, 256), 256, 0, es>>>(s->qacc, s->qfrz, (size_t)ne * nl);
+        k_row_tot<<<blocks(ne, 256), 256, 0, es>>>(s->qfrz, ne, nl, s->q_rowtot);
     }
     if ((conn || ltr) && lmax >= 2) {
-        k_pool<<<blocks((long)(lmax - 1) * M, 256), 256, 0, stream>>>(L, lmax, s->cnt);
+        k_pool<<<blocks((long)(lmax - 1) * M, 256), 256, 0, es>>>(L, lmax, s->cnt);
         if (conn) {
             // bucket the pool by light subspace; alias rows of Q over the non-empty buckets
             const long maxp = (long)(lmax - 1) * M;
-            k_fill_i<<<blocks(nl, 256), 256, 0, stream>>>(s->lcount, 0, (size_t)nl);
-            k_pool_label<<<blocks(maxp, 256), 256, 0, stream>>>(S, L, CD, s->cnt);
-            k_scan_sub<<<1, 1024, 0, stream>>>(s->lcount, s->loff, s->lfill, s->lnonempty, s->ln_ne, nl);
-            k_scatter_pool<<<blocks(maxp, 256), 256, 0, stream>>>(L, CD, s->cnt);
-            k_alias_rows<<<blocks(ne, 64), 64, 0, stream>>>(s->qfrz, ne, nl, s->lnonempty, s->ln_ne, p->defensive,
+            k_fill_i<<<blocks(nl, 256), 256, 0, es>>>(s->lcount, 0, (size_t)nl);
+            k_pool_label<<<blocks(maxp, 256), 256, 0, es>>>(S, L, CD, s->cnt);
+            k_scan_sub<<<1, 1024, 0, es>>>(s->lcount, s->loff, s->lfill, s->lnonempty, s->ln_ne, nl);
+            k_scatter_pool<<<blocks(maxp, 256), 256, 0, es>>>(L, CD, s->cnt);
+            k_alias_rows<<<blocks(ne, 64), 64, 0, es>>>(s->qfrz, ne, nl, s->lnonempty, s->ln_ne, p->defensive,
                                                            s->q_alprob, s->q_alidx, s->q_rowsum, s->q_scratch);
         }
-        k_light_phi<<<blocks(M, 256), 256, 0, stream>>>(S, L, mk, CD, s->cnt);
-    }
-    // The eye pass, light tracing and the bucket sizes kept for the next iteration read the light
-    // store, the connection pool and frozen statistics only, none of the reciprocal estimates, so
-    // they run on a second stream beside the reciprocal block and join before the proxy
-    // connections. Iterations with PT_FLAG_TIMING stay on one stream so that each timed kernel has
-    // the device to itself, and so do captured iterations (pt_render_batch, pt_render_scenes: a
-    // fork inside the multi-scene capture ended the process; their scenes already run side by
-    // side as the graph's branches).
-    const bool overlap = !timing && !graph && proxy && s->side;
-    hipStream_t es = stream;
-    if (overlap) {
-        HIPCHK(hipEventRecord(s->ev_fork, stream));
-        HIPCHK(hipStreamWaitEvent(s->side, s->ev_fork, 0));
-        es = s->side;
+        k_light_phi<<<blocks(M, 256), 256, 0, es>>>(S, L, mk, CD, s->cnt);
     }
     // eye pass. Without MIS the proxy strategy alone scores the proxy-class paths (a partition);
     // with MIS, PT/NEE keep them with the weights of Section 5.4.
