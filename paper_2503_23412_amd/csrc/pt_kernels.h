@@ -909,6 +909,65 @@ __device__ __forceinline__ void chain_consume(float fq, float u, int nv, float i
     }
 }
 
+// the same for 256 samples held four per lane (sample 4 * lane + i), in sample order: one
+// memory round trip of the rounds' consumer covers four times as many samples
+__device__ __forceinline__ void chain_consume4(const float (&fq)[4], const float (&uu)[4], float invB, ChainRun &st,
+                                               uint32_t seed, uint32_t chain, uint32_t iter)
+{
+    const int lane = __lane_id();
+    float g[4];
+    uint32_t kids[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        g[i] = 1.0f - fq[i] * invB;
+        const float ag = fabsf(g[i]), fl = floorf(ag);
+        kids[i] = (uint32_t)fminf(fl, 1.0e6f) + (uu[i] < ag - fl ? 1u : 0u);
+    }
+    int l = 0;
+    while (l < 256 && st.alive && st.pos + st.neg > 0) {
+        if (st.pos == 1 && st.neg == 0) {
+            // the first event at or after sample l; samples before it continue the chain
+            int e = 256;
+#pragma unroll
+            for (int i = 3; i >= 0; --i) {
+                const int j = 4 * lane + i;
+                if (j >= l && (kids[i] == 0u || g[i] < 0.0f || st.ns + (uint32_t)(j - l) == st.next_flip)) e = j;
+            }
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) e = min(e, __shfl_xor(e, off));
+            float sum = 0.0f;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int j = 4 * lane + i;
+                sum += (j >= l && j < e) ? g[i] : 0.0f;
+            }
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) sum += __shfl_xor(sum, off);
+            st.ans += (double)sum;
+            st.ns += (uint32_t)(e - l);
+            l = e;
+            if (l >= 256) break;
+        }
+        // one sample through the general rule
+        if (st.ns == st.next_flip) {
+            if (chain_coin(seed, chain, iter, st.coin++) < 0.5f) st.weight *= 2.0f;
+            else { st.alive = false; break; }
+            st.next_flip *= 2u;
+        }
+        const int li = l & 3;
+        const float gs = li == 0 ? g[0] : li == 1 ? g[1] : li == 2 ? g[2] : g[3];
+        const uint32_t ks = li == 0 ? kids[0] : li == 1 ? kids[1] : li == 2 ? kids[2] : kids[3];
+        const float gl = __shfl(gs, l >> 2);
+        const uint32_t kl = (uint32_t)__shfl((int)ks, l >> 2);
+        bool positive = st.pos > 0;
+        if (positive) st.pos--; else st.neg--;
+        st.ns++;
+        st.ans += positive ? (double)gl : -(double)gl;
+        if (positive == (gl >= 0.0f)) st.pos += kl; else st.neg += kl;
+        ++l;
+    }
+}
+
 __device__ __forceinline__ void chain_finish(Cand &c, const ChainRun &st, bool trunc, float mx, float *runmax,
                                              unsigned long long *cnt)
 {
@@ -974,13 +1033,16 @@ __global__ void __launch_bounds__(64 * RW, PT_RECIP_WAVES) k_recip(SceneDev S, C
     count_traversal(C, cnt, C_VISITS_A, C_TESTS_A, C_TRIPS_A);
 }
 
-// samples per chain in round r for n running chains: doubling from stage A's budget (1024), so
-// that a chain draws at most about twice the samples it uses, within the buffer
+// samples per chain in round r for n running chains: doubling from 1024, so that a chain draws at
+// most about twice the samples it uses; when few chains remain, enough to fill the device in one
+// launch (CHAIN_FILL samples over all chains), so that long chains end in fewer latency-bound
+// rounds; within the buffer; a multiple of 256 (the consumer's block)
+#define CHAIN_FILL (1u << 18)
 __device__ __forceinline__ uint32_t chain_round_size(uint32_t n, int round)
 {
-    const uint32_t gmax = 1024u << round;
-    const uint32_t fit = (CHAIN_BUF / max(n, 1u)) & ~63u;
-    return max(64u, min(gmax, fit));
+    const uint32_t want = max(1024u << round, CHAIN_FILL / max(n, 1u)) & ~255u;
+    const uint32_t fit = (CHAIN_BUF / max(n, 1u)) & ~255u;
+    return max(256u, min(want, fit));
 }
 
 // round r, part 1: every lane of the grid draws samples for the running chains
@@ -1027,10 +1089,11 @@ __global__ void __launch_bounds__(64 * RW) k_chain_consume(Cand *cand, const Cha
         const uint32_t G = chain_round_size(n, round);
         const float2 *b = buf + (size_t)wave * G;
         float mx = q.mx;
-        for (uint32_t base = 0; base < G && st.alive && st.pos + st.neg > 0; base += 64) {
-            const float2 v = b[base + lane];
-            mx = fmaxf(mx, v.x);
-            chain_consume(v.x, v.y, 64, invB, st, seed, q.chain, iter);
+        for (uint32_t base = 0; base < G && st.alive && st.pos + st.neg > 0; base += 256) {
+            const float4 v0 = *(const float4 *)(b + base + 4 * lane), v1 = *(const float4 *)(b + base + 4 * lane + 2);
+            const float fq[4] = {v0.x, v0.z, v1.x, v1.z}, uu[4] = {v0.y, v0.w, v1.y, v1.w};
+            mx = fmaxf(mx, fmaxf(fmaxf(fq[0], fq[1]), fmaxf(fq[2], fq[3])));
+            chain_consume4(fq, uu, invB, st, seed, q.chain, iter);
         }
 #pragma unroll
         for (int off = 32; off > 0; off >>= 1) mx = fmaxf(mx, __shfl_xor(mx, off));
