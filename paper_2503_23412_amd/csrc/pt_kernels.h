@@ -69,13 +69,13 @@ __device__ __forceinline__ uint32_t iter_of(const unsigned long long *cnt) { ret
 
 // closest hit for every queued ray; rays live in (ro, rd) by path id, ro.w = ignored triangle,
 // rd.w = tmax; writes hit[pid] = (t, b1, b2, triangle or -1)
-template <bool COUNT>
+template <bool COUNT, typename SE>
 __global__ void __launch_bounds__(WG) k_extend(SceneDev S, const uint32_t *__restrict__ q,
                                                const unsigned long long *__restrict__ cnt, int cidx,
                                                const float4 *__restrict__ ro, const float4 *__restrict__ rd,
                                                float4 *__restrict__ hit, unsigned long long *stats, int ray_ctr)
 {
-    __shared__ int stk[PT_STACK * WG];
+    __shared__ SE stk[PT_STACK * WG];
     const int i = blockIdx.x * WG + threadIdx.x;
     const int n = (int)cnt[cidx];
     uint32_t visits = 0, tests = 0;
@@ -84,7 +84,7 @@ __global__ void __launch_bounds__(WG) k_extend(SceneDev S, const uint32_t *__res
         const int pid = q[i];
         const float4 o = ro[pid], d = rd[pid];
         Hit h;
-        traverse<false, COUNT>(S, xyz(o), xyz(d), S.tmin, d.w, fbits(o.w), -1, stk + threadIdx.x, WG, h, &visits, &tests);
+        traverse<false, COUNT>(S, xyz(o), xyz(d), S.tmin, d.w, fbits(o.w), -1, stk_col(stk, (int)threadIdx.x), WG, h, &visits, &tests);
         hit[pid] = make_float4(h.t, h.b1, h.b2, ibits(h.tri));
     }
     wave_count(stats + ray_ctr, act ? 1u : 0u);
@@ -1525,10 +1525,11 @@ __global__ void k_eye_shade(SceneDev S, EyeBuf E, EyeParams P, SubDev D, LightBu
 // weighted against the other strategies (w = M / (M + A_k)); with the proxy strategy and its MIS,
 // proxy-class paths are weighed against emission hits, NEE and the proxy (w = M / (M + A'_k +
 // B_k P_proxy / P_0), A' without connections, B_k the emission-hit term of A_k).
+template <typename SE>
 __global__ void __launch_bounds__(WG) k_lt(SceneDev S, LightBuf L, EyeParams P, SubDev D, ConnDev C, float *frame,
                                            unsigned long long *cnt)
 {
-    __shared__ int stk[PT_STACK * WG];
+    __shared__ SE stk[PT_STACK * WG];
     const int i = blockIdx.x * WG + threadIdx.x;
     const uint32_t npool = (uint32_t)cnt[C_POOL];
     uint32_t done = 0, rays = 0;
@@ -1626,7 +1627,7 @@ __global__ void __launch_bounds__(WG) k_lt(SceneDev S, LightBuf L, EyeParams P, 
                     if (nonzero3(c)) {
                         Hit hh;
                         rays = 1;
-                        if (!traverse<true, false>(S, y, wyc, S.tmin, dist * 0.9999f, ty, -1, stk + threadIdx.x, WG, hh)) {
+                        if (!traverse<true, false>(S, y, wyc, S.tmin, dist * 0.9999f, ty, -1, stk_col(stk, (int)threadIdx.x), WG, hh)) {
                             atomic_add3(frame + 3 * (py * cam.w + px), c);
                             done = 1;
                         }
@@ -1640,16 +1641,17 @@ __global__ void __launch_bounds__(WG) k_lt(SceneDev S, LightBuf L, EyeParams P, 
 }
 
 // shadow rays of NEE and connections; a visible connection's luminance trains Q while learning
+template <typename SE>
 __global__ void __launch_bounds__(WG) k_occluded(SceneDev S, EyeBuf E, ConnDev C, int t, unsigned long long *cnt)
 {
-    __shared__ int stk[PT_STACK * WG];
+    __shared__ SE stk[PT_STACK * WG];
     const int i = blockIdx.x * WG + threadIdx.x;
     const int n = (int)cnt[C_SHD0 + t];
     const bool act = i < n;
     if (act) {
         const ShadowRay sr = E.shadow[i];
         Hit h;
-        if (!traverse<true, false>(S, xyz(sr.o), xyz(sr.d), S.tmin, sr.d.w, fbits(sr.o.w), sr.ign1, stk + threadIdx.x,
+        if (!traverse<true, false>(S, xyz(sr.o), xyz(sr.d), S.tmin, sr.d.w, fbits(sr.o.w), sr.ign1, stk_col(stk, (int)threadIdx.x),
                                    WG, h)) {
             atomic_add3(E.frame + 3 * fbits(sr.c.w), xyz(sr.c));
             if (sr.tag >= 0 && C.qacc && cnt[C_LEARN])
@@ -1673,15 +1675,16 @@ struct StatBuf {
 // then at each new vertex, abort on an S/D mismatch, weight with 1/P's estimate and normalise by
 // M pi_inc rho pi_j c; p(h*) = 1 (class A) or 1/A (class B). With MIS the contribution is
 // weighted against PT and NEE (Section 5.4) with the same surrogate densities the eye pass uses.
+template <typename SE>
 __global__ void __launch_bounds__(WG) k_proxy(SceneDev S, EyeBuf E, const Cand *__restrict__ cand,
                                               const uint32_t *__restrict__ final_, EyeParams P, SubDev D,
                                               StatBuf SB, MlpTrain MT, int repeats, unsigned long long *cnt)
 {
-    __shared__ int stk[PT_STACK * WG];
+    __shared__ SE stk[PT_STACK * WG];
     const int i = blockIdx.x * WG + threadIdx.x;
     const int n = (int)cnt[C_PROXYQ];
     const int nk = (int)cnt[C_NFINAL];
-    Ctx C{S, stk + threadIdx.x, 0u, (int)blockDim.x};
+    CtxT<SE> C{S, stk_col(stk, (int)threadIdx.x), 0u, (int)blockDim.x};
     uint32_t valid = 0;
     if (i < n && nk > 0) {
         const ProxyItem it = E.proxy[i];

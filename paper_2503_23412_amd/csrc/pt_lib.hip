@@ -50,6 +50,23 @@ pt_status check_device()
 
 }  // namespace
 
+// launch a traversal kernel with the scene's stack entry type (16-bit for trees below 65,536 nodes)
+#define PT_STK(sc, kern, grid, block, strm, ...)                                                \
+    do {                                                                                        \
+        if ((sc)->stk16) kern<uint16_t><<<(grid), (block), 0, (strm)>>>(__VA_ARGS__);          \
+        else kern<int><<<(grid), (block), 0, (strm)>>>(__VA_ARGS__);                            \
+    } while (0)
+#define PT_STK_EXT(sc, counting, grid, block, strm, ...)                                        \
+    do {                                                                                        \
+        if ((sc)->stk16) {                                                                      \
+            if (counting) k_extend<true, uint16_t><<<(grid), (block), 0, (strm)>>>(__VA_ARGS__); \
+            else k_extend<false, uint16_t><<<(grid), (block), 0, (strm)>>>(__VA_ARGS__);         \
+        } else {                                                                                \
+            if (counting) k_extend<true, int><<<(grid), (block), 0, (strm)>>>(__VA_ARGS__);      \
+            else k_extend<false, int><<<(grid), (block), 0, (strm)>>>(__VA_ARGS__);              \
+        }                                                                                       \
+    } while (0)
+
 struct pt_scene {
     int device = 0;
     int W = 0, H = 0, npix = 0, max_light = 0, ntri = 0;
@@ -465,8 +482,8 @@ extern "C" pt_status pt_build_subspaces(pt_scene *s, const pt_subspace_params *p
     k_iter<<<1, 1, 0, st>>>(s->cnt, key, 0, 0);
     k_light_gen<<<blocks(L.M, 256), 256, 0, st>>>(S, L, p->seed, s->cnt);
     for (int vi = 1; vi < PT_LMAX; ++vi) {
-        k_extend<false><<<blocks(L.M, WG), WG, 0, st>>>(S, L.q[(vi - 1) & 1], s->cnt, C_LIGHT_Q0 + vi - 1, L.ro, L.rd,
-                                                        L.hit, s->cnt, C_RAYS_LIGHT);
+        PT_STK_EXT(s, false, blocks(L.M, WG), WG, st, S, L.q[(vi - 1) & 1], s->cnt, C_LIGHT_Q0 + vi - 1, L.ro, L.rd,
+                   L.hit, s->cnt, C_RAYS_LIGHT);
         k_light_shade<<<blocks(L.M, 256), 256, 0, st>>>(S, L, p->seed, vi, PT_LMAX, s->cnt);
     }
     unsigned long long c[C_COUNT];
@@ -494,8 +511,8 @@ extern "C" pt_status pt_build_subspaces(pt_scene *s, const pt_subspace_params *p
     k_zero<<<blocks(C_COUNT, 256), 256, 0, st>>>(s->cnt, C_COUNT);
     k_camera<<<blocks(np, 256), 256, 0, st>>>(S, E, p->seed, s->cnt);
     for (int t = 1; t <= EP.K; ++t) {
-        k_extend<false><<<blocks(np, WG), WG, 0, st>>>(S, E.q[(t - 1) & 1], s->cnt, C_EYE_Q0 + t - 1, E.ro, E.rd, E.hit,
-                                                       s->cnt, C_RAYS_EYE);
+        PT_STK_EXT(s, false, blocks(np, WG), WG, st, S, E.q[(t - 1) & 1], s->cnt, C_EYE_Q0 + t - 1, E.ro, E.rd, E.hit,
+                   s->cnt, C_RAYS_EYE);
         k_eye_shade<<<blocks(np, 256), 256, 0, st>>>(S, E, EP, D, L, ConnDev{}, t, s->cnt);
     }
     k_fill<<<blocks(3L * np, 256), 256, 0, st>>>(E.frame, 0.0f, (size_t)3 * np);
@@ -679,12 +696,6 @@ pt_status check_params(pt_scene *s, const pt_iter_params *p, float *acc)
     return PT_OK;
 }
 
-// launch a chain kernel with the scene's traversal-stack entry type
-#define PT_STK_LAUNCH(kern, grid, block, ...)                                                   \
-    do {                                                                                        \
-        if (s->stk16) kern<uint16_t><<<(grid), (block), 0, stream>>>(__VA_ARGS__);             \
-        else kern<int><<<(grid), (block), 0, stream>>>(__VA_ARGS__);                            \
-    } while (0)
 
 
 // Enqueues one iteration on `stream`: kernel launches only (no host synchronisation, no
@@ -731,8 +742,8 @@ pt_status enqueue_iteration(pt_scene *s, const pt_iter_params *p, float *acc, fl
     if (proxy || conn || ltr) {
         k_light_gen<<<blocks(M, 256), 256, 0, stream>>>(S, L, p->seed, s->cnt);
         for (int vi = 1; vi < lmax; ++vi) {
-            k_extend<false><<<blocks(M, WG), WG, 0, stream>>>(S, L.q[(vi - 1) & 1], s->cnt, C_LIGHT_Q0 + vi - 1, L.ro,
-                                                              L.rd, L.hit, s->cnt, C_RAYS_LIGHT);
+            PT_STK_EXT(s, false, blocks(M, WG), WG, stream, S, L.q[(vi - 1) & 1], s->cnt, C_LIGHT_Q0 + vi - 1, L.ro,
+                       L.rd, L.hit, s->cnt, C_RAYS_LIGHT);
             k_light_shade<<<blocks(M, 256), 256, 0, stream>>>(S, L, p->seed, vi, lmax, s->cnt);
         }
     }
@@ -811,18 +822,14 @@ pt_status enqueue_iteration(pt_scene *s, const pt_iter_params *p, float *acc, fl
     k_camera<<<blocks(np, 256), 256, 0, es>>>(S, E, p->seed, s->cnt);
     for (int t = 1; t <= p->max_depth; ++t) {
         if (timing) HIPCHK(hipEventRecord(s->ev[2 * (t - 1)], es));
-        if (count)
-            k_extend<true><<<blocks(np, WG), WG, 0, es>>>(S, E.q[(t - 1) & 1], s->cnt, C_EYE_Q0 + t - 1, E.ro, E.rd,
-                                                              E.hit, s->cnt, C_RAYS_EYE);
-        else
-            k_extend<false><<<blocks(np, WG), WG, 0, es>>>(S, E.q[(t - 1) & 1], s->cnt, C_EYE_Q0 + t - 1, E.ro, E.rd,
-                                                               E.hit, s->cnt, C_RAYS_EYE);
+        PT_STK_EXT(s, count, blocks(np, WG), WG, es, S, E.q[(t - 1) & 1], s->cnt, C_EYE_Q0 + t - 1, E.ro, E.rd, E.hit,
+                   s->cnt, C_RAYS_EYE);
         if (timing) HIPCHK(hipEventRecord(s->ev[2 * (t - 1) + 1], es));
         k_eye_shade<<<blocks(np, 256), 256, 0, es>>>(S, E, EP, D, L, CD, t, s->cnt);
-        k_occluded<<<blocks(2L * np, WG), WG, 0, es>>>(S, E, CD, t, s->cnt);
+        PT_STK(s, k_occluded, blocks(2L * np, WG), WG, es, S, E, CD, t, s->cnt);
     }
     if (ltr && lmax >= 2)
-        k_lt<<<blocks((long)(lmax - 1) * M, WG), WG, 0, es>>>(S, L, EP, D, CD, E.frame, s->cnt);
+        PT_STK(s, k_lt, blocks((long)(lmax - 1) * M, WG), WG, es, S, L, EP, D, CD, E.frame, s->cnt);
     if (conn && lmax >= 2) k_conn_prev<<<blocks(nl, 256), 256, 0, es>>>(CD, s->lcount_prev, s->lne_prev);
     if (proxy) {
         if (lmax >= 2) {
@@ -831,19 +838,19 @@ pt_status enqueue_iteration(pt_scene *s, const pt_iter_params *p, float *acc, fl
             k_keep<<<blocks(maxc, 256), 256, 0, stream>>>(p->cand_cap, p->seed, s->kept, maxc, s->cnt);
             const size_t e0 = 2 * (size_t)p->max_depth;
             if (timing) HIPCHK(hipEventRecord(s->ev[e0], stream));
-            PT_STK_LAUNCH(k_pilot, s->persist_wg, 64 * RW, S, s->cand, s->kept, p->pilot, p->seed, s->runmax, s->cnt);
+            PT_STK(s, k_pilot, s->persist_wg, 64 * RW, stream, S, s->cand, s->kept, p->pilot, p->seed, s->runmax, s->cnt);
             k_roulette<<<blocks(maxc, 256), 256, 0, stream>>>(s->cand, s->kept, s->final_, s->cost_bin, s->runmax,
                                                               S.em_area, p->recip_repeats, p->cost_cap, p->seed, s->cnt);
             k_order<<<blocks(maxc, 256), 256, 0, stream>>>(s->cost_bin, s->order, s->cnt);
             const uint32_t n1 = (uint32_t)std::max(64.0f, p->cost_cap / (float)p->recip_repeats);
             if (timing) HIPCHK(hipEventRecord(s->ev[e0 + 1], stream));
-            PT_STK_LAUNCH(k_recip, s->persist_wg, 64 * RW, S, s->cand, s->final_, s->order, p->recip_repeats, p->seed, n1,
+            PT_STK(s, k_recip, s->persist_wg, 64 * RW, stream, S, s->cand, s->final_, s->order, p->recip_repeats, p->seed, n1,
                           s->tune_budget, s->runmax, s->chq[0], s->cnt);
             if (timing) HIPCHK(hipEventRecord(s->ev[e0 + 2], stream));
             for (int r = 0; r < CHAIN_ROUNDS; ++r) {
                 const int in = r & 1, out = in ^ 1;
                 k_set_counter<<<1, 1, 0, stream>>>(s->cnt, C_LONGQ0 + out, 0ull);
-                PT_STK_LAUNCH(k_chain_gen, s->tune_gen_grid, WG, S, s->cand, s->chq[in], C_LONGQ0 + in, r, p->seed,
+                PT_STK(s, k_chain_gen, s->tune_gen_grid, WG, stream, S, s->cand, s->chq[in], C_LONGQ0 + in, r, p->seed,
                               s->chbuf, s->cnt);
                 k_chain_consume<<<2048, 64 * RW, 0, stream>>>(s->cand, s->chq[in], C_LONGQ0 + in, s->chq[out],
                                                               C_LONGQ0 + out, r, r == CHAIN_ROUNDS - 1 ? 1 : 0,
@@ -881,8 +888,8 @@ pt_status enqueue_iteration(pt_scene *s, const pt_iter_params *p, float *acc, fl
                                                           gamma ? 1 : 0, p->seed, s->cnt);
     }
     if (EP.proxy_on)
-        k_proxy<<<blocks(np, WG), WG, 0, stream>>>(S, E, s->cand, s->final_, EP, D, SB, s->MT, p->recip_repeats,
-                                                   s->cnt);
+        PT_STK(s, k_proxy, blocks(np, WG), WG, stream, S, E, s->cand, s->final_, EP, D, SB, s->MT, p->recip_repeats,
+               s->cnt);
     if (EP.mlp_on) {
         // online training on this iteration's samples (no work unless the iteration recorded some)
         k_mlp_enc_feat<<<blocks(MLP_CAP, 256), 256, 0, stream>>>(s->MT.feat, MLP_CAP, s->cnt, C_MLP_N, s->mx);
