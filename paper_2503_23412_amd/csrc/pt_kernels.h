@@ -253,6 +253,7 @@ struct ConnDev {
     int n_lsub, n_eye, M;
     // this iteration: label of every pool vertex (index i * M + path), buckets, alias rows
     int *lab;
+    int *rank;                 // place of every pool vertex within its bucket (index i * M + path)
     int *count, *off, *fill, *list, *nonempty, *n_nonempty;
     const float *al_prob, *row_sum;
     const int *al_idx;
@@ -300,23 +301,34 @@ __device__ __forceinline__ float conn_sel(const ConnDev &C, int T, int Sl)
 }
 
 // label every pool vertex and count the buckets
-__global__ void k_pool_label(SceneDev S, LightBuf L, ConnDev C, unsigned long long *cnt)
+// the pool as in k_pool, and at once every pool vertex's light subspace label and its place in
+// that label's bucket (the bucket counter before the increment), so that the scatter after the
+// scan of the counts needs no atomics
+__global__ void k_pool_label(SceneDev S, LightBuf L, int lmax, ConnDev C, unsigned long long *cnt)
 {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= (int)cnt[C_POOL]) return;
-    const uint32_t v = L.pool[i];
+    const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = 1 + (int)(idx / L.M), pid = (int)(idx % L.M);
+    bool in = false;
+    uint32_t v = 0;
+    if (j < lmax) {
+        v = (uint32_t)j * (uint32_t)L.M + (uint32_t)pid;
+        in = j < sig_count(L.sig[pid]) && !(L.lfl[v] & LV_DIRAC);
+    }
+    const int slot = wave_push(cnt + C_POOL, in);
+    if (!in) return;
+    L.pool[slot] = v;
     const float4 y = L.lv[v];
     const float3 w = normalize3(xyz(L.lv[v - (uint32_t)L.M]) - xyz(y));
     const int lab = conn_label_light(S, C, xyz(y), S.shade[fbits(y.w)].n, w);
     C.lab[v] = lab;
-    atomicAdd(C.count + lab, 1);
+    C.rank[v] = atomicAdd(C.count + lab, 1);
 }
 __global__ void k_scatter_pool(LightBuf L, ConnDev C, const unsigned long long *cnt)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= (int)cnt[C_POOL]) return;
     const uint32_t v = L.pool[i];
-    C.list[atomicAdd(C.fill + C.lab[v], 1)] = (int)v;
+    C.list[C.off[C.lab[v]] + C.rank[v]] = (int)v;
 }
 // end of an iteration: its bucket sizes become the next iteration's frozen inputs
 __global__ void k_conn_prev(ConnDev C, int *count_prev, float *ne_prev)

@@ -67,6 +67,19 @@ pt_status check_device()
         }                                                                                       \
     } while (0)
 
+// alias rows of a T x n table over its non-empty columns: one wavefront per row when the row
+// fits LDS, else one thread per row
+static void alias_rows(const float *tab, int ne, int n, const int *nonempty, const int *n_nonempty, float defensive,
+                       float *al_prob, int *al_idx, float *row_sum, int *scratch, hipStream_t st)
+{
+    if (n <= ALIAS_LDS_COLS)
+        k_alias_rows_wave<<<ne, 64, (size_t)16 * n, st>>>(tab, ne, n, nonempty, n_nonempty, defensive, al_prob, al_idx,
+                                                          row_sum);
+    else
+        k_alias_rows<<<blocks(ne, 64), 64, 0, st>>>(tab, ne, n, nonempty, n_nonempty, defensive, al_prob, al_idx, row_sum,
+                                                   scratch);
+}
+
 struct pt_scene {
     int device = 0;
     int W = 0, H = 0, npix = 0, max_light = 0, ntri = 0;
@@ -93,7 +106,7 @@ struct pt_scene {
     float *light_c = nullptr, *qacc = nullptr, *qfrz = nullptr, *q_alprob = nullptr, *q_rowsum = nullptr,
           *q_rowtot = nullptr, *lne_prev = nullptr;
     int *lcount = nullptr, *loff = nullptr, *lfill = nullptr, *lnonempty = nullptr, *ln_ne = nullptr, *llist = nullptr,
-        *plab = nullptr, *q_alidx = nullptr, *q_scratch = nullptr, *lcount_prev = nullptr;
+        *plab = nullptr, *prank = nullptr, *q_alidx = nullptr, *q_scratch = nullptr, *lcount_prev = nullptr;
     ChainState *chq[2] = {nullptr, nullptr};   // running reciprocal chains between rounds
     float2 *chbuf = nullptr;                   // (f/q, u) samples of one round
     bool subspaces_ready = false;
@@ -291,7 +304,7 @@ extern "C" pt_status pt_scene_upload(const pt_scene_desc *d, void *stream_, pt_s
         AL(s->E.ro, np); AL(s->E.rd, np); AL(s->E.hit, np); AL(s->E.beta, np); AL(s->E.info, np); AL(s->E.mis, np);
         AL(s->E.q[0], np); AL(s->E.q[1], np);
         AL(s->E.shadow, 2 * (size_t)np); AL(s->E.proxy, np); AL(s->E.mis2, np);
-        AL(s->llist, (size_t)PT_LSTORE * M); AL(s->plab, (size_t)PT_LSTORE * M);
+        AL(s->llist, (size_t)PT_LSTORE * M); AL(s->plab, (size_t)PT_LSTORE * M); AL(s->prank, (size_t)PT_LSTORE * M);
         AL(s->E.frame, (size_t)3 * np);
         AL(s->cnt, C_COUNT);
         AL(s->runmax, 16);
@@ -768,7 +781,7 @@ pt_status enqueue_iteration(pt_scene *s, const pt_iter_params *p, float *acc, fl
     if (conn) {
         CD.light = cent_set(s->light_c, s->gs_light); CD.eye = cent_set(s->eye_c, s->gs_eye);
         CD.n_lsub = nl; CD.n_eye = ne; CD.M = M;
-        CD.lab = s->plab; CD.count = s->lcount; CD.off = s->loff; CD.fill = s->lfill; CD.list = s->llist;
+        CD.lab = s->plab; CD.rank = s->prank; CD.count = s->lcount; CD.off = s->loff; CD.fill = s->lfill; CD.list = s->llist;
         CD.nonempty = s->lnonempty; CD.n_nonempty = s->ln_ne;
         CD.al_prob = s->q_alprob; CD.al_idx = s->q_alidx; CD.row_sum = s->q_rowsum; CD.q = s->qfrz;
         CD.row_tot = s->q_rowtot; CD.count_prev = s->lcount_prev; CD.ne_prev = s->lne_prev;
@@ -778,16 +791,16 @@ pt_status enqueue_iteration(pt_scene *s, const pt_iter_params *p, float *acc, fl
         k_row_tot<<<blocks(ne, 256), 256, 0, es>>>(s->qfrz, ne, nl, s->q_rowtot);
     }
     if ((conn || ltr) && lmax >= 2) {
-        k_pool<<<blocks((long)(lmax - 1) * M, 256), 256, 0, es>>>(L, lmax, s->cnt);
+        const long maxp = (long)(lmax - 1) * M;
+        if (!conn) k_pool<<<blocks(maxp, 256), 256, 0, es>>>(L, lmax, s->cnt);
         if (conn) {
-            // bucket the pool by light subspace; alias rows of Q over the non-empty buckets
-            const long maxp = (long)(lmax - 1) * M;
+            // the pool, bucketed by light subspace; alias rows of Q over the non-empty buckets
             k_fill_i<<<blocks(nl, 256), 256, 0, es>>>(s->lcount, 0, (size_t)nl);
-            k_pool_label<<<blocks(maxp, 256), 256, 0, es>>>(S, L, CD, s->cnt);
+            k_pool_label<<<blocks(maxp, 256), 256, 0, es>>>(S, L, lmax, CD, s->cnt);
             k_scan_sub<<<1, 1024, 0, es>>>(s->lcount, s->loff, s->lfill, s->lnonempty, s->ln_ne, nl);
             k_scatter_pool<<<blocks(maxp, 256), 256, 0, es>>>(L, CD, s->cnt);
-            k_alias_rows<<<blocks(ne, 64), 64, 0, es>>>(s->qfrz, ne, nl, s->lnonempty, s->ln_ne, p->defensive,
-                                                           s->q_alprob, s->q_alidx, s->q_rowsum, s->q_scratch);
+            alias_rows(s->qfrz, ne, nl, s->lnonempty, s->ln_ne, p->defensive, s->q_alprob, s->q_alidx, s->q_rowsum,
+                       s->q_scratch, es);
         }
         k_light_phi<<<blocks(M, 256), 256, 0, es>>>(S, L, mk, CD, s->cnt);
     }
@@ -865,9 +878,8 @@ pt_status enqueue_iteration(pt_scene *s, const pt_iter_params *p, float *acc, fl
                 k_scan_sub<<<1, 1024, 0, stream>>>(s->s_count, s->s_off, s->s_fill, s->nonempty, s->n_ne, ns);
                 k_scatter_sub<<<blocks(maxc, 256), 256, 0, stream>>>(s->cand, s->final_, s->cnt, s->s_fill, s->s_list);
                 if (gamma)
-                    k_alias_rows<<<blocks(ne, 64), 64, 0, stream>>>(s->gamma_frz, ne, ns, s->nonempty, s->n_ne,
-                                                                   p->defensive, s->al_prob, s->al_idx, s->row_sum,
-                                                                   s->al_scratch);
+                    alias_rows(s->gamma_frz, ne, ns, s->nonempty, s->n_ne, p->defensive, s->al_prob, s->al_idx,
+                               s->row_sum, s->al_scratch, stream);
                 k_rstat<<<blocks(maxc, 256), 256, 0, stream>>>(s->cand, s->final_, s->cnt, p->recip_repeats, ns,
                                                                   s->rstat_acc);
             }

@@ -212,6 +212,52 @@ __global__ void k_alias_rows(const float *gamma, int n_eye, int n_spec, const in
     while (nl > 0) { const int gg = large[--nl]; pr[gg] = 1.0f; ai[gg] = gg; }
     while (ns > 0) { const int l = small[--ns]; pr[l] = 1.0f; ai[l] = l; }
 }
+// The same tables with one wavefront per row: the row's probabilities and Vose's worklists in LDS
+// (16 bytes per column, dynamic), the sums and probabilities formed by the 64 lanes, the
+// sequential construction by lane 0 on LDS. Same output as k_alias_rows.
+#define ALIAS_LDS_COLS 2048
+__global__ void __launch_bounds__(64) k_alias_rows_wave(const float *gamma, int n_eye, int n_spec, const int *nonempty,
+                                                        const int *n_nonempty, float defensive, float *al_prob,
+                                                        int *al_idx, float *row_sum)
+{
+    extern __shared__ float alias_sh[];
+    const int T = blockIdx.x, lane = threadIdx.x;
+    if (T >= n_eye) return;   // block-uniform
+    const int ne = *n_nonempty;
+    const float *g = gamma + (size_t)T * n_spec;
+    float rs = 0.0f;
+    for (int j = lane; j < ne; j += 64) rs += g[nonempty[j]];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) rs += __shfl_xor(rs, off);
+    if (lane == 0) row_sum[T] = rs;
+    if (ne == 0) return;
+    float *pr = alias_sh;
+    int *ai = (int *)(pr + n_spec), *small = ai + n_spec, *large = small + n_spec;
+    for (int j = lane; j < ne; j += 64) {
+        const float p = rs > 0.0f ? (1.0f - defensive) * g[nonempty[j]] / rs + defensive / ne : 1.0f / ne;
+        pr[j] = p * ne;
+    }
+    __syncthreads();
+    if (lane == 0) {
+        int ns = 0, nl = 0;
+        for (int j = 0; j < ne; ++j) {
+            if (pr[j] < 1.0f) small[ns++] = j; else large[nl++] = j;
+        }
+        while (ns > 0 && nl > 0) {
+            const int l = small[--ns], gg = large[--nl];
+            ai[l] = gg;
+            pr[gg] = (pr[gg] + pr[l]) - 1.0f;
+            if (pr[gg] < 1.0f) small[ns++] = gg; else large[nl++] = gg;
+        }
+        while (nl > 0) { const int gg = large[--nl]; pr[gg] = 1.0f; ai[gg] = gg; }
+        while (ns > 0) { const int l = small[--ns]; pr[l] = 1.0f; ai[l] = l; }
+    }
+    __syncthreads();
+    float *po = al_prob + (size_t)T * n_spec;
+    int *io = al_idx + (size_t)T * n_spec;
+    for (int j = lane; j < ne; j += 64) { po[j] = pr[j]; io[j] = ai[j]; }
+}
+
 // selection probability of subspace S from eye subspace T (the density the alias row samples)
 __device__ __forceinline__ float sel_prob(const SubDev &D, int T, int S)
 {
