@@ -50,6 +50,10 @@ pt_status check_device()
 
 }  // namespace
 
+#ifndef PT_PERSIST_PER_CU
+#define PT_PERSIST_PER_CU 4   // workgroups per CU of the persistent pilot and stage-A grids
+#endif
+
 // launch a traversal kernel with the scene's stack entry type (16-bit for trees below 65,536 nodes)
 #define PT_STK(sc, kern, grid, block, strm, ...)                                                \
     do {                                                                                        \
@@ -218,7 +222,7 @@ extern "C" pt_status pt_scene_upload(const pt_scene_desc *d, void *stream_, pt_s
         {
             int ncu = 0;
             HIPCHK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, s->device));
-            s->persist_wg = 4 * std::max(ncu, 1);
+            s->persist_wg = PT_PERSIST_PER_CU * std::max(ncu, 1);
             // the second stream of an iteration (default priority) and its fork / join events
             HIPCHK(hipStreamCreateWithFlags(&s->side, hipStreamNonBlocking));
             HIPCHK(hipEventCreateWithFlags(&s->ev_fork, hipEventDisableTiming));
