@@ -108,6 +108,9 @@ enum {
                                        (1 - mlp_mix) x the plain row (Gamma row with PT_FLAG_GAMMA,
                                        else uniform over the non-empty subspaces); trained online
                                        while iteration < train_iters */
+    ,
+    PT_FLAG_BOOTH = 1u << 12        /* reciprocal chains with Booth's roulette (parameter booth_r)
+                                       instead of the RRS function of equ:rr (RR ablation) */
 };
 
 typedef struct {
@@ -128,6 +131,7 @@ typedef struct {
     uint32_t flags;
     float mlp_lr;            /* Adam step size of the learned selection (1e-3) */
     float mlp_mix;           /* weight of the network in the selection mixture, in [0, 1) (0.9) */
+    float booth_r;           /* PT_FLAG_BOOTH: parameter of Booth's roulette (> 0) */
 } pt_iter_params;
 
 /* Host-visible per-iteration statistics (valid once the stream is synchronised when
@@ -233,7 +237,10 @@ typedef struct {
     int32_t hc_prim;         /* -1 for class A */
     float hc_b1, hc_b2;      /* barycentrics of y_0 on hc_prim (emission texture lookup) */
 } pt_cand_desc;
-enum { PT_EST_ITILDE = 0, PT_EST_SIGN = 1 };
+/* PT_EST_BOOTH: Booth's Russian roulette (the comparison of Section 4.2 and the RR ablation of
+ * Section 6): one chain without splitting that, after a prefix of j samples, goes on with
+ * probability min(1, prod_{i<j} |1 - f/(Bq)| / booth_r). */
+enum { PT_EST_ITILDE = 0, PT_EST_SIGN = 1, PT_EST_BOOTH = 2 };
 typedef struct {
     int32_t mode;            /* PT_RECIP_TABLE */
     int32_t n;               /* table size */
@@ -241,7 +248,7 @@ typedef struct {
     const float *q_dev;      /* [n] supporting pmf q(x) > 0 where f > 0 (sums to 1) */
     float B;                 /* the constant B > 0 (B >= max f/q: no splitting) */
     int32_t n_est;           /* independent estimates of 1 / sum f */
-    int32_t estimator;       /* PT_EST_ITILDE or PT_EST_SIGN */
+    int32_t estimator;       /* PT_EST_ITILDE, PT_EST_SIGN or PT_EST_BOOTH */
     uint32_t seed;
     uint32_t cap;            /* sample cap per estimate (0: 65536); hitting it marks the count */
     /* PT_RECIP_CANDIDATE only (s required): the incomplete sub-path, in host memory; per =
@@ -250,6 +257,7 @@ typedef struct {
     const pt_cand_desc *cand;
     int32_t per;
     float *out_p_dev;
+    float booth_r;           /* PT_EST_BOOTH: the roulette's parameter (> 0) */
 } pt_recip_query;
 /* Writes out_est_dev[n_est] (float: estimates of 1 / sum f, or of 1 / P for a candidate) and
  * out_nsamples_dev[n_est] (samples used; bit 31 set when the cap truncated that estimate).

@@ -675,6 +675,30 @@ static double isign(recip_ctx *c)
     return ans;
 }
 
+/* Booth's Russian roulette for 1/int f (Section 4.2, the comparison with Booth 2007; the RR
+ * ablation of Section 6): one chain, no splitting. After the prefix of j samples the chain goes
+ * on with probability r_j = min(1, prod_{i<j} |g_i| / rhat) and the terms beyond it are divided
+ * by r_j, so the estimate is [1 + sum_k prod_{i<k} g_i / prod_{1<=j<k} r_j] / B (equ:RRS_estimator
+ * with Booth's RR function; reading R26). One uniform number is drawn per sample after it, as
+ * I~ draws one for its split, so that on a binary f/q with rhat <= 1 both take the same
+ * decisions from the same stream. */
+static double ibooth(recip_ctx *c, double rhat)
+{
+    double ans = 1.0, prod = 1.0, w = 1.0;
+    for (;;) {
+        if (c->nsamp >= c->cap) { c->truncated = 1; break; }
+        c->nsamp++;
+        double fq = c->sample(c->ctx, c->rng);
+        double g = 1.0 - fq / c->B;
+        prod *= g;
+        ans += prod / w;
+        double r = fmin(1.0, fabs(prod) / rhat);
+        if (!(rng_u01(c->rng) < r)) break;
+        w *= r;
+    }
+    return ans / c->B;
+}
+
 typedef struct { const double *f, *q; double *cdf; int n; } table_ctx;
 static double table_sample(void *p, rng_t *r)
 {
@@ -686,11 +710,11 @@ static double table_sample(void *p, rng_t *r)
 }
 
 /* Discrete problem: target 1 / sum_i f[i], supporting pmf q (q[i] > 0 wherever f[i] > 0).
- * estimator 0 = I~ (the paper's estimator), 1 = I (sign estimator).
- * est[i] and nsamp[i] receive each independent estimate and its sample count.
+ * estimator 0 = I~ (the paper's estimator), 1 = I (sign estimator), 2 = Booth's roulette with
+ * parameter rhat. est[i] and nsamp[i] receive each independent estimate and its sample count.
  * Returns the number of truncated estimates (sample cap reached). */
 int or_recip_table(const double *f, const double *q, int n, double B, int estimator, int n_est,
-                   uint32_t seed, long cap, double *est, double *nsamp)
+                   uint32_t seed, long cap, double *est, double *nsamp, double rhat)
 {
     table_ctx t = {f, q, (double *)malloc(sizeof(double) * (size_t)n), n};
     double acc = 0;
@@ -700,7 +724,7 @@ int or_recip_table(const double *f, const double *q, int n, double B, int estima
         rng_t r;
         rng_init(&r, seed, ST_TABLE, (uint32_t)e, 0, 0);
         recip_ctx c = {table_sample, &t, &r, B, 0, cap > 0 ? cap : (1L << 24), 0};
-        est[e] = estimator == 0 ? itilde(&c) : isign(&c);
+        est[e] = estimator == 0 ? itilde(&c) : estimator == 1 ? isign(&c) : ibooth(&c, rhat);
         nsamp[e] = (double)c.nsamp;
         trunc += c.truncated;
     }

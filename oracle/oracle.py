@@ -63,7 +63,7 @@ def lib():
         L.or_render.argtypes = [P, ctypes.POINTER(Params), P, P, ctypes.POINTER(Stats)]
         L.or_recip_table.restype = ctypes.c_int
         L.or_recip_table.argtypes = [P, P, ctypes.c_int, ctypes.c_double, ctypes.c_int, ctypes.c_int,
-                                     ctypes.c_uint32, ctypes.c_long, P, P]
+                                     ctypes.c_uint32, ctypes.c_long, P, P, ctypes.c_double]
         L.or_recip_candidate.restype = ctypes.c_int
         L.or_recip_candidate.argtypes = [P, ctypes.c_int, ctypes.c_int, P, ctypes.c_int, P, ctypes.c_int,
                                          ctypes.c_double, ctypes.c_int, ctypes.c_int, ctypes.c_uint32, P, P, P]
@@ -86,12 +86,14 @@ def philox(ctr, key):
     return out
 
 
-def recip_table(f, q, B, n_est, estimator=0, seed=1, cap=1 << 24):
+def recip_table(f, q, B, n_est, estimator=0, seed=1, cap=1 << 24, rhat=1.0):
+    """estimator 0: I~, 1: the sign estimator I, 2: Booth's roulette with parameter rhat."""
     f = np.ascontiguousarray(f, np.float64)
     q = np.ascontiguousarray(q, np.float64)
     est = np.zeros(n_est)
     ns = np.zeros(n_est)
-    tr = lib().or_recip_table(_p(f), _p(q), len(f), float(B), estimator, n_est, seed, cap, _p(est), _p(ns))
+    tr = lib().or_recip_table(_p(f), _p(q), len(f), float(B), estimator, n_est, seed, cap, _p(est), _p(ns),
+                              float(rhat))
     return est, ns, tr
 
 

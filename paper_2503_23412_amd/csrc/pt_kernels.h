@@ -860,13 +860,15 @@ struct ChainState {
     uint32_t ci, chain;        // candidate index; chain id = ci * 8 + repeat
     double ans;                // 1 + sum of s g so far (the estimate is ans weight / B)
     float weight, mx;          // roulette weight; largest f/q drawn (bucket statistics)
-    uint32_t pos, neg, ns, next_flip, coin, pad;
+    uint32_t pos, neg, ns, next_flip, coin;
+    float bprod, bw;           // Booth's roulette: product of g so far, product of continuation probabilities
 };
 struct ChainRun {
     double ans;
     float weight;
     uint32_t pos, neg, ns, next_flip, coin;
     bool alive;
+    float bprod, bw;
 };
 #define CHAIN_COIN 0x80000000u   // Philox counters of the roulette coins
 #define CHAIN_LONG 0x00100000u   // Philox counters of the samples drawn in rounds
@@ -881,11 +883,35 @@ __device__ __forceinline__ float chain_coin(uint32_t seed, uint32_t chain, uint3
 }
 
 // consume lanes 0 .. nv-1 of (fq, u) in lane order; wave-uniform state
+// Booth's roulette on sample values g (lane order, from lane l): no splitting; after a prefix the
+// chain goes on with probability min(1, |prod g| / booth_r) and later terms are divided by the
+// product of those probabilities; the chain roulette's flips apply as in the RRS chains
+__device__ __forceinline__ void booth_step(float gl, float ul, float booth_r, ChainRun &st, uint32_t seed,
+                                           uint32_t chain, uint32_t iter)
+{
+    if (st.ns == st.next_flip) {
+        if (chain_coin(seed, chain, iter, st.coin++) < 0.5f) st.weight *= 2.0f;
+        else { st.alive = false; return; }
+        st.next_flip *= 2u;
+    }
+    st.ns++;
+    st.bprod *= gl;
+    st.ans += (double)(st.bprod / st.bw);
+    const float r = fminf(1.0f, fabsf(st.bprod) / booth_r);
+    if (!(ul < r)) { st.pos = 0; return; }
+    st.bw *= r;
+}
+
 __device__ __forceinline__ void chain_consume(float fq, float u, int nv, float invB, ChainRun &st, uint32_t seed,
-                                              uint32_t chain, uint32_t iter)
+                                              uint32_t chain, uint32_t iter, float booth_r = 0.0f)
 {
     const int lane = __lane_id();
     const float g = 1.0f - fq * invB;
+    if (booth_r > 0.0f) {
+        for (int l = 0; l < nv && st.alive && st.pos > 0; ++l)
+            booth_step(__shfl(g, l), __shfl(u, l), booth_r, st, seed, chain, iter);
+        return;
+    }
     const float ag = fabsf(g), fl = floorf(ag);
     const uint32_t kids = (uint32_t)fminf(fl, 1.0e6f) + (u < ag - fl ? 1u : 0u);
     int l = 0;
@@ -924,7 +950,7 @@ __device__ __forceinline__ void chain_consume(float fq, float u, int nv, float i
 // the same for 256 samples held four per lane (sample 4 * lane + i), in sample order: one
 // memory round trip of the rounds' consumer covers four times as many samples
 __device__ __forceinline__ void chain_consume4(const float (&fq)[4], const float (&uu)[4], float invB, ChainRun &st,
-                                               uint32_t seed, uint32_t chain, uint32_t iter)
+                                               uint32_t seed, uint32_t chain, uint32_t iter, float booth_r = 0.0f)
 {
     const int lane = __lane_id();
     float g[4];
@@ -934,6 +960,15 @@ __device__ __forceinline__ void chain_consume4(const float (&fq)[4], const float
         g[i] = 1.0f - fq[i] * invB;
         const float ag = fabsf(g[i]), fl = floorf(ag);
         kids[i] = (uint32_t)fminf(fl, 1.0e6f) + (uu[i] < ag - fl ? 1u : 0u);
+    }
+    if (booth_r > 0.0f) {
+        for (int l = 0; l < 256 && st.alive && st.pos > 0; ++l) {
+            const int li = l & 3;
+            const float gs = li == 0 ? g[0] : li == 1 ? g[1] : li == 2 ? g[2] : g[3];
+            const float us = li == 0 ? uu[0] : li == 1 ? uu[1] : li == 2 ? uu[2] : uu[3];
+            booth_step(__shfl(gs, l >> 2), __shfl(us, l >> 2), booth_r, st, seed, chain, iter);
+        }
+        return;
     }
     int l = 0;
     while (l < 256 && st.alive && st.pos + st.neg > 0) {
@@ -996,7 +1031,7 @@ template <typename SE>
 __global__ void __launch_bounds__(64 * RW, PT_RECIP_WAVES) k_recip(SceneDev S, Cand *cand, const uint32_t *final_,
                                                    const uint32_t *order, int repeats,
                                                    uint32_t seed, uint32_t n1, uint32_t budget, float *runmax,
-                                                   ChainState *longq, unsigned long long *cnt)
+                                                   ChainState *longq, float booth_r, unsigned long long *cnt)
 {
     const uint32_t iter = iter_of(cnt);
     __shared__ SE stk[PT_STACK * 64 * RW];
@@ -1009,14 +1044,14 @@ __global__ void __launch_bounds__(64 * RW, PT_RECIP_WAVES) k_recip(SceneDev S, C
         const uint32_t chain = ci * 8u + (uint32_t)(wave % repeats);
         Cand &c = cand[ci];
         const float invB = 1.0f / c.B;
-        ChainRun st{1.0, 1.0f, 1u, 0u, 0u, n1, 0u, true};
+        ChainRun st{1.0, 1.0f, 1u, 0u, 0u, n1, 0u, true, 1.0f, 1.0f};
         float mx = 0.0f;
         for (int step = 0; st.alive && st.pos + st.neg > 0 && st.ns < budget; ++step) {
             Rng r = rng_make(seed, S_RECIP, chain, iter, (uint32_t)(step * 64 + lane));
             const float fq = fq_sample(C, c, r);
             const float u = rng_f(r);
             mx = fmaxf(mx, fq);
-            chain_consume(fq, u, 64, invB, st, seed, chain, iter);
+            chain_consume(fq, u, 64, invB, st, seed, chain, iter, booth_r);
             drawn += 64;
         }
 #pragma unroll
@@ -1030,7 +1065,8 @@ __global__ void __launch_bounds__(64 * RW, PT_RECIP_WAVES) k_recip(SceneDev S, C
                 if (slot >= CHAIN_LIST_CAP) slot = -1;
             }
             if (slot >= 0) {
-                ChainState q{ci, chain, st.ans, st.weight, mx, st.pos, st.neg, st.ns, st.next_flip, st.coin, 0u};
+                ChainState q{ci, chain, st.ans, st.weight, mx, st.pos, st.neg, st.ns, st.next_flip, st.coin,
+                             st.bprod, st.bw};
                 longq[slot] = q;
             } else {
                 if (running) atomicAdd(cnt + C_RECIP_TRUNC, 1ull);
@@ -1087,7 +1123,7 @@ __global__ void __launch_bounds__(WG, PT_GEN_WAVES) k_chain_gen(SceneDev S, cons
 __global__ void __launch_bounds__(64 * RW) k_chain_consume(Cand *cand, const ChainState *__restrict__ list, int cidx,
                                                            ChainState *next, int cidx_next, int round, int last,
                                                            uint32_t seed, const float2 *__restrict__ buf,
-                                                           float *runmax, unsigned long long *cnt)
+                                                           float *runmax, float booth_r, unsigned long long *cnt)
 {
     const uint32_t iter = iter_of(cnt);
     const int lane = threadIdx.x & 63;
@@ -1097,7 +1133,7 @@ __global__ void __launch_bounds__(64 * RW) k_chain_consume(Cand *cand, const Cha
         const ChainState q = list[wave];
         Cand &c = cand[q.ci];
         const float invB = 1.0f / c.B;
-        ChainRun st{q.ans, q.weight, q.pos, q.neg, q.ns, q.next_flip, q.coin, true};
+        ChainRun st{q.ans, q.weight, q.pos, q.neg, q.ns, q.next_flip, q.coin, true, q.bprod, q.bw};
         const uint32_t G = chain_round_size(n, round);
         const float2 *b = buf + (size_t)wave * G;
         float mx = q.mx;
@@ -1105,7 +1141,7 @@ __global__ void __launch_bounds__(64 * RW) k_chain_consume(Cand *cand, const Cha
             const float4 v0 = *(const float4 *)(b + base + 4 * lane), v1 = *(const float4 *)(b + base + 4 * lane + 2);
             const float fq[4] = {v0.x, v0.z, v1.x, v1.z}, uu[4] = {v0.y, v0.w, v1.y, v1.w};
             mx = fmaxf(mx, fmaxf(fmaxf(fq[0], fq[1]), fmaxf(fq[2], fq[3])));
-            chain_consume4(fq, uu, invB, st, seed, q.chain, iter);
+            chain_consume4(fq, uu, invB, st, seed, q.chain, iter, booth_r);
         }
 #pragma unroll
         for (int off = 32; off > 0; off >>= 1) mx = fmaxf(mx, __shfl_xor(mx, off));
@@ -1118,7 +1154,8 @@ __global__ void __launch_bounds__(64 * RW) k_chain_consume(Cand *cand, const Cha
                 if (slot >= CHAIN_LIST_CAP) slot = -1;
             }
             if (slot >= 0) {
-                ChainState o{q.ci, q.chain, st.ans, st.weight, mx, st.pos, st.neg, st.ns, st.next_flip, st.coin, 0u};
+                ChainState o{q.ci, q.chain, st.ans, st.weight, mx, st.pos, st.neg, st.ns, st.next_flip, st.coin,
+                             st.bprod, st.bw};
                 next[slot] = o;
             } else {
                 if (running) atomicAdd(cnt + C_RECIP_TRUNC, 1ull);
@@ -1953,13 +1990,38 @@ __global__ void __launch_bounds__(WG) k_trace_closest(SceneDev S, const float *r
 
 // Table mode of the reciprocal estimator: target 1 / sum f, supporting pmf q (inverse-CDF by a
 // linear scan), estimator I~ (sign_est = 0) or the sign estimator I (sign_est = 1).
-__global__ void k_recip_table(const float *f, const float *q, int n, float B, int n_est, int sign_est, uint32_t seed,
-                              uint32_t cap, float *out, uint32_t *ns_out)
+__global__ void k_recip_table(const float *f, const float *q, int n, float B, int n_est, int est, float booth_r,
+                              uint32_t seed, uint32_t cap, float *out, uint32_t *ns_out)
 {
     const int e = blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= n_est) return;
     Rng r = rng_make(seed, S_TABLE, (uint32_t)e, 0u, 0u);
     const float invB = 1.0f / B;
+    const int sign_est = est == 1;
+    if (est == 2) {
+        // Booth's roulette: one chain, go on with probability min(1, |prod g| / booth_r), the
+        // terms beyond divided by the product of those probabilities; one uniform number per
+        // sample after it, drawn where I~ draws its split
+        float ans = 1.0f, prod = 1.0f, w = 1.0f;
+        uint32_t ns = 0, trunc = 0;
+        for (;;) {
+            if (ns >= cap) { trunc = 1; break; }
+            const float x = rng_f(r);
+            float acc = 0.0f;
+            int k = 0;
+            for (; k < n - 1; ++k) { acc += q[k]; if (x < acc) break; }
+            const float g = 1.0f - f[k] / (q[k] * B);
+            ns++;
+            prod *= g;
+            ans += prod / w;
+            const float rr = fminf(1.0f, fabsf(prod) / booth_r);
+            if (!(rng_f(r) < rr)) break;
+            w *= rr;
+        }
+        out[e] = ans * invB;
+        ns_out[e] = ns | (trunc << 31);
+        return;
+    }
     float ans = invB;
     uint32_t pos = 1, neg = 0, ns = 0, trunc = 0;
     while (pos + neg > 0) {

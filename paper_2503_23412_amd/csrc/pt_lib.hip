@@ -710,6 +710,7 @@ pt_status check_params(pt_scene *s, const pt_iter_params *p, float *acc)
         return set_err(PT_EINVAL, "light-vertex connections and light tracing support max_depth <= %d", PT_LSTORE);
     if ((p->flags & PT_FLAG_MLP) && !(p->mlp_mix >= 0.0f && p->mlp_mix < 1.0f && p->mlp_lr > 0.0f))
         return set_err(PT_EINVAL, "PT_FLAG_MLP needs 0 <= mlp_mix < 1 and mlp_lr > 0");
+    if ((p->flags & PT_FLAG_BOOTH) && !(p->booth_r > 0.0f)) return set_err(PT_EINVAL, "PT_FLAG_BOOTH needs booth_r > 0");
     return PT_OK;
 }
 
@@ -860,9 +861,10 @@ pt_status enqueue_iteration(pt_scene *s, const pt_iter_params *p, float *acc, fl
                                                               S.em_area, p->recip_repeats, p->cost_cap, p->seed, s->cnt);
             k_order<<<blocks(maxc, 256), 256, 0, stream>>>(s->cost_bin, s->order, s->cnt);
             const uint32_t n1 = (uint32_t)std::max(64.0f, p->cost_cap / (float)p->recip_repeats);
+            const float booth_r = (p->flags & PT_FLAG_BOOTH) ? p->booth_r : 0.0f;
             if (timing) HIPCHK(hipEventRecord(s->ev[e0 + 1], stream));
             PT_STK(s, k_recip, s->persist_wg, 64 * RW, stream, S, s->cand, s->final_, s->order, p->recip_repeats, p->seed, n1,
-                          s->tune_budget, s->runmax, s->chq[0], s->cnt);
+                          s->tune_budget, s->runmax, s->chq[0], booth_r, s->cnt);
             if (timing) HIPCHK(hipEventRecord(s->ev[e0 + 2], stream));
             for (int r = 0; r < CHAIN_ROUNDS; ++r) {
                 const int in = r & 1, out = in ^ 1;
@@ -871,7 +873,7 @@ pt_status enqueue_iteration(pt_scene *s, const pt_iter_params *p, float *acc, fl
                               s->chbuf, s->cnt);
                 k_chain_consume<<<2048, 64 * RW, 0, stream>>>(s->cand, s->chq[in], C_LONGQ0 + in, s->chq[out],
                                                               C_LONGQ0 + out, r, r == CHAIN_ROUNDS - 1 ? 1 : 0,
-                                                              p->seed, s->chbuf, s->runmax, s->cnt);
+                                                              p->seed, s->chbuf, s->runmax, booth_r, s->cnt);
             }
             if (timing) HIPCHK(hipEventRecord(s->ev[e0 + 3], stream));
             if (labels) {
@@ -1031,10 +1033,12 @@ extern "C" pt_status pt_reciprocal_estimate(pt_scene *s, const pt_recip_query *q
     const uint32_t cap = q->cap ? q->cap : 65536u;
     if (q->mode == PT_RECIP_TABLE) {
         if (q->n <= 0 || !q->f_dev || !q->q_dev) return set_err(PT_EINVAL, "bad table query");
-        if (q->estimator != PT_EST_ITILDE && q->estimator != PT_EST_SIGN) return set_err(PT_EINVAL, "unknown estimator");
+        if (q->estimator != PT_EST_ITILDE && q->estimator != PT_EST_SIGN && q->estimator != PT_EST_BOOTH)
+            return set_err(PT_EINVAL, "unknown estimator");
+        if (q->estimator == PT_EST_BOOTH && !(q->booth_r > 0.0f)) return set_err(PT_EINVAL, "booth_r must be positive");
         if (!s) TRY(check_device());
         k_recip_table<<<blocks(q->n_est, 256), 256, 0, stream>>>(q->f_dev, q->q_dev, q->n, q->B, q->n_est,
-                                                                 q->estimator, q->seed, cap, out, ns);
+                                                                 q->estimator, q->booth_r, q->seed, cap, out, ns);
     } else if (q->mode == PT_RECIP_CANDIDATE) {
         const pt_cand_desc *d = q->cand;
         if (!s || !d) return set_err(PT_EINVAL, "candidate mode needs a scene and a candidate");

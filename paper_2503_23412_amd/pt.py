@@ -24,9 +24,11 @@ PT_FLAG_MIS = 1 << 8
 PT_FLAG_MLP = 1 << 9
 PT_FLAG_SPC = 1 << 10
 PT_FLAG_LT = 1 << 11
+PT_FLAG_BOOTH = 1 << 12
 
 PT_EST_ITILDE = 0
 PT_EST_SIGN = 1
+PT_EST_BOOTH = 2
 
 EXPORTED = ["pt_scene_upload", "pt_scene_release", "pt_build_subspaces", "pt_render_iteration", "pt_render_batch",
             "pt_render_scenes", "pt_autotune",
@@ -56,7 +58,7 @@ class IterParams(ctypes.Structure):
         ("u_max", ctypes.c_int32), ("pilot", ctypes.c_int32), ("cost_cap", ctypes.c_float),
         ("train_iters", ctypes.c_int32), ("tile", ctypes.c_int32), ("tile_threshold", ctypes.c_float),
         ("tile_low_prob", ctypes.c_float), ("defensive", ctypes.c_float), ("flags", ctypes.c_uint32),
-        ("mlp_lr", ctypes.c_float), ("mlp_mix", ctypes.c_float),
+        ("mlp_lr", ctypes.c_float), ("mlp_mix", ctypes.c_float), ("booth_r", ctypes.c_float),
     ]
 
 
@@ -91,7 +93,8 @@ class RecipQuery(ctypes.Structure):
     _fields_ = [("mode", ctypes.c_int32), ("n", ctypes.c_int32), ("f_dev", ctypes.c_void_p),
                 ("q_dev", ctypes.c_void_p), ("B", ctypes.c_float), ("n_est", ctypes.c_int32),
                 ("estimator", ctypes.c_int32), ("seed", ctypes.c_uint32), ("cap", ctypes.c_uint32),
-                ("cand", ctypes.POINTER(CandDesc)), ("per", ctypes.c_int32), ("out_p_dev", ctypes.c_void_p)]
+                ("cand", ctypes.POINTER(CandDesc)), ("per", ctypes.c_int32), ("out_p_dev", ctypes.c_void_p),
+                ("booth_r", ctypes.c_float)]
 
 
 _lib = None
@@ -153,7 +156,7 @@ def _ptr(t):
 def default_params(**kw):
     p = dict(iteration=0, seed=0, max_depth=8, n_light=4096, cand_cap=400, recip_repeats=5, u_max=4, pilot=16,
              cost_cap=4096.0, train_iters=40, tile=10, tile_threshold=0.05, tile_low_prob=0.2, defensive=0.1,
-             flags=PT_FLAG_NEE | PT_FLAG_PROXY, mlp_lr=1e-3, mlp_mix=0.9)
+             flags=PT_FLAG_NEE | PT_FLAG_PROXY, mlp_lr=1e-3, mlp_mix=0.9, booth_r=1.0)
     p.update(kw)
     return p
 
@@ -252,10 +255,11 @@ class Scene:
                                       _stream(stream)))
 
 
-def reciprocal_table(f, q, B, n_est, out, nsamples, estimator=PT_EST_ITILDE, seed=1, cap=0, stream=None):
+def reciprocal_table(f, q, B, n_est, out, nsamples, estimator=PT_EST_ITILDE, seed=1, cap=0, booth_r=1.0,
+                     stream=None):
     """f, q: float32 device tensors; out float32 [n_est], nsamples int32 [n_est] (device)."""
     qq = RecipQuery(0, int(f.shape[0]), f.data_ptr(), q.data_ptr(), float(B), int(n_est), int(estimator), int(seed),
-                    int(cap), None, 0, None)
+                    int(cap), None, 0, None, float(booth_r))
     _check(lib().pt_reciprocal_estimate(None, ctypes.byref(qq), _ptr(out), _ptr(nsamples), _stream(stream)))
 
 

@@ -32,7 +32,7 @@ def test_header_symbols_exported(ptlib):
 def test_struct_sizes_match_header(ptlib):
     # the ctypes mirrors must have the C layouts (checked against hand-computed sizes)
     assert ctypes.sizeof(ptlib.SceneDesc) == 4 + 4 + 8 * 3 + 4 + 4 + 8 + 4 + 4 + 8 + 8 + 4 * 4
-    assert ctypes.sizeof(ptlib.IterParams) == 17 * 4
+    assert ctypes.sizeof(ptlib.IterParams) == 18 * 4
     assert ctypes.sizeof(ptlib.IterStats) == (29 + 25) * 8
     assert ctypes.sizeof(ptlib.SubspaceParams) == 6 * 4
 

@@ -124,6 +124,44 @@ def test_recip_table_matches_closed_forms_and_oracle(gpu, oracle):
                 assert abs(es.var() - var_sign) < 5 * math.sqrt((m4s - es.var() ** 2) / n_est) + 1e-6
 
 
+def test_booth_table_matches_its_definition(gpu):
+    """Booth's roulette in the table kernel: on a binary f/q with booth_r <= 1 it takes the
+    decisions of I~ from the same draws (same sample counts, same estimates up to FP32 rounding);
+    on a constant f/q every estimate is the closed-form value of its own chain length and the
+    mean length follows the law (the oracle's pins, on the GPU)."""
+    torch, pt = gpu
+    n_est = 1 << 16
+    out = torch.empty(n_est, device="cuda")
+    ns = torch.empty(n_est, dtype=torch.int32, device="cuda")
+    f = torch.tensor([0.0, 0.25, 0.0, 0.25], device="cuda")
+    q = torch.full((4,), 0.25, device="cuda")
+    pt.reciprocal_table(f, q, 1.0, n_est, out, ns, estimator=pt.PT_EST_ITILDE, seed=5)
+    a, na = out.double().cpu().numpy(), ns.cpu().numpy().copy()
+    pt.reciprocal_table(f, q, 1.0, n_est, out, ns, estimator=pt.PT_EST_BOOTH, booth_r=1.0, seed=5)
+    b, nb = out.double().cpu().numpy(), ns.cpu().numpy()
+    assert np.array_equal(na, nb)
+    assert np.allclose(a, b, rtol=1e-5)
+    gamma, rhat = 0.5, 0.25
+    f = torch.tensor([0.25, 0.25], device="cuda")
+    q = torch.tensor([0.5, 0.5], device="cuda")
+    B = 0.5 / (1.0 - gamma)
+    pt.reciprocal_table(f, q, B, n_est, out, ns, estimator=pt.PT_EST_BOOTH, booth_r=rhat, seed=9, cap=1000)
+    est, L = out.double().cpu().numpy(), ns.cpu().numpy().astype(np.int64)
+    assert (L >> 31).sum() == 0
+    r = [min(1.0, gamma ** j / rhat) for j in range(1, 40)]
+    est_of, p_of, reach, w, acc = [], [], 1.0, 1.0, 1.0
+    for k in range(1, 39):
+        acc += gamma ** k / w
+        est_of.append(acc / B)
+        p_of.append(reach * (1.0 - r[k - 1]))
+        reach *= r[k - 1]
+        w *= r[k - 1]
+    est_of, p_of = np.array(est_of), np.array(p_of)
+    assert np.allclose(est, est_of[L - 1], rtol=1e-4)
+    EL = (p_of * np.arange(1, len(p_of) + 1)).sum()
+    assert abs(L.mean() - EL) < 5 * L.std() / math.sqrt(n_est)
+
+
 # ------------------------------------------------------------------------------ traversal
 @pytest.mark.parametrize("which", ["cornell", "projector", "glossy"])
 def test_bvh_closest_hit_matches_brute_force(gpu, oracle, which):
@@ -260,6 +298,32 @@ def test_glass_furnace_through_proxy(gpu, mode):
     assert abs(zm) < 4.5
     assert frac >= 0.99 and np.abs(z).max() < 7
     assert st["n_proxy_valid"] > 0 and st["n_recip_truncated"] == 0 and st["n_nan"] == 0
+
+
+def test_booth_roulette_glass_furnace(gpu):
+    """The reciprocal chains on Booth's roulette (booth_r = 0.05) instead of the RRS function:
+    the glass furnace through the proxy under MIS, depth 120, against the oracle's depth-120 value
+    (O1: 1.99969 +- 0.00026). Booth's estimates have infinite variance once the roulette binds,
+    so the image mean with the per-iteration standard error is the check, and per pixel only
+    gross errors are excluded."""
+    from synth import scenes
+    torch, pt = gpu
+    sc = scenes.furnace(albedo=0.5, le=1.0, glass_sphere=True, width=96, height=96, sphere_subdiv=2,
+                        enclosure="sphere")
+    flags = pt.PT_FLAG_NEE | pt.PT_FLAG_PROXY | pt.PT_FLAG_MIS | pt.PT_FLAG_GAMMA | pt.PT_FLAG_BOOTH
+    say("booth glass furnace")
+    its = []
+    m, v, st = _render(gpu, sc, 1024, it_means=its, max_depth=120, n_light=1024, cand_cap=128, flags=flags,
+                       booth_r=0.05)
+    expect, expect_se = 1.99969, 0.00026
+    se = float(np.std(its, ddof=1) / np.sqrt(len(its)))
+    zm = (m.mean() - expect) / math.hypot(se, expect_se)
+    z = (m[..., 0] - 2.0) / np.sqrt(v[..., 0] + 1e-30)
+    say(f"booth glass furnace: mean {m.mean():.5f} +- {se:.5f} z {zm:.2f}; frac |z|<4 {(np.abs(z) < 4).mean():.5f} "
+        f"recip samples {st['n_recip_samples']:.0f} proxy valid {st['n_proxy_valid']:.0f}")
+    assert abs(zm) < 4.5
+    assert (np.abs(z) < 4).mean() >= 0.99 and np.abs(z).max() < 7
+    assert st["n_nan"] == 0 and st["n_proxy_valid"] > 0 and st["n_recip_samples"] > 0
 
 
 # ------------------------------------------------------------------------------ proxy class

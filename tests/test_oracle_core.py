@@ -5,6 +5,10 @@
   mean 1/int f (Appendix C), the exact variance and expected cost when B >= max f/q (the
   geometric regime of Appendix E), the sign estimator's variance q/(B-Bq)^2 (Appendix E),
   V[I~] <= V[I] (Appendix F), divergence for beta/B >= 2 (Appendix B).
+- Booth's roulette (the RR ablation's baseline): identical to I~ on a binary f/q when its
+  parameter is at most 1 (both then go on with probability 1 exactly when g = 1, from the same
+  draws); on a constant f/q its estimate is a closed-form function of the chain length, whose
+  law is known, and the weights are unbiased exactly.
 - The binary BVH against brute force.
 - BSDFs: sampling densities (chi-square), reciprocity, energy, Snell and Fresnel.
 """
@@ -107,6 +111,63 @@ def test_recip_diverges_past_convergence_boundary(oracle):
     _, _, tr_bad = oracle.recip_table(f, q, 0.4 * f.sum(), 200, 0, seed=5, cap=20000)
     assert tr_ok == 0
     assert tr_bad > 50
+
+
+def test_booth_binary_identity_with_itilde(oracle):
+    """f/q in {0, B}: g in {1, 0}. I~ splits into one child exactly when g = 1, and Booth's
+    roulette (r <= 1) goes on with probability min(1, 1 / r) = 1 exactly then: the same chains."""
+    f, q = np.array([0.0, 0.25, 0.0, 0.25]), np.full(4, 0.25)
+    a, na, _ = oracle.recip_table(f, q, 1.0, 4000, 0, seed=7)
+    for rhat in (1.0, 0.5):
+        b, nb, _ = oracle.recip_table(f, q, 1.0, 4000, 2, seed=7, rhat=rhat)
+        assert np.array_equal(na, nb)
+        assert np.allclose(a, b, rtol=1e-12, atol=0)
+
+
+@pytest.mark.parametrize("rhat", [0.25, 0.05])
+def test_booth_constant_ratio_exact(oracle, rhat):
+    """f/q constant = B (1 - gamma): every g is gamma, the prefix product after j samples is
+    gamma^j, and the chain goes on after j samples with probability r_j = min(1, gamma^j / rhat).
+    The chain length L then has a closed-form law, and the estimate is a function of L alone:
+    est(L) = (1 + sum_{k<=L} gamma^k / prod_{j<k} r_j) / B. Checked: every estimate against
+    est(its own sample count), and E[L] against the law. The term of length k is divided by
+    prod_{j<k} r_j, the probability of reaching it, so its expectation is gamma^k and the sum is
+    1/int f; the sample mean itself is useless here, since the terms grow like gamma^(-k^2/2)
+    against their probability and the variance is infinite. A small sample cap makes a roulette
+    that never stops (one on |g| instead of the product) fail fast."""
+    gamma = 0.5
+    f, q = np.array([0.25, 0.25]), np.array([0.5, 0.5])
+    B = float((f / q).max()) / (1.0 - gamma)
+    r = [min(1.0, gamma ** j / rhat) for j in range(1, 80)]
+    est_of, p_of = [], []
+    reach, w, acc = 1.0, 1.0, 1.0
+    for L in range(1, 79):
+        acc += gamma ** L / w                 # the term of length L
+        est_of.append(acc / B)
+        p_of.append(reach * (1.0 - r[L - 1]))   # reached L, stopped after it
+        reach *= r[L - 1]
+        w *= r[L - 1]
+        if reach < 1e-30:                     # longer chains have no weight in the law
+            p_of[-1] += reach
+            break
+    est_of, p_of = np.array(est_of), np.array(p_of)
+    assert abs(p_of.sum() - 1.0) < 1e-12
+    est, ns, tr = oracle.recip_table(f, q, B, 200000, 2, seed=13, cap=1000, rhat=rhat)
+    assert tr == 0
+    L = ns.astype(np.int64)
+    assert np.allclose(est, est_of[L - 1], rtol=1e-12, atol=0)
+    EL = (p_of * np.arange(1, len(p_of) + 1)).sum()
+    assert abs(ns.mean() - EL) < 5 * ns.std() / math.sqrt(len(ns)), (ns.mean(), EL)
+
+
+def test_booth_large_rhat_has_heavy_tail(oracle):
+    """With rhat = 100 a chain goes on with probability at most 1 / 100 and carries the inverse
+    weight: a few estimates exceed the mean by orders of magnitude (the ablation's point)."""
+    f, q = np.array([0.2, 0.5, 0.3]), np.array([0.2, 0.25, 0.55])
+    B = float((f / q).max())
+    est, ns, _ = oracle.recip_table(f, q, B, 200000, 2, seed=12, rhat=100.0)
+    assert ns.mean() < 1.02
+    assert est.max() > 50.0 / f.sum()
 
 
 # ---------------------------------------------------------------------------- BVH
