@@ -1026,8 +1026,10 @@ __device__ __forceinline__ void chain_finish(Cand &c, const ChainRun &st, bool t
     atomic_maxf(runmax + (c.cls_u >> 8) * 5 + (c.cls_u & 0xFF), mx);
 }
 
-// stage A: one wavefront per chain, at most `budget` samples, then hand over to the rounds
-template <typename SE>
+// stage A: one wavefront per chain, at most `budget` samples, then hand over to the rounds;
+// BOOTH selects Booth's roulette (booth_r) at compile time, so that the default instance carries
+// none of its state
+template <typename SE, bool BOOTH = false>
 __global__ void __launch_bounds__(64 * RW, PT_RECIP_WAVES) k_recip(SceneDev S, Cand *cand, const uint32_t *final_,
                                                    const uint32_t *order, int repeats,
                                                    uint32_t seed, uint32_t n1, uint32_t budget, float *runmax,
@@ -1051,7 +1053,7 @@ __global__ void __launch_bounds__(64 * RW, PT_RECIP_WAVES) k_recip(SceneDev S, C
             const float fq = fq_sample(C, c, r);
             const float u = rng_f(r);
             mx = fmaxf(mx, fq);
-            chain_consume(fq, u, 64, invB, st, seed, chain, iter, booth_r);
+            chain_consume(fq, u, 64, invB, st, seed, chain, iter, BOOTH ? booth_r : 0.0f);
             drawn += 64;
         }
 #pragma unroll

@@ -863,8 +863,19 @@ pt_status enqueue_iteration(pt_scene *s, const pt_iter_params *p, float *acc, fl
             const uint32_t n1 = (uint32_t)std::max(64.0f, p->cost_cap / (float)p->recip_repeats);
             const float booth_r = (p->flags & PT_FLAG_BOOTH) ? p->booth_r : 0.0f;
             if (timing) HIPCHK(hipEventRecord(s->ev[e0 + 1], stream));
-            PT_STK(s, k_recip, s->persist_wg, 64 * RW, stream, S, s->cand, s->final_, s->order, p->recip_repeats, p->seed, n1,
-                          s->tune_budget, s->runmax, s->chq[0], booth_r, s->cnt);
+            if (booth_r > 0.0f) {
+                if (s->stk16)
+                    k_recip<uint16_t, true><<<s->persist_wg, 64 * RW, 0, stream>>>(
+                        S, s->cand, s->final_, s->order, p->recip_repeats, p->seed, n1, s->tune_budget, s->runmax,
+                        s->chq[0], booth_r, s->cnt);
+                else
+                    k_recip<int, true><<<s->persist_wg, 64 * RW, 0, stream>>>(
+                        S, s->cand, s->final_, s->order, p->recip_repeats, p->seed, n1, s->tune_budget, s->runmax,
+                        s->chq[0], booth_r, s->cnt);
+            } else {
+                PT_STK(s, k_recip, s->persist_wg, 64 * RW, stream, S, s->cand, s->final_, s->order, p->recip_repeats,
+                       p->seed, n1, s->tune_budget, s->runmax, s->chq[0], booth_r, s->cnt);
+            }
             if (timing) HIPCHK(hipEventRecord(s->ev[e0 + 2], stream));
             for (int r = 0; r < CHAIN_ROUNDS; ++r) {
                 const int in = r & 1, out = in ^ 1;
