@@ -460,3 +460,56 @@ def test_zz_config1_128_parity_with_oracle_reference(gpu):
     assert frac >= 0.999
     assert rel_l1 < 1.1 * floor + 0.005
     assert st["n_nan"] == 0 and st["n_recip_truncated"] == 0
+
+
+def test_zz_config1_full_size_block_means_match_oracle_reference(gpu):
+    """Config 1 at its full size and in the launch configuration bench.py times (512 x 512, depth
+    12, M = 500,000 light sub-paths, 20,000 expected candidates, 1,000 / 100 subspaces, the
+    autotuned chain schedule, the second stream): every 4 x 4 block of 512^2 pixels covers one
+    pixel of the same camera at 128^2 (the pixel's sample is uniform on its square), so the
+    block means estimate the stored 128^2 O3 reference. Their standard errors come from the
+    per-iteration block images, which holds the correlation between the pixels of one iteration
+    (they share light sub-paths and candidates)."""
+    from synth import scenes
+    torch, pt = gpu
+    cfg = scenes.config(1)
+    sc = cfg["scene"]
+    W, H = sc["width"], sc["height"]
+    assert (W, H) == (512, 512)
+    ref = np.load(os.path.join(GOLD, "cfg1_128_o3_ref.npz"))
+    flags = (pt.PT_FLAG_NEE | pt.PT_FLAG_PROXY | pt.PT_FLAG_MIS | pt.PT_FLAG_GAMMA | pt.PT_FLAG_TILES |
+             pt.PT_FLAG_SPC | pt.PT_FLAG_LT)
+    params = dict(max_depth=cfg["max_depth"], n_light=cfg["n_light"], cand_cap=cfg["cand_cap"], seed=cfg["seed"],
+                  flags=flags)
+    N = 256
+    say(f"config 1 full size, {N} iterations, 4x4 block means against the 128^2 reference")
+    S = pt.Scene(sc, max_light_paths=cfg["n_light"])
+    S.build_subspaces(n_eye=cfg["n_subspaces"], n_spec=cfg["n_spec"])
+    img = torch.zeros(W * H * 3, device="cuda")
+    k0 = S.autotune(img, None, iteration=0, **params)["iterations_rendered"]
+    s1 = torch.zeros(128 * 128 * 3, dtype=torch.float64, device="cuda")
+    s2 = torch.zeros_like(s1)
+    nan = trunc = 0.0
+    for k in range(N):
+        img.zero_()
+        st = S.render_iteration(img, None, stats=(k % 64 == 0 or k == N - 1), iteration=k0 + k, **params)
+        b = img.view(128, 4, 128, 4, 3).double().mean(dim=(1, 3)).reshape(-1)
+        s1 += b
+        s2 += b * b
+        if st:
+            nan += st["n_nan"]
+            trunc += st["n_recip_truncated"]
+    torch.cuda.synchronize()
+    S.release()
+    m = (s1 / N).cpu().numpy().reshape(128, 128, 3)
+    v = np.maximum((s2 / N).cpu().numpy().reshape(128, 128, 3) - m * m, 0) / (N - 1)
+    mo, vo = ref["mean"], ref["var_mean"]
+    z = (m - mo) / np.sqrt(v + vo + 1e-30)
+    frac = (np.abs(z) < 4).mean()
+    rel_l1 = np.abs(m - mo).sum() / mo.sum()
+    floor = (np.sqrt(2 / np.pi) * np.sqrt(v + vo)).sum() / mo.sum()
+    say(f"config 1 (512 -> 128 blocks): frac |z|<4 {frac:.5f} max|z| {np.abs(z).max():.2f} mean z {z.mean():.3f} "
+        f"relL1 {rel_l1:.5f} noise floor {floor:.5f}")
+    assert frac >= 0.999
+    assert rel_l1 < 1.1 * floor + 0.005
+    assert nan == 0 and trunc == 0
