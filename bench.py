@@ -102,7 +102,7 @@ def main():
                          "known size for scaling hardware byte counters")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (this build has no multi-GPU path)",
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the library has no multi-GPU path)",
               file=sys.stderr)
         sys.exit(2)
     import numpy as np

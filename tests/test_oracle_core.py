@@ -80,8 +80,10 @@ def test_recip_geometric_regime_closed_forms(oracle):
             assert cf["var"] <= cf["var_sign"] + 1e-15               # Appendix F
 
 
-def test_recip_survey_worked_numbers(oracle):
-    """f = (0.3, 1.2, 0.5), q = (1/2, 1/4, 1/4), B = 4.8: V[I~] ~ 0.1001, V[I] = 0.1458."""
+def test_recip_closed_forms_worked_example(oracle):
+    """f = (0.3, 1.2, 0.5), q = (1/2, 1/4, 1/4), B = 4.8, by hand: g = (7/8, 0, 7/12), E_g = 7/12,
+    E_g2 = 0.46788, m1 = 1.4, m2 = 4.26708, so V[I~] = (m2 - m1^2) / B^2 = 0.10013 and
+    V[I] = E_g / (B (1 - E_g))^2 = 7/48 = 0.14583 (Appendix E)."""
     f, q = np.array([0.3, 1.2, 0.5]), np.array([0.5, 0.25, 0.25])
     cf = _closed_forms(f, q, 4.8)
     assert abs(cf["var"] - 0.10013) < 1e-4

@@ -7,7 +7,7 @@ P4  class A, u = 2 through a perfect mirror: P equals the u = 1 density of the e
     mirrored about the mirror plane (image method); f/q is binary (Section 4.2's binary
     case), and the reciprocal estimate's mean is 1/P.
 P5  diffuse furnace: a closed box of emitting Lambertian walls reads Le (1 - a^K) / (1 - a)
-    with at most K segments (the benchmark spec's white-furnace closed form), for O1 and O2.
+    with at most K segments (the white-furnace closed form), for O1 and O2.
 P6  glass furnace: an emitting spherical enclosure (no corners, so the class B f/q stays
     bounded) around a lossless glass sphere; every pixel still reads the closed form (large
     K), for O1 and O2 (O2 routes the L S^u and L D S^u paths through the proxy).
