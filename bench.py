@@ -2,11 +2,12 @@
 
 A step is one rendering iteration (1 sample per pixel through every strategy: light pass,
 connection pool, candidates, reciprocal estimates, eye pass with emission hits, next-event
-estimation and probabilistic connections, light tracing, proxy connections, accumulation) of
-the projector caustic workload (512 x 512, depth 12, 500,000 light sub-paths per iteration,
-20,000 expected candidates). Prints one JSON line.
+estimation and probabilistic connections, light tracing, proxy connections, accumulation).
+Default workload: the glossy/specular procedural scene (config 2: 1024 x 1024, 198,740 tris,
+depth 12, 262,144 light sub-paths per iteration, 10,486 expected candidates, 1,000 / 100
+subspaces). --config 1 times the projector caustic scene (512 x 512). Prints one JSON line.
 
-  python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--config 2] [--no-cpu]
 """
 import argparse
 import json
@@ -19,6 +20,8 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 FP32_PEAK_TFLOPS = 157.3   # MI355X vector FP32 (256 CUs, 2.4 GHz, packed FMA)
+NODE_BYTES = 128           # one 4-wide BVH node (one 128-byte line)
+TRI_BYTES = 48             # one intersection triangle record
 # algorithmic FP32 operations per unit of traversal work (an FMA counts two):
 # a 4-wide node visit is four slab tests, each 6 FMAs for the six plane distances, 6 min/max
 # for the entry distance, 6 for the exit distance and 1 compare (25 per child);
@@ -27,7 +30,8 @@ FP32_PEAK_TFLOPS = 157.3   # MI355X vector FP32 (256 CUs, 2.4 GHz, packed FMA)
 # barycentric and distance bounds (52)
 FLOP_NODE = 100
 FLOP_TRI = 52
-PMC_FILE = os.path.join(ROOT, "profiles", "pmc_k_recip_projector_512.txt")
+PMC_FILES = {1: os.path.join(ROOT, "profiles", "pmc_k_recip_projector_512.txt"),
+             2: os.path.join(ROOT, "profiles", "pmc_glossy_1024.txt")}
 
 
 def log(*a):
@@ -47,34 +51,36 @@ def kernel_source_hash():
     return h.hexdigest()
 
 
-def recorded_traffic():
-    """HBM bytes per k_recip launch from the committed hardware-counter summary, or None when
-    the kernel sources no longer hash to the value the counters were taken with."""
+def recorded_traffic(config, kernel):
+    """HBM bytes per launch of `kernel` from the committed hardware-counter summary of this
+    workload, or None when there is none or the kernel sources no longer hash to the value the
+    counters were taken with. Lines: `source_sha256: <hex>` and `traffic_bytes_per_launch <kernel>: <bytes>`."""
     try:
-        txt = open(PMC_FILE).read()
-    except OSError:
+        txt = open(PMC_FILES[config]).read()
+    except (OSError, KeyError):
         return None
-    vals = {}
+    sha, val = None, None
     for line in txt.splitlines():
         line = line.strip()
-        for key in ("traffic_bytes_per_launch:", "source_sha256:"):
-            if line.startswith(key):
-                vals[key] = line[len(key):].strip()
-    if vals.get("source_sha256:") != kernel_source_hash() or "traffic_bytes_per_launch:" not in vals:
+        if line.startswith("source_sha256:"):
+            sha = line.split(":", 1)[1].strip()
+        elif line.startswith(f"traffic_bytes_per_launch {kernel}:"):
+            val = float(line.split(":", 1)[1])
+    if sha != kernel_source_hash():
         return None
-    return float(vals["traffic_bytes_per_launch:"])
+    return val
 
 
-def cpu_baseline(sc, params, budget_s=20.0):
-    """The FP64 oracle (O2, proxy-sampling BDPT) on a bounded sample of the same workload:
-    the projector scene at the same depth and light-path budget, on a pixel window of the
-    full-resolution camera (the oracle renders rows independently), timed on the host."""
-    import numpy as np
+def cpu_baseline(config, sc, params, budget_s=20.0):
+    """The FP64 oracle (O2, proxy-sampling BDPT) on a bounded sample of the same workload: the
+    same scene, camera view and depth rendered at 64 x 64 pixels (each pixel sample traces the
+    same kind of paths as at full resolution) with 1/64 of the light sub-paths and candidates per
+    iteration, timed on the host's cores."""
     from oracle import oracle as O
     from synth import scenes
     threads = os.cpu_count() or 1
-    # a 64 x 64 crop of the 512 x 512 image keeps the camera rays of the full render
-    small = scenes.projector(64, 64)
+    small = scenes.config(config)["scene"]
+    small["width"], small["height"] = 64, 64
     small["cam"] = sc["cam"]
     S = O.Scene(small)
     t0 = time.time()
@@ -86,8 +92,8 @@ def cpu_baseline(sc, params, budget_s=20.0):
         n += 1
     dt = time.time() - t0
     return {"value": 64 * 64 * n / dt, "unit": "full-path samples/s", "cores": threads, "kind": "oracle",
-            "sample": f"O2 on the projector scene, {n} iterations of a 64x64 pixel window with M={M} light "
-                      f"sub-paths (1/64 of the pixels and light paths per iteration)"}
+            "sample": f"O2 on the same scene and view at 64x64 pixels (full image {sc['width']}x{sc['height']}), "
+                      f"{n} iterations with M={M} light sub-paths (1/64 of the light paths per iteration)"}
 
 
 def main():
@@ -96,7 +102,7 @@ def main():
     ap.add_argument("--steps", type=int, default=64)
     ap.add_argument("--warmup", type=int, default=4)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--config", type=int, default=1)
+    ap.add_argument("--config", type=int, default=2)
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="after the run, one device-to-device copy of this many MiB: the reference kernel of "
                          "known size for scaling hardware byte counters")
@@ -153,24 +159,32 @@ def main():
     st = tim[-1]
     rays = st["rays_extend_eye"] + st["rays_extend_light"] + st["rays_shadow"] + st["rays_proxy"] + st["rays_recip"]
     n_launch = params["max_depth"]
-    # algorithmic work of the two traversal kernels: FP32 operations of every node visit and
-    # triangle test (FLOP_NODE, FLOP_TRI); the bytes of every visited 128-byte node and tested
-    # 48-byte triangle record are reported beside them (those reads are served from the caches:
-    # the measured HBM traffic is the `traffic` field)
+    # Roofline of the dominant traversal kernel in the units of the traversal roof (HBM bytes):
+    # `achieved` = the algorithmic bytes of one launch (every visited 128-byte node and every
+    # tested 48-byte triangle record, from the traversal counters of a counting iteration) over
+    # the launch's average duration (HIP events recorded on the launch stream inside the library);
+    # `traffic` = the bytes the hardware counters saw move between L2 and memory for one launch,
+    # when a summary of the current sources exists. The FP32 operations of the same work are
+    # reported beside them (FLOP_NODE, FLOP_TRI) against the vector FP32 peak.
     ext_flops = stc["node_visits"] * FLOP_NODE + stc["tri_tests"] * FLOP_TRI
     a_flops = stc["node_visits_stage_a"] * FLOP_NODE + stc["tri_tests_stage_a"] * FLOP_TRI
-    ext_bytes = stc["node_visits"] * 128 + stc["tri_tests"] * 48
-    a_bytes = stc["node_visits_stage_a"] * 128 + stc["tri_tests_stage_a"] * 48
+    ext_bytes = stc["node_visits"] * NODE_BYTES + stc["tri_tests"] * TRI_BYTES
+    a_bytes = stc["node_visits_stage_a"] * NODE_BYTES + stc["tri_tests_stage_a"] * TRI_BYTES
     cands = [
-        {"kernel": "k_extend (eye closest hit)", "ms_per_step": ms_ext, "launches": n_launch, "flops": ext_flops,
-         "bytes": ext_bytes, "traffic": None},
-        {"kernel": "k_recip (reciprocal chains, stage A)", "ms_per_step": ms_a, "launches": 1, "flops": a_flops,
-         "bytes": a_bytes, "traffic": recorded_traffic() if args.config == 1 else None},
+        {"kernel": "k_extend", "what": "eye closest hit", "ms_per_step": ms_ext, "launches": n_launch,
+         "flops": ext_flops, "bytes": ext_bytes},
+        {"kernel": "k_recip", "what": "reciprocal chains, stage A", "ms_per_step": ms_a, "launches": 1,
+         "flops": a_flops, "bytes": a_bytes},
     ]
     dom = max(cands, key=lambda c: c["ms_per_step"])
     per_launch_s = dom["ms_per_step"] / dom["launches"] * 1e-3
-    achieved = dom["flops"] / dom["launches"] / per_launch_s / 1e12 if per_launch_s > 0 else 0.0
+    bytes_launch = dom["bytes"] / dom["launches"]
+    achieved = bytes_launch / per_launch_s / 1e9 if per_launch_s > 0 else 0.0
+    traffic = recorded_traffic(args.config, dom["kernel"])
+    flops_tf = dom["flops"] / dom["launches"] / per_launch_s / 1e12 if per_launch_s > 0 else 0.0
     value = W * H * args.steps / dt
+    wl = {1: "projector caustic (config 1)", 2: "glossy/specular procedural (config 2)"}.get(args.config,
+                                                                                          f"config {args.config}")
     out = {
         "metric": "full-path samples/s",
         "value": value,
@@ -184,10 +198,10 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": f"projector caustic (config 1): {W}x{H}, {sc['tri'].shape[0]:,} tris, depth "
-                               f"{params['max_depth']}, M={params['n_light']:,} light sub-paths, "
-                               f"{params['cand_cap']:,} expected candidates; plain method (PT, NEE, probabilistic "
-                               f"connections, light tracing, proxy connections with variance-aware MIS, Gamma, tiles)",
+        "config": {"workload": f"{wl}: {W}x{H}, {sc['tri'].shape[0]:,} tris, depth {params['max_depth']}, "
+                               f"M={params['n_light']:,} light sub-paths, {params['cand_cap']:,} expected candidates; "
+                               f"plain method (PT, NEE, probabilistic connections, light tracing, proxy connections "
+                               f"with variance-aware MIS, Gamma, tiles)",
                    "spp_per_step": 1, "max_depth": params["max_depth"], "n_light": params["n_light"]},
         "mrays_per_s": rays * args.steps / dt / 1e6,
         "rays_per_step": rays,
@@ -199,18 +213,19 @@ def main():
         "ms_breakdown": {"eye_extension": ms_ext, "reciprocal_block": ms_rec, "reciprocal_stage_a": ms_a},
         "schedule": {"stage_a_budget": tune["stage_a_budget"], "round_grid": tune["round_grid"],
                      "autotune_iterations": k0, "ms_tuned": tune["ms_best"], "ms_default": tune["ms_previous"]},
-        "roofline": {"kernel": dom["kernel"], "bound": "alu", "achieved": achieved, "peak": FP32_PEAK_TFLOPS,
-                     "unit": "TFLOP/s", "frac": achieved / FP32_PEAK_TFLOPS, "traffic": dom["traffic"],
-                     "flops_per_launch": dom["flops"] / dom["launches"],
+        "roofline": {"kernel": f"{dom['kernel']} ({dom['what']})", "bound": "hbm", "achieved": achieved,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "algorithmic_bytes_per_launch": bytes_launch,
                      "ms_per_launch": dom["ms_per_step"] / dom["launches"],
-                     "node_tri_bytes_per_launch": dom["bytes"] / dom["launches"],
-                     "node_tri_GBs": dom["bytes"] / dom["launches"] / per_launch_s / 1e9 if per_launch_s > 0 else 0.0,
-                     "hbm_frac_of_traffic": (dom["traffic"] / per_launch_s / 1e9 / HBM_PEAK_GBS
-                                             if dom["traffic"] and per_launch_s > 0 else None)},
+                     "traffic_GBs": traffic / per_launch_s / 1e9 if traffic and per_launch_s > 0 else None,
+                     "fp32_TFLOPs": flops_tf, "fp32_frac": flops_tf / FP32_PEAK_TFLOPS,
+                     "kernels": {c["kernel"]: {"ms_per_launch": c["ms_per_step"] / c["launches"],
+                                               "GBs": (c["bytes"] / c["ms_per_step"] / 1e6 if c["ms_per_step"] > 0
+                                                       else 0.0)} for c in cands}},
     }
     if not args.no_cpu:
         log("cpu baseline (oracle)")
-        out["cpu_baseline"] = cpu_baseline(sc, params)
+        out["cpu_baseline"] = cpu_baseline(args.config, sc, params)
     S.release()
     if args.copy_mib > 0:
         a = torch.empty(args.copy_mib << 18, dtype=torch.float32, device="cuda").fill_(1.0)

@@ -37,7 +37,8 @@ enum {
     PT_ENOMEM = -2,       /* device allocation failed; the scene stays valid */
     PT_EDEVICE = -3,      /* a HIP call failed */
     PT_ESTATE = -4,       /* call out of order (e.g. render before build_subspaces) */
-    PT_EUNSUPPORTED = -5  /* not a gfx950 device */
+    PT_EUNSUPPORTED = -5  /* not a gfx950 device, or a scene the kernels cannot hold (e.g. a BVH whose
+                             traversal would need more stack entries than the kernels keep) */
 };
 
 typedef struct pt_scene pt_scene;
@@ -65,10 +66,16 @@ typedef struct {
     int32_t max_light_paths; /* capacity for M, light sub-paths per iteration */
 } pt_scene_desc;
 
-/* Upload a scene: validates the arrays, builds a binned-SAH BVH on the host, collapses it to
- * 4-wide 128-byte nodes, copies everything to the current device and allocates per-iteration
- * workspaces sized for width x height pixels and max_light_paths light sub-paths. Host arrays
- * may be freed on return. On success *out receives the handle. Synchronises hip_stream. */
+/* Upload a scene: the measurement's geometry, materials, emitters and sensor (Section 3.1: the
+ * path integral's surfaces and the pixel filters f_j, here a pinhole camera whose pixel (x, y)
+ * integrates over its square of the image plane), plus the capacity for the M light sub-paths
+ * every iteration traces (Section 3.2). Validates the arrays, builds a binned-SAH BVH on the
+ * host, collapses it to 4-wide 128-byte nodes, copies everything to the current device and
+ * allocates per-iteration workspaces sized for width x height pixels and max_light_paths light
+ * sub-paths. Host arrays may be freed on return. On success *out receives the handle.
+ * Synchronises hip_stream. Errors: PT_EINVAL for malformed arrays (nothing allocated),
+ * PT_EUNSUPPORTED when the tree's worst-case traversal needs more than the kernels' 48 stack
+ * entries, PT_ENOMEM when a device allocation fails. */
 pt_status pt_scene_upload(const pt_scene_desc *desc, void *hip_stream, pt_scene **out);
 
 /* Free everything the scene owns. Synchronises the device first. NULL is a no-op. */
@@ -167,7 +174,8 @@ pt_status pt_render_iteration(pt_scene *s, const pt_iter_params *p, float *accum
 /* n_iter consecutive iterations (p->iteration, p->iteration + 1, ...) by replaying one captured
  * HIP graph of an iteration; the same results as n_iter pt_render_iteration calls with the same
  * parameters. The graph is captured on first use and re-captured when the parameters (other
- * than the iteration index) or the buffers change. No statistics; PT_FLAG_TIMING is rejected. */
+ * than the iteration index), the buffers or the scene's state generation (see pt_render_scenes)
+ * change. No statistics; PT_FLAG_TIMING is rejected. */
 pt_status pt_render_batch(pt_scene *s, const pt_iter_params *p, uint32_t n_iter, float *accum_rgb_dev,
                           float *accum_sq_dev, void *hip_stream);
 
@@ -176,8 +184,11 @@ pt_status pt_render_batch(pt_scene *s, const pt_iter_params *p, uint32_t n_iter,
  * replayed n_iter times on hip_stream (iterations params[i].iteration, +1, ...). Scene i
  * accumulates into accum_rgb[i] / accum_sq[i] (accum_sq may be NULL) as pt_render_iteration
  * does. The graph belongs to scenes[0] and is rebuilt when a scene, a parameter other than the
- * iteration index, a buffer or a scene's tuned schedule changes; release the scenes of a batch
- * together. PT_FLAG_TIMING is rejected. */
+ * iteration index, a buffer or a scene's state changes: every scene carries a state generation,
+ * unique in the process, that upload, pt_build_subspaces, the network's allocation and
+ * pt_autotune advance, and the graph's key holds each scene's generation, so a graph is never
+ * replayed on a scene it was not captured for (a scene released and another uploaded at the same
+ * host address included). PT_FLAG_TIMING is rejected. */
 pt_status pt_render_scenes(pt_scene *const *scenes, const pt_iter_params *params, int32_t n_scenes, uint32_t n_iter,
                            float *const *accum_rgb, float *const *accum_sq, void *hip_stream);
 
@@ -265,7 +276,10 @@ typedef struct {
 pt_status pt_reciprocal_estimate(pt_scene *s, const pt_recip_query *q, float *out_est_dev,
                                  uint32_t *out_nsamples_dev, void *hip_stream);
 
-/* Image = accum / n_iter, written to the caller-owned out_rgb_dev[H*W*3]. */
+/* Image = accum / n_iter: the per-pixel estimate of I_j (Section 3.1) as the mean of n_iter
+ * iterations of one sample per pixel each (Section 6.1), written to the caller-owned
+ * out_rgb_dev[H*W*3] (row-major, 3 floats per pixel, the layout of accum_rgb_dev). accum_rgb_dev
+ * and out_rgb_dev may be the same buffer. PT_EINVAL for a NULL buffer or n_iter = 0. */
 pt_status pt_resolve_image(pt_scene *s, const float *accum_rgb_dev, uint32_t n_iter, float *out_rgb_dev,
                            void *hip_stream);
 
@@ -274,6 +288,39 @@ pt_status pt_resolve_image(pt_scene *s, const float *accum_rgb_dev, uint32_t n_i
  * -1). Ties in t go to the lower input triangle index. */
 pt_status pt_trace_closest(pt_scene *s, const float *rays_dev, int32_t n, float *t_dev, int32_t *prim_dev,
                            void *hip_stream);
+
+/* Running totals over every iteration the scene has rendered (pt_render_iteration, pt_render_batch,
+ * pt_render_scenes, pt_autotune), kept on the device and read here (synchronises hip_stream);
+ * reset != 0 clears them afterwards. The parity runs require n_nan = n_recip_truncated = 0 over
+ * all their iterations. captures counts the HIP graphs pt_render_batch and pt_render_scenes have
+ * captured for this scene; bvh_stack_need and bvh_depth describe the uploaded tree. */
+typedef struct {
+    double iterations, n_nan, n_recip_truncated, n_proxy_valid, n_recip_samples, n_cand;
+    double captures, bvh_stack_need, bvh_depth;
+} pt_totals;
+pt_status pt_scene_totals(pt_scene *s, pt_totals *out, int32_t reset, void *hip_stream);
+
+/* Test hook: the selection tables of the latest iteration (Section 5.6's Gamma rows for which = 0,
+ * the light-subspace rows Q of the probabilistic connections for which = 1), copied to host memory
+ * (synchronises hip_stream). n_rows x n_cols must be the table's shape (eye subspaces x specular,
+ * or light, subspaces). Writes *n_nonempty (columns non-empty this iteration), nonempty[n_cols]
+ * (their subspace ids, the first *n_nonempty valid), and per row T: prob[T*n_cols + j] and
+ * alias[T*n_cols + j] (the Walker alias row over column positions j < *n_nonempty),
+ * pmf[T*n_cols + S] (the probability the row realises for subspace S, which the estimators divide
+ * by; valid for non-empty S) and weights[T*n_cols + S] (the frozen learned weights the row was
+ * built from). */
+pt_status pt_selection_tables(pt_scene *s, int32_t which, int32_t n_rows, int32_t n_cols, int32_t *n_nonempty,
+                              int32_t *nonempty, float *prob, int32_t *alias, float *pmf, float *weights,
+                              void *hip_stream);
+
+/* Test hook: Philox4x32-10 (Salmon et al. 2011), the counter-based generator every random decision
+ * of the kernels draws from, on n rows of in_dev[6 n] = (counter 0..3, key 0..1) -> out_dev[4 n].
+ * Device buffers. */
+pt_status pt_philox(const uint32_t *in_dev, int32_t n, uint32_t *out_dev, void *hip_stream);
+
+/* Host only (no device needed): builds the 4-wide BVH pt_scene_upload would build for tri[n_tri*9]
+ * and reports its node count, the worst-case traversal stack it needs and its depth in levels. */
+pt_status pt_bvh_stats(const float *tri, int32_t n_tri, int32_t *n_nodes, int32_t *stack_need, int32_t *depth);
 
 /* Message for the last non-OK return on this thread ("" if none). */
 const char *pt_last_error(void);

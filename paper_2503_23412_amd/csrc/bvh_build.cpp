@@ -176,3 +176,31 @@ void pt_build_bvh4(const float *tri, int n, std::vector<BNode> &nodes, std::vect
     collapse(B, 0, nodes, 0);
     order = B.ref;
 }
+
+namespace {
+void stack_need_rec(const std::vector<BNode> &nodes, int n, int level, int &need, int &depth)
+{
+    int inner = 0, best = 0, deepest = level;
+    for (int k = 0; k < 4; ++k) {
+        if (nodes[n].count[k] != 0) continue;
+        ++inner;
+        int nd = 0, dp = 0;
+        stack_need_rec(nodes, nodes[n].child[k], level + 1, nd, dp);
+        best = std::max(best, nd);
+        deepest = std::max(deepest, dp);
+    }
+    need = std::max(inner - 1, 0) + best;
+    depth = deepest;
+}
+}  // namespace
+
+// Largest traversal stack a walk of the 4-wide tree can need: at a node with k inner children the
+// walk continues into one of them and pushes at most k - 1, so a subtree needs max(k - 1, 0) plus
+// the largest need of its inner children. depth receives the number of node levels.
+int pt_bvh4_stack_need(const std::vector<BNode> &nodes, int *depth)
+{
+    int need = 0, dp = 1;
+    if (!nodes.empty()) stack_need_rec(nodes, 0, 1, need, dp);
+    if (depth) *depth = dp;
+    return need;
+}

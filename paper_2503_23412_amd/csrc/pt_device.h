@@ -67,6 +67,24 @@ __device__ __forceinline__ uint32_t rng_u32(Rng &r)
 }
 // uniform float in [0, 1) with 24 random bits
 __device__ __forceinline__ float rng_f(Rng &r) { return (float)(rng_u32(r) >> 8) * (1.0f / 16777216.0f); }
+// index in [0, n) from 32 random bits x: floor(x n / 2^32)
+__device__ __forceinline__ int index_of(uint32_t x, int n) { return (int)__umulhi(x, (uint32_t)n); }
+__device__ __forceinline__ int rng_index(Rng &r, int n) { return index_of(rng_u32(r), n); }
+// the probability with which index_of returns i: the number of x with floor(x n / 2^32) = i,
+// ceil((i + 1) 2^32 / n) - ceil(i 2^32 / n), over 2^32 (within n / 2^32 of 1 / n)
+__device__ __forceinline__ double index_prob(int i, int n)
+{
+    const uint64_t a = (((uint64_t)i << 32) + (uint64_t)n - 1) / (uint64_t)n;
+    const uint64_t b = (((uint64_t)(i + 1) << 32) + (uint64_t)n - 1) / (uint64_t)n;
+    return (double)(b - a) * 2.3283064365386962890625e-10;
+}
+// the probability that a 24-bit rng_f draw lies below p: ceil(p 2^24) / 2^24, clamped to [0, 1]
+__device__ __forceinline__ double below_prob(float p)
+{
+    if (!(p > 0.0f)) return 0.0;
+    if (p >= 1.0f) return 1.0;
+    return ceil((double)p * 16777216.0) * (1.0 / 16777216.0);
+}
 
 enum { S_LIGHT = 11, S_CAND = 12, S_PILOT = 13, S_RECIP = 14, S_EYE = 15, S_PROXY = 16, S_TABLE = 17,
        S_ROUL = 18, S_PRE = 19, S_KMEANS = 20, S_TILE = 21, S_MLP = 22 };
@@ -429,9 +447,10 @@ __device__ __forceinline__ bool traverse_rt(const SceneDev &S, float3 o, float3 
         }
         PT_CSWAP(0, 1) PT_CSWAP(2, 3) PT_CSWAP(0, 2) PT_CSWAP(1, 3) PT_CSWAP(1, 2)
 #undef PT_CSWAP
-        // the nearest child continues in a register, the others are pushed far to near; the
-        // stack holds PT_STACK entries and a 4-wide tree needs at most 3 per level, so a push
-        // beyond it can only come from a malformed tree and is dropped
+        // the nearest child continues in a register, the others are pushed far to near. The
+        // stack holds PT_STACK entries, and pt_scene_upload rejects a tree whose worst-case walk
+        // (the largest sum over a root-to-leaf path of inner children less one) needs more, so
+        // the bound below only keeps a malformed tree from writing past the stack
         if (cid[0] >= 0) {
 #pragma unroll
             for (int k = 3; k >= 1; --k)

@@ -257,6 +257,7 @@ struct ConnDev {
     int *count, *off, *fill, *list, *nonempty, *n_nonempty;
     const float *al_prob, *row_sum;
     const int *al_idx;
+    const float *al_pmf;       // [n_eye * n_lsub] probability the alias row draws S_L (non-empty S_L only)
     const float *q;            // [n_eye * n_lsub] Q frozen for this iteration
     // MIS inputs from earlier iterations only
     const float *row_tot;      // [n_eye] row totals of the frozen Q
@@ -290,14 +291,12 @@ __device__ __forceinline__ float conn_k(const ConnDev &C, float on, int T, int S
     const float pi = rt > 0.0f ? (1.0f - C.defensive) * C.q[(size_t)T * C.n_lsub + Sl] / rt + C.defensive / ne : 1.0f / ne;
     return (float)C.M * pi / (float)cp;
 }
-// this iteration's selection probability of bucket Sl from row T (what the alias row samples)
+// this iteration's selection probability of bucket Sl from row T: what the alias row realises
 __device__ __forceinline__ float conn_sel(const ConnDev &C, int T, int Sl)
 {
     const int ne = *C.n_nonempty;
     if (ne <= 0 || C.count[Sl] <= 0) return 0.0f;
-    const float rs = C.row_sum[T];
-    return rs > 0.0f ? (1.0f - C.defensive) * C.q[(size_t)T * C.n_lsub + Sl] / rs + C.defensive / (float)ne
-                     : 1.0f / (float)ne;
+    return C.al_pmf[(size_t)T * C.n_lsub + Sl];
 }
 
 // label every pool vertex and count the buckets
@@ -1475,16 +1474,19 @@ __global__ void k_eye_shade(SceneDev S, EyeBuf E, EyeParams P, SubDev D, LightBu
                     }
                 }
                 // connection: light subspace from row T of Q, then one vertex of that bucket
-                const float uc = rng_f(r), uc1 = rng_f(r), uc2 = rng_f(r);
+                const uint32_t xc = rng_u32(r);
+                const float uc1 = rng_f(r);
+                const uint32_t xc2 = rng_u32(r);
                 const int T_z = (P.conn_on && !z_dirac) ? conn_label_eye(S, C, x, sh.n, wo) : 0;
                 const int ne_l = P.conn_on ? *C.n_nonempty : 0;
                 if (P.conn_on && !z_dirac && ne_l > 0 && P.mk.kS > 0.0f) {
-                    const int jl = min((int)(uc * (float)ne_l), ne_l - 1);
                     const size_t row = (size_t)T_z * C.n_lsub;
-                    const int Sl = C.nonempty[uc1 < C.al_prob[row + jl] ? jl : C.al_idx[row + jl]];
+                    const int Sl = C.nonempty[alias_draw(C.al_prob + row, C.al_idx + row, ne_l, xc, uc1)];
                     const int cs = C.count[Sl];
-                    const float sel = cs > 0 ? conn_sel(C, T_z, Sl) : 0.0f;
-                    const uint32_t v = (uint32_t)C.list[C.off[Sl] + min((int)(uc2 * (float)cs), max(cs - 1, 0))];
+                    // the bucket's vertex uniformly: index_of realises index_prob(k, cs)
+                    const int kv = cs > 0 ? index_of(xc2, cs) : 0;
+                    const float sel = cs > 0 ? conn_sel(C, T_z, Sl) * (float)(index_prob(kv, cs) * (double)cs) : 0.0f;
+                    const uint32_t v = (uint32_t)C.list[C.off[Sl] + kv];
                     const int j = (int)(v / (uint32_t)L.M), lp = (int)(v % (uint32_t)L.M);
                     const uint32_t sg = L.sig[lp];
                     if (sel > 0.0f && t + j + 1 <= P.K && conn_ok(P, light_tail_class(ph, uu, sg, j, P.u_max))) {
@@ -1749,31 +1751,35 @@ __global__ void __launch_bounds__(WG) k_proxy(SceneDev S, EyeBuf E, const Cand *
         int ci;
         float pi_j;
         int Ssel = 0;
-        const float u0 = rng_f(r), u1 = rng_f(r), u2 = rng_f(r);
+        // every selection divides by the probability its draw realises (index_prob, the alias
+        // row's realised pmf, the network mixture's), not by the nominal one
+        const uint32_t x0 = rng_u32(r);
+        const float u1 = rng_f(r);
+        const uint32_t x2 = rng_u32(r);
         if (P.mlp_on) {
             // S and its mixture probability from k_mlp_select, then uniformly within S
             Ssel = fbits(it.aux.z);
             const int cs = Ssel >= 0 ? D.s_count[Ssel] : 0;
             if (cs > 0) {
-                ci = D.s_list[D.s_off[Ssel] + min((int)(u2 * (float)cs), cs - 1)];
-                pi_j = it.aux.w / (float)cs;
+                const int k = index_of(x2, cs);
+                ci = D.s_list[D.s_off[Ssel] + k];
+                pi_j = (float)((double)it.aux.w * index_prob(k, cs));
             } else {
                 ci = 0;
                 pi_j = 0.0f;
             }
         } else if (P.gamma_on) {
             const int ne = *D.n_nonempty;
-            const int j = min((int)(u0 * (float)ne), ne - 1);
             const size_t row = (size_t)T * D.n_spec;
-            const int jj = u1 < D.al_prob[row + j] ? j : D.al_idx[row + j];
-            Ssel = D.nonempty[jj];
+            Ssel = D.nonempty[alias_draw(D.al_prob + row, D.al_idx + row, ne, x0, u1)];
             const int cs = D.s_count[Ssel];
-            const int k = min((int)(u2 * (float)cs), cs - 1);
+            const int k = index_of(x2, cs);
             ci = D.s_list[D.s_off[Ssel] + k];
-            pi_j = sel_prob(D, T, Ssel) / (float)cs;
+            pi_j = (float)((double)sel_prob(D, T, Ssel) * index_prob(k, cs));
         } else {
-            ci = (int)final_[min((int)(u0 * (float)nk), nk - 1)];
-            pi_j = 1.0f / (float)nk;
+            const int k = index_of(x0, nk);
+            ci = (int)final_[k];
+            pi_j = (float)index_prob(k, nk);
         }
         const Cand c = cand[ci];
         const int cls = c.cls_u >> 8, u = c.cls_u & 0xFF;
@@ -1957,6 +1963,33 @@ __global__ void k_accumulate(float *frame, float *acc, float *acc2, int npix, in
     wave_count(cnt + C_NAN, bad);
 }
 
+__global__ void k_fill_u64(unsigned long long *p, unsigned long long v, int n)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+// Philox4x32-10 of n (counter, key) rows: in[6 i .. 6 i + 5] = c0 c1 c2 c3 k0 k1 -> out[4 i .. 4 i + 3]
+__global__ void k_philox_hook(const uint32_t *in, int n, uint32_t *out)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const uint32_t *a = in + 6 * (size_t)i;
+    uint32_t o[4];
+    philox10(a[4], a[5], a[0], a[1], a[2], a[3], o);
+    for (int k = 0; k < 4; ++k) out[4 * (size_t)i + k] = o[k];
+}
+// the iteration's counts added to the scene's running totals
+__global__ void k_totals(const unsigned long long *cnt, unsigned long long *tot)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    tot[TOT_ITERS] += 1ull;
+    tot[TOT_NAN] += cnt[C_NAN];
+    tot[TOT_TRUNC] += cnt[C_RECIP_TRUNC];
+    tot[TOT_PROXY_VALID] += cnt[C_PROXY_VALID];
+    tot[TOT_RECIP_SAMPLES] += cnt[C_RECIP_SAMPLES];
+    tot[TOT_CAND] += cnt[C_NCAND];
+}
+
 __global__ void k_copy(const float *src, float *dst, size_t n)
 {
     const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1995,7 +2028,49 @@ __global__ void __launch_bounds__(WG) k_trace_closest(SceneDev S, const float *r
 
 // Table mode of the reciprocal estimator: target 1 / sum f, supporting pmf q (inverse-CDF by a
 // linear scan), estimator I~ (sign_est = 0) or the sign estimator I (sign_est = 1).
-__global__ void k_recip_table(const float *f, const float *q, int n, float B, int n_est, int est, float booth_r,
+// Cumulative sums of the supporting pmf q of a table problem, in double, by one workgroup of
+// 1024 threads (each a contiguous chunk): cdf[0] = 0, cdf[k + 1] = q[0] + ... + q[k].
+__global__ void __launch_bounds__(1024) k_table_cdf(const float *q, int n, double *cdf)
+{
+    __shared__ double part[1024];
+    const int t = threadIdx.x;
+    const int per = (n + 1023) / 1024;
+    const int a = min(n, t * per), b = min(n, a + per);
+    double acc = 0.0;
+    for (int k = a; k < b; ++k) acc += (double)q[k];
+    part[t] = acc;
+    __syncthreads();
+    // inclusive scan of the 1024 chunk sums (Hillis-Steele)
+    for (int off = 1; off < 1024; off <<= 1) {
+        const double v = t >= off ? part[t - off] : 0.0;
+        __syncthreads();
+        part[t] += v;
+        __syncthreads();
+    }
+    double run = t > 0 ? part[t - 1] : 0.0;
+    if (t == 0) cdf[0] = 0.0;
+    for (int k = a; k < b; ++k) {
+        run += (double)q[k];
+        cdf[k + 1] = run;
+    }
+}
+// One draw from the table's supporting pmf by inverse CDF: a 53-bit uniform scaled by the total,
+// binary search for the interval [cdf[k], cdf[k + 1]) that holds it. qk receives the probability
+// that this draw realises, (cdf[k + 1] - cdf[k]) / cdf[n], which the estimator divides by.
+__device__ __forceinline__ int table_draw(Rng &r, const double *cdf, int n, double &qk)
+{
+    const uint32_t xa = rng_u32(r), xb = rng_u32(r);
+    const double u = (double)(((uint64_t)xa << 21) | (uint64_t)(xb >> 11)) * (1.0 / 9007199254740992.0);
+    const double tot = cdf[n], t = u * tot;
+    int lo = 0, hi = n;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (cdf[mid] <= t) lo = mid; else hi = mid;
+    }
+    qk = (cdf[lo + 1] - cdf[lo]) / tot;
+    return lo;
+}
+__global__ void k_recip_table(const float *f, const double *cdf, int n, float B, int n_est, int est, float booth_r,
                               uint32_t seed, uint32_t cap, float *out, uint32_t *ns_out)
 {
     const int e = blockIdx.x * blockDim.x + threadIdx.x;
@@ -2011,11 +2086,9 @@ __global__ void k_recip_table(const float *f, const float *q, int n, float B, in
         uint32_t ns = 0, trunc = 0;
         for (;;) {
             if (ns >= cap) { trunc = 1; break; }
-            const float x = rng_f(r);
-            float acc = 0.0f;
-            int k = 0;
-            for (; k < n - 1; ++k) { acc += q[k]; if (x < acc) break; }
-            const float g = 1.0f - f[k] / (q[k] * B);
+            double qk;
+            const int k = table_draw(r, cdf, n, qk);
+            const float g = (float)(1.0 - (double)f[k] / (qk * (double)B));
             ns++;
             prod *= g;
             ans += prod / w;
@@ -2033,11 +2106,9 @@ __global__ void k_recip_table(const float *f, const float *q, int n, float B, in
         if (ns >= cap) { trunc = 1; break; }
         float s = 1.0f;
         if (pos > 0) pos--; else { neg--; s = -1.0f; }
-        const float x = rng_f(r);
-        float acc = 0.0f;
-        int k = 0;
-        for (; k < n - 1; ++k) { acc += q[k]; if (x < acc) break; }
-        const float g = 1.0f - f[k] / (q[k] * B);
+        double qk;
+        const int k = table_draw(r, cdf, n, qk);
+        const float g = (float)(1.0 - (double)f[k] / (qk * (double)B));
         ns++;
         ans += sign_est ? (ns > 1 ? s * invB : 0.0f) : s * g * invB;
         const float ag = fabsf(g), fl = floorf(ag);

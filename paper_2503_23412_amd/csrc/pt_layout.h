@@ -87,6 +87,9 @@ enum {
 static_assert(C_EYE_Q0 - C_LIGHT_Q0 >= PT_LSTORE, "light queue counters overlap");
 static_assert(C_SHD0 - C_EYE_Q0 >= PT_MAX_DEPTH + 1 && C_PROXYQ - C_SHD0 >= PT_MAX_DEPTH + 1, "queue counters overlap");
 
+// running totals over the iterations of a scene (not cleared per iteration)
+enum { TOT_ITERS = 0, TOT_NAN, TOT_TRUNC, TOT_PROXY_VALID, TOT_RECIP_SAMPLES, TOT_CAND, TOT_COUNT };
+
 // queued shadow ray: origin + first ignored triangle, direction + tmax, contribution + pixel,
 // second ignored triangle
 struct ShadowRay {

@@ -2,6 +2,7 @@
 // rendering iteration, the reciprocal estimator and image resolve.
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -13,10 +14,16 @@
 #include "pt_kernels.h"
 
 void pt_build_bvh4(const float *tri, int n, std::vector<BNode> &nodes, std::vector<int> &order);
+int pt_bvh4_stack_need(const std::vector<BNode> &nodes, int *depth);
 
 namespace {
 
 thread_local std::string g_err;
+// state generations: every change of a scene's device buffers or schedule takes the next value,
+// unique over the process, so that a captured graph is never replayed on a scene (or a scene
+// uploaded at the same host address) it was not captured for
+std::atomic<unsigned long long> g_generation{0};
+unsigned long long next_generation() { return ++g_generation; }
 
 pt_status set_err(pt_status code, const char *fmt, ...)
 {
@@ -74,18 +81,20 @@ pt_status check_device()
 // alias rows of a T x n table over its non-empty columns: one wavefront per row when the row
 // fits LDS, else one thread per row
 static void alias_rows(const float *tab, int ne, int n, const int *nonempty, const int *n_nonempty, float defensive,
-                       float *al_prob, int *al_idx, float *row_sum, int *scratch, hipStream_t st)
+                       float *al_prob, int *al_idx, float *row_sum, float *pmf, int *scratch, hipStream_t st)
 {
     if (n <= ALIAS_LDS_COLS)
         k_alias_rows_wave<<<ne, 64, (size_t)16 * n, st>>>(tab, ne, n, nonempty, n_nonempty, defensive, al_prob, al_idx,
-                                                          row_sum);
+                                                          row_sum, pmf);
     else
         k_alias_rows<<<blocks(ne, 64), 64, 0, st>>>(tab, ne, n, nonempty, n_nonempty, defensive, al_prob, al_idx, row_sum,
-                                                   scratch);
+                                                   pmf, scratch);
 }
 
 struct pt_scene {
     int device = 0;
+    unsigned long long gen = 0;   // state generation (next_generation)
+    int stack_need = 0, bvh_depth = 0;
     int W = 0, H = 0, npix = 0, max_light = 0, ntri = 0;
     float scene_diag = 1.0f;
     // geometry
@@ -104,10 +113,11 @@ struct pt_scene {
     uint32_t *kept = nullptr, *final_ = nullptr;
     uint32_t *cost_bin = nullptr, *order = nullptr;   // chain scheduling (longest expected first)
     unsigned long long *cnt = nullptr;
+    unsigned long long *tot = nullptr;   // [TOT_COUNT] running totals over iterations (k_totals)
     float *runmax = nullptr;   // [2 * 5] running maxima of f/q per (class, u)
     // subspace-based connections: light subspaces, buckets of the pool, Q (learned, frozen), alias rows
     int n_lsub = 0;
-    float *light_c = nullptr, *qacc = nullptr, *qfrz = nullptr, *q_alprob = nullptr, *q_rowsum = nullptr,
+    float *light_c = nullptr, *qacc = nullptr, *qfrz = nullptr, *q_alprob = nullptr, *q_alpmf = nullptr, *q_rowsum = nullptr,
           *q_rowtot = nullptr, *lne_prev = nullptr;
     int *lcount = nullptr, *loff = nullptr, *lfill = nullptr, *lnonempty = nullptr, *ln_ne = nullptr, *llist = nullptr,
         *plab = nullptr, *prank = nullptr, *q_alidx = nullptr, *q_scratch = nullptr, *lcount_prev = nullptr;
@@ -118,7 +128,7 @@ struct pt_scene {
     int n_eye = 0, n_spec = 0, tile = 10, tiles_x = 0, n_tiles = 0, km_cap = 0;
     float *eye_c = nullptr, *spec_c = nullptr, *km_sum = nullptr, *km_cnt = nullptr, *feat = nullptr;
     int *s_count = nullptr, *s_off = nullptr, *s_fill = nullptr, *s_list = nullptr, *nonempty = nullptr, *n_ne = nullptr;
-    float *al_prob = nullptr, *row_sum = nullptr, *gamma_acc = nullptr, *gamma_frz = nullptr;
+    float *al_prob = nullptr, *al_pmf = nullptr, *row_sum = nullptr, *gamma_acc = nullptr, *gamma_frz = nullptr;
     int *al_idx = nullptr, *al_scratch = nullptr;
     float *rstat_acc = nullptr, *rstat_frz = nullptr, *tile_proxy = nullptr, *tile_total = nullptr;
     float *prev = nullptr, *row_tot = nullptr;
@@ -161,6 +171,7 @@ struct pt_scene {
     std::vector<hipEvent_t> mevents;
     hipGraphExec_t gexec = nullptr;
     std::vector<char> gkey;
+    unsigned long long n_captures = 0;   // graphs captured by pt_render_batch / pt_render_scenes
 
     template <class T> pt_status alloc(T *&p, size_t n)
     {
@@ -234,6 +245,13 @@ extern "C" pt_status pt_scene_upload(const pt_scene_desc *d, void *stream_, pt_s
         std::vector<BNode> nodes;
         std::vector<int> order;
         pt_build_bvh4(d->tri, d->n_tri, nodes, order);
+        s->stack_need = pt_bvh4_stack_need(nodes, &s->bvh_depth);
+        if (s->stack_need > PT_STACK) {
+            const int need = s->stack_need;
+            delete s;
+            return set_err(PT_EUNSUPPORTED, "the BVH needs a traversal stack of %d entries; the kernels hold %d", need,
+                           PT_STACK);
+        }
         s->stk16 = nodes.size() < 65536;
         s->inv_order.assign(d->n_tri, 0);
         for (int i = 0; i < d->n_tri; ++i) s->inv_order[order[i]] = i;
@@ -311,6 +329,7 @@ extern "C" pt_status pt_scene_upload(const pt_scene_desc *d, void *stream_, pt_s
         AL(s->llist, (size_t)PT_LSTORE * M); AL(s->plab, (size_t)PT_LSTORE * M); AL(s->prank, (size_t)PT_LSTORE * M);
         AL(s->E.frame, (size_t)3 * np);
         AL(s->cnt, C_COUNT);
+        AL(s->tot, TOT_COUNT);
         AL(s->runmax, 16);
         AL(s->chq[0], CHAIN_LIST_CAP); AL(s->chq[1], CHAIN_LIST_CAP);
         AL(s->chbuf, CHAIN_BUF);
@@ -326,6 +345,7 @@ extern "C" pt_status pt_scene_upload(const pt_scene_desc *d, void *stream_, pt_s
         HIPCHK(hipMemcpyAsync(s->em_cdf, emc.data(), emc.size() * sizeof(float), hipMemcpyHostToDevice, stream));
         HIPCHK(hipMemsetAsync(s->E.frame, 0, sizeof(float) * 3 * np, stream));
         HIPCHK(hipMemsetAsync(s->runmax, 0, sizeof(float) * 16, stream));
+        HIPCHK(hipMemsetAsync(s->tot, 0, sizeof(unsigned long long) * TOT_COUNT, stream));
         HIPCHK(hipStreamSynchronize(stream));
         SceneDev &S = s->S;
         S.nodes = s->nodes; S.tris = s->tris; S.shade = s->shade; S.mats = s->mats; S.tex = s->tex;
@@ -345,6 +365,7 @@ extern "C" pt_status pt_scene_upload(const pt_scene_desc *d, void *stream_, pt_s
         S.cam.tan_half = std::tan(0.5f * c[9] * 3.14159265358979f / 180.0f);
         S.cam.aspect = (float)d->width / (float)d->height;
         S.cam.w = d->width; S.cam.h = d->height;
+        s->gen = next_generation();
         *out = s;
         return PT_OK;
     } catch (const std::exception &e) {
@@ -467,6 +488,7 @@ extern "C" pt_status pt_build_subspaces(pt_scene *s, const pt_subspace_params *p
         if (!s->ln_ne) { AL(s->ln_ne, 1); AL(s->lne_prev, 1); }
         AL(s->lcount_prev, nl);
         AL(s->qacc, (size_t)ne * nl); AL(s->qfrz, (size_t)ne * nl); AL(s->q_alprob, (size_t)ne * nl);
+        AL(s->q_alpmf, (size_t)ne * nl);
         AL(s->q_alidx, (size_t)ne * nl); AL(s->q_scratch, (size_t)2 * ne * nl); AL(s->q_rowsum, ne); AL(s->q_rowtot, ne);
 #undef AL
         s->n_lsub = nl;
@@ -480,6 +502,7 @@ extern "C" pt_status pt_build_subspaces(pt_scene *s, const pt_subspace_params *p
         AL(s->s_count, ns); AL(s->s_off, ns); AL(s->s_fill, ns); AL(s->nonempty, ns); AL(s->n_ne, 1);
         if (!s->s_list) AL(s->s_list, (size_t)4 * M);
         AL(s->al_prob, (size_t)ne * ns); AL(s->al_idx, (size_t)ne * ns); AL(s->al_scratch, (size_t)2 * ne * ns);
+        AL(s->al_pmf, (size_t)ne * ns);
         AL(s->row_sum, ne); AL(s->gamma_acc, (size_t)ne * ns); AL(s->gamma_frz, (size_t)ne * ns);
         AL(s->rstat_acc, (size_t)30 * ns); AL(s->rstat_frz, (size_t)30 * ns);
         AL(s->s_count_prev, ns); AL(s->row_tot, ne);
@@ -557,6 +580,7 @@ extern "C" pt_status pt_build_subspaces(pt_scene *s, const pt_subspace_params *p
     HIPCHK(hipStreamSynchronize(st));
     s->subspaces_ready = true;
     s->mlp_ready = false;   // the network starts again with the new subspaces
+    s->gen = next_generation();
     return PT_OK;
 }
 
@@ -635,6 +659,7 @@ pt_status ensure_mlp(pt_scene *s, hipStream_t st)
 #undef AL
         s->mlp_nout = nout; s->mlp_rows = R; s->mlp_np = (int)o.n;
         s->mlp_ready = false;
+        s->gen = next_generation();
     }
     if (!s->mlp_ready) {
         k_mlp_init<<<blocks(s->mlp_np, 256), 256, 0, st>>>(s->mw, s->mwb, s->mg, s->mm, s->mv, nout, 0x6d6c7001u);
@@ -788,7 +813,7 @@ pt_status enqueue_iteration(pt_scene *s, const pt_iter_params *p, float *acc, fl
         CD.n_lsub = nl; CD.n_eye = ne; CD.M = M;
         CD.lab = s->plab; CD.rank = s->prank; CD.count = s->lcount; CD.off = s->loff; CD.fill = s->lfill; CD.list = s->llist;
         CD.nonempty = s->lnonempty; CD.n_nonempty = s->ln_ne;
-        CD.al_prob = s->q_alprob; CD.al_idx = s->q_alidx; CD.row_sum = s->q_rowsum; CD.q = s->qfrz;
+        CD.al_prob = s->q_alprob; CD.al_idx = s->q_alidx; CD.al_pmf = s->q_alpmf; CD.row_sum = s->q_rowsum; CD.q = s->qfrz;
         CD.row_tot = s->q_rowtot; CD.count_prev = s->lcount_prev; CD.ne_prev = s->lne_prev;
         CD.defensive = p->defensive; CD.qacc = s->qacc;
         // Q of earlier iterations only
@@ -805,7 +830,7 @@ pt_status enqueue_iteration(pt_scene *s, const pt_iter_params *p, float *acc, fl
             k_scan_sub<<<1, 1024, 0, es>>>(s->lcount, s->loff, s->lfill, s->lnonempty, s->ln_ne, nl);
             k_scatter_pool<<<blocks(maxp, 256), 256, 0, es>>>(L, CD, s->cnt);
             alias_rows(s->qfrz, ne, nl, s->lnonempty, s->ln_ne, p->defensive, s->q_alprob, s->q_alidx, s->q_rowsum,
-                       s->q_scratch, es);
+                       s->q_alpmf, s->q_scratch, es);
         }
         k_light_phi<<<blocks(M, 256), 256, 0, es>>>(S, L, mk, CD, s->cnt);
     }
@@ -830,7 +855,7 @@ pt_status enqueue_iteration(pt_scene *s, const pt_iter_params *p, float *acc, fl
         D.eye_c = s->eye_c; D.spec_c = s->spec_c; D.n_eye = ne; D.n_spec = ns;
         D.eye = cent_set(s->eye_c, s->gs_eye); D.spec = cent_set(s->spec_c, s->gs_spec);
         D.s_count = s->s_count; D.s_off = s->s_off; D.s_list = s->s_list; D.nonempty = s->nonempty; D.n_nonempty = s->n_ne;
-        D.al_prob = s->al_prob; D.al_idx = s->al_idx; D.row_sum = s->row_sum; D.gamma = s->gamma_frz;
+        D.al_prob = s->al_prob; D.al_idx = s->al_idx; D.al_pmf = s->al_pmf; D.row_sum = s->row_sum; D.gamma = s->gamma_frz;
         D.defensive = p->defensive; D.rstat = s->rstat_frz;
         D.prev = s->prev; D.s_count_prev = s->s_count_prev; D.row_tot = s->row_tot;
         D.tile_proxy = s->tile_proxy; D.tile_total = s->tile_total; D.tile = s->tile; D.tiles_x = s->tiles_x;
@@ -896,7 +921,7 @@ pt_status enqueue_iteration(pt_scene *s, const pt_iter_params *p, float *acc, fl
                 k_scatter_sub<<<blocks(maxc, 256), 256, 0, stream>>>(s->cand, s->final_, s->cnt, s->s_fill, s->s_list);
                 if (gamma)
                     alias_rows(s->gamma_frz, ne, ns, s->nonempty, s->n_ne, p->defensive, s->al_prob, s->al_idx,
-                               s->row_sum, s->al_scratch, stream);
+                               s->row_sum, s->al_pmf, s->al_scratch, stream);
                 k_rstat<<<blocks(maxc, 256), 256, 0, stream>>>(s->cand, s->final_, s->cnt, p->recip_repeats, ns,
                                                                   s->rstat_acc);
             }
@@ -929,6 +954,7 @@ pt_status enqueue_iteration(pt_scene *s, const pt_iter_params *p, float *acc, fl
         k_prev_store<<<blocks(ns, 256), 256, 0, stream>>>(s->cnt, s->s_count, s->n_ne, ns, s->prev, s->s_count_prev);
     k_accumulate<<<blocks(np, 256), 256, 0, stream>>>(E.frame, acc, acc2, np, s->W, s->tile, s->tiles_x,
                                                       tiles ? s->tile_total : nullptr, s->cnt);
+    k_totals<<<1, 64, 0, stream>>>(s->cnt, s->tot);
     HIPCHK(hipGetLastError());
     return PT_OK;
 }
@@ -1014,7 +1040,11 @@ extern "C" pt_status pt_render_batch(pt_scene *s, const pt_iter_params *p, uint3
     std::vector<char> k((const char *)&key, (const char *)&key + sizeof(key));
     k.insert(k.end(), (const char *)&acc, (const char *)&acc + sizeof(acc));
     k.insert(k.end(), (const char *)&acc2, (const char *)&acc2 + sizeof(acc2));
+    k.insert(k.end(), (const char *)&s->gen, (const char *)&s->gen + sizeof(s->gen));
+    k.insert(k.end(), (const char *)&s->tune_budget, (const char *)&s->tune_budget + sizeof(s->tune_budget));
+    k.insert(k.end(), (const char *)&s->tune_gen_grid, (const char *)&s->tune_gen_grid + sizeof(s->tune_gen_grid));
     if (!s->gexec || k != s->gkey) {
+        ++s->n_captures;
         if (s->gexec) { HIPCHK(hipGraphExecDestroy(s->gexec)); s->gexec = nullptr; }
         if (!s->cap_stream) HIPCHK(hipStreamCreateWithFlags(&s->cap_stream, hipStreamNonBlocking));
         hipGraph_t g = nullptr;
@@ -1048,8 +1078,16 @@ extern "C" pt_status pt_reciprocal_estimate(pt_scene *s, const pt_recip_query *q
             return set_err(PT_EINVAL, "unknown estimator");
         if (q->estimator == PT_EST_BOOTH && !(q->booth_r > 0.0f)) return set_err(PT_EINVAL, "booth_r must be positive");
         if (!s) TRY(check_device());
-        k_recip_table<<<blocks(q->n_est, 256), 256, 0, stream>>>(q->f_dev, q->q_dev, q->n, q->B, q->n_est,
-                                                                 q->estimator, q->booth_r, q->seed, cap, out, ns);
+        // the cumulative sums of q in a stream-ordered workspace, released after the estimates
+        double *cdf = nullptr;
+        if (hipMallocAsync((void **)&cdf, sizeof(double) * ((size_t)q->n + 1), stream) != hipSuccess) {
+            (void)hipGetLastError();
+            return set_err(PT_ENOMEM, "workspace of %d doubles", q->n + 1);
+        }
+        k_table_cdf<<<1, 1024, 0, stream>>>(q->q_dev, q->n, cdf);
+        k_recip_table<<<blocks(q->n_est, 256), 256, 0, stream>>>(q->f_dev, cdf, q->n, q->B, q->n_est, q->estimator,
+                                                                 q->booth_r, q->seed, cap, out, ns);
+        HIPCHK(hipFreeAsync(cdf, stream));
     } else if (q->mode == PT_RECIP_CANDIDATE) {
         const pt_cand_desc *d = q->cand;
         if (!s || !d) return set_err(PT_EINVAL, "candidate mode needs a scene and a candidate");
@@ -1197,8 +1235,10 @@ extern "C" pt_status pt_render_scenes(pt_scene *const *scenes, const pt_iter_par
         k.insert(k.end(), (const char *)&b, (const char *)&b + sizeof(b));
         k.insert(k.end(), (const char *)&sp->tune_budget, (const char *)&sp->tune_budget + sizeof(uint32_t));
         k.insert(k.end(), (const char *)&sp->tune_gen_grid, (const char *)&sp->tune_gen_grid + sizeof(int));
+        k.insert(k.end(), (const char *)&sp->gen, (const char *)&sp->gen + sizeof(sp->gen));
     }
     if (!own->mgexec || k != own->mgkey) {
+        ++own->n_captures;
         if (own->mgexec) { HIPCHK(hipGraphExecDestroy(own->mgexec)); own->mgexec = nullptr; }
         if (!own->cap_stream) HIPCHK(hipStreamCreateWithFlags(&own->cap_stream, hipStreamNonBlocking));
         while ((int)own->mstreams.size() < n) {
@@ -1291,10 +1331,84 @@ extern "C" pt_status pt_autotune(pt_scene *s, const pt_iter_params *p, float *ac
     if (st != PT_OK) { s->tune_budget = b0; s->tune_gen_grid = g0; return st; }
     s->tune_budget = bb;
     s->tune_gen_grid = bg;
+    s->gen = next_generation();
     out->stage_a_budget = bb;
     out->round_grid = bg;
     out->ms_best = best;
     out->ms_previous = dflt;
     out->iterations_rendered = (uint32_t)used;
     return PT_OK;
+}
+
+extern "C" pt_status pt_scene_totals(pt_scene *s, pt_totals *out, int32_t reset, void *stream_)
+{
+    if (!s || !out) return set_err(PT_EINVAL, "null argument");
+    hipStream_t st = (hipStream_t)stream_;
+    unsigned long long t[TOT_COUNT];
+    HIPCHK(hipMemcpyAsync(t, s->tot, sizeof(t), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    out->iterations = (double)t[TOT_ITERS];
+    out->n_nan = (double)t[TOT_NAN];
+    out->n_recip_truncated = (double)t[TOT_TRUNC];
+    out->n_proxy_valid = (double)t[TOT_PROXY_VALID];
+    out->n_recip_samples = (double)t[TOT_RECIP_SAMPLES];
+    out->n_cand = (double)t[TOT_CAND];
+    out->captures = (double)s->n_captures;
+    out->bvh_stack_need = (double)s->stack_need;
+    out->bvh_depth = (double)s->bvh_depth;
+    if (reset) {
+        k_fill_u64<<<1, 64, 0, st>>>(s->tot, 0ull, TOT_COUNT);
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipStreamSynchronize(st));
+    }
+    return PT_OK;
+}
+
+extern "C" pt_status pt_selection_tables(pt_scene *s, int32_t which, int32_t n_rows, int32_t n_cols,
+                                         int32_t *n_nonempty, int32_t *nonempty, float *prob, int32_t *alias,
+                                         float *pmf, float *weights, void *stream_)
+{
+    if (!s || !n_nonempty || !nonempty || !prob || !alias || !pmf || !weights) return set_err(PT_EINVAL, "null argument");
+    if (!s->subspaces_ready) return set_err(PT_ESTATE, "pt_build_subspaces must run first");
+    if (which != 0 && which != 1) return set_err(PT_EINVAL, "which must be 0 (Gamma) or 1 (Q)");
+    const int R = s->n_eye, C = which == 0 ? s->n_spec : s->n_lsub;
+    if (n_rows != R || n_cols != C) return set_err(PT_EINVAL, "table is %d x %d, not %d x %d", R, C, n_rows, n_cols);
+    hipStream_t st = (hipStream_t)stream_;
+    const size_t n = (size_t)R * C;
+    HIPCHK(hipMemcpyAsync(n_nonempty, which == 0 ? s->n_ne : s->ln_ne, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(nonempty, which == 0 ? s->nonempty : s->lnonempty, C * sizeof(int), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(prob, which == 0 ? s->al_prob : s->q_alprob, n * sizeof(float), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(alias, which == 0 ? s->al_idx : s->q_alidx, n * sizeof(int), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(pmf, which == 0 ? s->al_pmf : s->q_alpmf, n * sizeof(float), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(weights, which == 0 ? s->gamma_frz : s->qfrz, n * sizeof(float), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    return PT_OK;
+}
+
+extern "C" pt_status pt_philox(const uint32_t *in_dev, int32_t n, uint32_t *out_dev, void *stream_)
+{
+    if (!in_dev || !out_dev || n < 0) return set_err(PT_EINVAL, "bad argument");
+    if (n == 0) return PT_OK;
+    TRY(check_device());
+    k_philox_hook<<<blocks(n, 256), 256, 0, (hipStream_t)stream_>>>(in_dev, n, out_dev);
+    HIPCHK(hipGetLastError());
+    return PT_OK;
+}
+
+extern "C" pt_status pt_bvh_stats(const float *tri, int32_t n_tri, int32_t *n_nodes, int32_t *stack_need,
+                                  int32_t *depth)
+{
+    if (!tri || n_tri <= 0 || !n_nodes || !stack_need || !depth) return set_err(PT_EINVAL, "bad argument");
+    try {
+        std::vector<BNode> nodes;
+        std::vector<int> order;
+        pt_build_bvh4(tri, n_tri, nodes, order);
+        int dp = 0;
+        *stack_need = pt_bvh4_stack_need(nodes, &dp);
+        *depth = dp;
+        *n_nodes = (int32_t)nodes.size();
+        return PT_OK;
+    } catch (const std::exception &e) {
+        return set_err(PT_ENOMEM, "host exception: %s", e.what());
+    }
 }

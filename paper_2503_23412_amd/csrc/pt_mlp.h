@@ -254,29 +254,43 @@ __global__ void k_mlp_select(EyeBuf E, SubDev D, const float *L, const float *bi
     Rng r = rng_make(seed, S_MLP, (uint32_t)__float_as_int(it.beta.w), (uint32_t)cnt[C_ITER], 1u);
     float mx = -3.0e38f;
     for (int j = 0; j < ne; ++j) mx = fmaxf(mx, l[D.nonempty[j]] + bias[D.nonempty[j]]);
-    float sum = 0.0f;
-    for (int j = 0; j < ne; ++j) sum += __expf(l[D.nonempty[j]] + bias[D.nonempty[j]] - mx);
-    const float u0 = rng_f(r), u1 = rng_f(r), u2 = rng_f(r);
+    // softmax terms summed in double: the inverse CDF below, with a 53-bit uniform, then draws
+    // S = nonempty[j] with probability e_j / sum to within 2^-52, the probability written out
+    double sum = 0.0;
+    for (int j = 0; j < ne; ++j) sum += (double)__expf(l[D.nonempty[j]] + bias[D.nonempty[j]] - mx);
+    const float u0 = rng_f(r);
+    const uint32_t xa = rng_u32(r), xb = rng_u32(r);
     int S;
     if (u0 < mix) {
-        const float target = u1 * sum;
-        float c = 0.0f;
-        S = D.nonempty[ne - 1];
+        const double u = (double)(((uint64_t)xa << 21) | (uint64_t)(xb >> 11)) * (1.0 / 9007199254740992.0);
+        const double target = u * sum;
+        double c = 0.0;
+        S = -1;
         for (int j = 0; j < ne; ++j) {
-            c += __expf(l[D.nonempty[j]] + bias[D.nonempty[j]] - mx);
-            if (target < c) { S = D.nonempty[j]; break; }
+            const double e = (double)__expf(l[D.nonempty[j]] + bias[D.nonempty[j]] - mx);
+            c += e;
+            if (e > 0.0) S = D.nonempty[j];
+            if (target < c) break;
         }
     } else if (gamma_on) {
-        const int j = min((int)(u1 * (float)ne), ne - 1);
         const size_t row = (size_t)T * D.n_spec;
-        S = D.nonempty[u2 < D.al_prob[row + j] ? j : D.al_idx[row + j]];
+        S = D.nonempty[alias_draw(D.al_prob + row, D.al_idx + row, ne, xa, (float)(xb >> 8) * (1.0f / 16777216.0f))];
     } else {
-        S = D.nonempty[min((int)(u1 * (float)ne), ne - 1)];
+        S = D.nonempty[index_of(xa, ne)];
     }
-    const float learned = __expf(l[S] + bias[S] - mx) / sum;
-    const float plain = gamma_on ? sel_prob(D, T, S) : 1.0f / (float)ne;
+    const double learned = (double)__expf(l[S] + bias[S] - mx) / sum;
+    double plain;
+    if (gamma_on) {
+        plain = (double)sel_prob(D, T, S);
+    } else {
+        int j = 0;
+        while (j < ne && D.nonempty[j] != S) ++j;
+        plain = index_prob(j, ne);
+    }
+    // the mixture weight the 24-bit draw u0 < mix realises
+    const double m = below_prob(mix);
     it.aux.z = __int_as_float(S);
-    it.aux.w = mix * learned + (1.0f - mix) * plain;
+    it.aux.w = (float)(m * learned + (1.0 - m) * plain);
 }
 
 // One training sample per valid proxy contribution of a learning iteration: the features of the

@@ -39,6 +39,7 @@ struct SubDev {
     const float *al_prob;    // [n_eye * n_spec]
     const int *al_idx;       // [n_eye * n_spec]
     const float *row_sum;    // [n_eye] sum of Gamma over non-empty S (0 = uniform row)
+    const float *al_pmf;     // [n_eye * n_spec] probability the alias row draws S (non-empty S only)
     const float *gamma;      // [n_eye * n_spec] frozen Gamma of this iteration
     float defensive;
     // frozen reciprocal statistics per (class, u, S): sum R, sum R^2, count
@@ -180,11 +181,33 @@ __global__ void k_scatter_sub(const Cand *cand, const uint32_t *final_, const un
     s_list[atomicAdd(s_fill + s, 1)] = (int)final_[i];
 }
 
+// Walker alias draw over the ne columns of a row: column index_of(x, ne), kept when the 24-bit
+// uniform u lies below its probability, else its alias
+__device__ __forceinline__ int alias_draw(const float *pr, const int *ai, int ne, uint32_t x, float u)
+{
+    const int c = index_of(x, ne);
+    return u < pr[c] ? c : ai[c];
+}
+// The probabilities with which alias_draw returns each column, from the table as stored: column
+// c is drawn with index_prob(c, ne) and kept with below_prob(pr[c]), else it gives ai[c]. These
+// are the selection probabilities the estimators divide by, so that the FP32 rounding of the
+// construction changes the sampling density and never the expectation. pm[ne] (double).
+__device__ __forceinline__ void alias_pmf(const float *pr, const int *ai, int ne, double *pm)
+{
+    for (int j = 0; j < ne; ++j) pm[j] = 0.0;
+    for (int c = 0; c < ne; ++c) {
+        const double w = index_prob(c, ne), st = below_prob(pr[c]);
+        pm[c] += w * st;
+        pm[ai[c]] += w * (1.0 - st);
+    }
+}
+
 // Gamma row T -> alias table over the non-empty subspaces (Vose's construction, one thread per
 // row, worklists in global scratch). Row probabilities: (1 - defensive) Gamma[T, S] / sum over
-// non-empty S + defensive / n_nonempty, or uniform when the row has no data.
+// non-empty S + defensive / n_nonempty, or uniform when the row has no data. pmf[T, S] receives
+// the probability the stored table realises for every non-empty S.
 __global__ void k_alias_rows(const float *gamma, int n_eye, int n_spec, const int *nonempty, const int *n_nonempty,
-                             float defensive, float *al_prob, int *al_idx, float *row_sum, int *scratch)
+                             float defensive, float *al_prob, int *al_idx, float *row_sum, float *pmf, int *scratch)
 {
     const int T = blockIdx.x * blockDim.x + threadIdx.x;
     if (T >= n_eye) return;
@@ -211,6 +234,11 @@ __global__ void k_alias_rows(const float *gamma, int n_eye, int n_spec, const in
     }
     while (nl > 0) { const int gg = large[--nl]; pr[gg] = 1.0f; ai[gg] = gg; }
     while (ns > 0) { const int l = small[--ns]; pr[l] = 1.0f; ai[l] = l; }
+    // the worklists are free now: the realised probabilities in their place
+    double *pm = (double *)small;
+    alias_pmf(pr, ai, ne, pm);
+    float *po = pmf + (size_t)T * n_spec;
+    for (int j = 0; j < ne; ++j) po[nonempty[j]] = (float)pm[j];
 }
 // The same tables with one wavefront per row: the row's probabilities and Vose's worklists in LDS
 // (16 bytes per column, dynamic), the sums and probabilities formed by the 64 lanes, the
@@ -218,7 +246,7 @@ __global__ void k_alias_rows(const float *gamma, int n_eye, int n_spec, const in
 #define ALIAS_LDS_COLS 2048
 __global__ void __launch_bounds__(64) k_alias_rows_wave(const float *gamma, int n_eye, int n_spec, const int *nonempty,
                                                         const int *n_nonempty, float defensive, float *al_prob,
-                                                        int *al_idx, float *row_sum)
+                                                        int *al_idx, float *row_sum, float *pmf)
 {
     extern __shared__ float alias_sh[];
     const int T = blockIdx.x, lane = threadIdx.x;
@@ -238,6 +266,9 @@ __global__ void __launch_bounds__(64) k_alias_rows_wave(const float *gamma, int 
         pr[j] = p * ne;
     }
     __syncthreads();
+    // the worklists (8 bytes per column from byte offset 8 n_spec) hold the realised
+    // probabilities once the construction is done
+    double *pm = (double *)small;
     if (lane == 0) {
         int ns = 0, nl = 0;
         for (int j = 0; j < ne; ++j) {
@@ -251,20 +282,21 @@ __global__ void __launch_bounds__(64) k_alias_rows_wave(const float *gamma, int 
         }
         while (nl > 0) { const int gg = large[--nl]; pr[gg] = 1.0f; ai[gg] = gg; }
         while (ns > 0) { const int l = small[--ns]; pr[l] = 1.0f; ai[l] = l; }
+        alias_pmf(pr, ai, ne, pm);
     }
     __syncthreads();
     float *po = al_prob + (size_t)T * n_spec;
     int *io = al_idx + (size_t)T * n_spec;
-    for (int j = lane; j < ne; j += 64) { po[j] = pr[j]; io[j] = ai[j]; }
+    float *qo = pmf + (size_t)T * n_spec;
+    for (int j = lane; j < ne; j += 64) { po[j] = pr[j]; io[j] = ai[j]; qo[nonempty[j]] = (float)pm[j]; }
 }
 
-// selection probability of subspace S from eye subspace T (the density the alias row samples)
+// selection probability of subspace S from eye subspace T: what the alias row realises
 __device__ __forceinline__ float sel_prob(const SubDev &D, int T, int S)
 {
     const int ne = *D.n_nonempty;
     if (ne == 0 || D.s_count[S] == 0) return 0.0f;
-    const float rs = D.row_sum[T];
-    return rs > 0.0f ? (1.0f - D.defensive) * D.gamma[(size_t)T * D.n_spec + S] / rs + D.defensive / ne : 1.0f / ne;
+    return D.al_pmf[(size_t)T * D.n_spec + S];
 }
 
 // selection probability of S from T under the frozen Gamma row (defensive mixture over the

@@ -33,7 +33,8 @@ PT_EST_BOOTH = 2
 EXPORTED = ["pt_scene_upload", "pt_scene_release", "pt_build_subspaces", "pt_render_iteration", "pt_render_batch",
             "pt_render_scenes", "pt_autotune",
             "pt_mlp_param_count", "pt_mlp_set_params", "pt_mlp_get_params", "pt_mlp_forward", "pt_mlp_train_step",
-            "pt_reciprocal_estimate", "pt_resolve_image", "pt_trace_closest", "pt_last_error"]
+            "pt_reciprocal_estimate", "pt_resolve_image", "pt_trace_closest", "pt_scene_totals",
+            "pt_selection_tables", "pt_philox", "pt_bvh_stats", "pt_last_error"]
 
 
 class SceneDesc(ctypes.Structure):
@@ -83,6 +84,12 @@ class TuneResult(ctypes.Structure):
                 ("ms_previous", ctypes.c_float), ("iterations_rendered", ctypes.c_uint32)]
 
 
+class Totals(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_double) for n in ("iterations", "n_nan", "n_recip_truncated", "n_proxy_valid",
+                                               "n_recip_samples", "n_cand", "captures", "bvh_stack_need",
+                                               "bvh_depth")]
+
+
 class CandDesc(ctypes.Structure):
     _fields_ = [("cls", ctypes.c_int32), ("u", ctypes.c_int32), ("v", ctypes.c_float * 3), ("v_prim", ctypes.c_int32),
                 ("hc", ctypes.c_float * 3), ("hc_prim", ctypes.c_int32), ("hc_b1", ctypes.c_float),
@@ -123,6 +130,10 @@ def lib():
         L.pt_mlp_get_params.argtypes = [P, P, I, P]
         L.pt_mlp_forward.argtypes = [P, P, I, P, P]
         L.pt_mlp_train_step.argtypes = [P, P, P, P, I, ctypes.c_float, P, P]
+        L.pt_scene_totals.argtypes = [P, ctypes.POINTER(Totals), I, P]
+        L.pt_selection_tables.argtypes = [P, I, I, I, P, P, P, P, P, P, P]
+        L.pt_philox.argtypes = [P, I, P, P]
+        L.pt_bvh_stats.argtypes = [P, I, P, P, P]
         L.pt_last_error.restype = ctypes.c_char_p
         for name in EXPORTED:
             if name == "pt_last_error":
@@ -250,6 +261,25 @@ class Scene:
                                        g.ctypes.data if g is not None else None, _stream(stream)))
         return g
 
+    def totals(self, reset=False, stream=None):
+        """Running totals over every iteration rendered so far (synchronises)."""
+        t = Totals()
+        _check(lib().pt_scene_totals(self.h, ctypes.byref(t), int(bool(reset)), _stream(stream)))
+        return {k: getattr(t, k) for k, _ in t._fields_}
+
+    def selection_tables(self, which, n_rows, n_cols, stream=None):
+        """The latest iteration's alias rows (which 0: Gamma, 1: Q) as host arrays."""
+        ne = ctypes.c_int32()
+        nonempty = np.zeros(n_cols, np.int32)
+        prob = np.zeros((n_rows, n_cols), np.float32)
+        alias = np.zeros((n_rows, n_cols), np.int32)
+        pmf = np.zeros((n_rows, n_cols), np.float32)
+        w = np.zeros((n_rows, n_cols), np.float32)
+        _check(lib().pt_selection_tables(self.h, int(which), int(n_rows), int(n_cols), ctypes.byref(ne),
+                                         nonempty.ctypes.data, prob.ctypes.data, alias.ctypes.data, pmf.ctypes.data,
+                                         w.ctypes.data, _stream(stream)))
+        return dict(n_nonempty=ne.value, nonempty=nonempty, prob=prob, alias=alias, pmf=pmf, weights=w)
+
     def trace_closest(self, rays, t_out, prim_out, stream=None):
         _check(lib().pt_trace_closest(self.h, _ptr(rays), int(rays.shape[0]), _ptr(t_out), _ptr(prim_out),
                                       _stream(stream)))
@@ -261,6 +291,19 @@ def reciprocal_table(f, q, B, n_est, out, nsamples, estimator=PT_EST_ITILDE, see
     qq = RecipQuery(0, int(f.shape[0]), f.data_ptr(), q.data_ptr(), float(B), int(n_est), int(estimator), int(seed),
                     int(cap), None, 0, None, float(booth_r))
     _check(lib().pt_reciprocal_estimate(None, ctypes.byref(qq), _ptr(out), _ptr(nsamples), _stream(stream)))
+
+
+def philox(inp, out, stream=None):
+    """inp: int32/uint32 device tensor [n, 6] (counter 0..3, key 0..1); out: [n, 4] (device)."""
+    _check(lib().pt_philox(_ptr(inp), int(inp.shape[0]), _ptr(out), _stream(stream)))
+
+
+def bvh_stats(tri):
+    """Host-only: (nodes, worst-case traversal stack, depth) of the 4-wide BVH of tri [n, 9]."""
+    t = np.ascontiguousarray(tri, np.float32).reshape(-1, 9)
+    a, b, c = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    _check(lib().pt_bvh_stats(t.ctypes.data, int(t.shape[0]), ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
+    return a.value, b.value, c.value
 
 
 def render_scenes(scenes, accums, accums_sq, n_iter, params, stream=None):

@@ -10,7 +10,7 @@ so O1 at any affordable sample count misreports its own error there. O3 reaches 
 by light tracing and vertex connections. Output per scene: per-pixel mean of the per-iteration
 pixel values, the variance of that mean, and the number of iterations, as a compressed .npz.
 
-usage: python tests/golden/make_references.py [cfg0|cfg1_128|all] [spp]
+usage: python tests/golden/make_references.py [cfg0|cfg1_128|glass_furnace|all] [spp] [threads]
 """
 import os
 import sys
@@ -28,12 +28,17 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 
 REFS = {
     # name: (scene builder, max depth, default spp, oracle method, file tag)
-    "cfg0": (lambda: scenes.cornell_glass(64, 64), 8, 65536, 0, "o1"),
+    "cfg0": (lambda: scenes.cornell_glass(64, 64), 8, 262144, 0, "o1"),
     "cfg1_128": (lambda: scenes.projector(128, 128), 12, 8192, 2, "o3"),
+    # a lossless glass sphere (IOR 1.5) in an emitting spherical enclosure of albedo 0.5, L_e = 1,
+    # depth 120: the closed form L_e / (1 - a) = 2 less the paths the depth limit cuts, which
+    # the tessellated sphere makes visible per pixel
+    "glass_furnace": (lambda: scenes.furnace(albedo=0.5, le=1.0, glass_sphere=True, width=64, height=64,
+                                             sphere_subdiv=2, enclosure="sphere"), 120, 4096, 0, "o1"),
 }
 
 
-def make(name, spp=None, batch=256):
+def make(name, spp=None, batch=256, threads=None):
     build, depth, default, method, tag = REFS[name]
     spp = spp or default
     S = O.Scene(build())
@@ -42,7 +47,7 @@ def make(name, spp=None, batch=256):
     t0 = time.time()
     for first in range(0, spp, batch):
         n = min(batch, spp - first)
-        a, b, _ = S.render(method=method, n_iter=n, first_iter=first, max_depth=depth, seed=12345)
+        a, b, _ = S.render(method=method, n_iter=n, first_iter=first, max_depth=depth, seed=12345, threads=threads)
         s += a
         s2 += b
         print(f"{name}: {first + n}/{spp} spp, {time.time() - t0:.0f} s", flush=True)
@@ -56,6 +61,7 @@ def make(name, spp=None, batch=256):
 
 if __name__ == "__main__":
     which = sys.argv[1] if len(sys.argv) > 1 else "all"
-    spp = int(sys.argv[2]) if len(sys.argv) > 2 else None
+    spp = int(sys.argv[2]) if len(sys.argv) > 2 and int(sys.argv[2]) > 0 else None
+    threads = int(sys.argv[3]) if len(sys.argv) > 3 else None
     for name in (REFS if which == "all" else [which]):
-        make(name, spp)
+        make(name, spp, threads=threads)

@@ -35,6 +35,7 @@ def test_struct_sizes_match_header(ptlib):
     assert ctypes.sizeof(ptlib.IterParams) == 18 * 4
     assert ctypes.sizeof(ptlib.IterStats) == (29 + 25) * 8
     assert ctypes.sizeof(ptlib.SubspaceParams) == 6 * 4
+    assert ctypes.sizeof(ptlib.Totals) == 9 * 8
 
 
 def test_invalid_arguments_rejected_without_device(ptlib):
@@ -63,3 +64,20 @@ def test_invalid_arguments_rejected_without_device(ptlib):
     assert L.pt_reciprocal_estimate(None, None, None, None, None) == -1
     assert L.pt_resolve_image(None, None, 1, None, None) == -1
     assert L.pt_scene_release(None) == 0
+
+
+def test_bvh_stack_need_fits_the_kernels(ptlib):
+    """The host BVH build (what pt_scene_upload runs) for the config scenes and a 1.4 M-triangle
+    variant of the glossy scene: worst-case traversal stacks within the kernels' 48 entries, and
+    the need at least the depth less one on these scenes (every level of a deep path of inner
+    nodes has siblings there)."""
+    from synth import scenes
+    cases = [scenes.cornell_glass(8, 8), scenes.projector(8, 8), scenes.glossy_procedural(8, 8),
+             scenes.glossy_procedural(8, 8, target_tris=2_000_000)]
+    for sc in cases:
+        nodes, need, depth = ptlib.bvh_stats(sc["tri"])
+        n = sc["tri"].shape[0]
+        assert n / 16 <= nodes <= n, (n, nodes)
+        assert depth - 1 <= need <= 48, (n, need, depth)
+    # one triangle: a single node with one leaf child needs no stack
+    assert ptlib.bvh_stats(np.array([[0, 0, 0, 1, 0, 0, 0, 1, 0]], np.float32)) == (1, 0, 1)

@@ -65,6 +65,35 @@ def _render(gpu, sc, N, max_light=1024, subspaces=(8, 8), it_means=None, **param
     return m, v, tot
 
 
+def _render_batches(gpu, sc, n_batches, per_batch, max_light=1024, subspaces=(8, 8), **params):
+    """n_batches x per_batch iterations replayed from one captured graph (pt_render_batch); per-pixel
+    mean, the variance of that mean from the spread of the batch means (batch means: robust to
+    heavy-tailed per-iteration values), the per-batch image means and the scene's running totals."""
+    torch, pt = gpu
+    W, H = sc["width"], sc["height"]
+    S = pt.Scene(sc, max_light_paths=max_light)
+    S.build_subspaces(n_eye=subspaces[0], n_spec=subspaces[1])
+    acc = torch.zeros(W * H * 3, device="cuda")
+    s1 = torch.zeros(W * H * 3, dtype=torch.float64, device="cuda")
+    s2 = torch.zeros_like(s1)
+    img = []
+    for b in range(n_batches):
+        acc.zero_()
+        S.render_batch(acc, None, per_batch, iteration=b * per_batch, **params)
+        bm = acc.double() / per_batch
+        s1 += bm
+        s2 += bm * bm
+        img.append(bm.mean())
+        if b % 16 == 15:
+            say(f"  batch {b + 1}/{n_batches}")
+    torch.cuda.synchronize()
+    tot = S.totals()
+    S.release()
+    m = (s1 / n_batches).cpu().numpy().reshape(H, W, 3)
+    v = np.maximum((s2 / n_batches).cpu().numpy().reshape(H, W, 3) - m * m, 0) / (n_batches - 1)
+    return m, v, np.array([float(x) for x in img]), tot
+
+
 def _furnace_ok(m, v, expect, tag):
     """Per-pixel bar of the grey furnaces: at least 99.9 % of pixels within 4 standard errors of
     the closed form. The three channels of a grey furnace carry the same value, so pixels (not
@@ -160,6 +189,135 @@ def test_booth_table_matches_its_definition(gpu):
     assert np.allclose(est, est_of[L - 1], rtol=1e-4)
     EL = (p_of * np.arange(1, len(p_of) + 1)).sum()
     assert abs(L.mean() - EL) < 5 * L.std() / math.sqrt(n_est)
+
+
+# ------------------------------------------------------------------------------ generator, selection, boundary
+def test_device_philox_known_answers(gpu):
+    """The kernels' Philox4x32-10 against the generator's published known-answer vectors."""
+    torch, pt = gpu
+    rows = [ln.split() for ln in open(os.path.join(GOLD, "philox4x32_10_kat.txt")) if ln.strip() and ln[0] != "#"]
+    a = np.array([[int(x, 16) for x in r] for r in rows], dtype=np.uint32)
+    inp = torch.from_numpy(a[:, :6].copy().view(np.int32)).cuda()
+    out = torch.zeros((len(a), 4), dtype=torch.int32, device="cuda")
+    pt.philox(inp, out)
+    torch.cuda.synchronize()
+    assert np.array_equal(out.cpu().numpy().view(np.uint32), a[:, 6:])
+
+
+def _alias_realised(prob, alias, ne):
+    """Probabilities with which a Walker alias row returns each of its ne columns under the
+    kernels' sampler: column floor(x ne / 2^32) of a uniform 32-bit x, kept when a uniform 24-bit
+    fraction lies below its probability, else its alias. Exact integer counts over the draws."""
+    out = np.zeros(ne)
+    for c in range(ne):
+        w = ((((c + 1) << 32) + ne - 1) // ne - ((c << 32) + ne - 1) // ne) / 2.0 ** 32
+        p = float(prob[c])
+        st = 1.0 if p >= 1.0 else (0.0 if p <= 0.0 else math.ceil(p * 2.0 ** 24) / 2.0 ** 24)
+        out[c] += w * st
+        out[int(alias[c])] += w * (1.0 - st)
+    return out
+
+
+def test_selection_tables_realise_their_probabilities(gpu):
+    """Pin of the alias tables: after a few learning iterations, every Gamma row (incomplete sub-path
+    selection, Section 5.6) and every row Q of the light-vertex connections, read back from the
+    device and enumerated on the host, realises the probabilities the estimators divide by (within
+    1e-6), and these are the learned rows mixed with the defensive fraction (within the FP32
+    rounding of the table construction)."""
+    from synth import scenes
+    torch, pt = gpu
+    sc = scenes.cornell_glass(32, 32)
+    S = pt.Scene(sc, max_light_paths=4096)
+    n_eye, n_spec = 16, 24
+    S.build_subspaces(n_eye=n_eye, n_spec=n_spec, n_light=20)
+    acc = torch.zeros(32 * 32 * 3, device="cuda")
+    flags = (pt.PT_FLAG_NEE | pt.PT_FLAG_PROXY | pt.PT_FLAG_MIS | pt.PT_FLAG_GAMMA | pt.PT_FLAG_SPC | pt.PT_FLAG_LT)
+    for k in range(12):
+        S.render_iteration(acc, None, iteration=k, max_depth=8, n_light=4096, cand_cap=400, flags=flags)
+    torch.cuda.synchronize()
+    for which, n_cols in ((0, n_spec), (1, 20)):
+        t = S.selection_tables(which, n_eye, n_cols)
+        ne = t["n_nonempty"]
+        ids = t["nonempty"][:ne]
+        assert 2 <= ne <= n_cols and len(set(ids.tolist())) == ne
+        learned_rows = 0
+        for T in range(n_eye):
+            real = _alias_realised(t["prob"][T, :ne], t["alias"][T, :ne], ne)
+            assert abs(real.sum() - 1.0) < 1e-12
+            dev = t["pmf"][T, ids].astype(np.float64)
+            assert np.max(np.abs(dev - real) / real) < 1e-6, (which, T)
+            w = t["weights"][T, ids].astype(np.float64)
+            tgt = (0.9 * w / w.sum() + 0.1 / ne) if w.sum() > 0 else np.full(ne, 1.0 / ne)
+            learned_rows += w.sum() > 0
+            assert np.max(np.abs(real - tgt) / tgt) < 1e-4, (which, T, np.max(np.abs(real - tgt) / tgt))
+        say(f"selection table {which}: {ne} non-empty columns, {learned_rows} learned rows")
+        assert learned_rows > 0
+    S.release()
+
+
+def test_resolve_and_call_order(gpu):
+    """pt_resolve_image on the device (accum / n, also in place), PT_ESTATE for a render before
+    pt_build_subspaces, PT_EINVAL for n_iter = 0, and the running totals."""
+    from synth import scenes
+    torch, pt = gpu
+    sc = scenes.furnace(albedo=0.5, le=1.0, width=16, height=16)
+    S = pt.Scene(sc, max_light_paths=256)
+    acc = torch.zeros(16 * 16 * 3, device="cuda")
+    with pytest.raises(pt.PTError) as e:
+        S.render_iteration(acc, None, iteration=0, max_depth=4, n_light=256, cand_cap=64)
+    assert e.value.code == -4
+    S.build_subspaces(n_eye=8, n_spec=8)
+    for k in range(8):
+        S.render_iteration(acc, None, iteration=k, max_depth=4, n_light=256, cand_cap=64)
+    out = torch.empty_like(acc)
+    S.resolve(acc, 8, out)
+    torch.cuda.synchronize()
+    assert torch.equal(out, acc * 0.125)
+    assert 0.5 < float(out.mean()) < 2.0
+    with pytest.raises(pt.PTError) as e:
+        S.resolve(acc, 0, out)
+    assert e.value.code == -1
+    ref = acc * np.float32(1.0 / 3.0)
+    S.resolve(acc, 3, acc)
+    torch.cuda.synchronize()
+    assert torch.equal(acc, ref)
+    tot = S.totals()
+    assert tot["iterations"] == 8 and tot["n_nan"] == 0 and tot["bvh_depth"] >= 1 and tot["bvh_stack_need"] >= 0
+    S.release()
+
+
+def test_graph_recaptured_when_a_scene_changes(gpu):
+    """Captured iterations are replayed only on the scene state they were captured for: the graph of
+    pt_render_batch is reused while nothing changes and captured again after pt_build_subspaces;
+    the multi-scene graph is captured again when a scene of the batch is released and another
+    uploaded in its place (a new state generation, whatever its host address)."""
+    from synth import scenes
+    torch, pt = gpu
+    prm = dict(max_depth=4, n_light=256, cand_cap=64, flags=pt.PT_FLAG_NEE | pt.PT_FLAG_PROXY)
+    A = pt.Scene(scenes.furnace(albedo=0.5, le=1.0, width=16, height=16), max_light_paths=256)
+    A.build_subspaces(n_eye=8, n_spec=8)
+    acc = torch.zeros(16 * 16 * 3, device="cuda")
+    A.render_batch(acc, None, 4, iteration=0, **prm)
+    A.render_batch(acc, None, 4, iteration=4, **prm)
+    assert A.totals()["captures"] == 1
+    A.build_subspaces(n_eye=8, n_spec=8)
+    A.render_batch(acc, None, 4, iteration=8, **prm)
+    assert A.totals()["captures"] == 2
+    B = pt.Scene(scenes.furnace(albedo=0.3, le=1.0, width=16, height=16), max_light_paths=256)
+    B.build_subspaces(n_eye=8, n_spec=8)
+    accb = torch.zeros_like(acc)
+    pt.render_scenes([A, B], [acc, accb], None, 4, [dict(prm, iteration=12), dict(prm, iteration=0)])
+    pt.render_scenes([A, B], [acc, accb], None, 4, [dict(prm, iteration=16), dict(prm, iteration=4)])
+    assert A.totals()["captures"] == 3
+    B.release()
+    C = pt.Scene(scenes.furnace(albedo=0.3, le=1.0, width=16, height=16), max_light_paths=256)
+    C.build_subspaces(n_eye=8, n_spec=8)
+    pt.render_scenes([A, C], [acc, accb], None, 4, [dict(prm, iteration=20), dict(prm, iteration=0)])
+    torch.cuda.synchronize()
+    assert A.totals()["captures"] == 4
+    assert C.totals()["iterations"] == 4 and A.totals()["iterations"] == 24
+    C.release()
+    A.release()
 
 
 # ------------------------------------------------------------------------------ traversal
@@ -268,62 +426,66 @@ def test_multi_scene_graph_and_autotune(gpu):
     sc.release()
 
 
+def _glass_ref():
+    ref = np.load(os.path.join(GOLD, "glass_furnace_o1_ref.npz"))
+    mo, vo = ref["mean"][..., 0], ref["var_mean"][..., 0]
+    # O1's pixels are independent: the standard error of its image mean follows from theirs
+    return mo, vo, float(mo.mean()), float(np.sqrt(vo.sum()) / mo.size)
+
+
 @pytest.mark.parametrize("mode", ["mis", "partition"])
 def test_glass_furnace_through_proxy(gpu, mode):
-    """A lossless glass sphere in an emitting spherical enclosure, depth 120, with the proxy under
-    MIS (with Gamma) or alone on its class (partition). All pixels of an iteration draw on the
-    same few hundred candidates and reciprocal estimates, so their errors are correlated: the
-    standard error of the image mean from the spread of per-iteration image means is 4-6 times
-    the independent-pixel one, and the count of pixels beyond 4 standard errors varies from 0 to
-    48 of 9,216 between runs of an unbiased render. The check of unbiasedness is therefore the
-    image mean against the depth-120 value of the oracle (O1: 1.99969 +- 0.00026, the closed form
-    2 less the paths cut by the depth limit); per pixel, gross errors are excluded (at least 99 %
-    within 4 standard errors, none beyond 7)."""
+    """A lossless glass sphere in an emitting spherical enclosure (albedo 0.5, L_e = 1), depth 120,
+    with the proxy under MIS (with Gamma) or alone on its class (partition), against the oracle's
+    per-pixel depth-120 reference (O1, tests/golden/glass_furnace_o1_ref.npz, written by
+    make_references.py). The pixels of one iteration share a few hundred candidates and their
+    reciprocal estimates, and single iterations are heavy-tailed, so the GPU's per-pixel standard
+    errors come from 64 batch means of 64 iterations each. Bar: at least 99.9 % of pixels within 4
+    combined standard errors, and the image mean within 4 combined standard errors."""
     from synth import scenes
     torch, pt = gpu
-    a, K = 0.5, 120
-    sc = scenes.furnace(albedo=a, le=1.0, glass_sphere=True, width=96, height=96, sphere_subdiv=2,
+    K = 120
+    sc = scenes.furnace(albedo=0.5, le=1.0, glass_sphere=True, width=64, height=64, sphere_subdiv=2,
                         enclosure="sphere")
     say(f"glass furnace {mode}")
     flags = pt.PT_FLAG_NEE | pt.PT_FLAG_PROXY | ((pt.PT_FLAG_MIS | pt.PT_FLAG_GAMMA) if mode == "mis" else 0)
-    its = []
-    m, v, st = _render(gpu, sc, 1024, it_means=its, max_depth=K, n_light=1024, cand_cap=128, flags=flags)
-    expect, expect_se = 1.99969, 0.00026
-    se = float(np.std(its, ddof=1) / np.sqrt(len(its)))
-    zm = (m.mean() - expect) / math.hypot(se, expect_se)
-    z = (m[..., 0] - (1 - a ** K) / (1 - a)) / np.sqrt(v[..., 0] + 1e-30)
+    m, v, img, tot = _render_batches(gpu, sc, 64, 64, max_depth=K, n_light=1024, cand_cap=128, flags=flags)
+    mo, vo, omean, ose = _glass_ref()
+    se = float(np.std(img, ddof=1) / np.sqrt(len(img)))
+    zm = (m.mean() - omean) / math.hypot(se, ose)
+    z = (m[..., 0] - mo) / np.sqrt(v[..., 0] + vo + 1e-30)
     frac = (np.abs(z) < 4).mean()
-    say(f"glass furnace {mode}: mean {m.mean():.5f} +- {se:.5f} (oracle {expect}) z {zm:.2f}; per pixel frac |z|<4 "
-        f"{frac:.5f} max|z| {np.abs(z).max():.2f}")
-    assert abs(zm) < 4.5
-    assert frac >= 0.99 and np.abs(z).max() < 7
-    assert st["n_proxy_valid"] > 0 and st["n_recip_truncated"] == 0 and st["n_nan"] == 0
+    say(f"glass furnace {mode}: mean {m.mean():.5f} +- {se:.5f} (oracle {omean:.5f} +- {ose:.5f}) z {zm:.2f}; per "
+        f"pixel frac |z|<4 {frac:.5f} max|z| {np.abs(z).max():.2f} z std {z.std():.3f}; totals {tot}")
+    assert abs(zm) < 4
+    assert frac >= 0.999
+    assert tot["n_proxy_valid"] > 0 and tot["n_recip_truncated"] == 0 and tot["n_nan"] == 0
 
 
 def test_booth_roulette_glass_furnace(gpu):
     """The reciprocal chains on Booth's roulette (booth_r = 0.05) instead of the RRS function:
-    the glass furnace through the proxy under MIS, depth 120, against the oracle's depth-120 value
-    (O1: 1.99969 +- 0.00026). Booth's estimates have infinite variance once the roulette binds,
-    so the image mean with the per-iteration standard error is the check, and per pixel only
-    gross errors are excluded."""
+    the glass furnace through the proxy under MIS, depth 120, against the oracle's per-pixel
+    depth-120 reference. Booth's estimates have infinite variance once the roulette binds (the
+    terms of a chain fall while the roulette keeps it alive with weights that grow), so only the
+    image mean with its batch-means standard error is the check here, and per pixel gross
+    errors are excluded (no pixel beyond 7 combined standard errors)."""
     from synth import scenes
     torch, pt = gpu
-    sc = scenes.furnace(albedo=0.5, le=1.0, glass_sphere=True, width=96, height=96, sphere_subdiv=2,
+    sc = scenes.furnace(albedo=0.5, le=1.0, glass_sphere=True, width=64, height=64, sphere_subdiv=2,
                         enclosure="sphere")
     flags = pt.PT_FLAG_NEE | pt.PT_FLAG_PROXY | pt.PT_FLAG_MIS | pt.PT_FLAG_GAMMA | pt.PT_FLAG_BOOTH
     say("booth glass furnace")
-    its = []
-    m, v, st = _render(gpu, sc, 1024, it_means=its, max_depth=120, n_light=1024, cand_cap=128, flags=flags,
-                       booth_r=0.05)
-    expect, expect_se = 1.99969, 0.00026
-    se = float(np.std(its, ddof=1) / np.sqrt(len(its)))
-    zm = (m.mean() - expect) / math.hypot(se, expect_se)
-    z = (m[..., 0] - 2.0) / np.sqrt(v[..., 0] + 1e-30)
+    m, v, img, tot = _render_batches(gpu, sc, 32, 32, max_depth=120, n_light=1024, cand_cap=128, flags=flags,
+                                     booth_r=0.05)
+    mo, vo, omean, ose = _glass_ref()
+    se = float(np.std(img, ddof=1) / np.sqrt(len(img)))
+    zm = (m.mean() - omean) / math.hypot(se, ose)
+    z = (m[..., 0] - mo) / np.sqrt(v[..., 0] + vo + 1e-30)
     say(f"booth glass furnace: mean {m.mean():.5f} +- {se:.5f} z {zm:.2f}; frac |z|<4 {(np.abs(z) < 4).mean():.5f} "
-        f"recip samples {st['n_recip_samples']:.0f} proxy valid {st['n_proxy_valid']:.0f}")
-    assert abs(zm) < 4.5
-    assert (np.abs(z) < 4).mean() >= 0.99 and np.abs(z).max() < 7
-    assert st["n_nan"] == 0 and st["n_proxy_valid"] > 0 and st["n_recip_samples"] > 0
+        f"max|z| {np.abs(z).max():.2f}; totals {tot}")
+    assert abs(zm) < 4
+    assert np.abs(z).max() < 7
+    assert tot["n_nan"] == 0 and tot["n_proxy_valid"] > 0 and tot["n_recip_samples"] > 0
 
 
 # ------------------------------------------------------------------------------ proxy class
@@ -375,7 +537,7 @@ def _agree(a, b, k=4.0):
     return abs(a.mean() - b.mean()) < k * math.sqrt(a.var() / len(a) + b.var() / len(b))
 
 
-@pytest.mark.parametrize("case", ["A1", "A2", "A3", "A4", "B1", "B2", "B3"])
+@pytest.mark.parametrize("case", ["A1", "A2", "A3", "A4", "B1", "B2", "B3", "B4"])
 def test_candidate_density_and_reciprocal_match_oracle(gpu, oracle, case):
     """Per-candidate plain Monte Carlo estimates of P and RRS estimates of 1/P on a glass sphere
     inside an emitting enclosure (classes A and B, u = 1..4): GPU vs oracle."""
@@ -408,31 +570,53 @@ def test_candidate_probe_closed_forms(gpu, oracle):
 
 
 # ------------------------------------------------------------------------------ config 0 parity
-@pytest.mark.timeout(900)
-def test_zz_config0_parity_with_oracle_reference(gpu):
-    """Config 0 (64 x 64 glass Cornell box, depth 8), every strategy of the method, vs the stored O1
-    reference image."""
+CFG0_FLAGS = ("NEE", "PROXY", "MIS", "GAMMA", "TILES", "SPC", "LT")
+
+
+def _cfg0_parity(gpu, extra_flags=(), tag="config 0", **extra):
+    """Config 0 (64 x 64 glass Cornell box, depth 8, M = 4,096, cap 400, 64 / 64 subspaces) at
+    65,536 iterations (64 batch means of 1,024) against the stored O1 reference (262,144 spp)."""
     from synth import scenes
     torch, pt = gpu
     ref = np.load(os.path.join(GOLD, "cfg0_o1_ref.npz"))
-    N = 4096
-    say(f"config 0 parity, {N} spp")
-    flags = (pt.PT_FLAG_NEE | pt.PT_FLAG_PROXY | pt.PT_FLAG_MIS | pt.PT_FLAG_GAMMA | pt.PT_FLAG_TILES |
-             pt.PT_FLAG_SPC | pt.PT_FLAG_LT)
-    m, v, st = _render(gpu, scenes.cornell_glass(64, 64), N, max_light=4096, subspaces=(64, 64), max_depth=8,
-                       n_light=4096, cand_cap=400, flags=flags)
+    flags = 0
+    for f in CFG0_FLAGS + tuple(extra_flags):
+        flags |= getattr(pt, "PT_FLAG_" + f)
+    say(f"{tag}: 65,536 iterations")
+    m, v, img, tot = _render_batches(gpu, scenes.cornell_glass(64, 64), 64, 1024, max_light=4096,
+                                     subspaces=(64, 64), max_depth=8, n_light=4096, cand_cap=400, flags=flags, **extra)
     mo, vo = ref["mean"], ref["var_mean"]
     z = (m - mo) / np.sqrt(v + vo + 1e-30)
     frac = (np.abs(z) < 4).mean()
     rel_l1 = np.abs(m - mo).sum() / mo.sum()
     floor = (np.sqrt(2 / np.pi) * np.sqrt(v + vo)).sum() / mo.sum()
-    say(f"config 0: frac |z|<4 {frac:.5f} max|z| {np.abs(z).max():.2f} relL1 {rel_l1:.5f} noise floor {floor:.5f}")
+    say(f"{tag}: frac |z|<4 {frac:.5f} max|z| {np.abs(z).max():.2f} mean z {z.mean():.4f} relL1 {rel_l1:.5f} "
+        f"noise floor {floor:.5f} (reference {int(ref['spp'])} spp); totals {tot}")
+    return frac, rel_l1, floor, tot
+
+
+@pytest.mark.timeout(900)
+def test_zz_config0_parity_with_oracle_reference(gpu):
+    """Config 0, every strategy of the method: per-pixel means within 4 combined standard errors on
+    at least 99.9 % of pixel channels, and whole-image relative L1 below 0.5 %."""
+    frac, rel_l1, floor, tot = _cfg0_parity(gpu)
     assert frac >= 0.999
-    # whole-image relative L1 must sit at the noise floor that the per-pixel errors predict
-    assert rel_l1 < 1.1 * floor + 0.005
-    assert st["n_nan"] == 0 and st["n_recip_truncated"] == 0
+    assert rel_l1 < 0.005
+    assert tot["iterations"] == 65536 and tot["n_nan"] == 0 and tot["n_recip_truncated"] == 0
 
 
+
+
+@pytest.mark.timeout(900)
+def test_zz_config0_parity_with_learned_selection(gpu):
+    """Config 0 with the learned selection on (PT_FLAG_MLP: the network's softmax, mixed with 10 %
+    of the Gamma row, picks the specular subspace; trained online by the library's own kernels
+    during the first 512 iterations), at the bar of the plain method."""
+    frac, rel_l1, floor, tot = _cfg0_parity(gpu, extra_flags=("MLP",), tag="config 0 learned", train_iters=512,
+                                            mlp_mix=0.9, mlp_lr=1e-3)
+    assert frac >= 0.999
+    assert rel_l1 < 0.005
+    assert tot["n_nan"] == 0 and tot["n_recip_truncated"] == 0
 
 
 def test_zz_config1_128_parity_with_oracle_reference(gpu):
@@ -455,10 +639,13 @@ def test_zz_config1_128_parity_with_oracle_reference(gpu):
     frac = (np.abs(z) < 4).mean()
     rel_l1 = np.abs(m - mo).sum() / mo.sum()
     floor = (np.sqrt(2 / np.pi) * np.sqrt(v + vo)).sum() / mo.sum()
-    say(f"config 1 (128): frac |z|<4 {frac:.5f} max|z| {np.abs(z).max():.2f} relL1 {rel_l1:.5f} noise floor {floor:.5f} "
-        f"connections {st['n_connections']:.0f} proxy valid {st['n_proxy_valid']:.0f}")
+    say(f"config 1 (128): frac |z|<4 {frac:.5f} max|z| {np.abs(z).max():.2f} mean z {z.mean():.4f} relL1 {rel_l1:.5f} "
+        f"noise floor {floor:.5f} connections {st['n_connections']:.0f} proxy valid {st['n_proxy_valid']:.0f}")
     assert frac >= 0.999
-    assert rel_l1 < 1.1 * floor + 0.005
+    # the whole-image relative L1 of two unbiased images is the noise floor the per-pixel errors
+    # predict (a sum over 49,152 pixel channels, so it concentrates within a few per cent of it);
+    # a bias adds to it
+    assert rel_l1 < 1.1 * floor
     assert st["n_nan"] == 0 and st["n_recip_truncated"] == 0
 
 
@@ -489,17 +676,18 @@ def test_zz_config1_full_size_block_means_match_oracle_reference(gpu):
     k0 = S.autotune(img, None, iteration=0, **params)["iterations_rendered"]
     s1 = torch.zeros(128 * 128 * 3, dtype=torch.float64, device="cuda")
     s2 = torch.zeros_like(s1)
-    nan = trunc = 0.0
+    S.totals(reset=True)
     for k in range(N):
         img.zero_()
-        st = S.render_iteration(img, None, stats=(k % 64 == 0 or k == N - 1), iteration=k0 + k, **params)
+        S.render_iteration(img, None, iteration=k0 + k, **params)
         b = img.view(128, 4, 128, 4, 3).double().mean(dim=(1, 3)).reshape(-1)
         s1 += b
         s2 += b * b
-        if st:
-            nan += st["n_nan"]
-            trunc += st["n_recip_truncated"]
+        if k % 64 == 63:
+            say(f"  {k + 1}/{N} iterations")
     torch.cuda.synchronize()
+    tot = S.totals()
+    assert tot["iterations"] == N
     S.release()
     m = (s1 / N).cpu().numpy().reshape(128, 128, 3)
     v = np.maximum((s2 / N).cpu().numpy().reshape(128, 128, 3) - m * m, 0) / (N - 1)
@@ -509,7 +697,7 @@ def test_zz_config1_full_size_block_means_match_oracle_reference(gpu):
     rel_l1 = np.abs(m - mo).sum() / mo.sum()
     floor = (np.sqrt(2 / np.pi) * np.sqrt(v + vo)).sum() / mo.sum()
     say(f"config 1 (512 -> 128 blocks): frac |z|<4 {frac:.5f} max|z| {np.abs(z).max():.2f} mean z {z.mean():.3f} "
-        f"relL1 {rel_l1:.5f} noise floor {floor:.5f}")
+        f"relL1 {rel_l1:.5f} noise floor {floor:.5f}; totals {tot}")
     assert frac >= 0.999
-    assert rel_l1 < 1.1 * floor + 0.005
-    assert nan == 0 and trunc == 0
+    assert rel_l1 < 1.1 * floor
+    assert tot["n_nan"] == 0 and tot["n_recip_truncated"] == 0
