@@ -119,10 +119,14 @@ def main():
     cfg = scenes.config(args.config)
     sc = cfg["scene"]
     W, H = sc["width"], sc["height"]
-    # the plain method: every strategy of the iteration, no learned selection
+    # the plain method: every strategy of the iteration; config 3 adds the learned proposal (both
+    # heads, trained online in every iteration)
     flags = (pt.PT_FLAG_NEE | pt.PT_FLAG_PROXY | pt.PT_FLAG_MIS | pt.PT_FLAG_GAMMA | pt.PT_FLAG_TILES |
              pt.PT_FLAG_SPC | pt.PT_FLAG_LT)
     params = dict(max_depth=cfg["max_depth"], n_light=cfg["n_light"], cand_cap=cfg["cand_cap"], seed=cfg["seed"])
+    if cfg.get("mlp"):
+        flags |= pt.PT_FLAG_MLP | pt.PT_FLAG_MLP_DIR
+        params.update(mlp_mix=cfg["mlp_mix"], mlp_lr=cfg["mlp_lr"], train_iters=cfg["train_iters"])
     torch.cuda.set_device(0)
     log(f"upload: {sc['tri'].shape[0]} tris, {W}x{H}")
     S = pt.Scene(sc, max_light_paths=cfg["n_light"])
@@ -183,8 +187,8 @@ def main():
     traffic = recorded_traffic(args.config, dom["kernel"])
     flops_tf = dom["flops"] / dom["launches"] / per_launch_s / 1e12 if per_launch_s > 0 else 0.0
     value = W * H * args.steps / dt
-    wl = {1: "projector caustic (config 1)", 2: "glossy/specular procedural (config 2)"}.get(args.config,
-                                                                                          f"config {args.config}")
+    wl = {1: "projector caustic (config 1)", 2: "glossy/specular procedural (config 2)",
+          3: "glossy/specular procedural with the learned proposal (config 3)"}.get(args.config, f"config {args.config}")
     out = {
         "metric": "full-path samples/s",
         "value": value,
@@ -200,6 +204,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{wl}: {W}x{H}, {sc['tri'].shape[0]:,} tris, depth {params['max_depth']}, "
                                f"M={params['n_light']:,} light sub-paths, {params['cand_cap']:,} expected candidates; "
+                               + ("learned proposal (subspace softmax and vMF retrace directions, 10 % "
+                                  "defensive, trained online) on " if cfg.get("mlp") else "") +
                                f"plain method (PT, NEE, probabilistic connections, light tracing, proxy connections "
                                f"with variance-aware MIS, Gamma, tiles)",
                    "spp_per_step": 1, "max_depth": params["max_depth"], "n_light": params["n_light"]},

@@ -11,6 +11,13 @@
   gamma  The choice of the incomplete light sub-path that a proxy connection completes: by the
          subspace matrix Gamma[T, S] against uniformly (Section 6.3). Only the paths that proxy
          sampling builds are scored (the other strategies are switched off), as in that section.
+  learned  The learned proposal (network softmax over the specular subspaces, vMF mixture for the
+         first retrace direction at glossy vertices; 10 % defensive plain sampling, trained online
+         by the library's kernels) against the plain method, every strategy on, at EQUAL GPU TIME
+         (--seconds per variant). The reference is the plain method run for --ref-seconds on the same
+         scene; images are compared as 4 x 4 block means (a block of the full camera covers one pixel
+         of the same camera at a quarter of the resolution), which the reference's per-block standard
+         error turns into the floor mape_ref_floor reported beside the MAPE.
 
 Measures, per variant and checkpoint (iterations 2^k, wall time from the first iteration with a
 device synchronisation at each checkpoint):
@@ -63,7 +70,77 @@ def variants(study, pt):
         out = [("rrs", base, 1.0)]
         out += [(f"booth_r={r:g}", base | pt.PT_FLAG_BOOTH, r) for r in (0.01, 0.1, 1.0, 10.0, 100.0, 1000.0)]
         return out
+    if study == "learned":
+        return [("plain", full, 1.0), ("learned", full | pt.PT_FLAG_MLP | pt.PT_FLAG_MLP_DIR, 1.0),
+                ("learned_selection", full | pt.PT_FLAG_MLP, 1.0)]
     return [("gamma", proxy | pt.PT_FLAG_GAMMA, 1.0), ("uniform", proxy, 1.0)]
+
+
+def run_timed(torch, pt, sc, wl, flags, seconds, seed, n_checks=4):
+    """Iterations until `seconds` of rendering (device-synchronised wall time, set-up and autotuning
+    excluded); per checkpoint (seconds / 2^j), the mean image as 4 x 4 block means and the variance
+    of its mean from per-iteration block images."""
+    _, depth, n_light, cand_cap, subs, _ = wl
+    W, H = sc["width"], sc["height"]
+    params = dict(max_depth=depth, n_light=n_light, cand_cap=cand_cap, seed=seed, flags=flags, booth_r=1.0,
+                  train_iters=1 << 30, mlp_mix=0.9, mlp_lr=1e-3)
+    S = pt.Scene(sc, max_light_paths=n_light)
+    S.build_subspaces(n_eye=subs[0], n_spec=subs[1])
+    img = torch.zeros(W * H * 3, device="cuda")
+    S.autotune(torch.zeros_like(img), None, iteration=1 << 29, **params)
+    s1 = torch.zeros((H // 4) * (W // 4) * 3, dtype=torch.float64, device="cuda")
+    s2 = torch.zeros_like(s1)
+    torch.cuda.synchronize()
+    checks = sorted(seconds / 2 ** j for j in range(n_checks))
+    snaps, k, t_run = [], 0, 0.0
+    while checks:
+        t0 = time.perf_counter()
+        img.zero_()
+        S.render_iteration(img, None, iteration=k, **params)
+        torch.cuda.synchronize()
+        t_run += time.perf_counter() - t0
+        b = img.view(H // 4, 4, W // 4, 4, 3).double().mean(dim=(1, 3)).reshape(-1)
+        s1 += b
+        s2 += b * b
+        k += 1
+        if t_run >= checks[0]:
+            checks.pop(0)
+            m = (s1 / k).cpu().numpy().reshape(H // 4, W // 4, 3)
+            v = np.maximum((s2 / k).cpu().numpy().reshape(H // 4, W // 4, 3) - m * m, 0) / max(k - 1, 1)
+            snaps.append((k, t_run, m, v))
+    tot = S.totals()
+    S.release()
+    return snaps, tot
+
+
+def learned_study(a, torch, pt, sc, wl):
+    """Equal-time MAPE of the learned proposal against the plain method (see the module docstring)."""
+    print(f"# reference: plain method, {a.ref_seconds} s", flush=True)
+    ref_snaps, ref_tot = run_timed(torch, pt, sc, wl, variants("learned", pt)[0][1], a.ref_seconds, a.seed + 1000,
+                                   n_checks=1)
+    _, _, R, VR = ref_snaps[-1]
+    floor = float(np.mean(math.sqrt(2 / math.pi) * np.sqrt(VR) / (R + EPS)))
+    lines = []
+    for name, flags, _ in variants("learned", pt):
+        print(f"# learned study {a.workload}: {name}, {a.seconds} s", flush=True)
+        snaps, tot = run_timed(torch, pt, sc, wl, flags, a.seconds, a.seed)
+        for n, t, m, v in snaps:
+            rec = {"study": "learned", "workload": a.workload, "variant": name, "iters": n, "seconds": round(t, 3),
+                   "mape_ref": float(np.mean(np.abs(m - R) / (R + EPS))),
+                   "mape_se": float(np.mean(math.sqrt(2 / math.pi) * np.sqrt(v) / (R + EPS))),
+                   "mape_ref_floor": floor, "ref_iters": ref_snaps[-1][0], "ref_seconds": round(ref_snaps[-1][1], 2),
+                   "image_mean": float(m.mean()), "n_nan": tot["n_nan"], "n_recip_truncated": tot["n_recip_truncated"]}
+            lines.append(rec)
+            print(json.dumps(rec), flush=True)
+    if a.out:
+        with open(a.out, "w") as f:
+            for rec in lines:
+                f.write(json.dumps(rec) + "\n")
+    print(f"\nlearned vs plain on {a.workload} at {a.seconds} s each, seed {a.seed}; reference {a.ref_seconds} s "
+          f"(MAPE floor {floor:.4f})")
+    print(f"{'variant':<20}{'iters':>7}{'seconds':>10}{'mape_ref':>10}{'mape_se':>10}")
+    for rec in lines:
+        print(f"{rec['variant']:<20}{rec['iters']:>7}{rec['seconds']:>10.2f}{rec['mape_ref']:>10.4f}{rec['mape_se']:>10.4f}")
 
 
 def trimmed_mean(m):
@@ -104,11 +181,13 @@ def run_variant(torch, pt, sc, wl, flags, booth_r, n_iter, seed):
 
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
-    ap.add_argument("--study", choices=("rr", "rr_proxy", "gamma"), default="rr")
+    ap.add_argument("--study", choices=("rr", "rr_proxy", "gamma", "learned"), default="rr")
     ap.add_argument("--workload", choices=sorted(WORKLOADS), default="cornell_glass_64")
     ap.add_argument("--iters", type=int, default=256)
     ap.add_argument("--seed", type=int, default=7)
     ap.add_argument("--out", default=None, help="also write the JSON lines to this file")
+    ap.add_argument("--seconds", type=float, default=20.0, help="learned study: rendering time per variant")
+    ap.add_argument("--ref-seconds", type=float, default=240.0, help="learned study: rendering time of the reference")
     a = ap.parse_args()
 
     import torch
@@ -118,6 +197,9 @@ def main():
         sys.exit("bench_ablation.py needs a GPU")
     wl = WORKLOADS[a.workload]
     sc = wl[0](scenes)
+    if a.study == "learned":
+        learned_study(a, torch, pt, sc, wl)
+        return
     ref = np.load(os.path.join(GOLD, wl[5]))["mean"] if wl[5] and a.study == "rr" else None
 
     runs = []

@@ -116,8 +116,11 @@ enum {
                                        else uniform over the non-empty subspaces); trained online
                                        while iteration < train_iters */
     ,
-    PT_FLAG_BOOTH = 1u << 12        /* reciprocal chains with Booth's roulette (parameter booth_r)
+    PT_FLAG_BOOTH = 1u << 12,       /* reciprocal chains with Booth's roulette (parameter booth_r)
                                        instead of the RRS function of equ:rr (RR ablation) */
+    PT_FLAG_MLP_DIR = 1u << 13      /* with PT_FLAG_MLP: the first retrace direction at a glossy
+                                       (non-Dirac) y_{s-1} from mlp_mix x the network's vMF mixture +
+                                       (1 - mlp_mix) x BSDF sampling; trained online like the logits */
 };
 
 typedef struct {
@@ -209,31 +212,45 @@ typedef struct {
 pt_status pt_autotune(pt_scene *s, const pt_iter_params *p, float *accum_rgb_dev, float *accum_sq_dev,
                       pt_tune_result *out, void *hip_stream);
 
-/* Learned selection of the specular subspace (PT_FLAG_MLP). Not part of the paper's method: it
- * replaces the Gamma row of Section 5.6 by a network's softmax mixed with that row, and keeps
- * the selection probability exact, so the proxy estimator stays unbiased.
+/* Learned proposal of the proxy strategy (PT_FLAG_MLP, PT_FLAG_MLP_DIR). Not part of the paper's
+ * method: it replaces the Gamma row of Section 5.6 by a network's softmax mixed with that row
+ * and, with PT_FLAG_MLP_DIR, proposes the first retrace direction at a glossy y_{s-1} (Section 5.1's
+ * retrace samples the BSDF there) by an 8-lobe von Mises-Fisher mixture mixed with the BSDF. Every
+ * selection probability and direction density is exact, so the proxy estimator stays unbiased.
  *
- * Network: input = 9 features of the first diffuse eye vertex (position scaled to the scene's
- * bounding box in [0, 1], shading normal, unit direction toward the previous eye vertex), each
- * encoded as [raw, sin(2^b pi f), cos(2^b pi f) for b = 0..11] (225 values) and zero-padded to
- * 256; three hidden layers of 64 ReLU units; n_spec output logits (one per specular subspace).
- * BF16 operands with FP32 accumulation. Parameter vector (FP32, this order, row-major with the
- * input index first): W1[256][64], b1[64], W2[64][64], b2[64], W3[64][64], b3[64],
- * W4[64][n_spec], b4[n_spec]; logits = h3 W4 + b4. The network is re-initialised by
- * pt_build_subspaces (and on first use); the parameters live with the scene. */
+ * Network: input = 9 features of a vertex (position scaled to the scene's bounding box in [0, 1],
+ * shading normal, unit direction toward the eye side's previous vertex), each encoded as
+ * [raw, sin(2^b pi f), cos(2^b pi f) for b = 0..11] (225 values) and zero-padded to 256; three hidden
+ * layers of 64 ReLU units; n_out = n_spec + 40 outputs: one logit per specular subspace, then per
+ * lobe k = 0..7 the raw mean direction (3, normalised; +z when it vanishes), the log concentration
+ * (clamped to [-3, 10]) and the lobe's mixture logit. Lobe density (solid angle):
+ * kappa / (2 pi (1 - exp(-2 kappa))) exp(-kappa (1 - mu.w)). BF16 operands with FP32 accumulation.
+ * Parameter vector (FP32, this order, row-major with the input index first): W1[256][64], b1[64],
+ * W2[64][64], b2[64], W3[64][64], b3[64], W4[64][n_out], b4[n_out]; outputs = h3 W4 + b4. The logits
+ * are queried at the eye's first diffuse vertex, the mixture at the chosen y_{s-1} (direction toward
+ * z_d). The network is re-initialised by pt_build_subspaces (and on first use); the parameters live
+ * with the scene. */
 pt_status pt_mlp_param_count(const pt_scene *s, int32_t *count);   /* after pt_build_subspaces */
 /* host_params[count] -> the scene's network; clears the Adam moments and step count. Synchronous. */
 pt_status pt_mlp_set_params(pt_scene *s, const float *host_params, int32_t count, void *hip_stream);
 /* the scene's network -> host_params[count]. Synchronous. */
 pt_status pt_mlp_get_params(pt_scene *s, float *host_params, int32_t count, void *hip_stream);
-/* logits_dev[n][n_spec] (bias included) of feat_dev[n][9] (device, FP32). 1 <= n <= max(H*W, 65536). */
-pt_status pt_mlp_forward(pt_scene *s, const float *feat_dev, int32_t n, float *logits_dev, void *hip_stream);
-/* One training step on n weighted samples (device arrays feat[n][9], label[n] in [0, n_spec),
- * weight[n] >= 0): loss = sum_i w_i CE(softmax(logits_i), label_i) / sum_i w_i; the gradient is
- * copied to grad_host[count] when it is not NULL, then one Adam step (b1 0.9, b2 0.999, eps 1e-8,
- * step size lr) is applied. Synchronous. 1 <= n <= 65536. */
+/* out_dev[n][n_spec + 40] (bias included) of feat_dev[n][9] (device, FP32). 1 <= n <= max(H*W, 131072). */
+pt_status pt_mlp_forward(pt_scene *s, const float *feat_dev, int32_t n, float *out_dev, void *hip_stream);
+/* One training step on a batch of n subspace samples (device arrays feat[n][9], label[n] in
+ * [0, n_spec), weight[n] >= 0) and n_dir direction samples (feat_dir[n_dir][9], unit dir[n_dir][3],
+ * weight_dir[n_dir] >= 0): loss = sum_i w_i CE(softmax(logits_i), label_i) / sum_i w_i
+ * - sum_j v_j log p_mix(dir_j | outputs_j) / sum_j v_j (either part absent when its count is 0);
+ * the gradient is copied to grad_host[count] when it is not NULL, then one Adam step (b1 0.9,
+ * b2 0.999, eps 1e-8, step size lr) is applied. Synchronous. 0 <= n, n_dir <= 65536, n + n_dir >= 1. */
 pt_status pt_mlp_train_step(pt_scene *s, const float *feat_dev, const int32_t *label_dev, const float *weight_dev,
-                            int32_t n, float lr, float *grad_host, void *hip_stream);
+                            int32_t n, const float *feat_dir_dev, const float *dir_dev, const float *weight_dir_dev,
+                            int32_t n_dir, float lr, float *grad_host, void *hip_stream);
+/* Test hook: one direction from each of n vMF mixtures raw_dev[n][40] (the direction head's 40 outputs,
+ * bias included) by the sampler of the proxy retrace, with the mixture density it is weighted by:
+ * dir_dev[n][3], pdf_dev[n] (device). No scene needed. */
+pt_status pt_vmf_sample(const float *raw_dev, int32_t n, uint32_t seed, float *dir_dev, float *pdf_dev,
+                        void *hip_stream);
 
 /* Reciprocal estimator (Section 4.2, RRS estimator with r = |g|, Appendix A). */
 enum { PT_RECIP_TABLE = 0, PT_RECIP_CANDIDATE = 1 };

@@ -16,6 +16,16 @@ a network's softmax mixed with that row. What is fixed here is the interface bot
   * Adam (Kingma and Ba, 2015) with bias corrections.
 Everything is written out in plain matrix form; no fusion.
 
+The proxy-retrace direction head: when n_out = n_spec + 40, the outputs after the n_spec logits are
+an 8-lobe von Mises-Fisher mixture over directions on the unit sphere, 5 values per lobe: the mean
+direction (3 values, normalised), the log concentration (clamped to [LOG_KAPPA_MIN, LOG_KAPPA_MAX])
+and the lobe's mixture logit. A lobe's density is the vMF density
+    p(w) = kappa / (2 pi (1 - exp(-2 kappa))) exp(-kappa (1 - mu.w)),
+with 1 - mu.w written as |mu - w|^2 / 2 (equal for unit vectors, and free of cancellation near
+mu). It is trained on the weighted negative log-likelihood of the retrace directions of the
+proxy contributions: loss_vmf = -sum_i w_i log p_mix(w_i | x_i) / sum_i w_i, added to the cross
+entropy of the subspace rows.
+
 The network's stated precision is BF16 storage with FP32 accumulation. With bf16=True the
 forward and backward passes round to BF16 (round to nearest even) where that format stores
 values: the encoded inputs, the weight matrices, the hidden activations, the logit gradient and
@@ -31,6 +41,9 @@ N_IN = 256
 N_ENC = 225
 N_H = 64
 BANDS = 12
+N_LOBES = 8
+VMF_OUT = 5 * N_LOBES
+LOG_KAPPA_MIN, LOG_KAPPA_MAX = -3.0, 10.0
 
 
 def round_bf16(x):
@@ -119,25 +132,132 @@ def log_softmax(L):
     return L - m - np.log(np.exp(L - m).sum(axis=1, keepdims=True))
 
 
-def loss(params, n_out, feat, label, weight):
-    """Weighted mean cross entropy."""
-    L, _ = forward(params, n_out, feat)
-    lp = log_softmax(L)
-    w = np.asarray(weight, dtype=np.float64)
-    return float(-(w * lp[np.arange(L.shape[0]), np.asarray(label)]).sum() / w.sum())
+# ------------------------------------------------------------------ vMF retrace-direction head
+def vmf_lobes(R):
+    """Raw outputs R [n, 40] (bias included) -> per lobe: unit mean mu [n, 8, 3], concentration kappa
+    [n, 8], mixture weight pi [n, 8] (softmax of the lobe logits), the norm of the raw direction
+    [n, 8] and whether the log concentration lies strictly inside its clamp range [n, 8]."""
+    R = np.asarray(R, dtype=np.float64).reshape(-1, N_LOBES, 5)
+    m = R[..., :3]
+    nrm = np.sqrt((m * m).sum(-1))
+    # a vanishing raw direction gives the +z axis
+    mu = np.where((nrm > 1e-20)[..., None], m / np.maximum(nrm, 1e-300)[..., None], np.array([0.0, 0.0, 1.0]))
+    s = R[..., 3]
+    inside = (s > LOG_KAPPA_MIN) & (s < LOG_KAPPA_MAX)
+    kappa = np.exp(np.clip(s, LOG_KAPPA_MIN, LOG_KAPPA_MAX))
+    lg = R[..., 4]
+    e = np.exp(lg - lg.max(-1, keepdims=True))
+    return mu, kappa, e / e.sum(-1, keepdims=True), nrm, inside
 
 
-def grad(params, n_out, feat, label, weight, bf16=False):
-    """Gradient of loss() by the chain rule, layer by layer (flat vector, same layout)."""
+def vmf_lobe_pdf(mu, kappa, w):
+    """The von Mises-Fisher density on the unit sphere (solid-angle measure)."""
+    d = mu - w
+    h = 0.5 * (d * d).sum(-1)            # 1 - mu.w for unit vectors
+    return kappa / (2.0 * np.pi * -np.expm1(-2.0 * kappa)) * np.exp(-kappa * h)
+
+
+def vmf_pdf(R, w):
+    """Mixture density of the raw outputs R [n, 40] at the unit directions w [n, 3]."""
+    mu, kappa, pi, _, _ = vmf_lobes(R)
+    return (pi * vmf_lobe_pdf(mu, kappa, np.asarray(w, dtype=np.float64)[:, None, :])).sum(-1)
+
+
+def vmf_nll_grad(R, w):
+    """d(-log p_mix(w)) / dR [n, 40] by the chain rule, with responsibilities r_k = pi_k p_k / p_mix:
+    lobe logit pi_k - r_k; log concentration -r_k (1 - 2 kappa / (exp(2 kappa) - 1) - kappa h)
+    (zero where the clamp is active), with h = 1 - mu.w; raw direction m:
+    -r_k kappa (w - (mu.w) mu) / |m|."""
+    w = np.asarray(w, dtype=np.float64)
+    mu, kappa, pi, nrm, inside = vmf_lobes(R)
+    ww = w[:, None, :]
+    v = vmf_lobe_pdf(mu, kappa, ww)
+    r = pi * v / (pi * v).sum(-1, keepdims=True)
+    h = 0.5 * ((mu - ww) ** 2).sum(-1)
+    two_k = 2.0 * kappa
+    ratio = np.where(two_k < 700.0, two_k / np.expm1(np.minimum(two_k, 700.0)), 0.0)
+    G = np.zeros(mu.shape[:2] + (5,))
+    G[..., 4] = pi - r
+    G[..., 3] = np.where(inside, -r * (1.0 - ratio - kappa * h), 0.0)
+    cosw = (mu * ww).sum(-1)
+    G[..., :3] = np.where((nrm > 1e-20)[..., None],
+                          -(r * kappa / np.maximum(nrm, 1e-300))[..., None] * (ww - cosw[..., None] * mu), 0.0)
+    return G.reshape(-1, VMF_OUT)
+
+
+def vmf_sample(R, u):
+    """Directions drawn from the mixtures of R [n, 40] with uniforms u [n, 4]: the lobe by inverse CDF
+    of pi (u0), then 1 - mu.w = -log(u1 + (1 - u1) exp(-2 kappa)) / kappa (the inverse CDF of the
+    vMF's cosine) and the azimuth 2 pi u2 about mu."""
+    mu, kappa, pi, _, _ = vmf_lobes(R)
+    u = np.asarray(u, dtype=np.float64)
+    n = mu.shape[0]
+    k = np.minimum((np.cumsum(pi, -1) <= u[:, :1]).sum(-1), N_LOBES - 1)
+    m, kp = mu[np.arange(n), k], kappa[np.arange(n), k]
+    h = -np.log(u[:, 1] + (1.0 - u[:, 1]) * np.exp(-2.0 * kp)) / kp
+    st = np.sqrt(np.maximum(h * (2.0 - h), 0.0))
+    a = np.where(np.abs(m[:, 0:1]) > 0.9, [[0.0, 1.0, 0.0]], [[1.0, 0.0, 0.0]])
+    t = np.cross(m, a)
+    t /= np.linalg.norm(t, axis=1, keepdims=True)
+    b = np.cross(m, t)
+    ph = 2.0 * np.pi * u[:, 2]
+    return (1.0 - h)[:, None] * m + st[:, None] * (np.cos(ph)[:, None] * t + np.sin(ph)[:, None] * b)
+
+
+# ------------------------------------------------------------------ losses and gradients
+def _output_grad(L, n_spec, n_ce, label, w_ce, dirs, w_v):
+    """d loss / d outputs [n_ce + n_v, n_out]: the cross-entropy rows over the first n_spec columns,
+    then the vMF rows over the 40 columns after them."""
+    G = np.zeros_like(L)
+    if n_ce:
+        lp = log_softmax(L[:n_ce, :n_spec])
+        Gc = np.exp(lp)
+        Gc[np.arange(n_ce), np.asarray(label)] -= 1.0
+        G[:n_ce, :n_spec] = Gc * (w_ce / w_ce.sum())[:, None]
+    if dirs is not None and len(dirs):
+        G[n_ce:, n_spec:n_spec + VMF_OUT] = vmf_nll_grad(L[n_ce:, n_spec:n_spec + VMF_OUT], dirs) * \
+            (w_v / w_v.sum())[:, None]
+    return G
+
+
+def _rows(feat, vmf):
+    f = [np.asarray(feat, dtype=np.float64).reshape(-1, 9)] if feat is not None else [np.zeros((0, 9))]
+    if vmf is not None:
+        f.append(np.asarray(vmf[0], dtype=np.float64).reshape(-1, 9))
+    return np.concatenate(f, axis=0)
+
+
+def loss(params, n_out, feat, label, weight, n_spec=None, vmf=None):
+    """Weighted mean cross entropy of the subspace rows (softmax over the first n_spec outputs;
+    n_spec = n_out without the direction head), plus, given vmf = (feat, dirs, weight), the
+    weighted mean negative log-likelihood of the directions under the vMF mixture."""
+    n_spec = n_out if n_spec is None else n_spec
+    total = 0.0
+    if feat is not None and len(feat):
+        L, _ = forward(params, n_out, feat)
+        lp = log_softmax(L[:, :n_spec])
+        w = np.asarray(weight, dtype=np.float64)
+        total += float(-(w * lp[np.arange(L.shape[0]), np.asarray(label)]).sum() / w.sum())
+    if vmf is not None and len(vmf[0]):
+        L, _ = forward(params, n_out, vmf[0])
+        wv = np.asarray(vmf[2], dtype=np.float64)
+        p = vmf_pdf(L[:, n_spec:n_spec + VMF_OUT], vmf[1])
+        total += float(-(wv * np.log(p)).sum() / wv.sum())
+    return total
+
+
+def grad(params, n_out, feat, label, weight, bf16=False, n_spec=None, vmf=None):
+    """Gradient of loss() by the chain rule, layer by layer (flat vector, same layout). The
+    cross-entropy rows and the direction rows (vmf) pass through the network as one batch."""
+    n_spec = n_out if n_spec is None else n_spec
     st = _store(bf16)
     P = weights(params, n_out, bf16)
-    L, a = forward(params, n_out, feat, bf16)
-    w = np.asarray(weight, dtype=np.float64)
-    n = L.shape[0]
-    # d loss / d logits = w_i / W (softmax_i - onehot(S_i))
-    G4 = np.exp(log_softmax(L))
-    G4[np.arange(n), np.asarray(label)] -= 1.0
-    G4 = st(G4 * (w / w.sum())[:, None])
+    rows = _rows(feat, vmf)
+    n_ce = 0 if feat is None else len(feat)
+    L, a = forward(params, n_out, rows, bf16)
+    w_ce = np.asarray(weight, dtype=np.float64) if n_ce else None
+    dirs, w_v = (vmf[1], np.asarray(vmf[2], dtype=np.float64)) if vmf is not None else (None, None)
+    G4 = st(_output_grad(L, n_spec, n_ce, label, w_ce, dirs, w_v))
     g = {"W4": a["H3"].T @ G4, "b4": G4.sum(axis=0)}
     dH3 = G4 @ P["W4"].T
     dZ3 = st(dH3 * (a["Z3"] > 0))
@@ -154,25 +274,26 @@ def grad(params, n_out, feat, label, weight, bf16=False):
     return pack(g, n_out)
 
 
-def grad_scale(params, n_out, feat, label, weight):
+def grad_scale(params, n_out, feat, label, weight, n_spec=None, vmf=None):
     """Per block, sqrt(sum_i ||per-sample gradient_i||^2) of the loss's gradient (each sample's term
     of a weight block is the outer product of that layer's input and output gradient, so its
     Frobenius norm is the product of the two vectors' norms). This is the scale of the error of
     a gradient whose per-sample terms each carry a small relative error and whose sum cancels."""
+    n_spec = n_out if n_spec is None else n_spec
     P = unpack(params, n_out)
-    L, a = forward(params, n_out, feat)
-    w = np.asarray(weight, dtype=np.float64)
-    n = L.shape[0]
-    G4 = np.exp(log_softmax(L))
-    G4[np.arange(n), np.asarray(label)] -= 1.0
-    G4 *= (w / w.sum())[:, None]
-    rows = lambda M: np.sqrt((M * M).sum(axis=1))  # noqa: E731
-    out = {"W4": np.sqrt(((rows(a["H3"]) * rows(G4)) ** 2).sum()), "b4": np.sqrt((rows(G4) ** 2).sum())}
+    rows = _rows(feat, vmf)
+    n_ce = 0 if feat is None else len(feat)
+    L, a = forward(params, n_out, rows)
+    w_ce = np.asarray(weight, dtype=np.float64) if n_ce else None
+    dirs, w_v = (vmf[1], np.asarray(vmf[2], dtype=np.float64)) if vmf is not None else (None, None)
+    G4 = _output_grad(L, n_spec, n_ce, label, w_ce, dirs, w_v)
+    rn = lambda M: np.sqrt((M * M).sum(axis=1))  # noqa: E731
+    out = {"W4": np.sqrt(((rn(a["H3"]) * rn(G4)) ** 2).sum()), "b4": np.sqrt((rn(G4) ** 2).sum())}
     dZ = G4
     for l, (h, z) in zip((4, 3, 2), (("H2", "Z3"), ("H1", "Z2"), ("X", "Z1"))):
         dZ = (dZ @ P[f"W{l}"].T) * (a[z] > 0)
-        out[f"W{l - 1}"] = np.sqrt(((rows(a[h]) * rows(dZ)) ** 2).sum())
-        out[f"b{l - 1}"] = np.sqrt((rows(dZ) ** 2).sum())
+        out[f"W{l - 1}"] = np.sqrt(((rn(a[h]) * rn(dZ)) ** 2).sum())
+        out[f"b{l - 1}"] = np.sqrt((rn(dZ) ** 2).sum())
     return out
 
 

@@ -738,7 +738,6 @@ __device__ float fq_sample(CtxT<SE> &C, const Cand &c, Rng &r)
 #ifndef PT_GEN_WAVES
 #define PT_GEN_WAVES 1
 #endif
-__device__ __forceinline__ float lane_get(float v, int l) { return __shfl(v, l); }
 
 // The pilot and the stage-A chains run on a persistent grid (a few workgroups per CU): each
 // wavefront takes the next item from a device counter until the items, counted on the device,
@@ -748,8 +747,16 @@ __device__ __forceinline__ int next_item(unsigned long long *counter)
 {
     int k = 0;
     if (__lane_id() == 0) k = (int)atomicAdd(counter, 1ull);
-    return __shfl(k, 0);
+    // readfirstlane (lane 0: the whole wavefront is active here) marks the item wave-uniform, so
+    // that the item's candidate record and chain state are scalar loads and scalar registers
+    return __builtin_amdgcn_readfirstlane(k);
 }
+// value of lane l (l wave-uniform) as a wave-uniform scalar
+__device__ __forceinline__ float lane_f(float v, int l) { return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l)); }
+__device__ __forceinline__ uint32_t lane_u(uint32_t v, int l) { return (uint32_t)__builtin_amdgcn_readlane((int)v, l); }
+// a value every lane holds equally (after a butterfly reduction), as a wave-uniform scalar
+__device__ __forceinline__ float uni_f(float v) { return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v))); }
+__device__ __forceinline__ int uni_i(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
 // pilot: 64-sample steps until at least `pilot` samples with 8 non-zero values, or 256 samples
 template <typename SE>
@@ -908,7 +915,7 @@ __device__ __forceinline__ void chain_consume(float fq, float u, int nv, float i
     const float g = 1.0f - fq * invB;
     if (booth_r > 0.0f) {
         for (int l = 0; l < nv && st.alive && st.pos > 0; ++l)
-            booth_step(__shfl(g, l), __shfl(u, l), booth_r, st, seed, chain, iter);
+            booth_step(lane_f(g, l), lane_f(u, l), booth_r, st, seed, chain, iter);
         return;
     }
     const float ag = fabsf(g), fl = floorf(ag);
@@ -924,7 +931,7 @@ __device__ __forceinline__ void chain_consume(float fq, float u, int nv, float i
             float sum = (lane >= l && lane < e) ? g : 0.0f;
 #pragma unroll
             for (int off = 32; off > 0; off >>= 1) sum += __shfl_xor(sum, off);
-            st.ans += (double)sum;
+            st.ans += (double)uni_f(sum);
             st.ns += (uint32_t)(e - l);
             l = e;
             if (l >= nv) break;
@@ -935,8 +942,8 @@ __device__ __forceinline__ void chain_consume(float fq, float u, int nv, float i
             else { st.alive = false; break; }
             st.next_flip *= 2u;
         }
-        const float gl = __shfl(g, l);
-        const uint32_t kl = (uint32_t)__shfl((int)kids, l);
+        const float gl = lane_f(g, l);
+        const uint32_t kl = lane_u(kids, l);
         bool positive = st.pos > 0;
         if (positive) st.pos--; else st.neg--;
         st.ns++;
@@ -965,7 +972,7 @@ __device__ __forceinline__ void chain_consume4(const float (&fq)[4], const float
             const int li = l & 3;
             const float gs = li == 0 ? g[0] : li == 1 ? g[1] : li == 2 ? g[2] : g[3];
             const float us = li == 0 ? uu[0] : li == 1 ? uu[1] : li == 2 ? uu[2] : uu[3];
-            booth_step(__shfl(gs, l >> 2), __shfl(us, l >> 2), booth_r, st, seed, chain, iter);
+            booth_step(lane_f(gs, l >> 2), lane_f(us, l >> 2), booth_r, st, seed, chain, iter);
         }
         return;
     }
@@ -981,6 +988,7 @@ __device__ __forceinline__ void chain_consume4(const float (&fq)[4], const float
             }
 #pragma unroll
             for (int off = 32; off > 0; off >>= 1) e = min(e, __shfl_xor(e, off));
+            e = uni_i(e);
             float sum = 0.0f;
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
@@ -989,7 +997,7 @@ __device__ __forceinline__ void chain_consume4(const float (&fq)[4], const float
             }
 #pragma unroll
             for (int off = 32; off > 0; off >>= 1) sum += __shfl_xor(sum, off);
-            st.ans += (double)sum;
+            st.ans += (double)uni_f(sum);
             st.ns += (uint32_t)(e - l);
             l = e;
             if (l >= 256) break;
@@ -1003,8 +1011,8 @@ __device__ __forceinline__ void chain_consume4(const float (&fq)[4], const float
         const int li = l & 3;
         const float gs = li == 0 ? g[0] : li == 1 ? g[1] : li == 2 ? g[2] : g[3];
         const uint32_t ks = li == 0 ? kids[0] : li == 1 ? kids[1] : li == 2 ? kids[2] : kids[3];
-        const float gl = __shfl(gs, l >> 2);
-        const uint32_t kl = (uint32_t)__shfl((int)ks, l >> 2);
+        const float gl = lane_f(gs, l >> 2);
+        const uint32_t kl = lane_u(ks, l >> 2);
         bool positive = st.pos > 0;
         if (positive) st.pos--; else st.neg--;
         st.ns++;
@@ -1198,8 +1206,8 @@ __global__ void __launch_bounds__(64 * RW) k_recip_point(SceneDev S, Cand c, int
         const float u = rng_f(r);
         for (int l = 0; l < 64; ++l) {
             if (pos + neg == 0) break;
-            const float g = 1.0f - lane_get(fq, l) * invB;
-            const float ul = lane_get(u, l);
+            const float g = 1.0f - lane_f(fq, l) * invB;
+            const float ul = lane_f(u, l);
             float sgn = 1.0f;
             if (pos > 0) pos--; else { neg--; sgn = -1.0f; }
             ns++;
@@ -1272,6 +1280,8 @@ struct EyeParams {
     int labels_on;   // compute eye subspaces T (Gamma selection or MIS)
     int gamma_on;
     int mlp_on;      // subspace S chosen by k_mlp_select (learned mixture) before k_proxy
+    int vmf_on;      // first retrace direction at a glossy y_{s-1} from the learned vMF mixture
+    float mix;       // weight of the learned densities in their mixtures with plain sampling
     int tiles_on;
     int M, cand_cap;
     MisK mk;             // strategy factors of the connection MIS
@@ -1734,7 +1744,8 @@ struct StatBuf {
 template <typename SE>
 __global__ void __launch_bounds__(WG) k_proxy(SceneDev S, EyeBuf E, const Cand *__restrict__ cand,
                                               const uint32_t *__restrict__ final_, EyeParams P, SubDev D,
-                                              StatBuf SB, MlpTrain MT, int repeats, unsigned long long *cnt)
+                                              StatBuf SB, MlpTrain MT, const float *vmf, int repeats,
+                                              unsigned long long *cnt)
 {
     __shared__ SE stk[PT_STACK * WG];
     const int i = blockIdx.x * WG + threadIdx.x;
@@ -1757,17 +1768,12 @@ __global__ void __launch_bounds__(WG) k_proxy(SceneDev S, EyeBuf E, const Cand *
         const float u1 = rng_f(r);
         const uint32_t x2 = rng_u32(r);
         if (P.mlp_on) {
-            // S and its mixture probability from k_mlp_select, then uniformly within S
+            // S from the learned mixture and the sub-path within it, with their probability,
+            // drawn by k_mlp_select
             Ssel = fbits(it.aux.z);
-            const int cs = Ssel >= 0 ? D.s_count[Ssel] : 0;
-            if (cs > 0) {
-                const int k = index_of(x2, cs);
-                ci = D.s_list[D.s_off[Ssel] + k];
-                pi_j = (float)((double)it.aux.w * index_prob(k, cs));
-            } else {
-                ci = 0;
-                pi_j = 0.0f;
-            }
+            ci = fbits(it.mis.z);
+            pi_j = ci >= 0 ? it.mis.w : 0.0f;
+            if (ci < 0) ci = 0;
         } else if (P.gamma_on) {
             const int ne = *D.n_nonempty;
             const size_t row = (size_t)T * D.n_spec;
@@ -1786,6 +1792,9 @@ __global__ void __launch_bounds__(WG) k_proxy(SceneDev S, EyeBuf E, const Cand *
         const int d = fbits(it.wo.w);
         float3 zn = f3(0.f, 0.f, 1.f);
         float3 add = f3(0.f, 0.f, 0.f);
+        // the direction head's training sample of this contribution (glossy y_{s-1} only)
+        bool glossy_rec = false;
+        float3 rv = f3(0.f, 0.f, 0.f), rvn = rv, rwo = rv, rdir = rv;
         if (d + 1 + u + cls <= P.K && pi_j > 0.0f) {
             const float3 xd = xyz(it.x);
             const int td = fbits(it.x.w);
@@ -1811,10 +1820,38 @@ __global__ void __launch_bounds__(WG) k_proxy(SceneDev S, EyeBuf E, const Cand *
                 qp[0] = xd; qt[0] = td; qp[1] = v; qt[1] = vt;
                 bool ok = true, last_delta = false;
                 float last_pdf = 0.0f, J0 = 0.0f, pb_y1 = 0.0f;
+                bool glossy_first = false;
                 for (int k = 1; k <= u && ok; ++k) {
                     const MatDev m = S.mats[S.shade[curt].mat];
                     const float a = rng_f(r), b = rng_f(r), cc = rng_f(r);
-                    const BS bs = bsdf_sample(m, curn, wo, a, b, cc, true);
+                    BS bs;
+                    if (k == 1 && P.vmf_on && !(m.flags & MF_DELTA)) {
+                        // a glossy y_{s-1}: mix x learned vMF mixture + (1 - mix) x BSDF sampling,
+                        // weighted by f |cos| over the mixture's density (the realised mixture
+                        // weight of the 24-bit draw); the MIS weights keep the BSDF density
+                        glossy_first = true;
+                        const float *R = vmf + (size_t)i * MLP_VMF;
+                        const float um = rng_f(r);
+                        const double mw = below_prob(P.mix);
+                        float3 wi;
+                        if (um < P.mix) {
+                            wi = vmf_mix_sample(R, a, b, cc);
+                        } else {
+                            const BS b0 = bsdf_sample(m, curn, wo, a, b, cc, true);
+                            wi = b0.wi;
+                            if (!b0.ok) wi = f3(0.f, 0.f, 0.f);
+                        }
+                        const float pb = bsdf_pdf(m, curn, wo, wi);
+                        const float pm = (float)(mw * (double)vmf_mix_pdf(R, wi) + (1.0 - mw) * (double)pb);
+                        const float3 fv = bsdf_f(m, curn, wo, wi);
+                        bs.wi = wi;
+                        bs.delta = false;
+                        bs.pdf = pb;
+                        bs.ok = pm > 0.0f && nonzero3(fv) && dot3(wi, wi) > 0.5f;
+                        bs.w = bs.ok ? fv * (fabsf(dot3(curn, wi)) / pm) : f3(0.f, 0.f, 0.f);
+                    } else {
+                        bs = bsdf_sample(m, curn, wo, a, b, cc, true);
+                    }
                     Hit h;
                     if (!bs.ok || !closest(C, cur, bs.wi, curt, h)) { ok = false; break; }
                     if (k == 1) first_dir = bs.wi;
@@ -1917,6 +1954,7 @@ __global__ void __launch_bounds__(WG) k_proxy(SceneDev S, EyeBuf E, const Cand *
                         w = prx > 0.0f ? prx / (hit + lt + nee + prx) : 0.0f;
                     }
                     add = xyz(it.beta) * fz * thr * term * (G * scale * w);
+                    if (glossy_first) { glossy_rec = true; rv = v; rvn = vn; rwo = -wzv; rdir = first_dir; }
                 }
             }
         }
@@ -1927,6 +1965,7 @@ __global__ void __launch_bounds__(WG) k_proxy(SceneDev S, EyeBuf E, const Cand *
                 const float l = lum(add);
                 if (P.gamma_on) unsafeAtomicAdd(SB.gamma_acc + (size_t)T * D.n_spec + Ssel, l);
                 if (P.mlp_on && l > 0.0f) mlp_record(S, MT, cnt, xyz(it.x), zn, xyz(it.wo), Ssel, l);
+                if (P.vmf_on && glossy_rec && l > 0.0f) mlp_record_dir(S, MT, cnt, rv, rvn, rwo, rdir, l);
                 if (P.tiles_on) {
                     const int tl = (pix / S.cam.w) / D.tile * D.tiles_x + (pix % S.cam.w) / D.tile;
                     unsafeAtomicAdd(SB.tile_proxy + tl, l);

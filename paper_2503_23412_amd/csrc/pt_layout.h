@@ -77,7 +77,9 @@ enum {
     C_PROXYQ = C_SHD0 + PT_MAX_DEPTH + 1, C_NCAND, C_NKEPT, C_NFINAL,
     C_RAYS_EYE, C_RAYS_LIGHT, C_RAYS_SHADOW, C_RAYS_PROXY, C_RAYS_RECIP,
     C_RECIP_SAMPLES, C_RECIP_TRUNC, C_LONGQ0, C_LONGQ1, C_CHAIN_HIST, C_CHAIN_MAX = C_CHAIN_HIST + 24, C_POOL, C_SPC, C_LT, C_PROXY_ATT, C_PROXY_VALID, C_NAN, C_VISITS, C_TESTS, C_VISITS_R, C_TESTS_R, C_VISITS_A, C_TESTS_A, C_TRIPS_A, C_SAMPLES_A, C_DRAWN_A, C_DRAWN_P, C_WORK_A, C_WORK_P, C_COSTH0, C_COSTF0 = C_COSTH0 + 16, C_STACK_OVF = C_COSTF0 + 16,
-    C_MLP_N,                 // training samples recorded this iteration
+    C_MLP_N,                 // training samples of the subspace head recorded this iteration
+    C_MLP_NV,                // training samples of the retrace-direction head recorded this iteration
+    C_MLP_ROWS,              // training rows of this iteration (both heads, each capped)
     C_ITER, C_LEARN,         // iteration index and "still learning" flag (kept across k_zero)
     C_MLP_T,                 // Adam steps taken (kept across k_zero)
     C_COUNT

@@ -134,13 +134,15 @@ struct pt_scene {
     float *prev = nullptr, *row_tot = nullptr;
     int *s_count_prev = nullptr;
     // learned selection: parameters (FP32 master, BF16 copy, gradient, Adam moments) and
-    // activations for max(npix, MLP_CAP) rows
+    // activations for max(npix, 2 MLP_CAP) rows
     int mlp_nout = 0, mlp_rows = 0, mlp_np = 0;
     bool mlp_ready = false;
     float *mw = nullptr, *mg = nullptr, *mm = nullptr, *mv = nullptr;
+    uint16_t *mwt = nullptr;   // transposed BF16 weight matrices (k_mlp_transpose) for the fused forward pass
     uint16_t *mwb = nullptr, *mx = nullptr, *mh[3] = {nullptr, nullptr, nullptr}, *mdz[2] = {nullptr, nullptr},
              *mg4 = nullptr;
     float *mz = nullptr, *ml = nullptr, *mdh = nullptr;
+    float *mvmf = nullptr;   // [npix x MLP_VMF] mixture outputs (bias included) of every proxy item's y_{s-1}
     MlpTrain MT{};
     // group searches of the centroid sets (eye T, specular S, light S_L)
     struct GroupSet {
@@ -634,26 +636,39 @@ void gemm(hipStream_t st, int M, int N, int K, const uint16_t *A, int sam, int s
     k_gemm<<<grid, 256, 0, st>>>(M, N, K, A, sam, sak, B, sbk, sbn, C, scm, 0, cnt, m_cidx, k_cidx);
 }
 
-// allocation (once per output width) and, unless ready, initialisation of the network
+// the transposed BF16 weight matrices the fused forward pass reads, from the BF16 copy
+void mlp_transpose(pt_scene *s, hipStream_t st)
+{
+    const MlpOff o = mlp_off(s->mlp_nout);
+    const long n = (long)MLP_IN * MLP_H + 2L * MLP_H * MLP_H + (long)MLP_H * s->mlp_nout;
+    k_mlp_transpose<<<blocks(n, 256), 256, 0, st>>>(s->mwb, s->mwt, s->mlp_nout, o.W1, o.W2, o.W3, o.W4);
+}
+
+// allocation (once per output width: n_spec logits + MLP_VMF mixture outputs) and, unless ready,
+// initialisation of the network
 pt_status ensure_mlp(pt_scene *s, hipStream_t st)
 {
     if (!s->subspaces_ready) return set_err(PT_ESTATE, "pt_build_subspaces must run first");
-    const int nout = s->n_spec;
+    const int nout = s->n_spec + MLP_VMF;
     if (s->mlp_nout != nout) {
         const MlpOff o = mlp_off(nout);
-        const int R = std::max(s->npix, MLP_CAP);
+        // rows: every pixel's query, or a training batch of both heads' samples
+        const int R = std::max(s->npix, 2 * MLP_CAP);
         pt_status e;
 #define AL(ptr, n) if ((e = s->alloc(ptr, n)) != PT_OK) return e;
-        AL(s->mw, o.n); AL(s->mg, o.n); AL(s->mm, o.n); AL(s->mv, o.n); AL(s->mwb, o.n);
+        AL(s->mw, o.n); AL(s->mg, o.n); AL(s->mm, o.n); AL(s->mv, o.n); AL(s->mwb, o.n); AL(s->mwt, o.n);
         AL(s->mx, (size_t)R * MLP_IN);
         for (int k = 0; k < 3; ++k) AL(s->mh[k], (size_t)R * MLP_H);
         for (int k = 0; k < 2; ++k) AL(s->mdz[k], (size_t)R * MLP_H);
-        AL(s->mg4, (size_t)MLP_CAP * nout);
+        AL(s->mg4, (size_t)2 * MLP_CAP * nout);
         AL(s->mz, (size_t)R * MLP_H); AL(s->mdh, (size_t)R * MLP_H);
         AL(s->ml, (size_t)R * nout);
+        AL(s->mvmf, (size_t)s->npix * MLP_VMF);
         if (!s->MT.feat) {
             AL(s->MT.feat, (size_t)MLP_CAP * 9); AL(s->MT.label, MLP_CAP); AL(s->MT.weight, MLP_CAP);
             AL(s->MT.wsum, 1);
+            AL(s->MT.vfeat, (size_t)MLP_CAP * 9); AL(s->MT.vdir, (size_t)MLP_CAP * 3); AL(s->MT.vweight, MLP_CAP);
+            AL(s->MT.vwsum, 1);
             s->MT.cap = MLP_CAP;
         }
 #undef AL
@@ -663,6 +678,7 @@ pt_status ensure_mlp(pt_scene *s, hipStream_t st)
     }
     if (!s->mlp_ready) {
         k_mlp_init<<<blocks(s->mlp_np, 256), 256, 0, st>>>(s->mw, s->mwb, s->mg, s->mm, s->mv, nout, 0x6d6c7001u);
+        mlp_transpose(s, st);
         k_set_counter<<<1, 1, 0, st>>>(s->cnt, C_MLP_T, 0ull);
         HIPCHK(hipGetLastError());
         s->mlp_ready = true;
@@ -670,46 +686,51 @@ pt_status ensure_mlp(pt_scene *s, hipStream_t st)
     return PT_OK;
 }
 
-// logits (no bias) of the first rows of s->mx: rows = min(M, cnt[m_cidx]) (or M); hidden
-// activations kept in mh[0..2] for the backward pass
-void mlp_forward(pt_scene *s, int M, const unsigned long long *cnt, int m_cidx, float *logits, hipStream_t st)
+// outputs col0 .. col0 + ncols - 1 of the first rows of s->mx into out (row stride ncols), with
+// bias_out[col] added when given: rows = min(M, cnt[m_cidx]) (or M), one fused launch; keep_h: the
+// hidden activations go to mh[0..2] for the backward pass
+void mlp_forward(pt_scene *s, int M, const unsigned long long *cnt, int m_cidx, float *out, int col0, int ncols,
+                 hipStream_t st, const float *bias_out = nullptr, bool keep_h = false)
 {
-    const MlpOff o = mlp_off(s->mlp_nout);
-    const uint16_t *in = s->mx;
-    const size_t Wo[3] = {o.W1, o.W2, o.W3}, bo[3] = {o.b1, o.b2, o.b3};
-    for (int l = 0; l < 3; ++l) {
-        const int K = l == 0 ? MLP_IN : MLP_H;
-        gemm(st, M, MLP_H, K, in, K, 1, s->mwb + Wo[l], MLP_H, 1, s->mz, MLP_H, cnt, m_cidx, -1, 1);
-        k_bias_relu<<<blocks((long)M * MLP_H, 256), 256, 0, st>>>(s->mz, s->mw + bo[l], s->mh[l], M, MLP_H, cnt, m_cidx);
-        in = s->mh[l];
-    }
-    gemm(st, M, s->mlp_nout, MLP_H, in, MLP_H, 1, s->mwb + o.W4, s->mlp_nout, 1, logits, s->mlp_nout, cnt, m_cidx, -1, 1);
+    const int nout = s->mlp_nout;
+    const MlpOff o = mlp_off(nout);
+    const int grid = std::max(1, std::min(blocks(M, MLP_FT_ROWS), 2048));
+    if (keep_h)
+        k_mlp_fwd<true><<<grid, 256, 0, st>>>(s->mx, M, cnt, m_cidx, s->mwt, s->mw, o.W1, o.b1, o.W2, o.b2, o.W3, o.b3,
+                                              o.W4, nout, col0, ncols, out, bias_out, s->mh[0], s->mh[1], s->mh[2]);
+    else
+        k_mlp_fwd<false><<<grid, 256, 0, st>>>(s->mx, M, cnt, m_cidx, s->mwt, s->mw, o.W1, o.b1, o.W2, o.b2, o.W3,
+                                               o.b3, o.W4, nout, col0, ncols, out, bias_out, nullptr, nullptr, nullptr);
 }
 
-// gradient of the weighted cross entropy over the R = min(MLP_CAP, cnt[C_MLP_N]) samples whose
-// features are encoded in s->mx, labels/weights in s->MT (sum of weights in MT.wsum), added into
-// s->mg (which is zero before)
-void mlp_backward(pt_scene *s, const int *label, const float *weight, hipStream_t st)
+// gradient of the training batch's loss (rows: T's min(cap, C_MLP_N) subspace samples, then its
+// min(cap, C_MLP_NV) direction samples, encoded in s->mx; cnt[C_MLP_ROWS] set): the weighted
+// cross entropy of the logits plus the weighted negative log-likelihood of the directions under
+// the vMF mixture, each over its own weight sum, added into s->mg (which is zero before)
+void mlp_backward(pt_scene *s, const MlpTrain &T, hipStream_t st)
 {
-    const int R = MLP_CAP, N = s->mlp_nout;
+    const int R = 2 * MLP_CAP, N = s->mlp_nout, ns = s->n_spec;
     const MlpOff o = mlp_off(N);
     unsigned long long *cnt = s->cnt;
-    mlp_forward(s, R, cnt, C_MLP_N, s->ml, st);
-    k_ce_grad<<<R, 256, 0, st>>>(s->ml, s->mw + o.b4, label, weight, s->MT.wsum, R, N, s->mg4, cnt, C_MLP_N);
-    k_colsum<<<dim3(blocks(N, 64), R / MLP_STRIP), 64, 0, st>>>(s->mg4, R, N, s->mg + o.b4, cnt, C_MLP_N);
+    mlp_forward(s, R, cnt, C_MLP_ROWS, s->ml, 0, N, st, nullptr, true);
+    k_ce_grad<<<MLP_CAP, 256, 0, st>>>(s->ml, s->mw + o.b4, T.label, T.weight, T.wsum, MLP_CAP, ns, N, s->mg4, cnt,
+                                       C_MLP_N);
+    k_vmf_grad<<<blocks(MLP_CAP, 256), 256, 0, st>>>(s->ml, s->mw + o.b4, T.vdir, T.vweight, T.vwsum, N, ns, s->mg4,
+                                                     cnt, MLP_CAP);
+    k_colsum<<<dim3(blocks(N, 64), R / MLP_STRIP), 64, 0, st>>>(s->mg4, R, N, s->mg + o.b4, cnt, C_MLP_ROWS);
     // layer 4: dW4 = H3^T G4, dH3 = G4 W4^T
-    gemm(st, MLP_H, N, R, s->mh[2], 1, MLP_H, s->mg4, N, 1, s->mg + o.W4, N, cnt, -1, C_MLP_N, MLP_KSPLIT);
-    gemm(st, R, MLP_H, N, s->mg4, N, 1, s->mwb + o.W4, 1, N, s->mdh, MLP_H, cnt, C_MLP_N, -1, 1);
+    gemm(st, MLP_H, N, R, s->mh[2], 1, MLP_H, s->mg4, N, 1, s->mg + o.W4, N, cnt, -1, C_MLP_ROWS, MLP_KSPLIT);
+    gemm(st, R, MLP_H, N, s->mg4, N, 1, s->mwb + o.W4, 1, N, s->mdh, MLP_H, cnt, C_MLP_ROWS, -1, 1);
     const size_t Wo[3] = {o.W1, o.W2, o.W3}, bo[3] = {o.b1, o.b2, o.b3};
     for (int l = 2; l >= 0; --l) {
         uint16_t *dz = s->mdz[l & 1];
-        k_relu_back<<<blocks((long)R * MLP_H, 256), 256, 0, st>>>(s->mdh, s->mh[l], dz, R, MLP_H, cnt, C_MLP_N);
-        k_colsum<<<dim3(1, R / MLP_STRIP), 64, 0, st>>>(dz, R, MLP_H, s->mg + bo[l], cnt, C_MLP_N);
+        k_relu_back<<<blocks((long)R * MLP_H, 256), 256, 0, st>>>(s->mdh, s->mh[l], dz, R, MLP_H, cnt, C_MLP_ROWS);
+        k_colsum<<<dim3(1, R / MLP_STRIP), 64, 0, st>>>(dz, R, MLP_H, s->mg + bo[l], cnt, C_MLP_ROWS);
         const uint16_t *in = l == 0 ? s->mx : s->mh[l - 1];
         const int K = l == 0 ? MLP_IN : MLP_H;
-        gemm(st, K, MLP_H, R, in, 1, K, dz, MLP_H, 1, s->mg + Wo[l], MLP_H, cnt, -1, C_MLP_N, MLP_KSPLIT);
+        gemm(st, K, MLP_H, R, in, 1, K, dz, MLP_H, 1, s->mg + Wo[l], MLP_H, cnt, -1, C_MLP_ROWS, MLP_KSPLIT);
         if (l > 0)
-            gemm(st, R, MLP_H, MLP_H, dz, MLP_H, 1, s->mwb + Wo[l], 1, MLP_H, s->mdh, MLP_H, cnt, C_MLP_N, -1, 1);
+            gemm(st, R, MLP_H, MLP_H, dz, MLP_H, 1, s->mwb + Wo[l], 1, MLP_H, s->mdh, MLP_H, cnt, C_MLP_ROWS, -1, 1);
     }
 }
 
@@ -717,6 +738,7 @@ void mlp_adam(pt_scene *s, float lr, hipStream_t st)
 {
     k_adam<<<blocks(s->mlp_np, 256), 256, 0, st>>>(s->mw, s->mwb, s->mg, s->mm, s->mv, s->mlp_np, lr, 0.9f, 0.999f,
                                                    1e-8f, s->cnt);
+    mlp_transpose(s, st);
     k_mlp_tick<<<1, 1, 0, st>>>(s->cnt);
 }
 
@@ -767,7 +789,7 @@ pt_status enqueue_iteration(pt_scene *s, const pt_iter_params *p, float *acc, fl
     const bool gamma = proxy && (p->flags & PT_FLAG_GAMMA);
     const bool mis = proxy && (p->flags & PT_FLAG_MIS);
     const bool tiles = proxy && (p->flags & PT_FLAG_TILES) && p->tile == s->tile;
-    const bool mlp = proxy && (p->flags & PT_FLAG_MLP) && s->mlp_ready && s->mlp_nout == s->n_spec;
+    const bool mlp = proxy && (p->flags & PT_FLAG_MLP) && s->mlp_ready && s->mlp_nout == s->n_spec + MLP_VMF;
     const bool labels = gamma || mis || mlp;
     const int ne = s->n_eye, ns = s->n_spec;
     k_zero<<<blocks(C_COUNT, 256), 256, 0, stream>>>(s->cnt, C_COUNT);
@@ -932,22 +954,32 @@ pt_status enqueue_iteration(pt_scene *s, const pt_iter_params *p, float *acc, fl
         HIPCHK(hipStreamWaitEvent(stream, s->ev_join, 0));
     }
     StatBuf SB{s->gamma_acc, s->tile_proxy, s->tile_total};
+    const bool vmf = EP.mlp_on && (p->flags & PT_FLAG_MLP_DIR);
     if (EP.mlp_on) {
-        // the network's logits for every queued first diffuse vertex, then S per item
+        // the network's logits for every queued first diffuse vertex, then S and the incomplete
+        // sub-path per item; for the direction head, the mixture at each chosen y_{s-1}
         const MlpOff o = mlp_off(s->mlp_nout);
         k_fill<<<1, 64, 0, stream>>>(s->MT.wsum, 0.0f, 1);
+        k_fill<<<1, 64, 0, stream>>>(s->MT.vwsum, 0.0f, 1);
         k_mlp_enc_items<<<blocks(np, 256), 256, 0, stream>>>(S, E.proxy, s->cnt, s->mx);
-        mlp_forward(s, np, s->cnt, C_PROXYQ, s->ml, stream);
-        k_mlp_select<<<blocks(np, 256), 256, 0, stream>>>(E, D, s->ml, s->mw + o.b4, s->mlp_nout, p->mlp_mix,
-                                                          gamma ? 1 : 0, p->seed, s->cnt);
+        mlp_forward(s, np, s->cnt, C_PROXYQ, s->ml, 0, ns, stream);
+        k_mlp_select<<<blocks(np, 256), 256, 0, stream>>>(E, D, s->ml, s->mw + o.b4, ns, p->mlp_mix, gamma ? 1 : 0,
+                                                          p->seed, s->cnt);
+        if (vmf) {
+            k_mlp_enc_retrace<<<blocks(np, 256), 256, 0, stream>>>(S, E.proxy, s->cand, s->cnt, s->mx);
+            mlp_forward(s, np, s->cnt, C_PROXYQ, s->mvmf, ns, MLP_VMF, stream, s->mw + o.b4 + ns);
+        }
     }
+    EP.vmf_on = vmf ? 1 : 0;
+    EP.mix = p->mlp_mix;
     if (EP.proxy_on)
-        PT_STK(s, k_proxy, blocks(np, WG), WG, stream, S, E, s->cand, s->final_, EP, D, SB, s->MT, p->recip_repeats,
-               s->cnt);
+        PT_STK(s, k_proxy, blocks(np, WG), WG, stream, S, E, s->cand, s->final_, EP, D, SB, s->MT, s->mvmf,
+               p->recip_repeats, s->cnt);
     if (EP.mlp_on) {
         // online training on this iteration's samples (no work unless the iteration recorded some)
-        k_mlp_enc_feat<<<blocks(MLP_CAP, 256), 256, 0, stream>>>(s->MT.feat, MLP_CAP, s->cnt, C_MLP_N, s->mx);
-        mlp_backward(s, s->MT.label, s->MT.weight, stream);
+        k_mlp_rows<<<1, 1, 0, stream>>>(s->cnt, MLP_CAP);
+        k_mlp_enc_train<<<blocks(2 * MLP_CAP, 256), 256, 0, stream>>>(s->MT, s->cnt, s->mx);
+        mlp_backward(s, s->MT, stream);
         mlp_adam(s, p->mlp_lr, stream);
     }
     if (labels && s->prev)
@@ -1065,6 +1097,21 @@ extern "C" pt_status pt_render_batch(pt_scene *s, const pt_iter_params *p, uint3
     return PT_OK;
 }
 
+namespace {
+// validation shared by both table-mode entry points
+pt_status check_table_query(const pt_recip_query *q, const float *out, const uint32_t *ns)
+{
+    if (!q || !out || !ns) return set_err(PT_EINVAL, "null argument");
+    if (q->n_est <= 0 || !(q->B > 0.0f)) return set_err(PT_EINVAL, "n_est and B must be positive");
+    if (q->mode != PT_RECIP_TABLE) return set_err(PT_EINVAL, "not a table query");
+    if (q->n <= 0 || !q->f_dev || !q->q_dev) return set_err(PT_EINVAL, "bad table query");
+    if (q->estimator != PT_EST_ITILDE && q->estimator != PT_EST_SIGN && q->estimator != PT_EST_BOOTH)
+        return set_err(PT_EINVAL, "unknown estimator");
+    if (q->estimator == PT_EST_BOOTH && !(q->booth_r > 0.0f)) return set_err(PT_EINVAL, "booth_r must be positive");
+    return PT_OK;
+}
+}  // namespace
+
 extern "C" pt_status pt_reciprocal_estimate(pt_scene *s, const pt_recip_query *q, float *out, uint32_t *ns,
                                             void *stream_)
 {
@@ -1073,10 +1120,7 @@ extern "C" pt_status pt_reciprocal_estimate(pt_scene *s, const pt_recip_query *q
     hipStream_t stream = (hipStream_t)stream_;
     const uint32_t cap = q->cap ? q->cap : 65536u;
     if (q->mode == PT_RECIP_TABLE) {
-        if (q->n <= 0 || !q->f_dev || !q->q_dev) return set_err(PT_EINVAL, "bad table query");
-        if (q->estimator != PT_EST_ITILDE && q->estimator != PT_EST_SIGN && q->estimator != PT_EST_BOOTH)
-            return set_err(PT_EINVAL, "unknown estimator");
-        if (q->estimator == PT_EST_BOOTH && !(q->booth_r > 0.0f)) return set_err(PT_EINVAL, "booth_r must be positive");
+        TRY(check_table_query(q, out, ns));
         if (!s) TRY(check_device());
         // the cumulative sums of q in a stream-ordered workspace, released after the estimates
         double *cdf = nullptr;
@@ -1135,7 +1179,7 @@ extern "C" pt_status pt_mlp_param_count(const pt_scene *s, int32_t *count)
 {
     if (!s || !count) return set_err(PT_EINVAL, "null argument");
     if (!s->subspaces_ready) return set_err(PT_ESTATE, "pt_build_subspaces must run first");
-    *count = (int32_t)mlp_off(s->n_spec).n;
+    *count = (int32_t)mlp_off(s->n_spec + MLP_VMF).n;
     return PT_OK;
 }
 
@@ -1148,6 +1192,7 @@ extern "C" pt_status pt_mlp_set_params(pt_scene *s, const float *host, int32_t c
     const size_t n = (size_t)count;
     HIPCHK(hipMemcpyAsync(s->mw, host, n * sizeof(float), hipMemcpyHostToDevice, st));
     k_to_bf16<<<blocks((long)n, 256), 256, 0, st>>>(s->mw, s->mwb, n);
+    mlp_transpose(s, st);
     k_fill<<<blocks((long)n, 256), 256, 0, st>>>(s->mg, 0.0f, n);
     k_fill<<<blocks((long)n, 256), 256, 0, st>>>(s->mm, 0.0f, n);
     k_fill<<<blocks((long)n, 256), 256, 0, st>>>(s->mv, 0.0f, n);
@@ -1168,39 +1213,65 @@ extern "C" pt_status pt_mlp_get_params(pt_scene *s, float *host, int32_t count, 
     return PT_OK;
 }
 
-extern "C" pt_status pt_mlp_forward(pt_scene *s, const float *feat, int32_t n, float *logits, void *stream_)
+extern "C" pt_status pt_mlp_forward(pt_scene *s, const float *feat, int32_t n, float *out, void *stream_)
 {
-    if (!s || !feat || !logits) return set_err(PT_EINVAL, "null argument");
+    if (!s || !feat || !out) return set_err(PT_EINVAL, "null argument");
     hipStream_t st = (hipStream_t)stream_;
     TRY(ensure_mlp(s, st));
     if (n < 1 || n > s->mlp_rows) return set_err(PT_EINVAL, "n out of range [1, %d]", s->mlp_rows);
     const MlpOff o = mlp_off(s->mlp_nout);
     k_mlp_enc_feat<<<blocks(n, 256), 256, 0, st>>>(feat, n, s->cnt, -1, s->mx);
-    mlp_forward(s, n, s->cnt, -1, logits, st);
-    k_add_bias<<<blocks((long)n * s->mlp_nout, 256), 256, 0, st>>>(logits, s->mw + o.b4, n, s->mlp_nout);
+    mlp_forward(s, n, s->cnt, -1, out, 0, s->mlp_nout, st);
+    k_add_bias<<<blocks((long)n * s->mlp_nout, 256), 256, 0, st>>>(out, s->mw + o.b4, n, s->mlp_nout);
     HIPCHK(hipGetLastError());
     return PT_OK;
 }
 
 extern "C" pt_status pt_mlp_train_step(pt_scene *s, const float *feat, const int32_t *label, const float *weight,
-                                       int32_t n, float lr, float *grad_host, void *stream_)
+                                       int32_t n, const float *feat_dir, const float *dir, const float *weight_dir,
+                                       int32_t n_dir, float lr, float *grad_host, void *stream_)
 {
-    if (!s || !feat || !label || !weight) return set_err(PT_EINVAL, "null argument");
-    if (n < 1 || n > MLP_CAP) return set_err(PT_EINVAL, "n out of range [1, %d]", MLP_CAP);
+    if (!s || (n > 0 && (!feat || !label || !weight)) || (n_dir > 0 && (!feat_dir || !dir || !weight_dir)))
+        return set_err(PT_EINVAL, "null argument");
+    if (n < 0 || n > MLP_CAP || n_dir < 0 || n_dir > MLP_CAP || n + n_dir < 1)
+        return set_err(PT_EINVAL, "n and n_dir out of range [0, %d], not both 0", MLP_CAP);
     if (!(lr > 0.0f)) return set_err(PT_EINVAL, "lr must be positive");
     hipStream_t st = (hipStream_t)stream_;
     TRY(ensure_mlp(s, st));
+    // the caller's arrays as this step's training batch
+    MlpTrain T = s->MT;
+    T.feat = const_cast<float *>(feat); T.label = const_cast<int *>(label); T.weight = const_cast<float *>(weight);
+    T.vfeat = const_cast<float *>(feat_dir); T.vdir = const_cast<float *>(dir);
+    T.vweight = const_cast<float *>(weight_dir);
     k_set_counter<<<1, 1, 0, st>>>(s->cnt, C_MLP_N, (unsigned long long)n);
-    k_sum1<<<1, 256, 0, st>>>(weight, n, s->MT.wsum);
-    k_mlp_enc_feat<<<blocks(n, 256), 256, 0, st>>>(feat, n, s->cnt, -1, s->mx);
-    mlp_backward(s, label, weight, st);
+    k_set_counter<<<1, 1, 0, st>>>(s->cnt, C_MLP_NV, (unsigned long long)n_dir);
+    k_mlp_rows<<<1, 1, 0, st>>>(s->cnt, MLP_CAP);
+    k_fill<<<1, 64, 0, st>>>(T.wsum, 0.0f, 1);
+    k_fill<<<1, 64, 0, st>>>(T.vwsum, 0.0f, 1);
+    if (n > 0) k_sum1<<<1, 256, 0, st>>>(weight, n, T.wsum);
+    if (n_dir > 0) k_sum1<<<1, 256, 0, st>>>(weight_dir, n_dir, T.vwsum);
+    k_mlp_enc_train<<<blocks(n + n_dir, 256), 256, 0, st>>>(T, s->cnt, s->mx);
+    mlp_backward(s, T, st);
     if (grad_host) {
         HIPCHK(hipMemcpyAsync(grad_host, s->mg, (size_t)s->mlp_np * sizeof(float), hipMemcpyDeviceToHost, st));
     }
     mlp_adam(s, lr, st);
     k_set_counter<<<1, 1, 0, st>>>(s->cnt, C_MLP_N, 0ull);
+    k_set_counter<<<1, 1, 0, st>>>(s->cnt, C_MLP_NV, 0ull);
+    k_set_counter<<<1, 1, 0, st>>>(s->cnt, C_MLP_ROWS, 0ull);
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(st));
+    return PT_OK;
+}
+
+extern "C" pt_status pt_vmf_sample(const float *raw_dev, int32_t n, uint32_t seed, float *dir_dev, float *pdf_dev,
+                                   void *stream_)
+{
+    if (!raw_dev || !dir_dev || !pdf_dev || n < 0) return set_err(PT_EINVAL, "bad argument");
+    if (n == 0) return PT_OK;
+    TRY(check_device());
+    k_vmf_hook<<<blocks(n, 256), 256, 0, (hipStream_t)stream_>>>(raw_dev, n, seed, dir_dev, pdf_dev);
+    HIPCHK(hipGetLastError());
     return PT_OK;
 }
 

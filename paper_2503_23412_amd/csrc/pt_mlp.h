@@ -1,10 +1,16 @@
-// Learned proposal for the selection of incomplete sub-paths: an MLP maps the features of the
-// eye's first diffuse vertex (9-D: position in the scene box, normal, direction toward the
-// previous eye vertex; 12-band sin/cos encoding + raw = 225, padded to 256) through three
-// hidden layers of 64 ReLU units to one logit per specular subspace. The proxy strategy picks
-// S from 0.9 softmax(logits over the non-empty subspaces) + 0.1 plain row (defensive), so every
-// selection probability stays positive and exactly known. It is trained online on the proxy
-// contributions of earlier iterations (contribution-weighted cross entropy) with Adam.
+// Learned proposal of the proxy strategy: an MLP maps 9 features of a vertex (position in the
+// scene box, normal, direction toward the previous vertex of the eye side; 12-band sin/cos
+// encoding + raw = 225, padded to 256) through three hidden layers of 64 ReLU units to n_spec
+// subspace logits followed by an 8-lobe von Mises-Fisher mixture over directions (5 outputs per
+// lobe: mean direction, log concentration, mixture logit).
+//  * Queried at the eye's first diffuse vertex, the logits pick the specular subspace S from
+//    mix softmax(logits over the non-empty subspaces) + (1 - mix) plain row (defensive).
+//  * Queried at the chosen incomplete sub-path's y_{s-1} (direction toward z_d), the mixture
+//    proposes the first retrace direction at a glossy (non-Dirac) y_{s-1}: mix vMF mixture +
+//    (1 - mix) BSDF sampling, with the mixture density in the retrace pdf.
+// Every probability stays positive wherever the plain sampling's does and is exactly known, so
+// the estimator stays unbiased. Both heads train online on the proxy contributions of the
+// iterations (contribution-weighted cross entropy and negative log-likelihood) with Adam.
 //
 // The dense layers run on MFMA: v_mfma_f32_16x16x32_bf16, BF16 operands, FP32 accumulation.
 #pragma once
@@ -16,6 +22,10 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 #define MLP_IN 256
 #define MLP_H 64
 #define MLP_BANDS 12
+#define MLP_LOBES 8
+#define MLP_VMF (5 * MLP_LOBES)
+#define VMF_LOGK_MIN (-3.0f)
+#define VMF_LOGK_MAX 10.0f
 
 __device__ __forceinline__ uint16_t f2bf(float f)
 {
@@ -90,6 +100,124 @@ __global__ void k_gemm(int M, int N, int K, const uint16_t *__restrict__ A, int 
     }
 }
 
+// Transposed BF16 copies of the four weight matrices for the fused forward pass: for layer l with
+// W_l[K][N] (row-major at offset off_l of the parameter vector), Wt_l[n][k] = W_l[k][n] at the same
+// offset of wt, so that one lane's 8 consecutive k of a column are one 16-byte load.
+__global__ void k_mlp_transpose(const uint16_t *wb, uint16_t *wt, int nout, size_t oW1, size_t oW2, size_t oW3,
+                                size_t oW4)
+{
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const size_t n1 = (size_t)MLP_IN * MLP_H, n2 = (size_t)MLP_H * MLP_H, n4 = (size_t)MLP_H * nout;
+    size_t off, K, N, j;
+    if (i < n1) { off = oW1; K = MLP_IN; N = MLP_H; j = i; }
+    else if (i < n1 + n2) { off = oW2; K = MLP_H; N = MLP_H; j = i - n1; }
+    else if (i < n1 + 2 * n2) { off = oW3; K = MLP_H; N = MLP_H; j = i - n1 - n2; }
+    else if (i < n1 + 2 * n2 + n4) { off = oW4; K = MLP_H; N = (size_t)nout; j = i - n1 - 2 * n2; }
+    else return;
+    const size_t k = j / N, n = j % N;
+    wt[off + n * K + k] = wb[off + j];
+}
+
+// Fused forward pass of the whole network on MFMA (v_mfma_f32_16x16x32_bf16, FP32 accumulation):
+// one workgroup of four wavefronts per 64-row tile (a persistent loop over tiles), each wavefront a
+// strip of 16 rows through all four layers. Lane (r, g) = (lane % 16, lane / 16) feeds row r's
+// inputs 8 g .. 8 g + 7 of each 32-wide k step (one 16-byte load) and column r's weights
+// (16-byte loads from the transposed copies, which every tile rereads from the caches); hidden
+// activations (bias, ReLU, BF16) go through a per-wavefront LDS strip that turns the MFMA's output
+// layout (rows 4 g .. 4 g + 3 of column r) into the next layer's input layout. Writes the outputs
+// col0 .. col0 + ncols - 1 of rows < min(M, cnt[m_cidx]) (or M) to out (row stride ncols), with
+// bias_out[col] added when given; keep_h: the hidden activations also go to H1..H3 (row stride 64)
+// for the backward pass.
+#define MLP_FT_ROWS 64
+#define MLP_STRIP_LD (MLP_H + 8)   // padded LDS row (144 bytes): 16-byte lane reads fall in distinct banks
+__device__ __forceinline__ bf16x8 ld8(const uint16_t *p)
+{
+    return __builtin_bit_cast(bf16x8, *(const uint4 *)p);
+}
+// one hidden layer for the wavefront's 16 rows: inputs from X (layer 1) or from the LDS strip,
+// 64 outputs in four 16 x 16 MFMA tiles, then bias, ReLU and BF16 back into the strip (and to H)
+template <int K, bool FROM_X, bool KEEP_H>
+__device__ __forceinline__ void mlp_fwd_layer(const uint16_t *__restrict__ X, int row0, int Mv,
+                                              const uint16_t *__restrict__ Wt, const float *__restrict__ bias,
+                                              uint16_t *hs, uint16_t *H, int r, int g)
+{
+    f32x4 acc[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+    // two k steps in flight: enough loads to cover the latency without holding every step's
+    // fragments in registers
+#pragma unroll 2
+    for (int k0 = 0; k0 < K; k0 += 32) {
+        bf16x8 a;
+        if (FROM_X) {
+            const int row = row0 + r;
+            a = row < Mv ? ld8(X + (size_t)row * MLP_IN + k0 + 8 * g) : bf16x8{};
+        } else {
+            a = ld8(hs + r * MLP_STRIP_LD + k0 + 8 * g);
+        }
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const bf16x8 b = ld8(Wt + (size_t)(t * 16 + r) * K + k0 + 8 * g);
+            acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[t], 0, 0, 0);
+        }
+    }
+    __syncthreads();   // every lane's reads of the strip precede its overwrite
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        const float b = bias[t * 16 + r];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const uint16_t h = f2bf(fmaxf(acc[t][j] + b, 0.0f));
+            hs[(4 * g + j) * MLP_STRIP_LD + t * 16 + r] = h;
+            const int m = row0 + 4 * g + j;
+            if (KEEP_H && m < Mv) H[(size_t)m * MLP_H + t * 16 + r] = h;
+        }
+    }
+    __syncthreads();
+}
+template <bool KEEP_H>
+__global__ void __launch_bounds__(256, 4) k_mlp_fwd(const uint16_t *__restrict__ X, int M, const unsigned long long *cnt,
+                                                   int m_cidx, const uint16_t *__restrict__ wt,
+                                                   const float *__restrict__ w, size_t oW1, size_t ob1, size_t oW2,
+                                                   size_t ob2, size_t oW3, size_t ob3, size_t oW4, int nout, int col0,
+                                                   int ncols, float *__restrict__ out,
+                                                   const float *__restrict__ bias_out, uint16_t *H1, uint16_t *H2,
+                                                   uint16_t *H3)
+{
+    __shared__ __align__(16) uint16_t strip[4][16 * MLP_STRIP_LD];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int r = lane & 15, g = lane >> 4;
+    const int Mv = m_cidx >= 0 ? min(M, (int)cnt[m_cidx]) : M;
+    uint16_t *hs = strip[wave];
+    for (int tile = blockIdx.x; tile * MLP_FT_ROWS < Mv; tile += gridDim.x) {
+        const int row0 = tile * MLP_FT_ROWS + wave * 16;
+        mlp_fwd_layer<MLP_IN, true, KEEP_H>(X, row0, Mv, wt + oW1, w + ob1, hs, H1, r, g);
+        mlp_fwd_layer<MLP_H, false, KEEP_H>(X, row0, Mv, wt + oW2, w + ob2, hs, H2, r, g);
+        mlp_fwd_layer<MLP_H, false, KEEP_H>(X, row0, Mv, wt + oW3, w + ob3, hs, H3, r, g);
+        // output layer: 16 columns per MFMA tile, K = 64 in two steps
+        const bf16x8 a0 = ld8(hs + r * MLP_STRIP_LD + 8 * g), a1 = ld8(hs + r * MLP_STRIP_LD + 32 + 8 * g);
+#pragma unroll 1
+        for (int c0 = 0; c0 < ncols; c0 += 16) {
+            const int n = col0 + c0 + r;
+            const bool nin = c0 + r < ncols;
+            const uint16_t *wc = wt + oW4 + (size_t)n * MLP_H;
+            const bf16x8 b0 = nin ? ld8(wc + 8 * g) : bf16x8{}, b1 = nin ? ld8(wc + 32 + 8 * g) : bf16x8{};
+            f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, b0, acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, b1, acc, 0, 0, 0);
+            if (nin) {
+                const float bo = bias_out ? bias_out[c0 + r] : 0.0f;
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const int m = row0 + 4 * g + j;
+                    if (m < Mv) out[(size_t)m * ncols + c0 + r] = acc[j] + bo;
+                }
+            }
+        }
+        __syncthreads();   // the strip is rewritten by the next tile
+    }
+}
+
 // H = relu(Z + b) as bf16, rows < count
 __global__ void k_bias_relu(const float *Z, const float *bias, uint16_t *H, int M, int N,
                             const unsigned long long *cnt, int m_cidx)
@@ -101,16 +229,17 @@ __global__ void k_bias_relu(const float *Z, const float *bias, uint16_t *H, int 
 }
 
 // softmax cross entropy gradient of weighted samples: G = w_i (softmax(L_i + b) - onehot(S_i))
-// / sum w (bf16), over all n_out logits (one 256-thread block per row)
+// / sum w (bf16) over the first N columns of rows of stride ld (the other ld - N columns of G are
+// cleared), rows < min(M, cnt[m_cidx]) (one 256-thread block per row)
 __global__ void k_ce_grad(const float *L, const float *bias, const int *label, const float *weight,
-                          const float *wsum, int M, int N, uint16_t *G, const unsigned long long *cnt, int m_cidx)
+                          const float *wsum, int M, int N, int ld, uint16_t *G, const unsigned long long *cnt, int m_cidx)
 {
     const int row = blockIdx.x;
     const int Mv = m_cidx >= 0 ? min(M, (int)cnt[m_cidx]) : M;
     if (row >= Mv) return;
     const float wsum_inv = *wsum > 0.0f ? 1.0f / *wsum : 0.0f;
     __shared__ float red[256];
-    const float *l = L + (size_t)row * N;
+    const float *l = L + (size_t)row * ld;
     float mx = -3.0e38f;
     for (int j = threadIdx.x; j < N; j += blockDim.x) mx = fmaxf(mx, l[j] + bias[j]);
     red[threadIdx.x] = mx;
@@ -132,9 +261,132 @@ __global__ void k_ce_grad(const float *L, const float *bias, const int *label, c
     const float inv = 1.0f / red[0];
     const float w = weight[row] * wsum_inv;
     const int lab = label[row];
-    for (int j = threadIdx.x; j < N; j += blockDim.x) {
-        const float gj = w * (__expf(l[j] + bias[j] - mx) * inv - (j == lab ? 1.0f : 0.0f));
-        G[(size_t)row * N + j] = f2bf(gj);
+    for (int j = threadIdx.x; j < ld; j += blockDim.x) {
+        const float gj = j < N ? w * (__expf(l[j] + bias[j] - mx) * inv - (j == lab ? 1.0f : 0.0f)) : 0.0f;
+        G[(size_t)row * ld + j] = f2bf(gj);
+    }
+}
+
+// ------------------------------------------------------------------ vMF retrace-direction head
+// Lobe k of the raw outputs R (40 floats, bias included): unit mean (the raw direction
+// normalised; +z if it vanishes), concentration exp(clamp(log kappa)), mixture logit.
+__device__ __forceinline__ void vmf_lobe(const float *R, int k, float3 &mu, float &kappa, float &nrm)
+{
+    const float3 m = f3(R[5 * k], R[5 * k + 1], R[5 * k + 2]);
+    nrm = sqrtf(dot3(m, m));
+    mu = nrm > 1e-20f ? m * (1.0f / nrm) : f3(0.f, 0.f, 1.f);
+    kappa = expf(fminf(fmaxf(R[5 * k + 3], VMF_LOGK_MIN), VMF_LOGK_MAX));
+}
+// von Mises-Fisher density (solid angle): kappa / (2 pi (1 - exp(-2 kappa))) exp(-kappa h), with
+// h = 1 - mu.w written as |mu - w|^2 / 2 (no cancellation near the mean)
+__device__ __forceinline__ float vmf_lobe_pdf(float3 mu, float kappa, float3 w)
+{
+    const float3 d = mu - w;
+    const float h = 0.5f * dot3(d, d);
+    return kappa / (2.0f * PT_PI * -expm1f(-2.0f * kappa)) * expf(-kappa * h);
+}
+// lobe probabilities that the inverse-CDF draw below realises with a 24-bit uniform u0: lobe k
+// for c_{k-1} <= u0 < c_k (c = cumulative softmax of the lobe logits, the last one forced to 1),
+// so P(k) = below_prob(c_k) - below_prob(c_{k-1})
+__device__ __forceinline__ void vmf_weights(const float *R, float cdf[MLP_LOBES], float pr[MLP_LOBES])
+{
+    float mx = -3.0e38f;
+    for (int k = 0; k < MLP_LOBES; ++k) mx = fmaxf(mx, R[5 * k + 4]);
+    float e[MLP_LOBES], sum = 0.0f;
+    for (int k = 0; k < MLP_LOBES; ++k) { e[k] = expf(R[5 * k + 4] - mx); sum += e[k]; }
+    float c = 0.0f;
+    double prev = 0.0;
+    for (int k = 0; k < MLP_LOBES; ++k) {
+        c += e[k] / sum;
+        cdf[k] = k == MLP_LOBES - 1 ? 2.0f : c;
+        const double b = k == MLP_LOBES - 1 ? 1.0 : below_prob(c);
+        pr[k] = (float)(b - prev);
+        prev = b;
+    }
+}
+__device__ __forceinline__ float vmf_mix_pdf(const float *R, float3 w)
+{
+    float cdf[MLP_LOBES], pr[MLP_LOBES];
+    vmf_weights(R, cdf, pr);
+    float p = 0.0f;
+    for (int k = 0; k < MLP_LOBES; ++k) {
+        float3 mu;
+        float kappa, nrm;
+        vmf_lobe(R, k, mu, kappa, nrm);
+        p += pr[k] * vmf_lobe_pdf(mu, kappa, w);
+    }
+    return p;
+}
+// a direction from the mixture: the lobe by inverse CDF (u0), then h = 1 - mu.w =
+// -log(v + (1 - v) exp(-2 kappa)) / kappa with v = 1 - u1 in (0, 1] (the inverse CDF of the vMF's
+// cosine), the azimuth 2 pi u2 about the mean
+__device__ __forceinline__ float3 vmf_mix_sample(const float *R, float u0, float u1, float u2)
+{
+    float cdf[MLP_LOBES], pr[MLP_LOBES];
+    vmf_weights(R, cdf, pr);
+    int k = 0;
+    while (k < MLP_LOBES - 1 && !(u0 < cdf[k])) ++k;
+    float3 mu;
+    float kappa, nrm;
+    vmf_lobe(R, k, mu, kappa, nrm);
+    const float v = 1.0f - u1;
+    const float h = fminf(-logf(v + (1.0f - v) * expf(-2.0f * kappa)) / kappa, 2.0f);
+    const float st = sqrtf(fmaxf(h * (2.0f - h), 0.0f));
+    float3 t, b;
+    basis(mu, t, b);
+    float sp, cp;
+    sincosf(2.0f * PT_PI * u2, &sp, &cp);
+    return normalize3(mu * (1.0f - h) + (t * cp + b * sp) * st);
+}
+// gradient of the weighted negative log-likelihood of directions (rows [r0, r0 + nv) of L, stride
+// ld, the 40 mixture outputs from column c0; weights over their sum) into G (bf16, the other
+// columns of those rows cleared): lobe logit pi_k - r_k; log concentration
+// -r_k (1 - 2 kappa / (exp(2 kappa) - 1) - kappa h) inside the clamp; raw direction
+// -r_k kappa (w - (mu.w) mu) / |m|; r_k = pi_k p_k / p the lobe's responsibility
+__global__ void k_vmf_grad(const float *L, const float *bias, const float *dir, const float *weight,
+                           const float *wsum, int ld, int c0, uint16_t *G, const unsigned long long *cnt, int cap)
+{
+    const int nce = min((int)cnt[C_MLP_N], cap), nv = min((int)cnt[C_MLP_NV], cap);
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= nv) return;
+    const int row = nce + j;
+    float R[MLP_VMF];
+    for (int q = 0; q < MLP_VMF; ++q) R[q] = L[(size_t)row * ld + c0 + q] + bias[c0 + q];
+    const float3 w = f3(dir[3 * (size_t)j], dir[3 * (size_t)j + 1], dir[3 * (size_t)j + 2]);
+    const float ws = *wsum > 0.0f ? weight[j] / *wsum : 0.0f;
+    float mx = -3.0e38f;
+    for (int k = 0; k < MLP_LOBES; ++k) mx = fmaxf(mx, R[5 * k + 4]);
+    float pi[MLP_LOBES], pk[MLP_LOBES], sum = 0.0f, p = 0.0f;
+    for (int k = 0; k < MLP_LOBES; ++k) { pi[k] = expf(R[5 * k + 4] - mx); sum += pi[k]; }
+    for (int k = 0; k < MLP_LOBES; ++k) {
+        pi[k] /= sum;
+        float3 mu;
+        float kappa, nrm;
+        vmf_lobe(R, k, mu, kappa, nrm);
+        pk[k] = vmf_lobe_pdf(mu, kappa, w);
+        p += pi[k] * pk[k];
+    }
+    uint16_t *g = G + (size_t)row * ld;
+    for (int q = 0; q < c0; ++q) g[q] = 0;
+    for (int q = c0 + MLP_VMF; q < ld; ++q) g[q] = 0;
+    for (int k = 0; k < MLP_LOBES; ++k) {
+        float3 mu;
+        float kappa, nrm;
+        vmf_lobe(R, k, mu, kappa, nrm);
+        const float r = p > 0.0f ? pi[k] * pk[k] / p : 0.0f;
+        const float3 d = mu - w;
+        const float h = 0.5f * dot3(d, d);
+        const float two_k = 2.0f * kappa;
+        const float ratio = two_k < 80.0f ? two_k / expm1f(two_k) : 0.0f;
+        const float s = R[5 * k + 3];
+        const float gs = (s > VMF_LOGK_MIN && s < VMF_LOGK_MAX) ? -r * (1.0f - ratio - kappa * h) : 0.0f;
+        const float cw = dot3(mu, w);
+        const float3 gm = nrm > 1e-20f ? (w - mu * cw) * (-r * kappa / nrm) : f3(0.f, 0.f, 0.f);
+        g[c0 + 5 * k + 0] = f2bf(ws * gm.x);
+        g[c0 + 5 * k + 1] = f2bf(ws * gm.y);
+        g[c0 + 5 * k + 2] = f2bf(ws * gm.z);
+        g[c0 + 5 * k + 3] = f2bf(ws * gs);
+        g[c0 + 5 * k + 4] = f2bf(ws * (pi[k] - r));
     }
 }
 
@@ -165,12 +417,12 @@ __global__ void k_colsum(const uint16_t *G, int M, int N, float *db, const unsig
 
 // Adam (Kingma and Ba): m = b1 m + (1-b1) g, v = b2 v + (1-b2) g^2, w -= lr mhat / (sqrt(vhat) + eps)
 // with the bias corrections of step t = cnt[C_MLP_T] + 1; refreshes the bf16 copy and clears the
-// gradient. Runs only when this iteration recorded training samples.
+// gradient. Runs only when this iteration has training rows.
 __global__ void k_adam(float *w, uint16_t *wb, float *g, float *m, float *v, int n, float lr, float b1, float b2,
                        float eps, const unsigned long long *cnt)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n || cnt[C_MLP_N] == 0) return;
+    if (i >= n || cnt[C_MLP_ROWS] == 0) return;
     const float t = (float)(cnt[C_MLP_T] + 1ull);
     const float bc1 = 1.0f - powf(b1, t), bc2 = 1.0f - powf(b2, t);
     const float gi = g[i];
@@ -185,7 +437,7 @@ __global__ void k_adam(float *w, uint16_t *wb, float *g, float *m, float *v, int
 // Adam step counter, after k_adam
 __global__ void k_mlp_tick(unsigned long long *cnt)
 {
-    if (threadIdx.x == 0 && blockIdx.x == 0 && cnt[C_MLP_N] != 0) cnt[C_MLP_T] += 1ull;
+    if (threadIdx.x == 0 && blockIdx.x == 0 && cnt[C_MLP_ROWS] != 0) cnt[C_MLP_T] += 1ull;
 }
 
 // He-uniform weights, zero biases (output layer scaled by 0.1 so the first softmax is near
@@ -239,7 +491,9 @@ __global__ void k_add_bias(float *L, const float *bias, int M, int N)
 // Selection of the specular subspace for every proxy item: with probability `mix` from the
 // network's softmax restricted to the non-empty subspaces (inverse CDF), otherwise from the
 // plain row (Gamma alias row, or uniform over the non-empty subspaces). The probability of
-// the chosen S under the mixture is written with it: aux.z = S (bits), aux.w = pi_S.
+// the chosen S under the mixture is written with it: aux.z = S (bits), aux.w = pi_S; then an
+// incomplete sub-path of S uniformly: mis.z = its index (bits), mis.w = its overall selection
+// probability. L holds n_out logits per row (bias not included).
 __global__ void k_mlp_select(EyeBuf E, SubDev D, const float *L, const float *bias, int n_out, float mix, int gamma_on,
                              uint32_t seed, const unsigned long long *cnt)
 {
@@ -248,7 +502,11 @@ __global__ void k_mlp_select(EyeBuf E, SubDev D, const float *L, const float *bi
     ProxyItem &it = E.proxy[i];
     // the subspace lists are rebuilt only in iterations that keep candidates
     const int ne = cnt[C_NFINAL] > 0 ? min(*D.n_nonempty, D.n_spec) : 0;
-    if (ne <= 0) { it.aux.z = __int_as_float(-1); it.aux.w = 0.0f; return; }
+    if (ne <= 0) {
+        it.aux.z = __int_as_float(-1); it.aux.w = 0.0f;
+        it.mis.z = __int_as_float(-1); it.mis.w = 0.0f;
+        return;
+    }
     const int T = __float_as_int(it.aux.x);
     const float *l = L + (size_t)i * n_out;
     Rng r = rng_make(seed, S_MLP, (uint32_t)__float_as_int(it.beta.w), (uint32_t)cnt[C_ITER], 1u);
@@ -289,17 +547,34 @@ __global__ void k_mlp_select(EyeBuf E, SubDev D, const float *L, const float *bi
     }
     // the mixture weight the 24-bit draw u0 < mix realises
     const double m = below_prob(mix);
+    const double piS = m * learned + (1.0 - m) * plain;
     it.aux.z = __int_as_float(S);
-    it.aux.w = (float)(m * learned + (1.0 - m) * plain);
+    it.aux.w = (float)piS;
+    // then the incomplete sub-path uniformly within S: its index and overall selection probability
+    const int cs = D.s_count[S];
+    if (cs > 0) {
+        const int k = index_of(rng_u32(r), cs);
+        it.mis.z = __int_as_float(D.s_list[D.s_off[S] + k]);
+        it.mis.w = (float)(piS * index_prob(k, cs));
+    } else {
+        it.mis.z = __int_as_float(-1);
+        it.mis.w = 0.0f;
+    }
 }
 
-// One training sample per valid proxy contribution of a learning iteration: the features of the
-// first diffuse eye vertex, the selected subspace and the contribution's luminance as weight.
+// Training samples of a learning iteration, one per valid proxy contribution: for the subspace
+// head the features of the first diffuse eye vertex, the selected subspace and the
+// contribution's luminance as weight; for the direction head the features of y_{s-1} (direction
+// toward z_d), the first retrace direction and the same weight (retraces from glossy y_{s-1}).
 struct MlpTrain {
     float *feat;     // [cap x 9]
     int *label;      // [cap]
     float *weight;   // [cap]
     float *wsum;     // [1]
+    float *vfeat;    // [cap x 9]
+    float *vdir;     // [cap x 3]
+    float *vweight;  // [cap]
+    float *vwsum;    // [1]
     int cap;
 };
 __device__ __forceinline__ void mlp_record(const SceneDev &S, const MlpTrain &T, unsigned long long *cnt, float3 x,
@@ -313,4 +588,63 @@ __device__ __forceinline__ void mlp_record(const SceneDev &S, const MlpTrain &T,
     T.label[slot] = Ssel;
     T.weight[slot] = w;
     unsafeAtomicAdd(T.wsum, w);
+}
+__device__ __forceinline__ void mlp_record_dir(const SceneDev &S, const MlpTrain &T, unsigned long long *cnt, float3 x,
+                                               float3 n, float3 wo, float3 dir, float w)
+{
+    const int slot = (int)atomicAdd(cnt + C_MLP_NV, 1ull);
+    if (slot >= T.cap) return;
+    float f[9];
+    feat9(S, x, n, wo, f);
+    for (int j = 0; j < 9; ++j) T.vfeat[9 * (size_t)slot + j] = f[j];
+    T.vdir[3 * (size_t)slot] = dir.x; T.vdir[3 * (size_t)slot + 1] = dir.y; T.vdir[3 * (size_t)slot + 2] = dir.z;
+    T.vweight[slot] = w;
+    unsafeAtomicAdd(T.vwsum, w);
+}
+// rows of this iteration's training batch: the subspace samples, then the direction samples
+__global__ void k_mlp_rows(unsigned long long *cnt, int cap)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0)
+        cnt[C_MLP_ROWS] = (unsigned long long)(min((int)cnt[C_MLP_N], cap) + min((int)cnt[C_MLP_NV], cap));
+}
+// encoded rows of the training batch (subspace rows first)
+__global__ void k_mlp_enc_train(MlpTrain T, const unsigned long long *cnt, uint16_t *X)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int nce = min((int)cnt[C_MLP_N], T.cap), nv = min((int)cnt[C_MLP_NV], T.cap);
+    if (i >= nce + nv) return;
+    const float *src = i < nce ? T.feat + 9 * (size_t)i : T.vfeat + 9 * (size_t)(i - nce);
+    float f[9];
+    for (int j = 0; j < 9; ++j) f[j] = src[j];
+    mlp_encode(f, X + (size_t)i * MLP_IN);
+}
+// features of every proxy item's chosen y_{s-1} (position, normal, direction toward z_d) ->
+// encoded rows of X (zeros for an item without a choice)
+__global__ void k_mlp_enc_retrace(SceneDev S, const ProxyItem *items, const Cand *cand, const unsigned long long *cnt,
+                                  uint16_t *X)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (int)cnt[C_PROXYQ]) return;
+    const ProxyItem &p = items[i];
+    const int ci = __float_as_int(p.mis.z);
+    float f[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    if (ci >= 0 && p.mis.w > 0.0f) {
+        const Cand &c = cand[ci];
+        const float3 v = xyz(c.v);
+        feat9(S, v, S.shade[__float_as_int(c.v.w)].n, normalize3(xyz(p.x) - v), f);
+    }
+    mlp_encode(f, X + (size_t)i * MLP_IN);
+}
+// test hook: n draws from the mixtures raw[n][40] (bias included) with their mixture density
+__global__ void k_vmf_hook(const float *raw, int n, uint32_t seed, float *dir, float *pdf)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    float R[MLP_VMF];
+    for (int q = 0; q < MLP_VMF; ++q) R[q] = raw[(size_t)i * MLP_VMF + q];
+    Rng r = rng_make(seed, S_MLP, (uint32_t)i, 7u, 0u);
+    const float u0 = rng_f(r), u1 = rng_f(r), u2 = rng_f(r);
+    const float3 w = vmf_mix_sample(R, u0, u1, u2);
+    dir[3 * (size_t)i] = w.x; dir[3 * (size_t)i + 1] = w.y; dir[3 * (size_t)i + 2] = w.z;
+    pdf[i] = vmf_mix_pdf(R, w);
 }

@@ -25,6 +25,8 @@ PT_FLAG_MLP = 1 << 9
 PT_FLAG_SPC = 1 << 10
 PT_FLAG_LT = 1 << 11
 PT_FLAG_BOOTH = 1 << 12
+PT_FLAG_MLP_DIR = 1 << 13
+MLP_VMF = 40   # outputs of the direction head after the n_spec logits
 
 PT_EST_ITILDE = 0
 PT_EST_SIGN = 1
@@ -34,7 +36,7 @@ EXPORTED = ["pt_scene_upload", "pt_scene_release", "pt_build_subspaces", "pt_ren
             "pt_render_scenes", "pt_autotune",
             "pt_mlp_param_count", "pt_mlp_set_params", "pt_mlp_get_params", "pt_mlp_forward", "pt_mlp_train_step",
             "pt_reciprocal_estimate", "pt_resolve_image", "pt_trace_closest", "pt_scene_totals",
-            "pt_selection_tables", "pt_philox", "pt_bvh_stats", "pt_last_error"]
+            "pt_selection_tables", "pt_philox", "pt_bvh_stats", "pt_vmf_sample", "pt_last_error"]
 
 
 class SceneDesc(ctypes.Structure):
@@ -129,7 +131,8 @@ def lib():
         L.pt_mlp_set_params.argtypes = [P, P, I, P]
         L.pt_mlp_get_params.argtypes = [P, P, I, P]
         L.pt_mlp_forward.argtypes = [P, P, I, P, P]
-        L.pt_mlp_train_step.argtypes = [P, P, P, P, I, ctypes.c_float, P, P]
+        L.pt_mlp_train_step.argtypes = [P, P, P, P, I, P, P, P, I, ctypes.c_float, P, P]
+        L.pt_vmf_sample.argtypes = [P, I, ctypes.c_uint32, P, P, P]
         L.pt_scene_totals.argtypes = [P, ctypes.POINTER(Totals), I, P]
         L.pt_selection_tables.argtypes = [P, I, I, I, P, P, P, P, P, P, P]
         L.pt_philox.argtypes = [P, I, P, P]
@@ -250,15 +253,21 @@ class Scene:
         _check(lib().pt_mlp_get_params(self.h, a.ctypes.data, int(a.size), _stream(stream)))
         return a
 
-    def mlp_forward(self, feat, logits, stream=None):
-        """feat: float32 device [n, 9]; logits: float32 device [n, n_spec]."""
-        _check(lib().pt_mlp_forward(self.h, _ptr(feat), int(feat.shape[0]), _ptr(logits), _stream(stream)))
+    def mlp_forward(self, feat, out, stream=None):
+        """feat: float32 device [n, 9]; out: float32 device [n, n_spec + MLP_VMF] (logits, then the
+        direction head's mixture outputs; bias included)."""
+        _check(lib().pt_mlp_forward(self.h, _ptr(feat), int(feat.shape[0]), _ptr(out), _stream(stream)))
 
-    def mlp_train_step(self, feat, label, weight, lr, want_grad=False, stream=None):
-        """One Adam step on weighted samples (device tensors); returns the gradient when asked."""
+    def mlp_train_step(self, feat, label, weight, lr, feat_dir=None, dirs=None, weight_dir=None, want_grad=False,
+                       stream=None):
+        """One Adam step on weighted subspace samples and (optionally) weighted direction samples
+        (device tensors); returns the gradient when asked."""
         g = np.empty(self.mlp_param_count(), dtype=np.float32) if want_grad else None
-        _check(lib().pt_mlp_train_step(self.h, _ptr(feat), _ptr(label), _ptr(weight), int(feat.shape[0]), float(lr),
-                                       g.ctypes.data if g is not None else None, _stream(stream)))
+        n = int(feat.shape[0]) if feat is not None else 0
+        nd = int(feat_dir.shape[0]) if feat_dir is not None else 0
+        _check(lib().pt_mlp_train_step(self.h, _ptr(feat), _ptr(label), _ptr(weight), n, _ptr(feat_dir), _ptr(dirs),
+                                       _ptr(weight_dir), nd, float(lr), g.ctypes.data if g is not None else None,
+                                       _stream(stream)))
         return g
 
     def totals(self, reset=False, stream=None):
@@ -296,6 +305,11 @@ def reciprocal_table(f, q, B, n_est, out, nsamples, estimator=PT_EST_ITILDE, see
 def philox(inp, out, stream=None):
     """inp: int32/uint32 device tensor [n, 6] (counter 0..3, key 0..1); out: [n, 4] (device)."""
     _check(lib().pt_philox(_ptr(inp), int(inp.shape[0]), _ptr(out), _stream(stream)))
+
+
+def vmf_sample(raw, seed, dirs, pdf, stream=None):
+    """raw: float32 device [n, 40] mixtures; writes dirs [n, 3] and pdf [n] (device)."""
+    _check(lib().pt_vmf_sample(_ptr(raw), int(raw.shape[0]), int(seed), _ptr(dirs), _ptr(pdf), _stream(stream)))
 
 
 def bvh_stats(tri):

@@ -364,8 +364,9 @@ def formfactor_plane(mirror=False, width=8, height=8):
     return b.build(cam, width, height)
 
 
-def mirror_room(width=16, height=16):
-    """Small diffuse room with a ceiling light, a tilted perfect mirror and a coarse glass ball.
+def mirror_room(width=16, height=16, mirror_roughness=0.0):
+    """Small diffuse room with a ceiling light, a tilted perfect mirror and a coarse glass ball
+    (mirror_roughness > 0: a glossy GGX conductor in place of the perfect mirror).
 
     Produces short proxy-class paths of both classes (light -> mirror -> floor, light -> glass
     -> floor, light -> wall -> mirror -> floor) that unidirectional path tracing also finds
@@ -376,7 +377,7 @@ def mirror_room(width=16, height=16):
     b.add_tris(box_tris([-1, 0, -1], [1, 2, 1], n=1, inward=True), wall)
     light = b.add_material(material(MAT_LAMBERT, (0.0, 0.0, 0.0), le=(8.0, 8.0, 8.0)))
     b.add_rect((0.3, 1.99, 0.0), (0.3, 0, 0), (0, 0, 0.3), (0, -1, 0), light)
-    mir = b.add_material(material(MAT_CONDUCTOR, (0.95, 0.95, 0.95), roughness=0.0))
+    mir = b.add_material(material(MAT_CONDUCTOR, (0.95, 0.95, 0.95), roughness=mirror_roughness))
     c = np.array([-0.6, 1.0, 0.0])
     n = np.array([1.0, -0.35, 0.0])
     n /= np.linalg.norm(n)
@@ -390,6 +391,76 @@ def mirror_room(width=16, height=16):
     return b.build(cam, width, height)
 
 
+def serving_scene(seed, width, height, target_tris):
+    """One scene of the batched serving workload: a room shell with two ceiling lights and about
+    24 objects on a grid, `target_tris` triangles in all. Per object: 25 % perfect mirror, 25 %
+    smooth dielectric (IOR U[1.3, 1.7]), 25 % GGX conductor (roughness U[0.001, 0.05]), 25 %
+    Lambert (albedo U[0.2, 0.8]); so that mirror/glass chains of several specular vertices occur."""
+    rng = _rng(1000 + seed)
+    b = Builder()
+    lo, hi = np.array([-4.0, 0.0, -4.0]), np.array([4.0, 4.0, 4.0])
+    shell = b.add_material(material(MAT_LAMBERT, (0.6, 0.6, 0.6)))
+    b.add_tris(box_tris(lo, hi, n=1, inward=True), shell)
+    lm = b.add_material(material(MAT_LAMBERT, (0.0, 0.0, 0.0), le=(16.0, 16.0, 16.0)))
+    for cx in (-1.5, 1.5):
+        b.add_rect((cx, 3.99, 0.0), (0.4, 0, 0), (0, 0, 0.4), (0, -1, 0), lm)
+    n_obj = 24
+    per_obj = max(20.0, (target_tris - 16) / n_obj)
+    gx, gz = 6, 4
+    for k in range(n_obj):
+        i, j = k % gx, k // gx
+        size = rng.uniform(0.5, 2.0) * 0.4
+        cx = -3.3 + 6.6 * (i + 0.5) / gx + rng.uniform(-0.1, 0.1)
+        cz = -3.3 + 6.6 * (j + 0.5) / gz + rng.uniform(-0.1, 0.1)
+        cy = size + rng.uniform(0.0, 1.2)
+        u = rng.uniform()
+        if u < 0.25:
+            m = b.add_material(material(MAT_CONDUCTOR, (0.95, 0.95, 0.95), roughness=0.0))
+        elif u < 0.5:
+            m = b.add_material(material(MAT_DIELECTRIC, ior=rng.uniform(1.3, 1.7)))
+        elif u < 0.75:
+            m = b.add_material(material(MAT_CONDUCTOR, tuple(rng.uniform(0.5, 1.0, 3)),
+                                        roughness=rng.uniform(0.001, 0.05)))
+        else:
+            m = b.add_material(material(MAT_LAMBERT, tuple(rng.uniform(0.2, 0.8, 3))))
+        if rng.uniform() < 0.5:
+            # icosphere with the subdivision closest to the per-object budget (20 * 4^s triangles)
+            sub = int(np.clip(round(math.log(per_obj / 20.0, 4)), 0, 8))
+            v, f = icosphere(sub)
+            freq = rng.uniform(2.0, 5.0, 3)
+            phase = rng.uniform(0, 2 * np.pi, 3)
+            disp = 1.0 + 0.1 * np.sin(freq[0] * v[:, 0] + phase[0]) * np.sin(freq[1] * v[:, 1] + phase[1]) \
+                * np.sin(freq[2] * v[:, 2] + phase[2])
+            v = v * disp[:, None] * size + np.array([cx, cy, cz])
+            b.add_tris(mesh_to_tris(v, f), m)
+        else:
+            n = max(1, int(round(math.sqrt(per_obj / 12.0))))
+            ext = size * rng.uniform(0.6, 1.0, 3)
+            b.add_tris(box_tris([cx, cy, cz] - ext, [cx, cy, cz] + ext, n=n), m)
+    cam = [0.0, 2.0, 3.9, 0.0, 1.0, -1.0, 0.0, 1.0, 0.0, 60.0]
+    return b.build(cam, width, height)
+
+
+SERVING_RES = ((256, 256), (640, 480), (1280, 720), (1920, 1080))
+
+
+def serving_batch(n_scenes=16, key=4, max_tris=2_000_000, res_cap=None):
+    """The 16 scenes of the batched serving workload (config 4): scene i has a triangle budget
+    drawn log-uniformly from [10^3, max_tris] and a resolution drawn from SERVING_RES (res_cap
+    limits the resolution index, for small test runs). Returns a list of (scene, spec) pairs."""
+    rng = _rng(key)
+    out = []
+    for i in range(n_scenes):
+        tris = int(round(math.exp(rng.uniform(math.log(1e3), math.log(max_tris)))))
+        r = int(rng.integers(0, len(SERVING_RES)))
+        if res_cap is not None:
+            r = min(r, res_cap)
+        w, h = SERVING_RES[r]
+        sc = serving_scene(i, w, h, tris)
+        out.append((sc, dict(target_tris=tris, width=w, height=h)))
+    return out
+
+
 CONFIGS = {
     0: dict(scene=lambda: cornell_glass(64, 64), spp=16, max_depth=8, n_light=4096, cand_cap=400,
             n_subspaces=64, n_spec=64, n_ctrl=10, seed=0),
@@ -397,6 +468,11 @@ CONFIGS = {
             n_subspaces=1000, n_spec=100, n_ctrl=10, seed=0),
     2: dict(scene=lambda: glossy_procedural(1024, 1024), spp=256, max_depth=12, n_light=262_144,
             cand_cap=10_486, n_subspaces=1000, n_spec=100, n_ctrl=10, seed=0),
+    # config 2's scene with the learned selection: 10 % defensive plain sampling, online training
+    # on up to 65,536 contribution samples per iteration, Adam step 1e-3
+    3: dict(scene=lambda: glossy_procedural(1024, 1024), spp=256, max_depth=12, n_light=262_144,
+            cand_cap=10_486, n_subspaces=1000, n_spec=100, n_ctrl=10, seed=0, mlp=True, mlp_mix=0.9,
+            mlp_lr=1e-3, train_iters=1_000_000),
 }
 
 

@@ -11,7 +11,7 @@ import bench_ablation as ba  # noqa: E402
 
 def _flags():
     names = ["NEE", "PROXY", "ONLY_PROXY_CLASS", "ONLY_OTHER", "GAMMA", "TILES", "TIMING", "COUNT", "MIS", "MLP",
-             "SPC", "LT", "BOOTH"]
+             "SPC", "LT", "BOOTH", "MLP_DIR"]
     return types.SimpleNamespace(**{f"PT_FLAG_{n}": 1 << i for i, n in enumerate(names)})
 
 
@@ -46,3 +46,13 @@ def test_trimmed_mean_ignores_a_single_firefly():
     assert m2.mean() > 50 * m.mean()
     assert abs(base - np.sort(m.ravel())[: int(0.999 * m.size)].mean()) < 1e-15
     assert abs(base - 0.5) < 0.02
+
+
+def test_learned_variants_add_only_the_network():
+    pt = _flags()
+    v = ba.variants("learned", pt)
+    assert [n for n, _, _ in v] == ["plain", "learned", "learned_selection"]
+    plain = v[0][1]
+    assert plain & pt.PT_FLAG_MIS and not plain & (pt.PT_FLAG_MLP | pt.PT_FLAG_MLP_DIR)
+    assert v[1][1] == plain | pt.PT_FLAG_MLP | pt.PT_FLAG_MLP_DIR
+    assert v[2][1] == plain | pt.PT_FLAG_MLP

@@ -23,6 +23,7 @@ from synth import scenes  # noqa: E402
 
 pytestmark = pytest.mark.gpu
 N_SPEC = 24
+N_OUT = N_SPEC + mlp.VMF_OUT   # logits, then the direction head's mixture
 
 
 @pytest.fixture(scope="module")
@@ -34,7 +35,7 @@ def scene():
     s.release()
 
 
-def _params(rng, n_out=N_SPEC):
+def _params(rng, n_out=N_OUT):
     blocks = {}
     for name, shape in mlp.layout(n_out):
         if len(shape) == 2:
@@ -58,7 +59,7 @@ def _cos(a, b):
 def test_forward_matches_oracle(scene, n):
     rng = np.random.default_rng(10 + n)
     p = _params(rng)
-    assert scene.mlp_param_count() == p.size == mlp.count(N_SPEC)
+    assert scene.mlp_param_count() == p.size == mlp.count(N_OUT)
     scene.mlp_set_params(p)
     np.testing.assert_array_equal(scene.mlp_get_params(), p)
     feat = rng.uniform(0.0, 1.0, size=(n, 9))
@@ -66,36 +67,50 @@ def test_forward_matches_oracle(scene, n):
     feat[:, 3:6] /= np.linalg.norm(feat[:, 3:6], axis=1, keepdims=True)
     feat[:, 6:9] /= np.linalg.norm(feat[:, 6:9], axis=1, keepdims=True)
     fd = torch.tensor(feat, dtype=torch.float32, device="cuda")
-    out = torch.full((n, N_SPEC), float("nan"), dtype=torch.float32, device="cuda")
+    out = torch.full((n, N_OUT), float("nan"), dtype=torch.float32, device="cuda")
     scene.mlp_forward(fd, out)
     torch.cuda.synchronize()
     got = out.double().cpu().numpy()
-    ref, _ = mlp.forward(p.astype(np.float64), N_SPEC, feat.astype(np.float32).astype(np.float64))
+    ref, _ = mlp.forward(p.astype(np.float64), N_OUT, feat.astype(np.float32).astype(np.float64))
     print(f"forward n={n}: rel-L2 {_rel(got, ref):.2e}", flush=True)
     assert np.all(np.isfinite(got))
     assert _rel(got, ref) < 2e-2
     assert _cos(got.ravel(), ref.ravel()) > 0.999
 
 
-@pytest.mark.parametrize("n", [300, 5003])
-def test_gradient_and_adam_match_oracle(scene, n):
-    rng = np.random.default_rng(20 + n)
+def _unit(rng, n):
+    w = rng.normal(size=(n, 3))
+    return w / np.linalg.norm(w, axis=1, keepdims=True)
+
+
+@pytest.mark.parametrize("n,n_dir", [(300, 0), (5003, 0), (0, 2000), (5003, 4001)])
+def test_gradient_and_adam_match_oracle(scene, n, n_dir):
+    """Subspace rows (cross entropy of the logits) and direction rows (negative log-likelihood under
+    the vMF mixture) in one training batch, against the oracle's gradient of the same loss."""
+    rng = np.random.default_rng(20 + n + 7 * n_dir)
     p = _params(rng)
     scene.mlp_set_params(p)
     feat = rng.uniform(0.0, 1.0, size=(n, 9))
     label = rng.integers(0, N_SPEC, size=n)
     weight = rng.exponential(1.0, size=n)
-    dev = lambda a, dt: torch.tensor(a, dtype=dt, device="cuda")  # noqa: E731
+    fv = rng.uniform(0.0, 1.0, size=(n_dir, 9))
+    dv = _unit(rng, n_dir)
+    wv = rng.exponential(1.0, size=n_dir)
+    dev = lambda a, dt: torch.tensor(a, dtype=dt, device="cuda") if len(a) else None  # noqa: E731
     lr = 1e-3
     g = scene.mlp_train_step(dev(feat, torch.float32), dev(label, torch.int32), dev(weight, torch.float32), lr,
-                             want_grad=True)
-    ref = mlp.grad(p.astype(np.float64), N_SPEC, feat.astype(np.float32).astype(np.float64), label,
-                   weight.astype(np.float32).astype(np.float64))
-    f64, w64 = feat.astype(np.float32).astype(np.float64), weight.astype(np.float32).astype(np.float64)
-    scale = mlp.grad_scale(p.astype(np.float64), N_SPEC, f64, label, w64)
-    ref16 = mlp.grad(p.astype(np.float64), N_SPEC, f64, label, w64, bf16=True)
+                             feat_dir=dev(fv, torch.float32), dirs=dev(dv, torch.float32),
+                             weight_dir=dev(wv, torch.float32), want_grad=True)
+    c = lambda a: a.astype(np.float32).astype(np.float64)  # noqa: E731
+    f64, w64 = c(feat), c(weight)
+    vmf = (c(fv), c(dv), c(wv)) if n_dir else None
+    fe = f64 if n else None
+    kw = dict(n_spec=N_SPEC, vmf=vmf)
+    ref = mlp.grad(p.astype(np.float64), N_OUT, fe, label, w64, **kw)
+    scale = mlp.grad_scale(p.astype(np.float64), N_OUT, fe, label, w64, **kw)
+    ref16 = mlp.grad(p.astype(np.float64), N_OUT, fe, label, w64, bf16=True, **kw)
     off, bad = 0, []
-    for name, shape in mlp.layout(N_SPEC):
+    for name, shape in mlp.layout(N_OUT):
         k = int(np.prod(shape))
         a, b, b16 = g[off:off + k].astype(np.float64), ref[off:off + k], ref16[off:off + k]
         e64, e16, model = (float(np.linalg.norm(a - b)), float(np.linalg.norm(a - b16)),
@@ -113,3 +128,56 @@ def test_gradient_and_adam_match_oracle(scene, n):
     g32 = g.astype(np.float32)
     expect = p - np.float32(lr) * g32 / (np.abs(g32) + np.float32(1e-8))
     np.testing.assert_allclose(p1, expect, rtol=1e-6, atol=1e-8)
+
+
+def test_vmf_sampler_matches_its_density():
+    """The retrace's vMF mixture sampler on the device: its reported density equals the oracle's
+    mixture density at the drawn direction; a single lobe's draws follow the vMF law of the cosine to
+    the mean (Kolmogorov-Smirnov against (1 - exp(-kappa h)) / (1 - exp(-2 kappa)), h = 1 - mu.w);
+    the lobes of a mixture are drawn with their weights."""
+    from paper_2503_23412_amd import pt
+    from scipy import stats
+    rng = np.random.default_rng(40)
+    n = 1 << 18
+    raw = np.zeros((n, 40), np.float32)
+    for k in range(8):
+        raw[:, 5 * k:5 * k + 3] = _unit(rng, n) * rng.uniform(0.5, 3.0, size=(n, 1))
+        raw[:, 5 * k + 3] = rng.uniform(-2.5, 9.5, size=n)
+        raw[:, 5 * k + 4] = rng.normal(size=n)
+    rd = torch.tensor(raw, device="cuda")
+    dirs = torch.empty((n, 3), device="cuda")
+    pdf = torch.empty(n, device="cuda")
+    pt.vmf_sample(rd, 11, dirs, pdf)
+    torch.cuda.synchronize()
+    w, pg = dirs.double().cpu().numpy(), pdf.double().cpu().numpy()
+    np.testing.assert_allclose(np.linalg.norm(w, axis=1), 1.0, atol=1e-6)
+    po = mlp.vmf_pdf(raw.astype(np.float64), w)
+    rel = np.abs(pg - po) / po
+    print(f"vmf density: max rel {rel.max():.2e} median {np.median(rel):.2e}", flush=True)
+    assert np.quantile(rel, 0.999) < 1e-4 and rel.max() < 1e-3
+    for kappa in (0.2, 5.0, 3000.0):
+        mu = np.array([0.0, 0.6, 0.8])
+        raw1 = np.zeros((n, 40), np.float32)
+        raw1[:, 0:3] = mu * 2.0
+        raw1[:, 3] = np.log(kappa)
+        raw1[:, 4] = 60.0
+        pt.vmf_sample(torch.tensor(raw1, device="cuda"), 12, dirs, pdf)
+        torch.cuda.synchronize()
+        w = dirs.double().cpu().numpy()
+        h = np.maximum(1.0 - w @ mu, 0.0)
+        cdf = lambda x: -np.expm1(-kappa * x) / -np.expm1(-2 * kappa)  # noqa: E731
+        pv = stats.kstest(h, cdf).pvalue
+        print(f"vmf lobe kappa {kappa}: KS p {pv:.3g}", flush=True)
+        assert pv > 1e-4
+    means = _unit(np.random.default_rng(41), 8)
+    logits = np.array([0.0, 1.0, -1.0, 0.5, 2.0, -2.0, 0.0, 0.3], np.float32)
+    raw2 = np.zeros((n, 40), np.float32)
+    for k in range(8):
+        raw2[:, 5 * k:5 * k + 3] = means[k]
+        raw2[:, 5 * k + 3] = np.log(5000.0)
+        raw2[:, 5 * k + 4] = logits[k]
+    pt.vmf_sample(torch.tensor(raw2, device="cuda"), 13, dirs, pdf)
+    torch.cuda.synchronize()
+    k = (dirs.double().cpu().numpy() @ means.T).argmax(1)
+    pi = np.exp(logits.astype(np.float64)) / np.exp(logits.astype(np.float64)).sum()
+    assert stats.chisquare(np.bincount(k, minlength=8), pi * n).pvalue > 1e-4

@@ -227,3 +227,147 @@ def test_fp32_argument_encoding():
         # fp32(pi) and the product each round by at most half an ulp (2^-24 relative)
         bound = 2.0 ** b * np.pi * 2 * 2.0 ** -24 * 1.01 + 1e-15
         assert np.all(np.abs(X32[:, cols] - X[:, cols]) <= bound)
+
+
+# ------------------------------------------------------------------ vMF retrace-direction head
+def _unit(rng, n):
+    w = rng.normal(size=(n, 3))
+    return w / np.linalg.norm(w, axis=1, keepdims=True)
+
+
+@pytest.mark.parametrize("log_kappa", [-3.0, 0.0, np.log(30.0), np.log(2.0e4)])
+def test_vmf_lobe_density_integrates_to_one(log_kappa):
+    """The lobe density, evaluated at directions on the sphere, integrates to one over the sphere
+    (quadrature in the polar angle about a tilted mean, uniform in azimuth; dense near the mean
+    for large concentrations), and its mixture with identical lobes is that lobe."""
+    from scipy import integrate
+    kappa = float(np.exp(log_kappa))
+    mu = np.array([0.3, -0.5, 0.8])
+    mu /= np.linalg.norm(mu)
+    a = np.cross(mu, [1.0, 0.0, 0.0])
+    a /= np.linalg.norm(a)
+    b = np.cross(mu, a)
+
+    def ring(theta):
+        ph = np.linspace(0.0, 2 * np.pi, 64, endpoint=False)
+        w = (np.cos(theta) * mu[None, :] + np.sin(theta) * (np.cos(ph)[:, None] * a + np.sin(ph)[:, None] * b))
+        return float(mlp.vmf_lobe_pdf(mu[None, :], np.full(64, kappa), w).mean()) * 2 * np.pi * np.sin(theta)
+
+    pts = [t for t in (0.5 / np.sqrt(kappa), 2 / np.sqrt(kappa), 8 / np.sqrt(kappa)) if t < np.pi]
+    tot, _ = integrate.quad(ring, 0.0, np.pi, points=pts, limit=400, epsabs=1e-12, epsrel=1e-10)
+    assert tot == pytest.approx(1.0, rel=1e-7)
+    # a mixture of eight copies of the lobe is the lobe
+    R = np.zeros((5, 40))
+    for k in range(8):
+        R[:, 5 * k:5 * k + 3] = mu * 2.5
+        R[:, 5 * k + 3] = log_kappa
+        R[:, 5 * k + 4] = 0.7 * k
+    w = _unit(np.random.default_rng(1), 5)
+    np.testing.assert_allclose(mlp.vmf_pdf(R, w), mlp.vmf_lobe_pdf(mu[None, :], np.full(5, kappa), w), rtol=1e-13)
+
+
+def test_vmf_sampling_matches_its_density():
+    """Samples of one lobe: the cosine to the mean has the vMF's law (CDF (1 - exp(-kappa h)) /
+    (1 - exp(-2 kappa)) of h = 1 - mu.w, Kolmogorov-Smirnov) and mean coth(kappa) - 1/kappa; the
+    azimuth is uniform; the lobes of a mixture are drawn with their weights."""
+    from scipy import stats
+    rng = np.random.default_rng(2)
+    n = 200_000
+    for kappa in (0.2, 5.0, 3000.0):
+        mu = np.array([0.0, 0.6, 0.8])
+        R = np.zeros((n, 40))
+        R[:, 0:3] = mu * 3.0
+        R[:, 3] = np.log(kappa)
+        R[:, 4] = 50.0          # the first lobe only
+        w = mlp.vmf_sample(R, rng.uniform(size=(n, 4)))
+        np.testing.assert_allclose(np.linalg.norm(w, axis=1), 1.0, atol=1e-12)
+        h = 1.0 - w @ mu
+        cdf = lambda x: -np.expm1(-kappa * x) / -np.expm1(-2 * kappa)  # noqa: E731
+        assert stats.kstest(h, cdf).pvalue > 1e-4
+        m = float((w @ mu).mean())
+        assert abs(m - (1 / np.tanh(kappa) - 1 / kappa)) < 5 * (w @ mu).std() / np.sqrt(n)
+    # lobe frequencies under distinct, well separated means
+    R = np.zeros((n, 40))
+    logits = np.array([0.0, 1.0, -1.0, 0.5, 2.0, -2.0, 0.0, 0.3])
+    means = _unit(np.random.default_rng(3), 8)
+    for k in range(8):
+        R[:, 5 * k:5 * k + 3] = means[k]
+        R[:, 5 * k + 3] = np.log(5000.0)
+        R[:, 5 * k + 4] = logits[k]
+    w = mlp.vmf_sample(R, rng.uniform(size=(n, 4)))
+    k = (w @ means.T).argmax(1)
+    pi = np.exp(logits) / np.exp(logits).sum()
+    counts = np.bincount(k, minlength=8)
+    assert stats.chisquare(counts, pi * n).pvalue > 1e-4
+
+
+def test_vmf_nll_gradient_by_finite_differences():
+    """d(-log p_mix)/dR against central differences of the mixture density, on raw outputs whose
+    log concentrations lie inside the clamp (and zero for the clamped ones)."""
+    rng = np.random.default_rng(4)
+    n = 6
+    R = rng.normal(size=(n, 40))
+    R[:, 3::5] = rng.uniform(-2.5, 4.0, size=(n, 8))
+    R[0, 3] = 11.0          # clamped: no gradient through it
+    w = _unit(rng, n)
+    G = mlp.vmf_nll_grad(R, w)
+    eps = 1e-6
+    for j in range(40):
+        d = np.zeros_like(R)
+        d[:, j] = eps
+        fd = (-np.log(mlp.vmf_pdf(R + d, w)) + np.log(mlp.vmf_pdf(R - d, w))) / (2 * eps)
+        np.testing.assert_allclose(G[:, j], fd, rtol=1e-5, atol=1e-8, err_msg=str(j))
+    assert G[0, 3] == 0.0
+
+
+def test_network_gradient_with_direction_rows():
+    """The whole network's gradient with subspace rows and direction rows in one batch, against
+    central differences of loss() and against torch.autograd (float64) of the same loss written
+    with torch ops (the vMF log-density from its closed form)."""
+    torch = pytest.importorskip("torch")
+    rng = np.random.default_rng(5)
+    n_spec = 12
+    n_out = n_spec + mlp.VMF_OUT
+    params = _params(rng, n_out)
+    feat, label, weight = _data(rng, 7, n_spec)
+    fv = rng.uniform(-1.0, 1.0, size=(5, 9))
+    dv = _unit(rng, 5)
+    wv = rng.exponential(1.0, size=5)
+    vmf = (fv, dv, wv)
+    g = mlp.grad(params, n_out, feat, label, weight, n_spec=n_spec, vmf=vmf)
+    eps = 1e-6
+    for _ in range(6):
+        d = rng.normal(size=params.size)
+        d /= np.linalg.norm(d)
+        fd = (mlp.loss(params + eps * d, n_out, feat, label, weight, n_spec=n_spec, vmf=vmf) -
+              mlp.loss(params - eps * d, n_out, feat, label, weight, n_spec=n_spec, vmf=vmf)) / (2 * eps)
+        assert fd == pytest.approx(float(g @ d), rel=1e-6, abs=1e-12)
+    blocks = {k: torch.tensor(v, dtype=torch.float64, requires_grad=True) for k, v in mlp.unpack(params, n_out).items()}
+
+    def net(f):
+        f = torch.tensor(f, dtype=torch.float64)
+        cols = []
+        for j in range(9):
+            cols.append(f[:, j:j + 1])
+            for b in range(12):
+                a = f[:, j:j + 1] * (np.pi * 2.0 ** b)
+                cols += [torch.sin(a), torch.cos(a)]
+        h = torch.cat(cols + [torch.zeros(f.shape[0], 31, dtype=torch.float64)], dim=1)
+        for l in (1, 2, 3):
+            h = torch.relu(h @ blocks[f"W{l}"] + blocks[f"b{l}"])
+        return h @ blocks["W4"] + blocks["b4"]
+
+    Lc = net(feat)[:, :n_spec]
+    w = torch.tensor(weight, dtype=torch.float64)
+    ce = torch.nn.functional.cross_entropy(Lc, torch.tensor(label), reduction="none")
+    R = net(fv)[:, n_spec:].reshape(5, 8, 5)
+    mu = R[..., :3] / R[..., :3].norm(dim=-1, keepdim=True)
+    kap = torch.exp(torch.clamp(R[..., 3], mlp.LOG_KAPPA_MIN, mlp.LOG_KAPPA_MAX))
+    logpi = torch.log_softmax(R[..., 4], dim=-1)
+    wt = torch.tensor(dv, dtype=torch.float64)[:, None, :]
+    logv = torch.log(kap) - np.log(2 * np.pi) - torch.log(-torch.expm1(-2 * kap)) - kap * (1 - (mu * wt).sum(-1))
+    nll = -torch.logsumexp(logpi + logv, dim=-1)
+    wvt = torch.tensor(wv, dtype=torch.float64)
+    ((w * ce).sum() / w.sum() + (wvt * nll).sum() / wvt.sum()).backward()
+    ref = np.concatenate([blocks[name].grad.numpy().ravel() for name, _ in mlp.layout(n_out)])
+    np.testing.assert_allclose(g, ref, rtol=1e-9, atol=1e-13)
