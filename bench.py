@@ -103,6 +103,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=4)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--config", type=int, default=2)
+    ap.add_argument("--tris", type=int, default=0,
+                    help="configs 2 and 3: triangle budget of the glossy scene instead of 200,000 (8,000,000 gives "
+                         "4.2 M triangles, 285 MB of nodes and triangle records, beyond the 256 MB Infinity Cache)")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="after the run, one device-to-device copy of this many MiB: the reference kernel of "
                          "known size for scaling hardware byte counters")
@@ -117,6 +120,8 @@ def main():
     from synth import scenes
 
     cfg = scenes.config(args.config)
+    if args.tris and args.config in (2, 3):
+        cfg["scene"] = scenes.glossy_procedural(1024, 1024, target_tris=args.tris)
     sc = cfg["scene"]
     W, H = sc["width"], sc["height"]
     # the plain method: every strategy of the iteration; config 3 adds the learned proposal (both
@@ -184,7 +189,7 @@ def main():
     per_launch_s = dom["ms_per_step"] / dom["launches"] * 1e-3
     bytes_launch = dom["bytes"] / dom["launches"]
     achieved = bytes_launch / per_launch_s / 1e9 if per_launch_s > 0 else 0.0
-    traffic = recorded_traffic(args.config, dom["kernel"])
+    traffic = recorded_traffic(args.config, dom["kernel"]) if not args.tris else None
     flops_tf = dom["flops"] / dom["launches"] / per_launch_s / 1e12 if per_launch_s > 0 else 0.0
     value = W * H * args.steps / dt
     wl = {1: "projector caustic (config 1)", 2: "glossy/specular procedural (config 2)",

@@ -62,7 +62,8 @@ typedef struct {
     const float *tex;        /* [tex_h * tex_w] emission texture, row-major, nearest lookup */
     const float *camera;     /* [10] position, target, up, vertical fov (degrees) */
     int32_t width, height;   /* image size */
-    int32_t bvh_width;       /* 4 (only width 4 is built) */
+    int32_t bvh_width;       /* 4 or 8: the BVH width the walks use; 0: both trees are built and
+                                the 4-wide one is used until pt_autotune picks */
     int32_t max_light_paths; /* capacity for M, light sub-paths per iteration */
 } pt_scene_desc;
 
@@ -70,12 +71,15 @@ typedef struct {
  * path integral's surfaces and the pixel filters f_j, here a pinhole camera whose pixel (x, y)
  * integrates over its square of the image plane), plus the capacity for the M light sub-paths
  * every iteration traces (Section 3.2). Validates the arrays, builds a binned-SAH BVH on the
- * host, collapses it to 4-wide 128-byte nodes, copies everything to the current device and
+ * host, collapses it to 4-wide 128-byte nodes and/or 8-wide 128-byte nodes with 8-bit quantised
+ * child boxes (bvh_width; both share the leaves), copies everything to the current device and
  * allocates per-iteration workspaces sized for width x height pixels and max_light_paths light
  * sub-paths. Host arrays may be freed on return. On success *out receives the handle.
  * Synchronises hip_stream. Errors: PT_EINVAL for malformed arrays (nothing allocated),
- * PT_EUNSUPPORTED when the tree's worst-case traversal needs more than the kernels' 48 stack
- * entries, PT_ENOMEM when a device allocation fails. */
+ * PT_EUNSUPPORTED when the requested tree's worst-case traversal needs more stack entries than
+ * the kernels hold (48 per thread for 4-wide walks, 64 for 8-wide ones; bvh_width 0: when
+ * neither tree fits; a tree that does not fit is not kept),
+ * PT_ENOMEM when a device allocation fails. */
 pt_status pt_scene_upload(const pt_scene_desc *desc, void *hip_stream, pt_scene **out);
 
 /* Free everything the scene owns. Synchronises the device first. NULL is a no-op. */
@@ -83,8 +87,8 @@ pt_status pt_scene_release(pt_scene *s);
 
 /* Subspace construction (Section 3.2, SPCBPT's subspaces; Section 5.5's specular and control
  * subspaces): pre-traces n_pretrace paths and clusters eye first-diffuse vertices (T), specular
- * light vertices (S) and connectable light vertices (S_L) by (position, normal, incident
- * direction) with k-means. Resets the selection matrices Gamma (Section 5.6) and Q (light-vertex
+ * light vertices (S), connectable light vertices (S_L) and the control vertices of class-B
+ * incomplete sub-paths (C) by (position, normal, incident direction) with k-means. Resets the selection matrices Gamma (Section 5.6) and Q (light-vertex
  * connections) to uniform and clears all running statistics.
  * Must be called once before pt_render_iteration. */
 typedef struct {
@@ -94,6 +98,9 @@ typedef struct {
     int32_t kmeans_iters;    /* Lloyd iterations */
     uint32_t seed;
     int32_t n_light;         /* light subspaces S_L of the probabilistic connections (<= 4096; 0: n_eye) */
+    int32_t n_ctrl;          /* control subspaces C (Section 5.5) of the class-B control vertices y_0 on the
+                                emitters (<= 256; 0 or 1: none). The reciprocal statistics that feed the
+                                MIS weights (Section 5.4) and the floor of B are kept per (class, u, S, C) */
 } pt_subspace_params;
 pt_status pt_build_subspaces(pt_scene *s, const pt_subspace_params *p, void *hip_stream);
 
@@ -131,7 +138,9 @@ typedef struct {
     int32_t cand_cap;        /* expected number of candidates kept per iteration (400) */
     int32_t recip_repeats;   /* reciprocal estimates averaged per candidate (5) */
     int32_t u_max;           /* longest specular run handled by the proxy strategy (<= 4) */
-    int32_t pilot;           /* minimum pilot samples per candidate (B and cost estimate) */
+    int32_t pilot;           /* minimum pilot samples per candidate (B and cost estimate); 0: no pilot, B and
+                                beta from the candidate's (class, u, S, C) bucket statistics of earlier
+                                iterations (needs PT_FLAG_GAMMA, PT_FLAG_MIS or PT_FLAG_MLP) */
     float cost_cap;          /* expected chain samples per candidate above which it is roulette-kept */
     int32_t train_iters;     /* iterations during which Gamma and tile statistics learn (40) */
     int32_t tile;            /* tile edge in pixels (10) */
@@ -184,7 +193,12 @@ pt_status pt_render_batch(pt_scene *s, const pt_iter_params *p, uint32_t n_iter,
 
 /* Several scenes (1 .. 64, each appearing once) per launch: one HIP graph holds one iteration of
  * every scene, each on its own branch so that the device runs small scenes side by side, and is
- * replayed n_iter times on hip_stream (iterations params[i].iteration, +1, ...). Scene i
+ * replayed n_iter times on hip_stream (iterations params[i].iteration, +1, ...). With two or more
+ * scenes the first stage of the reciprocal chains (the iteration's largest kernel) is one
+ * persistent launch for all of them: the branches join after their roulette, one grid takes
+ * (scene, chain) items from a single work queue over every scene's chains (scenes[0]'s queue
+ * chunk, see pt_autotune), and the branches fork again for the chain rounds and the rest of the
+ * iteration; each scene's estimates are those of pt_render_iteration with its parameters. Scene i
  * accumulates into accum_rgb[i] / accum_sq[i] (accum_sq may be NULL) as pt_render_iteration
  * does. The graph belongs to scenes[0] and is rebuilt when a scene, a parameter other than the
  * iteration index, a buffer or a scene's state changes: every scene carries a state generation,
@@ -195,19 +209,29 @@ pt_status pt_render_batch(pt_scene *s, const pt_iter_params *p, uint32_t n_iter,
 pt_status pt_render_scenes(pt_scene *const *scenes, const pt_iter_params *params, int32_t n_scenes, uint32_t n_iter,
                            float *const *accum_rgb, float *const *accum_sq, void *hip_stream);
 
-/* Schedule autotuning of the reciprocal chains on this scene and parameters: the sample budget
- * of the one-wavefront stage (512 .. 8192) and the grid of the round kernels (1,024 .. 8,192
- * blocks) are each timed over three iterations (after one to settle) and the fastest pair is kept
- * by the scene for later iterations. Every pair gives the same estimator (the chains consume
- * i.i.d. samples whoever draws them), so the choice changes speed only. The timed iterations
- * render into accum_rgb / accum_sq (iterations p->iteration, +1, ...); their number is returned
- * in iterations_rendered. Synchronises hip_stream. */
+/* Schedule autotuning on this scene and parameters, by coordinate descent: each knob is timed over
+ * three iterations (after one to settle) for each of its values, with the choices made before
+ * it, and the fastest value is kept by the scene for later iterations. The knobs, in order: the
+ * BVH width the walks use (4 or 8, when the scene was uploaded with bvh_width 0 and both trees
+ * fit the stack); the sample budget of the reciprocal chains' one-wavefront stage (512 .. 8192)
+ * with the grid of their round kernels (1,024 .. 8,192 blocks); the workgroup size of the ray
+ * extension launches (64, 128, 256 threads: each thread's traversal stack lives in LDS, so the
+ * size trades occupancy per CU against workgroups in flight); the number of chains a wavefront
+ * of the one-wavefront stage takes from its work queue per visit (1, 2, 4; also used by the
+ * multi-scene stage of pt_render_scenes). Every choice gives the same estimator (a ray's hit
+ * does not depend on the tree's width or its workgroup, and the chains consume i.i.d. samples
+ * whoever draws them), so it changes speed only. The timed iterations render into accum_rgb /
+ * accum_sq (iterations p->iteration, +1, ...); their number is returned in iterations_rendered.
+ * Synchronises hip_stream. */
 typedef struct {
     uint32_t stage_a_budget;     /* chosen sample budget of the one-wavefront stage */
     int32_t round_grid;          /* chosen blocks of the round kernels */
-    float ms_best;               /* iteration time with the chosen pair */
+    float ms_best;               /* iteration time with the chosen schedule */
     float ms_previous;           /* iteration time with the pair the scene had before */
     uint32_t iterations_rendered;
+    int32_t ext_wg;              /* chosen workgroup size of the extension launches */
+    int32_t queue_chunk;         /* chosen chains per take from stage A's work queue */
+    int32_t bvh_width;           /* BVH width the walks use from now on (4 or 8) */
 } pt_tune_result;
 pt_status pt_autotune(pt_scene *s, const pt_iter_params *p, float *accum_rgb_dev, float *accum_sq_dev,
                       pt_tune_result *out, void *hip_stream);
@@ -235,7 +259,7 @@ pt_status pt_mlp_param_count(const pt_scene *s, int32_t *count);   /* after pt_b
 pt_status pt_mlp_set_params(pt_scene *s, const float *host_params, int32_t count, void *hip_stream);
 /* the scene's network -> host_params[count]. Synchronous. */
 pt_status pt_mlp_get_params(pt_scene *s, float *host_params, int32_t count, void *hip_stream);
-/* out_dev[n][n_spec + 40] (bias included) of feat_dev[n][9] (device, FP32). 1 <= n <= max(H*W, 131072). */
+/* out_dev[n][n_spec + 40] (bias included) of feat_dev[n][9] (device, FP32). 1 <= n <= 131072. */
 pt_status pt_mlp_forward(pt_scene *s, const float *feat_dev, int32_t n, float *out_dev, void *hip_stream);
 /* One training step on a batch of n subspace samples (device arrays feat[n][9], label[n] in
  * [0, n_spec), weight[n] >= 0) and n_dir direction samples (feat_dir[n_dir][9], unit dir[n_dir][3],
@@ -317,6 +341,12 @@ typedef struct {
 } pt_totals;
 pt_status pt_scene_totals(pt_scene *s, pt_totals *out, int32_t reset, void *hip_stream);
 
+/* Per-iteration latency from the device's wall clock: the time from the first to the last kernel of
+ * iterations first .. first + n - 1 (of any render call), in ms, to ms_host[n]; -1 for an iteration
+ * whose record is not there (not rendered yet, still running, or more than PT_TS_CAP = 4096
+ * iterations ago). n <= 4096. Synchronises hip_stream. */
+pt_status pt_iteration_times(pt_scene *s, uint32_t first, int32_t n, double *ms_host, void *hip_stream);
+
 /* Test hook: the selection tables of the latest iteration (Section 5.6's Gamma rows for which = 0,
  * the light-subspace rows Q of the probabilistic connections for which = 1), copied to host memory
  * (synchronises hip_stream). n_rows x n_cols must be the table's shape (eye subspaces x specular,
@@ -335,9 +365,11 @@ pt_status pt_selection_tables(pt_scene *s, int32_t which, int32_t n_rows, int32_
  * Device buffers. */
 pt_status pt_philox(const uint32_t *in_dev, int32_t n, uint32_t *out_dev, void *hip_stream);
 
-/* Host only (no device needed): builds the 4-wide BVH pt_scene_upload would build for tri[n_tri*9]
- * and reports its node count, the worst-case traversal stack it needs and its depth in levels. */
-pt_status pt_bvh_stats(const float *tri, int32_t n_tri, int32_t *n_nodes, int32_t *stack_need, int32_t *depth);
+/* Host only (no device needed): builds the BVH of the given width (4 or 8) that pt_scene_upload
+ * would build for tri[n_tri*9] and reports its node count, the worst-case traversal stack it
+ * needs and its depth in levels. */
+pt_status pt_bvh_stats(const float *tri, int32_t n_tri, int32_t width, int32_t *n_nodes, int32_t *stack_need,
+                       int32_t *depth);
 
 /* Message for the last non-OK return on this thread ("" if none). */
 const char *pt_last_error(void);

@@ -1,7 +1,8 @@
 // Host-side BVH construction: binned SAH binary tree (16 bins, three axes), collapsed into
-// 4-wide nodes of one 128-byte line each (the child with the largest surface area is opened
-// until four children are reached). Triangles are reordered so that every leaf is one
-// contiguous range of at most 4 triangles.
+// 4-wide nodes of one 128-byte line each and, on request, into 8-wide nodes with quantised child
+// boxes, also one line each (the child with the largest surface area is opened until the width
+// is reached). Triangles are reordered so that every leaf is one contiguous range of at most 4
+// triangles; both trees share the leaves, hence the triangle order.
 #include <algorithm>
 #include <cfloat>
 #include <cmath>
@@ -110,25 +111,10 @@ static void set_child(BNode &n, int k, const Box &b, int child, int count)
 }
 
 // collapse binary node `bn` into wide node index `wi` of `out`
+static std::vector<int> open_children(const Builder &B, int bn, int w);
 static void collapse(const Builder &B, int bn, std::vector<BNode> &out, int wi)
 {
-    std::vector<int> kids;
-    const BinNode &root = B.nodes[bn];
-    if (root.left < 0) kids.push_back(bn);
-    else { kids.push_back(root.left); kids.push_back(root.right); }
-    while ((int)kids.size() < 4) {
-        int pick = -1;
-        float pa = -1.0f;
-        for (int i = 0; i < (int)kids.size(); ++i) {
-            const BinNode &c = B.nodes[kids[i]];
-            if (c.left >= 0 && c.box.area() > pa) { pa = c.box.area(); pick = i; }
-        }
-        if (pick < 0) break;
-        const int c = kids[pick];
-        kids.erase(kids.begin() + pick);
-        kids.push_back(B.nodes[c].left);
-        kids.push_back(B.nodes[c].right);
-    }
+    const std::vector<int> kids = open_children(B, bn, 4);
     BNode n;
     std::memset(&n, 0, sizeof(n));
     for (int k = 0; k < 4; ++k) {
@@ -151,14 +137,91 @@ static void collapse(const Builder &B, int bn, std::vector<BNode> &out, int wi)
     for (auto &pr : inner) collapse(B, pr.second, out, out[wi].child[pr.first]);
 }
 
-}  // namespace ptbvh
-
-// Builds the 4-wide BVH. tri: n*9 floats. Writes nodes and the triangle order
-// (order[i] = input index of the i-th triangle in BVH order).
-void pt_build_bvh4(const float *tri, int n, std::vector<BNode> &nodes, std::vector<int> &order)
+// the children of binary node `bn` in a node of width w: open the child of largest area until w
+static std::vector<int> open_children(const Builder &B, int bn, int w)
 {
-    using namespace ptbvh;
-    Builder B;
+    std::vector<int> kids;
+    const BinNode &root = B.nodes[bn];
+    if (root.left < 0) kids.push_back(bn);
+    else { kids.push_back(root.left); kids.push_back(root.right); }
+    while ((int)kids.size() < w) {
+        int pick = -1;
+        float pa = -1.0f;
+        for (int i = 0; i < (int)kids.size(); ++i) {
+            const BinNode &c = B.nodes[kids[i]];
+            if (c.left >= 0 && c.box.area() > pa) { pa = c.box.area(); pick = i; }
+        }
+        if (pick < 0) break;
+        const int c = kids[pick];
+        kids.erase(kids.begin() + pick);
+        kids.push_back(B.nodes[c].left);
+        kids.push_back(B.nodes[c].right);
+    }
+    return kids;
+}
+
+// quantisation of one axis of an 8-wide node: the scale 2^k is the smallest power of two with
+// (hi - lo) / 2^k <= 255, the grid starts at lo; planes round outwards (checked in float, the
+// precision the traversal decodes them in, and stepped one more cell out when rounding there
+// would cut into the box)
+static void quant_axis(float lo, float hi, float &org, uint8_t &ebits, float &scale)
+{
+    org = lo;
+    const double ext = std::max((double)hi - (double)lo, 0.0);
+    int k = -126;
+    if (ext > 0.0) k = std::max(-126, (int)std::ceil(std::log2(ext / 255.0)));
+    while (std::ldexp(255.0, k) < ext) ++k;
+    scale = std::ldexp(1.0f, k);
+    ebits = (uint8_t)(k + 127);
+}
+static uint8_t q_lo(float v, float org, float scale)
+{
+    int q = (int)std::floor(((double)v - (double)org) / (double)scale);
+    q = std::min(std::max(q, 0), 255);
+    while (q > 0 && org + (float)q * scale > v) --q;
+    return (uint8_t)q;
+}
+static uint8_t q_hi(float v, float org, float scale)
+{
+    int q = (int)std::ceil(((double)v - (double)org) / (double)scale);
+    q = std::min(std::max(q, 0), 255);
+    while (q < 255 && org + (float)q * scale < v) ++q;
+    return (uint8_t)q;
+}
+
+// collapse binary node `bn` into 8-wide node index `wi` of `out`
+static void collapse8(const Builder &B, int bn, std::vector<BNode8> &out, int wi)
+{
+    const std::vector<int> kids = open_children(B, bn, 8);
+    BNode8 n;
+    std::memset(&n, 0, sizeof(n));
+    Box nb;
+    for (int c : kids) nb.grow(B.nodes[c].box);
+    float org[3], sc[3];
+    for (int a = 0; a < 3; ++a) quant_axis(nb.lo[a], nb.hi[a], org[a], n.e[a], sc[a]);
+    for (int a = 0; a < 3; ++a) n.org[a] = org[a];
+    for (int k = 0; k < 8; ++k) { n.child[k] = -1; n.count[k] = PT_CHILD_EMPTY; }
+    std::vector<std::pair<int, int>> inner;   // (slot, binary node)
+    for (int k = 0; k < (int)kids.size(); ++k) {
+        const BinNode &c = B.nodes[kids[k]];
+        n.qlo_x[k] = q_lo(c.box.lo[0], org[0], sc[0]); n.qhi_x[k] = q_hi(c.box.hi[0], org[0], sc[0]);
+        n.qlo_y[k] = q_lo(c.box.lo[1], org[1], sc[1]); n.qhi_y[k] = q_hi(c.box.hi[1], org[1], sc[1]);
+        n.qlo_z[k] = q_lo(c.box.lo[2], org[2], sc[2]); n.qhi_z[k] = q_hi(c.box.hi[2], org[2], sc[2]);
+        if (c.left < 0) { n.child[k] = c.first; n.count[k] = (uint8_t)c.count; }
+        else inner.push_back({k, kids[k]});
+    }
+    for (auto &pr : inner) {
+        const int idx = (int)out.size();
+        out.emplace_back();
+        n.child[pr.first] = idx;
+        n.count[pr.first] = 0;
+    }
+    out[wi] = n;
+    for (auto &pr : inner) collapse8(B, pr.second, out, out[wi].child[pr.first]);
+}
+
+static void build_binary(Builder &B, const float *tri, int n)
+{
     B.tbox.resize(n);
     B.cent.resize(3 * (size_t)n);
     B.ref.resize(n);
@@ -171,10 +234,33 @@ void pt_build_bvh4(const float *tri, int n, std::vector<BNode> &nodes, std::vect
     }
     B.nodes.reserve(2 * (size_t)n + 1);
     B.build(0, n);
+}
+
+}  // namespace ptbvh
+
+// Builds the 4-wide BVH and, when nodes8 is given, the 8-wide one over the same leaves.
+// tri: n*9 floats. Writes nodes and the triangle order (order[i] = input index of the i-th
+// triangle in BVH order).
+void pt_build_bvh(const float *tri, int n, std::vector<BNode> &nodes, std::vector<BNode8> *nodes8,
+                  std::vector<int> &order)
+{
+    using namespace ptbvh;
+    Builder B;
+    build_binary(B, tri, n);
     nodes.clear();
     nodes.emplace_back();
     collapse(B, 0, nodes, 0);
+    if (nodes8) {
+        nodes8->clear();
+        nodes8->emplace_back();
+        collapse8(B, 0, *nodes8, 0);
+    }
     order = B.ref;
+}
+
+void pt_build_bvh4(const float *tri, int n, std::vector<BNode> &nodes, std::vector<int> &order)
+{
+    pt_build_bvh(tri, n, nodes, nullptr, order);
 }
 
 namespace {
@@ -201,6 +287,32 @@ int pt_bvh4_stack_need(const std::vector<BNode> &nodes, int *depth)
 {
     int need = 0, dp = 1;
     if (!nodes.empty()) stack_need_rec(nodes, 0, 1, need, dp);
+    if (depth) *depth = dp;
+    return need;
+}
+
+namespace {
+void stack_need8_rec(const std::vector<BNode8> &nodes, int n, int level, int &need, int &depth)
+{
+    int inner = 0, best = 0, deepest = level;
+    for (int k = 0; k < 8; ++k) {
+        if (nodes[n].count[k] != 0) continue;
+        ++inner;
+        int nd = 0, dp = 0;
+        stack_need8_rec(nodes, nodes[n].child[k], level + 1, nd, dp);
+        best = std::max(best, nd);
+        deepest = std::max(deepest, dp);
+    }
+    need = std::max(inner - 1, 0) + best;
+    depth = deepest;
+}
+}  // namespace
+
+// the same bound for the 8-wide tree
+int pt_bvh8_stack_need(const std::vector<BNode8> &nodes, int *depth)
+{
+    int need = 0, dp = 1;
+    if (!nodes.empty()) stack_need8_rec(nodes, 0, 1, need, dp);
     if (depth) *depth = dp;
     return need;
 }

@@ -266,6 +266,7 @@ __device__ __forceinline__ float side_eta(const MatDev &m, float3 n, float3 w)
 // ----------------------------------------------------------------------------- scene access
 struct SceneDev {
     const BNode *__restrict__ nodes;
+    const BNode8 *__restrict__ nodes8;     // the 8-wide tree (walked by kernels with 8-wide stacks), or null
     const TriIsect *__restrict__ tris;     // BVH order
     const TriShade *__restrict__ shade;    // BVH order
     const MatDev *__restrict__ mats;
@@ -349,23 +350,152 @@ __device__ __forceinline__ bool isect(const TriIsect &T, float3 o, float3 d, flo
 // (trees of fewer than 65,536 nodes, half the LDS) pack entries 2j and 2j + 1 of thread i into
 // the two halves of dword j * nthreads + i. A thread's pointer is its column's first element
 // (stk_col).
-__device__ __forceinline__ int &stk_at(int *stk, int k, int stride) { return stk[k * stride]; }
-__device__ __forceinline__ uint16_t &stk_at(uint16_t *stk, int k, int stride)
+//
+// The entry type also selects the tree a kernel walks, at compile time: uint16_t and int walk the
+// 4-wide nodes, int16_t and uint32_t (the same sizes) the 8-wide ones, so that a kernel holds the
+// registers of one walk only. 16-bit entries hold node indices below 65,536 (int16_t ones read
+// back through uint16_t).
+template <typename SE> struct stk_wide8 { static constexpr bool value = false; };
+template <> struct stk_wide8<int16_t> { static constexpr bool value = true; };
+template <> struct stk_wide8<uint32_t> { static constexpr bool value = true; };
+// entries per thread: the 8-wide walk pushes up to seven children a node
+template <typename SE>
+__host__ __device__ constexpr int stk_depth() { return stk_wide8<SE>::value ? PT_STACK8 : PT_STACK; }
+template <typename SE>
+__device__ __forceinline__ SE &stk_at(SE *stk, int k, int stride)
 {
-    return stk[(k >> 1) * 2 * stride + (k & 1)];
+    if constexpr (sizeof(SE) == 2) return stk[(k >> 1) * 2 * stride + (k & 1)];
+    else return stk[k * stride];
+}
+template <typename SE>
+__device__ __forceinline__ int stk_node(SE v)
+{
+    if constexpr (sizeof(SE) == 2) return (int)(uint16_t)v;
+    else return (int)v;
 }
 template <typename SE>
 __device__ __forceinline__ SE *stk_col(SE *base, int thread) { return base + (sizeof(SE) == 2 ? 2 : 1) * thread; }
 
+// the 8-wide walk (BNode8): the contract of traverse_rt below. A node is one 128-byte line read
+// as seven 16-byte loads; a child plane at grid cell q lies at t = q * (2^(e-127) / d) +
+// (org - o) / d, one FMA per plane. Children are taken in entry order through a 19-comparator
+// network (Batcher's odd-even merge sort of eight).
+template <bool COUNT, typename SE>
+__device__ __forceinline__ bool traverse8_rt(const SceneDev &S, float3 o, float3 d, float tmin, float tmax, int ign0,
+                                             int ign1, bool any, SE *stk, int stride, Hit &h, uint32_t *visits,
+                                             uint32_t *tests, uint32_t *wave_trips)
+{
+    const float3 inv = f3(1.0f / d.x, 1.0f / d.y, 1.0f / d.z);
+    h.tri = -1; h.t = tmax;
+    int sp = 0;
+    int node = 0;
+    for (;;) {
+        const uint4 *P = (const uint4 *)(S.nodes8 + node);
+        if (COUNT) {
+            (*visits)++;
+            if (wave_trips && __lane_id() == __ffsll((long long)__ballot(1)) - 1) (*wave_trips)++;
+        }
+        const uint4 w0 = P[0], qx = P[1], qy = P[2], qz = P[3], c0 = P[4], c1 = P[5];
+        const uint2 cn = *(const uint2 *)(P + 6);
+        const float ax = __uint_as_float((w0.w & 0xFFu) << 23) * inv.x;
+        const float ay = __uint_as_float(((w0.w >> 8) & 0xFFu) << 23) * inv.y;
+        const float az = __uint_as_float(((w0.w >> 16) & 0xFFu) << 23) * inv.z;
+        const float bx = (__uint_as_float(w0.x) - o.x) * inv.x;
+        const float by = (__uint_as_float(w0.y) - o.y) * inv.y;
+        const float bz = (__uint_as_float(w0.z) - o.z) * inv.z;
+        const int cha[8] = {(int)c0.x, (int)c0.y, (int)c0.z, (int)c0.w, (int)c1.x, (int)c1.y, (int)c1.z, (int)c1.w};
+        float tn[8];
+        bool hitc[8];
+        int cna[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const int sh = 8 * (k & 3);
+            const uint32_t lox = k < 4 ? qx.x : qx.y, hix = k < 4 ? qx.z : qx.w;
+            const uint32_t loy = k < 4 ? qy.x : qy.y, hiy = k < 4 ? qy.z : qy.w;
+            const uint32_t loz = k < 4 ? qz.x : qz.y, hiz = k < 4 ? qz.z : qz.w;
+            const float tlx = (float)((lox >> sh) & 0xFFu) * ax + bx, thx = (float)((hix >> sh) & 0xFFu) * ax + bx;
+            const float tly = (float)((loy >> sh) & 0xFFu) * ay + by, thy = (float)((hiy >> sh) & 0xFFu) * ay + by;
+            const float tlz = (float)((loz >> sh) & 0xFFu) * az + bz, thz = (float)((hiz >> sh) & 0xFFu) * az + bz;
+            const float t0 = fmaxf(fmaxf(fminf(tlx, thx), fminf(tly, thy)), fmaxf(fminf(tlz, thz), 0.0f));
+            const float t1 = fminf(fminf(fmaxf(tlx, thx), fmaxf(tly, thy)), fminf(fmaxf(tlz, thz), h.t));
+            cna[k] = (int)(((k < 4 ? cn.x : cn.y) >> sh) & 0xFFu);
+            hitc[k] = t0 <= t1 * 1.00000024f && cna[k] != PT_CHILD_EMPTY;
+            tn[k] = t0;
+        }
+        // leaves: one run over the hit leaves' triangles (as in the 4-wide walk)
+        int e[8];
+        int ntot = 0;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            ntot += (hitc[k] && cna[k] > 0) ? cna[k] : 0;
+            e[k] = ntot;
+        }
+        for (int j = 0; j < ntot; ++j) {
+            int i = cha[7] + (j - e[6]);
+#pragma unroll
+            for (int k = 6; k >= 0; --k)
+                if (j < e[k]) i = cha[k] + (j - (k > 0 ? e[k - 1] : 0));
+            const TriIsect &T = S.tris[i];
+            if (COUNT) (*tests)++;
+            const int pid = T.prim;
+            if (i == ign0 || i == ign1) continue;
+            float t, b1, b2;
+            if (isect(T, o, d, tmin, tmax, t, b1, b2)) {
+                if (t < h.t || (t == h.t && h.tri >= 0 && pid < S.tris[h.tri].prim)) {
+                    h.t = t; h.b1 = b1; h.b2 = b2; h.tri = i;
+                    if (any) return true;
+                }
+            }
+        }
+        float key[8];
+        int cid[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const bool take = hitc[k] && cna[k] == 0 && tn[k] <= h.t;
+            key[k] = take ? tn[k] : 3.0e38f;
+            cid[k] = take ? cha[k] : -1;
+        }
+#define PT_CSWAP(a, b)                                                                     \
+        {                                                                                  \
+            const bool sw = key[b] < key[a];                                               \
+            const float ka = key[a], kb = key[b];                                          \
+            const int ca = cid[a], cb = cid[b];                                            \
+            key[a] = sw ? kb : ka; key[b] = sw ? ka : kb;                                  \
+            cid[a] = sw ? cb : ca; cid[b] = sw ? ca : cb;                                  \
+        }
+        PT_CSWAP(0, 1) PT_CSWAP(2, 3) PT_CSWAP(4, 5) PT_CSWAP(6, 7)
+        PT_CSWAP(0, 2) PT_CSWAP(1, 3) PT_CSWAP(4, 6) PT_CSWAP(5, 7)
+        PT_CSWAP(1, 2) PT_CSWAP(5, 6)
+        PT_CSWAP(0, 4) PT_CSWAP(1, 5) PT_CSWAP(2, 6) PT_CSWAP(3, 7)
+        PT_CSWAP(2, 4) PT_CSWAP(3, 5)
+        PT_CSWAP(1, 2) PT_CSWAP(3, 4) PT_CSWAP(5, 6)
+#undef PT_CSWAP
+        // as in the 4-wide walk, pt_scene_upload keeps the 8-wide tree only when its worst-case
+        // walk fits the stack (PT_STACK8 entries); the bound only guards a malformed tree
+        if (cid[0] >= 0) {
+#pragma unroll
+            for (int k = 7; k >= 1; --k)
+                if (cid[k] >= 0 && sp < stk_depth<SE>()) stk_at(stk, sp++, stride) = (SE)cid[k];
+            node = cid[0];
+        } else {
+            if (sp == 0) break;
+            node = stk_node(stk_at(stk, --sp, stride));
+        }
+    }
+    return h.tri >= 0;
+}
+
 // `any` ends the walk at the first hit (visibility); it is a run-time argument so that a kernel
 // can trace visibility and closest-hit rays at one call site, and constant-folds where the
-// caller passes a constant.
+// caller passes a constant. Stacks of int16_t or uint32_t entries walk the 8-wide tree.
 template <bool COUNT, typename SE>
 __device__ __forceinline__ bool traverse_rt(const SceneDev &S, float3 o, float3 d, float tmin, float tmax, int ign0,
                                             int ign1, bool any, SE *stk, int stride, Hit &h,
                                             uint32_t *visits = nullptr, uint32_t *tests = nullptr,
                                             uint32_t *wave_trips = nullptr)
 {
+    if constexpr (stk_wide8<SE>::value)
+        return traverse8_rt<COUNT>(S, o, d, tmin, tmax, ign0, ign1, any, stk, stride, h, visits, tests, wave_trips);
     const float3 inv = f3(1.0f / d.x, 1.0f / d.y, 1.0f / d.z);
     const float3 oi = o * inv;
     h.tri = -1; h.t = tmax;
@@ -454,11 +584,11 @@ __device__ __forceinline__ bool traverse_rt(const SceneDev &S, float3 o, float3 
         if (cid[0] >= 0) {
 #pragma unroll
             for (int k = 3; k >= 1; --k)
-                if (cid[k] >= 0 && sp < PT_STACK) stk_at(stk, sp++, stride) = (SE)cid[k];
+                if (cid[k] >= 0 && sp < stk_depth<SE>()) stk_at(stk, sp++, stride) = (SE)cid[k];
             node = cid[0];
         } else {
             if (sp == 0) break;
-            node = (int)stk_at(stk, --sp, stride);
+            node = stk_node(stk_at(stk, --sp, stride));
         }
     }
     return h.tri >= 0;

@@ -57,26 +57,32 @@ __global__ void k_zero(unsigned long long *cnt, int n)
     if (i < n && i != C_ITER && i != C_LEARN && i != C_MLP_T) cnt[i] = 0ull;
 }
 // iteration index in device memory: set (direct calls) or advanced by one (graph replays)
-__global__ void k_iter(unsigned long long *cnt, uint32_t value, int advance, int train_iters)
+// (stamp: the iteration starts here; its device wall-clock time goes to the ring ts)
+__global__ void k_iter(unsigned long long *cnt, uint32_t value, int advance, int train_iters, long long *ts, int stamp)
 {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
         const uint32_t it = advance ? (uint32_t)cnt[C_ITER] + 1u : value;
         cnt[C_ITER] = it;
         cnt[C_LEARN] = (int)it < train_iters ? 1ull : 0ull;
+        if (stamp && ts) {
+            ts[2 * (it % PT_TS_CAP)] = wall_clock64();
+            ts[2 * (it % PT_TS_CAP) + 1] = 0;
+        }
     }
 }
 __device__ __forceinline__ uint32_t iter_of(const unsigned long long *cnt) { return (uint32_t)cnt[C_ITER]; }
 
 // closest hit for every queued ray; rays live in (ro, rd) by path id, ro.w = ignored triangle,
-// rd.w = tmax; writes hit[pid] = (t, b1, b2, triangle or -1)
-template <bool COUNT, typename SE>
-__global__ void __launch_bounds__(WG) k_extend(SceneDev S, const uint32_t *__restrict__ q,
-                                               const unsigned long long *__restrict__ cnt, int cidx,
-                                               const float4 *__restrict__ ro, const float4 *__restrict__ rd,
-                                               float4 *__restrict__ hit, unsigned long long *stats, int ray_ctr)
+// rd.w = tmax; writes hit[pid] = (t, b1, b2, triangle or -1). WGS threads per workgroup (the
+// autotuner's choice of 64, 128 or 256; the LDS stack is stk_depth<SE>() x WGS entries)
+template <bool COUNT, typename SE, int WGS = WG>
+__global__ void __launch_bounds__(WGS) k_extend(SceneDev S, const uint32_t *__restrict__ q,
+                                                const unsigned long long *__restrict__ cnt, int cidx,
+                                                const float4 *__restrict__ ro, const float4 *__restrict__ rd,
+                                                float4 *__restrict__ hit, unsigned long long *stats, int ray_ctr)
 {
-    __shared__ SE stk[PT_STACK * WG];
-    const int i = blockIdx.x * WG + threadIdx.x;
+    __shared__ SE stk[stk_depth<SE>() * WGS];
+    const int i = blockIdx.x * WGS + threadIdx.x;
     const int n = (int)cnt[cidx];
     uint32_t visits = 0, tests = 0;
     const bool act = i < n;
@@ -84,7 +90,8 @@ __global__ void __launch_bounds__(WG) k_extend(SceneDev S, const uint32_t *__res
         const int pid = q[i];
         const float4 o = ro[pid], d = rd[pid];
         Hit h;
-        traverse<false, COUNT>(S, xyz(o), xyz(d), S.tmin, d.w, fbits(o.w), -1, stk_col(stk, (int)threadIdx.x), WG, h, &visits, &tests);
+        traverse<false, COUNT>(S, xyz(o), xyz(d), S.tmin, d.w, fbits(o.w), -1, stk_col(stk, (int)threadIdx.x), WGS, h,
+                               &visits, &tests);
         hit[pid] = make_float4(h.t, h.b1, h.b2, ibits(h.tri));
     }
     wave_count(stats + ray_ctr, act ? 1u : 0u);
@@ -764,7 +771,7 @@ __global__ void __launch_bounds__(64 * RW, PT_PILOT_WAVES) k_pilot(SceneDev S, C
                                                    uint32_t seed, float *runmax, unsigned long long *cnt)
 {
     const uint32_t iter = iter_of(cnt);
-    __shared__ SE stk[PT_STACK * 64 * RW];
+    __shared__ SE stk[stk_depth<SE>() * 64 * RW];
     const int lane = threadIdx.x & 63;
     const int n = (int)cnt[C_NKEPT];
     CtxT<SE> C{S, stk_col(stk, (int)threadIdx.x), 0u, (int)blockDim.x};
@@ -797,11 +804,12 @@ __global__ void __launch_bounds__(64 * RW, PT_PILOT_WAVES) k_pilot(SceneDev S, C
     count_traversal(C, cnt);
 }
 
-// B_j = max(pilot max, bucket running max) (Appendix E's B = max f/q, per (class, u) bucket as in
-// Section 5.5's statistics); cost roulette: keep with rho = min(1, cost_cap / (R B / beta))
+// B_j (Appendix E's B = max f/q): from the candidate's pilot and the (class, u) running max, or,
+// without a pilot, from its (class, u, S, C) bucket's statistics (Section 5.5); cost roulette: keep
+// with rho = min(1, cost_cap / (R B / beta))
 __global__ void k_roulette(Cand *cand, const uint32_t *kept, uint32_t *final_, uint32_t *cost_bin,
-                           const float *runmax, float em_area, int repeats, float cost_cap, uint32_t seed,
-                           unsigned long long *cnt)
+                           const float *runmax, SubDev D, int labelled, float em_area, int repeats, float cost_cap,
+                           uint32_t seed, unsigned long long *cnt)
 {
     const uint32_t iter = iter_of(cnt);
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -815,8 +823,18 @@ __global__ void k_roulette(Cand *cand, const uint32_t *kept, uint32_t *final_, u
         float gmax = 0.f;
         for (int k = 0; k < 10; ++k) gmax = fmaxf(gmax, runmax[k]);
         const float Bb = runmax[b] > 0.f ? runmax[b] : (gmax > 0.f ? gmax : 1.0f / em_area);
-        const float B = fmaxf(c.pmax, Bb);
-        const float beta = c.pmax > 0.f ? c.psum / c.pn : B / (2.0f * fmaxf(c.pn, 1.0f));
+        // with a pilot (c.pn > 0): B = max(pilot max, (class, u) running max), beta the pilot mean.
+        // Without one: the (class, u, S, C) bucket's f/q statistics of earlier iterations (Section
+        // 5.5): B its largest value and beta its mean, the (class, u) running max while the bucket
+        // has none. Any B with beta / B in (0, 2) leaves the estimate unbiased (Appendix B).
+        const int sb = labelled ? 3 * stat_bucket(D, c.cls_u >> 8, c.cls_u & 0xFF, c.spec_sub & 0xFFFF,
+                                                  c.spec_sub >> 16) : 0;
+        const bool piloted = c.pn > 0.f;
+        const bool bucket = !piloted && labelled && D.bstat[sb] > 0.f && D.bstat[sb + 2] > 0.f;
+        const float B = piloted ? fmaxf(c.pmax, Bb) : (bucket ? D.bstat[sb] : Bb);
+        float beta;
+        if (piloted) beta = c.pmax > 0.f ? c.psum / c.pn : B / (2.0f * c.pn);
+        else beta = (bucket && D.bstat[sb + 1] > 0.f) ? D.bstat[sb + 1] / D.bstat[sb + 2] : 0.5f * B;
         const float cost = (float)repeats * B / beta;
         const float rho = (cost_cap > 0.f && cost > cost_cap) ? cost_cap / cost : 1.0f;
         Rng r = rng_make(seed, S_ROUL, (uint32_t)i, iter, 0u);
@@ -1031,63 +1049,146 @@ __device__ __forceinline__ void chain_finish(Cand &c, const ChainRun &st, bool t
     const float est = (st.alive || trunc) ? (float)(st.ans * (double)st.weight / (double)c.B) : 0.0f;
     unsafeAtomicAdd(&c.recip_sum, est);
     atomic_maxf(runmax + (c.cls_u >> 8) * 5 + (c.cls_u & 0xFF), mx);
+    atomic_maxf(&c.pmax, mx);   // the candidate's largest f/q, pilot and chains (bucket statistics)
 }
 
-// stage A: one wavefront per chain, at most `budget` samples, then hand over to the rounds;
-// BOOTH selects Booth's roulette (booth_r) at compile time, so that the default instance carries
-// none of its state
+// stage A of one chain (item `wave` of a scene's (candidate, repeat) list, wave-uniform): one
+// wavefront draws at most `budget` samples, then hands a running chain over to the rounds
+template <typename SE, bool BOOTH>
+__device__ __forceinline__ void stage_a_chain(CtxT<SE> &C, Cand *cand, const uint32_t *final_, const uint32_t *order,
+                                              int wave, int repeats, uint32_t seed, uint32_t iter, uint32_t n1,
+                                              uint32_t budget, float *runmax, ChainState *longq, float booth_r,
+                                              unsigned long long *cnt, int lane, uint32_t &ns, uint32_t &drawn)
+{
+    const uint32_t ci = final_[order[wave / repeats]];
+    const uint32_t chain = ci * 8u + (uint32_t)(wave % repeats);
+    Cand &c = cand[ci];
+    const float invB = 1.0f / c.B;
+    ChainRun st{1.0, 1.0f, 1u, 0u, 0u, n1, 0u, true, 1.0f, 1.0f};
+    float mx = 0.0f, fs = 0.0f;
+    uint32_t nd = 0;
+    for (int step = 0; st.alive && st.pos + st.neg > 0 && st.ns < budget; ++step) {
+        Rng r = rng_make(seed, S_RECIP, chain, iter, (uint32_t)(step * 64 + lane));
+        const float fq = fq_sample(C, c, r);
+        const float u = rng_f(r);
+        mx = fmaxf(mx, fq);
+        fs += fq;
+        chain_consume(fq, u, 64, invB, st, seed, chain, iter, BOOTH ? booth_r : 0.0f);
+        drawn += 64;
+        nd += 64;
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        mx = fmaxf(mx, __shfl_xor(mx, off));
+        fs += __shfl_xor(fs, off);
+    }
+    // every f/q this stage drew is an i.i.d. sample of the candidate's ratio: its (class, u, S, C)
+    // bucket's mean estimates beta for later iterations
+    if (lane == 0 && nd > 0) {
+        unsafeAtomicAdd(&c.psum, fs);
+        unsafeAtomicAdd(&c.pn, (float)nd);
+    }
+    ns += st.ns;
+    if (lane == 0) {
+        const bool running = st.alive && st.pos + st.neg > 0;
+        int slot = -1;
+        if (running) {
+            slot = (int)atomicAdd(cnt + C_LONGQ0, 1ull);
+            if (slot >= CHAIN_LIST_CAP) slot = -1;
+        }
+        if (slot >= 0) {
+            ChainState q{ci, chain, st.ans, st.weight, mx, st.pos, st.neg, st.ns, st.next_flip, st.coin,
+                         st.bprod, st.bw};
+            longq[slot] = q;
+        } else {
+            if (running) atomicAdd(cnt + C_RECIP_TRUNC, 1ull);
+            chain_finish(c, st, running, mx, runmax, cnt);
+        }
+    }
+}
+
+// stage A over one scene's chains: a persistent grid whose wavefronts take the next chains from a
+// device counter; BOOTH selects Booth's roulette (booth_r) at compile time, so that the default
+// instance carries none of its state
 template <typename SE, bool BOOTH = false>
 __global__ void __launch_bounds__(64 * RW, PT_RECIP_WAVES) k_recip(SceneDev S, Cand *cand, const uint32_t *final_,
                                                    const uint32_t *order, int repeats,
                                                    uint32_t seed, uint32_t n1, uint32_t budget, float *runmax,
-                                                   ChainState *longq, float booth_r, unsigned long long *cnt)
+                                                   ChainState *longq, float booth_r, unsigned long long *cnt,
+                                                   int chunk)
 {
     const uint32_t iter = iter_of(cnt);
-    __shared__ SE stk[PT_STACK * 64 * RW];
+    __shared__ SE stk[stk_depth<SE>() * 64 * RW];
     const int lane = threadIdx.x & 63;
     const int n = (int)cnt[C_NFINAL] * repeats;
     CtxT<SE> C{S, stk_col(stk, (int)threadIdx.x), 0u, (int)blockDim.x};
     uint32_t ns = 0, drawn = 0;
-    for (int wave = next_item(cnt + C_WORK_A); wave < n; wave = next_item(cnt + C_WORK_A)) {   // wave-uniform
-        const uint32_t ci = final_[order[wave / repeats]];
-        const uint32_t chain = ci * 8u + (uint32_t)(wave % repeats);
-        Cand &c = cand[ci];
-        const float invB = 1.0f / c.B;
-        ChainRun st{1.0, 1.0f, 1u, 0u, 0u, n1, 0u, true, 1.0f, 1.0f};
-        float mx = 0.0f;
-        for (int step = 0; st.alive && st.pos + st.neg > 0 && st.ns < budget; ++step) {
-            Rng r = rng_make(seed, S_RECIP, chain, iter, (uint32_t)(step * 64 + lane));
-            const float fq = fq_sample(C, c, r);
-            const float u = rng_f(r);
-            mx = fmaxf(mx, fq);
-            chain_consume(fq, u, 64, invB, st, seed, chain, iter, BOOTH ? booth_r : 0.0f);
-            drawn += 64;
-        }
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1) mx = fmaxf(mx, __shfl_xor(mx, off));
-        ns += st.ns;
-        if (lane == 0) {
-            const bool running = st.alive && st.pos + st.neg > 0;
-            int slot = -1;
-            if (running) {
-                slot = (int)atomicAdd(cnt + C_LONGQ0, 1ull);
-                if (slot >= CHAIN_LIST_CAP) slot = -1;
-            }
-            if (slot >= 0) {
-                ChainState q{ci, chain, st.ans, st.weight, mx, st.pos, st.neg, st.ns, st.next_flip, st.coin,
-                             st.bprod, st.bw};
-                longq[slot] = q;
-            } else {
-                if (running) atomicAdd(cnt + C_RECIP_TRUNC, 1ull);
-                chain_finish(c, st, running, mx, runmax, cnt);
-            }
-        }
-    }
+    // chunk consecutive chains per take from the counter (wave-uniform)
+    for (int w0 = next_item(cnt + C_WORK_A) * chunk; w0 < n; w0 = next_item(cnt + C_WORK_A) * chunk)
+        for (int wave = w0; wave < min(w0 + chunk, n); ++wave)
+            stage_a_chain<SE, BOOTH>(C, cand, final_, order, wave, repeats, seed, iter, n1, budget, runmax, longq,
+                                     booth_r, cnt, lane, ns, drawn);
     wave_count(cnt + C_RECIP_SAMPLES, lane == 0 ? ns : 0u);
     wave_count(cnt + C_SAMPLES_A, lane == 0 ? ns : 0u);
     wave_count(cnt + C_DRAWN_A, lane == 0 ? drawn : 0u);
     wave_count(cnt + C_RAYS_RECIP, C.rays);
     count_traversal(C, cnt, C_VISITS_A, C_TESTS_A, C_TRIPS_A);
+}
+
+// one scene's share of a multi-scene stage A (what k_recip takes as arguments)
+struct RecipJob {
+    SceneDev S;
+    Cand *cand;
+    const uint32_t *final_, *order;
+    float *runmax;
+    ChainState *longq;
+    unsigned long long *cnt;
+    int repeats;
+    uint32_t seed, n1, budget;
+    float booth_r;
+};
+// the scenes' chain lists laid end to end: base[j] = first item of scene j, base[n] = all items;
+// the shared work counter restarts at zero
+__global__ void k_multi_base(const RecipJob *jobs, int n, uint32_t *base, unsigned long long *work)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    uint32_t b = 0;
+    for (int j = 0; j < n; ++j) {
+        base[j] = b;
+        b += (uint32_t)jobs[j].cnt[C_NFINAL] * (uint32_t)jobs[j].repeats;
+    }
+    base[n] = b;
+    *work = 0ull;
+}
+// stage A of several scenes in one persistent launch: the wavefronts take items from one work
+// queue over every scene's chains (chunk consecutive items per take), so that the scenes' uneven
+// chain counts share the device without a tail per scene; counts go to each item's scene
+template <typename SE, bool BOOTH>
+__global__ void __launch_bounds__(64 * RW, PT_RECIP_WAVES) k_recip_multi(const RecipJob *__restrict__ jobs, int n_jobs,
+                                                                         const uint32_t *__restrict__ base,
+                                                                         unsigned long long *work, int chunk)
+{
+    __shared__ SE stk[stk_depth<SE>() * 64 * RW];
+    const int lane = threadIdx.x & 63;
+    const int total = (int)base[n_jobs];
+    for (int w0 = next_item(work) * chunk; w0 < total; w0 = next_item(work) * chunk) {   // wave-uniform
+        const int w1 = min(w0 + chunk, total);
+        for (int w = w0; w < w1; ++w) {
+            int j = 0;
+            while (j + 1 < n_jobs && (int)base[j + 1] <= w) ++j;
+            j = __builtin_amdgcn_readfirstlane(j);
+            const RecipJob &J = jobs[j];
+            CtxT<SE> C{J.S, stk_col(stk, (int)threadIdx.x), 0u, (int)blockDim.x};
+            uint32_t ns = 0, drawn = 0;
+            stage_a_chain<SE, BOOTH>(C, J.cand, J.final_, J.order, w - (int)base[j], J.repeats, J.seed, iter_of(J.cnt),
+                                     J.n1, J.budget, J.runmax, J.longq, J.booth_r, J.cnt, lane, ns, drawn);
+            wave_count(J.cnt + C_RECIP_SAMPLES, lane == 0 ? ns : 0u);
+            wave_count(J.cnt + C_SAMPLES_A, lane == 0 ? ns : 0u);
+            wave_count(J.cnt + C_DRAWN_A, lane == 0 ? drawn : 0u);
+            wave_count(J.cnt + C_RAYS_RECIP, C.rays);
+            count_traversal(C, J.cnt, C_VISITS_A, C_TESTS_A, C_TRIPS_A);
+        }
+    }
 }
 
 // samples per chain in round r for n running chains: doubling from 1024, so that a chain draws at
@@ -1111,7 +1212,7 @@ __global__ void __launch_bounds__(WG, PT_GEN_WAVES) k_chain_gen(SceneDev S, cons
                                                   const ChainState *__restrict__ list, int cidx, int round,
                                                   uint32_t seed, float2 *buf, unsigned long long *cnt)
 {
-    __shared__ SE stk[PT_STACK * WG];
+    __shared__ SE stk[stk_depth<SE>() * WG];
     const uint32_t iter = iter_of(cnt);
     const uint32_t n = (uint32_t)min(cnt[cidx], (unsigned long long)CHAIN_LIST_CAP);
     CtxT<SE> C{S, stk_col(stk, (int)threadIdx.x), 0u, WG};
@@ -1378,7 +1479,9 @@ __global__ void k_eye_shade(SceneDev S, EyeBuf E, EyeParams P, SubDev D, LightBu
                             // three strategies build this proxy-class path (area measure at y_0,
                             // common factors dropped): BSDF hit, NEE at the previous vertex, proxy
                             const float J0 = cl / d2;
-                            const float Ap = proxy_mis_factor(D, ph == 2 ? 1 : 0, (int)uu, Sl,
+                            // class B: this emitter point is the control vertex y_0
+                            const int Cl = ph == 2 ? ctrl_label(S, D, x, tri) : 0;
+                            const float Ap = proxy_mis_factor(D, ph == 2 ? 1 : 0, (int)uu, Sl, Cl,
                                                               proxy_ksel(D, P, cnt, Tl, Sl, c_pix));
                             // w = 1 / (1 + C_0 + P_proxy / P_0), C_0 without the connections
                             const float hit = mis.x * bt.w * J0;
@@ -1451,7 +1554,9 @@ __global__ void k_eye_shade(SceneDev S, EyeBuf E, EyeParams P, SubDev D, LightBu
                                         Sv = nearest_set(D.spec, f);
                                     }
                                     const float J0 = cl / dist2;
-                                    const float Ap = proxy_mis_factor(D, ph == 2 ? 1 : 0, (int)uu, Sv,
+                                    // class B: the light sample is the control vertex y_0
+                                    const int Cv = ph == 2 ? ctrl_label(S, D, Lp.p, Lp.tri) : 0;
+                                    const float Ap = proxy_mis_factor(D, ph == 2 ? 1 : 0, (int)uu, Sv, Cv,
                                                                       proxy_ksel(D, P, cnt, Tl, Sv, c_pix));
                                     const float hitp = pz * pb * J0, nee = pz / S.em_area;
                                     const float prx = ph == 2 ? Ap / S.em_area : Ap * pb * J0;
@@ -1595,7 +1700,7 @@ template <typename SE>
 __global__ void __launch_bounds__(WG) k_lt(SceneDev S, LightBuf L, EyeParams P, SubDev D, ConnDev C, float *frame,
                                            unsigned long long *cnt)
 {
-    __shared__ SE stk[PT_STACK * WG];
+    __shared__ SE stk[stk_depth<SE>() * WG];
     const int i = blockIdx.x * WG + threadIdx.x;
     const uint32_t npool = (uint32_t)cnt[C_POOL];
     uint32_t done = 0, rays = 0;
@@ -1664,7 +1769,10 @@ __global__ void __launch_bounds__(WG) k_lt(SceneDev S, LightBuf L, EyeParams P, 
                                 feat9(S, ys, ns, normalize3(ys2 - ys), f);
                                 const int Sl = nearest_set(D.spec, f);
                                 const float c_pix = P.tiles_on ? tile_prob(D, py * cam.w + px, cam.w) : 1.0f;
-                                const float Ap = proxy_mis_factor(D, clsB ? 1 : 0, u, Sl, proxy_ksel(D, P, cnt, Tl, Sl, c_pix));
+                                // class B: the path's emitter point y_0 is the control vertex
+                                const int Cl = clsB ? ctrl_label(S, D, xyz(L.lv[lp]), fbits(L.lv[lp].w)) : 0;
+                                const float Ap = proxy_mis_factor(D, clsB ? 1 : 0, u, Sl, Cl,
+                                                                  proxy_ksel(D, P, cnt, Tl, Sl, c_pix));
                                 float X;
                                 if (clsB) {
                                     const float3 y0 = xyz(L.lv[lp]), y1 = xyz(L.lv[(size_t)L.M + lp]), y2 = xyz(L.lv[2 * (size_t)L.M + lp]);
@@ -1710,7 +1818,7 @@ __global__ void __launch_bounds__(WG) k_lt(SceneDev S, LightBuf L, EyeParams P, 
 template <typename SE>
 __global__ void __launch_bounds__(WG) k_occluded(SceneDev S, EyeBuf E, ConnDev C, int t, unsigned long long *cnt)
 {
-    __shared__ SE stk[PT_STACK * WG];
+    __shared__ SE stk[stk_depth<SE>() * WG];
     const int i = blockIdx.x * WG + threadIdx.x;
     const int n = (int)cnt[C_SHD0 + t];
     const bool act = i < n;
@@ -1747,7 +1855,7 @@ __global__ void __launch_bounds__(WG) k_proxy(SceneDev S, EyeBuf E, const Cand *
                                               StatBuf SB, MlpTrain MT, const float *vmf, int repeats,
                                               unsigned long long *cnt)
 {
-    __shared__ SE stk[PT_STACK * WG];
+    __shared__ SE stk[stk_depth<SE>() * WG];
     const int i = blockIdx.x * WG + threadIdx.x;
     const int n = (int)cnt[C_PROXYQ];
     const int nk = (int)cnt[C_NFINAL];
@@ -1897,7 +2005,8 @@ __global__ void __launch_bounds__(WG) k_proxy(SceneDev S, EyeBuf E, const Cand *
                         feat9(S, v, vn, first_dir, f);
                         const int Sm = nearest_set(D.spec, f);
                         const float pz = bsdf_pdf(md, shd.n, xyz(it.wo), wzv) * fabsf(dot3(vn, wzv)) / d2;
-                        const float Ap = proxy_mis_factor(D, cls, u, Sm, proxy_ksel(D, P, cnt, T, Sm, c_pix));
+                        const int Cm = cls ? ctrl_label(S, D, xyz(c.hc), fbits(c.hc.w)) : 0;
+                        const float Ap = proxy_mis_factor(D, cls, u, Sm, Cm, proxy_ksel(D, P, cnt, T, Sm, c_pix));
                         float hit, nee, prx;
                         if (cls == 0) {
                             hit = pz * last_pdf * J0;
@@ -2017,10 +2126,11 @@ __global__ void k_philox_hook(const uint32_t *in, int n, uint32_t *out)
     philox10(a[4], a[5], a[0], a[1], a[2], a[3], o);
     for (int k = 0; k < 4; ++k) out[4 * (size_t)i + k] = o[k];
 }
-// the iteration's counts added to the scene's running totals
-__global__ void k_totals(const unsigned long long *cnt, unsigned long long *tot)
+// the iteration's counts added to the scene's running totals; the iteration's end stamp
+__global__ void k_totals(const unsigned long long *cnt, unsigned long long *tot, long long *ts)
 {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    if (ts) ts[2 * ((uint32_t)cnt[C_ITER] % PT_TS_CAP) + 1] = wall_clock64();
     tot[TOT_ITERS] += 1ull;
     tot[TOT_NAN] += cnt[C_NAN];
     tot[TOT_TRUNC] += cnt[C_RECIP_TRUNC];
@@ -2052,15 +2162,16 @@ __global__ void k_resolve(const float *acc, float *out, int n, float inv)
 }
 
 // ---------------------------------------------------------------------------------- test hooks
+template <typename SE>
 __global__ void __launch_bounds__(WG) k_trace_closest(SceneDev S, const float *rays, int n, float *t_out, int *prim_out)
 {
-    __shared__ int stk[PT_STACK * WG];
+    __shared__ SE stk[stk_depth<SE>() * WG];
     const int i = blockIdx.x * WG + threadIdx.x;
     if (i >= n) return;
     const float *r = rays + 8 * (size_t)i;
     Hit h;
     const bool ok = traverse<false, false>(S, f3(r[0], r[1], r[2]), f3(r[3], r[4], r[5]), r[6], r[7], -1, -1,
-                                           stk + threadIdx.x, WG, h);
+                                           stk_col(stk, (int)threadIdx.x), WG, h);
     t_out[i] = ok ? h.t : -1.0f;
     prim_out[i] = ok ? S.tris[h.tri].prim : -1;
 }

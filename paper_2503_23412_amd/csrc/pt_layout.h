@@ -12,6 +12,24 @@ struct alignas(128) BNode {
 };
 static_assert(sizeof(BNode) == 128, "BNode must be one 128-byte line");
 
+// 8-wide BVH node, also one 128-byte line: the child boxes are quantised to 8 bits per plane
+// on a per-node grid (compressed wide nodes in the manner of Ylitie, Karras and Laine, HPG 2017):
+// child k spans [org + qlo[k] * 2^(e - 127), org + qhi[k] * 2^(e - 127)] on each axis, with e the
+// biased float exponent of the axis's scale. The quantised box contains the child's exact box
+// (lower planes rounded down, upper planes up). count[k]: 0 inner node child[k], 1..4 a leaf of
+// that many consecutive triangles from child[k], PT_CHILD_EMPTY no child (child[k] = -1).
+#define PT_CHILD_EMPTY 0xFF
+struct alignas(128) BNode8 {
+    float org[3];
+    uint8_t e[3];
+    uint8_t pad0;
+    uint8_t qlo_x[8], qhi_x[8], qlo_y[8], qhi_y[8], qlo_z[8], qhi_z[8];
+    int32_t child[8];
+    uint8_t count[8];
+    uint32_t pad1[6];
+};
+static_assert(sizeof(BNode8) == 128, "BNode8 must be one 128-byte line");
+
 // Triangle for intersection (BVH order): 48 bytes.
 struct alignas(16) TriIsect {
     float v0[3];
@@ -52,7 +70,8 @@ struct CamDev {
 #define PT_LSTORE 16   // light vertices stored per path when light vertices are connected (SPC, LT)
 #define PT_MAX_DEPTH 127   // longest path, in segments
 enum { LV_S = 1, LV_DIRAC = 2 };   // per light vertex flags
-#define PT_STACK 48
+#define PT_STACK 48    // traversal stack entries per thread, 4-wide walks
+#define PT_STACK8 64   // and 8-wide walks
 
 // Incomplete light sub-path candidate (y_{s-1} plus the control vertex), 80 bytes.
 struct Cand {
@@ -88,6 +107,9 @@ enum {
 // every queue count has its own slot
 static_assert(C_EYE_Q0 - C_LIGHT_Q0 >= PT_LSTORE, "light queue counters overlap");
 static_assert(C_SHD0 - C_EYE_Q0 >= PT_MAX_DEPTH + 1 && C_PROXYQ - C_SHD0 >= PT_MAX_DEPTH + 1, "queue counters overlap");
+
+// device wall-clock stamps of the start and end of the latest PT_TS_CAP iterations (ring by index)
+#define PT_TS_CAP 4096
 
 // running totals over the iterations of a scene (not cleared per iteration)
 enum { TOT_ITERS = 0, TOT_NAN, TOT_TRUNC, TOT_PROXY_VALID, TOT_RECIP_SAMPLES, TOT_CAND, TOT_COUNT };

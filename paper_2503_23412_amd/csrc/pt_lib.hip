@@ -13,8 +13,10 @@
 #include "../../include/pt.h"
 #include "pt_kernels.h"
 
-void pt_build_bvh4(const float *tri, int n, std::vector<BNode> &nodes, std::vector<int> &order);
+void pt_build_bvh(const float *tri, int n, std::vector<BNode> &nodes, std::vector<BNode8> *nodes8,
+                  std::vector<int> &order);
 int pt_bvh4_stack_need(const std::vector<BNode> &nodes, int *depth);
+int pt_bvh8_stack_need(const std::vector<BNode8> &nodes, int *depth);
 
 namespace {
 
@@ -61,22 +63,61 @@ pt_status check_device()
 #define PT_PERSIST_PER_CU 4   // workgroups per CU of the persistent pilot and stage-A grids
 #endif
 
-// launch a traversal kernel with the scene's stack entry type (16-bit for trees below 65,536 nodes)
+// launch a traversal kernel with the scene's stack entry type: 16-bit for trees below 65,536
+// nodes, and a type of the same size that walks the 8-wide tree when the scene uses it
+// (uint16_t / int: 4-wide; int16_t / uint32_t: 8-wide)
 #define PT_STK(sc, kern, grid, block, strm, ...)                                                \
     do {                                                                                        \
-        if ((sc)->stk16) kern<uint16_t><<<(grid), (block), 0, (strm)>>>(__VA_ARGS__);          \
-        else kern<int><<<(grid), (block), 0, (strm)>>>(__VA_ARGS__);                            \
-    } while (0)
-#define PT_STK_EXT(sc, counting, grid, block, strm, ...)                                        \
-    do {                                                                                        \
-        if ((sc)->stk16) {                                                                      \
-            if (counting) k_extend<true, uint16_t><<<(grid), (block), 0, (strm)>>>(__VA_ARGS__); \
-            else k_extend<false, uint16_t><<<(grid), (block), 0, (strm)>>>(__VA_ARGS__);         \
+        if ((sc)->bvh_cur == 8) {                                                               \
+            if ((sc)->stk16) kern<int16_t><<<(grid), (block), 0, (strm)>>>(__VA_ARGS__);        \
+            else kern<uint32_t><<<(grid), (block), 0, (strm)>>>(__VA_ARGS__);                   \
         } else {                                                                                \
-            if (counting) k_extend<true, int><<<(grid), (block), 0, (strm)>>>(__VA_ARGS__);      \
-            else k_extend<false, int><<<(grid), (block), 0, (strm)>>>(__VA_ARGS__);              \
+            if ((sc)->stk16) kern<uint16_t><<<(grid), (block), 0, (strm)>>>(__VA_ARGS__);       \
+            else kern<int><<<(grid), (block), 0, (strm)>>>(__VA_ARGS__);                        \
         }                                                                                       \
     } while (0)
+// extension launches over n rays with the scene's tuned workgroup size (64, 128 or 256)
+#define PT_EXT_WG(sc, counting, SEt, WGv, n, strm, ...)                                                        \
+    do {                                                                                                     \
+        if (counting) k_extend<true, SEt, WGv><<<blocks((n), WGv), WGv, 0, (strm)>>>(__VA_ARGS__);           \
+        else k_extend<false, SEt, WGv><<<blocks((n), WGv), WGv, 0, (strm)>>>(__VA_ARGS__);                   \
+    } while (0)
+#define PT_EXT_SE(sc, counting, SEt, n, strm, ...)                                                           \
+    do {                                                                                                     \
+        if ((sc)->ext_wg == 64) PT_EXT_WG(sc, counting, SEt, 64, n, strm, __VA_ARGS__);                      \
+        else if ((sc)->ext_wg == 256) PT_EXT_WG(sc, counting, SEt, 256, n, strm, __VA_ARGS__);               \
+        else PT_EXT_WG(sc, counting, SEt, 128, n, strm, __VA_ARGS__);                                        \
+    } while (0)
+#define PT_STK_EXT(sc, counting, n, strm, ...)                                                              \
+    do {                                                                                                     \
+        if ((sc)->bvh_cur == 8) {                                                                            \
+            if ((sc)->stk16) PT_EXT_SE(sc, counting, int16_t, n, strm, __VA_ARGS__);                         \
+            else PT_EXT_SE(sc, counting, uint32_t, n, strm, __VA_ARGS__);                                    \
+        } else {                                                                                             \
+            if ((sc)->stk16) PT_EXT_SE(sc, counting, uint16_t, n, strm, __VA_ARGS__);                        \
+            else PT_EXT_SE(sc, counting, int, n, strm, __VA_ARGS__);                                         \
+        }                                                                                                    \
+    } while (0)
+// PT_STK for kernels with a second (bool) template argument
+#define PT_STK_B(sc, kern, B, grid, block, strm, ...)                                           \
+    do {                                                                                        \
+        if ((sc)->bvh_cur == 8) {                                                               \
+            if ((sc)->stk16) kern<int16_t, B><<<(grid), (block), 0, (strm)>>>(__VA_ARGS__);     \
+            else kern<uint32_t, B><<<(grid), (block), 0, (strm)>>>(__VA_ARGS__);                \
+        } else {                                                                                \
+            if ((sc)->stk16) kern<uint16_t, B><<<(grid), (block), 0, (strm)>>>(__VA_ARGS__);    \
+            else kern<int, B><<<(grid), (block), 0, (strm)>>>(__VA_ARGS__);                     \
+        }                                                                                       \
+    } while (0)
+// stage A with Booth's roulette: its own instances (template argument BOOTH)
+template <typename SE>
+static void launch_recip_booth(int grid, hipStream_t st, SceneDev S, Cand *cand, const uint32_t *final_,
+                               const uint32_t *order, int repeats, uint32_t seed, uint32_t n1, uint32_t budget,
+                               float *runmax, ChainState *longq, float booth_r, unsigned long long *cnt, int chunk)
+{
+    k_recip<SE, true><<<grid, 64 * RW, 0, st>>>(S, cand, final_, order, repeats, seed, n1, budget, runmax, longq,
+                                                booth_r, cnt, chunk);
+}
 
 // alias rows of a T x n table over its non-empty columns: one wavefront per row when the row
 // fits LDS, else one thread per row
@@ -99,6 +140,7 @@ struct pt_scene {
     float scene_diag = 1.0f;
     // geometry
     BNode *nodes = nullptr;
+    BNode8 *nodes8 = nullptr;   // the 8-wide tree (uploaded when bvh_width is 0 or 8 and its walk fits)
     TriIsect *tris = nullptr;
     TriShade *shade = nullptr;
     MatDev *mats = nullptr;
@@ -114,6 +156,8 @@ struct pt_scene {
     uint32_t *cost_bin = nullptr, *order = nullptr;   // chain scheduling (longest expected first)
     unsigned long long *cnt = nullptr;
     unsigned long long *tot = nullptr;   // [TOT_COUNT] running totals over iterations (k_totals)
+    long long *ts = nullptr;             // [2 PT_TS_CAP] wall-clock start / end of the latest iterations
+    int wall_khz = 0;                    // device wall-clock rate
     float *runmax = nullptr;   // [2 * 5] running maxima of f/q per (class, u)
     // subspace-based connections: light subspaces, buckets of the pool, Q (learned, frozen), alias rows
     int n_lsub = 0;
@@ -131,6 +175,9 @@ struct pt_scene {
     float *al_prob = nullptr, *al_pmf = nullptr, *row_sum = nullptr, *gamma_acc = nullptr, *gamma_frz = nullptr;
     int *al_idx = nullptr, *al_scratch = nullptr;
     float *rstat_acc = nullptr, *rstat_frz = nullptr, *tile_proxy = nullptr, *tile_total = nullptr;
+    // control subspaces (Section 5.5) and the bucket maxima of f/q by (class, u, S, C)
+    int n_ctrl = 1, stat_cap = 0;
+    float *ctrl_c = nullptr, *bstat_acc = nullptr, *bstat_frz = nullptr;
     float *prev = nullptr, *row_tot = nullptr;
     int *s_count_prev = nullptr;
     // learned selection: parameters (FP32 master, BF16 copy, gradient, Adam moments) and
@@ -160,8 +207,14 @@ struct pt_scene {
     int tune_gen_grid = 8192;
     // workgroups of the persistent pilot and stage-A launches: four per CU
     int persist_wg = 1024;
+    // workgroup size of the extension (closest-hit) launches (pt_autotune: 64, 128 or 256)
+    int ext_wg = 128;
     // the chain kernels keep 16-bit traversal stack entries when the tree has fewer than 65,536 nodes
     bool stk16 = false;
+    // BVH widths available to the walks, and the one in use (S.nodes8 set when it is 8)
+    bool has4 = false, has8 = false;
+    int bvh_cur = 4;
+    int stack_need4 = 0, bvh_depth4 = 0, stack_need8 = 0, bvh_depth8 = 0;
     // second stream of an iteration: the eye pass and light tracing run on it beside the
     // reciprocal estimates (default priority), forked and joined with these events
     hipStream_t side = nullptr;
@@ -169,6 +222,10 @@ struct pt_scene {
     // multi-scene graph (pt_render_scenes) owned by the first scene of a batch
     hipGraphExec_t mgexec = nullptr;
     std::vector<char> mgkey;
+    RecipJob *mjobs = nullptr;           // multi-scene stage A: one job per scene (device)
+    uint32_t *mbase = nullptr;           // the scenes' first items, then the total (device)
+    unsigned long long *mwork = nullptr; // the shared work counter (device)
+    int queue_chunk = 1;                 // chains per take from the multi-scene work queue
     std::vector<hipStream_t> mstreams;
     std::vector<hipEvent_t> mevents;
     hipGraphExec_t gexec = nullptr;
@@ -190,6 +247,9 @@ struct pt_scene {
     {
         if (gexec) (void)hipGraphExecDestroy(gexec);
         if (mgexec) (void)hipGraphExecDestroy(mgexec);
+        if (mjobs) (void)hipFree(mjobs);
+        if (mbase) (void)hipFree(mbase);
+        if (mwork) (void)hipFree(mwork);
         for (hipStream_t q : mstreams) (void)hipStreamDestroy(q);
         for (hipEvent_t e : mevents) (void)hipEventDestroy(e);
         if (cap_stream) (void)hipStreamDestroy(cap_stream);
@@ -221,7 +281,8 @@ extern "C" pt_status pt_scene_upload(const pt_scene_desc *d, void *stream_, pt_s
         if (d->tex_w <= 0 || d->tex_h <= 0 || !d->tex) return set_err(PT_EINVAL, "missing emission texture");
         if (d->max_light_paths <= 0 || d->max_light_paths > (1 << 24))
             return set_err(PT_EINVAL, "max_light_paths out of range");
-        if (d->bvh_width != 4 && d->bvh_width != 0) return set_err(PT_EINVAL, "only 4-wide BVH nodes are built");
+        if (d->bvh_width != 4 && d->bvh_width != 8 && d->bvh_width != 0)
+            return set_err(PT_EINVAL, "bvh_width must be 0, 4 or 8");
         for (int i = 0; i < d->n_tri; ++i)
             if (d->tri_mat[i] < 0 || d->tri_mat[i] >= d->n_mat) return set_err(PT_EINVAL, "triangle %d: bad material", i);
         for (int m = 0; m < d->n_mat; ++m) {
@@ -236,6 +297,7 @@ extern "C" pt_status pt_scene_upload(const pt_scene_desc *d, void *stream_, pt_s
             int ncu = 0;
             HIPCHK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, s->device));
             s->persist_wg = PT_PERSIST_PER_CU * std::max(ncu, 1);
+            HIPCHK(hipDeviceGetAttribute(&s->wall_khz, hipDeviceAttributeWallClockRate, s->device));
             // the second stream of an iteration (default priority) and its fork / join events
             HIPCHK(hipStreamCreateWithFlags(&s->side, hipStreamNonBlocking));
             HIPCHK(hipEventCreateWithFlags(&s->ev_fork, hipEventDisableTiming));
@@ -245,16 +307,26 @@ extern "C" pt_status pt_scene_upload(const pt_scene_desc *d, void *stream_, pt_s
         s->ntri = d->n_tri;
         // BVH
         std::vector<BNode> nodes;
+        std::vector<BNode8> nodes8;
         std::vector<int> order;
-        pt_build_bvh4(d->tri, d->n_tri, nodes, order);
-        s->stack_need = pt_bvh4_stack_need(nodes, &s->bvh_depth);
-        if (s->stack_need > PT_STACK) {
-            const int need = s->stack_need;
+        const bool want8 = d->bvh_width != 4;
+        pt_build_bvh(d->tri, d->n_tri, nodes, want8 ? &nodes8 : nullptr, order);
+        s->stack_need4 = pt_bvh4_stack_need(nodes, &s->bvh_depth4);
+        if (want8) s->stack_need8 = pt_bvh8_stack_need(nodes8, &s->bvh_depth8);
+        // a width is available when its worst-case walk fits the kernels' stack
+        s->has4 = d->bvh_width != 8 && s->stack_need4 <= PT_STACK;
+        s->has8 = want8 && s->stack_need8 <= PT_STACK8;
+        if ((d->bvh_width == 4 && !s->has4) || (d->bvh_width == 8 && !s->has8) || (!s->has4 && !s->has8)) {
+            const bool w8 = d->bvh_width == 8;
+            const int need = w8 ? s->stack_need8 : s->stack_need4;
             delete s;
-            return set_err(PT_EUNSUPPORTED, "the BVH needs a traversal stack of %d entries; the kernels hold %d", need,
-                           PT_STACK);
+            return set_err(PT_EUNSUPPORTED, "the %d-wide BVH needs a traversal stack of %d entries; the kernels hold %d",
+                           w8 ? 8 : 4, need, w8 ? PT_STACK8 : PT_STACK);
         }
-        s->stk16 = nodes.size() < 65536;
+        s->bvh_cur = s->has4 ? 4 : 8;
+        s->stack_need = s->bvh_cur == 4 ? s->stack_need4 : s->stack_need8;
+        s->bvh_depth = s->bvh_cur == 4 ? s->bvh_depth4 : s->bvh_depth8;
+        s->stk16 = nodes.size() < 65536 && nodes8.size() < 65536;
         s->inv_order.assign(d->n_tri, 0);
         for (int i = 0; i < d->n_tri; ++i) s->inv_order[order[i]] = i;
         std::vector<TriIsect> ti(d->n_tri);
@@ -310,6 +382,7 @@ extern "C" pt_status pt_scene_upload(const pt_scene_desc *d, void *stream_, pt_s
         pt_status st;
 #define AL(p, n) if ((st = s->alloc(p, n)) != PT_OK) { delete s; return st; }
         AL(s->nodes, nodes.size());
+        if (s->has8) AL(s->nodes8, nodes8.size());
         AL(s->tris, ti.size());
         AL(s->shade, ts.size());
         AL(s->mats, mats.size());
@@ -332,6 +405,7 @@ extern "C" pt_status pt_scene_upload(const pt_scene_desc *d, void *stream_, pt_s
         AL(s->E.frame, (size_t)3 * np);
         AL(s->cnt, C_COUNT);
         AL(s->tot, TOT_COUNT);
+        AL(s->ts, 2 * PT_TS_CAP);
         AL(s->runmax, 16);
         AL(s->chq[0], CHAIN_LIST_CAP); AL(s->chq[1], CHAIN_LIST_CAP);
         AL(s->chbuf, CHAIN_BUF);
@@ -339,6 +413,9 @@ extern "C" pt_status pt_scene_upload(const pt_scene_desc *d, void *stream_, pt_s
         s->L.M = M;
         s->E.npix = np;
         HIPCHK(hipMemcpyAsync(s->nodes, nodes.data(), nodes.size() * sizeof(BNode), hipMemcpyHostToDevice, stream));
+        if (s->has8)
+            HIPCHK(hipMemcpyAsync(s->nodes8, nodes8.data(), nodes8.size() * sizeof(BNode8), hipMemcpyHostToDevice,
+                                  stream));
         HIPCHK(hipMemcpyAsync(s->tris, ti.data(), ti.size() * sizeof(TriIsect), hipMemcpyHostToDevice, stream));
         HIPCHK(hipMemcpyAsync(s->shade, ts.data(), ts.size() * sizeof(TriShade), hipMemcpyHostToDevice, stream));
         HIPCHK(hipMemcpyAsync(s->mats, mats.data(), mats.size() * sizeof(MatDev), hipMemcpyHostToDevice, stream));
@@ -348,9 +425,10 @@ extern "C" pt_status pt_scene_upload(const pt_scene_desc *d, void *stream_, pt_s
         HIPCHK(hipMemsetAsync(s->E.frame, 0, sizeof(float) * 3 * np, stream));
         HIPCHK(hipMemsetAsync(s->runmax, 0, sizeof(float) * 16, stream));
         HIPCHK(hipMemsetAsync(s->tot, 0, sizeof(unsigned long long) * TOT_COUNT, stream));
+        HIPCHK(hipMemsetAsync(s->ts, 0, sizeof(long long) * 2 * PT_TS_CAP, stream));
         HIPCHK(hipStreamSynchronize(stream));
         SceneDev &S = s->S;
-        S.nodes = s->nodes; S.tris = s->tris; S.shade = s->shade; S.mats = s->mats; S.tex = s->tex;
+        S.nodes = s->nodes; S.nodes8 = s->nodes8; S.tris = s->tris; S.shade = s->shade; S.mats = s->mats; S.tex = s->tex;
         S.tex_w = d->tex_w; S.tex_h = d->tex_h; S.em_tri = s->em_tri; S.em_cdf = s->em_cdf; S.n_em = (int)em.size();
         S.em_area = (float)area_acc;
         S.tmin = 2e-6f * s->scene_diag;
@@ -454,6 +532,23 @@ __global__ void k_feat_cands(SceneDev S, const Cand *cand, const unsigned long l
     feat9(S, xyz(c.v), S.shade[__float_as_int(c.v.w)].n, oct_dec(make_float2(c.pad[0], c.pad[1])), f);
     for (int j = 0; j < 9; ++j) feat[FEAT * (size_t)i + j] = f[j];
 }
+__global__ void k_set_counter(unsigned long long *cnt, int idx, unsigned long long v)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) cnt[idx] = v;
+}
+// features of the class-B candidates' control vertices y_0 (position, emitter normal, no
+// direction), compacted with the counter cnt[slot]
+__global__ void k_feat_ctrl(SceneDev S, const Cand *cand, unsigned long long *cnt, float *feat, int slot)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (int)cnt[C_NCAND]) return;
+    const Cand &c = cand[i];
+    if (!(c.cls_u >> 8)) return;
+    float f[9];
+    feat9(S, xyz(c.hc), S.shade[__float_as_int(c.hc.w)].n, f3(0.f, 0.f, 0.f), f);
+    const int k = (int)atomicAdd(cnt + slot, 1ull);
+    for (int j = 0; j < 9; ++j) feat[FEAT * (size_t)k + j] = f[j];
+}
 __global__ void k_feat_proxy(SceneDev S, const ProxyItem *items, const unsigned long long *cnt, float *feat)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -469,9 +564,11 @@ extern "C" pt_status pt_build_subspaces(pt_scene *s, const pt_subspace_params *p
 {
     if (!s || !p) return set_err(PT_EINVAL, "null argument");
     if (p->n_eye <= 0 || p->n_eye > 4096 || p->n_spec <= 0 || p->n_spec > 4096 || p->n_pretrace < 0 ||
-        p->kmeans_iters < 0 || p->kmeans_iters > 64 || p->n_light < 0 || p->n_light > 4096)
+        p->kmeans_iters < 0 || p->kmeans_iters > 64 || p->n_light < 0 || p->n_light > 4096 || p->n_ctrl < 0 ||
+        p->n_ctrl > 256)
         return set_err(PT_EINVAL, "subspace parameters out of range");
     const int nl = p->n_light > 0 ? p->n_light : p->n_eye;
+    const int nc = std::max(1, p->n_ctrl);
     hipStream_t st = (hipStream_t)stream_;
     const int M = s->max_light, np = s->npix;
     const int ne = p->n_eye, ns = p->n_spec;
@@ -506,7 +603,6 @@ extern "C" pt_status pt_build_subspaces(pt_scene *s, const pt_subspace_params *p
         AL(s->al_prob, (size_t)ne * ns); AL(s->al_idx, (size_t)ne * ns); AL(s->al_scratch, (size_t)2 * ne * ns);
         AL(s->al_pmf, (size_t)ne * ns);
         AL(s->row_sum, ne); AL(s->gamma_acc, (size_t)ne * ns); AL(s->gamma_frz, (size_t)ne * ns);
-        AL(s->rstat_acc, (size_t)30 * ns); AL(s->rstat_frz, (size_t)30 * ns);
         AL(s->s_count_prev, ns); AL(s->row_tot, ne);
         if (!s->prev) AL(s->prev, 4);
         s->tiles_x = (s->W + s->tile - 1) / s->tile;
@@ -515,16 +611,27 @@ extern "C" pt_status pt_build_subspaces(pt_scene *s, const pt_subspace_params *p
 #undef AL
         s->n_eye = ne; s->n_spec = ns;
     }
+    // statistics by (class, u, S, C): 10 x n_ctrl x n_spec buckets
+    if ((long)10 * nc * ns > s->stat_cap) {
+        pt_status e;
+#define AL(ptr, n) if ((e = s->alloc(ptr, n)) != PT_OK) return e;
+        AL(s->rstat_acc, (size_t)30 * nc * ns); AL(s->rstat_frz, (size_t)30 * nc * ns);
+        AL(s->bstat_acc, (size_t)30 * nc * ns); AL(s->bstat_frz, (size_t)30 * nc * ns);
+        AL(s->ctrl_c, (size_t)256 * FEAT);
+#undef AL
+        s->stat_cap = 10 * nc * ns;
+    }
+    s->n_ctrl = nc;
     // pre-trace: light sub-paths -> candidate specular vertices; eye paths -> first diffuse vertices
     SceneDev S = s->S;
     LightBuf L = s->L;
     L.M = std::max(1, std::min(M, p->n_pretrace > 0 ? p->n_pretrace : M));
     const uint32_t key = 0xFFFFFF00u;
     k_zero<<<blocks(C_COUNT, 256), 256, 0, st>>>(s->cnt, C_COUNT);
-    k_iter<<<1, 1, 0, st>>>(s->cnt, key, 0, 0);
+    k_iter<<<1, 1, 0, st>>>(s->cnt, key, 0, 0, nullptr, 0);
     k_light_gen<<<blocks(L.M, 256), 256, 0, st>>>(S, L, p->seed, s->cnt);
     for (int vi = 1; vi < PT_LMAX; ++vi) {
-        PT_STK_EXT(s, false, blocks(L.M, WG), WG, st, S, L.q[(vi - 1) & 1], s->cnt, C_LIGHT_Q0 + vi - 1, L.ro, L.rd,
+        PT_STK_EXT(s, false, L.M, st, S, L.q[(vi - 1) & 1], s->cnt, C_LIGHT_Q0 + vi - 1, L.ro, L.rd,
                    L.hit, s->cnt, C_RAYS_LIGHT);
         k_light_shade<<<blocks(L.M, 256), 256, 0, st>>>(S, L, p->seed, vi, PT_LMAX, s->cnt);
     }
@@ -545,6 +652,15 @@ extern "C" pt_status pt_build_subspaces(pt_scene *s, const pt_subspace_params *p
     HIPCHK(hipStreamSynchronize(st));
     TRY(run_kmeans(s, s->feat, (int)c[C_NCAND], s->spec_c, ns, p->kmeans_iters, st));
     TRY(build_groups(s, s->spec_c, ns, s->gs_spec, p->kmeans_iters, st));
+    // control subspaces: the control vertices y_0 of the class-B candidates (position, normal)
+    if (nc > 1) {
+        k_set_counter<<<1, 1, 0, st>>>(s->cnt, C_MLP_ROWS, 0ull);
+        k_feat_ctrl<<<blocks(4L * L.M, 256), 256, 0, st>>>(S, s->cand, s->cnt, s->feat, C_MLP_ROWS);
+        HIPCHK(hipMemcpyAsync(c, s->cnt, sizeof(c), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        TRY(run_kmeans(s, s->feat, (int)c[C_MLP_ROWS], s->ctrl_c, nc, p->kmeans_iters, st));
+        k_set_counter<<<1, 1, 0, st>>>(s->cnt, C_MLP_ROWS, 0ull);
+    }
     // eye: first diffuse vertices of one pass (the proxy queue collects them)
     EyeBuf E = s->E;
     EyeParams EP{};
@@ -553,7 +669,7 @@ extern "C" pt_status pt_build_subspaces(pt_scene *s, const pt_subspace_params *p
     k_zero<<<blocks(C_COUNT, 256), 256, 0, st>>>(s->cnt, C_COUNT);
     k_camera<<<blocks(np, 256), 256, 0, st>>>(S, E, p->seed, s->cnt);
     for (int t = 1; t <= EP.K; ++t) {
-        PT_STK_EXT(s, false, blocks(np, WG), WG, st, S, E.q[(t - 1) & 1], s->cnt, C_EYE_Q0 + t - 1, E.ro, E.rd, E.hit,
+        PT_STK_EXT(s, false, np, st, S, E.q[(t - 1) & 1], s->cnt, C_EYE_Q0 + t - 1, E.ro, E.rd, E.hit,
                    s->cnt, C_RAYS_EYE);
         k_eye_shade<<<blocks(np, 256), 256, 0, st>>>(S, E, EP, D, L, ConnDev{}, t, s->cnt);
     }
@@ -565,7 +681,8 @@ extern "C" pt_status pt_build_subspaces(pt_scene *s, const pt_subspace_params *p
     TRY(build_groups(s, s->eye_c, ne, s->gs_eye, p->kmeans_iters, st));
     // statistics start from nothing
     k_fill<<<blocks((long)ne * ns, 256), 256, 0, st>>>(s->gamma_acc, 0.0f, (size_t)ne * ns);
-    k_fill<<<blocks(30L * ns, 256), 256, 0, st>>>(s->rstat_acc, 0.0f, (size_t)30 * ns);
+    k_fill<<<blocks(30L * nc * ns, 256), 256, 0, st>>>(s->rstat_acc, 0.0f, (size_t)30 * nc * ns);
+    k_fill<<<blocks(30L * nc * ns, 256), 256, 0, st>>>(s->bstat_acc, 0.0f, (size_t)30 * nc * ns);
     k_fill<<<blocks(s->n_tiles, 256), 256, 0, st>>>(s->tile_proxy, 0.0f, (size_t)s->n_tiles);
     k_fill<<<blocks(s->n_tiles, 256), 256, 0, st>>>(s->tile_total, 0.0f, (size_t)s->n_tiles);
     k_fill<<<1, 16, 0, st>>>(s->runmax, 0.0f, 16);
@@ -587,7 +704,8 @@ extern "C" pt_status pt_build_subspaces(pt_scene *s, const pt_subspace_params *p
 }
 
 namespace {
-#define MLP_CAP 65536   // training samples per iteration
+#define MLP_CAP 65536   // training samples per iteration (each head)
+#define MLP_CHUNK (2 * MLP_CAP)   // proxy items per chunk of the per-iteration queries
 #define MLP_KSPLIT 32   // K splits of the weight-gradient products (K = samples)
 
 struct MlpOff {
@@ -604,10 +722,6 @@ MlpOff mlp_off(int nout)
     return o;
 }
 
-__global__ void k_set_counter(unsigned long long *cnt, int idx, unsigned long long v)
-{
-    if (threadIdx.x == 0 && blockIdx.x == 0) cnt[idx] = v;
-}
 __global__ void k_to_bf16(const float *w, uint16_t *wb, size_t n)
 {
     const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -652,8 +766,8 @@ pt_status ensure_mlp(pt_scene *s, hipStream_t st)
     const int nout = s->n_spec + MLP_VMF;
     if (s->mlp_nout != nout) {
         const MlpOff o = mlp_off(nout);
-        // rows: every pixel's query, or a training batch of both heads' samples
-        const int R = std::max(s->npix, 2 * MLP_CAP);
+        // rows: one chunk of the per-item queries, or a training batch of both heads' samples
+        const int R = 2 * MLP_CAP;
         pt_status e;
 #define AL(ptr, n) if ((e = s->alloc(ptr, n)) != PT_OK) return e;
         AL(s->mw, o.n); AL(s->mg, o.n); AL(s->mm, o.n); AL(s->mv, o.n); AL(s->mwb, o.n); AL(s->mwt, o.n);
@@ -687,20 +801,21 @@ pt_status ensure_mlp(pt_scene *s, hipStream_t st)
 }
 
 // outputs col0 .. col0 + ncols - 1 of the first rows of s->mx into out (row stride ncols), with
-// bias_out[col] added when given: rows = min(M, cnt[m_cidx]) (or M), one fused launch; keep_h: the
-// hidden activations go to mh[0..2] for the backward pass
+// bias_out[col] added when given: rows = min(M, cnt[m_cidx] - off) (or M), one fused launch;
+// keep_h: the hidden activations go to mh[0..2] for the backward pass
 void mlp_forward(pt_scene *s, int M, const unsigned long long *cnt, int m_cidx, float *out, int col0, int ncols,
-                 hipStream_t st, const float *bias_out = nullptr, bool keep_h = false)
+                 hipStream_t st, const float *bias_out = nullptr, bool keep_h = false, int off = 0)
 {
     const int nout = s->mlp_nout;
     const MlpOff o = mlp_off(nout);
     const int grid = std::max(1, std::min(blocks(M, MLP_FT_ROWS), 2048));
     if (keep_h)
         k_mlp_fwd<true><<<grid, 256, 0, st>>>(s->mx, M, cnt, m_cidx, s->mwt, s->mw, o.W1, o.b1, o.W2, o.b2, o.W3, o.b3,
-                                              o.W4, nout, col0, ncols, out, bias_out, s->mh[0], s->mh[1], s->mh[2]);
+                                              o.W4, nout, col0, ncols, out, bias_out, s->mh[0], s->mh[1], s->mh[2], off);
     else
         k_mlp_fwd<false><<<grid, 256, 0, st>>>(s->mx, M, cnt, m_cidx, s->mwt, s->mw, o.W1, o.b1, o.W2, o.b2, o.W3,
-                                               o.b3, o.W4, nout, col0, ncols, out, bias_out, nullptr, nullptr, nullptr);
+                                               o.b3, o.W4, nout, col0, ncols, out, bias_out, nullptr, nullptr, nullptr,
+                                               off);
 }
 
 // gradient of the training batch's loss (rows: T's min(cap, C_MLP_N) subspace samples, then its
@@ -750,7 +865,9 @@ pt_status check_params(pt_scene *s, const pt_iter_params *p, float *acc)
     if (p->n_light < 1 || p->n_light > s->max_light) return set_err(PT_EINVAL, "n_light out of range [1, %d]", s->max_light);
     if (p->u_max < 1 || p->u_max > 4) return set_err(PT_EINVAL, "u_max out of range [1, 4]");
     if (p->recip_repeats < 1 || p->recip_repeats > 8) return set_err(PT_EINVAL, "recip_repeats out of range [1, 8]");
-    if (p->cand_cap < 1 || p->pilot < 1) return set_err(PT_EINVAL, "cand_cap and pilot must be positive");
+    if (p->cand_cap < 1 || p->pilot < 0) return set_err(PT_EINVAL, "cand_cap must be positive, pilot not negative");
+    if (p->pilot == 0 && (p->flags & PT_FLAG_PROXY) && !(p->flags & (PT_FLAG_GAMMA | PT_FLAG_MIS | PT_FLAG_MLP)))
+        return set_err(PT_EINVAL, "pilot = 0 needs the subspace statistics (PT_FLAG_GAMMA, PT_FLAG_MIS or PT_FLAG_MLP)");
     if ((p->flags & PT_FLAG_ONLY_PROXY_CLASS) && (p->flags & PT_FLAG_ONLY_OTHER))
         return set_err(PT_EINVAL, "class filters are exclusive");
     if ((p->flags & (PT_FLAG_SPC | PT_FLAG_LT)) && p->max_depth > PT_LSTORE)
@@ -766,9 +883,15 @@ pt_status check_params(pt_scene *s, const pt_iter_params *p, float *acc)
 // Enqueues one iteration on `stream`: kernel launches only (no host synchronisation, no
 // memset), so the sequence can be captured into a HIP graph. graph = true: the iteration index
 // in device memory is advanced by one instead of being set from p->iteration.
+// stage A's first-round sample count of a chain
+uint32_t stage_a_n1(const pt_iter_params *p) { return (uint32_t)std::max(64.0f, p->cost_cap / (float)p->recip_repeats); }
+
+// part: 0 = the whole iteration; 1 = up to the reciprocal chains' stage A (exclusive); 2 = from
+// the chain rounds on (a multi-scene graph runs stage A of all its scenes in one launch between)
 pt_status enqueue_iteration(pt_scene *s, const pt_iter_params *p, float *acc, float *acc2, hipStream_t stream,
-                            bool graph)
+                            bool graph, int part = 0)
 {
+    const bool pre = part != 2, post = part != 1;
     SceneDev S = s->S;
     LightBuf L = s->L;
     L.M = p->n_light;
@@ -792,22 +915,24 @@ pt_status enqueue_iteration(pt_scene *s, const pt_iter_params *p, float *acc, fl
     const bool mlp = proxy && (p->flags & PT_FLAG_MLP) && s->mlp_ready && s->mlp_nout == s->n_spec + MLP_VMF;
     const bool labels = gamma || mis || mlp;
     const int ne = s->n_eye, ns = s->n_spec;
-    k_zero<<<blocks(C_COUNT, 256), 256, 0, stream>>>(s->cnt, C_COUNT);
-    k_iter<<<1, 1, 0, stream>>>(s->cnt, p->iteration, graph ? 1 : 0, p->train_iters);
-    if (labels) {
+    if (pre) k_zero<<<blocks(C_COUNT, 256), 256, 0, stream>>>(s->cnt, C_COUNT);
+    if (pre) k_iter<<<1, 1, 0, stream>>>(s->cnt, p->iteration, graph ? 1 : 0, p->train_iters, s->ts, 1);
+    if (labels && pre) {
         // statistics of earlier iterations only: frozen copies for this iteration
         k_copy<<<blocks((long)ne * ns, 256), 256, 0, stream>>>(s->gamma_acc, s->gamma_frz, (size_t)ne * ns);
-        k_copy<<<blocks(30L * ns, 256), 256, 0, stream>>>(s->rstat_acc, s->rstat_frz, (size_t)30 * ns);
+        const size_t nst = (size_t)10 * s->n_ctrl * ns;
+        k_copy<<<blocks((long)(3 * nst), 256), 256, 0, stream>>>(s->rstat_acc, s->rstat_frz, 3 * nst);
+        k_copy<<<blocks((long)(3 * nst), 256), 256, 0, stream>>>(s->bstat_acc, s->bstat_frz, 3 * nst);
         k_row_tot<<<blocks(ne, 256), 256, 0, stream>>>(s->gamma_frz, ne, ns, s->row_tot);
     }
     const bool conn = (p->flags & PT_FLAG_SPC) != 0, ltr = (p->flags & PT_FLAG_LT) != 0;
     // light sub-paths: y_0 .. y_{lmax-1}; connections and light tracing use every vertex a path
     // within max_depth segments can have, the proxy candidates the first PT_LMAX
     const int lmax = (conn || ltr) ? p->max_depth : std::min(p->max_depth - 1, PT_LMAX);
-    if (proxy || conn || ltr) {
+    if (pre && (proxy || conn || ltr)) {
         k_light_gen<<<blocks(M, 256), 256, 0, stream>>>(S, L, p->seed, s->cnt);
         for (int vi = 1; vi < lmax; ++vi) {
-            PT_STK_EXT(s, false, blocks(M, WG), WG, stream, S, L.q[(vi - 1) & 1], s->cnt, C_LIGHT_Q0 + vi - 1, L.ro,
+            PT_STK_EXT(s, false, M, stream, S, L.q[(vi - 1) & 1], s->cnt, C_LIGHT_Q0 + vi - 1, L.ro,
                        L.rd, L.hit, s->cnt, C_RAYS_LIGHT);
             k_light_shade<<<blocks(M, 256), 256, 0, stream>>>(S, L, p->seed, vi, lmax, s->cnt);
         }
@@ -820,7 +945,7 @@ pt_status enqueue_iteration(pt_scene *s, const pt_iter_params *p, float *acc, fl
     // the device to itself, and so do captured iterations (pt_render_batch, pt_render_scenes: a
     // fork inside the multi-scene capture ended the process; their scenes already run side by
     // side as the graph's branches).
-    const bool overlap = !timing && !graph && proxy && s->side;
+    const bool overlap = !timing && !graph && proxy && s->side && part == 0;
     hipStream_t es = stream;
     if (overlap) {
         HIPCHK(hipEventRecord(s->ev_fork, stream));
@@ -839,10 +964,10 @@ pt_status enqueue_iteration(pt_scene *s, const pt_iter_params *p, float *acc, fl
         CD.row_tot = s->q_rowtot; CD.count_prev = s->lcount_prev; CD.ne_prev = s->lne_prev;
         CD.defensive = p->defensive; CD.qacc = s->qacc;
         // Q of earlier iterations only
-        k_copy<<<blocks((long)ne * nl, 256), 256, 0, es>>>(s->qacc, s->qfrz, (size_t)ne * nl);
-        k_row_tot<<<blocks(ne, 256), 256, 0, es>>>(s->qfrz, ne, nl, s->q_rowtot);
+        if (pre) k_copy<<<blocks((long)ne * nl, 256), 256, 0, es>>>(s->qacc, s->qfrz, (size_t)ne * nl);
+        if (pre) k_row_tot<<<blocks(ne, 256), 256, 0, es>>>(s->qfrz, ne, nl, s->q_rowtot);
     }
-    if ((conn || ltr) && lmax >= 2) {
+    if (pre && (conn || ltr) && lmax >= 2) {
         const long maxp = (long)(lmax - 1) * M;
         if (!conn) k_pool<<<blocks(maxp, 256), 256, 0, es>>>(L, lmax, s->cnt);
         if (conn) {
@@ -878,53 +1003,71 @@ pt_status enqueue_iteration(pt_scene *s, const pt_iter_params *p, float *acc, fl
         D.eye = cent_set(s->eye_c, s->gs_eye); D.spec = cent_set(s->spec_c, s->gs_spec);
         D.s_count = s->s_count; D.s_off = s->s_off; D.s_list = s->s_list; D.nonempty = s->nonempty; D.n_nonempty = s->n_ne;
         D.al_prob = s->al_prob; D.al_idx = s->al_idx; D.al_pmf = s->al_pmf; D.row_sum = s->row_sum; D.gamma = s->gamma_frz;
-        D.defensive = p->defensive; D.rstat = s->rstat_frz;
+        D.defensive = p->defensive; D.rstat = s->rstat_frz; D.bstat = s->bstat_frz;
+        D.ctrl_c = s->ctrl_c; D.n_ctrl = s->n_ctrl;
         D.prev = s->prev; D.s_count_prev = s->s_count_prev; D.row_tot = s->row_tot;
         D.tile_proxy = s->tile_proxy; D.tile_total = s->tile_total; D.tile = s->tile; D.tiles_x = s->tiles_x;
         D.tile_thr = p->tile_threshold; D.tile_low = p->tile_low_prob;
     }
     const int np = s->npix;
-    k_camera<<<blocks(np, 256), 256, 0, es>>>(S, E, p->seed, s->cnt);
-    for (int t = 1; t <= p->max_depth; ++t) {
+    if (pre) k_camera<<<blocks(np, 256), 256, 0, es>>>(S, E, p->seed, s->cnt);
+    for (int t = 1; pre && t <= p->max_depth; ++t) {
         if (timing) HIPCHK(hipEventRecord(s->ev[2 * (t - 1)], es));
-        PT_STK_EXT(s, count, blocks(np, WG), WG, es, S, E.q[(t - 1) & 1], s->cnt, C_EYE_Q0 + t - 1, E.ro, E.rd, E.hit,
+        PT_STK_EXT(s, count, np, es, S, E.q[(t - 1) & 1], s->cnt, C_EYE_Q0 + t - 1, E.ro, E.rd, E.hit,
                    s->cnt, C_RAYS_EYE);
         if (timing) HIPCHK(hipEventRecord(s->ev[2 * (t - 1) + 1], es));
         k_eye_shade<<<blocks(np, 256), 256, 0, es>>>(S, E, EP, D, L, CD, t, s->cnt);
         PT_STK(s, k_occluded, blocks(2L * np, WG), WG, es, S, E, CD, t, s->cnt);
     }
-    if (ltr && lmax >= 2)
+    if (pre && ltr && lmax >= 2)
         PT_STK(s, k_lt, blocks((long)(lmax - 1) * M, WG), WG, es, S, L, EP, D, CD, E.frame, s->cnt);
-    if (conn && lmax >= 2) k_conn_prev<<<blocks(nl, 256), 256, 0, es>>>(CD, s->lcount_prev, s->lne_prev);
+    if (pre && conn && lmax >= 2) k_conn_prev<<<blocks(nl, 256), 256, 0, es>>>(CD, s->lcount_prev, s->lne_prev);
     if (proxy) {
         if (lmax >= 2) {
-            k_candidates<<<blocks(M, 256), 256, 0, stream>>>(L, p->u_max, s->cand, s->cnt);
             const int maxc = 4 * M;
-            k_keep<<<blocks(maxc, 256), 256, 0, stream>>>(p->cand_cap, p->seed, s->kept, maxc, s->cnt);
             const size_t e0 = 2 * (size_t)p->max_depth;
-            if (timing) HIPCHK(hipEventRecord(s->ev[e0], stream));
-            PT_STK(s, k_pilot, s->persist_wg, 64 * RW, stream, S, s->cand, s->kept, p->pilot, p->seed, s->runmax, s->cnt);
-            k_roulette<<<blocks(maxc, 256), 256, 0, stream>>>(s->cand, s->kept, s->final_, s->cost_bin, s->runmax,
-                                                              S.em_area, p->recip_repeats, p->cost_cap, p->seed, s->cnt);
-            k_order<<<blocks(maxc, 256), 256, 0, stream>>>(s->cost_bin, s->order, s->cnt);
-            const uint32_t n1 = (uint32_t)std::max(64.0f, p->cost_cap / (float)p->recip_repeats);
+            if (pre) {
+                k_candidates<<<blocks(M, 256), 256, 0, stream>>>(L, p->u_max, s->cand, s->cnt);
+                k_keep<<<blocks(maxc, 256), 256, 0, stream>>>(p->cand_cap, p->seed, s->kept, maxc, s->cnt);
+                // subspace labels (S, C) of the kept candidates: their buckets' statistics give B a floor
+                if (labels) k_label_kept<<<blocks(maxc, 256), 256, 0, stream>>>(S, D, s->cand, s->kept, s->cnt);
+                if (timing) HIPCHK(hipEventRecord(s->ev[e0], stream));
+                // pilot = 0: B and beta of a candidate from its (class, u, S, C) bucket's statistics alone
+                if (p->pilot > 0)
+                    PT_STK(s, k_pilot, s->persist_wg, 64 * RW, stream, S, s->cand, s->kept, p->pilot, p->seed,
+                           s->runmax, s->cnt);
+                k_roulette<<<blocks(maxc, 256), 256, 0, stream>>>(s->cand, s->kept, s->final_, s->cost_bin, s->runmax,
+                                                                  D, labels ? 1 : 0, S.em_area, p->recip_repeats,
+                                                                  p->cost_cap, p->seed, s->cnt);
+                k_order<<<blocks(maxc, 256), 256, 0, stream>>>(s->cost_bin, s->order, s->cnt);
+            }
+            const uint32_t n1 = stage_a_n1(p);
             const float booth_r = (p->flags & PT_FLAG_BOOTH) ? p->booth_r : 0.0f;
             if (timing) HIPCHK(hipEventRecord(s->ev[e0 + 1], stream));
-            if (booth_r > 0.0f) {
-                if (s->stk16)
-                    k_recip<uint16_t, true><<<s->persist_wg, 64 * RW, 0, stream>>>(
-                        S, s->cand, s->final_, s->order, p->recip_repeats, p->seed, n1, s->tune_budget, s->runmax,
-                        s->chq[0], booth_r, s->cnt);
-                else
-                    k_recip<int, true><<<s->persist_wg, 64 * RW, 0, stream>>>(
-                        S, s->cand, s->final_, s->order, p->recip_repeats, p->seed, n1, s->tune_budget, s->runmax,
-                        s->chq[0], booth_r, s->cnt);
+            if (part != 0) {
+                // stage A belongs to the multi-scene launch between the two parts
+            } else if (booth_r > 0.0f) {
+                if (s->bvh_cur == 8) {
+                    if (s->stk16) launch_recip_booth<int16_t>(s->persist_wg, stream, S, s->cand, s->final_, s->order,
+                                                              p->recip_repeats, p->seed, n1, s->tune_budget, s->runmax,
+                                                              s->chq[0], booth_r, s->cnt, s->queue_chunk);
+                    else launch_recip_booth<uint32_t>(s->persist_wg, stream, S, s->cand, s->final_, s->order,
+                                                      p->recip_repeats, p->seed, n1, s->tune_budget, s->runmax,
+                                                      s->chq[0], booth_r, s->cnt, s->queue_chunk);
+                } else {
+                    if (s->stk16) launch_recip_booth<uint16_t>(s->persist_wg, stream, S, s->cand, s->final_, s->order,
+                                                               p->recip_repeats, p->seed, n1, s->tune_budget, s->runmax,
+                                                               s->chq[0], booth_r, s->cnt, s->queue_chunk);
+                    else launch_recip_booth<int>(s->persist_wg, stream, S, s->cand, s->final_, s->order,
+                                                 p->recip_repeats, p->seed, n1, s->tune_budget, s->runmax, s->chq[0],
+                                                 booth_r, s->cnt, s->queue_chunk);
+                }
             } else {
                 PT_STK(s, k_recip, s->persist_wg, 64 * RW, stream, S, s->cand, s->final_, s->order, p->recip_repeats,
-                       p->seed, n1, s->tune_budget, s->runmax, s->chq[0], booth_r, s->cnt);
+                       p->seed, n1, s->tune_budget, s->runmax, s->chq[0], booth_r, s->cnt, s->queue_chunk);
             }
             if (timing) HIPCHK(hipEventRecord(s->ev[e0 + 2], stream));
-            for (int r = 0; r < CHAIN_ROUNDS; ++r) {
+            for (int r = 0; post && r < CHAIN_ROUNDS; ++r) {
                 const int in = r & 1, out = in ^ 1;
                 k_set_counter<<<1, 1, 0, stream>>>(s->cnt, C_LONGQ0 + out, 0ull);
                 PT_STK(s, k_chain_gen, s->tune_gen_grid, WG, stream, S, s->cand, s->chq[in], C_LONGQ0 + in, r, p->seed,
@@ -934,20 +1077,22 @@ pt_status enqueue_iteration(pt_scene *s, const pt_iter_params *p, float *acc, fl
                                                               p->seed, s->chbuf, s->runmax, booth_r, s->cnt);
             }
             if (timing) HIPCHK(hipEventRecord(s->ev[e0 + 3], stream));
-            if (labels) {
-                SubDev D0{};
-                D0.spec_c = s->spec_c; D0.n_spec = ns; D0.spec = cent_set(s->spec_c, s->gs_spec);
+            if (labels && post) {
                 k_fill_i<<<blocks(ns, 256), 256, 0, stream>>>(s->s_count, 0, (size_t)ns);
-                k_label_cands<<<blocks(maxc, 256), 256, 0, stream>>>(S, D0, s->cand, s->final_, s->cnt, s->s_count);
+                k_count_sub<<<blocks(maxc, 256), 256, 0, stream>>>(s->cand, s->final_, s->cnt, s->s_count);
                 k_scan_sub<<<1, 1024, 0, stream>>>(s->s_count, s->s_off, s->s_fill, s->nonempty, s->n_ne, ns);
                 k_scatter_sub<<<blocks(maxc, 256), 256, 0, stream>>>(s->cand, s->final_, s->cnt, s->s_fill, s->s_list);
                 if (gamma)
                     alias_rows(s->gamma_frz, ne, ns, s->nonempty, s->n_ne, p->defensive, s->al_prob, s->al_idx,
                                s->row_sum, s->al_pmf, s->al_scratch, stream);
-                k_rstat<<<blocks(maxc, 256), 256, 0, stream>>>(s->cand, s->final_, s->cnt, p->recip_repeats, ns,
-                                                                  s->rstat_acc);
+                k_rstat<<<blocks(maxc, 256), 256, 0, stream>>>(s->cand, s->final_, s->cnt, p->recip_repeats, D,
+                                                                  s->rstat_acc, s->bstat_acc);
             }
         }
+    }
+    if (part == 1) {
+        HIPCHK(hipGetLastError());
+        return PT_OK;
     }
     if (overlap) {
         HIPCHK(hipEventRecord(s->ev_join, es));
@@ -961,13 +1106,19 @@ pt_status enqueue_iteration(pt_scene *s, const pt_iter_params *p, float *acc, fl
         const MlpOff o = mlp_off(s->mlp_nout);
         k_fill<<<1, 64, 0, stream>>>(s->MT.wsum, 0.0f, 1);
         k_fill<<<1, 64, 0, stream>>>(s->MT.vwsum, 0.0f, 1);
-        k_mlp_enc_items<<<blocks(np, 256), 256, 0, stream>>>(S, E.proxy, s->cnt, s->mx);
-        mlp_forward(s, np, s->cnt, C_PROXYQ, s->ml, 0, ns, stream);
-        k_mlp_select<<<blocks(np, 256), 256, 0, stream>>>(E, D, s->ml, s->mw + o.b4, ns, p->mlp_mix, gamma ? 1 : 0,
-                                                          p->seed, s->cnt);
-        if (vmf) {
-            k_mlp_enc_retrace<<<blocks(np, 256), 256, 0, stream>>>(S, E.proxy, s->cand, s->cnt, s->mx);
-            mlp_forward(s, np, s->cnt, C_PROXYQ, s->mvmf, ns, MLP_VMF, stream, s->mw + o.b4 + ns);
+        // in chunks of MLP_CHUNK items, so that the logits of a chunk (MLP_CHUNK x n_spec) bound the
+        // workspace whatever the image size
+        for (int c0 = 0; c0 < np; c0 += MLP_CHUNK) {
+            const int m = std::min(MLP_CHUNK, np - c0);
+            k_mlp_enc_items<<<blocks(m, 256), 256, 0, stream>>>(S, E.proxy, s->cnt, s->mx, c0, m);
+            mlp_forward(s, m, s->cnt, C_PROXYQ, s->ml, 0, ns, stream, nullptr, false, c0);
+            k_mlp_select<<<blocks(m, 256), 256, 0, stream>>>(E, D, s->ml, s->mw + o.b4, ns, p->mlp_mix, gamma ? 1 : 0,
+                                                             p->seed, s->cnt, c0, m);
+            if (vmf) {
+                k_mlp_enc_retrace<<<blocks(m, 256), 256, 0, stream>>>(S, E.proxy, s->cand, s->cnt, s->mx, c0, m);
+                mlp_forward(s, m, s->cnt, C_PROXYQ, s->mvmf + (size_t)c0 * MLP_VMF, ns, MLP_VMF, stream,
+                            s->mw + o.b4 + ns, false, c0);
+            }
         }
     }
     EP.vmf_on = vmf ? 1 : 0;
@@ -986,7 +1137,7 @@ pt_status enqueue_iteration(pt_scene *s, const pt_iter_params *p, float *acc, fl
         k_prev_store<<<blocks(ns, 256), 256, 0, stream>>>(s->cnt, s->s_count, s->n_ne, ns, s->prev, s->s_count_prev);
     k_accumulate<<<blocks(np, 256), 256, 0, stream>>>(E.frame, acc, acc2, np, s->W, s->tile, s->tiles_x,
                                                       tiles ? s->tile_total : nullptr, s->cnt);
-    k_totals<<<1, 64, 0, stream>>>(s->cnt, s->tot);
+    k_totals<<<1, 64, 0, stream>>>(s->cnt, s->tot, s->ts);
     HIPCHK(hipGetLastError());
     return PT_OK;
 }
@@ -1075,6 +1226,8 @@ extern "C" pt_status pt_render_batch(pt_scene *s, const pt_iter_params *p, uint3
     k.insert(k.end(), (const char *)&s->gen, (const char *)&s->gen + sizeof(s->gen));
     k.insert(k.end(), (const char *)&s->tune_budget, (const char *)&s->tune_budget + sizeof(s->tune_budget));
     k.insert(k.end(), (const char *)&s->tune_gen_grid, (const char *)&s->tune_gen_grid + sizeof(s->tune_gen_grid));
+    k.insert(k.end(), (const char *)&s->ext_wg, (const char *)&s->ext_wg + sizeof(s->ext_wg));
+    k.insert(k.end(), (const char *)&s->queue_chunk, (const char *)&s->queue_chunk + sizeof(s->queue_chunk));
     if (!s->gexec || k != s->gkey) {
         ++s->n_captures;
         if (s->gexec) { HIPCHK(hipGraphExecDestroy(s->gexec)); s->gexec = nullptr; }
@@ -1091,7 +1244,7 @@ extern "C" pt_status pt_render_batch(pt_scene *s, const pt_iter_params *p, uint3
         s->gkey = k;
     }
     // the captured iteration advances the device-side index first: start one below
-    k_iter<<<1, 1, 0, stream>>>(s->cnt, p->iteration - 1u, 0, p->train_iters);
+    k_iter<<<1, 1, 0, stream>>>(s->cnt, p->iteration - 1u, 0, p->train_iters, nullptr, 0);
     for (uint32_t i = 0; i < n_iter; ++i) HIPCHK(hipGraphLaunch(s->gexec, stream));
     HIPCHK(hipGetLastError());
     return PT_OK;
@@ -1170,7 +1323,7 @@ extern "C" pt_status pt_trace_closest(pt_scene *s, const float *rays, int32_t n,
     if (!s || !rays || !t || !prim || n < 0) return set_err(PT_EINVAL, "bad argument");
     if (n == 0) return PT_OK;
     hipStream_t stream = (hipStream_t)stream_;
-    k_trace_closest<<<blocks(n, WG), WG, 0, stream>>>(s->S, rays, n, t, prim);
+    PT_STK(s, k_trace_closest, blocks(n, WG), WG, stream, s->S, rays, n, t, prim);
     HIPCHK(hipGetLastError());
     return PT_OK;
 }
@@ -1307,6 +1460,8 @@ extern "C" pt_status pt_render_scenes(pt_scene *const *scenes, const pt_iter_par
         k.insert(k.end(), (const char *)&sp->tune_budget, (const char *)&sp->tune_budget + sizeof(uint32_t));
         k.insert(k.end(), (const char *)&sp->tune_gen_grid, (const char *)&sp->tune_gen_grid + sizeof(int));
         k.insert(k.end(), (const char *)&sp->gen, (const char *)&sp->gen + sizeof(sp->gen));
+        k.insert(k.end(), (const char *)&sp->queue_chunk, (const char *)&sp->queue_chunk + sizeof(int));
+        k.insert(k.end(), (const char *)&sp->ext_wg, (const char *)&sp->ext_wg + sizeof(int));
     }
     if (!own->mgexec || k != own->mgkey) {
         ++own->n_captures;
@@ -1317,23 +1472,72 @@ extern "C" pt_status pt_render_scenes(pt_scene *const *scenes, const pt_iter_par
             HIPCHK(hipStreamCreateWithFlags(&q, hipStreamNonBlocking));
             own->mstreams.push_back(q);
         }
-        while ((int)own->mevents.size() < n + 1) {
+        // stage A of every scene in one persistent launch: the jobs (device copies of what k_recip
+        // takes per scene) are written before the capture
+        // (one instance walks one tree type: the scenes must agree on the BVH width and stack entries,
+        // else every branch keeps its own stage A)
+        bool multi = false, same = true, booth = false;
+        for (int i = 0; i < n; ++i) {
+            const pt_scene *sp = scenes[i];
+            const pt_iter_params *q = &params[i];
+            const bool conn = (q->flags & PT_FLAG_SPC) != 0, ltr = (q->flags & PT_FLAG_LT) != 0;
+            const int lmax = (conn || ltr) ? q->max_depth : std::min(q->max_depth - 1, PT_LMAX);
+            multi |= (q->flags & PT_FLAG_PROXY) && lmax >= 2;
+            same &= sp->stk16 == own->stk16 && sp->bvh_cur == own->bvh_cur;
+            booth |= (q->flags & PT_FLAG_BOOTH) && q->booth_r > 0.0f;
+        }
+        multi = multi && same && n > 1;
+        if (multi) {
+            if (!own->mjobs) {
+                HIPCHK(hipMalloc(&own->mjobs, 64 * sizeof(RecipJob)));
+                HIPCHK(hipMalloc(&own->mbase, 65 * sizeof(uint32_t)));
+                HIPCHK(hipMalloc(&own->mwork, sizeof(unsigned long long)));
+            }
+            std::vector<RecipJob> jobs((size_t)n);
+            for (int i = 0; i < n; ++i) {
+                pt_scene *sp = scenes[i];
+                const pt_iter_params *q = &params[i];
+                RecipJob &J = jobs[(size_t)i];
+                J.S = sp->S;
+                J.cand = sp->cand; J.final_ = sp->final_; J.order = sp->order; J.runmax = sp->runmax;
+                J.longq = sp->chq[0]; J.cnt = sp->cnt; J.repeats = q->recip_repeats; J.seed = q->seed;
+                J.n1 = stage_a_n1(q); J.budget = sp->tune_budget;
+                J.booth_r = (q->flags & PT_FLAG_BOOTH) ? q->booth_r : 0.0f;
+            }
+            HIPCHK(hipMemcpy(own->mjobs, jobs.data(), jobs.size() * sizeof(RecipJob), hipMemcpyHostToDevice));
+        }
+        while ((int)own->mevents.size() < 2 * n + 2) {
             hipEvent_t e;
             HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
             own->mevents.push_back(e);
         }
-        // fork: every scene's iteration on its own stream, joined back into the capture stream
+        // fork: every scene's iteration on its own stream, joined back into the capture stream (in
+        // two parts around the shared stage A when there is one)
         hipGraph_t g = nullptr;
         HIPCHK(hipStreamBeginCapture(own->cap_stream, hipStreamCaptureModeThreadLocal));
         pt_status st = PT_OK;
-        hipError_t e = hipEventRecord(own->mevents[0], own->cap_stream);
-        for (int i = 0; i < n && st == PT_OK && e == hipSuccess; ++i) {
-            e = hipStreamWaitEvent(own->mstreams[i], own->mevents[0], 0);
-            if (e != hipSuccess) break;
-            st = enqueue_iteration(scenes[i], &params[i], acc[i], acc2 ? acc2[i] : nullptr, own->mstreams[i], true);
-            if (st != PT_OK) break;
-            e = hipEventRecord(own->mevents[i + 1], own->mstreams[i]);
-            if (e == hipSuccess) e = hipStreamWaitEvent(own->cap_stream, own->mevents[i + 1], 0);
+        hipError_t e = hipSuccess;
+        for (int part = multi ? 1 : 0; part <= (multi ? 2 : 0) && st == PT_OK && e == hipSuccess; ++part) {
+            hipEvent_t *ev = own->mevents.data() + (part == 2 ? n + 1 : 0);
+            e = hipEventRecord(ev[0], own->cap_stream);
+            for (int i = 0; i < n && st == PT_OK && e == hipSuccess; ++i) {
+                e = hipStreamWaitEvent(own->mstreams[i], ev[0], 0);
+                if (e != hipSuccess) break;
+                st = enqueue_iteration(scenes[i], &params[i], acc[i], acc2 ? acc2[i] : nullptr, own->mstreams[i], true,
+                                       part);
+                if (st != PT_OK) break;
+                e = hipEventRecord(ev[i + 1], own->mstreams[i]);
+                if (e == hipSuccess) e = hipStreamWaitEvent(own->cap_stream, ev[i + 1], 0);
+            }
+            if (part == 1 && st == PT_OK && e == hipSuccess) {
+                k_multi_base<<<1, 64, 0, own->cap_stream>>>(own->mjobs, n, own->mbase, own->mwork);
+                const int grid = own->persist_wg, chunk = std::max(1, own->queue_chunk);
+                if (booth) PT_STK_B(own, k_recip_multi, true, grid, 64 * RW, own->cap_stream, own->mjobs, n, own->mbase,
+                                    own->mwork, chunk);
+                else PT_STK_B(own, k_recip_multi, false, grid, 64 * RW, own->cap_stream, own->mjobs, n, own->mbase,
+                              own->mwork, chunk);
+                e = hipGetLastError();
+            }
         }
         const hipError_t e2 = hipStreamEndCapture(own->cap_stream, &g);
         if (st != PT_OK) { if (g) (void)hipGraphDestroy(g); return st; }
@@ -1347,7 +1551,7 @@ extern "C" pt_status pt_render_scenes(pt_scene *const *scenes, const pt_iter_par
         own->mgkey = k;
     }
     for (int i = 0; i < n; ++i)
-        k_iter<<<1, 1, 0, stream>>>(scenes[i]->cnt, params[i].iteration - 1u, 0, params[i].train_iters);
+        k_iter<<<1, 1, 0, stream>>>(scenes[i]->cnt, params[i].iteration - 1u, 0, params[i].train_iters, nullptr, 0);
     for (uint32_t it = 0; it < n_iter; ++it) HIPCHK(hipGraphLaunch(own->mgexec, stream));
     HIPCHK(hipGetLastError());
     return PT_OK;
@@ -1360,52 +1564,91 @@ extern "C" pt_status pt_autotune(pt_scene *s, const pt_iter_params *p, float *ac
     if (!out) return set_err(PT_EINVAL, "null result");
     hipStream_t stream = (hipStream_t)stream_;
     if (p->flags & PT_FLAG_MLP) TRY(ensure_mlp(s, stream));
-    static const uint32_t budgets[5] = {512u, 1024u, 2048u, 4096u, 8192u};
-    static const int grids[3] = {1024, 2048, 8192};
     hipEvent_t e0, e1;
     HIPCHK(hipEventCreate(&e0));
     HIPCHK(hipEventCreate(&e1));
     pt_iter_params q = *p;
     q.flags &= ~(uint32_t)(PT_FLAG_TIMING | PT_FLAG_COUNT);
-    float best = 3.0e38f, dflt = 0.0f;
-    uint32_t bb = s->tune_budget;
-    int bg = s->tune_gen_grid;
-    const uint32_t b0 = s->tune_budget;
-    const int g0 = s->tune_gen_grid;
     int used = 0;
+    // iteration time with the scene's current knobs: one iteration to settle, three timed
+    auto timed = [&](float &ms) -> pt_status {
+        q.iteration = p->iteration + (uint32_t)used++;
+        pt_status st = enqueue_iteration(s, &q, acc, acc2, stream, false);
+        if (st != PT_OK) return st;
+        if (hipEventRecord(e0, stream) != hipSuccess) return set_err(PT_EDEVICE, "event record failed");
+        for (int r = 0; r < 3; ++r) {
+            q.iteration = p->iteration + (uint32_t)used++;
+            if ((st = enqueue_iteration(s, &q, acc, acc2, stream, false)) != PT_OK) return st;
+        }
+        if (hipEventRecord(e1, stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+            hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
+            return set_err(PT_EDEVICE, "event timing failed");
+        ms *= 1.0f / 3.0f;
+        return PT_OK;
+    };
+    auto set_width = [&](int w) {
+        s->bvh_cur = w;
+        s->stack_need = w == 8 ? s->stack_need8 : s->stack_need4;
+        s->bvh_depth = w == 8 ? s->bvh_depth8 : s->bvh_depth4;
+    };
+    const uint32_t b0 = s->tune_budget;
+    const int g0 = s->tune_gen_grid, w0 = s->ext_wg, c0 = s->queue_chunk, v0 = s->bvh_cur;
     pt_status st = PT_OK;
+    float dflt = 0.0f, best = 3.0e38f, ms = 0.0f;
+    // coordinate descent, each knob timed with the choices made before it: the BVH width (when
+    // both trees are there), the chain schedule (stage-A budget x round grid), the extension
+    // workgroup size, the queue chunk
+    int bv = v0;
+    st = timed(dflt);
+    best = dflt;
+    if (st == PT_OK && s->has4 && s->has8) {
+        set_width(v0 == 4 ? 8 : 4);
+        if ((st = timed(ms)) == PT_OK && ms < best) { best = ms; bv = s->bvh_cur; }
+        set_width(bv);
+    }
+    static const uint32_t budgets[5] = {512u, 1024u, 2048u, 4096u, 8192u};
+    static const int grids[3] = {1024, 2048, 8192};
+    uint32_t bb = b0;
+    int bg = g0;
+    float best_s = 3.0e38f;
     for (int bi = 0; bi < 5 && st == PT_OK; ++bi)
         for (int gi = 0; gi < 3 && st == PT_OK; ++gi) {
             s->tune_budget = budgets[bi];
             s->tune_gen_grid = grids[gi];
-            // one iteration to settle, three timed
-            q.iteration = p->iteration + (uint32_t)used++;
-            if ((st = enqueue_iteration(s, &q, acc, acc2, stream, false)) != PT_OK) break;
-            if (hipEventRecord(e0, stream) != hipSuccess) { st = set_err(PT_EDEVICE, "event record failed"); break; }
-            for (int r = 0; r < 3 && st == PT_OK; ++r) {
-                q.iteration = p->iteration + (uint32_t)used++;
-                st = enqueue_iteration(s, &q, acc, acc2, stream, false);
-            }
-            if (st != PT_OK) break;
-            float ms = 0.0f;
-            if (hipEventRecord(e1, stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
-                hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
-                st = set_err(PT_EDEVICE, "event timing failed");
-                break;
-            }
-            ms *= 1.0f / 3.0f;
-            if (budgets[bi] == b0 && grids[gi] == g0) dflt = ms;
-            if (ms < best) { best = ms; bb = budgets[bi]; bg = grids[gi]; }
+            if ((st = timed(ms)) == PT_OK && ms < best_s) { best_s = ms; bb = budgets[bi]; bg = grids[gi]; }
         }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
-    if (st != PT_OK) { s->tune_budget = b0; s->tune_gen_grid = g0; return st; }
     s->tune_budget = bb;
     s->tune_gen_grid = bg;
+    static const int wgs[3] = {64, 128, 256};
+    int bw = w0;
+    float best_w = 3.0e38f;
+    for (int wi = 0; wi < 3 && st == PT_OK; ++wi) {
+        s->ext_wg = wgs[wi];
+        if ((st = timed(ms)) == PT_OK && ms < best_w) { best_w = ms; bw = wgs[wi]; }
+    }
+    s->ext_wg = bw;
+    static const int chunks[3] = {1, 2, 4};
+    int bc = c0;
+    float best_c = 3.0e38f;
+    for (int ci = 0; ci < 3 && st == PT_OK; ++ci) {
+        s->queue_chunk = chunks[ci];
+        if ((st = timed(ms)) == PT_OK && ms < best_c) { best_c = ms; bc = chunks[ci]; }
+    }
+    s->queue_chunk = bc;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (st != PT_OK) {
+        s->tune_budget = b0; s->tune_gen_grid = g0; s->ext_wg = w0; s->queue_chunk = c0;
+        set_width(v0);
+        return st;
+    }
     s->gen = next_generation();
     out->stage_a_budget = bb;
     out->round_grid = bg;
-    out->ms_best = best;
+    out->ext_wg = bw;
+    out->queue_chunk = bc;
+    out->bvh_width = s->bvh_cur;
+    out->ms_best = std::min(std::min(best, best_s), std::min(best_w, best_c));
     out->ms_previous = dflt;
     out->iterations_rendered = (uint32_t)used;
     return PT_OK;
@@ -1431,6 +1674,21 @@ extern "C" pt_status pt_scene_totals(pt_scene *s, pt_totals *out, int32_t reset,
         k_fill_u64<<<1, 64, 0, st>>>(s->tot, 0ull, TOT_COUNT);
         HIPCHK(hipGetLastError());
         HIPCHK(hipStreamSynchronize(st));
+    }
+    return PT_OK;
+}
+
+extern "C" pt_status pt_iteration_times(pt_scene *s, uint32_t first, int32_t n, double *ms, void *stream_)
+{
+    if (!s || !ms || n < 0 || n > PT_TS_CAP) return set_err(PT_EINVAL, "bad argument (n <= %d)", PT_TS_CAP);
+    hipStream_t st = (hipStream_t)stream_;
+    std::vector<long long> t(2 * PT_TS_CAP);
+    HIPCHK(hipMemcpyAsync(t.data(), s->ts, t.size() * sizeof(long long), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    for (int i = 0; i < n; ++i) {
+        const uint32_t slot = (first + (uint32_t)i) % PT_TS_CAP;
+        const long long a = t[2 * slot], b = t[2 * slot + 1];
+        ms[i] = (b > a && a > 0 && s->wall_khz > 0) ? (double)(b - a) / (double)s->wall_khz : -1.0;
     }
     return PT_OK;
 }
@@ -1466,20 +1724,23 @@ extern "C" pt_status pt_philox(const uint32_t *in_dev, int32_t n, uint32_t *out_
     return PT_OK;
 }
 
-extern "C" pt_status pt_bvh_stats(const float *tri, int32_t n_tri, int32_t *n_nodes, int32_t *stack_need,
-                                  int32_t *depth)
+extern "C" pt_status pt_bvh_stats(const float *tri, int32_t n_tri, int32_t width, int32_t *n_nodes,
+                                  int32_t *stack_need, int32_t *depth)
 {
     if (!tri || n_tri <= 0 || !n_nodes || !stack_need || !depth) return set_err(PT_EINVAL, "bad argument");
+    if (width != 4 && width != 8) return set_err(PT_EINVAL, "width must be 4 or 8");
     try {
         std::vector<BNode> nodes;
+        std::vector<BNode8> nodes8;
         std::vector<int> order;
-        pt_build_bvh4(tri, n_tri, nodes, order);
+        pt_build_bvh(tri, n_tri, nodes, width == 8 ? &nodes8 : nullptr, order);
         int dp = 0;
-        *stack_need = pt_bvh4_stack_need(nodes, &dp);
+        *stack_need = width == 8 ? pt_bvh8_stack_need(nodes8, &dp) : pt_bvh4_stack_need(nodes, &dp);
         *depth = dp;
-        *n_nodes = (int32_t)nodes.size();
+        *n_nodes = (int32_t)(width == 8 ? nodes8.size() : nodes.size());
         return PT_OK;
     } catch (const std::exception &e) {
         return set_err(PT_ENOMEM, "host exception: %s", e.what());
     }
 }
+

@@ -118,7 +118,8 @@ __global__ void k_mlp_transpose(const uint16_t *wb, uint16_t *wt, int nout, size
     wt[off + n * K + k] = wb[off + j];
 }
 
-// Fused forward pass of the whole network on MFMA (v_mfma_f32_16x16x32_bf16, FP32 accumulation):
+// Fused forward pass of the whole network on MFMA (v_mfma_f32_16x16x32_bf16, FP32 accumulation)
+// over one chunk of rows (rows off .. off + M - 1 of the queue, at X row 0):
 // one workgroup of four wavefronts per 64-row tile (a persistent loop over tiles), each wavefront a
 // strip of 16 rows through all four layers. Lane (r, g) = (lane % 16, lane / 16) feeds row r's
 // inputs 8 g .. 8 g + 7 of each 32-wide k step (one 16-byte load) and column r's weights
@@ -182,12 +183,13 @@ __global__ void __launch_bounds__(256, 4) k_mlp_fwd(const uint16_t *__restrict__
                                                    size_t ob2, size_t oW3, size_t ob3, size_t oW4, int nout, int col0,
                                                    int ncols, float *__restrict__ out,
                                                    const float *__restrict__ bias_out, uint16_t *H1, uint16_t *H2,
-                                                   uint16_t *H3)
+                                                   uint16_t *H3, int off)
 {
     __shared__ __align__(16) uint16_t strip[4][16 * MLP_STRIP_LD];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int r = lane & 15, g = lane >> 4;
-    const int Mv = m_cidx >= 0 ? min(M, (int)cnt[m_cidx]) : M;
+    // rows of this chunk: the device count less the chunk's offset, at most M
+    const int Mv = m_cidx >= 0 ? max(0, min(M, (int)cnt[m_cidx] - off)) : M;
     uint16_t *hs = strip[wave];
     for (int tile = blockIdx.x; tile * MLP_FT_ROWS < Mv; tile += gridDim.x) {
         const int row0 = tile * MLP_FT_ROWS + wave * 16;
@@ -461,12 +463,13 @@ __global__ void k_mlp_init(float *w, uint16_t *wb, float *g, float *m, float *v,
     w[i] = x; wb[i] = f2bf(x); g[i] = 0.0f; m[i] = 0.0f; v[i] = 0.0f;
 }
 
-// features of the proxy items' first diffuse vertices -> encoded rows of X
-__global__ void k_mlp_enc_items(SceneDev S, const ProxyItem *items, const unsigned long long *cnt, uint16_t *X)
+// features of the proxy items' first diffuse vertices (items off .. off + M - 1) -> encoded rows of X
+__global__ void k_mlp_enc_items(SceneDev S, const ProxyItem *items, const unsigned long long *cnt, uint16_t *X, int off,
+                                int M)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= (int)cnt[C_PROXYQ]) return;
-    const ProxyItem &p = items[i];
+    if (i >= M || off + i >= (int)cnt[C_PROXYQ]) return;
+    const ProxyItem &p = items[off + i];
     float f[9];
     feat9(S, xyz(p.x), S.shade[__float_as_int(p.x.w)].n, xyz(p.wo), f);
     mlp_encode(f, X + (size_t)i * MLP_IN);
@@ -493,13 +496,14 @@ __global__ void k_add_bias(float *L, const float *bias, int M, int N)
 // plain row (Gamma alias row, or uniform over the non-empty subspaces). The probability of
 // the chosen S under the mixture is written with it: aux.z = S (bits), aux.w = pi_S; then an
 // incomplete sub-path of S uniformly: mis.z = its index (bits), mis.w = its overall selection
-// probability. L holds n_out logits per row (bias not included).
+// probability. Items off .. off + M - 1; L holds n_out logits per item of the chunk (bias not
+// included).
 __global__ void k_mlp_select(EyeBuf E, SubDev D, const float *L, const float *bias, int n_out, float mix, int gamma_on,
-                             uint32_t seed, const unsigned long long *cnt)
+                             uint32_t seed, const unsigned long long *cnt, int off, int M)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= (int)cnt[C_PROXYQ]) return;
-    ProxyItem &it = E.proxy[i];
+    if (i >= M || off + i >= (int)cnt[C_PROXYQ]) return;
+    ProxyItem &it = E.proxy[off + i];
     // the subspace lists are rebuilt only in iterations that keep candidates
     const int ne = cnt[C_NFINAL] > 0 ? min(*D.n_nonempty, D.n_spec) : 0;
     if (ne <= 0) {
@@ -619,13 +623,13 @@ __global__ void k_mlp_enc_train(MlpTrain T, const unsigned long long *cnt, uint1
     mlp_encode(f, X + (size_t)i * MLP_IN);
 }
 // features of every proxy item's chosen y_{s-1} (position, normal, direction toward z_d) ->
-// encoded rows of X (zeros for an item without a choice)
+// encoded rows of X (zeros for an item without a choice); items off .. off + M - 1
 __global__ void k_mlp_enc_retrace(SceneDev S, const ProxyItem *items, const Cand *cand, const unsigned long long *cnt,
-                                  uint16_t *X)
+                                  uint16_t *X, int off, int M)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= (int)cnt[C_PROXYQ]) return;
-    const ProxyItem &p = items[i];
+    if (i >= M || off + i >= (int)cnt[C_PROXYQ]) return;
+    const ProxyItem &p = items[off + i];
     const int ci = __float_as_int(p.mis.z);
     float f[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
     if (ci >= 0 && p.mis.w > 0.0f) {

@@ -42,8 +42,14 @@ struct SubDev {
     const float *al_pmf;     // [n_eye * n_spec] probability the alias row draws S (non-empty S only)
     const float *gamma;      // [n_eye * n_spec] frozen Gamma of this iteration
     float defensive;
-    // frozen reciprocal statistics per (class, u, S): sum R, sum R^2, count
-    const float *rstat;      // [10 * n_spec * 3]
+    // control subspaces C of the incomplete sub-paths' control vertices (class B: y_0 on an
+    // emitter; class A has none and takes C = 0), Section 5.5
+    const float *ctrl_c;     // [n_ctrl * FEAT]
+    int n_ctrl;
+    // frozen reciprocal statistics per (class, u, S, C): sum R, sum R^2 / rho, count; and the
+    // bucket's f/q samples: largest value (a floor of its B), sum, count (its mean estimates beta)
+    const float *rstat;      // [10 * n_ctrl * n_spec * 3]
+    const float *bstat;      // [10 * n_ctrl * n_spec * 3]
     // the previous iteration's candidate counts (n_cand, n_final, non-empty subspaces), its
     // per-subspace counts and the frozen Gamma row totals: the MIS surrogate's inputs, none of
     // which depends on this iteration's light paths
@@ -140,17 +146,39 @@ __global__ void k_km_update(float *cent, const float *sums, const float *counts,
 }
 
 // ------------------------------------------------------------------------------ bucketing
-__global__ void k_label_cands(SceneDev S, SubDev D, Cand *cand, const uint32_t *final_, const unsigned long long *cnt,
-                              int *s_count)
+// control subspace of a control vertex y_0 on emitter triangle t0 (features: position, normal and
+// no direction, since the control vertex of class B carries no direction); 0 with one subspace
+__device__ __forceinline__ int ctrl_label(const SceneDev &S, const SubDev &D, float3 y0, int t0)
+{
+    if (D.n_ctrl <= 1) return 0;
+    float f[9];
+    feat9(S, y0, S.shade[t0].n, f3(0.f, 0.f, 0.f), f);
+    return nearest(D.ctrl_c, D.n_ctrl, f);
+}
+// bucket of the (class, u, S, C) statistics
+__device__ __forceinline__ int stat_bucket(const SubDev &D, int cls, int u, int S, int C)
+{
+    return ((cls * 5 + u) * D.n_ctrl + C) * D.n_spec + S;
+}
+// labels of the kept candidates, before their reciprocal estimates: specular subspace S of
+// y_{s-1} (with its incident direction) and control subspace C, as spec_sub = S | C << 16
+__global__ void k_label_kept(SceneDev S, SubDev D, Cand *cand, const uint32_t *kept, const unsigned long long *cnt)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= (int)cnt[C_NFINAL]) return;
-    Cand &c = cand[final_[i]];
+    if (i >= (int)cnt[C_NKEPT]) return;
+    Cand &c = cand[kept[i]];
     float f[9];
     feat9(S, xyz(c.v), S.shade[__float_as_int(c.v.w)].n, oct_dec(make_float2(c.pad[0], c.pad[1])), f);
     const int s = nearest_set(D.spec, f);
-    c.spec_sub = s;
-    atomicAdd(s_count + s, 1);
+    const int C = (c.cls_u >> 8) ? ctrl_label(S, D, xyz(c.hc), __float_as_int(c.hc.w)) : 0;
+    c.spec_sub = s | (C << 16);
+}
+// bucket sizes of the final candidates by S
+__global__ void k_count_sub(const Cand *cand, const uint32_t *final_, const unsigned long long *cnt, int *s_count)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (int)cnt[C_NFINAL]) return;
+    atomicAdd(s_count + (cand[final_[i]].spec_sub & 0xFFFF), 1);
 }
 // one workgroup: exclusive scan of the counts and the list of non-empty subspaces
 __global__ void k_scan_sub(const int *s_count, int *s_off, int *s_fill, int *nonempty, int *n_nonempty, int K)
@@ -177,7 +205,7 @@ __global__ void k_scatter_sub(const Cand *cand, const uint32_t *final_, const un
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= (int)cnt[C_NFINAL]) return;
-    const int s = cand[final_[i]].spec_sub;
+    const int s = cand[final_[i]].spec_sub & 0xFFFF;
     s_list[atomicAdd(s_fill + s, 1)] = (int)final_[i];
 }
 
@@ -328,28 +356,33 @@ __global__ void k_prev_store(const unsigned long long *cnt, const int *s_count, 
     }
 }
 
-// reciprocal statistics of the final candidates (accumulated for later iterations)
-__global__ void k_rstat(const Cand *cand, const uint32_t *final_, const unsigned long long *cnt, int repeats, int n_spec,
-                        float *rstat_acc)
+// reciprocal statistics of the final candidates by (class, u, S, C) (accumulated for later
+// iterations), and the bucket's f/q samples: largest value (the candidates' pilot and chain
+// maxima), sum and count of every f/q the pilot and the first chain stage drew
+__global__ void k_rstat(const Cand *cand, const uint32_t *final_, const unsigned long long *cnt, int repeats, SubDev D,
+                        float *rstat_acc, float *bstat_acc)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= (int)cnt[C_NFINAL] || !cnt[C_LEARN]) return;
     const Cand &c = cand[final_[i]];
     const float R = c.recip_sum / (float)repeats;
-    const int b = ((c.cls_u >> 8) * 5 + (c.cls_u & 0xFF)) * n_spec + c.spec_sub;
+    const int b = stat_bucket(D, c.cls_u >> 8, c.cls_u & 0xFF, c.spec_sub & 0xFFFF, c.spec_sub >> 16);
     // the second moment of the unbiased factor R 1{kept} / rho is E[R^2] / rho
     unsafeAtomicAdd(rstat_acc + 3 * b + 0, R);
     unsafeAtomicAdd(rstat_acc + 3 * b + 1, R * R / fmaxf(c.rho, 1e-6f));
     unsafeAtomicAdd(rstat_acc + 3 * b + 2, 1.0f);
+    if (c.pmax > 0.0f) atomicMax((int *)(bstat_acc + 3 * b), __float_as_int(c.pmax));
+    unsafeAtomicAdd(bstat_acc + 3 * b + 1, c.psum);
+    unsafeAtomicAdd(bstat_acc + 3 * b + 2, c.pn);
 }
 
 // Surrogate of the proxy strategy's density factor for MIS (Section 5.4, equ:MIS_1 with
 // E[1/p~^2] p = (1 + V_rel) / p): K' P^ / (1 + V_rel), with P^ = 1 / mean R and V_rel the
-// relative variance of R 1{kept} / rho (second moment E[R^2 / rho]) in the (class, u, S) bucket
-// from earlier iterations, K' = M pi_inc c pi_sel.
-__device__ __forceinline__ float proxy_mis_factor(const SubDev &D, int cls, int u, int S, float k_sel)
+// relative variance of R 1{kept} / rho (second moment E[R^2 / rho]) in the (class, u, S, C) bucket
+// of Section 5.5 from earlier iterations, K' = M pi_inc c pi_sel.
+__device__ __forceinline__ float proxy_mis_factor(const SubDev &D, int cls, int u, int S, int C, float k_sel)
 {
-    const int b = (cls * 5 + u) * D.n_spec + S;
+    const int b = stat_bucket(D, cls, u, S, C);
     const float n = D.rstat[3 * b + 2];
     if (!(n > 0.0f) || !(k_sel > 0.0f)) return 0.0f;
     const float m = D.rstat[3 * b + 0] / n, m2 = D.rstat[3 * b + 1] / n;

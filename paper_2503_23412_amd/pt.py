@@ -36,7 +36,8 @@ EXPORTED = ["pt_scene_upload", "pt_scene_release", "pt_build_subspaces", "pt_ren
             "pt_render_scenes", "pt_autotune",
             "pt_mlp_param_count", "pt_mlp_set_params", "pt_mlp_get_params", "pt_mlp_forward", "pt_mlp_train_step",
             "pt_reciprocal_estimate", "pt_resolve_image", "pt_trace_closest", "pt_scene_totals",
-            "pt_selection_tables", "pt_philox", "pt_bvh_stats", "pt_vmf_sample", "pt_last_error"]
+            "pt_selection_tables", "pt_iteration_times", "pt_philox", "pt_bvh_stats",
+            "pt_vmf_sample", "pt_last_error"]
 
 
 class SceneDesc(ctypes.Structure):
@@ -51,7 +52,8 @@ class SceneDesc(ctypes.Structure):
 
 class SubspaceParams(ctypes.Structure):
     _fields_ = [("n_pretrace", ctypes.c_int32), ("n_eye", ctypes.c_int32), ("n_spec", ctypes.c_int32),
-                ("kmeans_iters", ctypes.c_int32), ("seed", ctypes.c_uint32), ("n_light", ctypes.c_int32)]
+                ("kmeans_iters", ctypes.c_int32), ("seed", ctypes.c_uint32), ("n_light", ctypes.c_int32),
+                ("n_ctrl", ctypes.c_int32)]
 
 
 class IterParams(ctypes.Structure):
@@ -83,7 +85,8 @@ class IterStats(ctypes.Structure):
 
 class TuneResult(ctypes.Structure):
     _fields_ = [("stage_a_budget", ctypes.c_uint32), ("round_grid", ctypes.c_int32), ("ms_best", ctypes.c_float),
-                ("ms_previous", ctypes.c_float), ("iterations_rendered", ctypes.c_uint32)]
+                ("ms_previous", ctypes.c_float), ("iterations_rendered", ctypes.c_uint32),
+                ("ext_wg", ctypes.c_int32), ("queue_chunk", ctypes.c_int32), ("bvh_width", ctypes.c_int32)]
 
 
 class Totals(ctypes.Structure):
@@ -136,7 +139,8 @@ def lib():
         L.pt_scene_totals.argtypes = [P, ctypes.POINTER(Totals), I, P]
         L.pt_selection_tables.argtypes = [P, I, I, I, P, P, P, P, P, P, P]
         L.pt_philox.argtypes = [P, I, P, P]
-        L.pt_bvh_stats.argtypes = [P, I, P, P, P]
+        L.pt_iteration_times.argtypes = [P, ctypes.c_uint32, I, P, P]
+        L.pt_bvh_stats.argtypes = [P, I, I, P, P, P]
         L.pt_last_error.restype = ctypes.c_char_p
         for name in EXPORTED:
             if name == "pt_last_error":
@@ -178,13 +182,13 @@ def default_params(**kw):
 class Scene:
     """A scene uploaded to the current HIP device."""
 
-    def __init__(self, sc, max_light_paths=4096, stream=None):
+    def __init__(self, sc, max_light_paths=4096, stream=None, bvh_width=4):
         self._host = [np.ascontiguousarray(sc[k]) for k in ("tri", "tri_mat", "tri_uv", "mats", "tex", "cam")]
         tri, tri_mat, tri_uv, mats, tex, cam = self._host
         self.width, self.height = int(sc["width"]), int(sc["height"])
         d = SceneDesc(tri.shape[0], tri.ctypes.data, tri_mat.ctypes.data, tri_uv.ctypes.data, mats.shape[0],
                       mats.ctypes.data, tex.shape[1], tex.shape[0], tex.ctypes.data, cam.ctypes.data,
-                      self.width, self.height, 4, int(max_light_paths))
+                      self.width, self.height, int(bvh_width), int(max_light_paths))
         h = ctypes.c_void_p()
         _check(lib().pt_scene_upload(ctypes.byref(d), _stream(stream), ctypes.byref(h)))
         self.h = h
@@ -201,8 +205,9 @@ class Scene:
         except Exception:
             pass
 
-    def build_subspaces(self, n_pretrace=0, n_eye=64, n_spec=64, kmeans_iters=8, seed=0, n_light=0, stream=None):
-        p = SubspaceParams(n_pretrace, n_eye, n_spec, kmeans_iters, seed, n_light)
+    def build_subspaces(self, n_pretrace=0, n_eye=64, n_spec=64, kmeans_iters=8, seed=0, n_light=0, n_ctrl=10,
+                        stream=None):
+        p = SubspaceParams(n_pretrace, n_eye, n_spec, kmeans_iters, seed, n_light, n_ctrl)
         _check(lib().pt_build_subspaces(self.h, ctypes.byref(p), _stream(stream)))
 
     def render_iteration(self, accum, accum_sq=None, stats=False, stream=None, **params):
@@ -276,6 +281,12 @@ class Scene:
         _check(lib().pt_scene_totals(self.h, ctypes.byref(t), int(bool(reset)), _stream(stream)))
         return {k: getattr(t, k) for k, _ in t._fields_}
 
+    def iteration_times(self, first, n, stream=None):
+        """Device wall-clock duration (ms) of iterations first .. first + n - 1 (-1 where unrecorded)."""
+        out = np.zeros(n, np.float64)
+        _check(lib().pt_iteration_times(self.h, int(first), int(n), out.ctypes.data, _stream(stream)))
+        return out
+
     def selection_tables(self, which, n_rows, n_cols, stream=None):
         """The latest iteration's alias rows (which 0: Gamma, 1: Q) as host arrays."""
         ne = ctypes.c_int32()
@@ -312,11 +323,12 @@ def vmf_sample(raw, seed, dirs, pdf, stream=None):
     _check(lib().pt_vmf_sample(_ptr(raw), int(raw.shape[0]), int(seed), _ptr(dirs), _ptr(pdf), _stream(stream)))
 
 
-def bvh_stats(tri):
-    """Host-only: (nodes, worst-case traversal stack, depth) of the 4-wide BVH of tri [n, 9]."""
+def bvh_stats(tri, width=4):
+    """Host-only: (nodes, worst-case traversal stack, depth) of the BVH of tri [n, 9] (width 4 or 8)."""
     t = np.ascontiguousarray(tri, np.float32).reshape(-1, 9)
     a, b, c = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
-    _check(lib().pt_bvh_stats(t.ctypes.data, int(t.shape[0]), ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
+    _check(lib().pt_bvh_stats(t.ctypes.data, int(t.shape[0]), int(width), ctypes.byref(a), ctypes.byref(b),
+                              ctypes.byref(c)))
     return a.value, b.value, c.value
 
 

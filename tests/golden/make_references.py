@@ -10,7 +10,7 @@ so O1 at any affordable sample count misreports its own error there. O3 reaches 
 by light tracing and vertex connections. Output per scene: per-pixel mean of the per-iteration
 pixel values, the variance of that mean, and the number of iterations, as a compressed .npz.
 
-usage: python tests/golden/make_references.py [cfg0|cfg1_128|glass_furnace|all] [spp] [threads]
+usage: python tests/golden/make_references.py [cfg0|cfg1_128|glass_furnace|glossy_room|all] [spp] [threads]
 """
 import os
 import sys
@@ -35,7 +35,13 @@ REFS = {
     # the tessellated sphere makes visible per pixel
     "glass_furnace": (lambda: scenes.furnace(albedo=0.5, le=1.0, glass_sphere=True, width=64, height=64,
                                              sphere_subdiv=2, enclosure="sphere"), 120, 4096, 0, "o1"),
+    # the small room with a glossy GGX mirror (roughness 0.1), depth 8, path tracing restricted
+    # to the proxy class with specular runs of at most two vertices (what the proxy strategy
+    # alone estimates)
+    "glossy_room": (lambda: scenes.mirror_room(16, 16, mirror_roughness=0.1), 8, 65536, 0, "o1"),
 }
+# render options beyond the method and depth
+EXTRA = {"glossy_room": dict(u_max=2, class_filter=1)}
 
 
 def make(name, spp=None, batch=256, threads=None):
@@ -47,7 +53,8 @@ def make(name, spp=None, batch=256, threads=None):
     t0 = time.time()
     for first in range(0, spp, batch):
         n = min(batch, spp - first)
-        a, b, _ = S.render(method=method, n_iter=n, first_iter=first, max_depth=depth, seed=12345, threads=threads)
+        a, b, _ = S.render(method=method, n_iter=n, first_iter=first, max_depth=depth, seed=12345, threads=threads,
+                           **EXTRA.get(name, {}))
         s += a
         s2 += b
         print(f"{name}: {first + n}/{spp} spp, {time.time() - t0:.0f} s", flush=True)
@@ -55,7 +62,7 @@ def make(name, spp=None, batch=256, threads=None):
     var_mean = np.maximum(s2 / spp - mean * mean, 0.0) / spp
     out = os.path.join(HERE, f"{name}_{tag}_ref.npz")
     np.savez_compressed(out, mean=mean.astype(np.float64), var_mean=var_mean.astype(np.float64), spp=spp,
-                        max_depth=depth, seed=12345, method=method)
+                        max_depth=depth, seed=12345, method=method, **EXTRA.get(name, {}))
     print("wrote", out, flush=True)
 
 

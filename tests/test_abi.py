@@ -34,8 +34,9 @@ def test_struct_sizes_match_header(ptlib):
     assert ctypes.sizeof(ptlib.SceneDesc) == 4 + 4 + 8 * 3 + 4 + 4 + 8 + 4 + 4 + 8 + 8 + 4 * 4
     assert ctypes.sizeof(ptlib.IterParams) == 18 * 4
     assert ctypes.sizeof(ptlib.IterStats) == (29 + 25) * 8
-    assert ctypes.sizeof(ptlib.SubspaceParams) == 6 * 4
+    assert ctypes.sizeof(ptlib.SubspaceParams) == 7 * 4
     assert ctypes.sizeof(ptlib.Totals) == 9 * 8
+    assert ctypes.sizeof(ptlib.TuneResult) == 8 * 4
 
 
 def test_invalid_arguments_rejected_without_device(ptlib):
@@ -58,8 +59,9 @@ def test_invalid_arguments_rejected_without_device(ptlib):
                         tex.ctypes.data, cam.ctypes.data, 8, 8, 4, 16)
     assert L.pt_scene_upload(ctypes.byref(d), None, ctypes.byref(h)) == -1
     assert b"material" in L.pt_last_error()
-    d.bvh_width = 8
+    d.bvh_width = 6
     assert L.pt_scene_upload(ctypes.byref(d), None, ctypes.byref(h)) == -1
+    assert b"bvh_width" in L.pt_last_error()
     assert L.pt_render_iteration(None, None, None, None, None, None) == -1
     assert L.pt_reciprocal_estimate(None, None, None, None, None) == -1
     assert L.pt_resolve_image(None, None, 1, None, None) == -1
@@ -67,10 +69,10 @@ def test_invalid_arguments_rejected_without_device(ptlib):
 
 
 def test_bvh_stack_need_fits_the_kernels(ptlib):
-    """The host BVH build (what pt_scene_upload runs) for the config scenes and a 1.4 M-triangle
-    variant of the glossy scene: worst-case traversal stacks within the kernels' 48 entries, and
-    the need at least the depth less one on these scenes (every level of a deep path of inner
-    nodes has siblings there)."""
+    """The host BVH builds (what pt_scene_upload runs) for the config scenes and a 1.4 M-triangle
+    variant of the glossy scene: worst-case traversal stacks within the kernels' 48 entries
+    (4-wide) and 64 (8-wide), and the need at least the depth less one on these scenes (every
+    level of a deep path of inner nodes has siblings there)."""
     from synth import scenes
     cases = [scenes.cornell_glass(8, 8), scenes.projector(8, 8), scenes.glossy_procedural(8, 8),
              scenes.glossy_procedural(8, 8, target_tris=2_000_000)]
@@ -79,5 +81,10 @@ def test_bvh_stack_need_fits_the_kernels(ptlib):
         n = sc["tri"].shape[0]
         assert n / 16 <= nodes <= n, (n, nodes)
         assert depth - 1 <= need <= 48, (n, need, depth)
+        # the 8-wide tree over the same leaves: fewer nodes and levels, a walk within 64 entries
+        nodes8, need8, depth8 = ptlib.bvh_stats(sc["tri"], width=8)
+        assert n / 32 <= nodes8 < nodes and depth8 < depth, (n, nodes8, depth8)
+        assert depth8 - 1 <= need8 <= 64, (n, need8, depth8)
     # one triangle: a single node with one leaf child needs no stack
-    assert ptlib.bvh_stats(np.array([[0, 0, 0, 1, 0, 0, 0, 1, 0]], np.float32)) == (1, 0, 1)
+    one = np.array([[0, 0, 0, 1, 0, 0, 0, 1, 0]], np.float32)
+    assert ptlib.bvh_stats(one) == (1, 0, 1) and ptlib.bvh_stats(one, width=8) == (1, 0, 1)

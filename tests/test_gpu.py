@@ -7,6 +7,7 @@ to FP32 rounding of the hit distance.
 import math
 import os
 import sys
+import time
 
 import numpy as np
 import pytest
@@ -77,6 +78,7 @@ def _render_batches(gpu, sc, n_batches, per_batch, max_light=1024, subspaces=(8,
     s1 = torch.zeros(W * H * 3, dtype=torch.float64, device="cuda")
     s2 = torch.zeros_like(s1)
     img = []
+    t0 = time.time()
     for b in range(n_batches):
         acc.zero_()
         S.render_batch(acc, None, per_batch, iteration=b * per_batch, **params)
@@ -85,7 +87,8 @@ def _render_batches(gpu, sc, n_batches, per_batch, max_light=1024, subspaces=(8,
         s2 += bm * bm
         img.append(bm.mean())
         if b % 16 == 15:
-            say(f"  batch {b + 1}/{n_batches}")
+            torch.cuda.synchronize()
+            say(f"  batch {b + 1}/{n_batches} ({time.time() - t0:.1f} s)")
     torch.cuda.synchronize()
     tot = S.totals()
     S.release()
@@ -321,13 +324,16 @@ def test_graph_recaptured_when_a_scene_changes(gpu):
 
 
 # ------------------------------------------------------------------------------ traversal
+@pytest.mark.parametrize("width", [4, 8])
 @pytest.mark.parametrize("which", ["cornell", "projector", "glossy"])
-def test_bvh_closest_hit_matches_brute_force(gpu, oracle, which):
+def test_bvh_closest_hit_matches_brute_force(gpu, oracle, which, width):
+    """Closest hits of random rays through the 4-wide and the 8-wide (quantised) tree against the
+    oracle's brute force over every triangle."""
     torch, pt = gpu
     from synth import scenes
     sc = {"cornell": lambda: scenes.cornell_glass(8, 8), "projector": lambda: scenes.projector(8, 8),
           "glossy": lambda: scenes.glossy_procedural(8, 8, target_tris=20000)}[which]()
-    say(f"bvh {which}: {sc['tri'].shape[0]} tris")
+    say(f"bvh {which} width {width}: {sc['tri'].shape[0]} tris")
     rng = np.random.Generator(np.random.Philox(key=5))
     tri = sc["tri"].reshape(-1, 3, 3).astype(np.float64)
     lo, hi = tri.min((0, 1)), tri.max((0, 1))
@@ -336,7 +342,7 @@ def test_bvh_closest_hit_matches_brute_force(gpu, oracle, which):
     d = rng.normal(size=(n, 3))
     d /= np.linalg.norm(d, axis=1, keepdims=True)
     rays = np.concatenate([o, d, np.full((n, 1), 1e-6), np.full((n, 1), 1e30)], axis=1)
-    S = pt.Scene(sc, max_light_paths=16)
+    S = pt.Scene(sc, max_light_paths=16, bvh_width=width)
     rd = torch.tensor(rays, dtype=torch.float32, device="cuda")
     t = torch.empty(n, device="cuda")
     p = torch.empty(n, dtype=torch.int32, device="cuda")
@@ -416,6 +422,7 @@ def test_multi_scene_graph_and_autotune(gpu):
     r = sc.autotune(acc, acc2, iteration=0, max_depth=K, n_light=1024, cand_cap=128, flags=flags)
     say("autotune", r)
     assert r["stage_a_budget"] in (512, 1024, 2048, 4096, 8192) and r["round_grid"] in (1024, 2048, 8192)
+    assert r["ext_wg"] in (64, 128, 256) and r["queue_chunk"] in (1, 2, 4)
     n = r["iterations_rendered"]
     for k in range(n, 512):
         sc.render_iteration(acc, acc2, iteration=k, max_depth=K, n_light=1024, cand_cap=128, flags=flags)
@@ -424,6 +431,75 @@ def test_multi_scene_graph_and_autotune(gpu):
     v = np.maximum((acc2 / 512).double().cpu().numpy().reshape(48, 48, 3) - m * m, 0) / 512
     assert _furnace_ok(m, v, (1 - 0.5 ** K) / 0.5, "autotuned furnace")
     sc.release()
+
+
+def test_scene_in_a_batch_matches_the_scene_alone(gpu):
+    """The 64 x 64 glass Cornell box (config 0's scene, every strategy) rendered alone
+    (pt_render_iteration, two streams) and as one branch of a three-scene graph (pt_render_scenes,
+    beside two furnaces of other sizes): 16 batches of 256 iterations each, different seeds;
+    standard errors from the batch means (single iterations are heavy-tailed). Per pixel within 4
+    combined standard errors on 99.9 % of pixel channels, relative L1 within 10 % of the noise
+    floor; the two furnaces of the batch against their closed form."""
+    from synth import scenes
+    torch, pt = gpu
+    flags = (pt.PT_FLAG_NEE | pt.PT_FLAG_PROXY | pt.PT_FLAG_MIS | pt.PT_FLAG_GAMMA | pt.PT_FLAG_TILES |
+             pt.PT_FLAG_SPC | pt.PT_FLAG_LT)
+    NB, PB = 16, 256
+    N = NB * PB
+    prm = dict(max_depth=8, n_light=4096, cand_cap=400, flags=flags)
+    specs = [(scenes.cornell_glass(64, 64), 4096, (64, 64), prm),
+             (scenes.furnace(albedo=0.5, le=1.0, width=48, height=48), 1024, (8, 8),
+              dict(max_depth=6, n_light=1024, cand_cap=128, flags=flags)),
+             (scenes.furnace(albedo=0.3, le=1.0, width=32, height=40), 1024, (8, 8),
+              dict(max_depth=6, n_light=1024, cand_cap=128, flags=flags))]
+
+    def moments(batches):
+        b = np.stack(batches)
+        return b.mean(0), b.var(0, ddof=1) / len(batches)
+
+    say("config 0 scene alone")
+    sc0 = specs[0][0]
+    S0 = pt.Scene(sc0, max_light_paths=4096)
+    S0.build_subspaces(n_eye=64, n_spec=64)
+    acc = torch.zeros(64 * 64 * 3, device="cuda")
+    alone = []
+    for bi in range(NB):
+        acc.zero_()
+        for k in range(PB):
+            S0.render_iteration(acc, None, iteration=bi * PB + k, seed=3, **prm)
+        alone.append((acc / PB).double().cpu().numpy().reshape(64, 64, 3))
+    S0.release()
+    m1, v1 = moments(alone)
+    say("config 0 scene in a batch of three")
+    S, A = [], []
+    for sc, ml, sub, q in specs:
+        x = pt.Scene(sc, max_light_paths=ml)
+        x.build_subspaces(n_eye=sub[0], n_spec=sub[1])
+        S.append(x)
+        A.append(torch.zeros(sc["width"] * sc["height"] * 3, device="cuda"))
+    batches = [[] for _ in specs]
+    for bi in range(NB):
+        for t in A:
+            t.zero_()
+        pt.render_scenes(S, A, None, PB, [dict(q, seed=11, iteration=bi * PB) for _, _, _, q in specs])
+        for j, ((sc, _, _, _), t) in enumerate(zip(specs, A)):
+            batches[j].append((t / PB).double().cpu().numpy().reshape(sc["height"], sc["width"], 3))
+    tots = [x.totals() for x in S]
+    for x in S:
+        x.release()
+    res = [moments(bs) for bs in batches]
+    m2, v2 = res[0]
+    z = (m1 - m2) / np.sqrt(v1 + v2 + 1e-30)
+    frac = (np.abs(z) < 4).mean()
+    rel_l1 = np.abs(m1 - m2).sum() / m2.sum()
+    floor = (np.sqrt(2 / np.pi) * np.sqrt(v1 + v2)).sum() / m2.sum()
+    say(f"alone vs batch: frac |z|<4 {frac:.5f} max|z| {np.abs(z).max():.2f} mean z {z.mean():.4f} relL1 "
+        f"{rel_l1:.5f} floor {floor:.5f}")
+    assert frac >= 0.999
+    assert rel_l1 < 1.1 * floor
+    for (m, v), a in zip(res[1:], (0.5, 0.3)):
+        assert _furnace_ok(m, v, (1 - a ** 6) / (1 - a), f"batch furnace a={a}")
+    assert all(t["n_nan"] == 0 and t["n_recip_truncated"] == 0 and t["iterations"] == N for t in tots)
 
 
 def _glass_ref():
@@ -527,31 +603,42 @@ def test_proxy_class_matches_oracle_path_tracing(gpu, oracle):
     assert st["n_recip_truncated"] == 0 and st["n_proxy_valid"] > 0
 
 
-def test_learned_proposal_proxy_class_matches_oracle(gpu, oracle):
+def test_learned_proposal_proxy_class_matches_oracle(gpu):
     """The proxy strategy alone with both learned heads on (PT_FLAG_MLP: the subspace picked by the
     network's softmax mixed with 10 % of the plain row; PT_FLAG_MLP_DIR: the first retrace direction
     at the glossy mirror (GGX, roughness 0.1) drawn from 0.9 x the network's vMF mixture + 0.1 x BSDF
-    sampling), trained online in every iteration, against the oracle's path tracing restricted to
-    the proxy class on the same room: per pixel within 4 combined standard errors on 99 % of pixel
-    channels (16 x 16 x 3), and the image sums within 4 standard errors."""
+    sampling), trained online in every iteration, and without them, against the oracle's path
+    tracing restricted to the proxy class on the same room (tests/golden/glossy_room_o1_ref.npz,
+    65,536 spp, written by make_references.py): per pixel within 4 combined standard errors on 99 %
+    of pixel channels (16 x 16 x 3), and the image sums within 4 standard errors. 16,384
+    iterations each; the GPU side's standard errors come from 64 batch means of 256 iterations.
+    (The proxy estimates here are heavy-tailed, more so with the learned heads, whose defensive
+    mixture trades rarer samples for larger weights: at 2,048 iterations a few pixels sit 5-6
+    standard errors low in most runs, because their rare large values have not been drawn yet.)"""
     from synth import scenes
     torch, pt = gpu
     sc = scenes.mirror_room(16, 16, mirror_roughness=0.1)
-    N = 2048
-    say("glossy room proxy class, learned proposal")
-    flags = (pt.PT_FLAG_NEE | pt.PT_FLAG_PROXY | pt.PT_FLAG_ONLY_PROXY_CLASS | pt.PT_FLAG_MLP | pt.PT_FLAG_MLP_DIR)
-    m, v, st = _render(gpu, sc, N, max_depth=8, n_light=1024, cand_cap=256, u_max=2, flags=flags, train_iters=N,
-                       mlp_mix=0.9, mlp_lr=1e-3)
-    O = oracle.Scene(sc)
-    s1, q1, _ = O.render(method=0, n_iter=4 * N, max_depth=8, u_max=2, class_filter=1, seed=9)
-    mo = s1 / (4 * N)
-    vo = np.maximum(q1 / (4 * N) - mo * mo, 0) / (4 * N)
-    z = (m - mo) / np.sqrt(v + vo + 1e-30)
-    say(f"glossy room learned: totals {m.sum():.5f} vs {mo.sum():.5f} +- {math.sqrt(v.sum() + vo.sum()):.5f}; frac |z|<4 "
-        f"{(np.abs(z) < 4).mean():.4f} max|z| {np.abs(z).max():.2f}; stats {st}")
-    assert (np.abs(z) < 4).mean() >= 0.99, np.abs(z).max()
-    assert abs(m.sum() - mo.sum()) < 4 * math.sqrt(v.sum() + vo.sum())
-    assert st["n_recip_truncated"] == 0 and st["n_proxy_valid"] > 0 and st["n_nan"] == 0
+    ref = np.load(os.path.join(GOLD, "glossy_room_o1_ref.npz"))
+    mo, vo = ref["mean"], ref["var_mean"]
+    assert int(ref["u_max"]) == 2 and int(ref["class_filter"]) == 1 and int(ref["max_depth"]) == 8
+    NB, PB = 64, 256
+    N = NB * PB
+    base = pt.PT_FLAG_NEE | pt.PT_FLAG_PROXY | pt.PT_FLAG_ONLY_PROXY_CLASS
+    for name, flags in (("learned", base | pt.PT_FLAG_MLP | pt.PT_FLAG_MLP_DIR), ("plain", base)):
+        say(f"glossy room proxy class, {name}")
+        m, v, img, tot = _render_batches(gpu, sc, NB, PB, max_depth=8, n_light=1024, cand_cap=256, u_max=2,
+                                         flags=flags, train_iters=N, mlp_mix=0.9, mlp_lr=1e-3)
+        z = (m - mo) / np.sqrt(v + vo + 1e-30)
+        # the image sum's standard error from the batch sums (pixels of one iteration are correlated)
+        se_sum = math.hypot(float(np.std(img, ddof=1) / np.sqrt(NB)) * m.size, math.sqrt(vo.sum()))
+        far = [(int(i // 48), int(i // 3 % 16), int(i % 3), round(float(z.flat[i]), 2))
+               for i in np.flatnonzero(np.abs(z) >= 4)]
+        say(f"glossy room {name}: totals {m.sum():.5f} vs {mo.sum():.5f} +- {se_sum:.5f}; frac |z|<4 "
+            f"{(np.abs(z) < 4).mean():.4f} max|z| {np.abs(z).max():.2f} z mean {z.mean():.3f}; beyond 4 "
+            f"(row, col, channel, z): {far}; totals {tot}")
+        assert (np.abs(z) < 4).mean() >= 0.99, (name, np.abs(z).max())
+        assert abs(m.sum() - mo.sum()) < 4 * se_sum, name
+        assert tot["n_recip_truncated"] == 0 and tot["n_proxy_valid"] > 0 and tot["n_nan"] == 0
 
 
 # ------------------------------------------------------------------------------ candidate probe
@@ -618,17 +705,17 @@ def test_candidate_probe_closed_forms(gpu, oracle):
 CFG0_FLAGS = ("NEE", "PROXY", "MIS", "GAMMA", "TILES", "SPC", "LT")
 
 
-def _cfg0_parity(gpu, extra_flags=(), tag="config 0", **extra):
+def _cfg0_parity(gpu, extra_flags=(), tag="config 0", n_batches=64, **extra):
     """Config 0 (64 x 64 glass Cornell box, depth 8, M = 4,096, cap 400, 64 / 64 subspaces) at
-    65,536 iterations (64 batch means of 1,024) against the stored O1 reference (262,144 spp)."""
+    n_batches x 1,024 iterations (batch means of 1,024) against the stored O1 reference (262,144 spp)."""
     from synth import scenes
     torch, pt = gpu
     ref = np.load(os.path.join(GOLD, "cfg0_o1_ref.npz"))
     flags = 0
     for f in CFG0_FLAGS + tuple(extra_flags):
         flags |= getattr(pt, "PT_FLAG_" + f)
-    say(f"{tag}: 65,536 iterations")
-    m, v, img, tot = _render_batches(gpu, scenes.cornell_glass(64, 64), 64, 1024, max_light=4096,
+    say(f"{tag}: {n_batches * 1024:,} iterations")
+    m, v, img, tot = _render_batches(gpu, scenes.cornell_glass(64, 64), n_batches, 1024, max_light=4096,
                                      subspaces=(64, 64), max_depth=8, n_light=4096, cand_cap=400, flags=flags, **extra)
     mo, vo = ref["mean"], ref["var_mean"]
     z = (m - mo) / np.sqrt(v + vo + 1e-30)
@@ -654,13 +741,16 @@ def test_zz_config0_parity_with_oracle_reference(gpu):
 
 @pytest.mark.timeout(900)
 def test_zz_config0_parity_with_learned_selection(gpu):
-    """Config 0 with the learned selection on (PT_FLAG_MLP: the network's softmax, mixed with 10 %
-    of the Gamma row, picks the specular subspace; trained online by the library's own kernels
-    during the first 512 iterations), at the bar of the plain method."""
+    """Config 0 with both learned heads on (PT_FLAG_MLP: the network's softmax, mixed with 10 %
+    of the Gamma row, picks the specular subspace; PT_FLAG_MLP_DIR: the vMF mixture proposes the
+    first retrace direction at glossy vertices; trained online by the library's own kernels during
+    the first 512 iterations), 16,384 iterations: per pixel the bar of the plain method, and the
+    whole-image relative L1 within 10 % of the noise floor the per-pixel errors predict (a sum
+    over 12,288 pixel channels: two unbiased images land within a few per cent of it)."""
     frac, rel_l1, floor, tot = _cfg0_parity(gpu, extra_flags=("MLP", "MLP_DIR"), tag="config 0 learned",
-                                            train_iters=512, mlp_mix=0.9, mlp_lr=1e-3)
+                                            n_batches=16, train_iters=512, mlp_mix=0.9, mlp_lr=1e-3)
     assert frac >= 0.999
-    assert rel_l1 < 0.005
+    assert rel_l1 < 1.1 * floor
     assert tot["n_nan"] == 0 and tot["n_recip_truncated"] == 0
 
 
