@@ -317,6 +317,19 @@ typedef struct {
 pt_status pt_reciprocal_estimate(pt_scene *s, const pt_recip_query *q, float *out_est_dev,
                                  uint32_t *out_nsamples_dev, void *hip_stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc): pt_reciprocal_estimate in PT_RECIP_TABLE mode, with the same
+ * arguments, kernels and results (bit for bit, for the same query), that allocates nothing. The
+ * cumulative sums of q go to a fixed device array of PT_NOALLOC_TABLE_MAX + 1 doubles (8 MiB, one
+ * per device, held until the process ends) instead of a per-call workspace. Tables longer than
+ * PT_NOALLOC_TABLE_MAX entries and any other mode return PT_EINVAL. Every call on a device shares
+ * that device's array: calls that overlap on one device (on different streams, or from different
+ * threads without ordering) race and give wrong estimates; calls ordered on one stream do not.
+ * No scene is needed. */
+#define PT_NOALLOC_TABLE_MAX (1 << 20)
+pt_status pt_reciprocal_estimate_noalloc(const pt_recip_query *q, float *out_est_dev, uint32_t *out_nsamples_dev,
+                                         void *hip_stream);
+
 /* Image = accum / n_iter: the per-pixel estimate of I_j (Section 3.1) as the mean of n_iter
  * iterations of one sample per pixel each (Section 6.1), written to the caller-owned
  * out_rgb_dev[H*W*3] (row-major, 3 floats per pixel, the layout of accum_rgb_dev). accum_rgb_dev

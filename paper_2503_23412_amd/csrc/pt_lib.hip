@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <atomic>
+#include <mutex>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -1744,3 +1745,53 @@ extern "C" pt_status pt_bvh_stats(const float *tri, int32_t n_tri, int32_t width
     }
 }
 
+// ---------------------------------------------------------------------------------------------
+// Table-mode reciprocal estimates without allocation. The cumulative sums of q live in this
+// file-scope device array instead of a per-call workspace; each device holds its own copy for the
+// life of the process. Host code never passes the array's name to a kernel (on the host it is a
+// stand-in, not a device address): its device address is taken once per device with
+// hipGetSymbolAddress and kept in table_scratch_dev.
+static __device__ __align__(256) double table_scratch[PT_NOALLOC_TABLE_MAX + 1];   // 8 MiB
+
+namespace {
+std::mutex g_table_scratch_mu;
+std::vector<double *> g_table_scratch_dev;   // per device ordinal
+
+// the current device's address of table_scratch (looked up on the first call on that device)
+pt_status table_scratch_dev(double **out)
+{
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lock(g_table_scratch_mu);
+    if ((int)g_table_scratch_dev.size() <= dev) g_table_scratch_dev.resize((size_t)dev + 1, nullptr);
+    if (!g_table_scratch_dev[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(table_scratch));
+        if (e != hipSuccess || !p)
+            return set_err(PT_EDEVICE, "hipGetSymbolAddress(table_scratch) failed: %s", hipGetErrorString(e));
+        g_table_scratch_dev[dev] = (double *)p;
+    }
+    *out = g_table_scratch_dev[dev];
+    return PT_OK;
+}
+}  // namespace
+
+extern "C" pt_status pt_reciprocal_estimate_noalloc(const pt_recip_query *q, float *out, uint32_t *ns, void *stream_)
+{
+    TRY(check_table_query(q, out, ns));
+    if (q->n > PT_NOALLOC_TABLE_MAX)
+        return set_err(PT_EINVAL, "table of %d entries: pt_reciprocal_estimate_noalloc holds at most %d", q->n,
+                       PT_NOALLOC_TABLE_MAX);
+    TRY(check_device());
+    double *cdf = nullptr;
+    TRY(table_scratch_dev(&cdf));
+    hipStream_t stream = (hipStream_t)stream_;
+    const uint32_t cap = q->cap ? q->cap : 65536u;
+    // k_table_cdf writes cdf[0 .. n] before k_recip_table reads it, so nothing of an earlier call
+    // (a longer table's tail included) is read
+    k_table_cdf<<<1, 1024, 0, stream>>>(q->q_dev, q->n, cdf);
+    k_recip_table<<<blocks(q->n_est, 256), 256, 0, stream>>>(q->f_dev, cdf, q->n, q->B, q->n_est, q->estimator,
+                                                             q->booth_r, q->seed, cap, out, ns);
+    HIPCHK(hipGetLastError());
+    return PT_OK;
+}

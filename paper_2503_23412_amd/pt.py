@@ -36,8 +36,9 @@ EXPORTED = ["pt_scene_upload", "pt_scene_release", "pt_build_subspaces", "pt_ren
             "pt_render_scenes", "pt_autotune",
             "pt_mlp_param_count", "pt_mlp_set_params", "pt_mlp_get_params", "pt_mlp_forward", "pt_mlp_train_step",
             "pt_reciprocal_estimate", "pt_resolve_image", "pt_trace_closest", "pt_scene_totals",
-            "pt_selection_tables", "pt_iteration_times", "pt_philox", "pt_bvh_stats",
+            "pt_selection_tables", "pt_iteration_times", "pt_philox", "pt_bvh_stats", "pt_reciprocal_estimate_noalloc",
             "pt_vmf_sample", "pt_last_error"]
+NOALLOC_TABLE_MAX = 1 << 20
 
 
 class SceneDesc(ctypes.Structure):
@@ -141,6 +142,7 @@ def lib():
         L.pt_philox.argtypes = [P, I, P, P]
         L.pt_iteration_times.argtypes = [P, ctypes.c_uint32, I, P, P]
         L.pt_bvh_stats.argtypes = [P, I, I, P, P, P]
+        L.pt_reciprocal_estimate_noalloc.argtypes = [ctypes.POINTER(RecipQuery), P, P, P]
         L.pt_last_error.restype = ctypes.c_char_p
         for name in EXPORTED:
             if name == "pt_last_error":
@@ -330,6 +332,14 @@ def bvh_stats(tri, width=4):
     _check(lib().pt_bvh_stats(t.ctypes.data, int(t.shape[0]), int(width), ctypes.byref(a), ctypes.byref(b),
                               ctypes.byref(c)))
     return a.value, b.value, c.value
+
+
+def reciprocal_table_noalloc(f, q, B, n_est, out, nsamples, estimator=PT_EST_ITILDE, seed=1, cap=0, booth_r=1.0,
+                             stream=None):
+    """reciprocal_table through the entry point that allocates nothing (tables <= NOALLOC_TABLE_MAX)."""
+    qq = RecipQuery(0, int(f.shape[0]), f.data_ptr(), q.data_ptr(), float(B), int(n_est), int(estimator), int(seed),
+                    int(cap), None, 0, None, float(booth_r))
+    _check(lib().pt_reciprocal_estimate_noalloc(ctypes.byref(qq), _ptr(out), _ptr(nsamples), _stream(stream)))
 
 
 def render_scenes(scenes, accums, accums_sq, n_iter, params, stream=None):
