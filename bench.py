@@ -30,8 +30,7 @@ TRI_BYTES = 48             # one intersection triangle record
 # barycentric and distance bounds (52)
 FLOP_NODE = 100
 FLOP_TRI = 52
-PMC_FILES = {1: os.path.join(ROOT, "profiles", "pmc_k_recip_projector_512.txt"),
-             2: os.path.join(ROOT, "profiles", "pmc_glossy_1024.txt")}
+PMC_FILES = {2: os.path.join(ROOT, "profiles", "pmc_glossy_1024.txt")}
 
 
 def log(*a):
@@ -106,6 +105,8 @@ def main():
     ap.add_argument("--tris", type=int, default=0,
                     help="configs 2 and 3: triangle budget of the glossy scene instead of 200,000 (8,000,000 gives "
                          "4.2 M triangles, 285 MB of nodes and triangle records, beyond the 256 MB Infinity Cache)")
+    ap.add_argument("--bvh-width", type=int, default=0, choices=(0, 4, 8),
+                    help="BVH width of the walks: 4, 8, or 0 to upload both trees and let the autotuner pick")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="after the run, one device-to-device copy of this many MiB: the reference kernel of "
                          "known size for scaling hardware byte counters")
@@ -134,7 +135,7 @@ def main():
         params.update(mlp_mix=cfg["mlp_mix"], mlp_lr=cfg["mlp_lr"], train_iters=cfg["train_iters"])
     torch.cuda.set_device(0)
     log(f"upload: {sc['tri'].shape[0]} tris, {W}x{H}")
-    S = pt.Scene(sc, max_light_paths=cfg["n_light"])
+    S = pt.Scene(sc, max_light_paths=cfg["n_light"], bvh_width=args.bvh_width)
     S.build_subspaces(n_eye=cfg["n_subspaces"], n_spec=cfg["n_spec"])
     acc = torch.zeros(W * H * 3, device="cuda")
     acc2 = torch.zeros_like(acc)
@@ -223,7 +224,9 @@ def main():
                                      "n_nan", "chain_len_max")},
         "ms_breakdown": {"eye_extension": ms_ext, "reciprocal_block": ms_rec, "reciprocal_stage_a": ms_a},
         "schedule": {"stage_a_budget": tune["stage_a_budget"], "round_grid": tune["round_grid"],
-                     "autotune_iterations": k0, "ms_tuned": tune["ms_best"], "ms_default": tune["ms_previous"]},
+                     "bvh_width": tune["bvh_width"], "extension_workgroup": tune["ext_wg"],
+                     "queue_chunk": tune["queue_chunk"], "autotune_iterations": k0, "ms_tuned": tune["ms_best"],
+                     "ms_default": tune["ms_previous"]},
         "roofline": {"kernel": f"{dom['kernel']} ({dom['what']})", "bound": "hbm", "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "algorithmic_bytes_per_launch": bytes_launch,

@@ -2,7 +2,8 @@
 """Batched serving benchmark (config 4): 16 seeded scenes of uneven size (10^3 .. 2 10^6 triangles,
 256^2 .. 1920x1080 pixels, mirror/glass/glossy materials, depth 16, 2,000 eye and specular
 subspaces each) rendered together, one HIP graph holding one iteration of every scene on its own
-branch (pt_render_scenes), replayed per iteration.
+branch (pt_render_scenes), with the first stage of every scene's reciprocal chains in one
+persistent launch over a shared work queue, replayed per iteration.
 
 Reports one JSON line: aggregate full-path samples/s over all scenes (pixels x iterations / wall
 time), and the per-scene iteration latency from the device's wall clock (first to last kernel of

@@ -110,6 +110,11 @@ pt_status check_device()
             else kern<int, B><<<(grid), (block), 0, (strm)>>>(__VA_ARGS__);                     \
         }                                                                                       \
     } while (0)
+// the stack entry choice of a multi-scene launch (PT_STK_B reads these two fields)
+struct MultiStk {
+    bool stk16;
+    int bvh_cur;
+};
 // stage A with Booth's roulette: its own instances (template argument BOOTH)
 template <typename SE>
 static void launch_recip_booth(int grid, hipStream_t st, SceneDev S, Cand *cand, const uint32_t *final_,
@@ -1475,16 +1480,17 @@ extern "C" pt_status pt_render_scenes(pt_scene *const *scenes, const pt_iter_par
         }
         // stage A of every scene in one persistent launch: the jobs (device copies of what k_recip
         // takes per scene) are written before the capture
-        // (one instance walks one tree type: the scenes must agree on the BVH width and stack entries,
-        // else every branch keeps its own stage A)
-        bool multi = false, same = true, booth = false;
+        // (one instance walks one tree width: the scenes must agree on it, else every branch keeps
+        // its own stage A; 32-bit stack entries when any scene needs them)
+        bool multi = false, same = true, booth = false, wide = false;
         for (int i = 0; i < n; ++i) {
             const pt_scene *sp = scenes[i];
             const pt_iter_params *q = &params[i];
             const bool conn = (q->flags & PT_FLAG_SPC) != 0, ltr = (q->flags & PT_FLAG_LT) != 0;
             const int lmax = (conn || ltr) ? q->max_depth : std::min(q->max_depth - 1, PT_LMAX);
             multi |= (q->flags & PT_FLAG_PROXY) && lmax >= 2;
-            same &= sp->stk16 == own->stk16 && sp->bvh_cur == own->bvh_cur;
+            same &= sp->bvh_cur == own->bvh_cur;
+            wide |= !sp->stk16;
             booth |= (q->flags & PT_FLAG_BOOTH) && q->booth_r > 0.0f;
         }
         multi = multi && same && n > 1;
@@ -1533,9 +1539,10 @@ extern "C" pt_status pt_render_scenes(pt_scene *const *scenes, const pt_iter_par
             if (part == 1 && st == PT_OK && e == hipSuccess) {
                 k_multi_base<<<1, 64, 0, own->cap_stream>>>(own->mjobs, n, own->mbase, own->mwork);
                 const int grid = own->persist_wg, chunk = std::max(1, own->queue_chunk);
-                if (booth) PT_STK_B(own, k_recip_multi, true, grid, 64 * RW, own->cap_stream, own->mjobs, n, own->mbase,
+                const MultiStk ms{!wide, own->bvh_cur};
+                if (booth) PT_STK_B(&ms, k_recip_multi, true, grid, 64 * RW, own->cap_stream, own->mjobs, n, own->mbase,
                                     own->mwork, chunk);
-                else PT_STK_B(own, k_recip_multi, false, grid, 64 * RW, own->cap_stream, own->mjobs, n, own->mbase,
+                else PT_STK_B(&ms, k_recip_multi, false, grid, 64 * RW, own->cap_stream, own->mjobs, n, own->mbase,
                               own->mwork, chunk);
                 e = hipGetLastError();
             }
