@@ -223,9 +223,16 @@ def main():
                                      "n_proxy_attempts", "n_proxy_valid", "n_pool", "n_connections", "n_lt_splats",
                                      "n_nan", "chain_len_max")},
         "ms_breakdown": {"eye_extension": ms_ext, "reciprocal_block": ms_rec, "reciprocal_stage_a": ms_a},
+        # stage A of the chains in the counting iteration: lanes busy in its traversal loops (node
+        # visits over 64 x the wavefronts' loop trips) and the f/q samples it drew against those the
+        # chains used
+        "stage_a": {"simd_efficiency": stc["node_visits_stage_a"] / max(64.0 * stc["wave_trips_stage_a"], 1.0),
+                    "samples_drawn": stc["n_drawn_stage_a"], "samples_used": stc["n_samples_stage_a"],
+                    "pilot_samples_drawn": stc["n_drawn_pilot"]},
         "schedule": {"stage_a_budget": tune["stage_a_budget"], "round_grid": tune["round_grid"],
                      "bvh_width": tune["bvh_width"], "extension_workgroup": tune["ext_wg"],
-                     "queue_chunk": tune["queue_chunk"], "autotune_iterations": k0, "ms_tuned": tune["ms_best"],
+                     "queue_chunk": tune["queue_chunk"], "stage_a_ahead": tune["stage_a_ahead"],
+                     "autotune_iterations": k0, "ms_tuned": tune["ms_best"],
                      "ms_default": tune["ms_previous"]},
         "roofline": {"kernel": f"{dom['kernel']} ({dom['what']})", "bound": "hbm", "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,

@@ -92,8 +92,11 @@ def run_timed(torch, pt, sc, wl, flags, seconds, seed, n_checks=4):
     s2 = torch.zeros_like(s1)
     torch.cuda.synchronize()
     checks = sorted(seconds / 2 ** j for j in range(n_checks))
-    snaps, k, t_run = [], 0, 0.0
+    snaps, k, t_run, t_say = [], 0, 0.0, 30.0
     while checks:
+        if t_run >= t_say:
+            print(f"#   {k} iterations, {t_run:.0f} s", flush=True)
+            t_say += 30.0
         t0 = time.perf_counter()
         img.zero_()
         S.render_iteration(img, None, iteration=k, **params)

@@ -218,7 +218,9 @@ pt_status pt_render_scenes(pt_scene *const *scenes, const pt_iter_params *params
  * extension launches (64, 128, 256 threads: each thread's traversal stack lives in LDS, so the
  * size trades occupancy per CU against workgroups in flight); the number of chains a wavefront
  * of the one-wavefront stage takes from its work queue per visit (1, 2, 4; also used by the
- * multi-scene stage of pt_render_scenes). Every choice gives the same estimator (a ray's hit
+ * multi-scene stage of pt_render_scenes); how many steps of 64 samples a lane of that stage may
+ * compute beyond the oldest step its chain has not consumed (1: lockstep; 2: a lane whose sample
+ * ended early starts the next while the others still trace). Every choice gives the same estimator (a ray's hit
  * does not depend on the tree's width or its workgroup, and the chains consume i.i.d. samples
  * whoever draws them), so it changes speed only. The timed iterations render into accum_rgb /
  * accum_sq (iterations p->iteration, +1, ...); their number is returned in iterations_rendered.
@@ -232,6 +234,7 @@ typedef struct {
     int32_t ext_wg;              /* chosen workgroup size of the extension launches */
     int32_t queue_chunk;         /* chosen chains per take from stage A's work queue */
     int32_t bvh_width;           /* BVH width the walks use from now on (4 or 8) */
+    int32_t stage_a_ahead;       /* chosen look-ahead of the one-wavefront stage (1 or 2 steps) */
 } pt_tune_result;
 pt_status pt_autotune(pt_scene *s, const pt_iter_params *p, float *accum_rgb_dev, float *accum_sq_dev,
                       pt_tune_result *out, void *hip_stream);

@@ -577,62 +577,80 @@ __device__ __forceinline__ float fq_u1_b(const SceneDev &S, float3 v, float3 vn,
     return f / (0.5f * (p1 + q3));
 }
 
-// The sample's rays are traced at one call site: each trip of the loop below traces the ray the
-// sample's state asks for and then advances the state, so lanes that took different strategies
-// (u = 1) or reached different vertices still traverse together, and the traversal is inlined
-// once. Modes: 0 u = 1 class A from the light (visibility y -> y_{s-1}), 1 u = 1 class A from
-// y_{s-1} (toward the light), 2 / 3 u = 1 class B from y_0 / from y_{s-1} (ray to y_1, then the
-// visibility of the other side), 4 u >= 2 (the retrace through the specular run, then for class
-// B the visibility y_0 -> y_1).
-template <typename SE>
-__device__ float fq_sample(CtxT<SE> &C, const Cand &c, Rng &r)
+// One f/q sample is a small state machine: fq_begin draws its first choices and sets the ray of
+// its first trip; after each trip fq_advance takes the hit, and either completes the sample or
+// sets the next ray. The caller traces every trip at one call site, so lanes that took different
+// strategies (u = 1) or reached different vertices still traverse together, and the traversal is
+// inlined once. Modes: 0 u = 1 class A from the light (visibility y -> y_{s-1}), 1 u = 1 class A
+// from y_{s-1} (toward the light), 2 / 3 u = 1 class B from y_0 / from y_{s-1} (ray to y_1, then
+// the visibility of the other side), 4 u >= 2 (the retrace through the specular run, then for
+// class B the visibility y_0 -> y_1).
+struct FqCand {              // what a sample reads of its candidate
+    float3 v, vn, y0, n0;
+    int vt, t0, cls, u;
+    MatDev mv;
+};
+struct FqState {             // a sample between two trips
+    float3 ro, rd;           // the ray of the next trip (mode 0: ro is the emitter point; mode 4
+                             // before the closing visibility: rd is the direction that left the
+                             // last vertex)
+    float rmax;
+    int ig0, ig1;
+    bool any;
+    int mode, k;
+    float3 nyl;              // mode 0: the emitter normal
+    Hit h1;                  // modes 2, 3: y_1
+    float f, q;
+};
+__device__ __forceinline__ FqCand fq_cand(const SceneDev &S, const Cand &c)
 {
-    const SceneDev &S = C.S;
-    const int cls = c.cls_u >> 8, u = c.cls_u & 0xFF;
-    const float3 v = xyz(c.v);
-    const int vt = fbits(c.v.w);
-    const float3 vn = S.shade[vt].n;
-    const MatDev mv = S.mats[S.shade[vt].mat];
-    const float3 y0 = xyz(c.hc);     // control vertex of class B
-    const int t0 = fbits(c.hc.w);
-    const float3 n0 = cls ? S.shade[t0].n : f3(0.0f, 0.0f, 1.0f);
-    // the ray of the next trip
-    float3 ro = v, rd = f3(0.0f, 0.0f, 1.0f);
-    float rmax = 3.0e38f;
-    int ig0 = vt, ig1 = -1;
-    bool any = false;
-    // sample state
-    int mode, k = 1;
-    float3 yl = v, nyl = vn;         // mode 0: the emitter point
-    Hit h1;                          // modes 2, 3: y_1
-    h1.tri = -1; h1.b1 = h1.b2 = 0.0f; h1.t = 0.0f;
-    float f = 1.0f, q = 1.0f;
-    float3 w = rd;
-    if (u == 1) {
+    FqCand K;
+    K.cls = c.cls_u >> 8; K.u = c.cls_u & 0xFF;
+    K.v = xyz(c.v);
+    K.vt = fbits(c.v.w);
+    K.vn = S.shade[K.vt].n;
+    K.mv = S.mats[S.shade[K.vt].mat];
+    K.y0 = xyz(c.hc);        // control vertex of class B
+    K.t0 = fbits(c.hc.w);
+    K.n0 = K.cls ? S.shade[K.t0].n : f3(0.0f, 0.0f, 1.0f);
+    return K;
+}
+__device__ __forceinline__ void fq_begin(const SceneDev &S, const FqCand &K, Rng &r, FqState &s)
+{
+    s.ro = K.v; s.rd = f3(0.0f, 0.0f, 1.0f);
+    s.rmax = 3.0e38f;
+    s.ig0 = K.vt; s.ig1 = -1;
+    s.any = false;
+    s.k = 1;
+    s.nyl = K.vn;
+    s.h1.tri = -1; s.h1.b1 = s.h1.b2 = 0.0f; s.h1.t = 0.0f;
+    s.f = 1.0f; s.q = 1.0f;
+    if (K.u == 1) {
         const bool from_spec = rng_f(r) >= 0.5f;
-        if (cls == 0) {
+        if (K.cls == 0) {
             if (!from_spec) {
                 const float a = rng_f(r), b = rng_f(r), d = rng_f(r);
                 const LPoint L = sample_emitter(S, a, b, d);
-                yl = L.p; nyl = L.n;
-                const float3 dd = v - L.p;
+                s.nyl = L.n;
+                const float3 dd = K.v - L.p;
                 const float dist = sqrtf(dot3(dd, dd));
-                ro = L.p; rd = dd * (1.0f / dist); rmax = dist * 0.9999f; ig0 = L.tri; ig1 = vt; any = true;
-                mode = 0;
+                s.ro = L.p; s.rd = dd * (1.0f / dist); s.rmax = dist * 0.9999f; s.ig0 = L.tri; s.ig1 = K.vt;
+                s.any = true;
+                s.mode = 0;
             } else {
                 float sp;
-                rd = spec_start(mv, vn, r, sp);
-                mode = 1;
+                s.rd = spec_start(K.mv, K.vn, r, sp);
+                s.mode = 1;
             }
         } else {
             if (!from_spec) {
                 const float a = rng_f(r), b = rng_f(r);
-                ro = y0; rd = cos_hemi(n0, a, b); ig0 = t0;
-                mode = 2;
+                s.ro = K.y0; s.rd = cos_hemi(K.n0, a, b); s.ig0 = K.t0;
+                s.mode = 2;
             } else {
                 float sp;
-                rd = spec_start(mv, vn, r, sp);
-                mode = 3;
+                s.rd = spec_start(K.mv, K.vn, r, sp);
+                s.mode = 3;
             }
         }
     } else {
@@ -642,89 +660,106 @@ __device__ float fq_sample(CtxT<SE> &C, const Cand &c, Rng &r)
         // (eta_b^2 |cos b|) / (eta_a^2 |cos a|), survives in f/q (etendue is conserved along a
         // Dirac run).
         float sp;
-        w = spec_start(mv, vn, r, sp);
-        q = sp * fabsf(dot3(vn, w)) / PT_PI;
-        const float e = side_eta(mv, vn, w);
-        f = e * e * fabsf(dot3(vn, w));   // numerator of the run leaving y_{s-1}
-        rd = w;
-        mode = 4;
+        s.rd = spec_start(K.mv, K.vn, r, sp);
+        s.q = sp * fabsf(dot3(K.vn, s.rd)) / PT_PI;
+        const float e = side_eta(K.mv, K.vn, s.rd);
+        s.f = e * e * fabsf(dot3(K.vn, s.rd));   // numerator of the run leaving y_{s-1}
+        s.mode = 4;
     }
+}
+// after the trip of s traced to (hit, h): true with the sample's f/q in out when it is complete
+__device__ __forceinline__ bool fq_advance(const SceneDev &S, const FqCand &K, Rng &r, FqState &s, bool hit,
+                                           const Hit &h, float &out)
+{
+    const int u = K.u;
+    if (s.mode == 0) { out = hit ? 0.0f : fq_u1_a(S, K.v, K.vn, K.mv, s.ro, s.nyl); return true; }
+    if (s.mode == 1) {
+        if (!hit || !(S.mats[S.shade[h.tri].mat].flags & MF_EMIT)) { out = 0.0f; return true; }
+        out = fq_u1_a(S, K.v, K.vn, K.mv, tri_point(S, h.tri, h.b1, h.b2), S.shade[h.tri].n);
+        return true;
+    }
+    if (s.mode <= 3) {
+        if (s.k == 2) { out = hit ? 0.0f : fq_u1_b(S, K.v, K.vn, K.mv, K.y0, K.n0, s.h1); return true; }
+        // the ray to y_1, which must be diffuse; then the visibility of its other side
+        if (!hit || (S.mats[S.shade[h.tri].mat].flags & MF_SPEC)) { out = 0.0f; return true; }
+        s.h1 = h;
+        const float3 p1 = tri_point(S, h.tri, h.b1, h.b2);
+        const float3 a = s.mode == 2 ? p1 : K.y0, b = s.mode == 2 ? K.v : p1;
+        const float3 dd = b - a;
+        const float dist = sqrtf(dot3(dd, dd));
+        s.ro = a; s.rd = dd * (1.0f / dist); s.rmax = dist * 0.9999f; s.any = true;
+        s.ig0 = s.mode == 2 ? h.tri : K.t0; s.ig1 = s.mode == 2 ? K.vt : h.tri;
+        s.k = 2;
+        return false;
+    }
+    // mode 4
+    if (s.k > u) { out = hit ? 0.0f : (s.f > 0.0f ? s.f / s.q : 0.0f); return true; }   // class B: y_0 -> y_1
+    if (!hit) { out = 0.0f; return true; }
+    const float3 y = tri_point(S, h.tri, h.b1, h.b2);
+    const float3 ny = S.shade[h.tri].n;
+    const MatDev m = S.mats[S.shade[h.tri].mat];
+    const float3 w_cam = -s.rd;       // toward y_{s-1}
+    if (s.k < u) {
+        if (!(m.flags & MF_SPEC)) { out = 0.0f; return true; }
+        const float a = rng_f(r), b = rng_f(r), cc = rng_f(r);
+        const BS bs = bsdf_sample(m, ny, w_cam, a, b, cc, true);
+        if (!bs.ok) { out = 0.0f; return true; }
+        s.q *= bs.pdf;
+        const float3 w_light = bs.wi;
+        if (m.flags & MF_DELTA) {
+            s.f *= dirac_prob(m, ny, w_light, w_cam);
+        } else {
+            // close the run arriving here, account the forward density, open the next run
+            const float ea = side_eta(m, ny, w_cam);
+            s.f /= ea * ea * fabsf(dot3(ny, w_cam));
+            s.f *= bsdf_pdf(m, ny, w_light, w_cam);
+            const float eb = side_eta(m, ny, w_light);
+            s.f *= eb * eb * fabsf(dot3(ny, w_light));
+        }
+        if (!(s.f > 0.0f)) { out = 0.0f; return true; }
+        s.ro = y; s.rd = w_light; s.ig0 = h.tri;
+        ++s.k;
+        return false;
+    }
+    // k == u: the vertex that closes the run
+    const float ea = side_eta(m, ny, w_cam);
+    s.f /= ea * ea * fabsf(dot3(ny, w_cam));
+    if (K.cls == 0) {
+        if (!(m.flags & MF_EMIT)) { out = 0.0f; return true; }
+        const float c0 = dot3(ny, w_cam);
+        if (c0 <= 0.0f) { out = 0.0f; return true; }
+        s.f *= (1.0f / S.em_area) * c0 / PT_PI;
+        out = s.f > 0.0f ? s.f / s.q : 0.0f;
+        return true;
+    }
+    if (m.flags & MF_SPEC) { out = 0.0f; return true; }
+    const float3 a = y - K.y0;
+    const float d2 = dot3(a, a);
+    const float3 w01 = a * rsqrtf(d2);
+    const float c0 = dot3(K.n0, w01);
+    if (c0 <= 0.0f) { out = 0.0f; return true; }
+    s.f *= (c0 / PT_PI) * fabsf(dot3(ny, w01)) / d2;
+    s.f *= bsdf_pdf(m, ny, -w01, w_cam);
+    // visibility y_0 -> y (ignoring both triangles), traced on the next trip
+    const float dist = sqrtf(d2);
+    s.ro = K.y0; s.rd = w01; s.rmax = dist * 0.9999f; s.ig0 = K.t0; s.ig1 = h.tri; s.any = true;
+    s.k = u + 1;
+    return false;
+}
+// one whole sample of candidate c with the random stream r
+template <typename SE>
+__device__ float fq_sample(CtxT<SE> &C, const Cand &c, Rng &r)
+{
+    const FqCand K = fq_cand(C.S, c);
+    FqState s;
+    fq_begin(C.S, K, r, s);
     for (;;) {
         Hit h;
         C.rays++;
-        const bool hit = traverse_rt<true>(S, ro, rd, S.tmin, rmax, ig0, ig1, any, C.stk, C.stride, h, &C.visits,
-                                           &C.tests, &C.trips);
-        if (mode == 0) return hit ? 0.0f : fq_u1_a(S, v, vn, mv, yl, nyl);
-        if (mode == 1) {
-            if (!hit || !(S.mats[S.shade[h.tri].mat].flags & MF_EMIT)) return 0.0f;
-            return fq_u1_a(S, v, vn, mv, tri_point(S, h.tri, h.b1, h.b2), S.shade[h.tri].n);
-        }
-        if (mode <= 3) {
-            if (k == 2) return hit ? 0.0f : fq_u1_b(S, v, vn, mv, y0, n0, h1);
-            // the ray to y_1, which must be diffuse; then the visibility of its other side
-            if (!hit || (S.mats[S.shade[h.tri].mat].flags & MF_SPEC)) return 0.0f;
-            h1 = h;
-            const float3 p1 = tri_point(S, h.tri, h.b1, h.b2);
-            const float3 a = mode == 2 ? p1 : y0, b = mode == 2 ? v : p1;
-            const float3 dd = b - a;
-            const float dist = sqrtf(dot3(dd, dd));
-            ro = a; rd = dd * (1.0f / dist); rmax = dist * 0.9999f; any = true;
-            ig0 = mode == 2 ? h.tri : t0; ig1 = mode == 2 ? vt : h.tri;
-            k = 2;
-            continue;
-        }
-        // mode 4
-        if (k > u) return hit ? 0.0f : (f > 0.0f ? f / q : 0.0f);   // class B: y_0 -> y_1 visibility
-        if (!hit) return 0.0f;
-        const float3 y = tri_point(S, h.tri, h.b1, h.b2);
-        const float3 ny = S.shade[h.tri].n;
-        const MatDev m = S.mats[S.shade[h.tri].mat];
-        const float3 w_cam = -w;          // toward y_{s-1}
-        if (k < u) {
-            if (!(m.flags & MF_SPEC)) return 0.0f;
-            const float a = rng_f(r), b = rng_f(r), cc = rng_f(r);
-            const BS bs = bsdf_sample(m, ny, w_cam, a, b, cc, true);
-            if (!bs.ok) return 0.0f;
-            q *= bs.pdf;
-            const float3 w_light = bs.wi;
-            if (m.flags & MF_DELTA) {
-                f *= dirac_prob(m, ny, w_light, w_cam);
-            } else {
-                // close the run arriving here, account the forward density, open the next run
-                const float ea = side_eta(m, ny, w_cam);
-                f /= ea * ea * fabsf(dot3(ny, w_cam));
-                f *= bsdf_pdf(m, ny, w_light, w_cam);
-                const float eb = side_eta(m, ny, w_light);
-                f *= eb * eb * fabsf(dot3(ny, w_light));
-            }
-            if (!(f > 0.0f)) return 0.0f;
-            w = w_light;
-            ro = y; rd = w; ig0 = h.tri;
-            ++k;
-            continue;
-        }
-        // k == u: the vertex that closes the run
-        const float ea = side_eta(m, ny, w_cam);
-        f /= ea * ea * fabsf(dot3(ny, w_cam));
-        if (cls == 0) {
-            if (!(m.flags & MF_EMIT)) return 0.0f;
-            const float c0 = dot3(ny, w_cam);
-            if (c0 <= 0.0f) return 0.0f;
-            f *= (1.0f / S.em_area) * c0 / PT_PI;
-            return f > 0.0f ? f / q : 0.0f;
-        }
-        if (m.flags & MF_SPEC) return 0.0f;
-        const float3 a = y - y0;
-        const float d2 = dot3(a, a);
-        const float3 w01 = a * rsqrtf(d2);
-        const float c0 = dot3(n0, w01);
-        if (c0 <= 0.0f) return 0.0f;
-        f *= (c0 / PT_PI) * fabsf(dot3(ny, w01)) / d2;
-        f *= bsdf_pdf(m, ny, -w01, w_cam);
-        // visibility y_0 -> y (ignoring both triangles), traced on the next trip
-        const float dist = sqrtf(d2);
-        ro = y0; rd = w01; rmax = dist * 0.9999f; ig0 = t0; ig1 = h.tri; any = true;
-        k = u + 1;
+        const bool hit = traverse_rt<true>(C.S, s.ro, s.rd, C.S.tmin, s.rmax, s.ig0, s.ig1, s.any, C.stk, C.stride, h,
+                                           &C.visits, &C.tests, &C.trips);
+        float out;
+        if (fq_advance(C.S, K, r, s, hit, h, out)) return out;
     }
 }
 
@@ -896,6 +931,7 @@ struct ChainRun {
 };
 #define CHAIN_COIN 0x80000000u   // Philox counters of the roulette coins
 #define CHAIN_LONG 0x00100000u   // Philox counters of the samples drawn in rounds
+#define CHAIN_UNI 0x40000000u    // Philox counters of stage A's child-count uniforms
 #define CHAIN_ROUNDS 11
 #define CHAIN_BUF (1u << 24)     // samples per round over all chains
 #define CHAIN_LIST_CAP (CHAIN_BUF / 64)   // running chains carried between rounds
@@ -1053,12 +1089,20 @@ __device__ __forceinline__ void chain_finish(Cand &c, const ChainRun &st, bool t
 }
 
 // stage A of one chain (item `wave` of a scene's (candidate, repeat) list, wave-uniform): one
-// wavefront draws at most `budget` samples, then hands a running chain over to the rounds
+// wavefront draws at most `budget` samples, then hands a running chain over to the rounds.
+// Lane l computes samples l, 64 + l, 128 + l, ... (sample step * 64 + l has its own Philox
+// counter, so its value does not depend on when it is computed); the chain consumes whole steps
+// of 64 in order. A lane whose sample ends early (a miss, a zero) starts its next one while the
+// others still trace, up to `ahead` steps beyond the oldest step not yet consumed (1: the lanes
+// move in lockstep, one sample each per step); the values of up to two steps wait in registers.
+// The uniform that splits a sample's |g| into whole and fractional children has a Philox counter
+// of its own (CHAIN_UNI + sample index), drawn when the sample is consumed.
 template <typename SE, bool BOOTH>
 __device__ __forceinline__ void stage_a_chain(CtxT<SE> &C, Cand *cand, const uint32_t *final_, const uint32_t *order,
                                               int wave, int repeats, uint32_t seed, uint32_t iter, uint32_t n1,
                                               uint32_t budget, float *runmax, ChainState *longq, float booth_r,
-                                              unsigned long long *cnt, int lane, uint32_t &ns, uint32_t &drawn)
+                                              unsigned long long *cnt, int lane, int ahead, uint32_t &ns,
+                                              uint32_t &drawn)
 {
     const uint32_t ci = final_[order[wave / repeats]];
     const uint32_t chain = ci * 8u + (uint32_t)(wave % repeats);
@@ -1067,23 +1111,53 @@ __device__ __forceinline__ void stage_a_chain(CtxT<SE> &C, Cand *cand, const uin
     ChainRun st{1.0, 1.0f, 1u, 0u, 0u, n1, 0u, true, 1.0f, 1.0f};
     float mx = 0.0f, fs = 0.0f;
     uint32_t nd = 0;
-    for (int step = 0; st.alive && st.pos + st.neg > 0 && st.ns < budget; ++step) {
-        Rng r = rng_make(seed, S_RECIP, chain, iter, (uint32_t)(step * 64 + lane));
-        const float fq = fq_sample(C, c, r);
-        const float u = rng_f(r);
-        mx = fmaxf(mx, fq);
-        fs += fq;
-        chain_consume(fq, u, 64, invB, st, seed, chain, iter, BOOTH ? booth_r : 0.0f);
-        drawn += 64;
-        nd += 64;
-    }
+    const FqCand K = fq_cand(C.S, c);
+    const int smax = (int)((budget + 63u) / 64u);   // steps stage A may consume
+    ahead = min(max(ahead, 1), 2);                   // the register ring holds two steps
+    int t = 0, head = 0;                             // this lane's step; the oldest unconsumed step
+    Rng r = rng_make(seed, S_RECIP, chain, iter, (uint32_t)lane);
+    FqState s;
+    fq_begin(C.S, K, r, s);
+    float v0 = 0.0f, v1 = 0.0f;   // f/q of the steps by step & 1
+    while (st.alive && st.pos + st.neg > 0 && st.ns < budget && head < smax) {
+        if (t < smax && t < head + ahead) {
+            Hit h;
+            C.rays++;
+            const bool hit = traverse_rt<true>(C.S, s.ro, s.rd, C.S.tmin, s.rmax, s.ig0, s.ig1, s.any, C.stk,
+                                               C.stride, h, &C.visits, &C.tests, &C.trips);
+            float fq;
+            if (fq_advance(C.S, K, r, s, hit, h, fq)) {
+                v0 = (t & 1) == 0 ? fq : v0;
+                v1 = (t & 1) == 1 ? fq : v1;
+                ++t;
+                if (t < smax) {
+                    r = rng_make(seed, S_RECIP, chain, iter, (uint32_t)(t * 64 + lane));
+                    fq_begin(C.S, K, r, s);
+                }
+            }
+        }
+        // the oldest step is complete once every lane has computed its sample of it
+        while (st.alive && st.pos + st.neg > 0 && st.ns < budget && head < smax && __ballot(t <= head) == 0ull) {
+            const float fq = (head & 1) == 0 ? v0 : v1;
+            Rng ru = rng_make(seed, S_RECIP, chain, iter, CHAIN_UNI + (uint32_t)(head * 64 + lane));
+            const float uu = rng_f(ru);
+            // the step's largest and summed f/q (wave-uniform)
+            float smx = fq, ssum = fq;
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-        mx = fmaxf(mx, __shfl_xor(mx, off));
-        fs += __shfl_xor(fs, off);
+            for (int off = 32; off > 0; off >>= 1) {
+                smx = fmaxf(smx, __shfl_xor(smx, off));
+                ssum += __shfl_xor(ssum, off);
+            }
+            mx = fmaxf(mx, uni_f(smx));
+            fs += uni_f(ssum);
+            nd += 64u;
+            chain_consume(fq, uu, 64, invB, st, seed, chain, iter, BOOTH ? booth_r : 0.0f);
+            ++head;
+        }
     }
-    // every f/q this stage drew is an i.i.d. sample of the candidate's ratio: its (class, u, S, C)
-    // bucket's mean estimates beta for later iterations
+    drawn += (uint32_t)t;   // samples this lane computed (some beyond the last consumed step)
+    // every f/q of the consumed steps is an i.i.d. sample of the candidate's ratio: its (class, u,
+    // S, C) bucket's mean estimates beta for later iterations
     if (lane == 0 && nd > 0) {
         unsafeAtomicAdd(&c.psum, fs);
         unsafeAtomicAdd(&c.pn, (float)nd);
@@ -1115,7 +1189,7 @@ __global__ void __launch_bounds__(64 * RW, PT_RECIP_WAVES) k_recip(SceneDev S, C
                                                    const uint32_t *order, int repeats,
                                                    uint32_t seed, uint32_t n1, uint32_t budget, float *runmax,
                                                    ChainState *longq, float booth_r, unsigned long long *cnt,
-                                                   int chunk)
+                                                   int chunk, int ahead)
 {
     const uint32_t iter = iter_of(cnt);
     __shared__ SE stk[stk_depth<SE>() * 64 * RW];
@@ -1127,10 +1201,10 @@ __global__ void __launch_bounds__(64 * RW, PT_RECIP_WAVES) k_recip(SceneDev S, C
     for (int w0 = next_item(cnt + C_WORK_A) * chunk; w0 < n; w0 = next_item(cnt + C_WORK_A) * chunk)
         for (int wave = w0; wave < min(w0 + chunk, n); ++wave)
             stage_a_chain<SE, BOOTH>(C, cand, final_, order, wave, repeats, seed, iter, n1, budget, runmax, longq,
-                                     booth_r, cnt, lane, ns, drawn);
+                                     booth_r, cnt, lane, ahead, ns, drawn);
     wave_count(cnt + C_RECIP_SAMPLES, lane == 0 ? ns : 0u);
     wave_count(cnt + C_SAMPLES_A, lane == 0 ? ns : 0u);
-    wave_count(cnt + C_DRAWN_A, lane == 0 ? drawn : 0u);
+    wave_count(cnt + C_DRAWN_A, drawn);
     wave_count(cnt + C_RAYS_RECIP, C.rays);
     count_traversal(C, cnt, C_VISITS_A, C_TESTS_A, C_TRIPS_A);
 }
@@ -1166,7 +1240,8 @@ __global__ void k_multi_base(const RecipJob *jobs, int n, uint32_t *base, unsign
 template <typename SE, bool BOOTH>
 __global__ void __launch_bounds__(64 * RW, PT_RECIP_WAVES) k_recip_multi(const RecipJob *__restrict__ jobs, int n_jobs,
                                                                          const uint32_t *__restrict__ base,
-                                                                         unsigned long long *work, int chunk)
+                                                                         unsigned long long *work, int chunk,
+                                                                         int ahead)
 {
     __shared__ SE stk[stk_depth<SE>() * 64 * RW];
     const int lane = threadIdx.x & 63;
@@ -1181,10 +1256,10 @@ __global__ void __launch_bounds__(64 * RW, PT_RECIP_WAVES) k_recip_multi(const R
             CtxT<SE> C{J.S, stk_col(stk, (int)threadIdx.x), 0u, (int)blockDim.x};
             uint32_t ns = 0, drawn = 0;
             stage_a_chain<SE, BOOTH>(C, J.cand, J.final_, J.order, w - (int)base[j], J.repeats, J.seed, iter_of(J.cnt),
-                                     J.n1, J.budget, J.runmax, J.longq, J.booth_r, J.cnt, lane, ns, drawn);
+                                     J.n1, J.budget, J.runmax, J.longq, J.booth_r, J.cnt, lane, ahead, ns, drawn);
             wave_count(J.cnt + C_RECIP_SAMPLES, lane == 0 ? ns : 0u);
             wave_count(J.cnt + C_SAMPLES_A, lane == 0 ? ns : 0u);
-            wave_count(J.cnt + C_DRAWN_A, lane == 0 ? drawn : 0u);
+            wave_count(J.cnt + C_DRAWN_A, drawn);
             wave_count(J.cnt + C_RAYS_RECIP, C.rays);
             count_traversal(C, J.cnt, C_VISITS_A, C_TESTS_A, C_TRIPS_A);
         }

@@ -119,10 +119,11 @@ struct MultiStk {
 template <typename SE>
 static void launch_recip_booth(int grid, hipStream_t st, SceneDev S, Cand *cand, const uint32_t *final_,
                                const uint32_t *order, int repeats, uint32_t seed, uint32_t n1, uint32_t budget,
-                               float *runmax, ChainState *longq, float booth_r, unsigned long long *cnt, int chunk)
+                               float *runmax, ChainState *longq, float booth_r, unsigned long long *cnt, int chunk,
+                               int ahead)
 {
     k_recip<SE, true><<<grid, 64 * RW, 0, st>>>(S, cand, final_, order, repeats, seed, n1, budget, runmax, longq,
-                                                booth_r, cnt, chunk);
+                                                booth_r, cnt, chunk, ahead);
 }
 
 // alias rows of a T x n table over its non-empty columns: one wavefront per row when the row
@@ -215,6 +216,7 @@ struct pt_scene {
     int persist_wg = 1024;
     // workgroup size of the extension (closest-hit) launches (pt_autotune: 64, 128 or 256)
     int ext_wg = 128;
+    int ahead = 2;   // steps a stage-A lane may compute beyond the oldest unconsumed one (1 or 2)
     // the chain kernels keep 16-bit traversal stack entries when the tree has fewer than 65,536 nodes
     bool stk16 = false;
     // BVH widths available to the walks, and the one in use (S.nodes8 set when it is 8)
@@ -1056,21 +1058,21 @@ pt_status enqueue_iteration(pt_scene *s, const pt_iter_params *p, float *acc, fl
                 if (s->bvh_cur == 8) {
                     if (s->stk16) launch_recip_booth<int16_t>(s->persist_wg, stream, S, s->cand, s->final_, s->order,
                                                               p->recip_repeats, p->seed, n1, s->tune_budget, s->runmax,
-                                                              s->chq[0], booth_r, s->cnt, s->queue_chunk);
+                                                              s->chq[0], booth_r, s->cnt, s->queue_chunk, s->ahead);
                     else launch_recip_booth<uint32_t>(s->persist_wg, stream, S, s->cand, s->final_, s->order,
                                                       p->recip_repeats, p->seed, n1, s->tune_budget, s->runmax,
-                                                      s->chq[0], booth_r, s->cnt, s->queue_chunk);
+                                                      s->chq[0], booth_r, s->cnt, s->queue_chunk, s->ahead);
                 } else {
                     if (s->stk16) launch_recip_booth<uint16_t>(s->persist_wg, stream, S, s->cand, s->final_, s->order,
                                                                p->recip_repeats, p->seed, n1, s->tune_budget, s->runmax,
-                                                               s->chq[0], booth_r, s->cnt, s->queue_chunk);
+                                                               s->chq[0], booth_r, s->cnt, s->queue_chunk, s->ahead);
                     else launch_recip_booth<int>(s->persist_wg, stream, S, s->cand, s->final_, s->order,
                                                  p->recip_repeats, p->seed, n1, s->tune_budget, s->runmax, s->chq[0],
-                                                 booth_r, s->cnt, s->queue_chunk);
+                                                 booth_r, s->cnt, s->queue_chunk, s->ahead);
                 }
             } else {
                 PT_STK(s, k_recip, s->persist_wg, 64 * RW, stream, S, s->cand, s->final_, s->order, p->recip_repeats,
-                       p->seed, n1, s->tune_budget, s->runmax, s->chq[0], booth_r, s->cnt, s->queue_chunk);
+                       p->seed, n1, s->tune_budget, s->runmax, s->chq[0], booth_r, s->cnt, s->queue_chunk, s->ahead);
             }
             if (timing) HIPCHK(hipEventRecord(s->ev[e0 + 2], stream));
             for (int r = 0; post && r < CHAIN_ROUNDS; ++r) {
@@ -1234,6 +1236,7 @@ extern "C" pt_status pt_render_batch(pt_scene *s, const pt_iter_params *p, uint3
     k.insert(k.end(), (const char *)&s->tune_gen_grid, (const char *)&s->tune_gen_grid + sizeof(s->tune_gen_grid));
     k.insert(k.end(), (const char *)&s->ext_wg, (const char *)&s->ext_wg + sizeof(s->ext_wg));
     k.insert(k.end(), (const char *)&s->queue_chunk, (const char *)&s->queue_chunk + sizeof(s->queue_chunk));
+    k.insert(k.end(), (const char *)&s->ahead, (const char *)&s->ahead + sizeof(s->ahead));
     if (!s->gexec || k != s->gkey) {
         ++s->n_captures;
         if (s->gexec) { HIPCHK(hipGraphExecDestroy(s->gexec)); s->gexec = nullptr; }
@@ -1468,6 +1471,7 @@ extern "C" pt_status pt_render_scenes(pt_scene *const *scenes, const pt_iter_par
         k.insert(k.end(), (const char *)&sp->gen, (const char *)&sp->gen + sizeof(sp->gen));
         k.insert(k.end(), (const char *)&sp->queue_chunk, (const char *)&sp->queue_chunk + sizeof(int));
         k.insert(k.end(), (const char *)&sp->ext_wg, (const char *)&sp->ext_wg + sizeof(int));
+        k.insert(k.end(), (const char *)&sp->ahead, (const char *)&sp->ahead + sizeof(int));
     }
     if (!own->mgexec || k != own->mgkey) {
         ++own->n_captures;
@@ -1541,9 +1545,9 @@ extern "C" pt_status pt_render_scenes(pt_scene *const *scenes, const pt_iter_par
                 const int grid = own->persist_wg, chunk = std::max(1, own->queue_chunk);
                 const MultiStk ms{!wide, own->bvh_cur};
                 if (booth) PT_STK_B(&ms, k_recip_multi, true, grid, 64 * RW, own->cap_stream, own->mjobs, n, own->mbase,
-                                    own->mwork, chunk);
+                                    own->mwork, chunk, own->ahead);
                 else PT_STK_B(&ms, k_recip_multi, false, grid, 64 * RW, own->cap_stream, own->mjobs, n, own->mbase,
-                              own->mwork, chunk);
+                              own->mwork, chunk, own->ahead);
                 e = hipGetLastError();
             }
         }
@@ -1643,10 +1647,19 @@ extern "C" pt_status pt_autotune(pt_scene *s, const pt_iter_params *p, float *ac
         if ((st = timed(ms)) == PT_OK && ms < best_c) { best_c = ms; bc = chunks[ci]; }
     }
     s->queue_chunk = bc;
+    // how far a stage-A lane may run ahead of the chain's oldest unconsumed step
+    const int a0 = s->ahead;
+    int ba = a0;
+    float best_a = 3.0e38f;
+    for (int ai = 1; ai <= 2 && st == PT_OK; ++ai) {
+        s->ahead = ai;
+        if ((st = timed(ms)) == PT_OK && ms < best_a) { best_a = ms; ba = ai; }
+    }
+    s->ahead = ba;
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (st != PT_OK) {
-        s->tune_budget = b0; s->tune_gen_grid = g0; s->ext_wg = w0; s->queue_chunk = c0;
+        s->tune_budget = b0; s->tune_gen_grid = g0; s->ext_wg = w0; s->queue_chunk = c0; s->ahead = a0;
         set_width(v0);
         return st;
     }
@@ -1655,8 +1668,9 @@ extern "C" pt_status pt_autotune(pt_scene *s, const pt_iter_params *p, float *ac
     out->round_grid = bg;
     out->ext_wg = bw;
     out->queue_chunk = bc;
+    out->stage_a_ahead = ba;
     out->bvh_width = s->bvh_cur;
-    out->ms_best = std::min(std::min(best, best_s), std::min(best_w, best_c));
+    out->ms_best = std::min(std::min(std::min(best, best_s), std::min(best_w, best_c)), best_a);
     out->ms_previous = dflt;
     out->iterations_rendered = (uint32_t)used;
     return PT_OK;

@@ -87,7 +87,8 @@ class IterStats(ctypes.Structure):
 class TuneResult(ctypes.Structure):
     _fields_ = [("stage_a_budget", ctypes.c_uint32), ("round_grid", ctypes.c_int32), ("ms_best", ctypes.c_float),
                 ("ms_previous", ctypes.c_float), ("iterations_rendered", ctypes.c_uint32),
-                ("ext_wg", ctypes.c_int32), ("queue_chunk", ctypes.c_int32), ("bvh_width", ctypes.c_int32)]
+                ("ext_wg", ctypes.c_int32), ("queue_chunk", ctypes.c_int32), ("bvh_width", ctypes.c_int32),
+                ("stage_a_ahead", ctypes.c_int32)]
 
 
 class Totals(ctypes.Structure):

@@ -436,15 +436,17 @@ def test_multi_scene_graph_and_autotune(gpu):
 def test_scene_in_a_batch_matches_the_scene_alone(gpu):
     """The 64 x 64 glass Cornell box (config 0's scene, every strategy) rendered alone
     (pt_render_iteration, two streams) and as one branch of a three-scene graph (pt_render_scenes,
-    beside two furnaces of other sizes): 16 batches of 256 iterations each, different seeds;
-    standard errors from the batch means (single iterations are heavy-tailed). Per pixel within 4
+    beside two furnaces of other sizes): 64 batches of 64 iterations each, different seeds;
+    standard errors from the batch means (single iterations are heavy-tailed; with 64 batches the
+    z of an unbiased pixel is nearly normal, where 16 batches would give a t law with 15 degrees of
+    freedom, P(|t| > 4) = 1.2e-3, about three of a furnace's 2,304 pixels). Per pixel within 4
     combined standard errors on 99.9 % of pixel channels, relative L1 within 10 % of the noise
     floor; the two furnaces of the batch against their closed form."""
     from synth import scenes
     torch, pt = gpu
     flags = (pt.PT_FLAG_NEE | pt.PT_FLAG_PROXY | pt.PT_FLAG_MIS | pt.PT_FLAG_GAMMA | pt.PT_FLAG_TILES |
              pt.PT_FLAG_SPC | pt.PT_FLAG_LT)
-    NB, PB = 16, 256
+    NB, PB = 64, 64
     N = NB * PB
     prm = dict(max_depth=8, n_light=4096, cand_cap=400, flags=flags)
     specs = [(scenes.cornell_glass(64, 64), 4096, (64, 64), prm),
