@@ -107,6 +107,9 @@ def main():
                          "4.2 M triangles, 285 MB of nodes and triangle records, beyond the 256 MB Infinity Cache)")
     ap.add_argument("--bvh-width", type=int, default=0, choices=(0, 4, 8),
                     help="BVH width of the walks: 4, 8, or 0 to upload both trees and let the autotuner pick")
+    ap.add_argument("--pilot", type=int, default=None,
+                    help="pilot samples per candidate (default 16; 0 takes B and beta from the (class, u, S, C) "
+                         "bucket statistics of earlier iterations alone, Section 5.5)")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="after the run, one device-to-device copy of this many MiB: the reference kernel of "
                          "known size for scaling hardware byte counters")
@@ -130,6 +133,8 @@ def main():
     flags = (pt.PT_FLAG_NEE | pt.PT_FLAG_PROXY | pt.PT_FLAG_MIS | pt.PT_FLAG_GAMMA | pt.PT_FLAG_TILES |
              pt.PT_FLAG_SPC | pt.PT_FLAG_LT)
     params = dict(max_depth=cfg["max_depth"], n_light=cfg["n_light"], cand_cap=cfg["cand_cap"], seed=cfg["seed"])
+    if args.pilot is not None:
+        params["pilot"] = args.pilot
     if cfg.get("mlp"):
         flags |= pt.PT_FLAG_MLP | pt.PT_FLAG_MLP_DIR
         params.update(mlp_mix=cfg["mlp_mix"], mlp_lr=cfg["mlp_lr"], train_iters=cfg["train_iters"])
@@ -214,7 +219,8 @@ def main():
                                   "defensive, trained online) on " if cfg.get("mlp") else "") +
                                f"plain method (PT, NEE, probabilistic connections, light tracing, proxy connections "
                                f"with variance-aware MIS, Gamma, tiles)",
-                   "spp_per_step": 1, "max_depth": params["max_depth"], "n_light": params["n_light"]},
+                   "spp_per_step": 1, "max_depth": params["max_depth"], "n_light": params["n_light"],
+                   "pilot": params.get("pilot", 16)},
         "mrays_per_s": rays * args.steps / dt / 1e6,
         "rays_per_step": rays,
         "ray_breakdown": {k: st[k] for k in ("rays_extend_eye", "rays_extend_light", "rays_shadow", "rays_proxy",
