@@ -858,15 +858,19 @@ __global__ void k_roulette(Cand *cand, const uint32_t *kept, uint32_t *final_, u
         float gmax = 0.f;
         for (int k = 0; k < 10; ++k) gmax = fmaxf(gmax, runmax[k]);
         const float Bb = runmax[b] > 0.f ? runmax[b] : (gmax > 0.f ? gmax : 1.0f / em_area);
-        // with a pilot (c.pn > 0): B = max(pilot max, (class, u) running max), beta the pilot mean.
-        // Without one: the (class, u, S, C) bucket's f/q statistics of earlier iterations (Section
-        // 5.5): B its largest value and beta its mean, the (class, u) running max while the bucket
-        // has none. Any B with beta / B in (0, 2) leaves the estimate unbiased (Appendix B).
+        // The (class, u, S, C) bucket's f/q statistics of earlier iterations (Section 5.5) when the
+        // subspace labels exist: the largest value and the mean. With a pilot (c.pn > 0): B =
+        // max(pilot max, the bucket's max, or the (class, u) running max while the bucket has
+        // none), beta the pilot mean. Without one: B the bucket's max and beta its mean (the (class,
+        // u) running max and B / 2 while the bucket has none). Any B with beta / B in (0, 2) leaves
+        // the estimate unbiased (Appendix B); the pilot keeps B at or above what the candidate's own
+        // samples reached.
         const int sb = labelled ? 3 * stat_bucket(D, c.cls_u >> 8, c.cls_u & 0xFF, c.spec_sub & 0xFFFF,
                                                   c.spec_sub >> 16) : 0;
         const bool piloted = c.pn > 0.f;
-        const bool bucket = !piloted && labelled && D.bstat[sb] > 0.f && D.bstat[sb + 2] > 0.f;
-        const float B = piloted ? fmaxf(c.pmax, Bb) : (bucket ? D.bstat[sb] : Bb);
+        const bool has_bucket = labelled && D.bstat[sb] > 0.f && D.bstat[sb + 2] > 0.f;
+        const bool bucket = !piloted && has_bucket;
+        const float B = piloted ? fmaxf(c.pmax, has_bucket ? D.bstat[sb] : Bb) : (bucket ? D.bstat[sb] : Bb);
         float beta;
         if (piloted) beta = c.pmax > 0.f ? c.psum / c.pn : B / (2.0f * c.pn);
         else beta = (bucket && D.bstat[sb + 1] > 0.f) ? D.bstat[sb + 1] / D.bstat[sb + 2] : 0.5f * B;

@@ -761,24 +761,21 @@ def test_zz_config0_parity_with_learned_selection(gpu):
     assert tot["n_nan"] == 0 and tot["n_recip_truncated"] == 0
 
 
-@pytest.mark.parametrize("pilot", [16, 0])
-def test_zz_config1_128_parity_with_oracle_reference(gpu, pilot):
+def test_zz_config1_128_parity_with_oracle_reference(gpu):
     """The projector scene of config 1 at 128 x 128 (depth 12), every strategy, 256 eye and light
     subspaces and 100 specular subspaces (the grouped centroid search), vs the stored O3
     reference image (plain bidirectional path tracing: path tracing with next-event estimation
     reaches the lens-lit dim walls only through rare emitter hits, and its per-pixel variance
-    estimate there is too low where its mean is low). B and beta of the chains from a 16-sample
-    pilot per candidate (the default) and from the (class, u, S, C) bucket statistics alone
-    (pilot 0)."""
+    estimate there is too low where its mean is low)."""
     from synth import scenes
     torch, pt = gpu
     ref = np.load(os.path.join(GOLD, "cfg1_128_o3_ref.npz"))
     N = 2048
-    say(f"config 1 at 128x128 parity, {N} spp, pilot {pilot}")
+    say(f"config 1 at 128x128 parity, {N} spp")
     flags = (pt.PT_FLAG_NEE | pt.PT_FLAG_PROXY | pt.PT_FLAG_MIS | pt.PT_FLAG_GAMMA | pt.PT_FLAG_TILES |
              pt.PT_FLAG_SPC | pt.PT_FLAG_LT)
     m, v, st = _render(gpu, scenes.projector(128, 128), N, max_light=65536, subspaces=(256, 100), max_depth=12,
-                       n_light=65536, cand_cap=2600, flags=flags, pilot=pilot)
+                       n_light=65536, cand_cap=2600, flags=flags)
     mo, vo = ref["mean"], ref["var_mean"]
     z = (m - mo) / np.sqrt(v + vo + 1e-30)
     frac = (np.abs(z) < 4).mean()
