@@ -144,11 +144,16 @@ def main():
     S.build_subspaces(n_eye=cfg["n_subspaces"], n_spec=cfg["n_spec"])
     acc = torch.zeros(W * H * 3, device="cuda")
     acc2 = torch.zeros_like(acc)
-    # warmup: the reciprocal-chain schedule autotuner (its timed iterations render like any other),
-    # then plain iterations
-    tune = S.autotune(acc, acc2, iteration=0, flags=flags, **params)
+    # warmup: 48 iterations, past the 40 in which Gamma, Q and the tile shares learn (their
+    # statistics, and with them the chains' cost, settle there, and a tuner timing its choices
+    # one after another while the cost still falls would favour whichever it times last); then the
+    # schedule autotuner (its timed iterations render like any other); then plain iterations
+    settle = 48
+    for k in range(settle):
+        S.render_iteration(acc, acc2, iteration=k, flags=flags, **params)
+    tune = S.autotune(acc, acc2, iteration=settle, flags=flags, **params)
     log(f"autotune: {tune}")
-    k0 = tune["iterations_rendered"]
+    k0 = settle + tune["iterations_rendered"]
     for k in range(args.warmup):
         S.render_iteration(acc, acc2, iteration=k0 + k, flags=flags, **params)
     torch.cuda.synchronize()

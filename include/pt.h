@@ -224,7 +224,9 @@ pt_status pt_render_scenes(pt_scene *const *scenes, const pt_iter_params *params
  * does not depend on the tree's width or its workgroup, and the chains consume i.i.d. samples
  * whoever draws them), so it changes speed only. The timed iterations render into accum_rgb /
  * accum_sq (iterations p->iteration, +1, ...); their number is returned in iterations_rendered.
- * Synchronises hip_stream. */
+ * The knobs are timed one after another, so call it once the iteration's cost has settled: after
+ * the first 40 iterations, in which the Gamma, Q and tile statistics learn (while they learn the
+ * cost falls, and the value timed last would look best). Synchronises hip_stream. */
 typedef struct {
     uint32_t stage_a_budget;     /* chosen sample budget of the one-wavefront stage */
     int32_t round_grid;          /* chosen blocks of the round kernels */
