@@ -1120,8 +1120,13 @@ pt_status enqueue_iteration(pt_scene *s, const pt_iter_params *p, float *acc, fl
             const int m = std::min(MLP_CHUNK, np - c0);
             k_mlp_enc_items<<<blocks(m, 256), 256, 0, stream>>>(S, E.proxy, s->cnt, s->mx, c0, m);
             mlp_forward(s, m, s->cnt, C_PROXYQ, s->ml, 0, ns, stream, nullptr, false, c0);
-            k_mlp_select<<<blocks(m, 256), 256, 0, stream>>>(E, D, s->ml, s->mw + o.b4, ns, p->mlp_mix, gamma ? 1 : 0,
-                                                             p->seed, s->cnt, c0, m);
+            // one thread per item over a few subspaces, one wavefront per item over many
+            if (ns > 32)
+                k_mlp_select_wave<<<blocks(m, 4), 256, 0, stream>>>(E, D, s->ml, s->mw + o.b4, ns, p->mlp_mix,
+                                                                    gamma ? 1 : 0, p->seed, s->cnt, c0, m);
+            else
+                k_mlp_select<<<blocks(m, 256), 256, 0, stream>>>(E, D, s->ml, s->mw + o.b4, ns, p->mlp_mix,
+                                                                 gamma ? 1 : 0, p->seed, s->cnt, c0, m);
             if (vmf) {
                 k_mlp_enc_retrace<<<blocks(m, 256), 256, 0, stream>>>(S, E.proxy, s->cand, s->cnt, s->mx, c0, m);
                 mlp_forward(s, m, s->cnt, C_PROXYQ, s->mvmf + (size_t)c0 * MLP_VMF, ns, MLP_VMF, stream,

@@ -566,6 +566,99 @@ __global__ void k_mlp_select(EyeBuf E, SubDev D, const float *L, const float *bi
     }
 }
 
+// The same selection with one wavefront per item, for many subspaces: the lanes read the item's
+// logits row together (coalesced) for the maximum and the sum of the softmax terms, and the
+// inverse CDF walks the row in blocks of 64 with a wavefront prefix sum in double. The draws
+// (the same Philox counters), the probability written out and the choice of the block-ordered
+// cumulative sum crossing the target are those of k_mlp_select up to the order of the double
+// additions; the probability divides by the sum the draw used.
+__device__ __forceinline__ double wave_sum_d(double v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    return v;
+}
+__global__ void __launch_bounds__(256) k_mlp_select_wave(EyeBuf E, SubDev D, const float *L, const float *bias,
+                                                         int n_out, float mix, int gamma_on, uint32_t seed,
+                                                         const unsigned long long *cnt, int off, int M)
+{
+    const int lane = threadIdx.x & 63;
+    const int i = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * 4 + (threadIdx.x >> 6)));   // one item per wave
+    if (i >= M || off + i >= (int)cnt[C_PROXYQ]) return;
+    ProxyItem &it = E.proxy[off + i];
+    const int ne = cnt[C_NFINAL] > 0 ? min(*D.n_nonempty, D.n_spec) : 0;
+    if (ne <= 0) {
+        if (lane == 0) {
+            it.aux.z = __int_as_float(-1); it.aux.w = 0.0f;
+            it.mis.z = __int_as_float(-1); it.mis.w = 0.0f;
+        }
+        return;
+    }
+    const int T = __float_as_int(it.aux.x);
+    const float *l = L + (size_t)i * n_out;
+    Rng r = rng_make(seed, S_MLP, (uint32_t)__float_as_int(it.beta.w), (uint32_t)cnt[C_ITER], 1u);
+    float mx = -3.0e38f;
+    for (int j = lane; j < ne; j += 64) mx = fmaxf(mx, l[D.nonempty[j]] + bias[D.nonempty[j]]);
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) mx = fmaxf(mx, __shfl_xor(mx, o));
+    double part = 0.0;
+    for (int j = lane; j < ne; j += 64) part += (double)__expf(l[D.nonempty[j]] + bias[D.nonempty[j]] - mx);
+    const double sum = wave_sum_d(part);
+    const float u0 = rng_f(r);
+    const uint32_t xa = rng_u32(r), xb = rng_u32(r);
+    int S, jS;
+    if (u0 < mix) {
+        const double u = (double)(((uint64_t)xa << 21) | (uint64_t)(xb >> 11)) * (1.0 / 9007199254740992.0);
+        const double target = u * sum;
+        double base = 0.0;
+        int last = -1;   // the last index with a non-zero term so far (the draw when rounding leaves no crossing)
+        jS = -1;
+        for (int b = 0; b < ne && jS < 0; b += 64) {
+            const int j = b + lane;
+            const double e = j < ne ? (double)__expf(l[D.nonempty[j]] + bias[D.nonempty[j]] - mx) : 0.0;
+            double c = e;   // inclusive prefix sum over the block
+#pragma unroll
+            for (int o = 1; o < 64; o <<= 1) {
+                const double t = __shfl_up(c, o);
+                if (lane >= o) c += t;
+            }
+            const unsigned long long cross = __ballot(e > 0.0 && target < base + c);
+            if (cross) {
+                jS = b + __ffsll((long long)cross) - 1;
+            } else {
+                const unsigned long long nz = __ballot(e > 0.0);
+                if (nz) last = b + 63 - __clzll((long long)nz);
+                base += __shfl(c, 63);
+            }
+        }
+        if (jS < 0) jS = last >= 0 ? last : 0;
+        S = D.nonempty[jS];
+    } else if (gamma_on) {
+        const size_t row = (size_t)T * D.n_spec;
+        jS = alias_draw(D.al_prob + row, D.al_idx + row, ne, xa, (float)(xb >> 8) * (1.0f / 16777216.0f));
+        S = D.nonempty[jS];
+    } else {
+        jS = index_of(xa, ne);
+        S = D.nonempty[jS];
+    }
+    if (lane != 0) return;
+    const double learned = (double)__expf(l[S] + bias[S] - mx) / sum;
+    const double plain = gamma_on ? (double)sel_prob(D, T, S) : index_prob(jS, ne);
+    const double m = below_prob(mix);
+    const double piS = m * learned + (1.0 - m) * plain;
+    it.aux.z = __int_as_float(S);
+    it.aux.w = (float)piS;
+    const int cs = D.s_count[S];
+    if (cs > 0) {
+        const int k = index_of(rng_u32(r), cs);
+        it.mis.z = __int_as_float(D.s_list[D.s_off[S] + k]);
+        it.mis.w = (float)(piS * index_prob(k, cs));
+    } else {
+        it.mis.z = __int_as_float(-1);
+        it.mis.w = 0.0f;
+    }
+}
+
 // Training samples of a learning iteration, one per valid proxy contribution: for the subspace
 // head the features of the first diffuse eye vertex, the selected subspace and the
 // contribution's luminance as weight; for the direction head the features of y_{s-1} (direction
