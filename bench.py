@@ -243,6 +243,7 @@ def main():
         "schedule": {"stage_a_budget": tune["stage_a_budget"], "round_grid": tune["round_grid"],
                      "bvh_width": tune["bvh_width"], "extension_workgroup": tune["ext_wg"],
                      "queue_chunk": tune["queue_chunk"], "stage_a_ahead": tune["stage_a_ahead"],
+                     "stage_a_refill": tune["stage_a_refill"],
                      "autotune_iterations": k0, "ms_tuned": tune["ms_best"],
                      "ms_default": tune["ms_previous"]},
         "roofline": {"kernel": f"{dom['kernel']} ({dom['what']})", "bound": "hbm", "achieved": achieved,

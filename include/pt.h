@@ -220,7 +220,9 @@ pt_status pt_render_scenes(pt_scene *const *scenes, const pt_iter_params *params
  * of the one-wavefront stage takes from its work queue per visit (1, 2, 4; also used by the
  * multi-scene stage of pt_render_scenes); how many steps of 64 samples a lane of that stage may
  * compute beyond the oldest step its chain has not consumed (1: lockstep; 2: a lane whose sample
- * ended early starts the next while the others still trace). Every choice gives the same estimator (a ray's hit
+ * ended early starts the next while the others still trace); whether that stage walks the tree
+ * one node at a time and restarts a lane whose walk ended (its next trip or next sample) while
+ * the others still walk (4-wide trees). Every choice gives the same estimator (a ray's hit
  * does not depend on the tree's width or its workgroup, and the chains consume i.i.d. samples
  * whoever draws them), so it changes speed only. The timed iterations render into accum_rgb /
  * accum_sq (iterations p->iteration, +1, ...); their number is returned in iterations_rendered.
@@ -237,9 +239,19 @@ typedef struct {
     int32_t queue_chunk;         /* chosen chains per take from stage A's work queue */
     int32_t bvh_width;           /* BVH width the walks use from now on (4 or 8) */
     int32_t stage_a_ahead;       /* chosen look-ahead of the one-wavefront stage (1 or 2 steps) */
+    int32_t stage_a_refill;      /* 1: that stage refills its walks node by node (4-wide trees) */
 } pt_tune_result;
 pt_status pt_autotune(pt_scene *s, const pt_iter_params *p, float *accum_rgb_dev, float *accum_sq_dev,
                       pt_tune_result *out, void *hip_stream);
+
+/* Set the schedule knobs pt_autotune chooses (the fields of pt_tune_result other than the
+ * timings and iteration count), e.g. to reuse one tuning on scenes of the same kind or to fix a
+ * schedule. Every schedule gives the same estimator. PT_EINVAL for a value out of range,
+ * PT_EUNSUPPORTED for a BVH width the scene holds no tree of. Advances the scene's state
+ * generation (a captured graph is re-captured). */
+pt_status pt_set_schedule(pt_scene *s, const pt_tune_result *knobs);
+/* The scene's current schedule knobs (timings and iteration count zero). */
+pt_status pt_get_schedule(const pt_scene *s, pt_tune_result *knobs);
 
 /* Learned proposal of the proxy strategy (PT_FLAG_MLP, PT_FLAG_MLP_DIR). Not part of the paper's
  * method: it replaces the Gamma row of Section 5.6 by a network's softmax mixed with that row

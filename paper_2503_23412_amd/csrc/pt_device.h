@@ -485,6 +485,125 @@ __device__ __forceinline__ bool traverse8_rt(const SceneDev &S, float3 o, float3
     return h.tri >= 0;
 }
 
+// One walk of the 4-wide tree in progress: the ray, its reciprocal direction, the nearest hit so
+// far, the node to visit next and the depth of the lane's stack. walk_step visits one node, so a
+// kernel can interleave the walks of its lanes with other work (a lane whose walk ended can start
+// another while the others still walk); traverse_rt runs walk_step to the end.
+struct Walk {
+    float3 o, d, inv, oi;
+    float tmin, tmax;
+    int ign0, ign1;
+    bool any;
+    int node, sp;
+    Hit h;
+};
+__device__ __forceinline__ void walk_begin(Walk &w, float3 o, float3 d, float tmin, float tmax, int ign0, int ign1,
+                                           bool any)
+{
+    w.o = o; w.d = d;
+    w.inv = f3(1.0f / d.x, 1.0f / d.y, 1.0f / d.z);
+    w.oi = o * w.inv;
+    w.tmin = tmin; w.tmax = tmax; w.ign0 = ign0; w.ign1 = ign1; w.any = any;
+    w.node = 0; w.sp = 0;
+    w.h.tri = -1; w.h.t = tmax; w.h.b1 = w.h.b2 = 0.0f;
+}
+// visit w.node: true when the walk has ended (w.h holds the nearest hit, tri -1 for none; with
+// `any` the first hit found)
+template <bool COUNT, typename SE>
+__device__ __forceinline__ bool walk_step(const SceneDev &S, Walk &w, SE *stk, int stride, uint32_t *visits,
+                                          uint32_t *tests, uint32_t *wave_trips)
+{
+    const BNode &N = S.nodes[w.node];
+    if (COUNT) {
+        (*visits)++;
+        // loop trips of the wavefront (counted by its first active lane): node visits over
+        // 64 x trips is the SIMD efficiency of the traversal
+        if (wave_trips && __lane_id() == __ffsll((long long)__ballot(1)) - 1) (*wave_trips)++;
+    }
+    // slab tests of the four children
+    const float4 lx = *(const float4 *)N.lo_x, hx = *(const float4 *)N.hi_x;
+    const float4 ly = *(const float4 *)N.lo_y, hy = *(const float4 *)N.hi_y;
+    const float4 lz = *(const float4 *)N.lo_z, hz = *(const float4 *)N.hi_z;
+    const int4 ch = *(const int4 *)N.child;
+    const int4 cn = *(const int4 *)N.count;
+    float tn[4];
+    bool hitc[4];
+    const float lxa[4] = {lx.x, lx.y, lx.z, lx.w}, hxa[4] = {hx.x, hx.y, hx.z, hx.w};
+    const float lya[4] = {ly.x, ly.y, ly.z, ly.w}, hya[4] = {hy.x, hy.y, hy.z, hy.w};
+    const float lza[4] = {lz.x, lz.y, lz.z, lz.w}, hza[4] = {hz.x, hz.y, hz.z, hz.w};
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const float ax = lxa[k] * w.inv.x - w.oi.x, bx = hxa[k] * w.inv.x - w.oi.x;
+        const float ay = lya[k] * w.inv.y - w.oi.y, by = hya[k] * w.inv.y - w.oi.y;
+        const float az = lza[k] * w.inv.z - w.oi.z, bz = hza[k] * w.inv.z - w.oi.z;
+        const float t0 = fmaxf(fmaxf(fminf(ax, bx), fminf(ay, by)), fmaxf(fminf(az, bz), 0.0f));
+        const float t1 = fminf(fminf(fmaxf(ax, bx), fmaxf(ay, by)), fminf(fmaxf(az, bz), w.h.t));
+        hitc[k] = t0 <= t1 * 1.00000024f;
+        tn[k] = t0;
+    }
+    const int cha[4] = {ch.x, ch.y, ch.z, ch.w}, cna[4] = {cn.x, cn.y, cn.z, cn.w};
+    // leaves: test their triangles now, as one run over the hit leaves' triangles, so that a
+    // wavefront's lanes step through their leaves together whichever children they are
+    int e[4];
+    int ntot = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        ntot += (hitc[k] && cna[k] > 0) ? cna[k] : 0;
+        e[k] = ntot;   // end of child k's triangles in the run
+    }
+    for (int j = 0; j < ntot; ++j) {
+        const int i = j < e[0] ? cha[0] + j
+                    : j < e[1] ? cha[1] + (j - e[0])
+                    : j < e[2] ? cha[2] + (j - e[1])
+                               : cha[3] + (j - e[2]);
+        const TriIsect &T = S.tris[i];
+        if (COUNT) (*tests)++;
+        const int pid = T.prim;
+        if (i == w.ign0 || i == w.ign1) continue;
+        float t, b1, b2;
+        if (isect(T, w.o, w.d, w.tmin, w.tmax, t, b1, b2)) {
+            if (t < w.h.t || (t == w.h.t && w.h.tri >= 0 && pid < S.tris[w.h.tri].prim)) {
+                w.h.t = t; w.h.b1 = b1; w.h.b2 = b2; w.h.tri = i;
+                if (w.any) return true;
+            }
+        }
+    }
+    // inner children still in front of the nearest hit, sorted by entry distance with a
+    // five-comparator network in registers (children that are not taken sort last)
+    float key[4];
+    int cid[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const bool take = hitc[k] && cna[k] == 0 && cha[k] >= 0 && tn[k] <= w.h.t;
+        key[k] = take ? tn[k] : 3.0e38f;
+        cid[k] = take ? cha[k] : -1;
+    }
+#define PT_CSWAP(a, b)                                                                     \
+    {                                                                                      \
+        const bool sw = key[b] < key[a];                                                   \
+        const float ka = key[a], kb = key[b];                                              \
+        const int ca = cid[a], cb = cid[b];                                                \
+        key[a] = sw ? kb : ka; key[b] = sw ? ka : kb;                                      \
+        cid[a] = sw ? cb : ca; cid[b] = sw ? ca : cb;                                      \
+    }
+    PT_CSWAP(0, 1) PT_CSWAP(2, 3) PT_CSWAP(0, 2) PT_CSWAP(1, 3) PT_CSWAP(1, 2)
+#undef PT_CSWAP
+    // the nearest child continues in a register, the others are pushed far to near. The
+    // stack holds PT_STACK entries, and pt_scene_upload rejects a tree whose worst-case walk
+    // (the largest sum over a root-to-leaf path of inner children less one) needs more, so
+    // the bound below only keeps a malformed tree from writing past the stack
+    if (cid[0] >= 0) {
+#pragma unroll
+        for (int k = 3; k >= 1; --k)
+            if (cid[k] >= 0 && w.sp < stk_depth<SE>()) stk_at(stk, w.sp++, stride) = (SE)cid[k];
+        w.node = cid[0];
+        return false;
+    }
+    if (w.sp == 0) return true;
+    w.node = stk_node(stk_at(stk, --w.sp, stride));
+    return false;
+}
+
 // `any` ends the walk at the first hit (visibility); it is a run-time argument so that a kernel
 // can trace visibility and closest-hit rays at one call site, and constant-folds where the
 // caller passes a constant. Stacks of int16_t or uint32_t entries walk the 8-wide tree.
@@ -494,104 +613,16 @@ __device__ __forceinline__ bool traverse_rt(const SceneDev &S, float3 o, float3 
                                             uint32_t *visits = nullptr, uint32_t *tests = nullptr,
                                             uint32_t *wave_trips = nullptr)
 {
-    if constexpr (stk_wide8<SE>::value)
+    if constexpr (stk_wide8<SE>::value) {
         return traverse8_rt<COUNT>(S, o, d, tmin, tmax, ign0, ign1, any, stk, stride, h, visits, tests, wave_trips);
-    const float3 inv = f3(1.0f / d.x, 1.0f / d.y, 1.0f / d.z);
-    const float3 oi = o * inv;
-    h.tri = -1; h.t = tmax;
-    int sp = 0;
-    int node = 0;
-    for (;;) {
-        const BNode &N = S.nodes[node];
-        if (COUNT) {
-            (*visits)++;
-            // loop trips of the wavefront (counted by its first active lane): node visits over
-            // 64 x trips is the SIMD efficiency of the traversal
-            if (wave_trips && __lane_id() == __ffsll((long long)__ballot(1)) - 1) (*wave_trips)++;
+    } else {
+        Walk w;
+        walk_begin(w, o, d, tmin, tmax, ign0, ign1, any);
+        while (!walk_step<COUNT>(S, w, stk, stride, visits, tests, wave_trips)) {
         }
-        // slab tests of the four children
-        const float4 lx = *(const float4 *)N.lo_x, hx = *(const float4 *)N.hi_x;
-        const float4 ly = *(const float4 *)N.lo_y, hy = *(const float4 *)N.hi_y;
-        const float4 lz = *(const float4 *)N.lo_z, hz = *(const float4 *)N.hi_z;
-        const int4 ch = *(const int4 *)N.child;
-        const int4 cn = *(const int4 *)N.count;
-        float tn[4];
-        bool hitc[4];
-        const float lxa[4] = {lx.x, lx.y, lx.z, lx.w}, hxa[4] = {hx.x, hx.y, hx.z, hx.w};
-        const float lya[4] = {ly.x, ly.y, ly.z, ly.w}, hya[4] = {hy.x, hy.y, hy.z, hy.w};
-        const float lza[4] = {lz.x, lz.y, lz.z, lz.w}, hza[4] = {hz.x, hz.y, hz.z, hz.w};
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            const float ax = lxa[k] * inv.x - oi.x, bx = hxa[k] * inv.x - oi.x;
-            const float ay = lya[k] * inv.y - oi.y, by = hya[k] * inv.y - oi.y;
-            const float az = lza[k] * inv.z - oi.z, bz = hza[k] * inv.z - oi.z;
-            const float t0 = fmaxf(fmaxf(fminf(ax, bx), fminf(ay, by)), fmaxf(fminf(az, bz), 0.0f));
-            const float t1 = fminf(fminf(fmaxf(ax, bx), fmaxf(ay, by)), fminf(fmaxf(az, bz), h.t));
-            hitc[k] = t0 <= t1 * 1.00000024f;
-            tn[k] = t0;
-        }
-        const int cha[4] = {ch.x, ch.y, ch.z, ch.w}, cna[4] = {cn.x, cn.y, cn.z, cn.w};
-        // leaves: test their triangles now, as one run over the hit leaves' triangles, so that a
-        // wavefront's lanes step through their leaves together whichever children they are
-        int e[4];
-        int ntot = 0;
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            ntot += (hitc[k] && cna[k] > 0) ? cna[k] : 0;
-            e[k] = ntot;   // end of child k's triangles in the run
-        }
-        for (int j = 0; j < ntot; ++j) {
-            const int i = j < e[0] ? cha[0] + j
-                        : j < e[1] ? cha[1] + (j - e[0])
-                        : j < e[2] ? cha[2] + (j - e[1])
-                                   : cha[3] + (j - e[2]);
-            const TriIsect &T = S.tris[i];
-            if (COUNT) (*tests)++;
-            const int pid = T.prim;
-            if (i == ign0 || i == ign1) continue;
-            float t, b1, b2;
-            if (isect(T, o, d, tmin, tmax, t, b1, b2)) {
-                if (t < h.t || (t == h.t && h.tri >= 0 && pid < S.tris[h.tri].prim)) {
-                    h.t = t; h.b1 = b1; h.b2 = b2; h.tri = i;
-                    if (any) return true;
-                }
-            }
-        }
-        // inner children still in front of the nearest hit, sorted by entry distance with a
-        // five-comparator network in registers (children that are not taken sort last)
-        float key[4];
-        int cid[4];
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            const bool take = hitc[k] && cna[k] == 0 && cha[k] >= 0 && tn[k] <= h.t;
-            key[k] = take ? tn[k] : 3.0e38f;
-            cid[k] = take ? cha[k] : -1;
-        }
-#define PT_CSWAP(a, b)                                                                     \
-        {                                                                                  \
-            const bool sw = key[b] < key[a];                                               \
-            const float ka = key[a], kb = key[b];                                          \
-            const int ca = cid[a], cb = cid[b];                                            \
-            key[a] = sw ? kb : ka; key[b] = sw ? ka : kb;                                  \
-            cid[a] = sw ? cb : ca; cid[b] = sw ? ca : cb;                                  \
-        }
-        PT_CSWAP(0, 1) PT_CSWAP(2, 3) PT_CSWAP(0, 2) PT_CSWAP(1, 3) PT_CSWAP(1, 2)
-#undef PT_CSWAP
-        // the nearest child continues in a register, the others are pushed far to near. The
-        // stack holds PT_STACK entries, and pt_scene_upload rejects a tree whose worst-case walk
-        // (the largest sum over a root-to-leaf path of inner children less one) needs more, so
-        // the bound below only keeps a malformed tree from writing past the stack
-        if (cid[0] >= 0) {
-#pragma unroll
-            for (int k = 3; k >= 1; --k)
-                if (cid[k] >= 0 && sp < stk_depth<SE>()) stk_at(stk, sp++, stride) = (SE)cid[k];
-            node = cid[0];
-        } else {
-            if (sp == 0) break;
-            node = stk_node(stk_at(stk, --sp, stride));
-        }
+        h = w.h;
+        return h.tri >= 0;
     }
-    return h.tri >= 0;
 }
 
 template <bool ANY, bool COUNT, typename SE>

@@ -1185,10 +1185,112 @@ __device__ __forceinline__ void stage_a_chain(CtxT<SE> &C, Cand *cand, const uin
     }
 }
 
+// Stage A of one chain with walks refilled node by node (4-wide trees): the lanes walk one node
+// at a time while at least PT_REFILL_MIN of them still walk; then every lane whose walk ended
+// advances its sample and, if the sample goes on, starts the walk of its next trip, or, if it is
+// complete, starts its next sample within the look-ahead; then the chain consumes the complete
+// steps. So a lane whose ray ended early starts more work instead of waiting for the longest walk
+// of the wavefront. The samples, their counters and the order of consumption are those of
+// stage_a_chain.
+#ifndef PT_REFILL_MIN
+#define PT_REFILL_MIN 40
+#endif
+template <typename SE, bool BOOTH>
+__device__ __forceinline__ void stage_a_chain_refill(CtxT<SE> &C, Cand *cand, const uint32_t *final_,
+                                                     const uint32_t *order, int wave, int repeats, uint32_t seed,
+                                                     uint32_t iter, uint32_t n1, uint32_t budget, float *runmax,
+                                                     ChainState *longq, float booth_r, unsigned long long *cnt,
+                                                     int lane, int ahead, uint32_t &ns, uint32_t &drawn)
+{
+    const uint32_t ci = final_[order[wave / repeats]];
+    const uint32_t chain = ci * 8u + (uint32_t)(wave % repeats);
+    Cand &c = cand[ci];
+    const float invB = 1.0f / c.B;
+    ChainRun st{1.0, 1.0f, 1u, 0u, 0u, n1, 0u, true, 1.0f, 1.0f};
+    float mx = 0.0f, fs = 0.0f;
+    uint32_t nd = 0;
+    const FqCand K = fq_cand(C.S, c);
+    const int smax = (int)((budget + 63u) / 64u);
+    ahead = min(max(ahead, 1), 2);
+    int t = 0, head = 0;
+    Rng r = rng_make(seed, S_RECIP, chain, iter, (uint32_t)lane);
+    FqState s;
+    fq_begin(C.S, K, r, s);
+    Walk w;
+    walk_begin(w, s.ro, s.rd, C.S.tmin, s.rmax, s.ig0, s.ig1, s.any);
+    C.rays++;
+    bool walking = true, busy = true;   // a ray in flight; a sample in flight
+    float v0 = 0.0f, v1 = 0.0f;
+    while (st.alive && st.pos + st.neg > 0 && st.ns < budget && head < smax) {
+        do {
+            if (walking && walk_step<true>(C.S, w, C.stk, C.stride, &C.visits, &C.tests, &C.trips)) walking = false;
+        } while (__popcll(__ballot(walking)) >= PT_REFILL_MIN);
+        if (busy && !walking) {
+            float fq;
+            if (fq_advance(C.S, K, r, s, w.h.tri >= 0, w.h, fq)) {
+                v0 = (t & 1) == 0 ? fq : v0;
+                v1 = (t & 1) == 1 ? fq : v1;
+                ++t;
+                busy = false;
+            } else {
+                walk_begin(w, s.ro, s.rd, C.S.tmin, s.rmax, s.ig0, s.ig1, s.any);
+                C.rays++;
+                walking = true;
+            }
+        }
+        if (!busy && t < smax && t < head + ahead) {
+            r = rng_make(seed, S_RECIP, chain, iter, (uint32_t)(t * 64 + lane));
+            fq_begin(C.S, K, r, s);
+            walk_begin(w, s.ro, s.rd, C.S.tmin, s.rmax, s.ig0, s.ig1, s.any);
+            C.rays++;
+            walking = true;
+            busy = true;
+        }
+        while (st.alive && st.pos + st.neg > 0 && st.ns < budget && head < smax && __ballot(t <= head) == 0ull) {
+            const float fq = (head & 1) == 0 ? v0 : v1;
+            Rng ru = rng_make(seed, S_RECIP, chain, iter, CHAIN_UNI + (uint32_t)(head * 64 + lane));
+            const float uu = rng_f(ru);
+            float smx = fq, ssum = fq;
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) {
+                smx = fmaxf(smx, __shfl_xor(smx, off));
+                ssum += __shfl_xor(ssum, off);
+            }
+            mx = fmaxf(mx, uni_f(smx));
+            fs += uni_f(ssum);
+            nd += 64u;
+            chain_consume(fq, uu, 64, invB, st, seed, chain, iter, BOOTH ? booth_r : 0.0f);
+            ++head;
+        }
+    }
+    drawn += (uint32_t)t;
+    if (lane == 0 && nd > 0) {
+        unsafeAtomicAdd(&c.psum, fs);
+        unsafeAtomicAdd(&c.pn, (float)nd);
+    }
+    ns += st.ns;
+    if (lane == 0) {
+        const bool running = st.alive && st.pos + st.neg > 0;
+        int slot = -1;
+        if (running) {
+            slot = (int)atomicAdd(cnt + C_LONGQ0, 1ull);
+            if (slot >= CHAIN_LIST_CAP) slot = -1;
+        }
+        if (slot >= 0) {
+            ChainState q{ci, chain, st.ans, st.weight, mx, st.pos, st.neg, st.ns, st.next_flip, st.coin,
+                         st.bprod, st.bw};
+            longq[slot] = q;
+        } else {
+            if (running) atomicAdd(cnt + C_RECIP_TRUNC, 1ull);
+            chain_finish(c, st, running, mx, runmax, cnt);
+        }
+    }
+}
+
 // stage A over one scene's chains: a persistent grid whose wavefronts take the next chains from a
 // device counter; BOOTH selects Booth's roulette (booth_r) at compile time, so that the default
 // instance carries none of its state
-template <typename SE, bool BOOTH = false>
+template <typename SE, bool BOOTH = false, bool REFILL = false>
 __global__ void __launch_bounds__(64 * RW, PT_RECIP_WAVES) k_recip(SceneDev S, Cand *cand, const uint32_t *final_,
                                                    const uint32_t *order, int repeats,
                                                    uint32_t seed, uint32_t n1, uint32_t budget, float *runmax,
@@ -1203,9 +1305,14 @@ __global__ void __launch_bounds__(64 * RW, PT_RECIP_WAVES) k_recip(SceneDev S, C
     uint32_t ns = 0, drawn = 0;
     // chunk consecutive chains per take from the counter (wave-uniform)
     for (int w0 = next_item(cnt + C_WORK_A) * chunk; w0 < n; w0 = next_item(cnt + C_WORK_A) * chunk)
-        for (int wave = w0; wave < min(w0 + chunk, n); ++wave)
-            stage_a_chain<SE, BOOTH>(C, cand, final_, order, wave, repeats, seed, iter, n1, budget, runmax, longq,
-                                     booth_r, cnt, lane, ahead, ns, drawn);
+        for (int wave = w0; wave < min(w0 + chunk, n); ++wave) {
+            if constexpr (REFILL && !stk_wide8<SE>::value)
+                stage_a_chain_refill<SE, BOOTH>(C, cand, final_, order, wave, repeats, seed, iter, n1, budget, runmax,
+                                                longq, booth_r, cnt, lane, ahead, ns, drawn);
+            else
+                stage_a_chain<SE, BOOTH>(C, cand, final_, order, wave, repeats, seed, iter, n1, budget, runmax, longq,
+                                         booth_r, cnt, lane, ahead, ns, drawn);
+        }
     wave_count(cnt + C_RECIP_SAMPLES, lane == 0 ? ns : 0u);
     wave_count(cnt + C_SAMPLES_A, lane == 0 ? ns : 0u);
     wave_count(cnt + C_DRAWN_A, drawn);

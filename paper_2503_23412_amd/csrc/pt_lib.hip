@@ -217,6 +217,7 @@ struct pt_scene {
     // workgroup size of the extension (closest-hit) launches (pt_autotune: 64, 128 or 256)
     int ext_wg = 128;
     int ahead = 2;   // steps a stage-A lane may compute beyond the oldest unconsumed one (1 or 2)
+    int refill = 0;  // stage A refills its walks node by node (4-wide trees)
     // the chain kernels keep 16-bit traversal stack entries when the tree has fewer than 65,536 nodes
     bool stk16 = false;
     // BVH widths available to the walks, and the one in use (S.nodes8 set when it is 8)
@@ -1070,6 +1071,16 @@ pt_status enqueue_iteration(pt_scene *s, const pt_iter_params *p, float *acc, fl
                                                  p->recip_repeats, p->seed, n1, s->tune_budget, s->runmax, s->chq[0],
                                                  booth_r, s->cnt, s->queue_chunk, s->ahead);
                 }
+            } else if (s->refill && s->bvh_cur == 4) {
+                // walks refilled node by node (4-wide trees)
+                if (s->stk16)
+                    k_recip<uint16_t, false, true><<<s->persist_wg, 64 * RW, 0, stream>>>(
+                        S, s->cand, s->final_, s->order, p->recip_repeats, p->seed, n1, s->tune_budget, s->runmax,
+                        s->chq[0], booth_r, s->cnt, s->queue_chunk, s->ahead);
+                else
+                    k_recip<int, false, true><<<s->persist_wg, 64 * RW, 0, stream>>>(
+                        S, s->cand, s->final_, s->order, p->recip_repeats, p->seed, n1, s->tune_budget, s->runmax,
+                        s->chq[0], booth_r, s->cnt, s->queue_chunk, s->ahead);
             } else {
                 PT_STK(s, k_recip, s->persist_wg, 64 * RW, stream, S, s->cand, s->final_, s->order, p->recip_repeats,
                        p->seed, n1, s->tune_budget, s->runmax, s->chq[0], booth_r, s->cnt, s->queue_chunk, s->ahead);
@@ -1242,6 +1253,7 @@ extern "C" pt_status pt_render_batch(pt_scene *s, const pt_iter_params *p, uint3
     k.insert(k.end(), (const char *)&s->ext_wg, (const char *)&s->ext_wg + sizeof(s->ext_wg));
     k.insert(k.end(), (const char *)&s->queue_chunk, (const char *)&s->queue_chunk + sizeof(s->queue_chunk));
     k.insert(k.end(), (const char *)&s->ahead, (const char *)&s->ahead + sizeof(s->ahead));
+    k.insert(k.end(), (const char *)&s->refill, (const char *)&s->refill + sizeof(s->refill));
     if (!s->gexec || k != s->gkey) {
         ++s->n_captures;
         if (s->gexec) { HIPCHK(hipGraphExecDestroy(s->gexec)); s->gexec = nullptr; }
@@ -1477,6 +1489,7 @@ extern "C" pt_status pt_render_scenes(pt_scene *const *scenes, const pt_iter_par
         k.insert(k.end(), (const char *)&sp->queue_chunk, (const char *)&sp->queue_chunk + sizeof(int));
         k.insert(k.end(), (const char *)&sp->ext_wg, (const char *)&sp->ext_wg + sizeof(int));
         k.insert(k.end(), (const char *)&sp->ahead, (const char *)&sp->ahead + sizeof(int));
+        k.insert(k.end(), (const char *)&sp->refill, (const char *)&sp->refill + sizeof(int));
     }
     if (!own->mgexec || k != own->mgkey) {
         ++own->n_captures;
@@ -1574,6 +1587,46 @@ extern "C" pt_status pt_render_scenes(pt_scene *const *scenes, const pt_iter_par
     return PT_OK;
 }
 
+extern "C" pt_status pt_get_schedule(const pt_scene *s, pt_tune_result *k)
+{
+    if (!s || !k) return set_err(PT_EINVAL, "null argument");
+    *k = pt_tune_result{};
+    k->stage_a_budget = s->tune_budget;
+    k->round_grid = s->tune_gen_grid;
+    k->ext_wg = s->ext_wg;
+    k->queue_chunk = s->queue_chunk;
+    k->bvh_width = s->bvh_cur;
+    k->stage_a_ahead = s->ahead;
+    k->stage_a_refill = s->refill;
+    return PT_OK;
+}
+
+extern "C" pt_status pt_set_schedule(pt_scene *s, const pt_tune_result *k)
+{
+    if (!s || !k) return set_err(PT_EINVAL, "null argument");
+    const uint32_t b = k->stage_a_budget;
+    if (b < 64u || b > (1u << 20)) return set_err(PT_EINVAL, "stage_a_budget %u out of range", b);
+    if (k->round_grid < 64 || k->round_grid > 65536) return set_err(PT_EINVAL, "round_grid %d out of range", k->round_grid);
+    if (k->ext_wg != 64 && k->ext_wg != 128 && k->ext_wg != 256) return set_err(PT_EINVAL, "ext_wg must be 64, 128 or 256");
+    if (k->queue_chunk < 1 || k->queue_chunk > 64) return set_err(PT_EINVAL, "queue_chunk %d out of range", k->queue_chunk);
+    if (k->stage_a_ahead < 1 || k->stage_a_ahead > 2) return set_err(PT_EINVAL, "stage_a_ahead must be 1 or 2");
+    if (k->stage_a_refill != 0 && k->stage_a_refill != 1) return set_err(PT_EINVAL, "stage_a_refill must be 0 or 1");
+    if (k->bvh_width != 4 && k->bvh_width != 8) return set_err(PT_EINVAL, "bvh_width must be 4 or 8");
+    if ((k->bvh_width == 4 && !s->has4) || (k->bvh_width == 8 && !s->has8))
+        return set_err(PT_EUNSUPPORTED, "the scene holds no %d-wide tree", k->bvh_width);
+    s->tune_budget = b;
+    s->tune_gen_grid = k->round_grid;
+    s->ext_wg = k->ext_wg;
+    s->queue_chunk = k->queue_chunk;
+    s->ahead = k->stage_a_ahead;
+    s->refill = k->stage_a_refill;
+    s->bvh_cur = k->bvh_width;
+    s->stack_need = s->bvh_cur == 8 ? s->stack_need8 : s->stack_need4;
+    s->bvh_depth = s->bvh_cur == 8 ? s->bvh_depth8 : s->bvh_depth4;
+    s->gen = next_generation();
+    return PT_OK;
+}
+
 extern "C" pt_status pt_autotune(pt_scene *s, const pt_iter_params *p, float *acc, float *acc2, pt_tune_result *out,
                                  void *stream_)
 {
@@ -1661,10 +1714,20 @@ extern "C" pt_status pt_autotune(pt_scene *s, const pt_iter_params *p, float *ac
         if ((st = timed(ms)) == PT_OK && ms < best_a) { best_a = ms; ba = ai; }
     }
     s->ahead = ba;
+    // and whether stage A refills its walks node by node (4-wide trees only)
+    const int r0 = s->refill;
+    int br = r0;
+    float best_r = 3.0e38f;
+    for (int ri = 0; ri <= (s->bvh_cur == 4 ? 1 : 0) && st == PT_OK; ++ri) {
+        s->refill = ri;
+        if ((st = timed(ms)) == PT_OK && ms < best_r) { best_r = ms; br = ri; }
+    }
+    s->refill = br;
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (st != PT_OK) {
         s->tune_budget = b0; s->tune_gen_grid = g0; s->ext_wg = w0; s->queue_chunk = c0; s->ahead = a0;
+        s->refill = r0;
         set_width(v0);
         return st;
     }
@@ -1674,8 +1737,9 @@ extern "C" pt_status pt_autotune(pt_scene *s, const pt_iter_params *p, float *ac
     out->ext_wg = bw;
     out->queue_chunk = bc;
     out->stage_a_ahead = ba;
+    out->stage_a_refill = br;
     out->bvh_width = s->bvh_cur;
-    out->ms_best = std::min(std::min(std::min(best, best_s), std::min(best_w, best_c)), best_a);
+    out->ms_best = std::min(std::min(std::min(best, best_s), std::min(best_w, best_c)), std::min(best_a, best_r));
     out->ms_previous = dflt;
     out->iterations_rendered = (uint32_t)used;
     return PT_OK;

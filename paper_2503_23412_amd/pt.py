@@ -33,7 +33,7 @@ PT_EST_SIGN = 1
 PT_EST_BOOTH = 2
 
 EXPORTED = ["pt_scene_upload", "pt_scene_release", "pt_build_subspaces", "pt_render_iteration", "pt_render_batch",
-            "pt_render_scenes", "pt_autotune",
+            "pt_render_scenes", "pt_autotune", "pt_set_schedule", "pt_get_schedule",
             "pt_mlp_param_count", "pt_mlp_set_params", "pt_mlp_get_params", "pt_mlp_forward", "pt_mlp_train_step",
             "pt_reciprocal_estimate", "pt_resolve_image", "pt_trace_closest", "pt_scene_totals",
             "pt_selection_tables", "pt_iteration_times", "pt_philox", "pt_bvh_stats", "pt_reciprocal_estimate_noalloc",
@@ -88,7 +88,7 @@ class TuneResult(ctypes.Structure):
     _fields_ = [("stage_a_budget", ctypes.c_uint32), ("round_grid", ctypes.c_int32), ("ms_best", ctypes.c_float),
                 ("ms_previous", ctypes.c_float), ("iterations_rendered", ctypes.c_uint32),
                 ("ext_wg", ctypes.c_int32), ("queue_chunk", ctypes.c_int32), ("bvh_width", ctypes.c_int32),
-                ("stage_a_ahead", ctypes.c_int32)]
+                ("stage_a_ahead", ctypes.c_int32), ("stage_a_refill", ctypes.c_int32)]
 
 
 class Totals(ctypes.Structure):
@@ -132,6 +132,8 @@ def lib():
         L.pt_trace_closest.argtypes = [P, P, I, P, P, P]
         L.pt_render_scenes.argtypes = [P, P, I, ctypes.c_uint32, P, P, P]
         L.pt_autotune.argtypes = [P, ctypes.POINTER(IterParams), P, P, ctypes.POINTER(TuneResult), P]
+        L.pt_set_schedule.argtypes = [P, ctypes.POINTER(TuneResult)]
+        L.pt_get_schedule.argtypes = [P, ctypes.POINTER(TuneResult)]
         L.pt_mlp_param_count.argtypes = [P, ctypes.POINTER(I)]
         L.pt_mlp_set_params.argtypes = [P, P, I, P]
         L.pt_mlp_get_params.argtypes = [P, P, I, P]
@@ -237,6 +239,19 @@ class Scene:
         q = RecipQuery(1, 0, None, None, float(B), int(n_est), 0, int(seed), int(cap), ctypes.pointer(d), int(per),
                        p_out.data_ptr() if p_out is not None else None)
         _check(lib().pt_reciprocal_estimate(self.h, ctypes.byref(q), _ptr(out), _ptr(nsamples), _stream(stream)))
+
+    def schedule(self):
+        """The scene's current schedule knobs (as last tuned or set), named as in autotune's result."""
+        r = TuneResult()
+        _check(lib().pt_get_schedule(self.h, ctypes.byref(r)))
+        return {k: getattr(r, k) for k, _ in r._fields_ if k not in ("ms_best", "ms_previous", "iterations_rendered")}
+
+    def set_schedule(self, **knobs):
+        """Set schedule knobs (names of the autotuner's result); the others keep their values."""
+        cur = self.schedule()
+        cur.update(knobs)
+        r = TuneResult(**cur)
+        _check(lib().pt_set_schedule(self.h, ctypes.byref(r)))
 
     def autotune(self, accum, accum_sq=None, stream=None, **params):
         """Time the reciprocal-chain schedule choices and keep the fastest (renders into accum)."""

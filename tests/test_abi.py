@@ -36,7 +36,7 @@ def test_struct_sizes_match_header(ptlib):
     assert ctypes.sizeof(ptlib.IterStats) == (29 + 25) * 8
     assert ctypes.sizeof(ptlib.SubspaceParams) == 7 * 4
     assert ctypes.sizeof(ptlib.Totals) == 9 * 8
-    assert ctypes.sizeof(ptlib.TuneResult) == 9 * 4
+    assert ctypes.sizeof(ptlib.TuneResult) == 10 * 4
 
 
 def test_invalid_arguments_rejected_without_device(ptlib):

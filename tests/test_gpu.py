@@ -31,7 +31,7 @@ def gpu():
     return torch, pt
 
 
-def _render(gpu, sc, N, max_light=1024, subspaces=(8, 8), it_means=None, **params):
+def _render(gpu, sc, N, max_light=1024, subspaces=(8, 8), it_means=None, schedule=None, **params):
     """N iterations; per-pixel mean and variance of the mean. it_means (a list) receives the image
     mean of every iteration, whose spread gives the standard error of the image mean when the
     pixels of one iteration are correlated (they share light sub-paths and candidates)."""
@@ -39,6 +39,9 @@ def _render(gpu, sc, N, max_light=1024, subspaces=(8, 8), it_means=None, **param
     W, H = sc["width"], sc["height"]
     S = pt.Scene(sc, max_light_paths=max_light)
     S.build_subspaces(n_eye=subspaces[0], n_spec=subspaces[1])
+    if schedule:
+        S.set_schedule(**schedule)
+        assert all(S.schedule()[k] == v for k, v in schedule.items())
     acc = torch.zeros(W * H * 3, device="cuda")
     acc2 = torch.zeros_like(acc)
     sums = torch.zeros(N + 1, dtype=torch.float64, device="cuda") if it_means is not None else None
@@ -286,6 +289,15 @@ def test_resolve_and_call_order(gpu):
     assert torch.equal(acc, ref)
     tot = S.totals()
     assert tot["iterations"] == 8 and tot["n_nan"] == 0 and tot["bvh_depth"] >= 1 and tot["bvh_stack_need"] >= 0
+    # schedule knobs: a round trip, and values out of range or a tree the scene does not hold
+    S.set_schedule(stage_a_budget=4096, ext_wg=64, queue_chunk=2, stage_a_ahead=1, stage_a_refill=1)
+    k = S.schedule()
+    assert (k["stage_a_budget"], k["ext_wg"], k["queue_chunk"], k["stage_a_ahead"], k["stage_a_refill"],
+            k["bvh_width"]) == (4096, 64, 2, 1, 1, 4)
+    for bad, code in ((dict(ext_wg=96), -1), (dict(stage_a_ahead=3), -1), (dict(bvh_width=8), -5)):
+        with pytest.raises(pt.PTError) as e:
+            S.set_schedule(**bad)
+        assert e.value.code == code, bad
     S.release()
 
 
@@ -365,13 +377,16 @@ def test_bvh_closest_hit_matches_brute_force(gpu, oracle, which, width):
 
 
 # ------------------------------------------------------------------------------ furnaces
-@pytest.mark.parametrize("proxy", ["pt_nee", "proxy", "connections", "light_tracing", "full", "full_depth16"])
+@pytest.mark.parametrize("proxy", ["pt_nee", "proxy", "connections", "light_tracing", "full", "full_depth16",
+                                   "full_refill"])
 def test_diffuse_furnace(gpu, proxy):
     """Closed form of the furnace; full_depth16 keeps light sub-paths of 16 vertices, every slot of
     the light-queue counters (a regression test: those counters once ran into the eye queue's)."""
     from synth import scenes
     torch, pt = gpu
     a, K = 0.5, (16 if proxy == "full_depth16" else 6)
+    refill = proxy.endswith("_refill")
+    proxy = proxy.replace("_refill", "")
     sc = scenes.furnace(albedo=a, le=1.0, width=48, height=48)
     say(f"diffuse furnace {proxy}")
     flags = {"pt_nee": pt.PT_FLAG_NEE, "proxy": pt.PT_FLAG_NEE | pt.PT_FLAG_PROXY,
@@ -379,7 +394,8 @@ def test_diffuse_furnace(gpu, proxy):
              "light_tracing": pt.PT_FLAG_NEE | pt.PT_FLAG_LT,
              "full": pt.PT_FLAG_NEE | pt.PT_FLAG_PROXY | pt.PT_FLAG_MIS | pt.PT_FLAG_GAMMA | pt.PT_FLAG_SPC |
              pt.PT_FLAG_LT}[proxy.replace("_depth16", "")]
-    m, v, st = _render(gpu, sc, 512, max_depth=K, n_light=1024, cand_cap=128, flags=flags)
+    m, v, st = _render(gpu, sc, 512, max_depth=K, n_light=1024, cand_cap=128, flags=flags,
+                       schedule=dict(stage_a_refill=1, stage_a_ahead=2) if refill else None)
     expect = (1 - a ** K) / (1 - a)
     assert _furnace_ok(m, v, expect, f"diffuse furnace {proxy}")
     assert abs(m.mean() - expect) < 4 * math.sqrt(v.mean() / m.size)
@@ -761,21 +777,24 @@ def test_zz_config0_parity_with_learned_selection(gpu):
     assert tot["n_nan"] == 0 and tot["n_recip_truncated"] == 0
 
 
-def test_zz_config1_128_parity_with_oracle_reference(gpu):
+@pytest.mark.parametrize("schedule", ["default", "refill"])
+def test_zz_config1_128_parity_with_oracle_reference(gpu, schedule):
     """The projector scene of config 1 at 128 x 128 (depth 12), every strategy, 256 eye and light
     subspaces and 100 specular subspaces (the grouped centroid search), vs the stored O3
     reference image (plain bidirectional path tracing: path tracing with next-event estimation
     reaches the lens-lit dim walls only through rare emitter hits, and its per-pixel variance
-    estimate there is too low where its mean is low)."""
+    estimate there is too low where its mean is low). With the default schedule, and with stage A
+    refilling its walks node by node (pt_set_schedule)."""
     from synth import scenes
     torch, pt = gpu
     ref = np.load(os.path.join(GOLD, "cfg1_128_o3_ref.npz"))
     N = 2048
-    say(f"config 1 at 128x128 parity, {N} spp")
+    say(f"config 1 at 128x128 parity, {N} spp, {schedule} schedule")
     flags = (pt.PT_FLAG_NEE | pt.PT_FLAG_PROXY | pt.PT_FLAG_MIS | pt.PT_FLAG_GAMMA | pt.PT_FLAG_TILES |
              pt.PT_FLAG_SPC | pt.PT_FLAG_LT)
     m, v, st = _render(gpu, scenes.projector(128, 128), N, max_light=65536, subspaces=(256, 100), max_depth=12,
-                       n_light=65536, cand_cap=2600, flags=flags)
+                       n_light=65536, cand_cap=2600, flags=flags,
+                       schedule=dict(stage_a_refill=1) if schedule == "refill" else None)
     mo, vo = ref["mean"], ref["var_mean"]
     z = (m - mo) / np.sqrt(v + vo + 1e-30)
     frac = (np.abs(z) < 4).mean()
