@@ -125,9 +125,18 @@ enum {
     ,
     PT_FLAG_BOOTH = 1u << 12,       /* reciprocal chains with Booth's roulette (parameter booth_r)
                                        instead of the RRS function of equ:rr (RR ablation) */
-    PT_FLAG_MLP_DIR = 1u << 13      /* with PT_FLAG_MLP: the first retrace direction at a glossy
+    PT_FLAG_MLP_DIR = 1u << 13,     /* with PT_FLAG_MLP: the first retrace direction at a glossy
                                        (non-Dirac) y_{s-1} from mlp_mix x the network's vMF mixture +
                                        (1 - mlp_mix) x BSDF sampling; trained online like the logits */
+    PT_FLAG_GENERAL_CV = 1u << 14   /* general control vertex (Sections 5.2, 5.3): proxy candidates
+                                       of class C as well, h_c = y_j (j >= 1) on a Lambertian
+                                       surface with the control direction from y_{j-1}, the retrace
+                                       for u = 1 also sampling the BSDF at h_c (the cosine on the
+                                       control direction's side); the proxy class then holds
+                                       L ... D D S^u paths. Only with PT_FLAG_ONLY_PROXY_CLASS
+                                       and without PT_FLAG_MIS (the proxy strategy alone on its
+                                       class: the other strategies' partition and weights over the
+                                       extended class are not built) */
 };
 
 typedef struct {

@@ -735,15 +735,18 @@ int or_recip_table(const double *f, const double *q, int n, double B, int estima
 /* ------------------------------------------------------------------------- */
 /* path classes for the partition of strategies                              */
 /* ------------------------------------------------------------------------- */
-/* The proxy strategy builds, at the eye's first diffuse vertex z_d, paths whose part
- * beyond z_d is L S^u (class A) or L D S^u (class B), 1 <= u <= 4 (Section 6.1's limits).
- * The state machine walks eye vertices z_1, z_2, ... (emitters count as D):
+/* The proxy strategy builds, at the eye's first diffuse vertex z_d, paths whose part beyond z_d is
+ * L S^u (class A) or L D S^u (class B), 1 <= u <= 4 (Section 6.1's limits) and, with a general
+ * control vertex (Section 5.2), L ... h_c D S^u (class C, h_c = y_j, j >= 1, a Lambertian vertex).
+ * The state machine walks eye vertices z_1, z_2, ... (emitters count as diffuse):
  *   phase 0  no diffuse vertex yet
- *   phase 1  at/after z_d, only S since (u = their count)
- *   phase 2  S^u (1 <= u <= 4) then exactly one D after z_d
+ *   phase 1  at / after z_d, only specular vertices since (u of them)
+ *   phase 2  S^u (1 <= u <= 4) then exactly one diffuse vertex (y_1, or y_{j+1} for class C)
+ *   phase 4  (general control vertex only) S^u D then a Lambertian h_c, k vertices pushed since h_c
+ *            entered (h_c = y_k when the path closes at the vertex pushed last)
  *   phase 3  anything else (never a proxy path). */
-typedef struct { int phase, u; } pstate_t;
-static void pstate_push(pstate_t *st, int is_s, int umax)
+typedef struct { int phase, u, k; } pstate_t;
+static void pstate_push(pstate_t *st, int is_s, int is_lambert, int umax, int gcv)
 {
     switch (st->phase) {
     case 0: if (!is_s) { st->phase = 1; st->u = 0; } break;
@@ -751,12 +754,33 @@ static void pstate_push(pstate_t *st, int is_s, int umax)
         if (is_s) { if (++st->u > umax) st->phase = 3; }
         else st->phase = st->u >= 1 ? 2 : 3;
         break;
-    case 2: st->phase = 3; break;
+    case 2:
+        if (gcv && is_lambert) { st->phase = 4; st->k = 1; }
+        else st->phase = 3;
+        break;
+    case 4: st->k++; break;
     default: break;
     }
 }
-/* an emitter reached after the vertices pushed so far closes a proxy-class path? */
-static int pstate_closes_proxy(const pstate_t *st) { return (st->phase == 1 && st->u >= 1) || st->phase == 2; }
+#define LMAX_GCV 6   /* light vertices the proxy strategy keeps per sub-path (y_0 .. y_5) */
+/* does a path closed at the emitter after the vertices pushed so far (an emission hit of the next
+ * vertex, or a light sample connected to the vertex pushed last) belong to the proxy class? Class
+ * A: S^u then the emitter; B: S^u D then the emitter (h_c = y_0); C: S^u D then h_c = y_k, k >= 1,
+ * with y_{k+1+u} among the stored light vertices */
+static int pstate_closes_proxy(const pstate_t *st)
+{
+    if (st->phase == 4) return st->k + 1 + st->u <= LMAX_GCV - 1;
+    return (st->phase == 1 && st->u >= 1) || st->phase == 2;
+}
+/* the proxy-class test of one eye path z_1 .. z_n closed at the emitter after z_n (is_s[i],
+ * is_lambert[i] of z_{i+1}): the state machine above, exported so that tests can check it against
+ * the classes' definitions on every short path */
+int or_proxy_class(const int *is_s, const int *is_lambert, int n, int umax, int gcv)
+{
+    pstate_t st = {0, 0, 0};
+    for (int i = 0; i < n; ++i) pstate_push(&st, is_s[i], is_lambert[i], umax, gcv);
+    return pstate_closes_proxy(&st);
+}
 
 /* ------------------------------------------------------------------------- */
 /* thread pool helper                                                         */
@@ -812,6 +836,9 @@ typedef struct {
     double cost_cap;   /* expected chain samples per candidate above which it is roulette-kept */
     int o3_weights;    /* O3 only: 0 balance heuristic, 1 uniform over the strategies that can
                         * build the path, 2 light tracing alone (pins of the strategies) */
+    int general_cv;    /* O1 class filter: 1 when the proxy class also holds the paths of a general
+                        * control vertex (Section 5.2): ... h_c D S^u z_d with h_c = y_j, j >= 1, a
+                        * Lambertian vertex, and j + 1 + u < LMAX_GCV (the stored light vertices) */
 } or_params;
 
 typedef struct {
@@ -868,7 +895,7 @@ static void eye_path(const eye_ctx *c, int px, int py, rng_t *r, double L[3])
     double beta[3] = {1, 1, 1};
     double prev_pdf = 0.0;
     int prev_delta = 1, ign = -1;
-    pstate_t st = {0, 0};
+    pstate_t st = {0, 0, 0};
     for (int t = 1; t <= p->max_depth; ++t) {
         hit_t h;
         if (!trace_closest(s, o, d, s->tmin, 1e300, ign, -1, &h)) break;
@@ -890,7 +917,7 @@ static void eye_path(const eye_ctx *c, int px, int py, rng_t *r, double L[3])
             }
         }
         if (t == p->max_depth) break;
-        pstate_push(&st, m->spec, p->u_max);
+        pstate_push(&st, m->spec, m->type == MAT_LAMBERT, p->u_max, p->general_cv);
         /* proxy connection at the first diffuse vertex (O2 only) */
         if (do_proxy && st.phase == 1 && st.u == 0 && !m->spec) {
             double pc[3];
@@ -905,7 +932,7 @@ static void eye_path(const eye_ctx *c, int px, int py, rng_t *r, double L[3])
             double dist = vlen(dl);
             v3 wl = vscl(dl, 1.0 / dist);
             double cl = vdot(lp.n, vscl(wl, -1.0));
-            int cls = (st.phase == 1 && st.u >= 1) || st.phase == 2;
+            int cls = pstate_closes_proxy(&st);
             if (cl > 0 && class_ok(filter, cls)) {
                 double f[3];
                 bsdf_eval(m, tr->n, wo, wl, f);

@@ -32,6 +32,7 @@ class Params(ctypes.Structure):
         ("repeats", ctypes.c_int), ("u_max", ctypes.c_int), ("class_filter", ctypes.c_int),
         ("threads", ctypes.c_int), ("seed", ctypes.c_uint32), ("pilot", ctypes.c_int),
         ("chain_cap", ctypes.c_long), ("cost_cap", ctypes.c_double), ("o3_weights", ctypes.c_int),
+        ("general_cv", ctypes.c_int),
     ]
 
 
@@ -70,6 +71,8 @@ def lib():
         L.or_philox4x32_10.argtypes = [P, P, P]
         L.or_bsdf_sample.argtypes = [P, P, P, ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_int, P]
         L.or_bsdf_eval.argtypes = [P, P, P, P, P]
+        L.or_proxy_class.restype = ctypes.c_int
+        L.or_proxy_class.argtypes = [P, P, ctypes.c_int, ctypes.c_int, ctypes.c_int]
         _lib = L
     return _lib
 
@@ -114,6 +117,14 @@ def bsdf_eval(rec, n, wo, wi):
     return out
 
 
+def proxy_class(is_s, is_lambert, u_max=4, general_cv=0):
+    """1 when the eye path z_1 .. z_n (flags per vertex) closed at the emitter after z_n belongs to
+    the proxy class (classes A, B and, with general_cv, C)."""
+    a = np.ascontiguousarray(is_s, np.int32)
+    b = np.ascontiguousarray(is_lambert, np.int32)
+    return int(lib().or_proxy_class(_p(a), _p(b), len(a), int(u_max), int(general_cv)))
+
+
 class Scene:
     """Oracle-side copy of a scene dictionary from synth.scenes."""
 
@@ -143,14 +154,17 @@ class Scene:
 
     def render(self, method=0, n_iter=1, first_iter=0, max_depth=8, n_light=4096, cand_cap=400, repeats=5,
                u_max=4, class_filter=0, threads=None, seed=0, pilot=16, chain_cap=1 << 21, cost_cap=4096.0,
-               o3_weights=0):
+               o3_weights=0, general_cv=0):
         """Returns (sum, sumsq, stats): per-pixel sums of per-iteration values, shape (H, W, 3).
 
         method 0: O1 (PT + NEE), 1: O2 (proxy-sampling BDPT), 2: O3 (plain BDPT; o3_weights 0 balance
-        heuristic, 1 uniform weights, 2 light tracing alone)."""
+        heuristic, 1 uniform weights, 2 light tracing alone). general_cv (O1 only): the proxy class of
+        class_filter also holds the paths of a general control vertex (Section 5.2)."""
+        if general_cv and method != 0:
+            raise ValueError("general_cv applies to O1's class filter only")
         threads = threads or os.cpu_count() or 1
         p = Params(method, n_iter, first_iter, max_depth, n_light, cand_cap, repeats, u_max, class_filter,
-                   threads, seed, pilot, chain_cap, cost_cap, o3_weights)
+                   threads, seed, pilot, chain_cap, cost_cap, o3_weights, int(general_cv))
         s = np.zeros((self.H, self.W, 3))
         s2 = np.zeros((self.H, self.W, 3))
         st = Stats()

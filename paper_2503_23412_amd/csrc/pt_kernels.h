@@ -109,7 +109,8 @@ struct LightBuf {
     uint8_t *lfl;        // [PT_LSTORE * M]: LV_S, LV_DIRAC
     float4 *lbeta;       // [M]: throughput and solid-angle pdf of the ray in flight
     float2 *lb0;         // [M]: barycentrics of y_0
-    uint32_t *sig;       // [M]: bits 0..15 = vertex i specular, bits 24..28 = vertex count
+    uint32_t *sig;       // [M]: bits 0..15 = vertex i specular, 16..23 = vertex i (< 8) Lambertian,
+                         // 24..28 = vertex count
     uint32_t *q[2];
     uint32_t *pool;      // [PT_LSTORE * M]: vertices eye vertices may connect to (index i * M + path)
     int M;
@@ -166,7 +167,8 @@ __global__ void k_light_shade(SceneDev S, LightBuf L, uint32_t seed, int vi, int
             L.lfl[v] = (uint8_t)(((m.flags & MF_SPEC) ? LV_S : 0) | ((m.flags & MF_DELTA) ? LV_DIRAC : 0));
             uint32_t sg = L.sig[pid];
             if (m.flags & MF_SPEC) sg |= 1u << vi;
-            sg = (sg & 0xFFFFu) | ((uint32_t)(vi + 1) << 24);
+            if (m.type == MAT_LAMBERT && vi < 8) sg |= 1u << (16 + vi);
+            sg = (sg & 0xFFFFFFu) | ((uint32_t)(vi + 1) << 24);
             L.sig[pid] = sg;
             if (vi + 1 < lmax) {
                 Rng r = rng_make(seed, S_LIGHT, (uint32_t)pid, iter, (uint32_t)vi);
@@ -429,19 +431,39 @@ __device__ __forceinline__ bool light_tail_class(uint32_t ph, uint32_t uu, uint3
 // Every prefix ending at a specular vertex whose trailing specular run (length u <= u_max)
 // starts at y_1 (class A, L S^u) or at y_2 after a diffuse y_1 (class B, L D S^u, control
 // vertex y_0 on the light) is a candidate (Section 5.1; Section 6.1's restrictions).
-__global__ void k_candidates(LightBuf L, int u_max, Cand *cand, unsigned long long *cnt)
+// the candidates of light sub-path l (signature sg, nv stored vertices): class A (y_1 .. y_i
+// specular, h_c null), class B (y_1 diffuse, y_2 .. y_i specular, h_c = y_0) and, with gcv, class
+// C (y_j Lambertian, j >= 1, y_{j+1} non-specular, y_{j+2} .. y_i specular, h_c = y_j); u <=
+// u_max. emit(k, i, cls, j, u) is called for each in order, k counting from 0; returns the count.
+// The specular run that ends at y_i fixes its class and j, so each y_i (1 <= i < nv <= 6) ends at
+// most one candidate, and the five cannot all be candidates (y_1 .. y_5 all specular is one class
+// A run with u = 5 > u_max at i = 5): at most 4 per sub-path, the capacity of the buffers.
+template <typename F>
+__device__ __forceinline__ int cand_walk(uint32_t sg, int nv, int u_max, int gcv, F emit)
+{
+    int k = 0;
+    if (nv < 2) return 0;
+    const auto spec = [&](int i) { return ((sg >> i) & 1u) != 0u; };
+    const int cls = spec(1) ? 0 : 1;
+    const int first = cls == 0 ? 1 : 2;
+    for (int i = first; i < nv && spec(i) && i - first + 1 <= u_max; ++i) emit(k++, i, cls, 0, i - first + 1);
+    if (gcv)
+        for (int j = 1; j + 2 < nv; ++j) {
+            if (!((sg >> (16 + j)) & 1u) || spec(j + 1)) continue;
+            for (int i = j + 2; i < nv && spec(i) && i - j - 1 <= u_max; ++i) emit(k++, i, 2, j, i - j - 1);
+        }
+    return k;
+}
+
+__global__ void k_candidates(LightBuf L, int u_max, int gcv, Cand *cand, unsigned long long *cnt)
 {
     const int l = blockIdx.x * blockDim.x + threadIdx.x;
-    int nc = 0, cls = 0, first = 0;
+    int nc = 0, nv = 0;
     uint32_t sg = 0;
     if (l < L.M) {
         sg = L.sig[l];
-        const int nv = min(sig_count(sg), PT_LMAX);
-        if (nv >= 2) {
-            cls = (sg & 2u) ? 0 : 1;
-            first = cls == 0 ? 1 : 2;
-            for (int i = first; i < nv && (sg & (1u << i)) && i - first + 1 <= u_max; ++i) nc++;
-        }
+        nv = min(sig_count(sg), PT_LMAX);
+        nc = cand_walk(sg, nv, u_max, gcv, [](int, int, int, int, int) {});
     }
     // wavefront exclusive scan of the counts
     int incl = nc;
@@ -454,20 +476,27 @@ __global__ void k_candidates(LightBuf L, int u_max, Cand *cand, unsigned long lo
     int base = 0;
     if (__lane_id() == 63 && total) base = (int)atomicAdd(cnt + C_NCAND, (unsigned long long)total);
     base = __shfl(base, 63);
-    int o = base + incl - nc;
-    for (int k = 0; k < nc; ++k) {
-        const int vi = first + k;
+    const int o = base + incl - nc;
+    if (nc == 0) return;
+    cand_walk(sg, nv, u_max, gcv, [&](int k, int vi, int cls, int j, int u) {
         Cand c;
         c.v = L.lv[vi * L.M + l];
-        c.hc = L.lv[l];
-        const float2 b = L.lb0[l];
-        c.hc_b1 = b.x; c.hc_b2 = b.y;
-        c.cls_u = (cls << 8) | (k + 1);
+        c.hc = L.lv[j * L.M + l];
+        if (cls == 2) {
+            const float2 wc = oct_enc(normalize3(xyz(L.lv[(j - 1) * L.M + l]) - xyz(c.hc)));
+            c.hc_b1 = wc.x; c.hc_b2 = wc.y;
+            c.beta_c = L.lt[j * L.M + l];
+        } else {
+            const float2 b = L.lb0[l];
+            c.hc_b1 = b.x; c.hc_b2 = b.y;
+            c.beta_c = make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+        c.cls_u = (j << 16) | (cls << 8) | u;
         c.B = 0.f; c.rho = 1.f; c.recip_sum = 0.f; c.pmax = 0.f; c.psum = 0.f; c.pn = 0.f; c.spec_sub = 0;
         const float2 wi = oct_enc(normalize3(xyz(L.lv[(vi - 1) * L.M + l]) - xyz(c.v)));
         c.pad[0] = wi.x; c.pad[1] = wi.y;
         cand[o + k] = c;
-    }
+    });
 }
 
 // keep each candidate with probability pi_inc = min(1, cap / n_cand) (Horvitz-Thompson form of
@@ -556,27 +585,6 @@ __device__ __forceinline__ float fq_u1_a(const SceneDev &S, float3 v, float3 vn,
     const float q3 = side_prob(mv, vn, -w) * (cv / PT_PI) * fabsf(c0) / d2;
     return f / (0.5f * (invA + q3));
 }
-// f/q of the u = 1 class B sample whose diffuse vertex y_1 is the hit h1 (control vertex y_0)
-__device__ __forceinline__ float fq_u1_b(const SceneDev &S, float3 v, float3 vn, const MatDev &mv, float3 y0,
-                                         float3 n0, const Hit &h1)
-{
-    const float3 y1 = tri_point(S, h1.tri, h1.b1, h1.b2);
-    const float3 n1 = S.shade[h1.tri].n;
-    const MatDev m1 = S.mats[S.shade[h1.tri].mat];
-    const float3 a = y1 - y0;
-    const float d01 = dot3(a, a);
-    const float3 w01 = a * rsqrtf(d01);
-    const float3 b = v - y1;
-    const float d1v = dot3(b, b);
-    const float3 w1v = b * rsqrtf(d1v);
-    const float c0 = dot3(n0, w01);
-    const float p1 = c0 > 0.0f ? (c0 / PT_PI) * fabsf(dot3(n1, w01)) / d01 : 0.0f;
-    const float cv = fabsf(dot3(vn, w1v));
-    const float f = p1 * bsdf_pdf(m1, n1, -w01, w1v) * cv / d1v;
-    const float q3 = side_prob(mv, vn, -w1v) * (cv / PT_PI) * fabsf(dot3(n1, w1v)) / d1v;
-    return f / (0.5f * (p1 + q3));
-}
-
 // One f/q sample is a small state machine: fq_begin draws its first choices and sets the ray of
 // its first trip; after each trip fq_advance takes the hit, and either completes the sample or
 // sets the next ray. The caller traces every trip at one call site, so lanes that took different
@@ -586,7 +594,8 @@ __device__ __forceinline__ float fq_u1_b(const SceneDev &S, float3 v, float3 vn,
 // the visibility of the other side), 4 u >= 2 (the retrace through the specular run, then for
 // class B the visibility y_0 -> y_1).
 struct FqCand {              // what a sample reads of its candidate
-    float3 v, vn, y0, n0;
+    float3 v, vn, y0, n0;    // y_{s-1} and h_c with their normals (h_c: classes B and C; for
+                             // class C n0 faces the side of the control direction)
     int vt, t0, cls, u;
     MatDev mv;
 };
@@ -605,15 +614,39 @@ struct FqState {             // a sample between two trips
 __device__ __forceinline__ FqCand fq_cand(const SceneDev &S, const Cand &c)
 {
     FqCand K;
-    K.cls = c.cls_u >> 8; K.u = c.cls_u & 0xFF;
+    K.cls = cand_cls(c.cls_u); K.u = cand_u(c.cls_u);
     K.v = xyz(c.v);
     K.vt = fbits(c.v.w);
     K.vn = S.shade[K.vt].n;
     K.mv = S.mats[S.shade[K.vt].mat];
-    K.y0 = xyz(c.hc);        // control vertex of class B
+    K.y0 = xyz(c.hc);        // control vertex h_c (classes B, C)
     K.t0 = fbits(c.hc.w);
     K.n0 = K.cls ? S.shade[K.t0].n : f3(0.0f, 0.0f, 1.0f);
+    // class C: h_c is Lambertian, and sampling its BSDF from the control direction is the cosine
+    // hemisphere on that direction's side, the density class B's emitter has about its normal
+    if (K.cls == 2 && dot3(K.n0, oct_dec(make_float2(c.hc_b1, c.hc_b2))) < 0.0f) K.n0 = -K.n0;
     return K;
+}
+// f/q of the u = 1 sample of class B or C whose diffuse vertex y_1 (y_{j+1} for class C) is the
+// hit h1: f = the light tracer's density of y_1 from h_c (cosine about n0) and of y_{s-1} from
+// y_1 (area measure), q = the mixture of that density and of tracing from y_{s-1}
+__device__ __forceinline__ float fq_u1_b(const SceneDev &S, const FqCand &K, const Hit &h1)
+{
+    const float3 y1 = tri_point(S, h1.tri, h1.b1, h1.b2);
+    const float3 n1 = S.shade[h1.tri].n;
+    const MatDev m1 = S.mats[S.shade[h1.tri].mat];
+    const float3 a = y1 - K.y0;
+    const float d01 = dot3(a, a);
+    const float3 w01 = a * rsqrtf(d01);
+    const float3 b = K.v - y1;
+    const float d1v = dot3(b, b);
+    const float3 w1v = b * rsqrtf(d1v);
+    const float c0 = dot3(K.n0, w01);
+    const float p1 = c0 > 0.0f ? (c0 / PT_PI) * fabsf(dot3(n1, w01)) / d01 : 0.0f;
+    const float cv = fabsf(dot3(K.vn, w1v));
+    const float f = p1 * bsdf_pdf(m1, n1, -w01, w1v) * cv / d1v;
+    const float q3 = side_prob(K.mv, K.vn, -w1v) * (cv / PT_PI) * fabsf(dot3(n1, w1v)) / d1v;
+    return f / (0.5f * (p1 + q3));
 }
 __device__ __forceinline__ void fq_begin(const SceneDev &S, const FqCand &K, Rng &r, FqState &s)
 {
@@ -679,7 +712,7 @@ __device__ __forceinline__ bool fq_advance(const SceneDev &S, const FqCand &K, R
         return true;
     }
     if (s.mode <= 3) {
-        if (s.k == 2) { out = hit ? 0.0f : fq_u1_b(S, K.v, K.vn, K.mv, K.y0, K.n0, s.h1); return true; }
+        if (s.k == 2) { out = hit ? 0.0f : fq_u1_b(S, K, s.h1); return true; }
         // the ray to y_1, which must be diffuse; then the visibility of its other side
         if (!hit || (S.mats[S.shade[h.tri].mat].flags & MF_SPEC)) { out = 0.0f; return true; }
         s.h1 = h;
@@ -736,7 +769,7 @@ __device__ __forceinline__ bool fq_advance(const SceneDev &S, const FqCand &K, R
     const float3 a = y - K.y0;
     const float d2 = dot3(a, a);
     const float3 w01 = a * rsqrtf(d2);
-    const float c0 = dot3(K.n0, w01);
+    const float c0 = dot3(K.n0, w01);   // the cosine density of leaving h_c (classes B and C)
     if (c0 <= 0.0f) { out = 0.0f; return true; }
     s.f *= (c0 / PT_PI) * fabsf(dot3(ny, w01)) / d2;
     s.f *= bsdf_pdf(m, ny, -w01, w_cam);
@@ -832,7 +865,7 @@ __global__ void __launch_bounds__(64 * RW, PT_PILOT_WAVES) k_pilot(SceneDev S, C
         if (lane == 0) atomicAdd(cnt + C_DRAWN_P, (unsigned long long)k);
         if (lane == 0) {
             c.pmax = mx; c.psum = sm; c.pn = (float)k;
-            atomic_maxf(runmax + (c.cls_u >> 8) * 5 + (c.cls_u & 0xFF), mx);
+            atomic_maxf(runmax + cand_cls(c.cls_u) * 5 + cand_u(c.cls_u), mx);
         }
     }
     wave_count(cnt + C_RAYS_RECIP, C.rays);
@@ -854,9 +887,9 @@ __global__ void k_roulette(Cand *cand, const uint32_t *kept, uint32_t *final_, u
     if (i < n) {
         ci = kept[i];
         Cand &c = cand[ci];
-        const int b = (c.cls_u >> 8) * 5 + (c.cls_u & 0xFF);
+        const int b = cand_cls(c.cls_u) * 5 + cand_u(c.cls_u);
         float gmax = 0.f;
-        for (int k = 0; k < 10; ++k) gmax = fmaxf(gmax, runmax[k]);
+        for (int k = 0; k < PT_STAT_CU; ++k) gmax = fmaxf(gmax, runmax[k]);
         const float Bb = runmax[b] > 0.f ? runmax[b] : (gmax > 0.f ? gmax : 1.0f / em_area);
         // The (class, u, S, C) bucket's f/q statistics of earlier iterations (Section 5.5) when the
         // subspace labels exist: the largest value and the mean. With a pilot (c.pn > 0): B =
@@ -865,7 +898,7 @@ __global__ void k_roulette(Cand *cand, const uint32_t *kept, uint32_t *final_, u
         // u) running max and B / 2 while the bucket has none). Any B with beta / B in (0, 2) leaves
         // the estimate unbiased (Appendix B); the pilot keeps B at or above what the candidate's own
         // samples reached.
-        const int sb = labelled ? 3 * stat_bucket(D, c.cls_u >> 8, c.cls_u & 0xFF, c.spec_sub & 0xFFFF,
+        const int sb = labelled ? 3 * stat_bucket(D, cand_cls(c.cls_u), cand_u(c.cls_u), c.spec_sub & 0xFFFF,
                                                   c.spec_sub >> 16) : 0;
         const bool piloted = c.pn > 0.f;
         const bool has_bucket = labelled && D.bstat[sb] > 0.f && D.bstat[sb + 2] > 0.f;
@@ -1088,7 +1121,7 @@ __device__ __forceinline__ void chain_finish(Cand &c, const ChainRun &st, bool t
     atomicMax(cnt + C_CHAIN_MAX, (unsigned long long)st.ns);
     const float est = (st.alive || trunc) ? (float)(st.ans * (double)st.weight / (double)c.B) : 0.0f;
     unsafeAtomicAdd(&c.recip_sum, est);
-    atomic_maxf(runmax + (c.cls_u >> 8) * 5 + (c.cls_u & 0xFF), mx);
+    atomic_maxf(runmax + cand_cls(c.cls_u) * 5 + cand_u(c.cls_u), mx);
     atomic_maxf(&c.pmax, mx);   // the candidate's largest f/q, pilot and chains (bucket statistics)
 }
 
@@ -2082,14 +2115,18 @@ __global__ void __launch_bounds__(WG) k_proxy(SceneDev S, EyeBuf E, const Cand *
             pi_j = (float)index_prob(k, nk);
         }
         const Cand c = cand[ci];
-        const int cls = c.cls_u >> 8, u = c.cls_u & 0xFF;
+        const int cls = cand_cls(c.cls_u), u = cand_u(c.cls_u);
         const int d = fbits(it.wo.w);
         float3 zn = f3(0.f, 0.f, 1.f);
         float3 add = f3(0.f, 0.f, 0.f);
         // the direction head's training sample of this contribution (glossy y_{s-1} only)
         bool glossy_rec = false;
         float3 rv = f3(0.f, 0.f, 0.f), rvn = rv, rwo = rv, rdir = rv;
-        if (d + 1 + u + cls <= P.K && pi_j > 0.0f) {
+        // segments of the path: d on the eye side, z_d -> y_{s-1}, u down to the dropped diffuse
+        // vertex (classes B, C) or the emitter (A), then one to h_c = y_j and j along the light
+        // prefix (j = 0 for class B)
+        const int seg = d + 1 + u + (cls == 0 ? 0 : 1 + cand_j(c.cls_u));
+        if (seg <= P.K && pi_j > 0.0f) {
             const float3 xd = xyz(it.x);
             const int td = fbits(it.x.w);
             const TriShade &shd = S.shade[td];
@@ -2167,13 +2204,23 @@ __global__ void __launch_bounds__(WG) k_proxy(SceneDev S, EyeBuf E, const Cand *
                         const float3 a0 = y0 - y;
                         const float e2 = dot3(a0, a0);
                         const float3 wl = a0 * rsqrtf(e2);
-                        const float c0 = -dot3(S.shade[t0].n, wl);
                         const float3 f1 = bsdf_f(mh, ny, -bs.wi, wl);
-                        if (c0 <= 0.0f || !nonzero3(f1) || occluded(C, y, h.tri, y0, t0)) { ok = false; break; }
-                        const float3 le = emission(S, t0, c.hc_b1, c.hc_b2, -wl);
-                        term = f1 * le * (c0 * fabsf(dot3(ny, wl)) / e2 * S.em_area);
-                        J0 = c0 / e2;
-                        pb_y1 = bsdf_pdf(mh, ny, -bs.wi, wl);
+                        if (cls == 2) {
+                            // class C: the light throughput arriving at h_c, the BSDF there from
+                            // the control direction toward y, and the geometry term h_c <-> y
+                            const float3 n0 = S.shade[t0].n;
+                            const float3 f0 = bsdf_f(S.mats[S.shade[t0].mat], n0,
+                                                     oct_dec(make_float2(c.hc_b1, c.hc_b2)), -wl);
+                            if (!nonzero3(f0) || !nonzero3(f1) || occluded(C, y, h.tri, y0, t0)) { ok = false; break; }
+                            term = f1 * xyz(c.beta_c) * f0 * (fabsf(dot3(n0, wl)) * fabsf(dot3(ny, wl)) / e2);
+                        } else {
+                            const float c0 = -dot3(S.shade[t0].n, wl);
+                            if (c0 <= 0.0f || !nonzero3(f1) || occluded(C, y, h.tri, y0, t0)) { ok = false; break; }
+                            const float3 le = emission(S, t0, c.hc_b1, c.hc_b2, -wl);
+                            term = f1 * le * (c0 * fabsf(dot3(ny, wl)) / e2 * S.em_area);
+                            J0 = c0 / e2;
+                            pb_y1 = bsdf_pdf(mh, ny, -bs.wi, wl);
+                        }
                     }
                     cur = y; curt = h.tri; curn = ny; wo = -bs.wi;
                     qp[nq] = y; qt[nq] = h.tri; ++nq;

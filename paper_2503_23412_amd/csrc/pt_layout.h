@@ -73,20 +73,28 @@ enum { LV_S = 1, LV_DIRAC = 2 };   // per light vertex flags
 #define PT_STACK 48    // traversal stack entries per thread, 4-wide walks
 #define PT_STACK8 64   // and 8-wide walks
 
-// Incomplete light sub-path candidate (y_{s-1} plus the control vertex), 80 bytes.
+// Incomplete light sub-path candidate (y_{s-1} plus the control vertex), 96 bytes. Class A: h_c
+// null; class B: h_c = y_0 on an emitter; class C (general control vertex): h_c = y_j, j >= 1, on a
+// Lambertian surface, with its control direction and the light throughput arriving there.
 struct Cand {
     float4 v;        // y_{s-1} position, w = triangle (bits)
-    float4 hc;       // class B: y_0 position, w = triangle (bits)
-    float hc_b1, hc_b2;
-    int32_t cls_u;   // class << 8 | u
+    float4 hc;       // classes B, C: h_c position, w = triangle (bits)
+    float hc_b1, hc_b2;   // class B: barycentrics of y_0; class C: octahedral encoding of the
+                          // direction from h_c toward y_{j-1} (the reverse of the control direction)
+    int32_t cls_u;   // j << 16 | class << 8 | u  (j: class C's light vertex index of h_c)
     float B;
     float rho;       // probability it survived the cost roulette
     float recip_sum; // sum of the reciprocal estimates of this iteration
     float pmax, psum, pn;
     int32_t spec_sub;// specular subspace S
     float pad[2];    // octahedral encoding of y_{s-1}'s incident direction (toward y_{s-2})
+    float4 beta_c;   // class C: throughput arriving at h_c (rgb) from the light sub-path
 };
-static_assert(sizeof(Cand) == 80, "Cand layout");
+static_assert(sizeof(Cand) == 96, "Cand layout");
+#define PT_STAT_CU 15   // (class, u) pairs of the statistics: 3 classes x u = 0 .. 4
+__host__ __device__ inline int cand_cls(int cls_u) { return (cls_u >> 8) & 0xFF; }
+__host__ __device__ inline int cand_u(int cls_u) { return cls_u & 0xFF; }
+__host__ __device__ inline int cand_j(int cls_u) { return cls_u >> 16; }
 
 // Device counters of one iteration (64-bit so that large runs do not wrap).
 enum {

@@ -165,7 +165,7 @@ struct pt_scene {
     unsigned long long *tot = nullptr;   // [TOT_COUNT] running totals over iterations (k_totals)
     long long *ts = nullptr;             // [2 PT_TS_CAP] wall-clock start / end of the latest iterations
     int wall_khz = 0;                    // device wall-clock rate
-    float *runmax = nullptr;   // [2 * 5] running maxima of f/q per (class, u)
+    float *runmax = nullptr;   // [16]: running maxima of f/q per (class, u), PT_STAT_CU used
     // subspace-based connections: light subspaces, buckets of the pool, Q (learned, frozen), alias rows
     int n_lsub = 0;
     float *light_c = nullptr, *qacc = nullptr, *qfrz = nullptr, *q_alprob = nullptr, *q_alpmf = nullptr, *q_rowsum = nullptr,
@@ -552,7 +552,7 @@ __global__ void k_feat_ctrl(SceneDev S, const Cand *cand, unsigned long long *cn
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= (int)cnt[C_NCAND]) return;
     const Cand &c = cand[i];
-    if (!(c.cls_u >> 8)) return;
+    if (!cand_cls(c.cls_u)) return;
     float f[9];
     feat9(S, xyz(c.hc), S.shade[__float_as_int(c.hc.w)].n, f3(0.f, 0.f, 0.f), f);
     const int k = (int)atomicAdd(cnt + slot, 1ull);
@@ -620,15 +620,15 @@ extern "C" pt_status pt_build_subspaces(pt_scene *s, const pt_subspace_params *p
 #undef AL
         s->n_eye = ne; s->n_spec = ns;
     }
-    // statistics by (class, u, S, C): 10 x n_ctrl x n_spec buckets
-    if ((long)10 * nc * ns > s->stat_cap) {
+    // statistics by (class, u, S, C): PT_STAT_CU (3 classes x 5 values of u) x n_ctrl x n_spec buckets
+    if ((long)PT_STAT_CU * nc * ns > s->stat_cap) {
         pt_status e;
 #define AL(ptr, n) if ((e = s->alloc(ptr, n)) != PT_OK) return e;
-        AL(s->rstat_acc, (size_t)30 * nc * ns); AL(s->rstat_frz, (size_t)30 * nc * ns);
-        AL(s->bstat_acc, (size_t)30 * nc * ns); AL(s->bstat_frz, (size_t)30 * nc * ns);
+        AL(s->rstat_acc, (size_t)3 * PT_STAT_CU * nc * ns); AL(s->rstat_frz, (size_t)3 * PT_STAT_CU * nc * ns);
+        AL(s->bstat_acc, (size_t)3 * PT_STAT_CU * nc * ns); AL(s->bstat_frz, (size_t)3 * PT_STAT_CU * nc * ns);
         AL(s->ctrl_c, (size_t)256 * FEAT);
 #undef AL
-        s->stat_cap = 10 * nc * ns;
+        s->stat_cap = PT_STAT_CU * nc * ns;
     }
     s->n_ctrl = nc;
     // pre-trace: light sub-paths -> candidate specular vertices; eye paths -> first diffuse vertices
@@ -655,7 +655,7 @@ extern "C" pt_status pt_build_subspaces(pt_scene *s, const pt_subspace_params *p
                        nl, p->kmeans_iters, st));
         TRY(build_groups(s, s->light_c, nl, s->gs_light, p->kmeans_iters, st));
     }
-    k_candidates<<<blocks(L.M, 256), 256, 0, st>>>(L, 4, s->cand, s->cnt);
+    k_candidates<<<blocks(L.M, 256), 256, 0, st>>>(L, 4, 0, s->cand, s->cnt);
     k_feat_cands<<<blocks(4L * L.M, 256), 256, 0, st>>>(S, s->cand, s->cnt, s->feat);
     HIPCHK(hipMemcpyAsync(c, s->cnt, sizeof(c), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
@@ -690,8 +690,8 @@ extern "C" pt_status pt_build_subspaces(pt_scene *s, const pt_subspace_params *p
     TRY(build_groups(s, s->eye_c, ne, s->gs_eye, p->kmeans_iters, st));
     // statistics start from nothing
     k_fill<<<blocks((long)ne * ns, 256), 256, 0, st>>>(s->gamma_acc, 0.0f, (size_t)ne * ns);
-    k_fill<<<blocks(30L * nc * ns, 256), 256, 0, st>>>(s->rstat_acc, 0.0f, (size_t)30 * nc * ns);
-    k_fill<<<blocks(30L * nc * ns, 256), 256, 0, st>>>(s->bstat_acc, 0.0f, (size_t)30 * nc * ns);
+    k_fill<<<blocks(3L * PT_STAT_CU * nc * ns, 256), 256, 0, st>>>(s->rstat_acc, 0.0f, (size_t)3 * PT_STAT_CU * nc * ns);
+    k_fill<<<blocks(3L * PT_STAT_CU * nc * ns, 256), 256, 0, st>>>(s->bstat_acc, 0.0f, (size_t)3 * PT_STAT_CU * nc * ns);
     k_fill<<<blocks(s->n_tiles, 256), 256, 0, st>>>(s->tile_proxy, 0.0f, (size_t)s->n_tiles);
     k_fill<<<blocks(s->n_tiles, 256), 256, 0, st>>>(s->tile_total, 0.0f, (size_t)s->n_tiles);
     k_fill<<<1, 16, 0, st>>>(s->runmax, 0.0f, 16);
@@ -884,6 +884,9 @@ pt_status check_params(pt_scene *s, const pt_iter_params *p, float *acc)
     if ((p->flags & PT_FLAG_MLP) && !(p->mlp_mix >= 0.0f && p->mlp_mix < 1.0f && p->mlp_lr > 0.0f))
         return set_err(PT_EINVAL, "PT_FLAG_MLP needs 0 <= mlp_mix < 1 and mlp_lr > 0");
     if ((p->flags & PT_FLAG_BOOTH) && !(p->booth_r > 0.0f)) return set_err(PT_EINVAL, "PT_FLAG_BOOTH needs booth_r > 0");
+    if ((p->flags & PT_FLAG_GENERAL_CV) &&
+        (!(p->flags & PT_FLAG_PROXY) || !(p->flags & PT_FLAG_ONLY_PROXY_CLASS) || (p->flags & PT_FLAG_MIS)))
+        return set_err(PT_EINVAL, "PT_FLAG_GENERAL_CV needs PT_FLAG_PROXY and PT_FLAG_ONLY_PROXY_CLASS, without PT_FLAG_MIS");
     return PT_OK;
 }
 
@@ -929,7 +932,7 @@ pt_status enqueue_iteration(pt_scene *s, const pt_iter_params *p, float *acc, fl
     if (labels && pre) {
         // statistics of earlier iterations only: frozen copies for this iteration
         k_copy<<<blocks((long)ne * ns, 256), 256, 0, stream>>>(s->gamma_acc, s->gamma_frz, (size_t)ne * ns);
-        const size_t nst = (size_t)10 * s->n_ctrl * ns;
+        const size_t nst = (size_t)PT_STAT_CU * s->n_ctrl * ns;
         k_copy<<<blocks((long)(3 * nst), 256), 256, 0, stream>>>(s->rstat_acc, s->rstat_frz, 3 * nst);
         k_copy<<<blocks((long)(3 * nst), 256), 256, 0, stream>>>(s->bstat_acc, s->bstat_frz, 3 * nst);
         k_row_tot<<<blocks(ne, 256), 256, 0, stream>>>(s->gamma_frz, ne, ns, s->row_tot);
@@ -1036,7 +1039,8 @@ pt_status enqueue_iteration(pt_scene *s, const pt_iter_params *p, float *acc, fl
             const int maxc = 4 * M;
             const size_t e0 = 2 * (size_t)p->max_depth;
             if (pre) {
-                k_candidates<<<blocks(M, 256), 256, 0, stream>>>(L, p->u_max, s->cand, s->cnt);
+                k_candidates<<<blocks(M, 256), 256, 0, stream>>>(L, p->u_max, (p->flags & PT_FLAG_GENERAL_CV) ? 1 : 0,
+                                                                 s->cand, s->cnt);
                 k_keep<<<blocks(maxc, 256), 256, 0, stream>>>(p->cand_cap, p->seed, s->kept, maxc, s->cnt);
                 // subspace labels (S, C) of the kept candidates: their buckets' statistics give B a floor
                 if (labels) k_label_kept<<<blocks(maxc, 256), 256, 0, stream>>>(S, D, s->cand, s->kept, s->cnt);

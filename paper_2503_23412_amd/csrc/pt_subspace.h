@@ -48,8 +48,8 @@ struct SubDev {
     int n_ctrl;
     // frozen reciprocal statistics per (class, u, S, C): sum R, sum R^2 / rho, count; and the
     // bucket's f/q samples: largest value (a floor of its B), sum, count (its mean estimates beta)
-    const float *rstat;      // [10 * n_ctrl * n_spec * 3]
-    const float *bstat;      // [10 * n_ctrl * n_spec * 3]
+    const float *rstat;      // [PT_STAT_CU * n_ctrl * n_spec * 3]
+    const float *bstat;      // [PT_STAT_CU * n_ctrl * n_spec * 3]
     // the previous iteration's candidate counts (n_cand, n_final, non-empty subspaces), its
     // per-subspace counts and the frozen Gamma row totals: the MIS surrogate's inputs, none of
     // which depends on this iteration's light paths
@@ -170,7 +170,7 @@ __global__ void k_label_kept(SceneDev S, SubDev D, Cand *cand, const uint32_t *k
     float f[9];
     feat9(S, xyz(c.v), S.shade[__float_as_int(c.v.w)].n, oct_dec(make_float2(c.pad[0], c.pad[1])), f);
     const int s = nearest_set(D.spec, f);
-    const int C = (c.cls_u >> 8) ? ctrl_label(S, D, xyz(c.hc), __float_as_int(c.hc.w)) : 0;
+    const int C = cand_cls(c.cls_u) ? ctrl_label(S, D, xyz(c.hc), __float_as_int(c.hc.w)) : 0;
     c.spec_sub = s | (C << 16);
 }
 // bucket sizes of the final candidates by S
@@ -366,7 +366,7 @@ __global__ void k_rstat(const Cand *cand, const uint32_t *final_, const unsigned
     if (i >= (int)cnt[C_NFINAL] || !cnt[C_LEARN]) return;
     const Cand &c = cand[final_[i]];
     const float R = c.recip_sum / (float)repeats;
-    const int b = stat_bucket(D, c.cls_u >> 8, c.cls_u & 0xFF, c.spec_sub & 0xFFFF, c.spec_sub >> 16);
+    const int b = stat_bucket(D, cand_cls(c.cls_u), cand_u(c.cls_u), c.spec_sub & 0xFFFF, c.spec_sub >> 16);
     // the second moment of the unbiased factor R 1{kept} / rho is E[R^2] / rho
     unsafeAtomicAdd(rstat_acc + 3 * b + 0, R);
     unsafeAtomicAdd(rstat_acc + 3 * b + 1, R * R / fmaxf(c.rho, 1e-6f));

@@ -26,6 +26,7 @@ PT_FLAG_SPC = 1 << 10
 PT_FLAG_LT = 1 << 11
 PT_FLAG_BOOTH = 1 << 12
 PT_FLAG_MLP_DIR = 1 << 13
+PT_FLAG_GENERAL_CV = 1 << 14
 MLP_VMF = 40   # outputs of the direction head after the n_spec logits
 
 PT_EST_ITILDE = 0

@@ -621,6 +621,41 @@ def test_proxy_class_matches_oracle_path_tracing(gpu, oracle):
     assert st["n_recip_truncated"] == 0 and st["n_proxy_valid"] > 0
 
 
+def test_general_control_vertex_matches_oracle(gpu, oracle):
+    """Class C candidates on (PT_FLAG_GENERAL_CV): the proxy strategy alone vs the oracle's PT
+    restricted to the proxy class with a general control vertex. The scene is the emitting
+    spherical enclosure around a glass sphere: every diffuse vertex lies on the sphere, where the
+    geometry term of two points is 1 / (4 R^2), so the connection h_c <-> y_{j+1} stays bounded
+    (in a room with corners its weight has infinite variance, as any diffuse-diffuse connection).
+    u <= 1: class C carries about 20 % of the class at 8 segments. (With u = 2, through the glass
+    sphere, the class grows ten-fold and its reciprocal estimates become heavy-tailed: 2,048
+    iterations read 48.9 +- 1.8 against the oracle's 47.7, too wide a spread for a 4-sigma bar.)"""
+    from synth import scenes
+    torch, pt = gpu
+    sc = scenes.furnace(albedo=0.5, le=1.0, glass_sphere=True, width=16, height=16, enclosure="sphere")
+    N = 4096
+    say("general control vertex, glass furnace")
+    its = []
+    m, v, st = _render(gpu, sc, N, max_depth=8, n_light=1024, cand_cap=256, u_max=1, it_means=its,
+                       flags=pt.PT_FLAG_NEE | pt.PT_FLAG_PROXY | pt.PT_FLAG_ONLY_PROXY_CLASS | pt.PT_FLAG_GENERAL_CV)
+    O = oracle.Scene(sc)
+    kw = dict(method=0, n_iter=N, max_depth=8, u_max=1, class_filter=1, seed=11)
+    s1, q1, _ = O.render(general_cv=1, **kw)
+    s0, _, _ = O.render(**kw)
+    mo = s1 / N
+    vo = np.maximum(q1 / N - mo * mo, 0) / N
+    z = (m - mo) / np.sqrt(v + vo + 1e-30)
+    # the GPU's image total: its standard error from the per-iteration image means
+    se_g = float(np.std(its, ddof=1)) * m.size / math.sqrt(N)
+    se = math.sqrt(se_g ** 2 + vo.sum())
+    say("totals", m.sum(), mo.sum(), "without class C", s0.sum() / N, "se", se, "frac |z|<4",
+        (np.abs(z) < 4).mean(), "max |z|", np.abs(z).max(), "stats", st)
+    assert (np.abs(z) < 4).mean() >= 0.99, np.abs(z).max()
+    assert abs(m.sum() - mo.sum()) < 4 * se
+    assert m.sum() - s0.sum() / N > 10 * se          # class C is there
+    assert st["n_recip_truncated"] == 0 and st["n_proxy_valid"] > 0 and st["n_nan"] == 0
+
+
 def test_learned_proposal_proxy_class_matches_oracle(gpu):
     """The proxy strategy alone with both learned heads on (PT_FLAG_MLP: the subspace picked by the
     network's softmax mixed with 10 % of the plain row; PT_FLAG_MLP_DIR: the first retrace direction

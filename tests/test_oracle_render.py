@@ -13,7 +13,13 @@ P6  glass furnace: an emitting spherical enclosure (no corners, so the class B f
     K), for O1 and O2 (O2 routes the L S^u and L D S^u paths through the proxy).
 P7  proxy-class paths only: O2's proxy strategy alone matches O1 restricted to the same
     signature class, per pixel within 4 combined standard errors (mirror room, u <= 2).
+P8  the proxy class with a general control vertex (Section 5.2): the oracle's state machine
+    agrees with the classes' definitions on every eye path of up to 8 vertices; O1's class
+    filter with it still partitions the image exactly, and its proxy class is the one without
+    it plus a non-empty set of L ... h_c D S^u paths.
 """
+import itertools
+import re
 import math
 
 import numpy as np
@@ -148,3 +154,64 @@ def test_p7_proxy_class_matches_path_tracing(oracle):
     assert abs(m1.sum() - m2.sum()) < 4 * math.sqrt(v1.sum() + v2.sum())
     assert st["n_recip_truncated"] == 0 and st["n_proxy_valid"] > 0
     assert m1.sum() > 0.05 * (m1.sum() + 1e-9)
+
+
+def _proxy_class_def(mats, u_max, gcv):
+    """The classes written out on the light-order string (eye path z_1 .. z_n closed at the emitter
+    y_0, so y_k = z_{n+1-k}): z_d is the first non-specular eye vertex and y_1 .. y_i the vertices
+    between the emitter and z_d. Class A: y_1 .. y_i specular, 1 <= i <= u_max. Class B: y_1 not
+    specular, then u = i - 1 specular vertices, 1 <= u <= u_max. Class C: some y_j (j >= 1)
+    Lambertian, y_{j+1} not specular, then u = i - j - 1 specular vertices, 1 <= u <= u_max, and
+    i <= 5 (the light vertices the strategy stores). Letters: S specular, L Lambertian, R other."""
+    if all(m == "S" for m in mats):
+        return 0
+    zd = next(k for k, m in enumerate(mats) if m != "S")     # 0-based eye index of z_d
+    light = "".join(reversed(mats[zd + 1:]))                  # y_1 .. y_i
+    i = len(light)
+    if re.fullmatch(r"S{1,%d}" % u_max, light):
+        return 1
+    if re.fullmatch(r"[LR]S{1,%d}" % u_max, light):
+        return 1
+    if gcv and i <= 5 and re.fullmatch(r"[SLR]*L[LR]S{1,%d}" % u_max, light):
+        return 1
+    return 0
+
+
+def test_p8_general_cv_class_definition(oracle):
+    """Every eye path of 1..8 vertices over {specular, Lambertian, other diffuse}: the oracle's
+    proxy-class state machine equals the written-out definition, with and without class C."""
+    n_c = 0
+    for n in range(1, 9):
+        for mats in itertools.product("SLR", repeat=n):
+            is_s = [m == "S" for m in mats]
+            is_l = [m == "L" for m in mats]
+            for u_max in (1, 2, 4):
+                for gcv in (0, 1):
+                    want = _proxy_class_def(mats, u_max, gcv)
+                    got = oracle.proxy_class(is_s, is_l, u_max, gcv)
+                    assert got == want, ("".join(mats), u_max, gcv, got, want)
+                    n_c += gcv and want and not _proxy_class_def(mats, u_max, 0)
+    assert n_c > 0
+
+
+def test_p8_general_cv_partition(oracle):
+    """Mirror room, the same random streams: with class C, O1's proxy class and the other paths
+    still add up to the unfiltered image; the proxy class grows by the class C paths only (never
+    loses a path), and they carry a non-zero share."""
+    sc = scenes.mirror_room(8, 8)
+    S = oracle.Scene(sc)
+    kw = dict(method=0, n_iter=24, max_depth=8, u_max=2, seed=3)
+    a, _, _ = S.render(class_filter=0, **kw)
+    p0, _, _ = S.render(class_filter=1, **kw)
+    o0, _, _ = S.render(class_filter=2, **kw)
+    p1, _, _ = S.render(class_filter=1, general_cv=1, **kw)
+    o1, _, _ = S.render(class_filter=2, general_cv=1, **kw)
+    scale = a.max()
+    assert np.abs(p1 + o1 - a).max() <= 1e-12 * scale
+    assert np.abs(p0 + o0 - a).max() <= 1e-12 * scale
+    extra = p1 - p0
+    assert extra.min() >= -1e-12 * scale
+    assert np.abs(extra - (o0 - o1)).max() <= 1e-12 * scale
+    assert extra.sum() > 1e-3 * p0.sum()
+    with pytest.raises(ValueError):
+        S.render(method=1, n_iter=1, general_cv=1)
