@@ -133,10 +133,10 @@ enum {
                                        surface with the control direction from y_{j-1}, the retrace
                                        for u = 1 also sampling the BSDF at h_c (the cosine on the
                                        control direction's side); the proxy class then holds
-                                       L ... D D S^u paths. Only with PT_FLAG_ONLY_PROXY_CLASS
-                                       and without PT_FLAG_MIS (the proxy strategy alone on its
-                                       class: the other strategies' partition and weights over the
-                                       extended class are not built) */
+                                       L ... D D S^u paths, which the other strategies then leave
+                                       to it. Needs PT_FLAG_PROXY; not with PT_FLAG_MIS (the
+                                       variance-aware weights over the larger class are not
+                                       built), so the strategies partition the paths */
 };
 
 typedef struct {
@@ -409,6 +409,16 @@ pt_status pt_philox(const uint32_t *in_dev, int32_t n, uint32_t *out_dev, void *
  * needs and its depth in levels. */
 pt_status pt_bvh_stats(const float *tri, int32_t n_tri, int32_t width, int32_t *n_nodes, int32_t *stack_need,
                        int32_t *depth);
+
+/* Host only (no device needed): the proxy-class test every strategy of the kernels applies to a
+ * path under the partition (classes A and B of Section 5.1 within Section 6.1's limits, and class C
+ * of Section 5.2 with general_cv), for tests of that partition. The path runs camera -> z_1 .. z_n
+ * -> y_j .. y_1 -> the emitter y_0: eye[i] (i < n_eye) holds z_{i+1}'s flags (bit 0 specular, bit 1
+ * Lambertian), light_sig a light sub-path signature (bit i: y_i specular, i < 16; bit 16 + i: y_i
+ * Lambertian, i < 8) whose vertices y_j .. y_1 (0 <= j <= 15) are joined; 1 <= u_max <= 4. *out = 1
+ * when the path belongs to the proxy class. */
+pt_status pt_proxy_class(const uint8_t *eye, int32_t n_eye, uint32_t light_sig, int32_t j, int32_t u_max,
+                         int32_t general_cv, int32_t *out);
 
 /* Message for the last non-OK return on this thread ("" if none). */
 const char *pt_last_error(void);

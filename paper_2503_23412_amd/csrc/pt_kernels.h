@@ -190,14 +190,27 @@ __global__ void k_light_shade(SceneDev S, LightBuf L, uint32_t seed, int vi, int
 
 // proxy-class state machine over eye vertices (emitters count as D): phase 0 before the first
 // diffuse vertex z_d; 1 at/after z_d with only specular vertices since (u of them); 2 after
-// S^u then one diffuse vertex; 3 never a proxy path
-__device__ __forceinline__ void pstate_push(uint32_t &ph, uint32_t &u, bool spec, int umax)
+// S^u then one diffuse vertex (y_1, or y_{j+1} of class C); 4 (general control vertex, gcv)
+// after a further Lambertian vertex h_c, k vertices pushed since h_c entered (h_c = y_k if the
+// path closes now) while y_{k+1+u} is still among the stored light vertices; 3 never a proxy path
+__host__ __device__ inline void pstate_push(uint32_t &ph, uint32_t &u, uint32_t &k, bool spec, bool lambert, int umax,
+                                            bool gcv)
 {
     if (ph == 0) { if (!spec) { ph = 1; u = 0; } }
     else if (ph == 1) {
         if (spec) { if (++u > (uint32_t)umax) ph = 3; }
         else ph = u >= 1 ? 2 : 3;
-    } else if (ph == 2) ph = 3;
+    } else if (ph == 2) {
+        k = 1;
+        ph = (gcv && lambert && k + 1 + u <= PT_LMAX - 1) ? 4 : 3;
+    } else if (ph == 4) {
+        if (++k + 1 + u > PT_LMAX - 1) ph = 3;
+    }
+}
+// does a path closed at an emitter after the vertices pushed so far belong to the proxy class?
+__host__ __device__ inline bool pstate_closes(uint32_t ph, uint32_t u)
+{
+    return (ph == 1 && u >= 1) || ph == 2 || ph == 4;
 }
 __device__ __forceinline__ bool class_ok(int filter, bool proxy_class)
 {
@@ -420,11 +433,14 @@ __global__ void k_feat_light(SceneDev S, LightBuf L, int lmax, float *feat, int 
 }
 
 // eye-side state machine over a connected light sub-path y_j .. y_1 (then the emitter, a D
-// vertex): is the full path in the proxy class?
-__device__ __forceinline__ bool light_tail_class(uint32_t ph, uint32_t uu, uint32_t sg, int j, int umax)
+// vertex): is the full path in the proxy class? (Lambertian flags exist for y_1 .. y_7; a class C
+// control vertex is never further along.)
+__host__ __device__ inline bool light_tail_class(uint32_t ph, uint32_t uu, uint32_t kk, uint32_t sg, int j, int umax,
+                                                 bool gcv)
 {
-    for (int i = j; i >= 1; --i) pstate_push(ph, uu, (sg >> i) & 1u, umax);
-    return (ph == 1 && uu >= 1) || ph == 2;
+    for (int i = j; i >= 1; --i)
+        pstate_push(ph, uu, kk, (sg >> i) & 1u, i < 8 && ((sg >> (16 + i)) & 1u), umax, gcv);
+    return pstate_closes(ph, uu);
 }
 
 // ---------------------------------------------------------------------------------- candidates
@@ -1606,6 +1622,7 @@ struct EyeParams {
     int M, cand_cap;
     MisK mk;             // strategy factors of the connection MIS
     int conn_on;         // light-vertex connections
+    int gcv;             // the proxy class holds class C (general control vertex) as well
 };
 // k_sel = M pi_inc c pi_sel: the proxy strategy's selection factor for a path whose first
 // diffuse eye vertex lies in T and whose y_{s-1} lies in S (surrogate used by both strategies)
@@ -1673,7 +1690,7 @@ __global__ void k_eye_shade(SceneDev S, EyeBuf E, EyeParams P, SubDev D, LightBu
             const float4 bt = E.beta[pid];
             const float3 beta = xyz(bt);
             uint32_t info = E.info[pid];
-            uint32_t ph = (info >> 9) & 3u, uu = (info >> 11) & 15u;
+            uint32_t ph = (info >> 9) & 7u, uu = (info >> 12) & 15u, kk = (info >> 16) & 7u;
             const bool prev_delta = (info >> 8) & 1u;
             float4 mis = P.labels_on ? E.mis[pid] : make_float4(0.f, 0.f, 0.f, 0.f);
             const int Tl = fbits(mis.y), Sl = fbits(mis.z);
@@ -1688,7 +1705,7 @@ __global__ void k_eye_shade(SceneDev S, EyeBuf E, EyeParams P, SubDev D, LightBu
             const int T_prev = fbits(m2.z);
             float3 add = f3(0.f, 0.f, 0.f);
             if (m.flags & MF_EMIT) {
-                const bool cls = (ph == 1 && uu >= 1) || ph == 2;
+                const bool cls = pstate_closes(ph, uu);
                 if (class_ok(P.filter, cls)) {
                     const float3 le = emission(S, tri, h.y, h.z, wo);
                     if (nonzero3(le)) {
@@ -1724,7 +1741,7 @@ __global__ void k_eye_shade(SceneDev S, EyeBuf E, EyeParams P, SubDev D, LightBu
                 const bool spec = (m.flags & MF_SPEC) != 0;
                 const bool z_dirac = (m.flags & MF_DELTA) != 0;
                 const uint32_t ph0 = ph, uu0 = uu;
-                pstate_push(ph, uu, spec, P.u_max);
+                pstate_push(ph, uu, kk, spec, m.type == MAT_LAMBERT, P.u_max, P.gcv != 0);
                 Rng r = rng_make(P.seed, S_EYE, (uint32_t)pid, iter_of(cnt), (uint32_t)t);
                 const bool at_zd = ph == 1 && uu == 0 && !spec;
                 int Tnew = Tl;
@@ -1744,7 +1761,7 @@ __global__ void k_eye_shade(SceneDev S, EyeBuf E, EyeParams P, SubDev D, LightBu
                     pi.mis = make_float4(rev_z, e0_t, 0.f, 0.f);
                 }
                 if (P.nee_on && !z_dirac && S.n_em > 0) {
-                    const bool cls = (ph == 1 && uu >= 1) || ph == 2;
+                    const bool cls = pstate_closes(ph, uu);
                     const bool mis3 = cls && P.mis_on && P.proxy_on;
                     if (class_ok(P.filter, cls)) {
                         const LPoint Lp = sample_emitter(S, u0, u1, u2);
@@ -1823,7 +1840,7 @@ __global__ void k_eye_shade(SceneDev S, EyeBuf E, EyeParams P, SubDev D, LightBu
                     const uint32_t v = (uint32_t)C.list[C.off[Sl] + kv];
                     const int j = (int)(v / (uint32_t)L.M), lp = (int)(v % (uint32_t)L.M);
                     const uint32_t sg = L.sig[lp];
-                    if (sel > 0.0f && t + j + 1 <= P.K && conn_ok(P, light_tail_class(ph, uu, sg, j, P.u_max))) {
+                    if (sel > 0.0f && t + j + 1 <= P.K && conn_ok(P, light_tail_class(ph, uu, kk, sg, j, P.u_max, P.gcv != 0))) {
                         const float4 yv = L.lv[v];
                         const int ty = fbits(yv.w);
                         const float3 y = xyz(yv), ny = S.shade[ty].n;
@@ -1875,7 +1892,7 @@ __global__ void k_eye_shade(SceneDev S, EyeBuf E, EyeParams P, SubDev D, LightBu
                         nro = make_float4(x.x, x.y, x.z, ibits(tri));
                         nrd = make_float4(bs.wi.x, bs.wi.y, bs.wi.z, 3.0e38f);
                         nbeta = make_float4(nb.x, nb.y, nb.z, bs.pdf);
-                        ninfo = (uint32_t)t | (bs.delta ? 1u << 8 : 0u) | (ph << 9) | (uu << 11);
+                        ninfo = (uint32_t)t | (bs.delta ? 1u << 8 : 0u) | (ph << 9) | (uu << 12) | (kk << 16);
                         nmis = make_float4(mis.x, ibits(Tnew), mis.z, 0.f);
                         // e_{t+1} d^2 = (K + e_t rev-pdf(z)) |cos| / rev(z), the light side being z_{t+1}
                         const float rp = rev_pdf(m, sh.n, bs.wi, wo), cw = fabsf(dot3(sh.n, bs.wi)) / rev_z;
@@ -1935,7 +1952,7 @@ __global__ void __launch_bounds__(WG) k_lt(SceneDev S, LightBuf L, EyeParams P, 
         const float3 wyc = dc * (1.0f / dist), dir = -wyc;
         const float ct = dot3(dir, cam.f);
         const uint32_t sg = L.sig[lp];
-        const bool cls = light_tail_class(0u, 0u, sg, j, P.u_max);
+        const bool cls = light_tail_class(0u, 0u, 0u, sg, j, P.u_max, P.gcv != 0);
         const bool with_proxy = P.proxy_on && P.mis_on;
         const bool ok = P.proxy_on ? (with_proxy ? class_ok(P.filter, cls) : (!cls && (P.filter == 0 || P.filter == 2)))
                                    : class_ok(P.filter, cls);

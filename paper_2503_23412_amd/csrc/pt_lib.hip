@@ -884,9 +884,8 @@ pt_status check_params(pt_scene *s, const pt_iter_params *p, float *acc)
     if ((p->flags & PT_FLAG_MLP) && !(p->mlp_mix >= 0.0f && p->mlp_mix < 1.0f && p->mlp_lr > 0.0f))
         return set_err(PT_EINVAL, "PT_FLAG_MLP needs 0 <= mlp_mix < 1 and mlp_lr > 0");
     if ((p->flags & PT_FLAG_BOOTH) && !(p->booth_r > 0.0f)) return set_err(PT_EINVAL, "PT_FLAG_BOOTH needs booth_r > 0");
-    if ((p->flags & PT_FLAG_GENERAL_CV) &&
-        (!(p->flags & PT_FLAG_PROXY) || !(p->flags & PT_FLAG_ONLY_PROXY_CLASS) || (p->flags & PT_FLAG_MIS)))
-        return set_err(PT_EINVAL, "PT_FLAG_GENERAL_CV needs PT_FLAG_PROXY and PT_FLAG_ONLY_PROXY_CLASS, without PT_FLAG_MIS");
+    if ((p->flags & PT_FLAG_GENERAL_CV) && (!(p->flags & PT_FLAG_PROXY) || (p->flags & PT_FLAG_MIS)))
+        return set_err(PT_EINVAL, "PT_FLAG_GENERAL_CV needs PT_FLAG_PROXY, without PT_FLAG_MIS");
     return PT_OK;
 }
 
@@ -1009,6 +1008,7 @@ pt_status enqueue_iteration(pt_scene *s, const pt_iter_params *p, float *acc, fl
     EP.tiles_on = tiles;
     EP.M = M; EP.cand_cap = p->cand_cap;
     EP.mk = mk; EP.conn_on = conn && lmax >= 2;
+    EP.gcv = (p->flags & PT_FLAG_GENERAL_CV) != 0;
     SubDev D{};
     if (s->n_eye > 0) {
         D.eye_c = s->eye_c; D.spec_c = s->spec_c; D.n_eye = ne; D.n_spec = ns;
@@ -1837,6 +1837,18 @@ extern "C" pt_status pt_bvh_stats(const float *tri, int32_t n_tri, int32_t width
     } catch (const std::exception &e) {
         return set_err(PT_ENOMEM, "host exception: %s", e.what());
     }
+}
+
+extern "C" pt_status pt_proxy_class(const uint8_t *eye, int32_t n_eye, uint32_t light_sig, int32_t j, int32_t u_max,
+                                    int32_t general_cv, int32_t *out)
+{
+    if (!out || n_eye < 0 || (n_eye > 0 && !eye) || j < 0 || j > 15 || u_max < 1 || u_max > 4)
+        return set_err(PT_EINVAL, "bad argument");
+    uint32_t ph = 0, uu = 0, kk = 0;
+    for (int i = 0; i < n_eye; ++i)
+        pstate_push(ph, uu, kk, (eye[i] & 1u) != 0, (eye[i] & 2u) != 0, u_max, general_cv != 0);
+    *out = light_tail_class(ph, uu, kk, light_sig, j, u_max, general_cv != 0) ? 1 : 0;
+    return PT_OK;
 }
 
 // ---------------------------------------------------------------------------------------------

@@ -37,7 +37,7 @@ EXPORTED = ["pt_scene_upload", "pt_scene_release", "pt_build_subspaces", "pt_ren
             "pt_render_scenes", "pt_autotune", "pt_set_schedule", "pt_get_schedule",
             "pt_mlp_param_count", "pt_mlp_set_params", "pt_mlp_get_params", "pt_mlp_forward", "pt_mlp_train_step",
             "pt_reciprocal_estimate", "pt_resolve_image", "pt_trace_closest", "pt_scene_totals",
-            "pt_selection_tables", "pt_iteration_times", "pt_philox", "pt_bvh_stats", "pt_reciprocal_estimate_noalloc",
+            "pt_selection_tables", "pt_iteration_times", "pt_philox", "pt_bvh_stats", "pt_reciprocal_estimate_noalloc", "pt_proxy_class",
             "pt_vmf_sample", "pt_last_error"]
 NOALLOC_TABLE_MAX = 1 << 20
 
@@ -147,6 +147,7 @@ def lib():
         L.pt_iteration_times.argtypes = [P, ctypes.c_uint32, I, P, P]
         L.pt_bvh_stats.argtypes = [P, I, I, P, P, P]
         L.pt_reciprocal_estimate_noalloc.argtypes = [ctypes.POINTER(RecipQuery), P, P, P]
+        L.pt_proxy_class.argtypes = [P, I, ctypes.c_uint32, I, I, I, ctypes.POINTER(I)]
         L.pt_last_error.restype = ctypes.c_char_p
         for name in EXPORTED:
             if name == "pt_last_error":
@@ -349,6 +350,16 @@ def bvh_stats(tri, width=4):
     _check(lib().pt_bvh_stats(t.ctypes.data, int(t.shape[0]), int(width), ctypes.byref(a), ctypes.byref(b),
                               ctypes.byref(c)))
     return a.value, b.value, c.value
+
+
+def proxy_class(eye_flags, light_sig=0, j=0, u_max=4, general_cv=0):
+    """Host-only: 1 when the path camera -> z_1 .. z_n (eye_flags: bit 0 specular, bit 1 Lambertian)
+    -> y_j .. y_1 (from the light signature light_sig) -> emitter is in the proxy class."""
+    e = np.ascontiguousarray(eye_flags, np.uint8)
+    out = ctypes.c_int32()
+    _check(lib().pt_proxy_class(e.ctypes.data if e.size else None, int(e.size), int(light_sig) & 0xFFFFFFFF, int(j),
+                                int(u_max), int(general_cv), ctypes.byref(out)))
+    return out.value
 
 
 def reciprocal_table_noalloc(f, q, B, n_est, out, nsamples, estimator=PT_EST_ITILDE, seed=1, cap=0, booth_r=1.0,

@@ -1,6 +1,7 @@
 """CPU checks of the C ABI: the library loads, exports every symbol include/pt.h declares, and
 rejects invalid arguments before touching a device."""
 import ctypes
+import itertools
 import os
 import re
 
@@ -88,3 +89,34 @@ def test_bvh_stack_need_fits_the_kernels(ptlib):
     # one triangle: a single node with one leaf child needs no stack
     one = np.array([[0, 0, 0, 1, 0, 0, 0, 1, 0]], np.float32)
     assert ptlib.bvh_stats(one) == (1, 0, 1) and ptlib.bvh_stats(one, width=8) == (1, 0, 1)
+
+
+def test_proxy_class_matches_the_oracle_on_every_short_path(ptlib, oracle):
+    """The proxy-class test the kernels apply (eye side, then the joined light tail from the light
+    sub-path signature) against the oracle's on every path of 1..7 vertices over {specular,
+    Lambertian, other diffuse}, every split into eye vertices and a joined light tail, u_max 1, 2,
+    4, with and without class C."""
+    n_paths = n_proxy = 0
+    for n in range(1, 8):
+        for mats in itertools.product("SLR", repeat=n):
+            is_s = [m == "S" for m in mats]
+            is_l = [m == "L" for m in mats]
+            eye = np.array([(1 if s else 0) | (2 if l else 0) for s, l in zip(is_s, is_l)], np.uint8)
+            for u_max in (1, 2, 4):
+                for gcv in (0, 1):
+                    want = oracle.proxy_class(is_s, is_l, u_max, gcv)
+                    n_paths += 1
+                    n_proxy += want
+                    for ne in range(n + 1):
+                        # z_1 .. z_ne on the eye side, the rest joined as y_j .. y_1 (y_k = z_{n+1-k})
+                        j = n - ne
+                        sig = 0
+                        for k in range(1, j + 1):
+                            z = n - k          # 0-based eye index of y_k
+                            sig |= (1 << k) if is_s[z] else 0
+                            sig |= (1 << (16 + k)) if is_l[z] else 0
+                        got = ptlib.proxy_class(eye[:ne], sig, j, u_max, gcv)
+                        assert got == want, ("".join(mats), ne, u_max, gcv, got, want)
+    assert 0 < n_proxy < n_paths
+    with pytest.raises(ptlib.PTError):
+        ptlib.proxy_class([0], 0, 0, u_max=5)

@@ -527,10 +527,11 @@ def _glass_ref():
     return mo, vo, float(mo.mean()), float(np.sqrt(vo.sum()) / mo.size)
 
 
-@pytest.mark.parametrize("mode", ["mis", "partition"])
+@pytest.mark.parametrize("mode", ["mis", "partition", "partition_gcv"])
 def test_glass_furnace_through_proxy(gpu, mode):
     """A lossless glass sphere in an emitting spherical enclosure (albedo 0.5, L_e = 1), depth 120,
-    with the proxy under MIS (with Gamma) or alone on its class (partition), against the oracle's
+    with the proxy under MIS (with Gamma) or alone on its class (partition; partition_gcv: its
+    class holds class C as well, u <= 1, and every other strategy leaves those paths to it), against the oracle's
     per-pixel depth-120 reference (O1, tests/golden/glass_furnace_o1_ref.npz, written by
     make_references.py). The pixels of one iteration share a few hundred candidates and their
     reciprocal estimates, and single iterations are heavy-tailed, so the GPU's per-pixel standard
@@ -554,8 +555,13 @@ def test_glass_furnace_through_proxy(gpu, mode):
                         enclosure="sphere")
     say(f"glass furnace {mode}")
     flags = pt.PT_FLAG_NEE | pt.PT_FLAG_PROXY | ((pt.PT_FLAG_MIS | pt.PT_FLAG_GAMMA) if mode == "mis" else 0)
+    extra = {}
+    if mode == "partition_gcv":
+        flags |= pt.PT_FLAG_GENERAL_CV
+        extra = dict(u_max=1)
     nb, per = (64, 64) if mode == "mis" else (32, 256)
-    m, v, img, tot = _render_batches(gpu, sc, nb, per, max_depth=K, n_light=1024, cand_cap=128, flags=flags)
+    m, v, img, tot = _render_batches(gpu, sc, nb, per, max_depth=K, n_light=1024, cand_cap=128, flags=flags,
+                                     **extra)
     mo, vo, omean, ose = _glass_ref()
     se = float(np.std(img, ddof=1) / np.sqrt(len(img)))
     zm = (m.mean() - omean) / math.hypot(se, ose)
