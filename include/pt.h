@@ -237,12 +237,15 @@ pt_status pt_render_scenes(pt_scene *const *scenes, const pt_iter_params *params
  * accum_sq (iterations p->iteration, +1, ...); their number is returned in iterations_rendered.
  * The knobs are timed one after another, so call it once the iteration's cost has settled: after
  * the first 40 iterations, in which the Gamma, Q and tile statistics learn (while they learn the
- * cost falls, and the value timed last would look best). Synchronises hip_stream. */
+ * cost falls, and the value timed last would look best). The starting knobs are timed twice
+ * before the descent, and at its end the chosen and the starting knobs are timed alternately
+ * twice each; the starting ones stay if they were faster (a transient slowdown during the descent
+ * leaves no slower schedule behind). Synchronises hip_stream. */
 typedef struct {
     uint32_t stage_a_budget;     /* chosen sample budget of the one-wavefront stage */
     int32_t round_grid;          /* chosen blocks of the round kernels */
-    float ms_best;               /* iteration time with the chosen schedule */
-    float ms_previous;           /* iteration time with the pair the scene had before */
+    float ms_best;               /* iteration time with the chosen schedule (final check) */
+    float ms_previous;           /* iteration time with the knobs the scene had before */
     uint32_t iterations_rendered;
     int32_t ext_wg;              /* chosen workgroup size of the extension launches */
     int32_t queue_chunk;         /* chosen chains per take from stage A's work queue */

@@ -1673,7 +1673,10 @@ extern "C" pt_status pt_autotune(pt_scene *s, const pt_iter_params *p, float *ac
     // both trees are there), the chain schedule (stage-A budget x round grid), the extension
     // workgroup size, the queue chunk
     int bv = v0;
+    // the incumbent twice (the faster counts), so that one slow measurement at the start (a
+    // transient of the device) does not make every alternative look better
     st = timed(dflt);
+    if (st == PT_OK && (st = timed(ms)) == PT_OK) dflt = std::min(dflt, ms);
     best = dflt;
     if (st == PT_OK && s->has4 && s->has8) {
         set_width(v0 == 4 ? 8 : 4);
@@ -1727,6 +1730,27 @@ extern "C" pt_status pt_autotune(pt_scene *s, const pt_iter_params *p, float *ac
         if ((st = timed(ms)) == PT_OK && ms < best_r) { best_r = ms; br = ri; }
     }
     s->refill = br;
+    // the chosen knobs against the ones the descent started from, timed alternately twice each:
+    // a transient slowdown during the descent must not leave a slower schedule in place
+    float ms_chosen = 3.0e38f, ms_start = 3.0e38f;
+    for (int r = 0; r < 2 && st == PT_OK; ++r) {
+        s->tune_budget = b0; s->tune_gen_grid = g0; s->ext_wg = w0; s->queue_chunk = c0; s->ahead = a0;
+        s->refill = r0;
+        set_width(v0);
+        if ((st = timed(ms)) != PT_OK) break;
+        ms_start = std::min(ms_start, ms);
+        s->tune_budget = bb; s->tune_gen_grid = bg; s->ext_wg = bw; s->queue_chunk = bc; s->ahead = ba;
+        s->refill = br;
+        set_width(bv);
+        if ((st = timed(ms)) != PT_OK) break;
+        ms_chosen = std::min(ms_chosen, ms);
+    }
+    if (st == PT_OK && ms_start < ms_chosen) {
+        bb = b0; bg = g0; bw = w0; bc = c0; ba = a0; br = r0; bv = v0;
+        s->tune_budget = bb; s->tune_gen_grid = bg; s->ext_wg = bw; s->queue_chunk = bc; s->ahead = ba;
+        s->refill = br;
+        set_width(bv);
+    }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (st != PT_OK) {
@@ -1743,8 +1767,8 @@ extern "C" pt_status pt_autotune(pt_scene *s, const pt_iter_params *p, float *ac
     out->stage_a_ahead = ba;
     out->stage_a_refill = br;
     out->bvh_width = s->bvh_cur;
-    out->ms_best = std::min(std::min(std::min(best, best_s), std::min(best_w, best_c)), std::min(best_a, best_r));
-    out->ms_previous = dflt;
+    out->ms_best = std::min(ms_start, ms_chosen);
+    out->ms_previous = std::min(dflt, ms_start);
     out->iterations_rendered = (uint32_t)used;
     return PT_OK;
 }
