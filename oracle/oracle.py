@@ -1,4 +1,4 @@
-"""ctypes wrapper of the FP64 CPU oracle (oracle.c).
+"""ctypes wrapper of the FP64 CPU oracle (oracle.c, and planes.c for the photon-plane workload).
 
 TEST INFRASTRUCTURE ONLY: imported by tests/, by the smoke check and by the CPU
 baseline leg of bench.py. The HIP library and its binding never import it.
@@ -12,15 +12,16 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB = os.path.join(HERE, "liboracle.so")
 SRC = os.path.join(HERE, "oracle.c")
+SRC_PLANES = os.path.join(HERE, "planes.c")
 
 
 def build(force=True):
-    """Compile oracle.c with gcc (O2, plain C11, pthreads)."""
+    """Compile oracle.c and planes.c with gcc (O2, plain C11, pthreads)."""
     if not force and os.path.exists(LIB):
         return LIB
     tmp = LIB + ".tmp"
     subprocess.check_call(["gcc", "-O2", "-std=c11", "-D_GNU_SOURCE", "-fPIC", "-shared", "-pthread",
-                           "-o", tmp, SRC, "-lm"])
+                           "-o", tmp, SRC, SRC_PLANES, "-lm"])
     os.replace(tmp, LIB)
     return LIB
 
@@ -71,6 +72,14 @@ def lib():
         L.or_philox4x32_10.argtypes = [P, P, P]
         L.or_bsdf_sample.argtypes = [P, P, P, ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_int, P]
         L.or_bsdf_eval.argtypes = [P, P, P, P, P]
+        D = ctypes.c_double
+        L.or_planes_chord.restype = D
+        L.or_planes_chord.argtypes = [D, D, D, D, D]
+        L.or_planes_J.restype = D
+        L.or_planes_J.argtypes = [D, D, D, D, D, D]
+        L.or_planes_reference.argtypes = [P, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, P]
+        L.or_planes_render.argtypes = [P, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_uint64, P,
+                                       P]
         L.or_proxy_class.restype = ctypes.c_int
         L.or_proxy_class.argtypes = [P, P, ctypes.c_int, ctypes.c_int, ctypes.c_int]
         _lib = L
@@ -115,6 +124,43 @@ def bsdf_eval(rec, n, wo, wi):
     out = np.zeros(4)
     lib().or_bsdf_eval(_p(rec), _p(n), _p(wo), _p(wi), _p(out))
     return out
+
+
+def planes_block(sc):
+    """The 27-double scene block of planes.c from a synth.scenes.planes_scene dictionary."""
+    b = np.concatenate([sc["light_c"], sc["light_u"], sc["light_v"], [sc["light_eu"], sc["light_ev"]], sc["le"],
+                        sc["camera"], [sc["sigma_s"], sc["sigma_t"], sc["t_max"]]]).astype(np.float64)
+    assert b.shape == (27,)
+    return np.ascontiguousarray(b)
+
+
+def planes_chord(eu, ev, a, b, alpha):
+    """Length of the chord of [-eu, eu] x [-ev, ev] through (a, b) at angle alpha."""
+    return lib().or_planes_chord(float(eu), float(ev), float(a), float(b), float(alpha))
+
+
+def planes_J(eu, ev, a, b, mu, mv):
+    """J = int_0^pi chord(alpha; a, b) |mu cos(alpha) + mv sin(alpha)| dalpha (piecewise Gauss-Legendre)."""
+    return lib().or_planes_J(float(eu), float(ev), float(a), float(b), float(mu), float(mv))
+
+
+def planes_reference(sc, nt=16, ny=8):
+    """Per-pixel single-scattered radiance of the pixel-centre rays by quadrature, [H, W, 3]."""
+    W, H = sc["width"], sc["height"]
+    img = np.zeros((H, W, 3))
+    blk = planes_block(sc)
+    lib().or_planes_reference(_p(blk), W, H, nt, ny, _p(img))
+    return img
+
+
+def planes_render(sc, n_planes, n_iter, seed=1):
+    """The photon-plane estimator with the exact reciprocal: per-pixel (sum, sumsq) over n_iter."""
+    W, H = sc["width"], sc["height"]
+    s = np.zeros((H, W, 3))
+    s2 = np.zeros((H, W, 3))
+    blk = planes_block(sc)
+    lib().or_planes_render(_p(blk), W, H, int(n_planes), int(n_iter), int(seed), _p(s), _p(s2))
+    return s, s2
 
 
 def proxy_class(is_s, is_lambert, u_max=4, general_cv=0):

@@ -484,3 +484,21 @@ def config(cfg_id):
 
 def tri_count(scene):
     return int(scene["tri"].shape[0])
+
+
+def planes_scene(width=64, height=64, sigma_s=0.5, sigma_t=0.6):
+    """The photon-plane workload (single scattering, Section 6.7's volumetric setting): a 1.0 x 0.6
+    rectangular Lambertian light 1.5 above the origin facing down (radiance 4), a homogeneous
+    medium filling space (isotropic phase function, sigma_s, sigma_t), nothing occluding, and a
+    pinhole camera below and in front looking up into the lit column (eye rays 15 to 40 degrees
+    above the light's plane, ending at t_max = 3.5, at least ~0.27 from the light). No eye ray runs
+    parallel to the light: there the CMIS estimate of a grazing plane grows like 1 / cos(theta)
+    and its variance diverges."""
+    return {
+        "light_c": np.array([0.0, 1.5, 0.0]), "light_u": np.array([1.0, 0.0, 0.0]),
+        "light_v": np.array([0.0, 0.0, 1.0]),   # emits toward u x v = (0, -1, 0)
+        "light_eu": 0.5, "light_ev": 0.3, "le": np.array([4.0, 4.0, 4.0]),
+        "camera": np.array([0.0, -1.0, 2.5, 0.0, 0.3, 0.0, 0.0, 1.0, 0.0, 24.0]),
+        "sigma_s": float(sigma_s), "sigma_t": float(sigma_t), "t_max": 3.5,
+        "width": int(width), "height": int(height),
+    }
