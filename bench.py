@@ -37,15 +37,18 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+# the headers that hold the device code of the render iteration's kernels (the photon-plane
+# kernels and the host file are not among them)
+KERNEL_SOURCES = ("pt_device.h", "pt_kernels.h", "pt_layout.h", "pt_mlp.h", "pt_subspace.h")
+
+
 def kernel_source_hash():
-    import glob
     import hashlib
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2503_23412_amd", "csrc")
-    for f in sorted(glob.glob(os.path.join(csrc, "*.h")) + glob.glob(os.path.join(csrc, "*.hip")),
-                    key=os.path.basename):
-        h.update(os.path.basename(f).encode())
-        with open(f, "rb") as fh:
+    for name in KERNEL_SOURCES:
+        h.update(name.encode())
+        with open(os.path.join(csrc, name), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
 

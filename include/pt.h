@@ -423,6 +423,48 @@ pt_status pt_bvh_stats(const float *tri, int32_t n_tri, int32_t width, int32_t *
 pt_status pt_proxy_class(const uint8_t *eye, int32_t n_eye, uint32_t light_sig, int32_t j, int32_t u_max,
                          int32_t general_cv, int32_t *out);
 
+/* ---------------------------------------------------------------------------------------------
+ * Photon planes (Section 6.7): reciprocal estimation as the CMIS weight of a continuous technique
+ * space. Single scattering in a homogeneous medium (isotropic phase function, filling space,
+ * nothing occluding) lit by one rectangular Lambertian light, rendered with photon planes: a point
+ * uniform on the light, a chord angle alpha uniform in [0, pi) (the light's chord through that
+ * point) and a cosine-distributed direction w span a plane; each pixel's centre ray gathers every
+ * plane it meets. alpha is the technique: the balance-heuristic weight over [0, pi) needs
+ * 1 / int p(alpha, xbar) dalpha, which one chain of the RRS estimator (Section 4.2, r = |g|)
+ * estimates without bias, with the supporting density q(alpha | xbar) read from a cached
+ * piecewise approximation of q* ~ p(., xbar) indexed by the light point and the angle that the
+ * eye and plane directions fix (2 MB, built at creation). */
+#define PT_PLANES_MAX (1 << 22)
+typedef struct pt_planes pt_planes;
+typedef struct {
+    float light_c[3];        /* light centre */
+    float light_u[3], light_v[3];   /* orthonormal axes; the light emits toward u x v */
+    float light_eu, light_ev;       /* half extents along u and v */
+    float le[3];             /* emitted radiance */
+    float camera[10];        /* position, target, up, vertical fov (degrees) */
+    float sigma_s, sigma_t;  /* scattering and extinction coefficients */
+    float t_max;             /* eye rays end at this distance */
+    int32_t width, height;
+    int32_t max_planes;      /* largest n_planes of a render call (<= PT_PLANES_MAX) */
+} pt_planes_desc;
+typedef struct {
+    double n_hits;           /* ray-plane hits of the call */
+    double n_samples;        /* f/q samples of their reciprocal chains */
+    double n_truncated;      /* chains cut at 4,096 samples (their estimates are biased) */
+    double n_nan;            /* pixels whose value was not finite (not accumulated) */
+} pt_planes_stats;
+/* Validates the description (PT_EINVAL), allocates the device buffers (PT_ENOMEM) and builds the
+ * q* cache on hip_stream (synchronised). */
+pt_status pt_planes_create(const pt_planes_desc *desc, void *hip_stream, pt_planes **out);
+/* One iteration: n_planes planes (0 <= n_planes <= max_planes) keyed by (seed, iteration); adds
+ * each pixel's value (the mean over the planes of the hits' estimates, RGB) to accum_rgb_dev
+ * [width*height*3] and its square to accum_sq_dev (may be NULL). Device buffers, row-major pixels.
+ * Kernel launches only, unless stats is non-NULL (then it synchronises and fills *stats). */
+pt_status pt_planes_render(pt_planes *p, int32_t n_planes, uint32_t iteration, uint32_t seed, float *accum_rgb_dev,
+                           float *accum_sq_dev, pt_planes_stats *stats, void *hip_stream);
+/* Frees the object (synchronises the device). NULL is a no-op. */
+pt_status pt_planes_release(pt_planes *p);
+
 /* Message for the last non-OK return on this thread ("" if none). */
 const char *pt_last_error(void);
 

@@ -13,6 +13,7 @@
 
 #include "../../include/pt.h"
 #include "pt_kernels.h"
+#include "pt_planes.h"
 
 void pt_build_bvh(const float *tri, int n, std::vector<BNode> &nodes, std::vector<BNode8> *nodes8,
                   std::vector<int> &order);
@@ -1861,6 +1862,117 @@ extern "C" pt_status pt_bvh_stats(const float *tri, int32_t n_tri, int32_t width
     } catch (const std::exception &e) {
         return set_err(PT_ENOMEM, "host exception: %s", e.what());
     }
+}
+
+// ---------------------------------------------------------------------------------------------
+// Photon planes (single scattering, Section 6.7)
+struct pt_planes {
+    PlaneDev P{};
+    uint32_t *alias = nullptr;
+    float *pk = nullptr;
+    float *z = nullptr;
+    PlaneRec *planes = nullptr;
+    unsigned long long *cnt = nullptr;
+    int max_planes = 0;
+    ~pt_planes()
+    {
+        (void)hipFree(alias); (void)hipFree(pk); (void)hipFree(z); (void)hipFree(planes); (void)hipFree(cnt);
+    }
+};
+
+extern "C" pt_status pt_planes_create(const pt_planes_desc *d, void *stream_, pt_planes **out)
+{
+    if (!d || !out) return set_err(PT_EINVAL, "null argument");
+    *out = nullptr;
+    const float *U = d->light_u, *V = d->light_v;
+    const float uu = U[0] * U[0] + U[1] * U[1] + U[2] * U[2], vv = V[0] * V[0] + V[1] * V[1] + V[2] * V[2];
+    const float uv = U[0] * V[0] + U[1] * V[1] + U[2] * V[2];
+    if (!(fabsf(uu - 1.0f) < 1e-4f && fabsf(vv - 1.0f) < 1e-4f && fabsf(uv) < 1e-4f))
+        return set_err(PT_EINVAL, "light axes must be orthonormal");
+    if (!(d->light_eu > 0.0f && d->light_ev > 0.0f)) return set_err(PT_EINVAL, "light half extents must be positive");
+    if (!(d->sigma_s >= 0.0f && d->sigma_t >= 0.0f && d->t_max > 0.0f))
+        return set_err(PT_EINVAL, "need sigma_s >= 0, sigma_t >= 0, t_max > 0");
+    if (d->width <= 0 || d->height <= 0 || (long)d->width * d->height > (1L << 26))
+        return set_err(PT_EINVAL, "bad image size %d x %d", d->width, d->height);
+    if (d->max_planes <= 0 || d->max_planes > PT_PLANES_MAX)
+        return set_err(PT_EINVAL, "max_planes must be in [1, %d]", PT_PLANES_MAX);
+    const float *cam = d->camera;
+    const float3 cp = make_float3(cam[0], cam[1], cam[2]), tg = make_float3(cam[3], cam[4], cam[5]), up = make_float3(cam[6], cam[7], cam[8]);
+    float3 fw = make_float3(tg.x - cp.x, tg.y - cp.y, tg.z - cp.z);
+    const float lf = sqrtf(fw.x * fw.x + fw.y * fw.y + fw.z * fw.z);
+    float3 rt = make_float3(fw.y * up.z - fw.z * up.y, fw.z * up.x - fw.x * up.z, fw.x * up.y - fw.y * up.x);
+    const float lr = sqrtf(rt.x * rt.x + rt.y * rt.y + rt.z * rt.z);
+    if (!(lf > 0.0f && lr > 0.0f && cam[9] > 0.0f && cam[9] < 180.0f))
+        return set_err(PT_EINVAL, "degenerate camera");
+    TRY(check_device());
+    hipStream_t st = (hipStream_t)stream_;
+    pt_planes *p = new pt_planes();
+    PlaneDev &P = p->P;
+    P.c = make_float3(d->light_c[0], d->light_c[1], d->light_c[2]);
+    P.U = make_float3(U[0], U[1], U[2]);
+    P.V = make_float3(V[0], V[1], V[2]);
+    P.N = make_float3(U[1] * V[2] - U[2] * V[1], U[2] * V[0] - U[0] * V[2], U[0] * V[1] - U[1] * V[0]);
+    P.eu = d->light_eu; P.ev = d->light_ev; P.area = 4.0f * d->light_eu * d->light_ev;
+    P.le = make_float3(d->le[0], d->le[1], d->le[2]);
+    P.cam_p = cp;
+    P.cam_f = make_float3(fw.x / lf, fw.y / lf, fw.z / lf);
+    P.cam_r = make_float3(rt.x / lr, rt.y / lr, rt.z / lr);
+    P.cam_u = make_float3(P.cam_r.y * P.cam_f.z - P.cam_r.z * P.cam_f.y, P.cam_r.z * P.cam_f.x - P.cam_r.x * P.cam_f.z,
+                 P.cam_r.x * P.cam_f.y - P.cam_r.y * P.cam_f.x);
+    P.tan_half = tanf(0.5f * cam[9] * 3.14159265358979f / 180.0f);
+    P.aspect = (float)d->width / (float)d->height;
+    P.ss = d->sigma_s; P.st = d->sigma_t; P.tmax = d->t_max;
+    P.w = d->width; P.h = d->height;
+    p->max_planes = d->max_planes;
+    if (hipMalloc((void **)&p->alias, sizeof(uint32_t) * PL_ENTRIES * PL_BINS) != hipSuccess ||
+        hipMalloc((void **)&p->pk, sizeof(float) * PL_ENTRIES * PL_BINS) != hipSuccess ||
+        hipMalloc((void **)&p->z, sizeof(float) * PL_ENTRIES) != hipSuccess ||
+        hipMalloc((void **)&p->planes, sizeof(PlaneRec) * (size_t)d->max_planes) != hipSuccess ||
+        hipMalloc((void **)&p->cnt, sizeof(unsigned long long) * PC_COUNT) != hipSuccess) {
+        (void)hipGetLastError();
+        delete p;
+        return set_err(PT_ENOMEM, "photon-plane buffers");
+    }
+    P.alias = p->alias; P.pk = p->pk; P.z = p->z;
+    k_planes_cache<<<blocks(PL_ENTRIES, 256), 256, 0, st>>>(P, p->alias, p->pk, p->z);
+    if (hipGetLastError() != hipSuccess || hipStreamSynchronize(st) != hipSuccess) {
+        delete p;
+        return set_err(PT_EDEVICE, "photon-plane cache");
+    }
+    *out = p;
+    return PT_OK;
+}
+
+extern "C" pt_status pt_planes_render(pt_planes *p, int32_t n_planes, uint32_t iteration, uint32_t seed,
+                                      float *acc, float *acc2, pt_planes_stats *stats, void *stream_)
+{
+    if (!p || !acc) return set_err(PT_EINVAL, "null argument");
+    if (n_planes < 0 || n_planes > p->max_planes)
+        return set_err(PT_EINVAL, "n_planes %d outside [0, %d]", n_planes, p->max_planes);
+    hipStream_t st = (hipStream_t)stream_;
+    k_fill_u64<<<1, 64, 0, st>>>(p->cnt, 0ull, PC_COUNT);
+    if (n_planes > 0) k_planes_gen<<<blocks(n_planes, 256), 256, 0, st>>>(p->P, n_planes, seed, iteration, p->planes);
+    k_planes_gather<<<blocks((long)p->P.w * p->P.h, 256), 256, 0, st>>>(p->P, p->planes, n_planes, seed, iteration,
+                                                                        acc, acc2, p->cnt);
+    HIPCHK(hipGetLastError());
+    if (stats) {
+        unsigned long long c[PC_COUNT];
+        HIPCHK(hipMemcpyAsync(c, p->cnt, sizeof(c), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        stats->n_hits = (double)c[PC_HITS];
+        stats->n_samples = (double)c[PC_SAMPLES];
+        stats->n_truncated = (double)c[PC_TRUNC];
+        stats->n_nan = (double)c[PC_NAN];
+    }
+    return PT_OK;
+}
+
+extern "C" pt_status pt_planes_release(pt_planes *p)
+{
+    if (!p) return PT_OK;
+    (void)hipDeviceSynchronize();
+    delete p;
+    return PT_OK;
 }
 
 extern "C" pt_status pt_proxy_class(const uint8_t *eye, int32_t n_eye, uint32_t light_sig, int32_t j, int32_t u_max,

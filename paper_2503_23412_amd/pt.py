@@ -37,9 +37,11 @@ EXPORTED = ["pt_scene_upload", "pt_scene_release", "pt_build_subspaces", "pt_ren
             "pt_render_scenes", "pt_autotune", "pt_set_schedule", "pt_get_schedule",
             "pt_mlp_param_count", "pt_mlp_set_params", "pt_mlp_get_params", "pt_mlp_forward", "pt_mlp_train_step",
             "pt_reciprocal_estimate", "pt_resolve_image", "pt_trace_closest", "pt_scene_totals",
-            "pt_selection_tables", "pt_iteration_times", "pt_philox", "pt_bvh_stats", "pt_reciprocal_estimate_noalloc", "pt_proxy_class",
-            "pt_vmf_sample", "pt_last_error"]
+            "pt_selection_tables", "pt_iteration_times", "pt_philox", "pt_bvh_stats", "pt_reciprocal_estimate_noalloc",
+            "pt_proxy_class", "pt_vmf_sample", "pt_planes_create", "pt_planes_render", "pt_planes_release",
+            "pt_last_error"]
 NOALLOC_TABLE_MAX = 1 << 20
+PLANES_MAX = 1 << 22
 
 
 class SceneDesc(ctypes.Structure):
@@ -148,6 +150,9 @@ def lib():
         L.pt_bvh_stats.argtypes = [P, I, I, P, P, P]
         L.pt_reciprocal_estimate_noalloc.argtypes = [ctypes.POINTER(RecipQuery), P, P, P]
         L.pt_proxy_class.argtypes = [P, I, ctypes.c_uint32, I, I, I, ctypes.POINTER(I)]
+        L.pt_planes_create.argtypes = [ctypes.POINTER(PlanesDesc), P, ctypes.POINTER(P)]
+        L.pt_planes_render.argtypes = [P, I, ctypes.c_uint32, ctypes.c_uint32, P, P, ctypes.POINTER(PlanesStats), P]
+        L.pt_planes_release.argtypes = [P]
         L.pt_last_error.restype = ctypes.c_char_p
         for name in EXPORTED:
             if name == "pt_last_error":
@@ -184,6 +189,50 @@ def default_params(**kw):
              flags=PT_FLAG_NEE | PT_FLAG_PROXY, mlp_lr=1e-3, mlp_mix=0.9, booth_r=1.0)
     p.update(kw)
     return p
+
+
+class PlanesDesc(ctypes.Structure):
+    _fields_ = [("light_c", ctypes.c_float * 3), ("light_u", ctypes.c_float * 3), ("light_v", ctypes.c_float * 3),
+                ("light_eu", ctypes.c_float), ("light_ev", ctypes.c_float), ("le", ctypes.c_float * 3),
+                ("camera", ctypes.c_float * 10), ("sigma_s", ctypes.c_float), ("sigma_t", ctypes.c_float),
+                ("t_max", ctypes.c_float), ("width", ctypes.c_int32), ("height", ctypes.c_int32),
+                ("max_planes", ctypes.c_int32)]
+
+
+class PlanesStats(ctypes.Structure):
+    _fields_ = [("n_hits", ctypes.c_double), ("n_samples", ctypes.c_double), ("n_truncated", ctypes.c_double),
+                ("n_nan", ctypes.c_double)]
+
+
+class Planes:
+    """Photon-plane single scattering (pt_planes_*) for a synth.scenes.planes_scene dictionary."""
+
+    def __init__(self, sc, max_planes, stream=None):
+        f = lambda v, n: (ctypes.c_float * n)(*[float(x) for x in v])  # noqa: E731
+        d = PlanesDesc(f(sc["light_c"], 3), f(sc["light_u"], 3), f(sc["light_v"], 3), float(sc["light_eu"]),
+                       float(sc["light_ev"]), f(sc["le"], 3), f(sc["camera"], 10), float(sc["sigma_s"]),
+                       float(sc["sigma_t"]), float(sc["t_max"]), int(sc["width"]), int(sc["height"]),
+                       int(max_planes))
+        self.h = ctypes.c_void_p()
+        self.W, self.H = int(sc["width"]), int(sc["height"])
+        _check(lib().pt_planes_create(ctypes.byref(d), _stream(stream), ctypes.byref(self.h)))
+
+    def render(self, accum, accum_sq, n_planes, iteration=0, seed=1, stats=False, stream=None):
+        st = PlanesStats() if stats else None
+        _check(lib().pt_planes_render(self.h, int(n_planes), int(iteration), int(seed), _ptr(accum), _ptr(accum_sq),
+                                      ctypes.byref(st) if st is not None else None, _stream(stream)))
+        return {k: getattr(st, k) for k, _ in PlanesStats._fields_} if st is not None else None
+
+    def release(self):
+        if self.h:
+            lib().pt_planes_release(self.h)
+            self.h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.release()
+        except Exception:
+            pass
 
 
 class Scene:

@@ -38,6 +38,8 @@ def test_struct_sizes_match_header(ptlib):
     assert ctypes.sizeof(ptlib.SubspaceParams) == 7 * 4
     assert ctypes.sizeof(ptlib.Totals) == 9 * 8
     assert ctypes.sizeof(ptlib.TuneResult) == 10 * 4
+    assert ctypes.sizeof(ptlib.PlanesDesc) == (3 * 3 + 2 + 3 + 10 + 3) * 4 + 3 * 4
+    assert ctypes.sizeof(ptlib.PlanesStats) == 4 * 8
 
 
 def test_invalid_arguments_rejected_without_device(ptlib):
@@ -67,6 +69,25 @@ def test_invalid_arguments_rejected_without_device(ptlib):
     assert L.pt_reciprocal_estimate(None, None, None, None, None) == -1
     assert L.pt_resolve_image(None, None, 1, None, None) == -1
     assert L.pt_scene_release(None) == 0
+    # photon planes: the description is validated before any device call
+    from synth import scenes
+    sc = scenes.planes_scene(8, 8)
+    f = lambda v, n: (ctypes.c_float * n)(*[float(x) for x in v])  # noqa: E731
+    def desc(**kw):
+        v = dict(sc, max_planes=64)
+        v.update(kw)
+        return ptlib.PlanesDesc(f(v["light_c"], 3), f(v["light_u"], 3), f(v["light_v"], 3), v["light_eu"],
+                                v["light_ev"], f(v["le"], 3), f(v["camera"], 10), v["sigma_s"], v["sigma_t"],
+                                v["t_max"], v["width"], v["height"], v["max_planes"])
+    hp = ctypes.c_void_p()
+    for bad, msg in ((dict(light_v=[1.0, 0.0, 0.0]), b"orthonormal"), (dict(light_eu=0.0), b"half extents"),
+                     (dict(sigma_t=-1.0), b"sigma"), (dict(width=0), b"image size"),
+                     (dict(max_planes=0), b"max_planes"), (dict(max_planes=ptlib.PLANES_MAX + 1), b"max_planes"),
+                     (dict(camera=[0, 0, 0, 0, 0, 0, 0, 1, 0, 30]), b"camera")):
+        assert L.pt_planes_create(ctypes.byref(desc(**bad)), None, ctypes.byref(hp)) == -1, bad
+        assert msg in L.pt_last_error(), (bad, L.pt_last_error())
+    assert L.pt_planes_render(None, 1, 0, 0, None, None, None, None) == -1
+    assert L.pt_planes_release(None) == 0
 
 
 def test_bvh_stack_need_fits_the_kernels(ptlib):

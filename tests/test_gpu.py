@@ -666,6 +666,51 @@ def test_general_control_vertex_matches_oracle(gpu, oracle):
     assert st["n_recip_truncated"] == 0 and st["n_proxy_valid"] > 0 and st["n_nan"] == 0
 
 
+# ------------------------------------------------------------------------------ photon planes
+@pytest.mark.parametrize("n_planes", [1000, 0])
+def test_photon_planes_match_single_scattering_reference(gpu, oracle, n_planes):
+    """Photon planes with the CMIS weight from one RRS chain per hit (pt_planes_*), 34 x 30 pixels
+    (a ragged last workgroup) and 1,000 planes per iteration (a ragged last LDS tile), against the
+    oracle's per-pixel single-scattering reference by quadrature: at least 99.9 % of pixels within
+    4 standard errors (iterations are i.i.d.), the image mean within 4 standard errors of the
+    per-iteration image means (the pixels of one iteration share its planes), no truncated chain.
+    n_planes = 0: the image stays black."""
+    from synth import scenes
+    torch, pt = gpu
+    sc = scenes.planes_scene(34, 30)
+    W, H = sc["width"], sc["height"]
+    P = pt.Planes(sc, max_planes=1024)
+    acc = torch.zeros(W * H * 3, device="cuda")
+    acc2 = torch.zeros_like(acc)
+    N = 1024 if n_planes else 4
+    sums = torch.zeros(N + 1, dtype=torch.float64, device="cuda")
+    tot = {"n_hits": 0.0, "n_samples": 0.0, "n_truncated": 0.0, "n_nan": 0.0}
+    for k in range(N):
+        st = P.render(acc, acc2, n_planes, iteration=k, seed=5, stats=(k % 64 == 0 or k == N - 1))
+        sums[k + 1] = acc.double().sum()
+        if st:
+            for key in tot:
+                tot[key] += st[key]
+    torch.cuda.synchronize()
+    P.release()
+    if not n_planes:
+        assert float(acc.abs().max()) == 0.0 and tot["n_hits"] == 0
+        return
+    ref = oracle.planes_reference(sc)
+    m = (acc / N).double().cpu().numpy().reshape(H, W, 3)
+    v = np.maximum((acc2 / N).double().cpu().numpy().reshape(H, W, 3) - m * m, 0) / N
+    z = (m - ref) / np.sqrt(v + 1e-30)
+    its = ((sums[1:] - sums[:-1]) / (W * H * 3)).cpu().numpy()
+    se = float(np.std(its, ddof=1)) / math.sqrt(N)
+    zm = (m.mean() - ref.mean()) / se
+    say(f"photon planes: mean {m.mean():.6f} ref {ref.mean():.6f} z {zm:.2f}; per pixel frac |z|<4 "
+        f"{(np.abs(z[..., 0]) < 4).mean():.4f} max|z| {np.abs(z[..., 0]).max():.2f} z mean {z[..., 0].mean():.3f} "
+        f"std {z[..., 0].std():.3f}; counters (every 64th iteration) {tot}")
+    assert (np.abs(z[..., 0]) < 4).mean() >= 0.999
+    assert abs(zm) < 4
+    assert tot["n_hits"] > 0 and tot["n_truncated"] == 0 and tot["n_nan"] == 0
+
+
 def test_learned_proposal_proxy_class_matches_oracle(gpu):
     """The proxy strategy alone with both learned heads on (PT_FLAG_MLP: the subspace picked by the
     network's softmax mixed with 10 % of the plain row; PT_FLAG_MLP_DIR: the first retrace direction
