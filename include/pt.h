@@ -433,7 +433,7 @@ pt_status pt_proxy_class(const uint8_t *eye, int32_t n_eye, uint32_t light_sig, 
  * 1 / int p(alpha, xbar) dalpha, which one chain of the RRS estimator (Section 4.2, r = |g|)
  * estimates without bias, with the supporting density q(alpha | xbar) read from a cached
  * piecewise approximation of q* ~ p(., xbar) indexed by the light point and the angle that the
- * eye and plane directions fix (2 MB, built at creation). */
+ * eye and plane directions fix (4 MB, built at creation). */
 #define PT_PLANES_MAX (1 << 22)
 typedef struct pt_planes pt_planes;
 typedef struct {
