@@ -459,7 +459,8 @@ pt_status pt_planes_create(const pt_planes_desc *desc, void *hip_stream, pt_plan
 /* One iteration: n_planes planes (0 <= n_planes <= max_planes) keyed by (seed, iteration); adds
  * each pixel's value (the mean over the planes of the hits' estimates, RGB) to accum_rgb_dev
  * [width*height*3] and its square to accum_sq_dev (may be NULL). Device buffers, row-major pixels.
- * Kernel launches only, unless stats is non-NULL (then it synchronises and fills *stats). */
+ * Kernel launches only, unless stats is non-NULL (then it synchronises and fills *stats). Calls on
+ * one object share its plane buffer and counters: issue them on one stream (or order them). */
 pt_status pt_planes_render(pt_planes *p, int32_t n_planes, uint32_t iteration, uint32_t seed, float *accum_rgb_dev,
                            float *accum_sq_dev, pt_planes_stats *stats, void *hip_stream);
 /* Frees the object (synchronises the device). NULL is a no-op. */
