@@ -836,9 +836,10 @@ typedef struct {
     double cost_cap;   /* expected chain samples per candidate above which it is roulette-kept */
     int o3_weights;    /* O3 only: 0 balance heuristic, 1 uniform over the strategies that can
                         * build the path, 2 light tracing alone (pins of the strategies) */
-    int general_cv;    /* O1 class filter: 1 when the proxy class also holds the paths of a general
-                        * control vertex (Section 5.2): ... h_c D S^u z_d with h_c = y_j, j >= 1, a
-                        * Lambertian vertex, and j + 1 + u < LMAX_GCV (the stored light vertices) */
+    int general_cv;    /* O1's class filter and O2: 1 when the proxy class also holds the paths of a
+                        * general control vertex (Section 5.2): ... h_c D S^u z_d with h_c = y_j,
+                        * j >= 1, a Lambertian vertex, and j + 1 + u < LMAX_GCV (the stored light
+                        * vertices); O2 then builds them from class C candidates */
 } or_params;
 
 typedef struct {
@@ -977,14 +978,23 @@ static void eye_row(void *ctx, int py)
 /* O2: light sub-paths, incomplete sub-path candidates, reciprocal estimates  */
 /* ------------------------------------------------------------------------- */
 #define LMAX 6   /* light vertices stored per sub-path: y_0 .. y_5 (class B with u = 4) */
-typedef struct { v3 p, n; int prim; double b1, b2; int is_s; } lvert_t;
+typedef struct {
+    v3 p, n; int prim; double b1, b2; int is_s;
+    int is_lam;       /* Lambertian (a possible general control vertex) */
+    double beta[3];   /* the light tracer's throughput arriving at the vertex: L_e A pi at y_1, then
+                       * times the adjoint BSDF weight f |cos| / pdf of every vertex passed */
+} lvert_t;
 typedef struct { lvert_t v[LMAX]; int nv; } lpath_t;
 
 typedef struct {
-    int cls;          /* 0: class A = L_DD S^u, h_c null; 1: class B = L_DD D S^u, h_c = y_0 */
+    int cls;          /* 0: class A = L_DD S^u, h_c null; 1: class B = L_DD D S^u, h_c = y_0;
+                       * 2: class C (general control vertex), h_c = y_j on a Lambertian surface */
     int u;            /* length of the trailing specular run */
+    int j;            /* class C: the light-order index of h_c */
     lvert_t v;        /* y_{s-1}, the specular vertex that is kept */
-    lvert_t hc;       /* y_0 for class B */
+    lvert_t hc;       /* y_0 for class B; y_j for class C with its normal turned toward y_{j-1}
+                       * (the side its BSDF is sampled on from the control direction) */
+    v3 wc;            /* class C: the direction from h_c toward y_{j-1} */
     double recip;     /* averaged reciprocal estimate of 1 / P(u, h_c, y_{s-1}, w_c) */
     double B;         /* the constant B used by this candidate's chains */
     double rho;       /* probability of keeping it after the pilot (cost roulette) */
@@ -995,9 +1005,9 @@ struct o2_iter {
     cand_t *cand; int ncand;
     int *kept; int nkept;
     double pi_inc;
-    double B[2][5];
+    double B[3][5];
     /* per-iteration statistics of f/q samples, per (class, u) bucket */
-    double fq_max[2][5], fq_sum[2][5], fq_n[2][5];
+    double fq_max[3][5], fq_sum[3][5], fq_n[3][5];
     double n_samples, n_trunc;
     long proxy_attempts, proxy_valid;
     pthread_mutex_t mu;
@@ -1019,8 +1029,13 @@ static void light_path(void *ctx, int l)
     if (!sample_light(s, &r, &y0)) return;
     lvert_t *v0 = &lp->v[0];
     v0->p = y0.p; v0->n = y0.n; v0->prim = y0.prim; v0->b1 = y0.b1; v0->b2 = y0.b2; v0->is_s = 0;
+    v0->is_lam = 0; v0->beta[0] = v0->beta[1] = v0->beta[2] = 0.0;
     lp->nv = 1;
     v3 d = cosine_dir(y0.n, rng_u01(&r), rng_u01(&r));
+    /* throughput of the ray leaving y_0: L_e cos / (p_A p_w) with p_A = 1/A, p_w = cos/pi */
+    double beta[3];
+    emitted(s, y0.prim, y0.b1, y0.b2, d, beta);
+    for (int k = 0; k < 3; ++k) beta[k] *= s->em_area * PI;
     v3 o = y0.p;
     int ign = y0.prim;
     int lmax = c->p->max_depth - 1 < LMAX ? c->p->max_depth - 1 : LMAX;
@@ -1031,16 +1046,21 @@ static void light_path(void *ctx, int l)
         v->p = hit_point(s, &h); v->n = s->tri[h.prim].n; v->prim = h.prim; v->b1 = h.b1; v->b2 = h.b2;
         const mat_t *m = &s->mat[s->tri[h.prim].mat];
         v->is_s = m->spec;
+        v->is_lam = m->type == MAT_LAMBERT;
+        for (int k = 0; k < 3; ++k) v->beta[k] = beta[k];
         bsample_t bs = bsdf_sample(m, v->n, vscl(d, -1.0), rng_u01(&r), rng_u01(&r), rng_u01(&r), MODE_LIGHT);
         if (!bs.ok) break;
+        for (int k = 0; k < 3; ++k) beta[k] *= bs.w[k];
         o = v->p; d = bs.wi; ign = h.prim;
     }
 }
 
 /* Section 5.1 / 6.1: every prefix ending at a specular vertex whose trailing specular run
  * (length u in [1, u_max]) starts at y_1 (class A, h_c null) or at y_2 after a diffuse y_1
- * (class B, h_c = y_0) is an incomplete sub-path candidate (reading R11). */
-static int collect_candidates(const lpath_t *lp, int u_max, cand_t *out)
+ * (class B, h_c = y_0) is an incomplete sub-path candidate (reading R11); with gcv also a run
+ * that starts at y_{j+2} after a diffuse y_{j+1} and a Lambertian y_j, j >= 1 (class C, h_c =
+ * y_j, Section 5.2). */
+static int collect_candidates(const lpath_t *lp, int u_max, int gcv, cand_t *out)
 {
     int n = 0;
     if (lp->nv < 2) return 0;
@@ -1055,6 +1075,16 @@ static int collect_candidates(const lpath_t *lp, int u_max, cand_t *out)
             c->cls = 1; c->u = i - 1; c->v = lp->v[i]; c->hc = lp->v[0];
         }
     }
+    if (gcv)
+        for (int j = 1; j + 2 < lp->nv; ++j) {
+            if (!lp->v[j].is_lam || lp->v[j + 1].is_s) continue;
+            for (int i = j + 2; i < lp->nv && lp->v[i].is_s && i - j - 1 <= u_max; ++i) {
+                cand_t *c = &out[n++];
+                c->cls = 2; c->u = i - j - 1; c->j = j; c->v = lp->v[i]; c->hc = lp->v[j];
+                c->wc = vnorm(vsub(lp->v[j - 1].p, lp->v[j].p));
+                if (vdot(c->hc.n, c->wc) < 0) c->hc.n = vscl(c->hc.n, -1.0);
+            }
+        }
     return n;
 }
 
@@ -1336,7 +1366,7 @@ static double proxy_connect(const scene_t *s, const or_params *p, struct o2_iter
     const cand_t *c = &it->cand[it->kept[k]];
     double pi_j = 1.0 / it->nkept;
     pthread_mutex_lock(&it->mu); it->proxy_attempts++; pthread_mutex_unlock(&it->mu);
-    int segs = d + 1 + c->u + (c->cls == 1 ? 1 : 0);
+    int segs = d + 1 + c->u + (c->cls == 0 ? 0 : 1 + c->j);
     if (segs > p->max_depth) return 0.0;
     v3 dv = vsub(c->v.p, xd);
     double d2 = vdot(dv, dv), dist = sqrt(d2);
@@ -1376,10 +1406,18 @@ static double proxy_connect(const scene_t *s, const or_params *p, struct o2_iter
             bsdf_eval(mh, s->tri[h.prim].n, vscl(bs.wi, -1.0), wl, f1);
             if (f1[0] == 0 && f1[1] == 0 && f1[2] == 0) return 0.0;
             if (!visible(s, x, h.prim, c->hc.p, c->hc.prim)) return 0.0;
-            double le[3];
-            emitted(s, c->hc.prim, c->hc.b1, c->hc.b2, vscl(wl, -1.0), le);
             double G01 = c0 * fabs(vdot(s->tri[h.prim].n, wl)) / e2;
-            for (int q = 0; q < 3; ++q) term[q] = f1[q] * G01 * le[q] * s->em_area;   /* / p(h*) */
+            if (c->cls == 1) {
+                double le[3];
+                emitted(s, c->hc.prim, c->hc.b1, c->hc.b2, vscl(wl, -1.0), le);
+                for (int q = 0; q < 3; ++q) term[q] = f1[q] * G01 * le[q] * s->em_area;   /* / p(h*) */
+            } else {
+                /* class C: the light throughput arriving at h_c, its BSDF from the control
+                 * direction toward x, the geometry term h_c <-> x */
+                double f0[3];
+                bsdf_eval(&s->mat[s->tri[c->hc.prim].mat], s->tri[c->hc.prim].n, c->wc, vscl(wl, -1.0), f0);
+                for (int q = 0; q < 3; ++q) term[q] = f1[q] * G01 * f0[q] * c->hc.beta[q];
+            }
         }
         cur = x; curprim = h.prim; curn = s->tri[h.prim].n; w_o = vscl(bs.wi, -1.0);
     }
@@ -1715,14 +1753,15 @@ int or_render(void *sp, const or_params *p, double *sum, double *sumsq, or_stats
     double *trunc = (double *)calloc((size_t)it.M * 4 + 1, sizeof(double));
     double *nsamp = (double *)calloc((size_t)it.M * 4 + 1, sizeof(double));
     /* running (class, u) statistics across iterations (reading R3) */
-    double run_max[2][5], run_sum[2][5], run_n[2][5];
+    double run_max[3][5], run_sum[3][5], run_n[3][5];
     memset(run_max, 0, sizeof(run_max)); memset(run_sum, 0, sizeof(run_sum)); memset(run_n, 0, sizeof(run_n));
     for (int iter = 0; iter < p->n_iter; ++iter) {
         int k = p->first_iter + iter;
         light_ctx lc = {s, p, &it, k};
         parallel_for(it.M, threads, light_path, &lc);
         it.ncand = 0;
-        for (int l = 0; l < it.M; ++l) it.ncand += collect_candidates(&it.paths[l], p->u_max, it.cand + it.ncand);
+        for (int l = 0; l < it.M; ++l)
+            it.ncand += collect_candidates(&it.paths[l], p->u_max, p->general_cv, it.cand + it.ncand);
         /* keep each candidate independently with probability pi_inc = min(1, cap / n_cand) */
         it.pi_inc = it.ncand > 0 ? fmin(1.0, (double)p->cand_cap / it.ncand) : 1.0;
         rng_t rk;
@@ -1743,8 +1782,8 @@ int or_render(void *sp, const or_params *p, double *sum, double *sumsq, or_stats
             run_sum[c->cls][c->u] += fqsum[i]; run_n[c->cls][c->u] += fqn[i];
         }
         double gmax = 0;
-        for (int a = 0; a < 2; ++a) for (int b = 0; b < 5; ++b) if (run_max[a][b] > gmax) gmax = run_max[a][b];
-        for (int a = 0; a < 2; ++a)
+        for (int a = 0; a < 3; ++a) for (int b = 0; b < 5; ++b) if (run_max[a][b] > gmax) gmax = run_max[a][b];
+        for (int a = 0; a < 3; ++a)
             for (int b = 0; b < 5; ++b) it.B[a][b] = run_max[a][b] > 0 ? run_max[a][b] : (gmax > 0 ? gmax : 1.0 / s->em_area);
         /* B_j = max(the candidate's pilot maximum, its (class, u) bucket's running maximum over
          * all earlier pilot and chain samples): the paper's per-bucket maximum of f/q (reading R3),

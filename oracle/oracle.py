@@ -204,10 +204,11 @@ class Scene:
         """Returns (sum, sumsq, stats): per-pixel sums of per-iteration values, shape (H, W, 3).
 
         method 0: O1 (PT + NEE), 1: O2 (proxy-sampling BDPT), 2: O3 (plain BDPT; o3_weights 0 balance
-        heuristic, 1 uniform weights, 2 light tracing alone). general_cv (O1 only): the proxy class of
-        class_filter also holds the paths of a general control vertex (Section 5.2)."""
-        if general_cv and method != 0:
-            raise ValueError("general_cv applies to O1's class filter only")
+        heuristic, 1 uniform weights, 2 light tracing alone). general_cv (O1, O2): the proxy class of
+        class_filter also holds the paths of a general control vertex (Section 5.2), which O2 builds
+        from class C candidates."""
+        if general_cv and method == 2:
+            raise ValueError("general_cv applies to O1's class filter and to O2 only")
         threads = threads or os.cpu_count() or 1
         p = Params(method, n_iter, first_iter, max_depth, n_light, cand_cap, repeats, u_max, class_filter,
                    threads, seed, pilot, chain_cap, cost_cap, o3_weights, int(general_cv))
