@@ -113,3 +113,38 @@ def test_pl4_plane_estimator_matches_reference(oracle):
     z = (m - ref) / np.sqrt(v + 1e-300)
     assert np.abs(z[..., 0]).max() < 4, np.abs(z).max()
     assert np.all(m > 0)
+
+
+def test_planes_scene_keeps_eye_rays_off_the_light_plane():
+    """The workload's stated geometry: every eye ray leaves the light's plane at 15 to 40 degrees
+    (none grazes it, where a plane's estimate would have unbounded variance) and stays at least
+    0.25 from the light up to t_max."""
+    sc = scenes.planes_scene(64, 64)
+    c, U, V = sc["light_c"], sc["light_u"], sc["light_v"]
+    N = np.cross(U, V)
+    cam = sc["camera"]
+    o = cam[:3]
+    f = cam[3:6] - o
+    f /= np.linalg.norm(f)
+    r = np.cross(f, cam[6:9])
+    r /= np.linalg.norm(r)
+    u = np.cross(r, f)
+    th = math.tan(0.5 * math.radians(cam[9]))
+    W, H = sc["width"], sc["height"]
+    ang = []
+    dmin = np.inf
+    ts = np.linspace(0.0, sc["t_max"], 200)
+    for py in (0, H // 2, H - 1):
+        for px in (0, W // 2, W - 1):
+            x = (2.0 * (px + 0.5) / W - 1.0) * th * W / H
+            y = (1.0 - 2.0 * (py + 0.5) / H) * th
+            d = f + x * r + y * u
+            d /= np.linalg.norm(d)
+            ang.append(math.degrees(math.asin(abs(np.dot(d, N)))))
+            for t in ts:
+                p = o + t * d - c
+                a, b, h = np.dot(p, U), np.dot(p, V), np.dot(p, N)
+                da, db = max(abs(a) - sc["light_eu"], 0.0), max(abs(b) - sc["light_ev"], 0.0)
+                dmin = min(dmin, math.sqrt(da * da + db * db + h * h))
+    assert 14.0 < min(ang) and max(ang) < 41.0, (min(ang), max(ang))
+    assert dmin > 0.25, dmin
