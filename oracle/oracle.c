@@ -27,8 +27,8 @@
  *   - the reciprocal estimator of 1/int f (Section 4.2, RRS estimator and
  *     Appendix A, Algorithm "Estimator I~", plus the sign estimator I).
  *
- * Readings of points the paper leaves open are listed in the design notes and
- * restated next to the code that takes them.
+ * Readings of points the paper leaves open are restated next to the code that
+ * takes them.
  */
 #include <math.h>
 #include <pthread.h>

@@ -12,7 +12,7 @@
  * Le[3], camera[10] (position, target, up, vertical field of view in degrees), sigma_s, sigma_t,
  * t_max. The medium fills space, the phase function is isotropic, nothing occludes.
  *
- * What is computed (derivation in the design notes):
+ * What is computed:
  *   the single-scattered radiance along the eye ray o + t d, 0 < t <= t_max,
  *     L = int dt int_A dA(y) e^{-st t} ss (1/4pi) Le cos(theta_y) / R^2 e^{-st R},  R = |x - y|;
  *   a photon plane: y0 uniform on the light, chord angle alpha uniform in [0, pi), direction w

@@ -224,8 +224,8 @@ def test_p9_o2_general_cv_matches_o1(oracle):
     has a bounded geometry term), 8 segments, u <= 1: O2 with class C candidates, the proxy alone
     on its class, against O1 restricted to the same class; class C is about 20 % of it. The proxy
     alone carries the reciprocal estimates' right tail unweighted, so its per-pixel means are
-    skewed low with standard errors that read low (the design notes' reading of the proxy-alone
-    statistics): the image total is the test of the expectation, and per pixel the upper side."""
+    skewed low with standard errors that read low: the image total is the test of the
+    expectation, and per pixel the upper side."""
     sc = scenes.furnace(albedo=0.5, le=1.0, glass_sphere=True, width=8, height=8, enclosure="sphere")
     S = oracle.Scene(sc)
     N1, N2 = 8192, 1024
